@@ -1,0 +1,551 @@
+"""Two-stage PHSVDS, float64, written step by step from the paper.
+
+Notation follows the paper: A is m x n (m >= n, full column rank),
+C = A^T A (eigenpairs (sigma_i^2, v_i)), B = [0 A^T; A 0] acting on [v; u]
+(eigenpairs (+-sigma_i, [v_i; +-u_i]) and m - n zeros), Section 1.
+
+Stage 1 (Algorithm 1): block GD+k on C for the k smallest (or largest)
+eigenpairs, stopped per pair by the dynamic tolerance of Section 3.1,
+    ||r_C|| < max(delta * s_i * s_n, floor * eps * s_n^2),
+where s_i is the targeted Ritz value's square root and s_n^2 the largest
+Ritz value seen so far (the running estimate of ||C||, Algorithm 1).
+
+Transition (Section 3.1, Algorithm 1 step 3): a complete Rayleigh-Ritz on C
+over the converged vectors plus the leading restart basis; it gives the
+shifts and initial vectors [v_i; A v_i / ||A v_i||] of stage 2, with a random
+left vector when sigma_i is too small to carry any accuracy (Section 3.3).
+
+Stage 2 (Algorithm 2): GD+k on B with the refined projection: for the
+current target shift s, the refined vector y minimises ||(W - s V) y|| over
+the search space through the R factor of W - s V; theta = y^T H y replaces
+the Ritz value; converged pairs are locked and the next initial guess is
+re-inserted; corrections are t = Prec(r).
+
+Readings where the paper is silent (the same readings bind the GPU path):
+  * basis sizes: p_max = max(35, 2k + 2b), p_min = max(21, ceil(0.6 p_max)),
+    and p_min <= p_max - 2b (the paper's 35/21 for blocks of 1-2);
+  * GD+k restart keeps the p_min lowest Ritz vectors plus the previous
+    iteration's b targeted Ritz vectors, orthogonalised against them;
+  * hard locking in both stages; only the first (k - locked) targets of the
+    block are tested for convergence;
+  * floor = 10 in the stage-1 test; a pair whose test is floor-limited, whose
+    residual is within 10x of that floor and has not improved by 10% over
+    the last L = max(100, 20 p_max / b) iterations is accepted as converged
+    to the floor (a guard against endless stagnation at rounding level);
+  * stage 2 is entered for the pairs whose stage-1 test was floor-limited,
+    i.e. delta * s_i < floor * eps * s_n (Section 3.1);
+  * the transition Rayleigh-Ritz over an orthonormal Z is evaluated as the
+    SVD of A Z (Z^T C Z = (AZ)^T (AZ)), which yields the same Ritz pairs of C
+    without squaring the small singular values;
+  * the Krylov fill of stage 2 starts from [v_1; u_1] / sqrt(2) and has
+    dimension p_min - k (Algorithm 2 step 2);
+  * block members 2..b of stage 2 are the next right singular vectors of R,
+    accepted only if theta > s / 2 and the two halves have balanced norms;
+  * dependent columns (norm drop by more than 1e10 under orthogonalisation)
+    are replaced by counter-based random vectors.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import rng as _rng
+
+EPS64 = 2.0 ** -52
+DEP_DROP = 1e-10
+
+
+def basis_sizes(k: int, b: int, max_basis: int | None = None, min_restart: int | None = None):
+    pmax = max_basis if max_basis else max(35, 2 * k + 2 * b)
+    pmin = min_restart if min_restart else max(21, int(math.ceil(0.6 * pmax)))
+    pmin = min(pmin, pmax - 2 * b)
+    if pmin < b:
+        raise ValueError("basis too small for the block size")
+    return pmax, pmin
+
+
+@dataclass
+class Stats:
+    mv_stage1: int = 0
+    mv_rr: int = 0
+    mv_stage2: int = 0
+    mv_final: int = 0
+    mv_prec: int = 0
+    iters1: int = 0
+    iters2: int = 0
+    restarts1: int = 0
+    restarts2: int = 0
+    stage2_pairs: int = 0
+    anorm_est: float = 0.0
+    res_stage1: list = field(default_factory=list)
+
+    @property
+    def mv_total(self):
+        return self.mv_stage1 + self.mv_rr + self.mv_stage2 + self.mv_final
+
+
+class _Rand:
+    """Random replacement vectors from the counter-based stream."""
+
+    def __init__(self, seed):
+        self.seed = seed
+        self.count = 0
+
+    def vec(self, n):
+        self.count += 1
+        return _rng.stream(self.seed, self.count, n)
+
+
+def _project_out(t, bases):
+    for Bm in bases:
+        if Bm is not None and Bm.shape[1]:
+            t = t - Bm @ (Bm.T @ t)
+    return t
+
+
+def orth_block(T, bases, rnd: _Rand):
+    """Orthonormal columns spanning T orthogonalised against ``bases``.
+
+    Column by column: two Gram-Schmidt passes against the bases and the
+    columns accepted so far (a third pass if the second still removed more
+    than half).  A column whose norm drops by more than 1/DEP_DROP is
+    replaced by a random vector, which is orthogonalised the same way."""
+    T = np.asarray(T, dtype=np.float64)
+    if T.ndim == 1:
+        T = T[:, None]
+    out = []
+    for j in range(T.shape[1]):
+        t = T[:, j].copy()
+        for attempt in range(3):
+            n0 = np.linalg.norm(t)
+            cur = bases + ([np.column_stack(out)] if out else [])
+            t1 = _project_out(t, cur)
+            n1 = np.linalg.norm(t1)
+            t2 = _project_out(t1, cur)
+            n2 = np.linalg.norm(t2)
+            if n2 < 0.5 * n1:
+                t2 = _project_out(t2, cur)
+                n2 = np.linalg.norm(t2)
+            if n0 > 0 and n2 > DEP_DROP * n0:
+                out.append(t2 / n2)
+                break
+            t = rnd.vec(T.shape[0])
+        else:
+            raise RuntimeError("could not extend the basis")
+    if not out:
+        return np.zeros((T.shape[0], 0))
+    return np.column_stack(out)
+
+
+def _small_orth_against(P, K):
+    """Orthonormal columns of P orthogonalised against orthonormal K
+    (small coefficient space); dependent columns are dropped."""
+    out = []
+    for j in range(P.shape[1]):
+        t = P[:, j].copy()
+        n0 = np.linalg.norm(t)
+        if n0 == 0:
+            continue
+        cur = [K] + ([np.column_stack(out)] if out else [])
+        for _ in range(2):
+            t = _project_out(t, cur)
+        n2 = np.linalg.norm(t)
+        if n2 > 1e-8 * n0:
+            out.append(t / n2)
+    if not out:
+        return np.zeros((P.shape[0], 0))
+    return np.column_stack(out)
+
+
+def _sym(H):
+    return 0.5 * (H + H.T)
+
+
+def _pad(Sc, rows):
+    P = np.zeros((rows, Sc.shape[1]))
+    P[: Sc.shape[0]] = Sc
+    return P
+
+
+# --------------------------------------------------------------------------
+# Stage 1: block GD+k on C = A^T A
+# --------------------------------------------------------------------------
+def stage1_gdk(A, k, tol, b, pmax, pmin, X0, which="smallest", precond=None, anorm=None,
+               max_restarts=10000, floor=10.0, eps=EPS64, seed=11, stats: Stats | None = None,
+               max_iters=None):
+    """Block GD+k on C for k extreme eigenpairs (Sections 2.2, 2.4, 3.1).
+
+    ``precond(R, theta, X) -> T`` maps the residual block to the correction
+    block (None: T = R).  Returns (X_lock, theta_lock, V_rest, s_n^2, info)
+    with theta ascending for 'smallest', descending for 'largest'."""
+    stats = stats if stats is not None else Stats()
+    n = A.shape[1]
+    rnd = _Rand(seed)
+
+    def Cop(X):
+        stats.mv_stage1 += X.shape[1]
+        return A.T @ (A @ X)
+
+    V = orth_block(X0, [], rnd)
+    W = Cop(V)
+    H = _sym(V.T @ W)
+    Xl = np.zeros((n, 0))
+    thl = []
+    sn2 = float(anorm) ** 2 if anorm else 0.0
+    prev = None
+    hist = []
+    L = max(100, 20 * int(math.ceil(pmax / b)))
+    it = 0
+    converged = False
+    while True:
+        it += 1
+        theta, S = np.linalg.eigh(H)
+        if which == "largest":
+            theta, S = theta[::-1], S[:, ::-1]
+        sn2 = max(sn2, float(theta.max()))
+        sn = math.sqrt(sn2)
+        p = V.shape[1]
+        nb = min(b, p)
+        X = V @ S[:, :nb]
+        R = W @ S[:, :nb] - X * theta[:nb]
+        rn = np.linalg.norm(R, axis=0)
+        need = k - len(thl)
+        conv = []
+        for i in range(min(nb, need)):
+            si = math.sqrt(max(theta[i], 0.0))
+            fl = floor * eps * sn2
+            thr = max(tol * si * sn, fl)
+            if rn[i] < thr:
+                conv.append(i)
+        # floor-limited stagnation acceptance for the leading target
+        si0 = math.sqrt(max(theta[0], 0.0))
+        if not conv and need > 0 and tol * si0 * sn < floor * eps * sn2:
+            hist.append(rn[0])
+            if len(hist) > 2 * L and rn[0] < 10.0 * floor * eps * sn2:
+                if min(hist[-L:]) > 0.9 * min(hist[:-L]):
+                    conv.append(0)
+        if conv:
+            hist = []
+            for i in conv:
+                Xl = np.column_stack([Xl, X[:, i]])
+                thl.append(float(theta[i]))
+                stats.res_stage1.append(float(rn[i]))
+            if len(thl) >= k:
+                converged = True
+                keep = [i for i in range(p) if i not in conv]
+                V = V @ S[:, keep]
+                break
+            keep = [i for i in range(p) if i not in conv]
+            V = V @ S[:, keep]
+            W = W @ S[:, keep]
+            H = np.diag(theta[keep])
+            prev = None
+            if V.shape[1] == 0:
+                V = orth_block(np.column_stack([rnd.vec(n) for _ in range(b)]), [Xl], rnd)
+                W = Cop(V)
+                H = _sym(V.T @ W)
+            continue
+        if stats.restarts1 > max_restarts or (max_iters and it > max_iters):
+            break
+        T = R if precond is None else precond(R, theta[:nb], X)
+        if p + nb > pmax:
+            Y = S[:, :pmin]
+            if prev is not None:
+                Pq = _small_orth_against(_pad(prev, p), Y)
+                Y = np.column_stack([Y, Pq])
+            V = V @ Y
+            W = W @ Y
+            H = _sym(Y.T @ H @ Y)
+            prev = Y.T @ S[:, :nb]
+            stats.restarts1 += 1
+        else:
+            prev = S[:, :nb]
+        T = orth_block(T, [Xl, V], rnd)
+        WT = Cop(T)
+        p = V.shape[1]
+        Hb = V.T @ WT
+        Ht = _sym(T.T @ WT)
+        H = np.block([[H, Hb], [Hb.T, Ht]])
+        V = np.column_stack([V, T])
+        W = np.column_stack([W, WT])
+        prev = _pad(prev, V.shape[1])
+    stats.iters1 += it
+    order = np.argsort(thl) if which == "smallest" else np.argsort(thl)[::-1]
+    thl = np.asarray(thl)[order]
+    Xl = Xl[:, order]
+    return Xl, thl, V, sn2, {"converged": converged, "iters": it}
+
+
+# --------------------------------------------------------------------------
+# Transition: post-processing Rayleigh-Ritz (Section 3.1, Algorithm 1 step 3)
+# --------------------------------------------------------------------------
+def transition_rr(A, Xl, Vrest, k, pmin, anorm, seed=13, stats: Stats | None = None):
+    """Rayleigh-Ritz of C on Z = orth([X_lock, leading restart vectors]).
+
+    Returns shifts sigma (ascending), right vectors v (n x k) and left
+    vectors u = A v / ||A v|| (m x k); u is random (orthogonalised against
+    the other u) when ||A v|| <= 10 eps ||A|| (Section 3.3)."""
+    stats = stats if stats is not None else Stats()
+    rnd = _Rand(seed)
+    extra = max(0, pmin - k)
+    Z0 = np.column_stack([Xl, Vrest[:, :extra]]) if extra and Vrest.shape[1] else Xl
+    Z = orth_block(Z0, [], rnd)
+    AZ = A @ Z
+    stats.mv_rr += Z.shape[1]
+    Ua, s, Vt = np.linalg.svd(AZ, full_matrices=False)
+    idx = np.argsort(s, kind="stable")[:k]
+    sig = s[idx]
+    v = Z @ Vt.T[:, idx]
+    u = Ua[:, idx].copy()
+    for i in range(k):
+        if sig[i] <= 10 * EPS64 * anorm:
+            others = [u[:, [j for j in range(k) if j != i and sig[j] > 10 * EPS64 * anorm]]]
+            r = orth_block(rnd.vec(A.shape[0])[:, None], others, rnd)
+            u[:, i] = r[:, 0]
+    return sig, v, u
+
+
+# --------------------------------------------------------------------------
+# Stage 2: GD+k with refined projection on B (Algorithm 2)
+# --------------------------------------------------------------------------
+def stage2_refined(A, shifts, v0, u0, tol, anorm, b, pmax, pmin, precondB=None,
+                   max_restarts=10000, seed=17, stats: Stats | None = None, max_iters=None):
+    """Interior eigenpairs of B near the given shifts (Algorithm 2).
+
+    Returns (sigma, X) with X = [v; u] unit vectors of B, in target order."""
+    stats = stats if stats is not None else Stats()
+    m, n = A.shape
+    N = m + n
+    k2 = len(shifts)
+    rnd = _Rand(seed)
+
+    def Bop(X):
+        stats.mv_stage2 += X.shape[1]
+        return np.vstack([A.T @ X[n:], A @ X[:n]])
+
+    Y0 = np.vstack([v0, u0]) / math.sqrt(2.0)
+    # step 2: K_{s-k}(B, y_1) by Lanczos (full reorthogonalisation) plus the seeds
+    nk = max(0, pmin - k2)
+    Kb = orth_block(Y0[:, :1], [], rnd)
+    t = None
+    for i in range(nk):
+        w = Bop(Kb[:, -1:])
+        if i < nk - 1:
+            Kb = np.column_stack([Kb, orth_block(w, [Kb], rnd)])
+        else:
+            t = w
+    V = orth_block(np.column_stack([Y0, Kb[:, 1:]]) if Kb.shape[1] > 1 else Y0, [], rnd)
+    W = Bop(V)
+    H = _sym(V.T @ W)
+    Xl = np.zeros((N, 0))
+    thl = []
+    j = 0
+    shift = float(shifts[0])
+    pend = t
+    prev = None
+    it = 0
+    thr = tol * anorm / math.sqrt(2.0)
+    while True:
+        if pend is not None:
+            T = orth_block(pend, [Xl, V], rnd)
+            WT = Bop(T)
+            Hb = V.T @ WT
+            H = np.block([[H, Hb], [Hb.T, _sym(T.T @ WT)]])
+            V = np.column_stack([V, T])
+            W = np.column_stack([W, WT])
+            if prev is not None:
+                prev = _pad(prev, V.shape[1])
+            pend = None
+        it += 1
+        p = V.shape[1]
+        # R factor of W - shift V (steps 5-7; the incremental update gives the
+        # same R up to column signs), then its SVD (step 9)
+        Rf = np.linalg.qr(W - shift * V, mode="r")
+        _, sv, Yt = np.linalg.svd(Rf)
+        order = np.argsort(sv, kind="stable")
+        Ys = Yt.T[:, order]
+        y = Ys[:, 0]
+        theta = float(y @ H @ y)
+        x = V @ y
+        r = W @ y - theta * x
+        rn = float(np.linalg.norm(r))
+        if rn < thr:
+            Xl = np.column_stack([Xl, x])
+            thl.append(theta)
+            j += 1
+            if j >= k2:
+                break
+            rest = Ys[:, 1:]
+            V = V @ rest
+            W = W @ rest
+            H = _sym(rest.T @ H @ rest)
+            shift = float(shifts[j])
+            pend = Y0[:, j:j + 1]
+            prev = None
+            continue
+        if stats.restarts2 > max_restarts or (max_iters and it > max_iters):
+            break
+        slots = [0]
+        thetas = [theta]
+        for c in range(1, p):
+            if len(slots) >= b or c > 2 * b:
+                break
+            yc = Ys[:, c]
+            thc = float(yc @ H @ yc)
+            xc = V @ yc
+            vn2 = float(xc[:n] @ xc[:n])
+            if thc > 0.5 * shift and abs(2.0 * vn2 - 1.0) < 0.1:
+                slots.append(c)
+                thetas.append(thc)
+        Ysl = Ys[:, slots]
+        X = V @ Ysl
+        Rr = W @ Ysl - X * np.asarray(thetas)[None, :]
+        nb = len(slots)
+        T = Rr if precondB is None else precondB(Rr, np.asarray(thetas), X)
+        if p + nb > pmax:
+            Yr = Ys[:, :pmin]
+            if prev is not None:
+                Yr = np.column_stack([Yr, _small_orth_against(prev, Yr)])
+            V = V @ Yr
+            W = W @ Yr
+            H = _sym(Yr.T @ H @ Yr)
+            prev = Yr.T @ Ysl
+            stats.restarts2 += 1
+        else:
+            prev = Ysl
+        pend = T
+    stats.iters2 += it
+    return np.asarray(thl), Xl
+
+
+# --------------------------------------------------------------------------
+# Preconditioners (Section 4; Jacobi is the plain comparison arm)
+# --------------------------------------------------------------------------
+def jacobi_diag(A):
+    """diag(C)_j = ||A_:,j||^2."""
+    A2 = A.multiply(A)
+    return np.asarray(A2.sum(axis=0)).ravel()
+
+
+def jacobi_precond_C(d, olsen=True, clamp=1e-3):
+    """t = M r with M = (diag(C) - theta I)^-1, optionally in the Olsen form
+    t = M r - e M x, e = x^T M r / x^T M x (GD_Olsen_PlusK, Section 5)."""
+
+    def apply(R, theta, X):
+        T = np.empty_like(R)
+        for i in range(R.shape[1]):
+            den = d - theta[i]
+            den = np.where(np.abs(den) < clamp * d, np.where(den >= 0, clamp * d, -clamp * d), den)
+            Mr = R[:, i] / den
+            if olsen:
+                Mx = X[:, i] / den
+                e = (X[:, i] @ Mr) / (X[:, i] @ Mx)
+                Mr = Mr - e * Mx
+            T[:, i] = Mr
+        return T
+
+    return apply
+
+
+def jacobi_precond_B(A, d, stats: Stats):
+    """B-form of a C preconditioner M = diag(C)^-1 (Section 4):
+    [f; g] -> [M (A^T g); A (M f)]."""
+    m, n = A.shape
+
+    def apply(R, theta, X):
+        f, g = R[:n], R[n:]
+        stats.mv_prec += R.shape[1]
+        return np.vstack([(A.T @ g) / d[:, None], A @ (f / d[:, None])])
+
+    return apply
+
+
+# --------------------------------------------------------------------------
+# Driver
+# --------------------------------------------------------------------------
+def _final(A, V, U, stats, AV=None):
+    """Explicit triplet residuals in float64 (Section 5 stopping test)."""
+    if AV is None:
+        AV = A @ V
+        stats.mv_final += V.shape[1]
+    sigma = np.einsum("ij,ij->j", U, AV)
+    neg = sigma < 0
+    U[:, neg] *= -1.0
+    sigma = np.abs(sigma)
+    rv = AV - U * sigma
+    ru = A.T @ U - V * sigma
+    res = np.sqrt((rv * rv).sum(0) + (ru * ru).sum(0))
+    return sigma, res, U
+
+
+def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, anorm=None,
+           stage2="auto", max_basis=None, min_restart=None, max_restarts=10000, floor=10.0,
+           seed=2, max_iters=None):
+    """k smallest (or largest) singular triplets of A by PHSVDS.
+
+    Returns dict(sigma, U, V, res, stats, stage1_sigma).  ``precond`` is
+    'none' or 'jacobi' (stage 1: Olsen-Jacobi on C; stage 2: its B-form)."""
+    import workloads  # seeded inputs only
+
+    m, n = A.shape
+    if m < n:
+        raise ValueError("A must have m >= n")
+    stats = Stats()
+    b = block
+    pmax, pmin = basis_sizes(k, b, max_basis, min_restart)
+    if X0 is None:
+        X0 = workloads.initial_block(n, b, seed)
+    pc1 = pcB = None
+    if precond == "jacobi":
+        d = jacobi_diag(A)
+        pc1 = jacobi_precond_C(d)
+        pcB = jacobi_precond_B(A, d, stats)
+    elif precond != "none":
+        raise ValueError(precond)
+    Xl, thl, Vr, sn2, info = stage1_gdk(A, k, tol, b, pmax, pmin, X0, which, pc1, anorm,
+                                        max_restarts, floor, EPS64, stats=stats,
+                                        max_iters=max_iters)
+    sn = math.sqrt(sn2)
+    stats.anorm_est = sn
+    an = float(anorm) if anorm else sn
+    s1 = np.sqrt(np.maximum(thl, 0.0))
+    kk = len(thl)
+    if which == "largest" or stage2 == "never":
+        need2 = 0
+    elif stage2 == "force":
+        need2 = kk
+    else:
+        need2 = int(np.sum(tol * s1 < floor * EPS64 * sn))
+    if need2 == 0:
+        V = Xl.copy()
+        AV = A @ V
+        stats.mv_final += V.shape[1]
+        nv = np.linalg.norm(AV, axis=0)
+        U = AV / np.where(nv > 0, nv, 1.0)
+        sigma, res, U = _final(A, V, U, stats, AV)
+    else:
+        sig_rr, v_rr, u_rr = transition_rr(A, Xl, Vr, kk, pmin, an, stats=stats)
+        stats.stage2_pairs = need2
+        th2, X2 = stage2_refined(A, sig_rr[:need2], v_rr[:, :need2], u_rr[:, :need2], tol, an,
+                                 b, pmax, pmin, pcB, max_restarts, stats=stats,
+                                 max_iters=max_iters)
+        got = X2.shape[1]
+        V = np.column_stack([X2[:n], v_rr[:, got:]])
+        U = np.column_stack([X2[n:], u_rr[:, got:]])
+        V = V / np.linalg.norm(V, axis=0)
+        U = U / np.linalg.norm(U, axis=0)
+        sigma, res, U = _final(A, V, U, stats)
+    order = np.argsort(sigma, kind="stable")
+    if which == "largest":
+        order = order[::-1]
+    sigma, res, U, V = sigma[order], res[order], U[:, order], V[:, order]
+    for i in range(V.shape[1]):
+        jmax = np.argmax(np.abs(V[:, i]))
+        if V[jmax, i] < 0:
+            V[:, i] *= -1.0
+            U[:, i] *= -1.0
+    return {"sigma": sigma, "U": U, "V": V, "res": res, "stats": stats,
+            "stage1_sigma": s1, "converged": bool(info["converged"]) and len(sigma) == k,
+            "anorm": an}
