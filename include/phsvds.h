@@ -1,0 +1,149 @@
+/*
+ * phsvds.h -- C ABI of the MI355X PHSVDS library (libphsvds.so).
+ *
+ * PHSVDS computes the k smallest (or largest) singular triplets
+ * (sigma_i, u_i, v_i) of a large sparse A in R^{m x n}, m >= n, full column
+ * rank (problem statement, Section 1, eq. (1)), by a two-stage method:
+ * stage 1 is a block GD+k eigensolver on C = A^T A stopped at the best
+ * accuracy C allows (Section 3.1, Algorithm 1); stage 2 is GD+k with a
+ * refined projection on B = [0 A^T; A 0] seeded by stage 1 (Section 3.2,
+ * Algorithm 2).
+ *
+ * Conventions for every entry point:
+ *   - "device" pointers are HIP device memory owned by the caller; the
+ *     library only reads inputs and writes outputs through them.
+ *   - All device work is enqueued on `stream` (a hipStream_t, NULL = the
+ *     null stream).  Host outputs are valid when the call returns.
+ *   - Block vectors passed to the SpMM calls are ROW-major (entry (i, j) of
+ *     an N x b block at index i*b + j).  Dense outputs U, V of phsvds_svds are
+ *     COLUMN-major (entry (i, j) at index i + j*ld with ld = rows).
+ *   - CSR inputs are zero-based, rows sorted by column, no duplicates,
+ *     rowptr[0] = 0, nnz < 2^31.
+ *   - Return value: PHSVDS_OK, PHSVDS_NOT_CONVERGED, or a negative error
+ *     code; phsvds_last_error() gives a message for the calling thread.
+ *     No C++ exception crosses this boundary.
+ */
+#ifndef PHSVDS_H
+#define PHSVDS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PHSVDS_OK 0
+#define PHSVDS_NOT_CONVERGED 1 /* outputs hold the best approximations */
+#define PHSVDS_EINVAL (-1)     /* invalid argument */
+#define PHSVDS_EBREAKDOWN (-2) /* unrecoverable numerical breakdown */
+#define PHSVDS_EHIP (-3)       /* HIP runtime error */
+#define PHSVDS_ENOMEM (-4)     /* workspace too small */
+
+/* Sparse A in CSR, float64 values (device pointers, caller-owned, read-only). */
+typedef struct {
+  int64_t m, n, nnz;
+  const int64_t *rowptr; /* m+1 */
+  const int32_t *colind; /* nnz */
+  const double *val;     /* nnz */
+} phsvds_csr;
+
+/* Preconditioner of the correction step t = Prec(r) (Algorithm 2 step 13;
+ * Section 4).  NONE: t = r.  JACOBI: t = (diag(C) - theta)^-1 r in stage 1
+ * (Olsen form), its B-form [M A^T g; A M f] in stage 2 (Section 4).
+ * GNN: the learned message-passing network given by `gnn_weights`
+ * (layout of phsvds_gnn_nweights), stage 1 only. */
+enum { PHSVDS_PREC_NONE = 0, PHSVDS_PREC_JACOBI = 1, PHSVDS_PREC_GNN = 2 };
+
+typedef struct {
+  int kind;
+  const float *gnn_weights; /* device, phsvds_gnn_nweights() floats, or NULL */
+  int gnn_width;            /* hidden width of the network (e.g. 32) */
+} phsvds_precond;
+
+typedef struct {
+  int which;       /* 0: smallest (default), 1: largest (Section 1, Section 3.1) */
+  int block;       /* block size b of the GD+k iteration (default 1) */
+  int max_basis;   /* p_max; 0: max(35, 2k + 2b) (Section 5 uses 35) */
+  int min_restart; /* p_min; 0: max(21, ceil(0.6 p_max)), capped at p_max - 2b */
+  int stage1_fp32; /* 1: stage 1 in float32 with float32 accumulation */
+  int fp64_continue; /* with stage1_fp32: continue stage 1 in float64 before B */
+  int stage2;      /* 0: automatic (Section 3.1 rule), 1: force, -1: never */
+  int max_restarts;   /* per stage (default 10000, Section 5) */
+  int64_t max_matvecs; /* 0: unlimited */
+  uint64_t seed;      /* counter-based stream for random vectors */
+  const double *init_block; /* device n x b column-major initial block, or NULL
+                               for [ones/sqrt(n), random] (Section 5) */
+  double anorm;        /* ||A|| if known (> 0), else the running estimate */
+  double floor_factor; /* multiple of eps*||C|| that ends stage 1 (default 10) */
+} phsvds_opts;
+
+typedef struct {
+  int64_t mv_stage1, mv_rr, mv_stage2, mv_final; /* products with A (Section 5 "MV") */
+  int64_t mv_prec;    /* A products inside preconditioners */
+  int64_t mv_floor;   /* |A| products for the float32 accuracy floor */
+  int64_t iters1, iters2, restarts1, restarts2;
+  int64_t stage2_pairs, fp32_locked;
+  double t_setup, t_stage1, t_stage2, t_total; /* seconds (host wall clock) */
+  double anorm_est;
+  double res_stage1[64]; /* residual ||r_C|| of each pair on leaving stage 1 */
+} phsvds_stats;
+
+/* Defaults of every field (paper parameters of Section 5). */
+void phsvds_default_opts(phsvds_opts *opts);
+
+/* Library version string; never NULL. */
+const char *phsvds_version(void);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *phsvds_last_error(void);
+
+/* Y = A X (or Y = |A| |X| if `absval`), X n x b, Y m x b, row-major blocks,
+ * b in {1, 2, 4, 8, 16, 32}.  "Matrix times block of vectors" of Section 3.3. */
+int phsvds_spmm_f64(const phsvds_csr *A, int b, const double *X, double *Y, int absval,
+                    void *stream);
+/* Same with float32 values/vectors (the float32 value array `val32` has the
+ * sparsity of A; A->val is not read). */
+int phsvds_spmm_f32(const phsvds_csr *A, const float *val32, int b, const float *X, float *Y,
+                    int absval, void *stream);
+
+/* CSR of A^T (n x m) built on the device: t_rowptr (n+1), t_colind (nnz),
+ * t_val (nnz); rows of A^T come out sorted by column.  `ws` must hold
+ * phsvds_transpose_ws_bytes(A) bytes.  The sort of a row of A^T with L
+ * entries costs O(L^2) comparisons in one workgroup when L > 32. */
+size_t phsvds_transpose_ws_bytes(const phsvds_csr *A);
+int phsvds_csr_transpose(const phsvds_csr *A, int64_t *t_rowptr, int32_t *t_colind,
+                         double *t_val, void *ws, size_t ws_bytes, void *stream);
+
+/* Device workspace needed by phsvds_svds for these sizes and options. */
+int phsvds_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int k, const phsvds_opts *opts,
+                           size_t *bytes);
+
+/* The k smallest (opts->which = 0) or largest singular triplets of A to
+ * sqrt(||r_u||^2 + ||r_v||^2) <= tol ||A|| (Section 5 stopping test).
+ *   sigma   host, k      singular values, ascending (descending if largest)
+ *   U       device, m x k column-major left vectors
+ *   V       device, n x k column-major right vectors; the largest-magnitude
+ *           entry of each v_i is positive
+ *   resnorm host, k      explicit float64 residuals of the returned triplets
+ *   stats   host, may be NULL
+ * Returns PHSVDS_OK, PHSVDS_NOT_CONVERGED (best approximations returned),
+ * or an error.  1 <= k <= 24, m >= n, tol > 0. */
+int phsvds_svds(const phsvds_csr *A, int k, double tol, const phsvds_precond *P,
+                const phsvds_opts *opts, void *workspace, size_t ws_bytes, void *stream,
+                double *sigma, double *U, double *V, double *resnorm, phsvds_stats *stats);
+
+/* Kernel timing for benchmarks: HIP event pairs recorded on the launching
+ * stream around each operation of a kind.  phsvds_profile(1) clears the
+ * counters and starts recording, phsvds_profile(0) stops.  Kinds:
+ * 0 float64 SpMM, 1 float32 SpMM, 2 tall X^T Y, 3 tall X S, 4 Ritz block.
+ * phsvds_profile_read returns the number of timed operations, their summed
+ * device time (s) and their summed algorithmic HBM bytes.  Not thread-safe
+ * against concurrent solves. */
+int phsvds_profile(int enable);
+int phsvds_profile_read(int kind, int64_t *launches, double *seconds, double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PHSVDS_H */

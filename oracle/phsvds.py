@@ -27,7 +27,10 @@ Readings where the paper is silent (the same readings bind the GPU path):
   * GD+k restart keeps the p_min lowest Ritz vectors plus the previous
     iteration's b targeted Ritz vectors, orthogonalised against them;
   * hard locking in both stages; only the first (k - locked) targets of the
-    block are tested for convergence;
+    block are tested for convergence; in stage 1 a pair that passes the test
+    on its recurrence residual W s - theta x is locked only if its explicit
+    residual C x - theta x passes too (one product per candidate); otherwise
+    W = C V and H are recomputed to remove the drift of the restarts;
   * floor = 10 in the stage-1 test; a pair whose test is floor-limited, whose
     residual is within 10x of that floor and has not improved by 10% over
     the last L = max(100, 20 p_max / b) iterations is accepted as converged
@@ -212,13 +215,13 @@ def stage1_gdk(A, k, tol, b, pmax, pmin, X0, which="smallest", precond=None, ano
         R = W @ S[:, :nb] - X * theta[:nb]
         rn = np.linalg.norm(R, axis=0)
         need = k - len(thl)
-        conv = []
-        for i in range(min(nb, need)):
+
+        def thr_of(i):
             si = math.sqrt(max(theta[i], 0.0))
-            fl = floor * eps * sn2
-            thr = max(tol * si * sn, fl)
-            if rn[i] < thr:
-                conv.append(i)
+            return max(tol * si * sn, floor * eps * sn2)
+
+        conv = [i for i in range(min(nb, need)) if rn[i] < thr_of(i)]
+        stag = None
         # floor-limited stagnation acceptance for the leading target
         si0 = math.sqrt(max(theta[0], 0.0))
         if not conv and need > 0 and tol * si0 * sn < floor * eps * sn2:
@@ -226,6 +229,20 @@ def stage1_gdk(A, k, tol, b, pmax, pmin, X0, which="smallest", precond=None, ano
             if len(hist) > 2 * L and rn[0] < 10.0 * floor * eps * sn2:
                 if min(hist[-L:]) > 0.9 * min(hist[:-L]):
                     conv.append(0)
+                    stag = 0
+        if conv and stag is None:
+            # lock only on the explicit residual C x - theta x: the recurrence
+            # W s - theta x drifts from it over restarts; on a mismatch the
+            # basis products are recomputed, W = C V
+            Xc = X[:, conv]
+            Rt = Cop(Xc) - Xc * theta[conv]
+            rt = np.linalg.norm(Rt, axis=0)
+            ok = [i for q, i in enumerate(conv) if rt[q] < thr_of(i)]
+            if len(ok) < len(conv):
+                W = Cop(V)
+                H = _sym(V.T @ W)
+                prev = None
+                continue
         if conv:
             hist = []
             for i in conv:

@@ -1,0 +1,252 @@
+"""MI355X PHSVDS: Python binding of libphsvds.so (argument marshalling only).
+
+Every numerical step runs in the library's HIP kernels; PyTorch supplies
+device memory and the current HIP stream.  There is no CPU fallback: if the
+library is not built, importing this package raises.
+
+The names follow the C ABI in include/phsvds.h:
+    svds_smallest(A, k, tol, precond) -> (sigma, U, V, info)   (phsvds_svds)
+    spmm(A, X)                        -> A X                   (phsvds_spmm_*)
+    csr_transpose(A)                  -> A^T                   (phsvds_csr_transpose)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch  # noqa: F401  (loads the HIP runtime the library shares)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libphsvds.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_1408_5535_amd/build.py "
+                      "(or __graft_entry__.build()) first")
+_lib = ctypes.CDLL(LIB_PATH)
+
+PHSVDS_OK = 0
+PHSVDS_NOT_CONVERGED = 1
+PREC = {"none": 0, "jacobi": 1, "gnn": 2}
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("colind", ctypes.c_void_p),
+                ("val", ctypes.c_void_p)]
+
+
+class _Precond(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("gnn_weights", ctypes.c_void_p),
+                ("gnn_width", ctypes.c_int)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("which", ctypes.c_int), ("block", ctypes.c_int), ("max_basis", ctypes.c_int),
+                ("min_restart", ctypes.c_int), ("stage1_fp32", ctypes.c_int),
+                ("fp64_continue", ctypes.c_int), ("stage2", ctypes.c_int),
+                ("max_restarts", ctypes.c_int), ("max_matvecs", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("init_block", ctypes.c_void_p),
+                ("anorm", ctypes.c_double), ("floor_factor", ctypes.c_double)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in
+                ("mv_stage1", "mv_rr", "mv_stage2", "mv_final", "mv_prec", "mv_floor",
+                 "iters1", "iters2", "restarts1", "restarts2", "stage2_pairs", "fp32_locked")] + \
+               [(f, ctypes.c_double) for f in
+                ("t_setup", "t_stage1", "t_stage2", "t_total", "anorm_est")] + \
+               [("res_stage1", ctypes.c_double * 64)]
+
+    def as_dict(self, k):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "res_stage1"}
+        d["res_stage1"] = list(self.res_stage1[:k])
+        d["mv_total"] = self.mv_stage1 + self.mv_rr + self.mv_stage2 + self.mv_final
+        return d
+
+
+_P = ctypes.c_void_p
+_lib.phsvds_version.restype = ctypes.c_char_p
+_lib.phsvds_last_error.restype = ctypes.c_char_p
+_lib.phsvds_default_opts.argtypes = [ctypes.POINTER(_Opts)]
+_lib.phsvds_spmm_f64.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, _P, _P, ctypes.c_int, _P]
+_lib.phsvds_spmm_f32.argtypes = [ctypes.POINTER(_Csr), _P, ctypes.c_int, _P, _P, ctypes.c_int, _P]
+_lib.phsvds_transpose_ws_bytes.argtypes = [ctypes.POINTER(_Csr)]
+_lib.phsvds_transpose_ws_bytes.restype = ctypes.c_size_t
+_lib.phsvds_csr_transpose.argtypes = [ctypes.POINTER(_Csr), _P, _P, _P, _P, ctypes.c_size_t, _P]
+_lib.phsvds_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_int, ctypes.POINTER(_Opts),
+                                        ctypes.POINTER(ctypes.c_size_t)]
+_lib.phsvds_svds.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, ctypes.c_double,
+                             ctypes.POINTER(_Precond), ctypes.POINTER(_Opts), _P, ctypes.c_size_t,
+                             _P, _P, _P, _P, _P, ctypes.POINTER(_Stats)]
+
+
+_lib.phsvds_profile.argtypes = [ctypes.c_int]
+_lib.phsvds_profile_read.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+PROFILE_KINDS = {"spmm_f64": 0, "spmm_f32": 1, "tn": 2, "nn": 3, "ritz": 4}
+
+
+def profile(enable: bool) -> None:
+    """Start (clearing counters) or stop event timing of the library's kernels."""
+    _check(_lib.phsvds_profile(int(enable)), "profile")
+
+
+def profile_read(kind) -> tuple:
+    """(timed operations, device seconds, algorithmic bytes) for a kind."""
+    if isinstance(kind, str):
+        kind = PROFILE_KINDS[kind]
+    n = ctypes.c_int64(0)
+    s = ctypes.c_double(0)
+    b = ctypes.c_double(0)
+    _check(_lib.phsvds_profile_read(kind, ctypes.byref(n), ctypes.byref(s), ctypes.byref(b)),
+           "profile_read")
+    return int(n.value), float(s.value), float(b.value)
+
+
+def version() -> str:
+    return _lib.phsvds_version().decode()
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise RuntimeError(f"{what} failed ({rc}): {_lib.phsvds_last_error().decode()}")
+    return rc
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class DeviceCSR:
+    """CSR matrix on the GPU: rowptr int64 (m+1), colind int32, val float64."""
+    m: int
+    n: int
+    rowptr: torch.Tensor
+    colind: torch.Tensor
+    val: torch.Tensor
+
+    @property
+    def nnz(self):
+        return int(self.colind.numel())
+
+    @classmethod
+    def from_scipy(cls, A, device="cuda"):
+        A = A.tocsr()
+        A.sort_indices()
+        return cls(A.shape[0], A.shape[1],
+                   torch.as_tensor(A.indptr.astype("int64")).to(device),
+                   torch.as_tensor(A.indices.astype("int32")).to(device),
+                   torch.as_tensor(A.data.astype("float64")).to(device))
+
+    def _c(self):
+        assert self.rowptr.dtype == torch.int64 and self.colind.dtype == torch.int32
+        assert self.val.dtype == torch.float64 and self.rowptr.is_cuda
+        return _Csr(self.m, self.n, self.nnz, self.rowptr.data_ptr(), self.colind.data_ptr(),
+                    self.val.data_ptr())
+
+
+def spmm(A: DeviceCSR, X: torch.Tensor, absval: bool = False, val32: torch.Tensor | None = None):
+    """Y = A X for a row-major block X (n x b, b in 1,2,4,8,16,32), float64
+    or float32 (then ``val32`` holds the float32 values of A)."""
+    assert X.is_cuda and X.is_contiguous() and X.shape[0] == A.n
+    b = 1 if X.dim() == 1 else X.shape[1]
+    Y = torch.empty((A.m,) + tuple(X.shape[1:]), dtype=X.dtype, device=X.device)
+    c = A._c()
+    if X.dtype == torch.float64:
+        _check(_lib.phsvds_spmm_f64(ctypes.byref(c), b, X.data_ptr(), Y.data_ptr(), int(absval),
+                                    _stream()), "spmm")
+    elif X.dtype == torch.float32:
+        if val32 is None:
+            val32 = A.val.float()
+        _check(_lib.phsvds_spmm_f32(ctypes.byref(c), val32.data_ptr(), b, X.data_ptr(),
+                                    Y.data_ptr(), int(absval), _stream()), "spmm")
+    else:
+        raise TypeError(X.dtype)
+    return Y
+
+
+def csr_transpose(A: DeviceCSR) -> DeviceCSR:
+    c = A._c()
+    dev = A.rowptr.device
+    trp = torch.empty(A.n + 1, dtype=torch.int64, device=dev)
+    tci = torch.empty(max(A.nnz, 1), dtype=torch.int32, device=dev)
+    tva = torch.empty(max(A.nnz, 1), dtype=torch.float64, device=dev)
+    wsb = _lib.phsvds_transpose_ws_bytes(ctypes.byref(c))
+    ws = torch.empty(max(int(wsb), 1), dtype=torch.uint8, device=dev)
+    _check(_lib.phsvds_csr_transpose(ctypes.byref(c), trp.data_ptr(), tci.data_ptr(),
+                                     tva.data_ptr(), ws.data_ptr(), wsb, _stream()), "transpose")
+    return DeviceCSR(A.n, A.m, trp, tci[:A.nnz], tva[:A.nnz])
+
+
+def make_opts(which="smallest", block=1, max_basis=0, min_restart=0, stage1_fp32=False,
+              fp64_continue=True, stage2="auto", max_restarts=10000, max_matvecs=0, seed=1,
+              init_block=None, anorm=0.0, floor_factor=10.0):
+    o = _Opts()
+    _lib.phsvds_default_opts(ctypes.byref(o))
+    o.which = {"smallest": 0, "largest": 1}[which]
+    o.block = block
+    o.max_basis = max_basis
+    o.min_restart = min_restart
+    o.stage1_fp32 = int(stage1_fp32)
+    o.fp64_continue = int(fp64_continue)
+    o.stage2 = {"auto": 0, "force": 1, "never": -1}[stage2]
+    o.max_restarts = max_restarts
+    o.max_matvecs = max_matvecs
+    o.seed = seed
+    keep = None
+    if init_block is not None:
+        # (n x b) tensor -> n x b column-major device array
+        keep = init_block.to(dtype=torch.float64, device="cuda").t().contiguous()
+        o.init_block = keep.data_ptr()
+    o.anorm = float(anorm)
+    o.floor_factor = floor_factor
+    o._keep = keep
+    return o
+
+
+def workspace_bytes(m, n, nnz, k, opts) -> int:
+    out = ctypes.c_size_t(0)
+    _check(_lib.phsvds_workspace_bytes(m, n, nnz, k, ctypes.byref(opts), ctypes.byref(out)),
+           "workspace_bytes")
+    return int(out.value)
+
+
+class Solver:
+    """Holds the workspace for repeated solves of one problem shape."""
+
+    def __init__(self, A: DeviceCSR, k: int, **opt_kw):
+        self.A, self.k = A, k
+        self.opts = make_opts(**opt_kw)
+        nbytes = workspace_bytes(A.m, A.n, A.nnz, k, self.opts)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=A.rowptr.device)
+        self.U = torch.empty((k, A.m), dtype=torch.float64, device=A.rowptr.device)
+        self.V = torch.empty((k, A.n), dtype=torch.float64, device=A.rowptr.device)
+
+    def solve(self, tol=1e-12, precond="none"):
+        import numpy as np
+        k = self.k
+        sig = (ctypes.c_double * k)()
+        res = (ctypes.c_double * k)()
+        st = _Stats()
+        pc = _Precond(PREC[precond], None, 0)
+        c = self.A._c()
+        rc = _lib.phsvds_svds(ctypes.byref(c), k, tol, ctypes.byref(pc), ctypes.byref(self.opts),
+                              self.ws.data_ptr(), self.ws.numel(), _stream(), sig,
+                              self.U.data_ptr(), self.V.data_ptr(), res, ctypes.byref(st))
+        _check(rc, "svds")
+        info = st.as_dict(k)
+        info["status"] = rc
+        info["res"] = np.array(res[:])
+        # column-major m x k == row-major k x m: transpose views
+        return np.array(sig[:]), self.U.T, self.V.T, info
+
+
+def svds_smallest(A: DeviceCSR, k: int, tol: float = 1e-12, precond: str = "none", **opt_kw):
+    """The k smallest (``which='largest'``: largest) singular triplets of A
+    to sqrt(||r_u||^2 + ||r_v||^2) <= tol ||A||.  Returns
+    (sigma, U (m x k), V (n x k), info)."""
+    return Solver(A, k, **opt_kw).solve(tol, precond)

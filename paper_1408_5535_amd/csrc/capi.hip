@@ -1,0 +1,616 @@
+// C ABI of libphsvds: argument checks, workspace planning, setup (CSR of
+// A^T, float32 copies, row bins, diag(C)), the two-stage driver and the
+// final float64 residual check.  No exception crosses the boundary.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+
+#include "solver.hpp"
+
+namespace phs {
+namespace {
+
+thread_local std::string g_err;
+
+double wall() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+template <typename F>
+int guarded(F &&f) {
+  try {
+    g_err.clear();
+    return f();
+  } catch (const Error &e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::exception &e) {
+    g_err = e.what();
+    return PHSVDS_EBREAKDOWN;
+  }
+}
+
+struct Dims {
+  int64_t m, n, nnz;
+  int k, b, bw, pmax, pmin;
+  bool fp32, cont, jac;
+};
+
+int width_for(int b) {
+  int w = 1;
+  while (w < b) w *= 2;
+  return w;
+}
+
+bool make_dims(int64_t m, int64_t n, int64_t nnz, int k, const phsvds_opts &o, Dims &d) {
+  d.m = m;
+  d.n = n;
+  d.nnz = nnz;
+  d.k = k;
+  d.b = o.block > 0 ? o.block : 1;
+  if (d.b > 16) return false;
+  d.bw = width_for(d.b);
+  d.pmax = o.max_basis > 0 ? o.max_basis : std::max(35, 2 * k + 2 * d.b);
+  d.pmin = o.min_restart > 0 ? o.min_restart : std::max(21, (int)std::ceil(0.6 * d.pmax));
+  d.pmin = std::min(d.pmin, d.pmax - 2 * d.b);
+  d.fp32 = o.stage1_fp32 != 0;
+  d.cont = d.fp32 && o.fp64_continue != 0;
+  d.jac = false;
+  return d.pmax <= 64 && d.pmin >= d.b && d.pmin >= 1 && k >= 1 && k <= 24 && k < d.pmax;
+}
+
+template <typename T>
+void take_stage1(Arena &ar, const Dims &d, Stage1Bufs<T> &b) {
+  for (int i = 0; i < 2; ++i) {
+    b.V[i] = ar.take<T>(d.n * d.pmax);
+    b.W[i] = ar.take<T>(d.n * d.pmax);
+  }
+  b.Xl = ar.take<T>(d.n * d.k);
+  b.Xb = ar.take<T>(d.n * d.bw);
+  b.Rb = ar.take<T>(d.n * d.bw);
+  b.Tb = ar.take<T>(d.n * d.bw);
+  b.T2b = ar.take<T>(d.n * d.bw);
+  b.WTb = ar.take<T>(d.n * d.bw);
+  b.Fb = ar.take<T>(d.n * d.bw);
+  b.Yb = ar.take<T>(d.m * d.bw);
+}
+
+struct Plan {
+  int64_t *trp;
+  int32_t *tci;
+  double *tva;
+  char *tws;
+  size_t tws_bytes;
+  int32_t *binA, *binAt, *binScr;
+  float *va32, *tva32;
+  double *diagC;
+  Scratch sc;
+  int *didx;
+  double *pool;
+  Stage1Bufs<float> s32;
+  Stage1Bufs<double> s64;
+  double *Xs, *Vr64;
+  TransBufs tb;
+  Stage2Bufs s2;
+  double *Vf, *Uf, *AV, *RU, *RV, *Fx, *Fy;
+};
+
+void carve(Arena &ar, const Dims &d, Plan &p) {
+  const int64_t m = d.m, n = d.n, N = m + n, nnz = d.nnz;
+  const int pz = std::max(d.k, d.pmin);
+  p.trp = ar.take<int64_t>(n + 1);
+  p.tci = ar.take<int32_t>(std::max<int64_t>(nnz, 1));
+  p.tva = ar.take<double>(std::max<int64_t>(nnz, 1));
+  p.tws_bytes = transpose_ws_bytes(m, n, nnz);
+  p.tws = ar.take<char>(p.tws_bytes);
+  p.binA = ar.take<int32_t>(m);
+  p.binAt = ar.take<int32_t>(n);
+  p.binScr = ar.take<int32_t>(16);
+  p.va32 = d.fp32 ? ar.take<float>(nnz) : nullptr;
+  p.tva32 = d.fp32 ? ar.take<float>(nnz) : nullptr;
+  p.diagC = ar.take<double>(n);
+  p.sc.part = ar.take<double>(kPartCap);
+  p.sc.aux = ar.take<double>(kAuxCap);
+  p.sc.flag = ar.take<int>(64);
+  p.didx = ar.take<int>(256);
+  p.pool = ar.take<double>(SmallPool::bytes() / 8);
+  if (d.fp32) take_stage1<float>(ar, d, p.s32);
+  if (!d.fp32 || d.cont) take_stage1<double>(ar, d, p.s64);
+  p.Xs = ar.take<double>(n * d.k);
+  p.Vr64 = ar.take<double>(n * d.pmax);
+  p.tb.Z = ar.take<double>(n * pz);
+  p.tb.AZ = ar.take<double>(m * pz);
+  p.tb.QZ = ar.take<double>(m * pz);
+  p.tb.Vt = ar.take<double>(n * d.k);
+  p.tb.Ut = ar.take<double>(m * d.k);
+  p.tb.Xn = ar.take<double>(n * d.bw);
+  p.tb.Ym = ar.take<double>(m * d.bw);
+  for (int i = 0; i < 2; ++i) {
+    p.s2.V[i] = ar.take<double>(N * d.pmax);
+    p.s2.W[i] = ar.take<double>(N * d.pmax);
+    p.s2.Q[i] = ar.take<double>(N * d.pmax);
+  }
+  p.s2.Xl = ar.take<double>(N * d.k);
+  p.s2.Y0 = ar.take<double>(N * d.k);
+  double **blk[] = {&p.s2.Tb, &p.s2.T2b, &p.s2.WTb, &p.s2.Xb, &p.s2.Rb, &p.s2.Cb, &p.s2.C2b};
+  for (double **q : blk) *q = ar.take<double>(N * d.bw);
+  p.Vf = ar.take<double>(n * d.k);
+  p.Uf = ar.take<double>(m * d.k);
+  p.AV = ar.take<double>(m * d.k);
+  p.RU = ar.take<double>(n * d.k);
+  p.RV = ar.take<double>(m * d.k);
+  p.Fx = ar.take<double>(std::max(n, m) * 8);
+  p.Fy = ar.take<double>(std::max(n, m) * 8);
+}
+
+// Y (rows_out x w, column-major) = op(A) X (column-major), in chunks of 8.
+void apply_cols(Ctx &c, const SpMat<double> &A, const double *X, int w, double *Y, double *Fx,
+                double *Fy) {
+  for (int c0 = 0; c0 < w; c0 += 8) {
+    int cw = std::min(8, w - c0);
+    Tall<double> src = cm(const_cast<double *>(X) + c0 * A.n, A.n, cw, A.n);
+    Tall<double> fx = {Fx, A.n, cw, 8, 1};
+    copy(src, fx, c.s);
+    spmm(A, 8, Fx, Fy, false, c.s);
+    Tall<double> fy = {Fy, A.m, cw, 8, 1};
+    copy(fy, cm(Y + c0 * A.m, A.m, cw, A.m), c.s);
+  }
+}
+
+__global__ void k_sign_fix(double *V, int64_t n, double *U, int64_t m) {
+  __shared__ double bv[256];
+  __shared__ int64_t bi[256];
+  const int j = blockIdx.x;
+  double *v = V + (int64_t)j * n;
+  double best = -1.0;
+  int64_t bidx = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    double a = fabs(v[i]);
+    if (a > best) {
+      best = a;
+      bidx = i;
+    }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = bidx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      double a = bv[threadIdx.x + o];
+      int64_t ai = bi[threadIdx.x + o];
+      if (a > bv[threadIdx.x] || (a == bv[threadIdx.x] && ai < bi[threadIdx.x])) {
+        bv[threadIdx.x] = a;
+        bi[threadIdx.x] = ai;
+      }
+    }
+    __syncthreads();
+  }
+  const double sg = v[bi[0]] < 0 ? -1.0 : 1.0;
+  __syncthreads();
+  if (sg < 0) {
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v[i] = -v[i];
+    double *u = U + (int64_t)j * m;
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) u[i] = -u[i];
+  }
+}
+
+int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc,
+              const phsvds_opts *oin, void *ws, size_t ws_bytes, void *stream, double *sigma,
+              double *Uout, double *Vout, double *resnorm, phsvds_stats *stats) {
+  const double t0 = wall();
+  PHS_REQUIRE(Ain && sigma && Uout && Vout && resnorm, kEinval, "null argument");
+  phsvds_opts o;
+  phsvds_default_opts(&o);
+  if (oin) o = *oin;
+  phsvds_stats stl;
+  std::memset(&stl, 0, sizeof(stl));
+  const int64_t m = Ain->m, n = Ain->n, nnz = Ain->nnz;
+  PHS_REQUIRE(m >= n && n >= 1 && nnz >= 0 && nnz < (int64_t(1) << 31), kEinval,
+              "need m >= n >= 1 and nnz < 2^31");
+  PHS_REQUIRE(tol > 0, kEinval, "tol must be positive");
+  PHS_REQUIRE(k <= n, kEinval, "k must not exceed n");
+  int pkind = Pc ? Pc->kind : PHSVDS_PREC_NONE;
+  PHS_REQUIRE(pkind == PHSVDS_PREC_NONE || pkind == PHSVDS_PREC_JACOBI, kEinval,
+              "unsupported preconditioner kind");
+  Dims d;
+  PHS_REQUIRE(make_dims(m, n, nnz, k, o, d), kEinval,
+              "unsupported sizes: need 1 <= k <= 24, block <= 16, max_basis <= 64");
+  d.jac = pkind == PHSVDS_PREC_JACOBI;
+  const bool largest = o.which == 1;
+  Arena ar;
+  ar.base = (char *)ws;
+  ar.size = ws_bytes;
+  Plan pl{};
+  carve(ar, d, pl);
+  Ctx c;
+  c.s = (hipStream_t)stream;
+  c.sc = pl.sc;
+  c.didx = pl.didx;
+  c.seed = o.seed;
+  c.st = &stl;
+  c.max_mv = o.max_matvecs;
+  SmallPool sp;
+  sp.base = pl.pool;
+  {
+    // identity used to copy small matrices through small_gemm
+    std::vector<double> eye((size_t)kSP * kSP, 0.0);
+    for (int i = 0; i < kSP; ++i) eye[i + (size_t)i * kSP] = 1.0;
+    c.h2d(sp.eye(), eye.data(), eye.size() * sizeof(double));
+  }
+  // ---------------------------------------------------------------- setup
+  SpMat<double> A64, At64;
+  A64.m = m;
+  A64.n = n;
+  A64.nnz = nnz;
+  A64.rowptr = Ain->rowptr;
+  A64.colind = Ain->colind;
+  A64.val = Ain->val;
+  csr_transpose(m, n, nnz, Ain->rowptr, Ain->colind, Ain->val, pl.trp, pl.tci, pl.tva, pl.tws,
+                pl.tws_bytes, c.s);
+  At64.m = n;
+  At64.n = m;
+  At64.nnz = nnz;
+  At64.rowptr = pl.trp;
+  At64.colind = pl.tci;
+  At64.val = pl.tva;
+  build_bins(m, A64.rowptr, pl.binA, pl.binScr, A64.bins, &A64.nbins, c.s);
+  A64.binrows = pl.binA;
+  if (A64.nbins == 1) A64.nbins = 0;
+  build_bins(n, At64.rowptr, pl.binAt, pl.binScr, At64.bins, &At64.nbins, c.s);
+  At64.binrows = pl.binAt;
+  if (At64.nbins == 1) At64.nbins = 0;
+  SpMat<float> A32, At32;
+  if (d.fp32) {
+    copy(cm(const_cast<double *>(Ain->val), nnz, 1, nnz), cm(pl.va32, nnz, 1, nnz), c.s);
+    copy(cm(pl.tva, nnz, 1, nnz), cm(pl.tva32, nnz, 1, nnz), c.s);
+    A32.m = m; A32.n = n; A32.nnz = nnz; A32.rowptr = A64.rowptr; A32.colind = A64.colind;
+    A32.val = pl.va32; A32.nbins = A64.nbins; A32.binrows = A64.binrows;
+    std::memcpy(A32.bins, A64.bins, sizeof(A64.bins));
+    At32.m = n; At32.n = m; At32.nnz = nnz; At32.rowptr = At64.rowptr; At32.colind = At64.colind;
+    At32.val = pl.tva32; At32.nbins = At64.nbins; At32.binrows = At64.binrows;
+    std::memcpy(At32.bins, At64.bins, sizeof(At64.bins));
+  }
+  if (d.jac) col_sq_norms(At64, pl.diagC, c.s);
+  c.sync();
+  const double t1 = wall();
+  stl.t_setup = t1 - t0;
+  // -------------------------------------------------------------- stage 1
+  Stage1Params P1{};
+  P1.k = k;
+  P1.b = d.b;
+  P1.bw = d.bw;
+  P1.pmax = d.pmax;
+  P1.pmin = d.pmin;
+  P1.largest = largest;
+  P1.tol = tol;
+  P1.floor = o.floor_factor > 0 ? o.floor_factor : 10.0;
+  P1.anorm = o.anorm;
+  P1.sn2_init = 0.0;
+  P1.max_restarts = o.max_restarts > 0 ? o.max_restarts : 10000;
+  P1.max_iters = 0;
+  P1.jacobi_d = d.jac ? pl.diagC : nullptr;
+  P1.init64 = o.init_block;
+  P1.init32 = nullptr;
+  P1.init_cols = d.b;
+  Stage1Result r1;
+  const double *Xl64 = nullptr, *Vr64 = nullptr;
+  int nvr = 0;
+  if (d.fp32) {
+    r1 = run_stage1<float>(c, A32, At32, P1, pl.s32, sp);
+    stl.fp32_locked = r1.nl;
+    stl.iters1 += r1.iters;
+    stl.restarts1 += r1.restarts;
+    if (d.cont) {
+      // continue stage 1 in float64 from the float32 basis
+      const int extra = std::min(r1.p, std::max(0, d.pmin - r1.nl));
+      double *init = pl.s64.V[1];
+      copy(cm(pl.s32.Xl, n, r1.nl, n), cm(init, n, r1.nl, n), c.s);
+      if (extra)
+        copy(cm((float *)r1.Vrest, n, extra, n), cm(init + (int64_t)r1.nl * n, n, extra, n), c.s);
+      Stage1Params P2 = P1;
+      P2.init64 = init;
+      P2.init_cols = r1.nl + extra;
+      P2.sn2_init = r1.sn2;
+      if (P2.init_cols < d.b) P2.init_cols = d.b;
+      r1 = run_stage1<double>(c, A64, At64, P2, pl.s64, sp);
+      Xl64 = pl.s64.Xl;
+      Vr64 = (const double *)r1.Vrest;
+      nvr = r1.p;
+    } else {
+      // float32 results move to float64 buffers (re-sorted below)
+      copy(cm(pl.s32.Xl, n, r1.nl, n), cm(pl.Xs, n, r1.nl, n), c.s);
+      copy(cm((float *)r1.Vrest, n, r1.p, n), cm(pl.Vr64, n, r1.p, n), c.s);
+      Xl64 = pl.Xs;
+      Vr64 = pl.Vr64;
+      nvr = r1.p;
+    }
+  } else {
+    r1 = run_stage1<double>(c, A64, At64, P1, pl.s64, sp);
+    Xl64 = pl.s64.Xl;
+    Vr64 = (const double *)r1.Vrest;
+    nvr = r1.p;
+  }
+  stl.iters1 += d.fp32 && !d.cont ? 0 : r1.iters;
+  stl.restarts1 += d.fp32 && !d.cont ? 0 : r1.restarts;
+  c.sync();
+  const double t2 = wall();
+  stl.t_stage1 = t2 - t1;
+  const double sn = std::sqrt(r1.sn2);
+  stl.anorm_est = sn;
+  const double an = o.anorm > 0 ? o.anorm : sn;
+  const int nl = r1.nl;
+  // sort the locked pairs (ascending, or descending for largest)
+  std::vector<int> ord(nl);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    return largest ? r1.theta[a] > r1.theta[b] : r1.theta[a] < r1.theta[b];
+  });
+  double *Xs = (Xl64 == pl.Xs) ? pl.tb.Vt : pl.Xs;  // sorted copy
+  std::vector<double> s1(nl);
+  std::vector<bool> tight(nl);
+  for (int i = 0; i < nl; ++i) {
+    copy(cm(const_cast<double *>(Xl64) + (int64_t)ord[i] * n, n, 1, n),
+         cm(Xs + (int64_t)i * n, n, 1, n), c.s);
+    s1[i] = std::sqrt(std::max(r1.theta[ord[i]], 0.0));
+    tight[i] = r1.tight[ord[i]];
+    if (i < 64) stl.res_stage1[i] = r1.res[ord[i]];
+  }
+  if (Xs == pl.tb.Vt) {  // keep Xs away from the transition outputs
+    copy(cm(pl.tb.Vt, n, nl, n), cm(pl.Vf, n, nl, n), c.s);
+    Xs = pl.Vf;
+  }
+  // stage-2 entry (Section 3.1): pairs whose stage-1 test was floor-limited
+  int need2 = 0;
+  if (!largest && o.stage2 != -1 && nl > 0) {
+    if (o.stage2 == 1) {
+      need2 = nl;
+    } else {
+      for (int i = 0; i < nl; ++i) {
+        bool floor_limited =
+            d.fp32 && !d.cont ? !tight[i] : (tol * s1[i] < P1.floor * kEps64 * sn);
+        if (floor_limited) need2 = i + 1;
+      }
+    }
+  }
+  stl.stage2_pairs = need2;
+  bool conv = r1.converged && nl == k;
+  double *Vsrc = Xs, *Usrc = nullptr;
+  if (need2 > 0) {
+    std::vector<double> shifts;
+    run_transition(c, A64, Xs, nl, Vr64, nvr, d.pmin, an, d.bw, pl.tb, sp, shifts);
+    Stage2Params P2{};
+    P2.k2 = need2;
+    P2.b = d.b;
+    P2.bw = d.bw;
+    P2.pmax = d.pmax;
+    P2.pmin = d.pmin;
+    P2.tol = tol;
+    P2.anorm = an;
+    P2.shifts = shifts.data();
+    P2.v0 = pl.tb.Vt;
+    P2.u0 = pl.tb.Ut;
+    P2.max_restarts = P1.max_restarts;
+    P2.max_iters = 0;
+    P2.jacobi_d = d.jac ? pl.diagC : nullptr;
+    Stage2Result r2 = run_stage2(c, A64, At64, P2, pl.s2, sp);
+    stl.iters2 = r2.iters;
+    stl.restarts2 = r2.restarts;
+    conv = conv && r2.converged;
+    // assemble: stage-2 pairs from [v; u], the rest from the transition
+    const int64_t N = m + n;
+    copy(cm(pl.tb.Vt, n, nl, n), cm(pl.Vf, n, nl, n), c.s);
+    copy(cm(pl.tb.Ut, m, nl, m), cm(pl.Uf, m, nl, m), c.s);
+    if (r2.nl) {
+      copy(cm(r2.Xl, n, r2.nl, N), cm(pl.Vf, n, r2.nl, n), c.s);
+      copy(cm(r2.Xl + n, m, r2.nl, N), cm(pl.Uf, m, r2.nl, m), c.s);
+    }
+    Vsrc = pl.Vf;
+    Usrc = pl.Uf;
+  } else {
+    if (Xs != pl.Vf) copy(cm(Xs, n, nl, n), cm(pl.Vf, n, nl, n), c.s);
+    Vsrc = pl.Vf;
+  }
+  c.sync();
+  const double t3 = wall();
+  stl.t_stage2 = t3 - t2;
+  // ------------------------------------------- final float64 check (Sec. 5)
+  double *nrm = sp.vec(20);
+  std::vector<double> f(nl), nh(nl);
+  if (nl > 0) {
+    colnorm2(cm(Vsrc, n, nl, n), 0, n, nrm, c.sc, c.s);
+    c.d2h(nh.data(), nrm, nl * sizeof(double));
+    c.sync();
+    for (int i = 0; i < nl; ++i) f[i] = nh[i] > 0 ? 1.0 / std::sqrt(nh[i]) : 0.0;
+    c.h2d(sp.vec(21), f.data(), nl * sizeof(double));
+    scale_cols(cm(Vsrc, n, nl, n), sp.vec(21), c.s);
+    apply_cols(c, A64, Vsrc, nl, pl.AV, pl.Fx, pl.Fy);
+    stl.mv_final += nl;
+    if (!Usrc) {
+      copy(cm(pl.AV, m, nl, m), cm(pl.Uf, m, nl, m), c.s);
+      Usrc = pl.Uf;
+    }
+    colnorm2(cm(Usrc, m, nl, m), 0, m, nrm, c.sc, c.s);
+    c.d2h(nh.data(), nrm, nl * sizeof(double));
+    c.sync();
+    for (int i = 0; i < nl; ++i) f[i] = nh[i] > 0 ? 1.0 / std::sqrt(nh[i]) : 0.0;
+    c.h2d(sp.vec(21), f.data(), nl * sizeof(double));
+    scale_cols(cm(Usrc, m, nl, m), sp.vec(21), c.s);
+  }
+  std::vector<double> sig(nl, 0.0), res(nl, 0.0);
+  if (nl > 0) {
+    double *G = sp.mat(31);
+    for (int c0 = 0; c0 < nl; c0 += 32) {
+      int w = std::min(32, nl - c0);
+      tn(cm(Usrc, m, nl, m), cm<double>(nullptr, m, 0, m), cm(pl.AV + (int64_t)c0 * m, m, w, m),
+         G + (int64_t)c0 * kSP, kSP, c.sc, c.s);
+    }
+    std::vector<double> gh((size_t)kSP * nl);
+    c.d2h(gh.data(), G, gh.size() * sizeof(double));
+    c.sync();
+    std::vector<double> flip(nl, 1.0), dneg((size_t)kSP * kSP, 0.0);
+    for (int i = 0; i < nl; ++i) {
+      sig[i] = gh[i + (size_t)i * kSP];
+      if (sig[i] < 0) {
+        flip[i] = -1.0;
+        sig[i] = -sig[i];
+      }
+      dneg[i + (size_t)i * kSP] = -sig[i];
+    }
+    c.h2d(sp.vec(21), flip.data(), nl * sizeof(double));
+    scale_cols(cm(Usrc, m, nl, m), sp.vec(21), c.s);
+    c.h2d(sp.mat(32), dneg.data(), dneg.size() * sizeof(double));
+    // r_v = A v - sigma u ; r_u = A^T u - sigma v
+    copy(cm(pl.AV, m, nl, m), cm(pl.RV, m, nl, m), c.s);
+    nn(cm(Usrc, m, nl, m), cm<double>(nullptr, m, 0, m), sp.mat(32), kSP, 1.0, cm(pl.RV, m, nl, m),
+       1.0, c.s);
+    apply_cols(c, At64, Usrc, nl, pl.RU, pl.Fx, pl.Fy);
+    nn(cm(Vsrc, n, nl, n), cm<double>(nullptr, n, 0, n), sp.mat(32), kSP, 1.0, cm(pl.RU, n, nl, n),
+       1.0, c.s);
+    std::vector<double> a(nl), bq(nl);
+    colnorm2(cm(pl.RV, m, nl, m), 0, m, nrm, c.sc, c.s);
+    c.d2h(a.data(), nrm, nl * sizeof(double));
+    c.sync();
+    colnorm2(cm(pl.RU, n, nl, n), 0, n, nrm, c.sc, c.s);
+    c.d2h(bq.data(), nrm, nl * sizeof(double));
+    c.sync();
+    for (int i = 0; i < nl; ++i) res[i] = std::sqrt(a[i] + bq[i]);
+  }
+  // order, sign convention, outputs
+  std::vector<int> fo(nl);
+  std::iota(fo.begin(), fo.end(), 0);
+  std::stable_sort(fo.begin(), fo.end(),
+                   [&](int a, int b) { return largest ? sig[a] > sig[b] : sig[a] < sig[b]; });
+  for (int i = 0; i < k; ++i) {
+    if (i < nl) {
+      int j = fo[i];
+      copy(cm(Vsrc + (int64_t)j * n, n, 1, n), cm(Vout + (int64_t)i * n, n, 1, n), c.s);
+      copy(cm(Usrc + (int64_t)j * m, m, 1, m), cm(Uout + (int64_t)i * m, m, 1, m), c.s);
+      sigma[i] = sig[j];
+      resnorm[i] = res[j];
+    } else {
+      PHS_HIP(hipMemsetAsync(Vout + (int64_t)i * n, 0, n * sizeof(double), c.s));
+      PHS_HIP(hipMemsetAsync(Uout + (int64_t)i * m, 0, m * sizeof(double), c.s));
+      sigma[i] = NAN;
+      resnorm[i] = INFINITY;
+    }
+  }
+  if (nl > 0) {
+    k_sign_fix<<<std::min(nl, k), 256, 0, c.s>>>(Vout, n, Uout, m);
+    PHS_CHECK_LAUNCH();
+  }
+  c.sync();
+  stl.t_total = wall() - t0;
+  if (stats) *stats = stl;
+  bool ok = conv && nl == k;
+  for (int i = 0; i < nl && ok; ++i) ok = res[i] <= tol * an * (1.0 + 1e-8);
+  return ok ? PHSVDS_OK : PHSVDS_NOT_CONVERGED;
+}
+
+}  // namespace
+}  // namespace phs
+
+using namespace phs;
+
+extern "C" {
+
+void phsvds_default_opts(phsvds_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->which = 0;
+  o->block = 1;
+  o->stage1_fp32 = 0;
+  o->fp64_continue = 1;
+  o->stage2 = 0;
+  o->max_restarts = 10000;
+  o->seed = 1;
+  o->floor_factor = 10.0;
+}
+
+const char *phsvds_version(void) { return "phsvds-mi355x 0.1 (gfx950)"; }
+
+const char *phsvds_last_error(void) { return g_err.c_str(); }
+
+int phsvds_spmm_f64(const phsvds_csr *A, int b, const double *X, double *Y, int absval,
+                    void *stream) {
+  return guarded([&]() {
+    PHS_REQUIRE(A && X && Y, kEinval, "null argument");
+    SpMat<double> S;
+    S.m = A->m;
+    S.n = A->n;
+    S.nnz = A->nnz;
+    S.rowptr = A->rowptr;
+    S.colind = A->colind;
+    S.val = A->val;
+    spmm(S, b, X, Y, absval != 0, (hipStream_t)stream);
+    return PHSVDS_OK;
+  });
+}
+
+int phsvds_spmm_f32(const phsvds_csr *A, const float *val32, int b, const float *X, float *Y,
+                    int absval, void *stream) {
+  return guarded([&]() {
+    PHS_REQUIRE(A && val32 && X && Y, kEinval, "null argument");
+    SpMat<float> S;
+    S.m = A->m;
+    S.n = A->n;
+    S.nnz = A->nnz;
+    S.rowptr = A->rowptr;
+    S.colind = A->colind;
+    S.val = val32;
+    spmm(S, b, X, Y, absval != 0, (hipStream_t)stream);
+    return PHSVDS_OK;
+  });
+}
+
+size_t phsvds_transpose_ws_bytes(const phsvds_csr *A) {
+  if (!A) return 0;
+  return transpose_ws_bytes(A->m, A->n, A->nnz);
+}
+
+int phsvds_csr_transpose(const phsvds_csr *A, int64_t *t_rowptr, int32_t *t_colind,
+                         double *t_val, void *ws, size_t ws_bytes, void *stream) {
+  return guarded([&]() {
+    PHS_REQUIRE(A && t_rowptr && t_colind && t_val, kEinval, "null argument");
+    PHS_REQUIRE(ws_bytes >= transpose_ws_bytes(A->m, A->n, A->nnz), kEnomem,
+                "transpose workspace too small");
+    csr_transpose(A->m, A->n, A->nnz, A->rowptr, A->colind, A->val, t_rowptr, t_colind, t_val,
+                  ws, ws_bytes, (hipStream_t)stream);
+    return PHSVDS_OK;
+  });
+}
+
+int phsvds_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int k, const phsvds_opts *oin,
+                           size_t *bytes) {
+  return guarded([&]() {
+    PHS_REQUIRE(bytes, kEinval, "null argument");
+    phsvds_opts o;
+    phsvds_default_opts(&o);
+    if (oin) o = *oin;
+    Dims d;
+    PHS_REQUIRE(m >= n && n >= 1 && make_dims(m, n, nnz, k, o, d), kEinval,
+                "unsupported sizes: need m >= n, 1 <= k <= 24, block <= 16, max_basis <= 64");
+    Arena ar;
+    ar.dry = true;
+    Plan pl{};
+    carve(ar, d, pl);
+    *bytes = ar.used;
+    return PHSVDS_OK;
+  });
+}
+
+int phsvds_svds(const phsvds_csr *A, int k, double tol, const phsvds_precond *P,
+                const phsvds_opts *opts, void *workspace, size_t ws_bytes, void *stream,
+                double *sigma, double *U, double *V, double *resnorm, phsvds_stats *stats) {
+  return guarded([&]() {
+    return svds_impl(A, k, tol, P, opts, workspace, ws_bytes, stream, sigma, U, V, resnorm,
+                     stats);
+  });
+}
+
+}  // extern "C"

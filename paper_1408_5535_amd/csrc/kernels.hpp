@@ -1,0 +1,164 @@
+// Host-side launchers of the PHSVDS device kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace phs {
+
+// ------------------------------------------------------------------ sparse
+struct Bin {
+  int32_t offset, count, lanes;
+};
+
+// CSR matrix on the device in working precision T.
+template <typename T>
+struct SpMat {
+  int64_t m = 0, n = 0, nnz = 0;
+  const int64_t *rowptr = nullptr;
+  const int32_t *colind = nullptr;
+  const T *val = nullptr;
+  int nbins = 0;  // 0: one launch over all rows
+  Bin bins[8];
+  const int32_t *binrows = nullptr;
+};
+
+int lanes_for_length(double avg);
+template <typename T>
+void spmm(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, hipStream_t s);
+size_t transpose_ws_bytes(int64_t m, int64_t n, int64_t nnz);
+void csr_transpose(int64_t m, int64_t n, int64_t nnz, const int64_t *rp, const int32_t *ci,
+                   const double *va, int64_t *trp, int32_t *tci, double *tva, void *ws,
+                   size_t ws_bytes, hipStream_t s);
+void build_bins(int64_t m, const int64_t *rp, int32_t *rows, int32_t *scratch, Bin *bins,
+                int *nbins, hipStream_t s);
+
+// ------------------------------------------------------------- tall blocks
+// A tall matrix view: element (i, j) at p[i * rs + j * cs].  Column-major
+// storage has rs = 1, cs = ld; a row-major block of width w has rs = w, cs = 1.
+template <typename T>
+struct Tall {
+  T *p = nullptr;
+  int64_t rows = 0;
+  int cols = 0;
+  int64_t rs = 1, cs = 0;
+  T *col(int j) const { return p + (int64_t)j * cs; }
+};
+template <typename T>
+inline Tall<T> cm(T *p, int64_t rows, int cols, int64_t ld) {
+  Tall<T> t;
+  t.p = p;
+  t.rows = rows;
+  t.cols = cols;
+  t.rs = 1;
+  t.cs = ld;
+  return t;
+}
+template <typename T>
+inline Tall<T> rm(T *p, int64_t rows, int cols) {
+  Tall<T> t;
+  t.p = p;
+  t.rows = rows;
+  t.cols = cols;
+  t.rs = cols;
+  t.cs = 1;
+  return t;
+}
+
+// Reduction scratch for the tall-skinny products.
+struct Scratch {
+  double *part = nullptr;  // partial sums, kPartCap doubles
+  double *aux = nullptr;   // small results, kAuxCap doubles
+  int *flag = nullptr;     // status flags (64 ints)
+};
+constexpr int64_t kPartCap = 1 << 21;
+constexpr int64_t kAuxCap = 1 << 16;
+
+// G (nx x ny, ld ldg, float64) = X^T Y, X = [X1 | X2] (X2 may have 0 cols).
+template <typename T>
+void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int ldg,
+        const Scratch &sc, hipStream_t s);
+// Y = alpha * [X1 | X2] S + beta * Y, S float64 (nx x ny, ld lds).
+template <typename T>
+void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double alpha,
+        const Tall<T> &Y, double beta, hipStream_t s);
+// Ritz block: X = V S, R = W S - X diag(theta) (row-major outputs, row stride ldx),
+// rn2[j] = ||R_:,j||^2; if ntop > 0 also xt2[j] = ||X_{0:ntop, j}||^2.
+template <typename T>
+void ritz(const Tall<T> &V, const Tall<T> &W, const double *S, int lds, const double *theta,
+          T *X, T *R, int nb, int ldx, double *rn2, double *xt2, int64_t ntop,
+          const Scratch &sc, hipStream_t s);
+// out[j] = sum_i X(i, j)^2 over rows [r0, r1) (float64 result, device).
+template <typename T>
+void colnorm2(const Tall<T> &X, int64_t r0, int64_t r1, double *out, const Scratch &sc,
+              hipStream_t s);
+// dst = src elementwise (any layouts, same shape), with type conversion.
+template <typename Ti, typename To>
+void copy(const Tall<Ti> &src, const Tall<To> &dst, hipStream_t s);
+// X(:, j) *= f[j] (f on device).
+template <typename T>
+void scale_cols(const Tall<T> &X, const double *f, hipStream_t s);
+// Y = X - shift * Z (same shapes).
+template <typename T>
+void axpby(const Tall<T> &X, const Tall<T> &Z, double shift, const Tall<T> &Y, hipStream_t s);
+// Column j of X := counter-based uniform(-0.5, 0.5) stream (seed, stream_id + j).
+template <typename T>
+void fill_random(const Tall<T> &X, uint64_t seed, uint64_t stream_id, hipStream_t s);
+// Jacobi: T = (d - theta_j)^-1 R, Olsen form if olsen (X = Ritz block).
+template <typename T>
+void jacobi_apply(const T *R, const T *X, const double *d, const double *theta, int64_t n,
+                  int nb, int ldx, bool olsen, T *Tout, const Scratch &sc, hipStream_t s);
+// d[j] = ||A_:,j||^2 from the CSR of A^T (row j of A^T is column j of A).
+void col_sq_norms(const SpMat<double> &At, double *d, hipStream_t s);
+// element-wise multiply rows: Y(i, :) = X(i, :) * w[i] (or / w[i] if inv).
+template <typename T>
+void row_scale(const T *X, const double *w, int64_t n, int b, bool inv, T *Y, hipStream_t s);
+
+// -------------------------------------------------- small dense (float64)
+// Symmetric eigendecomposition by cyclic Jacobi (one workgroup):
+// H (p x p, ld ldh) -> theta (p), S (p x p, ld lds); ascending, or
+// descending if `descending`.  H is not modified.
+void syevj(const double *H, int ldh, int p, bool descending, double *theta, double *S, int lds,
+           hipStream_t s);
+// One-sided Jacobi SVD of M (rows x cols, ld ldm, rows >= cols): singular
+// values ascending in sv, right vectors in Y (cols x cols, ld ldy).
+void svdj(const double *M, int ldm, int rows, int cols, double *sv, double *Y, int ldy,
+          hipStream_t s);
+// Cholesky G + shift I = R^T R (w x w) and Rinv = R^-1 (upper triangular,
+// ld ldr).  flag[0] = 1 on breakdown (non-positive pivot).
+void chol_inv(const double *G, int ldg, int w, double shift, double *R, double *Rinv, int ldr,
+              int *flag, hipStream_t s);
+// C = alpha op(A) op(B) + beta C, all small float64.
+void small_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const double *A, int lda,
+                const double *B, int ldb, double beta, double *C, int ldc, hipStream_t s);
+// Y = [K | orth(P against K)] (rows x (kc + kept)); dependent columns of P
+// are dropped; count[0] = kc + kept.
+void restart_basis(const double *K, int ldk, int rows, int kc, const double *P, int ldp, int pc,
+                   double *Y, int ldy, int *count, hipStream_t s);
+// Thin QR by two-pass modified Gram-Schmidt: M (rows x cols) = Q R.
+void small_qr(const double *M, int ldm, int rows, int cols, double *Q, int ldq, double *R,
+              int ldr, hipStream_t s);
+// H(0:p+nb, p:p+nb) = G, H(p:p+nb, 0:p) = G(0:p)^T, symmetrised diagonal block.
+void h_border(double *H, int ldh, int p, int nb, const double *G, int ldg, hipStream_t s);
+// Copy columns idx[0..nc) of A (rows x *) into B; idx on device.
+void gather_cols(const double *A, int lda, int rows, const int *idx, int nc, double *B, int ldb,
+                 hipStream_t s);
+// H = diag(d[idx[0..nc)]).
+void set_diag(double *H, int ldh, int nc, const double *d, const int *idx, hipStream_t s);
+// Zero rows [r0, r1) of a small matrix with nc columns.
+void zero_rows(double *A, int lda, int r0, int r1, int nc, hipStream_t s);
+// theta[j] = y_j^T H y_j for columns of Y (p x nc).
+void rayleigh_small(const double *H, int ldh, int p, const double *Y, int ldy, int nc,
+                    double *theta, hipStream_t s);
+
+// B += alpha A (small).
+void small_add(int M, int N, double alpha, const double *A, int lda, double *B, int ldb,
+               hipStream_t s);
+// Normalise a column from its squared norm on the device (zero if tiny).
+template <typename T>
+void norm_col(T *x, int64_t rows, const double *n2, double tiny, double *Rjj, hipStream_t s);
+// p[i * rs] = v for i < rows.
+template <typename T>
+void fill_const_col(T *p, int64_t rows, int64_t rs, double v, hipStream_t s);
+
+}  // namespace phs

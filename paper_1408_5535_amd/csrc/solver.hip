@@ -1,0 +1,717 @@
+// PHSVDS host orchestration: stage 1 (block GD+k on C = A^T A, Algorithm 1
+// with the dynamic tolerance of Section 3.1), the post-processing
+// Rayleigh-Ritz (Section 3.1), stage 2 (GD+k with the refined projection on
+// B = [0 A^T; A 0], Algorithm 2) and the final float64 residual check
+// (Section 5).  Every numerical step runs in the device kernels; the host
+// only reads Ritz values, residual norms and dependency flags (a few
+// hundred bytes per iteration) to take the method's control decisions.
+#include "solver.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace phs {
+
+void Ctx::d2h(void *h, const void *d, size_t bytes) {
+  PHS_HIP(hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s));
+}
+void Ctx::sync() { PHS_HIP(hipStreamSynchronize(s)); }
+void Ctx::h2d(void *d, const void *h, size_t bytes) {
+  // pageable source: the runtime stages it before returning
+  PHS_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
+  PHS_HIP(hipStreamSynchronize(s));
+}
+
+template <typename T>
+static Tall<T> rmv(T *p, int64_t rows, int cols, int bw) {
+  Tall<T> t;
+  t.p = p;
+  t.rows = rows;
+  t.cols = cols;
+  t.rs = bw;
+  t.cs = 1;
+  return t;
+}
+template <typename T>
+static Tall<T> none(int64_t rows) {
+  Tall<T> t;
+  t.p = nullptr;
+  t.rows = rows;
+  t.cols = 0;
+  t.rs = 1;
+  t.cs = 1;
+  return t;
+}
+
+// ------------------------------------------------------------------------
+// Block orthonormalisation: T (n x nb, row-major stride bw) against the
+// bases [B1 | B2] by two Gram-Schmidt passes (a third when the second still
+// removes more than half), then CholQR2 within the block.  Columns whose
+// norm drops by more than 1/dep_drop are replaced by random vectors; a
+// Cholesky breakdown falls back to shifted CholQR3.
+template <typename T>
+void orth_block(Ctx &c, T *&Tb, T *&T2b, int64_t n, int nb, int bw, const Tall<T> &B1,
+                const Tall<T> &B2, double dep_drop, SmallPool &sp) {
+  const Tall<T> none1 = none<T>(n);
+  const double u = std::is_same<T, float>::value ? kEps32 / 2 : kEps64 / 2;
+  double *n0 = sp.vec(0), *n1 = sp.vec(1);
+  double *G = sp.mat(0), *Gram = sp.mat(1), *R1 = sp.mat(2), *Ri1 = sp.mat(3);
+  const int ld = kSP;
+  bool shifted = false;
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    Tall<T> Tv = rmv(Tb, n, nb, bw);
+    colnorm2(Tv, 0, n, n0, c.sc, c.s);
+    int passes = 2;
+    for (int pass = 0; pass < passes; ++pass) {
+      if (B1.cols + B2.cols > 0) {
+        tn(B1, B2, Tv, G, ld, c.sc, c.s);
+        nn(B1, B2, G, ld, -1.0, Tv, 1.0, c.s);
+      }
+      if (pass == 0) colnorm2(Tv, 0, n, n1, c.sc, c.s);
+    }
+    tn(Tv, none1, Tv, Gram, ld, c.sc, c.s);
+    double h0[64], h1[64], hg[64 * 64];
+    c.d2h(h0, n0, nb * sizeof(double));
+    c.d2h(h1, n1, nb * sizeof(double));
+    c.d2h(hg, Gram, (size_t)ld * nb * sizeof(double));
+    c.sync();
+    bool third = false;
+    std::vector<int> dep;
+    for (int j = 0; j < nb; ++j) {
+      double a0 = std::sqrt(std::max(h0[j], 0.0)), a1 = std::sqrt(std::max(h1[j], 0.0));
+      double a2 = std::sqrt(std::max(hg[j + j * ld], 0.0));
+      if (!(a0 > 0.0) || !(a2 > dep_drop * a0) || !std::isfinite(a2)) {
+        dep.push_back(j);
+      } else if (a2 < 0.5 * a1 && B1.cols + B2.cols > 0) {
+        third = true;
+      }
+    }
+    if (!dep.empty()) {
+      for (int j : dep) {
+        Tall<T> col = rmv(Tb + j, n, 1, bw);
+        fill_random(col, c.seed, 1000000 + (c.nrand++) * 64, c.s);
+      }
+      continue;
+    }
+    if (third) {
+      tn(B1, B2, Tv, G, ld, c.sc, c.s);
+      nn(B1, B2, G, ld, -1.0, Tv, 1.0, c.s);
+      tn(Tv, none1, Tv, Gram, ld, c.sc, c.s);
+    }
+    // CholQR: two passes, or shifted CholQR3 after a breakdown
+    int npass = 2;
+    double shift = 0.0;
+    if (shifted) {
+      double tr = 0.0;
+      for (int j = 0; j < nb; ++j) tr += hg[j + j * ld];
+      shift = 11.0 * ((double)n * nb + (double)nb * (nb + 1)) * u * tr;
+      npass = 3;
+    }
+    bool broke = false;
+    for (int q = 0; q < npass; ++q) {
+      if (q > 0) tn(rmv(Tb, n, nb, bw), none1, rmv(Tb, n, nb, bw), Gram, ld, c.sc, c.s);
+      chol_inv(Gram, ld, nb, q == 0 ? shift : 0.0, R1, Ri1, ld, c.sc.flag, c.s);
+      nn(rmv(Tb, n, nb, bw), none1, Ri1, ld, 1.0, rmv(T2b, n, nb, bw), 0.0, c.s);
+      std::swap(Tb, T2b);
+      int fl = 0;
+      c.d2h(&fl, c.sc.flag, sizeof(int));
+      c.sync();
+      if (fl) {
+        broke = true;
+        break;
+      }
+    }
+    if (!broke) return;
+    shifted = true;
+  }
+  throw Error(kEbreak, "orthogonalisation failed to produce an independent block");
+}
+template void orth_block<float>(Ctx &, float *&, float *&, int64_t, int, int, const Tall<float> &,
+                                const Tall<float> &, double, SmallPool &);
+template void orth_block<double>(Ctx &, double *&, double *&, int64_t, int, int,
+                                 const Tall<double> &, const Tall<double> &, double, SmallPool &);
+
+// Left-looking Gram-Schmidt (two passes) on columns [j0, j1) of a
+// column-major X against all previous columns; R(:, j) accumulates the
+// coefficients when R != nullptr.  Zero (or, if `random_dep`, random)
+// replacements for dependent columns.
+void cgs_cols(Ctx &c, double *X, int64_t rows, int64_t ld, int j0, int j1, double *R, int ldr,
+              bool random_dep, SmallPool &sp) {
+  double *g = sp.vec(2), *n2 = sp.vec(3), *n0 = sp.vec(4);
+  for (int j = j0; j < j1; ++j) {
+    Tall<double> xj = cm(X + (int64_t)j * ld, rows, 1, rows);
+    for (int attempt = 0; attempt < 4; ++attempt) {
+      if (random_dep) colnorm2(xj, 0, rows, n0, c.sc, c.s);
+      if (j > 0) {
+        Tall<double> Q = cm(X, rows, j, ld);
+        for (int pass = 0; pass < 2; ++pass) {
+          tn(Q, none<double>(rows), xj, g, kSP, c.sc, c.s);
+          nn(Q, none<double>(rows), g, kSP, -1.0, xj, 1.0, c.s);
+          if (R) small_add(j, 1, 1.0, g, kSP, R + (int64_t)j * ldr, ldr, c.s);
+        }
+      }
+      colnorm2(xj, 0, rows, n2, c.sc, c.s);
+      if (random_dep) {
+        double h[2];
+        c.d2h(h, n0, sizeof(double));
+        c.d2h(h + 1, n2, sizeof(double));
+        c.sync();
+        if (!(h[0] > 0.0) || !(std::sqrt(h[1]) > kDepDropF64 * std::sqrt(h[0]))) {
+          fill_random(xj, c.seed, 2000000 + (c.nrand++) * 64, c.s);
+          continue;
+        }
+      }
+      break;
+    }
+    norm_col(X + (int64_t)j * ld, rows, n2, 1e-300, R ? R + j + (int64_t)j * ldr : nullptr, c.s);
+  }
+}
+
+// ------------------------------------------------------------------------
+// Stage 1: block GD+k on C = A^T A in working precision T.
+template <typename T>
+Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Stage1Params &P,
+                        Stage1Bufs<T> &bf, SmallPool &sp) {
+  const int64_t n = A.n, m = A.m;
+  const int k = P.k, b = P.b, bw = P.bw, pmax = P.pmax, pmin = P.pmin;
+  const bool largest = P.largest;
+  const bool fp32 = std::is_same<T, float>::value;
+  const double eps = fp32 ? kEps32 : kEps64;
+  const double dep_drop = fp32 ? 1e-4 : kDepDropF64;
+  const int ld = kSP;
+  T *V[2] = {bf.V[0], bf.V[1]}, *W[2] = {bf.W[0], bf.W[1]};
+  int cur = 0, p = 0, nl = 0, nprev = 0;
+  T *Tb = bf.Tb, *T2b = bf.T2b, *Rb = bf.Rb;
+  double *H = sp.mat(4), *S = sp.mat(5), *Y = sp.mat(6), *Hs = sp.mat(7), *prev = sp.mat(8),
+         *prev2 = sp.mat(9), *Gb = sp.mat(10);
+  double *theta = sp.vec(5), *rn2 = sp.vec(6), *rho2 = sp.vec(7);
+  int *cnt = c.sc.flag + 8;
+  Stage1Result res;
+  res.sn2 = P.anorm > 0 ? P.anorm * P.anorm : P.sn2_init;
+  std::vector<double> rho_h(bw, 0.0);
+  int rho_age = 1 << 30;
+
+  auto applyC = [&](T *X, int nb) {
+    spmm(A, bw, X, bf.Yb, false, c.s);
+    spmm(At, bw, bf.Yb, bf.WTb, false, c.s);
+    c.st->mv_stage1 += nb;
+  };
+  auto expand = [&](int nb) {
+    orth_block(c, Tb, T2b, n, nb, bw, cm(bf.Xl, n, nl, n), cm(V[cur], n, p, n), dep_drop, sp);
+    applyC(Tb, nb);
+    copy(rmv(Tb, n, nb, bw), cm(V[cur] + (int64_t)p * n, n, nb, n), c.s);
+    copy(rmv(bf.WTb, n, nb, bw), cm(W[cur] + (int64_t)p * n, n, nb, n), c.s);
+    tn(cm(V[cur], n, p + nb, n), none<T>(n), rmv(bf.WTb, n, nb, bw), Gb, ld, c.sc, c.s);
+    h_border(H, ld, p, nb, Gb, ld, c.s);
+    if (nprev) zero_rows(prev, ld, p, p + nb, nprev, c.s);
+    p += nb;
+  };
+
+  // initial block (Section 5: ones(n,1)/sqrt(n) plus seeded random columns),
+  // or a caller-given basis, expanded in chunks of the block width
+  {
+    int w0 = P.init_cols > 0 ? P.init_cols : b;
+    for (int c0 = 0; c0 < w0; c0 += bw) {
+      int w = std::min(bw, w0 - c0);
+      if (P.init64) {
+        copy(cm(const_cast<double *>(P.init64) + (int64_t)c0 * n, n, w, n), rmv(Tb, n, w, bw), c.s);
+      } else if (P.init32) {
+        copy(cm(const_cast<float *>(P.init32) + (int64_t)c0 * n, n, w, n), rmv(Tb, n, w, bw), c.s);
+      } else {
+        fill_random(rmv(Tb, n, w, bw), c.seed, 17 + c0, c.s);
+        if (c0 == 0) fill_const_col(Tb, n, (int64_t)bw, 1.0 / std::sqrt((double)n), c.s);
+      }
+      expand(w);
+    }
+  }
+  std::vector<double> th_h(pmax), rn_h(bw), hist;
+  const int L = std::max(100, 20 * ((pmax + b - 1) / b));
+  int64_t it = 0;
+  while (true) {
+    ++it;
+    syevj(H, ld, p, largest, theta, S, ld, c.s);
+    const int nb = std::min(b, p);
+    ritz(cm(V[cur], n, p, n), cm(W[cur], n, p, n), S, ld, theta, bf.Xb, Rb, nb, bw, rn2, nullptr,
+         0, c.sc, c.s);
+    // componentwise accuracy floor of float32 C x (|A|^T |A| |x|), refreshed
+    if (fp32 && (rho_age >= 10)) {
+      // |x| of the block: the abs-SpMM takes |.| of every operand itself
+      spmm(A, bw, bf.Xb, bf.Yb, true, c.s);
+      spmm(At, bw, bf.Yb, bf.Fb, true, c.s);
+      colnorm2(rmv(bf.Fb, n, nb, bw), 0, n, rho2, c.sc, c.s);
+      c.st->mv_floor += nb;
+      double hr[64];
+      c.d2h(hr, rho2, nb * sizeof(double));
+      c.sync();
+      for (int j = 0; j < nb; ++j) rho_h[j] = std::sqrt(hr[j]);
+      rho_age = 0;
+    }
+    ++rho_age;
+    c.d2h(th_h.data(), theta, p * sizeof(double));
+    c.d2h(rn_h.data(), rn2, nb * sizeof(double));
+    c.sync();
+    for (int j = 0; j < p; ++j) res.sn2 = std::max(res.sn2, th_h[j]);
+    const double sn = std::sqrt(res.sn2);
+    const int need = k - nl;
+    std::vector<int> conv;
+    auto floor_of = [&](int i) {
+      return fp32 ? P.floor * eps * std::max(rho_h[i], 0.0) : P.floor * eps * res.sn2;
+    };
+    for (int i = 0; i < std::min(nb, need); ++i) {
+      double si = std::sqrt(std::max(th_h[i], 0.0));
+      double thr = std::max(P.tol * si * sn, floor_of(i));
+      if (std::sqrt(std::max(rn_h[i], 0.0)) < thr) conv.push_back(i);
+    }
+    bool stag = false;
+    if (conv.empty() && need > 0) {
+      double si0 = std::sqrt(std::max(th_h[0], 0.0));
+      double fl0 = floor_of(0);
+      if (P.tol * si0 * sn < fl0) {
+        double r0 = std::sqrt(std::max(rn_h[0], 0.0));
+        hist.push_back(r0);
+        if ((int)hist.size() > 2 * L && r0 < 10.0 * fl0) {
+          double a = *std::min_element(hist.end() - L, hist.end());
+          double bmin = *std::min_element(hist.begin(), hist.end() - L);
+          if (a > 0.9 * bmin) {
+            conv.push_back(0);
+            stag = true;
+          }
+        }
+      }
+    }
+    if (!conv.empty() && !stag) {
+      // lock on the explicit residual C x - theta x only: the recurrence
+      // W s - theta x drifts from it over restarts; on a mismatch rebuild
+      // W = C V and H = V^T W
+      applyC(bf.Xb, nb);
+      std::vector<double> dneg((size_t)kSP * nb, 0.0);
+      for (int j = 0; j < nb; ++j) dneg[j + (size_t)j * kSP] = -th_h[j];
+      c.h2d(sp.mat(33), dneg.data(), dneg.size() * sizeof(double));
+      nn(rmv(bf.Xb, n, nb, bw), none<T>(n), sp.mat(33), ld, 1.0, rmv(bf.WTb, n, nb, bw), 1.0,
+         c.s);
+      colnorm2(rmv(bf.WTb, n, nb, bw), 0, n, rho2 + 64, c.sc, c.s);
+      double rt[64];
+      c.d2h(rt, rho2 + 64, nb * sizeof(double));
+      c.sync();
+      bool all_ok = true;
+      for (int i : conv) {
+        double si = std::sqrt(std::max(th_h[i], 0.0));
+        double thr = std::max(P.tol * si * sn, floor_of(i));
+        if (!(std::sqrt(std::max(rt[i], 0.0)) < thr)) all_ok = false;
+      }
+      if (!all_ok) {
+        for (int c0 = 0; c0 < p; c0 += bw) {
+          int w = std::min(bw, p - c0);
+          copy(cm(V[cur] + (int64_t)c0 * n, n, w, n), rmv(Tb, n, w, bw), c.s);
+          applyC(Tb, w);
+          copy(rmv(bf.WTb, n, w, bw), cm(W[cur] + (int64_t)c0 * n, n, w, n), c.s);
+        }
+        for (int c0 = 0; c0 < p; c0 += 32) {
+          int w = std::min(32, p - c0);
+          tn(cm(V[cur], n, p, n), none<T>(n), cm(W[cur] + (int64_t)c0 * n, n, w, n),
+             H + (int64_t)c0 * ld, ld, c.sc, c.s);
+        }
+        nprev = 0;
+        ++res.refreshes;
+        continue;
+      }
+    }
+    if (!conv.empty()) {
+      hist.clear();
+      for (int i : conv) {
+        copy(rmv(bf.Xb + i, n, 1, bw), cm(bf.Xl + (int64_t)nl * n, n, 1, n), c.s);
+        res.theta.push_back(th_h[i]);
+        res.res.push_back(std::sqrt(std::max(rn_h[i], 0.0)));
+        res.tight.push_back(std::sqrt(std::max(rn_h[i], 0.0)) <
+                            P.tol * std::sqrt(std::max(th_h[i], 0.0)) * sn);
+        ++nl;
+      }
+      std::vector<int> keep;
+      for (int j = 0; j < p; ++j)
+        if (std::find(conv.begin(), conv.end(), j) == conv.end()) keep.push_back(j);
+      const int nk = (int)keep.size();
+      if (nk > 0) {
+        c.h2d(c.didx, keep.data(), nk * sizeof(int));
+        gather_cols(S, ld, p, c.didx, nk, Y, ld, c.s);
+        nn(cm(V[cur], n, p, n), none<T>(n), Y, ld, 1.0, cm(V[1 - cur], n, nk, n), 0.0, c.s);
+        nn(cm(W[cur], n, p, n), none<T>(n), Y, ld, 1.0, cm(W[1 - cur], n, nk, n), 0.0, c.s);
+        set_diag(H, ld, nk, theta, c.didx, c.s);
+        cur = 1 - cur;
+      }
+      p = nk;
+      nprev = 0;
+      if (nl >= k) {
+        res.converged = true;
+        break;
+      }
+      if (p == 0) {
+        fill_random(rmv(Tb, n, b, bw), c.seed, 3000000 + (c.nrand++) * 64, c.s);
+        expand(b);
+      }
+      continue;
+    }
+    const bool out_of_budget = res.restarts > P.max_restarts ||
+                               (c.max_mv > 0 && c.st->mv_stage1 > c.max_mv) ||
+                               (P.max_iters > 0 && it > P.max_iters);
+    if (out_of_budget) break;
+    // correction T = Prec(R)
+    if (P.jacobi_d) {
+      jacobi_apply<T>(Rb, bf.Xb, P.jacobi_d, theta, n, nb, bw, true, Tb, c.sc, c.s);
+    } else {
+      std::swap(Tb, Rb);
+    }
+    if (p + nb > pmax) {
+      restart_basis(S, ld, p, pmin, prev, ld, nprev, Y, ld, cnt, c.s);
+      int hc = 0;
+      c.d2h(&hc, cnt, sizeof(int));
+      c.sync();
+      nn(cm(V[cur], n, p, n), none<T>(n), Y, ld, 1.0, cm(V[1 - cur], n, hc, n), 0.0, c.s);
+      nn(cm(W[cur], n, p, n), none<T>(n), Y, ld, 1.0, cm(W[1 - cur], n, hc, n), 0.0, c.s);
+      small_gemm(false, false, p, hc, p, 1.0, H, ld, Y, ld, 0.0, Hs, ld, c.s);
+      small_gemm(true, false, hc, hc, p, 1.0, Y, ld, Hs, ld, 0.0, H, ld, c.s);
+      small_gemm(true, false, hc, nb, p, 1.0, Y, ld, S, ld, 0.0, prev2, ld, c.s);
+      std::swap(prev, prev2);
+      nprev = nb;
+      cur = 1 - cur;
+      p = hc;
+      ++res.restarts;
+    } else {
+      small_gemm(false, false, p, nb, p, 1.0, S, ld, sp.eye(), ld, 0.0, prev, ld, c.s);
+      nprev = nb;
+    }
+    expand(nb);
+  }
+  res.iters = it;
+  res.nl = nl;
+  res.p = p;
+  res.Vrest = V[cur];
+  bf.Tb = Tb;
+  bf.T2b = T2b;
+  bf.Rb = Rb;
+  return res;
+}
+template Stage1Result run_stage1<float>(Ctx &, const SpMat<float> &, const SpMat<float> &,
+                                        const Stage1Params &, Stage1Bufs<float> &, SmallPool &);
+template Stage1Result run_stage1<double>(Ctx &, const SpMat<double> &, const SpMat<double> &,
+                                         const Stage1Params &, Stage1Bufs<double> &,
+                                         SmallPool &);
+
+// ------------------------------------------------------------------------
+// Transition Rayleigh-Ritz on C over Z = orth([X_lock, leading restart
+// vectors]), evaluated as the SVD of A Z (same Ritz pairs, no squaring).
+void run_transition(Ctx &c, const SpMat<double> &A, const double *Xl, int k, const double *Vr,
+                    int nvr, int pmin, double anorm, int bw, TransBufs &tb, SmallPool &sp,
+                    std::vector<double> &shifts) {
+  const int64_t n = A.n, m = A.m;
+  const int extra = std::min(nvr, std::max(0, pmin - k));
+  const int pz = k + extra;
+  copy(cm(const_cast<double *>(Xl), n, k, n), cm(tb.Z, n, k, n), c.s);
+  if (extra) copy(cm(const_cast<double *>(Vr), n, extra, n), cm(tb.Z + (int64_t)k * n, n, extra, n), c.s);
+  cgs_cols(c, tb.Z, n, n, 0, pz, nullptr, 0, true, sp);
+  for (int c0 = 0; c0 < pz; c0 += bw) {
+    int w = std::min(bw, pz - c0);
+    copy(cm(tb.Z + (int64_t)c0 * n, n, w, n), rmv(tb.Xn, n, w, bw), c.s);
+    spmm(A, bw, tb.Xn, tb.Ym, false, c.s);
+    copy(rmv(tb.Ym, m, w, bw), cm(tb.AZ + (int64_t)c0 * m, m, w, m), c.s);
+  }
+  c.st->mv_rr += pz;
+  copy(cm(tb.AZ, m, pz, m), cm(tb.QZ, m, pz, m), c.s);
+  cgs_cols(c, tb.QZ, m, m, 0, pz, nullptr, 0, false, sp);
+  double *M = sp.mat(11), *Yv = sp.mat(12), *sv = sp.vec(8), *nrm = sp.vec(9);
+  for (int c0 = 0; c0 < pz; c0 += 32) {
+    int w = std::min(32, pz - c0);
+    tn(cm(tb.QZ, m, pz, m), none<double>(m), cm(tb.AZ + (int64_t)c0 * m, m, w, m),
+       M + (int64_t)c0 * kSP, kSP, c.sc, c.s);
+  }
+  svdj(M, kSP, pz, pz, sv, Yv, kSP, c.s);
+  nn(cm(tb.Z, n, pz, n), none<double>(n), Yv, kSP, 1.0, cm(tb.Vt, n, k, n), 0.0, c.s);
+  nn(cm(tb.AZ, m, pz, m), none<double>(m), Yv, kSP, 1.0, cm(tb.Ut, m, k, m), 0.0, c.s);
+  shifts.resize(k);
+  c.d2h(shifts.data(), sv, k * sizeof(double));
+  colnorm2(cm(tb.Ut, m, k, m), 0, m, nrm, c.sc, c.s);
+  std::vector<double> nh(k);
+  c.d2h(nh.data(), nrm, k * sizeof(double));
+  c.sync();
+  std::vector<double> f(k);
+  std::vector<int> tiny;
+  for (int i = 0; i < k; ++i) {
+    double nv = std::sqrt(std::max(nh[i], 0.0));
+    f[i] = nv > 0 ? 1.0 / nv : 0.0;
+    if (shifts[i] <= 10.0 * kEps64 * anorm) tiny.push_back(i);
+  }
+  c.h2d(sp.vec(10), f.data(), k * sizeof(double));
+  scale_cols(cm(tb.Ut, m, k, m), sp.vec(10), c.s);
+  // left vectors of (numerically) zero singular values carry no accuracy
+  // from stage 1: random, orthogonalised against the others (Section 3.3)
+  for (int i : tiny) {
+    fill_random(cm(tb.Ut + (int64_t)i * m, m, 1, m), c.seed, 4000000 + (c.nrand++) * 64, c.s);
+    std::vector<int> others;
+    for (int j = 0; j < k; ++j)
+      if (std::find(tiny.begin(), tiny.end(), j) == tiny.end()) others.push_back(j);
+    // move the random column next to the others and orthogonalise it
+    double *tmp = tb.QZ;  // scratch, m x (others + 1)
+    for (size_t q = 0; q < others.size(); ++q)
+      copy(cm(tb.Ut + (int64_t)others[q] * m, m, 1, m), cm(tmp + (int64_t)q * m, m, 1, m), c.s);
+    copy(cm(tb.Ut + (int64_t)i * m, m, 1, m), cm(tmp + (int64_t)others.size() * m, m, 1, m), c.s);
+    cgs_cols(c, tmp, m, m, (int)others.size(), (int)others.size() + 1, nullptr, 0, true, sp);
+    copy(cm(tmp + (int64_t)others.size() * m, m, 1, m), cm(tb.Ut + (int64_t)i * m, m, 1, m), c.s);
+  }
+}
+
+// ------------------------------------------------------------------------
+// Stage 2: GD+k with the refined projection on B (Algorithm 2).
+Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
+                        const Stage2Params &P, Stage2Bufs &bf, SmallPool &sp) {
+  const int64_t n = A.n, m = A.m, N = n + m;
+  const int k2 = P.k2, b = P.b, bw = P.bw, pmax = P.pmax, pmin = P.pmin;
+  const int ld = kSP;
+  double *V[2] = {bf.V[0], bf.V[1]}, *W[2] = {bf.W[0], bf.W[1]}, *Q[2] = {bf.Q[0], bf.Q[1]};
+  int cur = 0, p = 0, nl = 0, nprev = 0;
+  double *Tb = bf.Tb, *T2b = bf.T2b, *Rb = bf.Rb;
+  double *H = sp.mat(13), *Rq = sp.mat(14), *Ys = sp.mat(15), *Ysl = sp.mat(16),
+         *Yr = sp.mat(17), *Hs = sp.mat(18), *prev = sp.mat(19), *prev2 = sp.mat(20),
+         *Gb = sp.mat(21), *Mq = sp.mat(22), *Qt = sp.mat(23), *Rt = sp.mat(24),
+         *G1 = sp.mat(25), *Rc1 = sp.mat(26), *Rci1 = sp.mat(27), *Rc2 = sp.mat(28),
+         *Rci2 = sp.mat(29), *Gram = sp.mat(30);
+  double *sv = sp.vec(11), *thc = sp.vec(12), *ths = sp.vec(13), *rn2 = sp.vec(14),
+         *xt2 = sp.vec(15);
+  int *cnt = c.sc.flag + 8;
+  Stage2Result res;
+  double shift = P.shifts[0];
+  bool qr_full = true;
+  const double thr = P.tol * P.anorm / std::sqrt(2.0);
+
+  auto applyB = [&](double *X, int nb) {
+    spmm(At, bw, X + n * bw, bf.WTb, false, c.s);
+    spmm(A, bw, X, bf.WTb + n * bw, false, c.s);
+    c.st->mv_stage2 += nb;
+  };
+  // QR update of W - shift V by the new block (columns p..p+nb): block
+  // Gram-Schmidt against Q, then CholQR2 of the remainder when it is well
+  // conditioned, column-wise Gram-Schmidt otherwise.
+  auto qr_update = [&](int nb) {
+    axpby(rmv(bf.WTb, N, nb, bw), rmv(Tb, N, nb, bw), shift, rmv(bf.Cb, N, nb, bw), c.s);
+    zero_rows(Rq, ld, p, p + nb, p + nb, c.s);
+    Tall<double> Cv = rmv(bf.Cb, N, nb, bw);
+    if (p > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        tn(cm(Q[cur], N, p, N), none<double>(N), Cv, G1, ld, c.sc, c.s);
+        nn(cm(Q[cur], N, p, N), none<double>(N), G1, ld, -1.0, Cv, 1.0, c.s);
+        if (pass == 0)
+          small_gemm(false, false, p, nb, nb, 1.0, G1, ld, sp.eye(), ld, 0.0,
+                     Rq + (int64_t)p * ld, ld, c.s);
+        else
+          small_add(p, nb, 1.0, G1, ld, Rq + (int64_t)p * ld, ld, c.s);
+      }
+    }
+    tn(Cv, none<double>(N), Cv, Gram, ld, c.sc, c.s);
+    chol_inv(Gram, ld, nb, 0.0, Rc1, Rci1, ld, c.sc.flag, c.s);
+    double rd[64 * 64];
+    int fl = 0;
+    c.d2h(rd, Rc1, (size_t)ld * nb * sizeof(double));
+    c.d2h(&fl, c.sc.flag, sizeof(int));
+    c.sync();
+    double dmax = 0, dmin = 1e300;
+    for (int j = 0; j < nb; ++j) {
+      dmax = std::max(dmax, std::fabs(rd[j + j * ld]));
+      dmin = std::min(dmin, std::fabs(rd[j + j * ld]));
+    }
+    if (!fl && dmin > 1e-6 * dmax) {
+      nn(Cv, none<double>(N), Rci1, ld, 1.0, rmv(bf.C2b, N, nb, bw), 0.0, c.s);
+      Tall<double> C2v = rmv(bf.C2b, N, nb, bw);
+      tn(C2v, none<double>(N), C2v, Gram, ld, c.sc, c.s);
+      chol_inv(Gram, ld, nb, 0.0, Rc2, Rci2, ld, c.sc.flag + 1, c.s);
+      nn(C2v, none<double>(N), Rci2, ld, 1.0, cm(Q[cur] + (int64_t)p * N, N, nb, N), 0.0, c.s);
+      // R_bb = R2 R1
+      small_gemm(false, false, nb, nb, nb, 1.0, Rc2, ld, Rc1, ld, 0.0, Rq + p + (int64_t)p * ld,
+                 ld, c.s);
+    } else {
+      copy(Cv, cm(Q[cur] + (int64_t)p * N, N, nb, N), c.s);
+      // coefficients against the new columns only: R(p:p+j, p+j)
+      cgs_cols(c, Q[cur], N, N, p, p + nb, Rq, ld, false, sp);
+    }
+  };
+  auto expand2 = [&](int nb) {
+    orth_block(c, Tb, T2b, N, nb, bw, cm(bf.Xl, N, nl, N), cm(V[cur], N, p, N), kDepDropF64, sp);
+    applyB(Tb, nb);
+    copy(rmv(Tb, N, nb, bw), cm(V[cur] + (int64_t)p * N, N, nb, N), c.s);
+    copy(rmv(bf.WTb, N, nb, bw), cm(W[cur] + (int64_t)p * N, N, nb, N), c.s);
+    tn(cm(V[cur], N, p + nb, N), none<double>(N), rmv(bf.WTb, N, nb, bw), Gb, ld, c.sc, c.s);
+    h_border(H, ld, p, nb, Gb, ld, c.s);
+    if (!qr_full) qr_update(nb);
+    if (nprev) zero_rows(prev, ld, p, p + nb, nprev, c.s);
+    p += nb;
+  };
+
+  // seeds y_i = [v_i; u_i] / sqrt(2) (Algorithm 2 step 1)
+  copy(cm(const_cast<double *>(P.v0), n, k2, n), cm(bf.Y0, n, k2, N), c.s);
+  copy(cm(const_cast<double *>(P.u0), m, k2, m), cm(bf.Y0 + n, m, k2, N), c.s);
+  {
+    std::vector<double> f(k2, 1.0 / std::sqrt(2.0));
+    c.h2d(sp.vec(16), f.data(), k2 * sizeof(double));
+    scale_cols(cm(bf.Y0, N, k2, N), sp.vec(16), c.s);
+  }
+  // Krylov fill K_{p_min - k}(B, y_1) by Lanczos with full
+  // reorthogonalisation; its last residual is the first correction (step 2)
+  const int nk = std::max(0, pmin - k2);
+  double *K = Q[1];  // scratch until the first QR
+  int npend = 0;
+  if (nk > 0) {
+    copy(cm(bf.Y0, N, 1, N), cm(K, N, 1, N), c.s);
+    cgs_cols(c, K, N, N, 0, 1, nullptr, 0, true, sp);
+    for (int i = 0; i < nk; ++i) {
+      double *src = K + (int64_t)i * N, *dst = K + (int64_t)(i + 1) * N;
+      spmm(At, 1, src + n, dst, false, c.s);
+      spmm(A, 1, src, dst + n, false, c.s);
+      c.st->mv_stage2 += 1;
+      if (i < nk - 1) cgs_cols(c, K, N, N, i + 1, i + 2, nullptr, 0, true, sp);
+    }
+  }
+  {
+    // initial basis: seeds and the Krylov vectors 2..nk, in chunks
+    std::vector<std::pair<double *, int>> cols;
+    for (int i = 0; i < k2; ++i) cols.push_back({bf.Y0 + (int64_t)i * N, 1});
+    for (int i = 1; i < nk; ++i) cols.push_back({K + (int64_t)i * N, 1});
+    for (size_t c0 = 0; c0 < cols.size(); c0 += bw) {
+      int w = (int)std::min<size_t>(bw, cols.size() - c0);
+      for (int q = 0; q < w; ++q)
+        copy(cm(cols[c0 + q].first, N, 1, N), rmv(Tb + q, N, 1, bw), c.s);
+      expand2(w);
+    }
+    if (nk > 0) {
+      copy(cm(K + (int64_t)nk * N, N, 1, N), rmv(Tb, N, 1, bw), c.s);
+      npend = 1;
+    }
+  }
+  std::vector<double> sv_h(pmax), th_h(2 * b + 2), rn_h(bw), xt_h(bw);
+  int64_t it = 0;
+  while (true) {
+    if (npend) {
+      expand2(npend);
+      npend = 0;
+    }
+    ++it;
+    if (qr_full) {
+      axpby(cm(W[cur], N, p, N), cm(V[cur], N, p, N), shift, cm(Q[cur], N, p, N), c.s);
+      zero_rows(Rq, ld, 0, p, p, c.s);
+      cgs_cols(c, Q[cur], N, N, 0, p, Rq, ld, false, sp);
+      qr_full = false;
+    }
+    svdj(Rq, ld, p, p, sv, Ys, ld, c.s);
+    const int ncand = std::min(p, 2 * b + 1);
+    rayleigh_small(H, ld, p, Ys, ld, ncand, thc, c.s);
+    c.d2h(th_h.data(), thc, ncand * sizeof(double));
+    c.sync();
+    std::vector<int> slots = {0};
+    for (int q = 1; q < ncand && (int)slots.size() < b; ++q)
+      if (th_h[q] > 0.5 * shift) slots.push_back(q);
+    int ns = (int)slots.size();
+    std::vector<double> ths_h(ns);
+    for (int q = 0; q < ns; ++q) ths_h[q] = th_h[slots[q]];
+    c.h2d(c.didx, slots.data(), ns * sizeof(int));
+    c.h2d(ths, ths_h.data(), ns * sizeof(double));
+    gather_cols(Ys, ld, p, c.didx, ns, Ysl, ld, c.s);
+    ritz(cm(V[cur], N, p, N), cm(W[cur], N, p, N), Ysl, ld, ths, bf.Xb, Rb, ns, bw, rn2, xt2, n,
+         c.sc, c.s);
+    c.d2h(rn_h.data(), rn2, ns * sizeof(double));
+    c.d2h(xt_h.data(), xt2, ns * sizeof(double));
+    c.sync();
+    const double r0 = std::sqrt(std::max(rn_h[0], 0.0));
+    if (r0 < thr) {
+      copy(rmv(bf.Xb, N, 1, bw), cm(bf.Xl + (int64_t)nl * N, N, 1, N), c.s);
+      res.theta.push_back(ths_h[0]);
+      ++nl;
+      if (nl >= k2) {
+        res.converged = true;
+        break;
+      }
+      // drop the locked direction: V <- V Ys(:, 1:p)
+      nn(cm(V[cur], N, p, N), none<double>(N), Ys + ld, ld, 1.0, cm(V[1 - cur], N, p - 1, N), 0.0,
+         c.s);
+      nn(cm(W[cur], N, p, N), none<double>(N), Ys + ld, ld, 1.0, cm(W[1 - cur], N, p - 1, N), 0.0,
+         c.s);
+      small_gemm(false, false, p, p - 1, p, 1.0, H, ld, Ys + ld, ld, 0.0, Hs, ld, c.s);
+      small_gemm(true, false, p - 1, p - 1, p, 1.0, Ys + ld, ld, Hs, ld, 0.0, H, ld, c.s);
+      cur = 1 - cur;
+      p -= 1;
+      shift = P.shifts[nl];
+      // re-introduce the next initial guess (Algorithm 2 step 11)
+      copy(cm(bf.Y0 + (int64_t)nl * N, N, 1, N), rmv(Tb, N, 1, bw), c.s);
+      npend = 1;
+      nprev = 0;
+      qr_full = true;
+      continue;
+    }
+    const bool out_of_budget = res.restarts > P.max_restarts ||
+                               (c.max_mv > 0 && c.st->mv_stage2 > c.max_mv) ||
+                               (P.max_iters > 0 && it > P.max_iters);
+    if (out_of_budget) break;
+    // balance guard for the non-target block members (B's zero and
+    // negative eigenvalues must not be taken for singular values)
+    std::vector<int> acc = {0};
+    for (int q = 1; q < ns; ++q)
+      if (std::fabs(2.0 * xt_h[q] - 1.0) < 0.1) acc.push_back(q);
+    if ((int)acc.size() < ns) {
+      for (size_t q = 0; q < acc.size(); ++q) {
+        if ((int)q != acc[q]) {
+          copy(rmv(bf.Xb + acc[q], N, 1, bw), rmv(bf.Xb + q, N, 1, bw), c.s);
+          copy(rmv(Rb + acc[q], N, 1, bw), rmv(Rb + q, N, 1, bw), c.s);
+        }
+      }
+      std::vector<int> idx2(acc.size());
+      for (size_t q = 0; q < acc.size(); ++q) idx2[q] = slots[acc[q]];
+      c.h2d(c.didx, idx2.data(), idx2.size() * sizeof(int));
+      gather_cols(Ys, ld, p, c.didx, (int)idx2.size(), Ysl, ld, c.s);
+      ns = (int)acc.size();
+    }
+    // correction t = Prec(r) (step 13)
+    if (P.jacobi_d) {
+      // B-form of the Jacobi preconditioner of C: [f; g] -> [M A^T g; A M f]
+      row_scale(Rb, P.jacobi_d, n, bw, true, bf.Cb, c.s);  // M f (top rows)
+      spmm(At, bw, Rb + n * bw, Tb, false, c.s);           // A^T g -> top
+      row_scale(Tb, P.jacobi_d, n, bw, true, Tb, c.s);     // M A^T g
+      spmm(A, bw, bf.Cb, Tb + n * bw, false, c.s);         // A M f -> bottom
+      c.st->mv_prec += ns;
+    } else {
+      std::swap(Tb, Rb);
+    }
+    if (p + ns > pmax) {
+      restart_basis(Ys, ld, p, pmin, prev, ld, nprev, Yr, ld, cnt, c.s);
+      int hc = 0;
+      c.d2h(&hc, cnt, sizeof(int));
+      c.sync();
+      nn(cm(V[cur], N, p, N), none<double>(N), Yr, ld, 1.0, cm(V[1 - cur], N, hc, N), 0.0, c.s);
+      nn(cm(W[cur], N, p, N), none<double>(N), Yr, ld, 1.0, cm(W[1 - cur], N, hc, N), 0.0, c.s);
+      small_gemm(false, false, p, hc, p, 1.0, H, ld, Yr, ld, 0.0, Hs, ld, c.s);
+      small_gemm(true, false, hc, hc, p, 1.0, Yr, ld, Hs, ld, 0.0, H, ld, c.s);
+      small_gemm(true, false, hc, ns, p, 1.0, Yr, ld, Ysl, ld, 0.0, prev2, ld, c.s);
+      std::swap(prev, prev2);
+      nprev = ns;
+      // same shift: W - s V = Q (R Yr); R Yr = Qt Rt gives the new factors
+      small_gemm(false, false, p, hc, p, 1.0, Rq, ld, Yr, ld, 0.0, Mq, ld, c.s);
+      small_qr(Mq, ld, p, hc, Qt, ld, Rt, ld, c.s);
+      nn(cm(Q[cur], N, p, N), none<double>(N), Qt, ld, 1.0, cm(Q[1 - cur], N, hc, N), 0.0, c.s);
+      zero_rows(Rq, ld, 0, pmax, pmax, c.s);
+      small_gemm(false, false, hc, hc, hc, 1.0, Rt, ld, sp.eye(), ld, 0.0, Rq, ld, c.s);
+      cur = 1 - cur;
+      p = hc;
+      ++res.restarts;
+    } else {
+      small_gemm(false, false, p, ns, ns, 1.0, Ysl, ld, sp.eye(), ld, 0.0, prev, ld, c.s);
+      nprev = ns;
+    }
+    npend = ns;
+  }
+  res.iters = it;
+  res.nl = nl;
+  res.Xl = bf.Xl;
+  bf.Tb = Tb;
+  bf.T2b = T2b;
+  bf.Rb = Rb;
+  return res;
+}
+
+}  // namespace phs

@@ -1,0 +1,110 @@
+// Internal interfaces of the PHSVDS host orchestration.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/phsvds.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace phs {
+
+constexpr int kSP = 128;               // leading dimension of small matrices
+constexpr double kEps64 = 2.220446049250313e-16;   // float64 spacing at 1
+constexpr double kEps32 = 1.1920928955078125e-07;  // float32 spacing at 1
+constexpr double kDepDropF64 = 1e-10;  // norm drop that marks a dependent column
+
+// Device pool of small float64 matrices (kSP x kSP) and vectors.
+struct SmallPool {
+  double *base = nullptr;
+  static constexpr int kMats = 40, kVecs = 24, kVecLen = 1024;
+  double *mat(int i) const { return base + (int64_t)i * kSP * kSP; }
+  double *vec(int i) const { return base + (int64_t)kMats * kSP * kSP + (int64_t)i * kVecLen; }
+  double *eye() const { return mat(kMats - 1); }
+  static size_t bytes() { return ((size_t)kMats * kSP * kSP + (size_t)kVecs * kVecLen) * 8; }
+};
+
+struct Ctx {
+  hipStream_t s = nullptr;
+  Scratch sc;
+  int *didx = nullptr;  // device int scratch (index lists)
+  uint64_t seed = 0;
+  uint64_t nrand = 0;
+  phsvds_stats *st = nullptr;
+  int64_t max_mv = 0;
+  void d2h(void *h, const void *d, size_t bytes);
+  void h2d(void *d, const void *h, size_t bytes);
+  void sync();
+};
+
+struct Stage1Params {
+  int k, b, bw, pmax, pmin;
+  bool largest;
+  double tol, floor, anorm, sn2_init;
+  int max_restarts;
+  int64_t max_iters;
+  const double *jacobi_d;  // diag(C) for the Jacobi preconditioner, or null
+  const double *init64;    // initial basis (n x init_cols, column-major) or null
+  const float *init32;
+  int init_cols;
+};
+
+template <typename T>
+struct Stage1Bufs {
+  T *V[2], *W[2], *Xl, *Xb, *Rb, *Tb, *T2b, *WTb, *Yb, *Fb;
+};
+
+struct Stage1Result {
+  bool converged = false;
+  int nl = 0, p = 0;
+  int64_t iters = 0, restarts = 0, refreshes = 0;
+  double sn2 = 0.0;
+  std::vector<double> theta, res;
+  std::vector<bool> tight;  // locked by the user tolerance (not by the floor)
+  void *Vrest = nullptr;
+};
+
+struct TransBufs {
+  double *Z, *AZ, *QZ, *Vt, *Ut, *Xn, *Ym;
+};
+
+struct Stage2Params {
+  int k2, b, bw, pmax, pmin;
+  double tol, anorm;
+  const double *shifts;
+  const double *v0, *u0;  // n x k2, m x k2 column-major seeds
+  int max_restarts;
+  int64_t max_iters;
+  const double *jacobi_d;
+};
+
+struct Stage2Bufs {
+  double *V[2], *W[2], *Q[2], *Xl, *Y0, *Tb, *T2b, *WTb, *Xb, *Rb, *Cb, *C2b;
+};
+
+struct Stage2Result {
+  bool converged = false;
+  int nl = 0;
+  int64_t iters = 0, restarts = 0;
+  std::vector<double> theta;
+  double *Xl = nullptr;
+};
+
+template <typename T>
+void orth_block(Ctx &c, T *&Tb, T *&T2b, int64_t n, int nb, int bw, const Tall<T> &B1,
+                const Tall<T> &B2, double dep_drop, SmallPool &sp);
+void cgs_cols(Ctx &c, double *X, int64_t rows, int64_t ld, int j0, int j1, double *R, int ldr,
+              bool random_dep, SmallPool &sp);
+template <typename T>
+Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Stage1Params &P,
+                        Stage1Bufs<T> &bf, SmallPool &sp);
+void run_transition(Ctx &c, const SpMat<double> &A, const double *Xl, int k, const double *Vr,
+                    int nvr, int pmin, double anorm, int bw, TransBufs &tb, SmallPool &sp,
+                    std::vector<double> &shifts);
+Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
+                        const Stage2Params &P, Stage2Bufs &bf, SmallPool &sp);
+
+}  // namespace phs

@@ -1,0 +1,401 @@
+// Sparse matrix times block of vectors, CSR, row-major blocks (gfx950).
+//
+// Y = A X with A m x n in CSR and X (n x B), Y (m x B) stored row-major, so
+// that every nonzero a_ic gathers one contiguous B-vector x_c (B * sizeof(T)
+// bytes: 32-64 B for B = 8).  G lanes of a wavefront share a row: each lane
+// walks the row's nonzeros with stride G and keeps B partial sums in
+// registers; the G partials are combined with cross-lane shuffles.  G is
+// chosen from the row-length distribution: 1 lane per row for the grid
+// operators (2-4 nonzeros per row), wider groups for random rows, and the
+// rows of a power-law matrix are split into length bins, each launched with
+// its own G (long rows get a whole wavefront).
+//
+// The CSR transpose is built on the device: column counts by atomics, an
+// exclusive scan, an atomic scatter, then a per-row sort that restores
+// column order (so A^T products are deterministic).
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "prof.hpp"
+
+namespace phs {
+
+template <typename T, int B>
+__device__ inline void load_row(const T *__restrict__ p, T (&o)[B]) {
+  if constexpr ((B * sizeof(T)) % 16 == 0) {
+    const uint4 *q = reinterpret_cast<const uint4 *>(p);
+#pragma unroll
+    for (int i = 0; i < (int)(B * sizeof(T) / 16); ++i) {
+      uint4 u = q[i];
+      __builtin_memcpy(&o[i * 16 / sizeof(T)], &u, 16);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < B; ++i) o[i] = p[i];
+  }
+}
+
+template <typename T, int B>
+__device__ inline void store_row(T *__restrict__ p, const T (&o)[B]) {
+  if constexpr ((B * sizeof(T)) % 16 == 0) {
+    uint4 *q = reinterpret_cast<uint4 *>(p);
+#pragma unroll
+    for (int i = 0; i < (int)(B * sizeof(T) / 16); ++i) {
+      uint4 u;
+      __builtin_memcpy(&u, &o[i * 16 / sizeof(T)], 16);
+      q[i] = u;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < B; ++i) p[i] = o[i];
+  }
+}
+
+// rows: optional list of row indices (a length bin); nullptr = all rows.
+template <typename T, int B, int G, bool ABS>
+__global__ __launch_bounds__(256) void k_spmm(int64_t nrows, const int32_t *__restrict__ rows,
+                                              const int64_t *__restrict__ rp,
+                                              const int32_t *__restrict__ ci,
+                                              const T *__restrict__ va,
+                                              const T *__restrict__ X, T *__restrict__ Y) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t slot = gid / G;
+  const int lane = (int)(threadIdx.x % G);
+  if (slot >= nrows) return;  // a whole group leaves together
+  const int64_t row = rows ? (int64_t)rows[slot] : slot;
+  T acc[B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) acc[j] = T(0);
+  const int64_t end = rp[row + 1];
+  for (int64_t p = rp[row] + lane; p < end; p += G) {
+    const int64_t c = ci[p];
+    T a = va[p];
+    T x[B];
+    load_row<T, B>(X + c * B, x);
+    if constexpr (ABS) {
+      a = fabs(a);
+#pragma unroll
+      for (int j = 0; j < B; ++j) x[j] = fabs(x[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j) acc[j] = fma(a, x[j], acc[j]);
+  }
+  if constexpr (G > 1) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+#pragma unroll
+      for (int j = 0; j < B; ++j) acc[j] += __shfl_xor(acc[j], off, G);
+    }
+  }
+  if (lane == 0) store_row<T, B>(Y + row * B, acc);
+}
+
+template <typename T, int B, bool ABS>
+static void launch_g(int G, int64_t nrows, const int32_t *rows, const int64_t *rp,
+                     const int32_t *ci, const T *va, const T *X, T *Y, hipStream_t s) {
+  if (nrows <= 0) return;
+  const int64_t threads = nrows * G;
+  dim3 grid(cdiv(threads, 256));
+  switch (G) {
+    case 1: k_spmm<T, B, 1, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
+    case 2: k_spmm<T, B, 2, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
+    case 4: k_spmm<T, B, 4, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
+    case 8: k_spmm<T, B, 8, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
+    case 16: k_spmm<T, B, 16, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
+    case 32: k_spmm<T, B, 32, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
+    default: k_spmm<T, B, 64, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
+  }
+  PHS_CHECK_LAUNCH();
+}
+
+template <typename T, bool ABS>
+static void launch_b(int b, int G, int64_t nrows, const int32_t *rows, const int64_t *rp,
+                     const int32_t *ci, const T *va, const T *X, T *Y, hipStream_t s) {
+  switch (b) {
+    case 1: launch_g<T, 1, ABS>(G, nrows, rows, rp, ci, va, X, Y, s); break;
+    case 2: launch_g<T, 2, ABS>(G, nrows, rows, rp, ci, va, X, Y, s); break;
+    case 4: launch_g<T, 4, ABS>(G, nrows, rows, rp, ci, va, X, Y, s); break;
+    case 8: launch_g<T, 8, ABS>(G, nrows, rows, rp, ci, va, X, Y, s); break;
+    case 16: launch_g<T, 16, ABS>(G, nrows, rows, rp, ci, va, X, Y, s); break;
+    case 32: launch_g<T, 32, ABS>(G, nrows, rows, rp, ci, va, X, Y, s); break;
+    default: throw Error(kEinval, "spmm: block width must be 1, 2, 4, 8, 16 or 32");
+  }
+}
+
+template <typename T>
+void spmm_launch(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, hipStream_t s);
+
+int lanes_for_length(double avg) {
+  if (avg <= 4) return 1;
+  if (avg <= 8) return 2;
+  if (avg <= 20) return 4;
+  if (avg <= 40) return 8;
+  if (avg <= 80) return 16;
+  if (avg <= 160) return 32;
+  return 64;
+}
+
+template <typename T>
+void spmm(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, hipStream_t s) {
+  const int kind = sizeof(T) == 8 ? kProfSpmm64 : kProfSpmm32;
+  prof_begin(kind, s);
+  spmm_launch(A, b, X, Y, absval, s);
+  // algorithmic bytes: values + column indices + row pointers + X + Y
+  prof_end(kind, s,
+           (double)A.nnz * (sizeof(T) + 4) + (double)(A.m + 1) * 8 +
+               (double)A.n * b * sizeof(T) + (double)A.m * b * sizeof(T));
+}
+
+template <typename T>
+void spmm_launch(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, hipStream_t s) {
+  if (A.nbins == 0) {
+    const int G = lanes_for_length(A.m ? (double)A.nnz / (double)A.m : 0.0);
+    if (absval)
+      launch_b<T, true>(b, G, A.m, nullptr, A.rowptr, A.colind, A.val, X, Y, s);
+    else
+      launch_b<T, false>(b, G, A.m, nullptr, A.rowptr, A.colind, A.val, X, Y, s);
+    return;
+  }
+  for (int k = 0; k < A.nbins; ++k) {
+    const Bin &bn = A.bins[k];
+    if (absval)
+      launch_b<T, true>(b, bn.lanes, bn.count, A.binrows + bn.offset, A.rowptr, A.colind, A.val,
+                        X, Y, s);
+    else
+      launch_b<T, false>(b, bn.lanes, bn.count, A.binrows + bn.offset, A.rowptr, A.colind, A.val,
+                         X, Y, s);
+  }
+}
+template void spmm<float>(const SpMat<float> &, int, const float *, float *, bool, hipStream_t);
+template void spmm<double>(const SpMat<double> &, int, const double *, double *, bool,
+                           hipStream_t);
+
+// ---------------------------------------------------------------- transpose
+__global__ void k_count_cols(int64_t nnz, const int32_t *__restrict__ ci, int32_t *cnt) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nnz) atomicAdd(&cnt[ci[p]], 1);
+}
+
+// Exclusive scan of n int32 counts into n+1 int64 offsets: tile sums,
+// a single-block scan of the tile sums, then per-tile scans.
+constexpr int kScanTile = 1024;
+__global__ __launch_bounds__(256) void k_tile_sums(int64_t n, const int32_t *cnt, int64_t *tsum) {
+  __shared__ int64_t red[256];
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int64_t s = 0;
+  for (int i = threadIdx.x; i < kScanTile; i += 256)
+    if (base + i < n) s += cnt[base + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tsum[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_scan_tiles(int64_t ntiles, int64_t *tsum) {
+  // sequential over chunks of 256, parallel within a chunk
+  __shared__ int64_t buf[256];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t c = 0; c < ntiles; c += 256) {
+    int64_t i = c + threadIdx.x;
+    int64_t v = i < ntiles ? tsum[i] : 0;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+      int64_t t = (int)threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < ntiles) tsum[i] = carry + buf[threadIdx.x] - v;  // exclusive
+    __syncthreads();
+    if (threadIdx.x == 255) carry += buf[255];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tile_scan(int64_t n, const int32_t *cnt,
+                                                   const int64_t *tsum, int64_t *out) {
+  __shared__ int64_t buf[kScanTile];
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  for (int i = threadIdx.x; i < kScanTile; i += 256) buf[i] = (base + i < n) ? cnt[base + i] : 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = tsum[blockIdx.x];
+    for (int i = 0; i < kScanTile; ++i) {
+      int64_t v = buf[i];
+      buf[i] = run;
+      run += v;
+    }
+    if (base + kScanTile >= n) out[n] = run;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kScanTile; i += 256)
+    if (base + i < n) out[base + i] = buf[i];
+}
+
+__global__ void k_scatter_t(int64_t m, const int64_t *__restrict__ rp,
+                            const int32_t *__restrict__ ci, const double *__restrict__ va,
+                            const int64_t *__restrict__ trp, int32_t *fill, int32_t *tci,
+                            double *tva) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= m) return;
+  for (int64_t p = rp[r]; p < rp[r + 1]; ++p) {
+    int c = ci[p];
+    int64_t pos = trp[c] + atomicAdd(&fill[c], 1);
+    tci[pos] = (int32_t)r;
+    tva[pos] = va[p];
+  }
+}
+
+__global__ void k_sort_short(int64_t n, const int64_t *__restrict__ trp, int32_t *tci,
+                             double *tva, int32_t *longlist, int32_t *nlong) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  int64_t a = trp[r], e = trp[r + 1];
+  if (e - a > 32) {
+    longlist[atomicAdd(nlong, 1)] = (int32_t)r;
+    return;
+  }
+  for (int64_t i = a + 1; i < e; ++i) {
+    int32_t key = tci[i];
+    double v = tva[i];
+    int64_t j = i - 1;
+    while (j >= a && tci[j] > key) {
+      tci[j + 1] = tci[j];
+      tva[j + 1] = tva[j];
+      --j;
+    }
+    tci[j + 1] = key;
+    tva[j + 1] = v;
+  }
+}
+
+// One block per long row: the rank of each (distinct) key is its position.
+__global__ __launch_bounds__(256) void k_sort_long(const int32_t *longlist,
+                                                   const int64_t *__restrict__ trp,
+                                                   int32_t *tci, double *tva, int32_t *tmpc,
+                                                   double *tmpv) {
+  const int64_t r = longlist[blockIdx.x];
+  const int64_t a = trp[r], len = trp[r + 1] - a;
+  for (int64_t i = threadIdx.x; i < len; i += 256) {
+    int32_t key = tci[a + i];
+    int64_t rank = 0;
+    for (int64_t j = 0; j < len; ++j) rank += tci[a + j] < key;
+    tmpc[a + rank] = key;
+    tmpv[a + rank] = tva[a + i];
+  }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < len; i += 256) {
+    tci[a + i] = tmpc[a + i];
+    tva[a + i] = tmpv[a + i];
+  }
+}
+
+size_t transpose_ws_bytes(int64_t m, int64_t n, int64_t nnz) {
+  Arena ar;
+  ar.dry = true;
+  ar.take<int32_t>(n);                  // counts / fill
+  ar.take<int64_t>(cdiv(n, kScanTile));  // tile sums
+  ar.take<int32_t>(n + 1);              // long rows (+ counter)
+  ar.take<int32_t>(nnz);
+  ar.take<double>(nnz);
+  (void)m;
+  return ar.used;
+}
+
+void csr_transpose(int64_t m, int64_t n, int64_t nnz, const int64_t *rp, const int32_t *ci,
+                   const double *va, int64_t *trp, int32_t *tci, double *tva, void *ws,
+                   size_t ws_bytes, hipStream_t s) {
+  Arena ar;
+  ar.base = (char *)ws;
+  ar.size = ws_bytes;
+  int32_t *cnt = ar.take<int32_t>(n);
+  int64_t ntiles = cdiv(n, kScanTile);
+  int64_t *tsum = ar.take<int64_t>(ntiles);
+  int32_t *longl = ar.take<int32_t>(n + 1);
+  int32_t *tmpc = ar.take<int32_t>(nnz);
+  double *tmpv = ar.take<double>(nnz);
+  int32_t *nlong = longl + n;
+  PHS_HIP(hipMemsetAsync(cnt, 0, n * sizeof(int32_t), s));
+  PHS_HIP(hipMemsetAsync(nlong, 0, sizeof(int32_t), s));
+  if (nnz) k_count_cols<<<cdiv(nnz, 256), 256, 0, s>>>(nnz, ci, cnt);
+  PHS_CHECK_LAUNCH();
+  if (n) {
+    k_tile_sums<<<ntiles, 256, 0, s>>>(n, cnt, tsum);
+    k_scan_tiles<<<1, 256, 0, s>>>(ntiles, tsum);
+    k_tile_scan<<<ntiles, 256, 0, s>>>(n, cnt, tsum, trp);
+    PHS_CHECK_LAUNCH();
+  } else {
+    PHS_HIP(hipMemsetAsync(trp, 0, sizeof(int64_t), s));
+  }
+  PHS_HIP(hipMemsetAsync(cnt, 0, n * sizeof(int32_t), s));
+  if (m) k_scatter_t<<<cdiv(m, 256), 256, 0, s>>>(m, rp, ci, va, trp, cnt, tci, tva);
+  if (n) k_sort_short<<<cdiv(n, 256), 256, 0, s>>>(n, trp, tci, tva, longl, nlong);
+  PHS_CHECK_LAUNCH();
+  int32_t nl = 0;
+  PHS_HIP(hipMemcpyAsync(&nl, nlong, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PHS_HIP(hipStreamSynchronize(s));
+  if (nl > 0) {
+    k_sort_long<<<nl, 256, 0, s>>>(longl, trp, tci, tva, tmpc, tmpv);
+    PHS_CHECK_LAUNCH();
+  }
+}
+
+// Row-length bins for skewed matrices: rows are grouped by the lane count
+// their length calls for, so that each launch has uniform work per group.
+__global__ void k_bin_count(int64_t m, const int64_t *__restrict__ rp, int32_t *cnt) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= m) return;
+  int64_t len = rp[r + 1] - rp[r];
+  int g = 0;
+  for (int lim = 4; g < 6 && len > lim; lim *= 2) ++g;  // 0..6 -> 1..64 lanes
+  atomicAdd(&cnt[g], 1);
+}
+
+__global__ void k_bin_fill(int64_t m, const int64_t *__restrict__ rp, const int32_t *offs,
+                           int32_t *fill, int32_t *rows) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= m) return;
+  int64_t len = rp[r + 1] - rp[r];
+  int g = 0;
+  for (int lim = 4; g < 6 && len > lim; lim *= 2) ++g;
+  rows[offs[g] + atomicAdd(&fill[g], 1)] = (int32_t)r;
+}
+
+// The order of rows inside a bin comes from atomics, but every row is
+// computed by one group in a fixed order, so results are deterministic.
+void build_bins(int64_t m, const int64_t *rp, int32_t *rows, int32_t *scratch, Bin *bins,
+                int *nbins, hipStream_t s) {
+  // scratch: 16 int32 (counts, offsets, fill)
+  PHS_HIP(hipMemsetAsync(scratch, 0, 16 * sizeof(int32_t), s));
+  k_bin_count<<<cdiv(m, 256), 256, 0, s>>>(m, rp, scratch);
+  PHS_CHECK_LAUNCH();
+  int32_t cnt[7];
+  PHS_HIP(hipMemcpyAsync(cnt, scratch, 7 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PHS_HIP(hipStreamSynchronize(s));
+  int32_t offs[8];
+  offs[0] = 0;
+  for (int g = 0; g < 7; ++g) offs[g + 1] = offs[g] + cnt[g];
+  PHS_HIP(hipMemcpyAsync(scratch + 8, offs, 7 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  PHS_HIP(hipMemsetAsync(scratch, 0, 7 * sizeof(int32_t), s));
+  k_bin_fill<<<cdiv(m, 256), 256, 0, s>>>(m, rp, scratch + 8, scratch, rows);
+  PHS_CHECK_LAUNCH();
+  int nb = 0;
+  for (int g = 0; g < 7; ++g) {
+    if (cnt[g] == 0) continue;
+    bins[nb].offset = offs[g];
+    bins[nb].count = cnt[g];
+    bins[nb].lanes = 1 << g;
+    ++nb;
+  }
+  *nbins = nb;
+  PHS_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace phs

@@ -1,0 +1,651 @@
+// Tall-skinny block kernels (N x p with N up to ~10^7, p <= 128).
+//
+// These carry the dense work of the GD+k iteration: projections X^T Y
+// (Rayleigh-Ritz borders, Gram-Schmidt coefficients, Gram matrices), basis
+// updates X S (Ritz vectors, restarts, Gram-Schmidt updates), residuals and
+// norms.  All of them stream the tall operands once from HBM; the small
+// operand lives in LDS.  Reductions go through per-block partials and a
+// second pass in float64, in a fixed order, so results are deterministic.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "prof.hpp"
+
+namespace phs {
+
+template <typename T>
+struct TV {  // trivially copyable kernel argument
+  const T *p;
+  int64_t rows;
+  int cols;
+  int64_t rs, cs;
+};
+template <typename T>
+static TV<T> tv(const Tall<T> &t) {
+  return TV<T>{t.p, t.rows, t.cols, t.rs, t.cs};
+}
+
+// Load rows [r0, r0+R) of a tall view into LDS (row-major, width w, column
+// offset j0 inside a row of width ld); rows past `rows` read as zero.
+template <typename T>
+__device__ inline void stage_rows(const TV<T> &x, int64_t r0, int R, T *lds, int ld, int j0) {
+  const int n = R * x.cols;
+  if (x.rs == 1) {  // column-major: consecutive threads walk a column
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+      int r = idx % R, j = idx / R;
+      int64_t gr = r0 + r;
+      lds[r * ld + j0 + j] = gr < x.rows ? x.p[gr + (int64_t)j * x.cs] : T(0);
+    }
+  } else {  // row-major: consecutive threads walk a row
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+      int r = idx / x.cols, j = idx % x.cols;
+      int64_t gr = r0 + r;
+      lds[r * ld + j0 + j] = gr < x.rows ? x.p[gr * x.rs + (int64_t)j * x.cs] : T(0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- X^T Y
+constexpr int kTnRows = 64;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tn(TV<T> x1, TV<T> x2, TV<T> y, int R, double *part) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T *xs = reinterpret_cast<T *>(smem);
+  const int nx = x1.cols + x2.cols, ny = y.cols;
+  T *ys = xs + R * nx;
+  const int64_t N = y.rows;
+  const int ti = (nx + 3) / 4, tj = (ny + 3) / 4, ntile = ti * tj;
+  const int S = max(1, 256 / ntile);
+  const int t = threadIdx.x;
+  const int tile = t % ntile, sg = t / ntile;
+  const bool active = sg < S && t < ntile * S;
+  const int i0 = (tile / tj) * 4, j0 = (tile % tj) * 4;
+  T acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = T(0);
+  for (int64_t r0 = (int64_t)blockIdx.x * R; r0 < N; r0 += (int64_t)gridDim.x * R) {
+    stage_rows(x1, r0, R, xs, nx, 0);
+    if (x2.cols) stage_rows(x2, r0, R, xs, nx, x1.cols);
+    stage_rows(y, r0, R, ys, ny, 0);
+    __syncthreads();
+    if (active) {
+      for (int r = sg; r < R; r += S) {
+        T xv[4], yv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) xv[a] = (i0 + a < nx) ? xs[r * nx + i0 + a] : T(0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) yv[c] = (j0 + c < ny) ? ys[r * ny + j0 + c] : T(0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[a][c] = fma(xv[a], yv[c], acc[a][c]);
+      }
+    }
+    __syncthreads();
+  }
+  // combine the S row groups of each tile in LDS (float64)
+  double *red = reinterpret_cast<double *>(smem);
+  if (active) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) red[t * 16 + a * 4 + c] = (double)acc[a][c];
+  }
+  __syncthreads();
+  if (t < ntile) {
+    double sum[16];
+    for (int q = 0; q < 16; ++q) sum[q] = 0.0;
+    for (int g = 0; g < S; ++g)
+      for (int q = 0; q < 16; ++q) sum[q] += red[(g * ntile + t) * 16 + q];
+    const int E = nx * ny;
+    for (int a = 0; a < 4; ++a)
+      for (int c = 0; c < 4; ++c) {
+        int i = i0 + a, j = j0 + c;
+        if (i < nx && j < ny) part[(int64_t)blockIdx.x * E + i * ny + j] = sum[a * 4 + c];
+      }
+  }
+}
+
+__global__ void k_reduce_parts(const double *part, int nblk, int nx, int ny, double *G, int ldg) {
+  const int E = nx * ny;
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * E + e];
+  int i = e / ny, j = e % ny;
+  G[i + (int64_t)j * ldg] = s;
+}
+
+static int tn_blocks(int64_t N, int E) {
+  int64_t nb = (N + kTnRows * 4 - 1) / (kTnRows * 4);
+  int64_t cap = kPartCap / (E > 0 ? E : 1);
+  if (cap > 1024) cap = 1024;
+  if (nb > cap) nb = cap;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+template <typename T>
+void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int ldg,
+        const Scratch &sc, hipStream_t s) {
+  const int nx = X1.cols + X2.cols, ny = Y.cols;
+  if (nx == 0 || ny == 0) return;
+  PHS_REQUIRE(nx <= 128 && ny <= 32, kEinval, "tn: operand too wide");
+  PHS_REQUIRE(((nx + 3) / 4) * ((ny + 3) / 4) <= 256, kEinval, "tn: too many tiles");
+  const int nblk = tn_blocks(Y.rows, nx * ny);
+  prof_begin(kProfTn, s);
+  int R = kTnRows;  // rows per LDS chunk, keeping the chunk within 64 KB
+  while (R > 8 && (size_t)R * (nx + ny) * sizeof(T) > 65536) R /= 2;
+  size_t lds = (size_t)R * (nx + ny) * sizeof(T);
+  if (lds < 256 * 16 * sizeof(double)) lds = 256 * 16 * sizeof(double);
+  k_tn<T><<<nblk, 256, lds, s>>>(tv(X1), tv(X2), tv(Y), R, sc.part);
+  k_reduce_parts<<<cdiv(nx * ny, 256), 256, 0, s>>>(sc.part, nblk, nx, ny, G, ldg);
+  PHS_CHECK_LAUNCH();
+  prof_end(kProfTn, s, (double)Y.rows * (nx + ny) * sizeof(T));
+}
+
+// ------------------------------------------------------------------ X S
+constexpr int kNnTile = 16;  // output columns per thread
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_nn(TV<T> x1, TV<T> x2, const double *S, int lds,
+                                            int ny, double alpha, T *yp, int64_t yrs,
+                                            int64_t ycs, double beta) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T *ss = reinterpret_cast<T *>(smem);
+  const int nx = x1.cols + x2.cols;
+  const int c0 = blockIdx.y * kNnTile;
+  const int nc = min(kNnTile, ny - c0);
+  for (int idx = threadIdx.x; idx < nx * kNnTile; idx += blockDim.x) {
+    int j = idx / kNnTile, c = idx % kNnTile;
+    ss[idx] = c < nc ? (T)S[j + (int64_t)(c0 + c) * lds] : T(0);
+  }
+  __syncthreads();
+  const int64_t N = x1.cols ? x1.rows : x2.rows;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    T acc[kNnTile];
+#pragma unroll
+    for (int c = 0; c < kNnTile; ++c) acc[c] = T(0);
+    for (int j = 0; j < x1.cols; ++j) {
+      T xv = x1.p[r * x1.rs + (int64_t)j * x1.cs];
+#pragma unroll
+      for (int c = 0; c < kNnTile; ++c) acc[c] = fma(xv, ss[j * kNnTile + c], acc[c]);
+    }
+    for (int j = 0; j < x2.cols; ++j) {
+      T xv = x2.p[r * x2.rs + (int64_t)j * x2.cs];
+#pragma unroll
+      for (int c = 0; c < kNnTile; ++c)
+        acc[c] = fma(xv, ss[(x1.cols + j) * kNnTile + c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < kNnTile; ++c) {
+      if (c < nc) {
+        T *dst = yp + r * yrs + (int64_t)(c0 + c) * ycs;
+        T v = (T)alpha * acc[c];
+        if (beta != 0.0) v += (T)beta * *dst;
+        *dst = v;
+      }
+    }
+  }
+}
+
+template <typename T>
+void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double alpha,
+        const Tall<T> &Y, double beta, hipStream_t s) {
+  const int nx = X1.cols + X2.cols, ny = Y.cols;
+  if (ny == 0 || Y.rows == 0) return;
+  if (nx == 0 && beta == 1.0) return;
+  PHS_REQUIRE(nx <= 160, kEinval, "nn: operand too wide");
+  int64_t blocks = cdiv(Y.rows, 256);
+  if (blocks > 4096) blocks = 4096;
+  dim3 grid((unsigned)blocks, cdiv(ny, kNnTile));
+  size_t shm = (size_t)(nx > 0 ? nx : 1) * kNnTile * sizeof(T);
+  Tall<T> a = X1, b = X2;
+  if (a.cols == 0 && b.cols == 0) a.rows = Y.rows;
+  prof_begin(kProfNn, s);
+  k_nn<T><<<grid, 256, shm, s>>>(tv(a), tv(b), S, lds, ny, alpha, Y.p, Y.rs, Y.cs, beta);
+  PHS_CHECK_LAUNCH();
+  prof_end(kProfNn, s, (double)Y.rows * (nx + ny * (beta != 0.0 ? 2 : 1)) * sizeof(T));
+}
+
+// ---------------------------------------------------------- Ritz block
+constexpr int kRitzMax = 32;
+
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_ritz(TV<T> V, TV<T> W, const double *S, int lds,
+                                              const double *theta, T *X, T *R, int ldx,
+                                              int64_t ntop, double *part) {
+  constexpr int nb = NB;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int p = V.cols;
+  T *ss = reinterpret_cast<T *>(smem);
+  double *red = reinterpret_cast<double *>(smem + ((p * kRitzMax * sizeof(T) + 15) & ~15));
+  for (int idx = threadIdx.x; idx < p * kRitzMax; idx += blockDim.x) {
+    int j = idx / kRitzMax, c = idx % kRitzMax;
+    ss[idx] = c < nb ? (T)S[j + (int64_t)c * lds] : T(0);
+  }
+  __shared__ T th[kRitzMax];
+  if (threadIdx.x < kRitzMax) th[threadIdx.x] = threadIdx.x < nb ? (T)theta[threadIdx.x] : T(0);
+  __syncthreads();
+  double rs[NB], xs[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) rs[c] = xs[c] = 0.0;
+  const int64_t N = V.rows;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    T ax[NB], aw[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) ax[c] = aw[c] = T(0);
+    for (int j = 0; j < p; ++j) {
+      T v = V.p[r + (int64_t)j * V.cs];
+      T w = W.p[r + (int64_t)j * W.cs];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        T sv = ss[j * kRitzMax + c];
+        ax[c] = fma(v, sv, ax[c]);
+        aw[c] = fma(w, sv, aw[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      T rr = aw[c] - th[c] * ax[c];
+      X[r * ldx + c] = ax[c];
+      R[r * ldx + c] = rr;
+      rs[c] += (double)rr * (double)rr;
+      if (r < ntop) xs[c] += (double)ax[c] * (double)ax[c];
+    }
+  }
+  // block reduction of the 2 nb sums
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    red[threadIdx.x] = rs[c];
+    red[256 + threadIdx.x] = xs[c];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) {
+        red[threadIdx.x] += red[threadIdx.x + o];
+        red[256 + threadIdx.x] += red[256 + threadIdx.x + o];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      part[(int64_t)blockIdx.x * 2 * nb + c] = red[0];
+      part[(int64_t)blockIdx.x * 2 * nb + nb + c] = red[256];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_reduce_vec(const double *part, int nblk, int E, double *out0, double *out1,
+                             int split) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * E + e];
+  if (e < split) {
+    if (out0) out0[e] = s;
+  } else if (out1) {
+    out1[e - split] = s;
+  }
+}
+
+template <typename T>
+void ritz(const Tall<T> &V, const Tall<T> &W, const double *S, int lds, const double *theta,
+          T *X, T *R, int nb, int ldx, double *rn2, double *xt2, int64_t ntop, const Scratch &sc,
+          hipStream_t s) {
+  PHS_REQUIRE(nb <= kRitzMax && V.rs == 1 && W.rs == 1, kEinval, "ritz: bad operands");
+  int64_t blocks = cdiv(V.rows, 256);
+  if (blocks > 1024) blocks = 1024;
+  size_t shm = ((V.cols * kRitzMax * sizeof(T) + 15) & ~(size_t)15) + 512 * sizeof(double);
+  prof_begin(kProfRitz, s);
+#define PHS_RITZ(NB)                                                                       \
+  k_ritz<T, NB><<<(unsigned)blocks, 256, shm, s>>>(tv(V), tv(W), S, lds, theta, X, R, ldx, ntop, \
+                                                    sc.part)
+  switch (nb) {
+    case 1: PHS_RITZ(1); break;
+    case 2: PHS_RITZ(2); break;
+    case 3: PHS_RITZ(3); break;
+    case 4: PHS_RITZ(4); break;
+    case 5: PHS_RITZ(5); break;
+    case 6: PHS_RITZ(6); break;
+    case 7: PHS_RITZ(7); break;
+    case 8: PHS_RITZ(8); break;
+    case 16: PHS_RITZ(16); break;
+    case 32: PHS_RITZ(32); break;
+    default: throw Error(kEinval, "ritz: unsupported block width");
+  }
+#undef PHS_RITZ
+  k_reduce_vec<<<1, 64, 0, s>>>(sc.part, (int)blocks, 2 * nb, rn2, xt2, nb);
+  PHS_CHECK_LAUNCH();
+  prof_end(kProfRitz, s, (double)V.rows * (2.0 * V.cols + 2.0 * nb) * sizeof(T));
+}
+
+// ------------------------------------------------------------ col norms
+template <typename T>
+__global__ __launch_bounds__(256) void k_colnorm2(TV<T> x, int64_t r0, int64_t r1,
+                                                  double *part) {
+  __shared__ double red[256];
+  for (int j = 0; j < x.cols; ++j) {
+    double acc = 0.0;
+    for (int64_t r = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < r1;
+         r += (int64_t)gridDim.x * blockDim.x) {
+      double v = (double)x.p[r * x.rs + (int64_t)j * x.cs];
+      acc += v * v;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * x.cols + j] = red[0];
+    __syncthreads();
+  }
+}
+
+template <typename T>
+void colnorm2(const Tall<T> &X, int64_t r0, int64_t r1, double *out, const Scratch &sc,
+              hipStream_t s) {
+  if (X.cols == 0) return;
+  int64_t blocks = cdiv(r1 - r0 > 0 ? r1 - r0 : 1, 256 * 4);
+  if (blocks > 512) blocks = 512;
+  k_colnorm2<T><<<(unsigned)blocks, 256, 0, s>>>(tv(X), r0, r1, sc.part);
+  k_reduce_vec<<<cdiv(X.cols, 64), 64, 0, s>>>(sc.part, (int)blocks, X.cols, out, nullptr,
+                                               X.cols);
+  PHS_CHECK_LAUNCH();
+}
+
+// ------------------------------------------------------- element-wise
+template <typename Ti, typename To>
+__global__ void k_copy(TV<Ti> a, To *bp, int64_t brs, int64_t bcs, bool dst_cm) {
+  const int64_t n = a.rows * a.cols;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i, j;
+    if (dst_cm) {
+      i = idx % a.rows;
+      j = idx / a.rows;
+    } else {
+      i = idx / a.cols;
+      j = idx % a.cols;
+    }
+    bp[i * brs + j * bcs] = (To)a.p[i * a.rs + j * a.cs];
+  }
+}
+
+template <typename Ti, typename To>
+void copy(const Tall<Ti> &src, const Tall<To> &dst, hipStream_t s) {
+  const int64_t n = src.rows * src.cols;
+  if (n == 0) return;
+  PHS_REQUIRE(src.rows == dst.rows && src.cols == dst.cols, kEinval, "copy: shape mismatch");
+  int64_t blocks = cdiv(n, 256);
+  if (blocks > 8192) blocks = 8192;
+  k_copy<Ti, To><<<(unsigned)blocks, 256, 0, s>>>(tv(src), dst.p, dst.rs, dst.cs, dst.rs == 1);
+  PHS_CHECK_LAUNCH();
+}
+
+template <typename T>
+__global__ void k_scale_cols(T *p, int64_t rows, int cols, int64_t rs, int64_t cs,
+                             const double *f) {
+  const int64_t n = rows * cols;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = rs == 1 ? idx % rows : idx / cols;
+    int64_t j = rs == 1 ? idx / rows : idx % cols;
+    p[i * rs + j * cs] *= (T)f[j];
+  }
+}
+
+template <typename T>
+void scale_cols(const Tall<T> &X, const double *f, hipStream_t s) {
+  const int64_t n = X.rows * X.cols;
+  if (n == 0) return;
+  int64_t blocks = cdiv(n, 256);
+  if (blocks > 8192) blocks = 8192;
+  k_scale_cols<T><<<(unsigned)blocks, 256, 0, s>>>(X.p, X.rows, X.cols, X.rs, X.cs, f);
+  PHS_CHECK_LAUNCH();
+}
+
+template <typename T>
+__global__ void k_axpby(TV<T> x, TV<T> z, double shift, T *yp, int64_t yrs, int64_t ycs) {
+  const int64_t n = x.rows * x.cols;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = yrs == 1 ? idx % x.rows : idx / x.cols;
+    int64_t j = yrs == 1 ? idx / x.rows : idx % x.cols;
+    yp[i * yrs + j * ycs] = x.p[i * x.rs + j * x.cs] - (T)shift * z.p[i * z.rs + j * z.cs];
+  }
+}
+
+template <typename T>
+void axpby(const Tall<T> &X, const Tall<T> &Z, double shift, const Tall<T> &Y, hipStream_t s) {
+  const int64_t n = X.rows * X.cols;
+  if (n == 0) return;
+  int64_t blocks = cdiv(n, 256);
+  if (blocks > 8192) blocks = 8192;
+  k_axpby<T><<<(unsigned)blocks, 256, 0, s>>>(tv(X), tv(Z), shift, Y.p, Y.rs, Y.cs);
+  PHS_CHECK_LAUNCH();
+}
+
+template <typename T>
+__global__ void k_fill_random(T *p, int64_t rows, int cols, int64_t rs, int64_t cs,
+                              uint64_t seed, uint64_t sid) {
+  const int64_t n = rows * cols;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = idx % rows, j = idx / rows;
+    p[i * rs + j * cs] = (T)stream_uniform(seed, sid + (uint64_t)j, (uint64_t)i);
+  }
+}
+
+template <typename T>
+void fill_random(const Tall<T> &X, uint64_t seed, uint64_t sid, hipStream_t s) {
+  const int64_t n = X.rows * X.cols;
+  if (n == 0) return;
+  int64_t blocks = cdiv(n, 256);
+  if (blocks > 8192) blocks = 8192;
+  k_fill_random<T><<<(unsigned)blocks, 256, 0, s>>>(X.p, X.rows, X.cols, X.rs, X.cs, seed, sid);
+  PHS_CHECK_LAUNCH();
+}
+
+// ------------------------------------------------------------ Jacobi
+// den = d - theta, clamped away from 0 by 1e-3 d (sign kept).
+__device__ inline double jac_den(double d, double th) {
+  double den = d - th, lim = 1e-3 * d;
+  if (fabs(den) < lim) den = den >= 0 ? lim : -lim;
+  return den;
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_jacobi1(const T *R, const T *X, const double *d,
+                                                 const double *theta, int64_t n, int ldx,
+                                                 bool olsen, T *Tout, double *part) {
+  constexpr int nb = NB;
+  __shared__ double red[2][256];
+  double a[NB], b[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) a[c] = b[c] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      double den = jac_den(d[i], theta[c]);
+      double mr = (double)R[i * ldx + c] / den;
+      Tout[i * ldx + c] = (T)mr;
+      if (olsen) {
+        double x = (double)X[i * ldx + c];
+        a[c] += x * mr;
+        b[c] += x * x / den;
+      }
+    }
+  }
+  if (!olsen) return;
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    red[0][threadIdx.x] = a[c];
+    red[1][threadIdx.x] = b[c];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) {
+        red[0][threadIdx.x] += red[0][threadIdx.x + o];
+        red[1][threadIdx.x] += red[1][threadIdx.x + o];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      part[(int64_t)blockIdx.x * 2 * nb + c] = red[0][0];
+      part[(int64_t)blockIdx.x * 2 * nb + nb + c] = red[1][0];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ void k_jacobi2(const T *X, const double *d, const double *theta, int64_t n, int nb,
+                          int ldx, const double *dots, T *Tout) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    for (int c = 0; c < nb; ++c) {
+      double e = dots[nb + c] != 0.0 ? dots[c] / dots[nb + c] : 0.0;
+      double den = jac_den(d[i], theta[c]);
+      Tout[i * ldx + c] = (T)((double)Tout[i * ldx + c] - e * (double)X[i * ldx + c] / den);
+    }
+  }
+}
+
+template <typename T>
+void jacobi_apply(const T *R, const T *X, const double *d, const double *theta, int64_t n,
+                  int nb, int ldx, bool olsen, T *Tout, const Scratch &sc, hipStream_t s) {
+  PHS_REQUIRE(nb <= kRitzMax, kEinval, "jacobi: block too wide");
+  int64_t blocks = cdiv(n, 256);
+  if (blocks > 1024) blocks = 1024;
+#define PHS_JAC(NB) \
+  k_jacobi1<T, NB><<<(unsigned)blocks, 256, 0, s>>>(R, X, d, theta, n, ldx, olsen, Tout, sc.part)
+  switch (nb) {
+    case 1: PHS_JAC(1); break;
+    case 2: PHS_JAC(2); break;
+    case 3: PHS_JAC(3); break;
+    case 4: PHS_JAC(4); break;
+    case 5: PHS_JAC(5); break;
+    case 6: PHS_JAC(6); break;
+    case 7: PHS_JAC(7); break;
+    case 8: PHS_JAC(8); break;
+    case 16: PHS_JAC(16); break;
+    case 32: PHS_JAC(32); break;
+    default: throw Error(kEinval, "jacobi: unsupported block width");
+  }
+#undef PHS_JAC
+  if (olsen) {
+    k_reduce_vec<<<1, 64, 0, s>>>(sc.part, (int)blocks, 2 * nb, sc.aux, nullptr, 2 * nb);
+    k_jacobi2<T><<<(unsigned)blocks, 256, 0, s>>>(X, d, theta, n, nb, ldx, sc.aux, Tout);
+  }
+  PHS_CHECK_LAUNCH();
+}
+
+__global__ void k_col_sq_norms(int64_t n, const int64_t *rp, const double *va, double *d) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int64_t p = rp[j]; p < rp[j + 1]; ++p) s += va[p] * va[p];
+  d[j] = s;
+}
+
+void col_sq_norms(const SpMat<double> &At, double *d, hipStream_t s) {
+  if (At.m == 0) return;
+  k_col_sq_norms<<<cdiv(At.m, 256), 256, 0, s>>>(At.m, At.rowptr, At.val, d);
+  PHS_CHECK_LAUNCH();
+}
+
+template <typename T>
+__global__ void k_row_scale(const T *X, const double *w, int64_t n, int b, bool inv, T *Y) {
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n * b;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = idx / b;
+    Y[idx] = inv ? (T)((double)X[idx] / w[i]) : (T)((double)X[idx] * w[i]);
+  }
+}
+
+template <typename T>
+void row_scale(const T *X, const double *w, int64_t n, int b, bool inv, T *Y, hipStream_t s) {
+  if (n * b == 0) return;
+  int64_t blocks = cdiv(n * b, 256);
+  if (blocks > 8192) blocks = 8192;
+  k_row_scale<T><<<(unsigned)blocks, 256, 0, s>>>(X, w, n, b, inv, Y);
+  PHS_CHECK_LAUNCH();
+}
+
+#define PHS_INST(T)                                                                           \
+  template void tn<T>(const Tall<T> &, const Tall<T> &, const Tall<T> &, double *, int,      \
+                      const Scratch &, hipStream_t);                                         \
+  template void nn<T>(const Tall<T> &, const Tall<T> &, const double *, int, double,         \
+                      const Tall<T> &, double, hipStream_t);                                 \
+  template void ritz<T>(const Tall<T> &, const Tall<T> &, const double *, int, const double *, \
+                        T *, T *, int, int, double *, double *, int64_t, const Scratch &,     \
+                        hipStream_t);                                                         \
+  template void colnorm2<T>(const Tall<T> &, int64_t, int64_t, double *, const Scratch &,     \
+                            hipStream_t);                                                     \
+  template void scale_cols<T>(const Tall<T> &, const double *, hipStream_t);                  \
+  template void axpby<T>(const Tall<T> &, const Tall<T> &, double, const Tall<T> &,           \
+                         hipStream_t);                                                        \
+  template void fill_random<T>(const Tall<T> &, uint64_t, uint64_t, hipStream_t);             \
+  template void jacobi_apply<T>(const T *, const T *, const double *, const double *, int64_t, \
+                                int, int, bool, T *, const Scratch &, hipStream_t);           \
+  template void row_scale<T>(const T *, const double *, int64_t, int, bool, T *, hipStream_t);
+PHS_INST(float)
+PHS_INST(double)
+template void copy<float, float>(const Tall<float> &, const Tall<float> &, hipStream_t);
+template void copy<double, double>(const Tall<double> &, const Tall<double> &, hipStream_t);
+template void copy<float, double>(const Tall<float> &, const Tall<double> &, hipStream_t);
+template void copy<double, float>(const Tall<double> &, const Tall<float> &, hipStream_t);
+
+}  // namespace phs
+
+namespace phs {
+
+// Normalise column j of a column-major X from its squared norm n2 (device):
+// X(:, j) /= sqrt(n2), or zeroed when n2 is below tiny; Rjj = sqrt(n2).
+template <typename T>
+__global__ void k_norm_col(T *x, int64_t rows, const double *n2, double tiny, double *Rjj) {
+  const double nv = sqrt(fmax(n2[0], 0.0));
+  const double f = nv > tiny ? 1.0 / nv : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = (T)((double)x[i] * f);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && Rjj) Rjj[0] = nv > tiny ? nv : 0.0;
+}
+
+template <typename T>
+void norm_col(T *x, int64_t rows, const double *n2, double tiny, double *Rjj, hipStream_t s) {
+  int64_t blocks = cdiv(rows, 256);
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  k_norm_col<T><<<(unsigned)blocks, 256, 0, s>>>(x, rows, n2, tiny, Rjj);
+  PHS_CHECK_LAUNCH();
+}
+template void norm_col<float>(float *, int64_t, const double *, double, double *, hipStream_t);
+template void norm_col<double>(double *, int64_t, const double *, double, double *, hipStream_t);
+
+template <typename T>
+__global__ void k_fill_const(T *p, int64_t rows, int64_t rs, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i * rs] = v;
+}
+
+template <typename T>
+void fill_const_col(T *p, int64_t rows, int64_t rs, double v, hipStream_t s) {
+  int64_t blocks = cdiv(rows, 256);
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  k_fill_const<T><<<(unsigned)blocks, 256, 0, s>>>(p, rows, rs, (T)v);
+  PHS_CHECK_LAUNCH();
+}
+template void fill_const_col<float>(float *, int64_t, int64_t, double, hipStream_t);
+template void fill_const_col<double>(double *, int64_t, int64_t, double, hipStream_t);
+
+}  // namespace phs
