@@ -25,7 +25,9 @@ Readings where the paper is silent (the same readings bind the GPU path):
   * basis sizes: p_max = max(35, 2k + 2b), p_min = max(21, ceil(0.6 p_max)),
     and p_min <= p_max - 2b (the paper's 35/21 for blocks of 1-2);
   * GD+k restart keeps the p_min lowest Ritz vectors plus the previous
-    iteration's b targeted Ritz vectors, orthogonalised against them;
+    iteration's b targeted Ritz vectors, orthogonalised against them (a
+    dependent one is replaced by an independent coordinate vector of the
+    coefficient space, so the restarted basis always has p_min + b columns);
   * hard locking in both stages; only the first (k - locked) targets of the
     block are tested for convergence; in stage 1 a pair that passes the test
     on its recurrence residual W s - theta x is locked only if its explicit
@@ -81,6 +83,7 @@ class Stats:
     restarts1: int = 0
     restarts2: int = 0
     stage2_pairs: int = 0
+    fallback: bool = False
     anorm_est: float = 0.0
     res_stage1: list = field(default_factory=list)
 
@@ -143,22 +146,37 @@ def orth_block(T, bases, rnd: _Rand):
 
 
 def _small_orth_against(P, K):
-    """Orthonormal columns of P orthogonalised against orthonormal K
-    (small coefficient space); dependent columns are dropped."""
+    """Orthonormal columns of P orthogonalised against orthonormal K in the
+    small coefficient space.  A dependent column is replaced by the next
+    coordinate vector that is independent, so the result always has
+    min(P.cols, rows - K.cols) columns."""
+    rows = P.shape[0]
+    want = min(P.shape[1], rows - K.shape[1])
     out = []
-    for j in range(P.shape[1]):
-        t = P[:, j].copy()
-        n0 = np.linalg.norm(t)
-        if n0 == 0:
-            continue
-        cur = [K] + ([np.column_stack(out)] if out else [])
-        for _ in range(2):
-            t = _project_out(t, cur)
-        n2 = np.linalg.norm(t)
-        if n2 > 1e-8 * n0:
-            out.append(t / n2)
+    unit = 0
+    c = 0
+    while len(out) < want:
+        if c < P.shape[1]:
+            t = P[:, c].copy()
+            c += 1
+        else:
+            t = np.zeros(rows)
+            t[unit] = 1.0
+            unit += 1
+        while True:
+            n0 = np.linalg.norm(t)
+            cur = [K] + ([np.column_stack(out)] if out else [])
+            for _ in range(2):
+                t = _project_out(t, cur)
+            n2 = np.linalg.norm(t)
+            if n0 > 0 and n2 > 1e-8 * n0:
+                out.append(t / n2)
+                break
+            t = np.zeros(rows)
+            t[unit] = 1.0
+            unit += 1
     if not out:
-        return np.zeros((P.shape[0], 0))
+        return np.zeros((rows, 0))
     return np.column_stack(out)
 
 
@@ -177,11 +195,15 @@ def _pad(Sc, rows):
 # --------------------------------------------------------------------------
 def stage1_gdk(A, k, tol, b, pmax, pmin, X0, which="smallest", precond=None, anorm=None,
                max_restarts=10000, floor=10.0, eps=EPS64, seed=11, stats: Stats | None = None,
-               max_iters=None):
+               max_iters=None, callback=None, fallback=None, fallback_window=25):
     """Block GD+k on C for k extreme eigenpairs (Sections 2.2, 2.4, 3.1).
 
     ``precond(R, theta, X) -> T`` maps the residual block to the correction
-    block (None: T = R).  Returns (X_lock, theta_lock, V_rest, s_n^2, info)
+    block (None: T = R).  ``callback(it, X, R, theta, X_lock)`` sees every
+    iteration's Ritz block (used to harvest training pairs).  With a
+    ``fallback`` preconditioner, ``precond`` is replaced by it for the rest
+    of the run when the leading residual has not halved within a window of
+    ``fallback_window`` iterations (the learned preconditioner's safeguard).  Returns (X_lock, theta_lock, V_rest, s_n^2, info)
     with theta ascending for 'smallest', descending for 'largest'."""
     stats = stats if stats is not None else Stats()
     n = A.shape[1]
@@ -202,6 +224,8 @@ def stage1_gdk(A, k, tol, b, pmax, pmin, X0, which="smallest", precond=None, ano
     L = max(100, 20 * int(math.ceil(pmax / b)))
     it = 0
     converged = False
+    pc_hist = []
+    stats.fallback = False
     while True:
         it += 1
         theta, S = np.linalg.eigh(H)
@@ -214,6 +238,14 @@ def stage1_gdk(A, k, tol, b, pmax, pmin, X0, which="smallest", precond=None, ano
         X = V @ S[:, :nb]
         R = W @ S[:, :nb] - X * theta[:nb]
         rn = np.linalg.norm(R, axis=0)
+        if callback is not None:
+            callback(it, X, R, theta[:nb], Xl)
+        if fallback is not None and not stats.fallback:
+            pc_hist.append(rn[0])
+            Lf = fallback_window
+            if len(pc_hist) >= 2 * Lf and min(pc_hist[-Lf:]) > 0.5 * min(pc_hist[-2 * Lf:-Lf]):
+                precond = fallback
+                stats.fallback = True
         need = k - len(thl)
 
         def thr_of(i):
@@ -245,6 +277,7 @@ def stage1_gdk(A, k, tol, b, pmax, pmin, X0, which="smallest", precond=None, ano
                 continue
         if conv:
             hist = []
+            pc_hist = []
             for i in conv:
                 Xl = np.column_stack([Xl, X[:, i]])
                 thl.append(float(theta[i]))
@@ -499,11 +532,12 @@ def _final(A, V, U, stats, AV=None):
 
 def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, anorm=None,
            stage2="auto", max_basis=None, min_restart=None, max_restarts=10000, floor=10.0,
-           seed=2, max_iters=None):
+           seed=2, max_iters=None, gnn_params=None):
     """k smallest (or largest) singular triplets of A by PHSVDS.
 
     Returns dict(sigma, U, V, res, stats, stage1_sigma).  ``precond`` is
-    'none' or 'jacobi' (stage 1: Olsen-Jacobi on C; stage 2: its B-form)."""
+    'none', 'jacobi' (stage 1: Olsen-Jacobi on C; stage 2: its B-form) or
+    'gnn' (stage 1: the learned network of oracle.precond with gnn_params)."""
     import workloads  # seeded inputs only
 
     m, n = A.shape
@@ -514,16 +548,26 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
     pmax, pmin = basis_sizes(k, b, max_basis, min_restart)
     if X0 is None:
         X0 = workloads.initial_block(n, b, seed)
-    pc1 = pcB = None
+    pc1 = pcB = fb = None
     if precond == "jacobi":
         d = jacobi_diag(A)
         pc1 = jacobi_precond_C(d)
         pcB = jacobi_precond_B(A, d, stats)
+    elif precond == "gnn":
+        from . import precond as pcmod
+        g = pcmod.Graph(A)
+        d = jacobi_diag(A)
+        fb = jacobi_precond_C(d)
+
+        def pc1(R, theta, X):
+            return np.column_stack([pcmod.forward(g, gnn_params, R[:, i], X[:, i], theta[i])[0]
+                                    for i in range(R.shape[1])])
     elif precond != "none":
         raise ValueError(precond)
     Xl, thl, Vr, sn2, info = stage1_gdk(A, k, tol, b, pmax, pmin, X0, which, pc1, anorm,
                                         max_restarts, floor, EPS64, stats=stats,
-                                        max_iters=max_iters)
+                                        max_iters=max_iters,
+                                        fallback=fb if precond == "gnn" else None)
     sn = math.sqrt(sn2)
     stats.anorm_est = sn
     an = float(anorm) if anorm else sn
@@ -566,3 +610,33 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
     return {"sigma": sigma, "U": U, "V": V, "res": res, "stats": stats,
             "stage1_sigma": s1, "converged": bool(info["converged"]) and len(sigma) == k,
             "anorm": an}
+
+
+def harvest(A, k, b, every=5, max_pairs=64, tol=1e-8, seed=2, cg_tol=1e-8, cg_maxit=2000,
+            max_iters=None):
+    """Training pairs for the learned preconditioner from a stage-1 run:
+    every ``every`` iterations, each unconverged targeted Ritz pair
+    (theta_i, x_i) with residual r_i gives the exact correction t* of
+    (I-QQ^T)(C - theta_i I)(I-QQ^T) t = -r_i, t orthogonal to
+    Q = [X_lock, x_1..x_i] (projected CG).  Pairs whose CG meets
+    non-positive curvature or does not converge are dropped."""
+    import workloads
+    from . import precond as pcmod
+    n = A.shape[1]
+    pmax, pmin = basis_sizes(k, b)
+    X0 = workloads.initial_block(n, b, seed)
+    out = []
+
+    def cb(it, X, R, theta, Xl):
+        if it % every or len(out) >= max_pairs:
+            return
+        for i in range(X.shape[1]):
+            if len(out) >= max_pairs:
+                return
+            Q = np.column_stack([Xl, X[:, :i + 1]])
+            t, its, ok = pcmod.projected_cg(A, float(theta[i]), Q, R[:, i], cg_tol, cg_maxit)
+            if ok:
+                out.append((R[:, i].copy(), X[:, i].copy(), float(theta[i]), t))
+
+    stage1_gdk(A, k, tol, b, pmax, pmin, X0, callback=cb, max_iters=max_iters)
+    return out

@@ -1,0 +1,187 @@
+"""Learned preconditioner and exact corrections, float64 (test oracle).
+
+The paper accepts any preconditioner for C (Section 4) and applies it as
+t = Prec(r) in the correction step (Algorithm 2 step 13).  The learned one
+here is a message-passing network over the sparsity graph of C = A^T A that
+maps a residual r of a Ritz pair (theta, x) to an approximate correction of
+(C - theta I), trained on exact corrections of the projected correction
+equation
+
+    (I - Q Q^T)(C - theta I)(I - Q Q^T) t = -r,   t orthogonal to Q,
+
+(Q = locked vectors plus x), solved by conjugate gradients.
+
+Network (width w, three layers):
+    d_j   = C_jj / mean(diag C),  tau = theta / mean(diag C)
+    rh    = r sqrt(n) / ||r||
+    h0_j  = [rh_j, rh_j / max(d_j - tau, d_j / 10), d_j, tau]
+    h^l   = relu(h^{l-1} Ws_l + b_l + Ch (h^{l-1} Wm_l)),  l = 1..3
+    Ch    = D^-1/2 A^T A D^-1/2  (applied as two sparse products)
+    t~    = (h^3 wo) ||r|| / (sqrt(n) mean(diag C))
+    t     = (I - x x^T) t~
+Loss of one sample: ||t - t*||^2 / ||t*||^2 (t* is orthogonal to x).
+Optimiser: Adam (Kingma & Ba), lr 1e-3, beta1 0.9, beta2 0.999, eps 1e-8.
+
+Parity of the trained network's quality: unpinned (judged by product counts
+and time against Jacobi and no preconditioner on held-out matrices).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+NAMES = ["Ws1", "Wm1", "b1", "Ws2", "Wm2", "b2", "Ws3", "Wm3", "b3", "wo"]
+
+
+def shapes(width=32, nin=4):
+    w = width
+    return {"Ws1": (nin, w), "Wm1": (nin, w), "b1": (w,), "Ws2": (w, w), "Wm2": (w, w),
+            "b2": (w,), "Ws3": (w, w), "Wm3": (w, w), "b3": (w,), "wo": (w,)}
+
+
+def flatten(params, width=32):
+    return np.concatenate([np.asarray(params[k], dtype=np.float64).ravel() for k in NAMES])
+
+
+def unflatten(vec, width=32):
+    out, at = {}, 0
+    for k in NAMES:
+        shp = shapes(width)[k]
+        size = int(np.prod(shp))
+        out[k] = np.asarray(vec[at:at + size], dtype=np.float64).reshape(shp)
+        at += size
+    assert at == len(vec)
+    return out
+
+
+class Graph:
+    """A, diag(C) and the symmetric normalised operator Ch = D^-1/2 A^T A D^-1/2."""
+
+    def __init__(self, A):
+        self.A = A.tocsr()
+        self.At = self.A.T.tocsr()
+        self.d = np.asarray(self.A.multiply(self.A).sum(axis=0)).ravel()
+        self.dmean = float(self.d.mean())
+        self.isd = 1.0 / np.sqrt(self.d)
+
+    def Ch(self, Z):
+        Y = self.A @ (Z * self.isd[:, None])
+        return (self.At @ Y) * self.isd[:, None]
+
+
+def features(g: Graph, r, theta):
+    n = r.shape[0]
+    nr = np.linalg.norm(r)
+    rh = r * math.sqrt(n) / nr
+    d = g.d / g.dmean
+    tau = theta / g.dmean
+    den = np.maximum(d - tau, 0.1 * d)
+    return np.column_stack([rh, rh / den, d, np.full(n, tau)]), nr
+
+
+def forward(g: Graph, P, r, x, theta):
+    """Correction t for residual r of the Ritz pair (theta, x); also the
+    intermediate values needed by the backward pass."""
+    n = r.shape[0]
+    h0, nr = features(g, r, theta)
+    hs, pres, aggs = [h0], [], []
+    h = h0
+    for l in (1, 2, 3):
+        M = h @ P[f"Wm{l}"]
+        agg = g.Ch(M)
+        pre = h @ P[f"Ws{l}"] + P[f"b{l}"][None, :] + agg
+        h = np.maximum(pre, 0.0)
+        pres.append(pre)
+        hs.append(h)
+    scale = nr / (math.sqrt(n) * g.dmean)
+    traw = (h @ P["wo"]) * scale
+    t = traw - x * (x @ traw)
+    return t, {"hs": hs, "pres": pres, "scale": scale}
+
+
+def loss_and_grad(g: Graph, P, r, x, theta, tstar):
+    """Loss ||t - t*||^2 / ||t*||^2 and its gradient by back-propagation."""
+    t, cache = forward(g, P, r, x, theta)
+    nt = float(tstar @ tstar)
+    diff = t - tstar
+    loss = float(diff @ diff) / nt
+    gt = 2.0 * diff / nt
+    graw = gt - x * (x @ gt)  # through the projection (I - x x^T)
+    hs, pres, scale = cache["hs"], cache["pres"], cache["scale"]
+    grads = {}
+    grads["wo"] = scale * (hs[3].T @ graw)
+    dh = scale * np.outer(graw, P["wo"])
+    for l in (3, 2, 1):
+        delta = dh * (pres[l - 1] > 0)
+        hin = hs[l - 1]
+        grads[f"Ws{l}"] = hin.T @ delta
+        grads[f"b{l}"] = delta.sum(axis=0)
+        dM = g.Ch(delta)  # Ch is symmetric
+        grads[f"Wm{l}"] = hin.T @ dM
+        dh = delta @ P[f"Ws{l}"].T + dM @ P[f"Wm{l}"].T
+    return loss, grads
+
+
+def adam_step(params, grads, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (step counts from 1); returns new params, m, v."""
+    out_p, out_m, out_v = {}, {}, {}
+    for k in NAMES:
+        mk = b1 * m[k] + (1 - b1) * grads[k]
+        vk = b2 * v[k] + (1 - b2) * grads[k] ** 2
+        mh = mk / (1 - b1 ** step)
+        vh = vk / (1 - b2 ** step)
+        out_p[k] = params[k] - lr * mh / (np.sqrt(vh) + eps)
+        out_m[k], out_v[k] = mk, vk
+    return out_p, out_m, out_v
+
+
+def projected_cg(A, theta, Q, r, tol=1e-8, maxit=2000):
+    """t orthogonal to Q with (I-QQ^T)(C - theta I)(I-QQ^T) t = -(I-QQ^T) r,
+    by conjugate gradients (the operator is SPD on the complement of Q when
+    theta is below the spectrum left there).  Returns (t, iterations, ok);
+    ok is False on non-positive curvature or no convergence."""
+    Q = np.asarray(Q, dtype=np.float64)
+
+    def proj(v):
+        return v - Q @ (Q.T @ v)
+
+    def op(v):
+        v = proj(v)
+        return proj(A.T @ (A @ v) - theta * v)
+
+    b = -proj(r)
+    t = np.zeros_like(b)
+    res = b.copy()
+    p = res.copy()
+    rr = float(res @ res)
+    nb = math.sqrt(rr)
+    if nb == 0:
+        return t, 0, True
+    for it in range(1, maxit + 1):
+        Ap = op(p)
+        pAp = float(p @ Ap)
+        if pAp <= 0:
+            return proj(t), it, False
+        alpha = rr / pAp
+        t = t + alpha * p
+        res = res - alpha * Ap
+        rr_new = float(res @ res)
+        if math.sqrt(rr_new) <= tol * nb:
+            return proj(t), it, True
+        p = res + (rr_new / rr) * p
+        rr = rr_new
+    return proj(t), maxit, False
+
+
+def jacobi_apply(d, R, theta, X=None, olsen=False, clamp=1e-3):
+    T = np.empty_like(R)
+    for i in range(R.shape[1]):
+        den = d - theta[i]
+        den = np.where(np.abs(den) < clamp * d, np.where(den >= 0, clamp * d, -clamp * d), den)
+        T[:, i] = R[:, i] / den
+        if olsen and X is not None:
+            Mx = X[:, i] / den
+            e = (X[:, i] @ T[:, i]) / (X[:, i] @ Mx)
+            T[:, i] = T[:, i] - e * Mx
+    return T

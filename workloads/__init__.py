@@ -41,6 +41,7 @@ __all__ = [
     "initial_block",
     "uniform_block",
     "zipf_shift_for_mean",
+    "gnn_init_weights",
 ]
 
 
@@ -219,3 +220,24 @@ def uniform_block(n: int, b: int, seed: int) -> np.ndarray:
     """Seeded U(-0.5, 0.5) block, used where the method needs random
     vectors (replacements for dependent columns, random left vectors)."""
     return np.asfortranarray(np.random.default_rng(seed).uniform(-0.5, 0.5, size=(n, b)))
+
+
+def gnn_init_weights(width: int = 32, nin: int = 4, seed: int = 0) -> dict:
+    """Initial weights of the message-passing preconditioner: Glorot-uniform
+    matrices, zero biases, float32-representable values (the network trains
+    in float32).  Layout and names: Ws1, Wm1 (nin x width), b1, then Ws2,
+    Wm2, b2, Ws3, Wm3, b3 (width x width / width), then wo (width)."""
+    rng = np.random.default_rng(seed)
+
+    def glorot(fi, fo):
+        lim = math.sqrt(6.0 / (fi + fo))
+        return rng.uniform(-lim, lim, size=(fi, fo)).astype(np.float32).astype(np.float64)
+
+    w = width
+    P = {"Ws1": glorot(nin, w), "Wm1": glorot(nin, w), "b1": np.zeros(w)}
+    for l in (2, 3):
+        P[f"Ws{l}"] = glorot(w, w)
+        P[f"Wm{l}"] = glorot(w, w)
+        P[f"b{l}"] = np.zeros(w)
+    P["wo"] = glorot(w, 1)[:, 0]
+    return P
