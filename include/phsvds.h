@@ -52,7 +52,9 @@ typedef struct {
  * Section 4).  NONE: t = r.  JACOBI: t = (diag(C) - theta)^-1 r in stage 1
  * (Olsen form), its B-form [M A^T g; A M f] in stage 2 (Section 4).
  * GNN: the learned message-passing network given by `gnn_weights`
- * (layout of phsvds_gnn_nweights), stage 1 only. */
+ * (layout below, phsvds_gnn_nweights floats), stage 1 only, with Jacobi as
+ * the fallback when the leading residual stops halving within 25
+ * iterations. */
 enum { PHSVDS_PREC_NONE = 0, PHSVDS_PREC_JACOBI = 1, PHSVDS_PREC_GNN = 2 };
 
 typedef struct {
@@ -76,6 +78,8 @@ typedef struct {
                                for [ones/sqrt(n), random] (Section 5) */
   double anorm;        /* ||A|| if known (> 0), else the running estimate */
   double floor_factor; /* multiple of eps*||C|| that ends stage 1 (default 10) */
+  int gnn_width;       /* width of the learned preconditioner the workspace must
+                          hold (0: none); must match phsvds_precond.gnn_width */
 } phsvds_opts;
 
 typedef struct {
@@ -84,6 +88,9 @@ typedef struct {
   int64_t mv_floor;   /* |A| products for the float32 accuracy floor */
   int64_t iters1, iters2, restarts1, restarts2;
   int64_t stage2_pairs, fp32_locked;
+  int64_t fallbacks;  /* learned preconditioner replaced by Jacobi (safeguard) */
+  int64_t refreshes;  /* W = C V rebuilt after a failed explicit-residual check */
+  int64_t rollbacks;  /* basis expansions undone after a failed deferred check */
   double t_setup, t_stage1, t_stage2, t_total; /* seconds (host wall clock) */
   double anorm_est;
   double res_stage1[64]; /* residual ||r_C|| of each pair on leaving stage 1 */
@@ -106,6 +113,16 @@ int phsvds_spmm_f64(const phsvds_csr *A, int b, const double *X, double *Y, int 
  * sparsity of A; A->val is not read). */
 int phsvds_spmm_f32(const phsvds_csr *A, const float *val32, int b, const float *X, float *Y,
                     int absval, void *stream);
+
+/* Rayleigh-Ritz eigenproblem of the search space, H s = theta s with
+ * H = V^T C V (Algorithm 1, the projection step of each iteration):
+ * H device p x p column-major (ld ldh >= p, symmetric part used, not
+ * modified), 1 <= p <= 64, 1 <= nvec <= p.  Writes the nvec eigenpairs at the
+ * wanted end (smallest ascending, or largest descending if `largest`) to
+ * theta[0..nvec) and columns 0..nvec-1 of S (device, ld lds >= p), and the
+ * eigenvalue at the other end to theta[p-1]; other entries are untouched. */
+int phsvds_rr_eig(const double *H, int ldh, int p, int nvec, int largest, double *theta,
+                  double *S, int lds, void *stream);
 
 /* CSR of A^T (n x m) built on the device: t_rowptr (n+1), t_colind (nnz),
  * t_val (nnz); rows of A^T come out sorted by column.  `ws` must hold
@@ -132,6 +149,52 @@ int phsvds_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int k, const phsvd
 int phsvds_svds(const phsvds_csr *A, int k, double tol, const phsvds_precond *P,
                 const phsvds_opts *opts, void *workspace, size_t ws_bytes, void *stream,
                 double *sigma, double *U, double *V, double *resnorm, phsvds_stats *stats);
+
+/* ---- Learned preconditioner (message-passing network over the graph of
+ * C = A^T A, float32).  Not in the paper: a preconditioner for C of the kind
+ * Section 4 admits.  Per node j, width w in {8, 16, 32}, three layers:
+ *   h0_j = [rh_j, rh_j / max(d_j - tau, d_j/10), d_j, tau],
+ *          rh = r sqrt(n)/||r||, d = diag(C)/mean diag(C), tau = theta/mean diag(C)
+ *   h^l = relu(h^{l-1} Ws_l + b_l + Ch (h^{l-1} Wm_l)), Ch = D^-1/2 A^T A D^-1/2
+ *   t   = (I - x x^T) (h^3 wo) ||r|| / (sqrt(n) mean diag(C))
+ * Weights: one float32 array, row-major blocks in the order
+ * Ws1, Wm1 (4 x w), b1 (w), Ws2, Wm2 (w x w), b2, Ws3, Wm3, b3, wo (w).
+ * A per-matrix workspace `gws` (phsvds_gnn_workspace_bytes) holds the
+ * prepared graph and activations; phsvds_gnn_prepare fills it once.
+ * r, x, t, tstar are device float32 vectors of length n. */
+int64_t phsvds_gnn_nweights(int width);
+size_t phsvds_gnn_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int width);
+int phsvds_gnn_prepare(const phsvds_csr *A, int width, void *gws, size_t gws_bytes,
+                       void *stream);
+/* t = network(r; x, theta). */
+int phsvds_gnn_forward(const phsvds_csr *A, int width, void *gws, size_t gws_bytes,
+                       const float *w, const float *r, const float *x, double theta, float *t,
+                       void *stream);
+/* Adds ||t - tstar||^2 / ||tstar||^2 to *loss and its gradient with respect to
+ * the weights to grad (device float64, phsvds_gnn_nweights entries). */
+int phsvds_gnn_loss_grad(const phsvds_csr *A, int width, void *gws, size_t gws_bytes,
+                         const float *w, const float *r, const float *x, double theta,
+                         const float *tstar, double *grad, double *loss, void *stream);
+/* One Adam step (Kingma & Ba; beta1 0.9, beta2 0.999, eps 1e-8) on the
+ * float32 weights w with moments m, v (device, nw floats), gradient
+ * grad * grad_scale; step counts from 1. */
+int phsvds_gnn_adam(float *w, float *m, float *v, const double *grad, int64_t nw, int step,
+                    double lr, double grad_scale, void *stream);
+
+/* Training pairs from a float64 stage-1 run on A (k smallest, opts->block):
+ * every `every` iterations, each targeted Ritz pair (theta, x) with residual
+ * r gets the exact correction t of (I-QQ^T)(C - theta I)(I-QQ^T) t = -r,
+ * t orthogonal to Q = [locked vectors, Ritz block], by projected CG
+ * (relative tolerance cg_tol, at most cg_maxit steps); pairs with
+ * non-positive curvature or no convergence are skipped.  Outputs (device,
+ * n x max_pairs column-major): R, X, T; theta (host, max_pairs); *count
+ * pairs written.  Stage 1 stops at tolerance `tol`. */
+int phsvds_harvest_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int k,
+                                   const phsvds_opts *opts, size_t *bytes);
+int phsvds_harvest(const phsvds_csr *A, int k, int every, int max_pairs, double tol,
+                   double cg_tol, int cg_maxit, const phsvds_opts *opts, void *workspace,
+                   size_t ws_bytes, void *stream, double *R, double *X, double *T, double *theta,
+                   int *count, phsvds_stats *stats);
 
 /* Kernel timing for benchmarks: HIP event pairs recorded on the launching
  * stream around each operation of a kind.  phsvds_profile(1) clears the

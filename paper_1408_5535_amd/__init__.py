@@ -47,13 +47,15 @@ class _Opts(ctypes.Structure):
                 ("fp64_continue", ctypes.c_int), ("stage2", ctypes.c_int),
                 ("max_restarts", ctypes.c_int), ("max_matvecs", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("init_block", ctypes.c_void_p),
-                ("anorm", ctypes.c_double), ("floor_factor", ctypes.c_double)]
+                ("anorm", ctypes.c_double), ("floor_factor", ctypes.c_double),
+                ("gnn_width", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in
                 ("mv_stage1", "mv_rr", "mv_stage2", "mv_final", "mv_prec", "mv_floor",
-                 "iters1", "iters2", "restarts1", "restarts2", "stage2_pairs", "fp32_locked")] + \
+                 "iters1", "iters2", "restarts1", "restarts2", "stage2_pairs", "fp32_locked",
+                 "fallbacks", "refreshes", "rollbacks")] + \
                [(f, ctypes.c_double) for f in
                 ("t_setup", "t_stage1", "t_stage2", "t_total", "anorm_est")] + \
                [("res_stage1", ctypes.c_double * 64)]
@@ -71,6 +73,8 @@ _lib.phsvds_last_error.restype = ctypes.c_char_p
 _lib.phsvds_default_opts.argtypes = [ctypes.POINTER(_Opts)]
 _lib.phsvds_spmm_f64.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, _P, _P, ctypes.c_int, _P]
 _lib.phsvds_spmm_f32.argtypes = [ctypes.POINTER(_Csr), _P, ctypes.c_int, _P, _P, ctypes.c_int, _P]
+_lib.phsvds_rr_eig.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P,
+                               _P, ctypes.c_int, _P]
 _lib.phsvds_transpose_ws_bytes.argtypes = [ctypes.POINTER(_Csr)]
 _lib.phsvds_transpose_ws_bytes.restype = ctypes.c_size_t
 _lib.phsvds_csr_transpose.argtypes = [ctypes.POINTER(_Csr), _P, _P, _P, _P, ctypes.c_size_t, _P]
@@ -169,6 +173,20 @@ def spmm(A: DeviceCSR, X: torch.Tensor, absval: bool = False, val32: torch.Tenso
     return Y
 
 
+def rr_eig(H: torch.Tensor, nvec: int, largest: bool = False):
+    """Selected eigenpairs of the symmetric p x p device float64 matrix H
+    (p <= 64): (theta (p,), S (p x p)); theta[:nvec], S[:, :nvec] are the
+    nvec wanted pairs, theta[p-1] the eigenvalue at the other end, the rest
+    NaN."""
+    p = H.shape[0]
+    Hc = H.to(dtype=torch.float64).t().contiguous()  # column-major
+    theta = torch.full((p,), float("nan"), dtype=torch.float64, device=H.device)
+    S = torch.full((p, p), float("nan"), dtype=torch.float64, device=H.device)
+    _check(_lib.phsvds_rr_eig(Hc.data_ptr(), p, p, nvec, int(largest), theta.data_ptr(),
+                              S.data_ptr(), p, _stream()), "rr_eig")
+    return theta, S.t()
+
+
 def csr_transpose(A: DeviceCSR) -> DeviceCSR:
     c = A._c()
     dev = A.rowptr.device
@@ -184,7 +202,7 @@ def csr_transpose(A: DeviceCSR) -> DeviceCSR:
 
 def make_opts(which="smallest", block=1, max_basis=0, min_restart=0, stage1_fp32=False,
               fp64_continue=True, stage2="auto", max_restarts=10000, max_matvecs=0, seed=1,
-              init_block=None, anorm=0.0, floor_factor=10.0):
+              init_block=None, anorm=0.0, floor_factor=10.0, gnn_width=0):
     o = _Opts()
     _lib.phsvds_default_opts(ctypes.byref(o))
     o.which = {"smallest": 0, "largest": 1}[which]
@@ -204,6 +222,7 @@ def make_opts(which="smallest", block=1, max_basis=0, min_restart=0, stage1_fp32
         o.init_block = keep.data_ptr()
     o.anorm = float(anorm)
     o.floor_factor = floor_factor
+    o.gnn_width = gnn_width
     o._keep = keep
     return o
 
@@ -226,13 +245,14 @@ class Solver:
         self.U = torch.empty((k, A.m), dtype=torch.float64, device=A.rowptr.device)
         self.V = torch.empty((k, A.n), dtype=torch.float64, device=A.rowptr.device)
 
-    def solve(self, tol=1e-12, precond="none"):
+    def solve(self, tol=1e-12, precond="none", gnn_weights=None, gnn_width=32):
         import numpy as np
         k = self.k
         sig = (ctypes.c_double * k)()
         res = (ctypes.c_double * k)()
         st = _Stats()
-        pc = _Precond(PREC[precond], None, 0)
+        pc = _Precond(PREC[precond], gnn_weights.data_ptr() if gnn_weights is not None else None,
+                      gnn_width)
         c = self.A._c()
         rc = _lib.phsvds_svds(ctypes.byref(c), k, tol, ctypes.byref(pc), ctypes.byref(self.opts),
                               self.ws.data_ptr(), self.ws.numel(), _stream(), sig,
@@ -245,8 +265,152 @@ class Solver:
         return np.array(sig[:]), self.U.T, self.V.T, info
 
 
-def svds_smallest(A: DeviceCSR, k: int, tol: float = 1e-12, precond: str = "none", **opt_kw):
+def svds_smallest(A: DeviceCSR, k: int, tol: float = 1e-12, precond: str = "none",
+                  gnn_weights=None, gnn_width=32, **opt_kw):
     """The k smallest (``which='largest'``: largest) singular triplets of A
     to sqrt(||r_u||^2 + ||r_v||^2) <= tol ||A||.  Returns
     (sigma, U (m x k), V (n x k), info)."""
-    return Solver(A, k, **opt_kw).solve(tol, precond)
+    if precond == "gnn":
+        opt_kw["gnn_width"] = gnn_width
+    return Solver(A, k, **opt_kw).solve(tol, precond, gnn_weights, gnn_width)
+
+
+# ---------------------------------------------------------------- learned preconditioner
+GNN_NAMES = ["Ws1", "Wm1", "b1", "Ws2", "Wm2", "b2", "Ws3", "Wm3", "b3", "wo"]
+_lib.phsvds_gnn_nweights.argtypes = [ctypes.c_int]
+_lib.phsvds_gnn_nweights.restype = ctypes.c_int64
+_lib.phsvds_gnn_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                            ctypes.c_int]
+_lib.phsvds_gnn_workspace_bytes.restype = ctypes.c_size_t
+_lib.phsvds_gnn_prepare.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, _P, ctypes.c_size_t, _P]
+_lib.phsvds_gnn_forward.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, _P, ctypes.c_size_t, _P,
+                                    _P, _P, ctypes.c_double, _P, _P]
+_lib.phsvds_gnn_loss_grad.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, _P, ctypes.c_size_t,
+                                      _P, _P, _P, ctypes.c_double, _P, _P, _P, _P]
+_lib.phsvds_gnn_adam.argtypes = [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
+                                 ctypes.c_double, _P]
+_lib.phsvds_harvest_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                                ctypes.c_int, ctypes.POINTER(_Opts),
+                                                ctypes.POINTER(ctypes.c_size_t)]
+_lib.phsvds_harvest.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                ctypes.POINTER(_Opts), _P, ctypes.c_size_t, _P, _P, _P, _P,
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(_Stats)]
+
+
+def gnn_nweights(width: int = 32) -> int:
+    return int(_lib.phsvds_gnn_nweights(width))
+
+
+def gnn_pack(params: dict, device="cuda") -> torch.Tensor:
+    """Weights dict (row-major fin x w matrices) -> flat float32 device tensor."""
+    import numpy as np
+    flat = np.concatenate([np.asarray(params[k], dtype=np.float64).ravel() for k in GNN_NAMES])
+    return torch.tensor(flat, dtype=torch.float32, device=device)
+
+
+def gnn_unpack(flat: torch.Tensor, width: int = 32, nin: int = 4) -> dict:
+    import numpy as np
+    v = flat.detach().double().cpu().numpy()
+    w = width
+    shp = {"Ws1": (nin, w), "Wm1": (nin, w), "b1": (w,), "Ws2": (w, w), "Wm2": (w, w),
+           "b2": (w,), "Ws3": (w, w), "Wm3": (w, w), "b3": (w,), "wo": (w,)}
+    out, at = {}, 0
+    for k in GNN_NAMES:
+        size = int(np.prod(shp[k]))
+        out[k] = v[at:at + size].reshape(shp[k])
+        at += size
+    return out
+
+
+class GnnGraph:
+    """Prepared per-matrix data for the learned preconditioner."""
+
+    def __init__(self, A: DeviceCSR, width: int = 32):
+        self.A, self.width = A, width
+        self.c = A._c()
+        nbytes = int(_lib.phsvds_gnn_workspace_bytes(A.m, A.n, A.nnz, width))
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=A.rowptr.device)
+        _check(_lib.phsvds_gnn_prepare(ctypes.byref(self.c), width, self.ws.data_ptr(), nbytes,
+                                       _stream()), "gnn_prepare")
+
+    def forward(self, w, r, x, theta):
+        t = torch.empty(self.A.n, dtype=torch.float32, device=r.device)
+        _check(_lib.phsvds_gnn_forward(ctypes.byref(self.c), self.width, self.ws.data_ptr(),
+                                       self.ws.numel(), w.data_ptr(), r.data_ptr(), x.data_ptr(),
+                                       float(theta), t.data_ptr(), _stream()), "gnn_forward")
+        return t
+
+    def loss_grad(self, w, r, x, theta, tstar, grad, loss):
+        """Accumulates the sample's loss into loss (float64 [1]) and its
+        gradient into grad (float64 [nweights])."""
+        _check(_lib.phsvds_gnn_loss_grad(ctypes.byref(self.c), self.width, self.ws.data_ptr(),
+                                         self.ws.numel(), w.data_ptr(), r.data_ptr(),
+                                         x.data_ptr(), float(theta), tstar.data_ptr(),
+                                         grad.data_ptr(), loss.data_ptr(), _stream()),
+               "gnn_loss_grad")
+
+
+def gnn_adam(w, m, v, grad, step, lr=1e-3, grad_scale=1.0):
+    _check(_lib.phsvds_gnn_adam(w.data_ptr(), m.data_ptr(), v.data_ptr(), grad.data_ptr(),
+                                w.numel(), step, lr, grad_scale, _stream()), "gnn_adam")
+
+
+def harvest(A: DeviceCSR, k: int, block: int = 4, every: int = 5, max_pairs: int = 64,
+            tol: float = 1e-8, cg_tol: float = 1e-8, cg_maxit: int = 2000, **opt_kw):
+    """(R, X, T, theta) training pairs from a float64 stage-1 run (columns of
+    n x count float64 device tensors)."""
+    import numpy as np
+    opts = make_opts(block=block, **opt_kw)
+    nb = ctypes.c_size_t(0)
+    _check(_lib.phsvds_harvest_workspace_bytes(A.m, A.n, A.nnz, k, ctypes.byref(opts),
+                                               ctypes.byref(nb)), "harvest_workspace_bytes")
+    dev = A.rowptr.device
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+    R = torch.empty((max(max_pairs, 1), A.n), dtype=torch.float64, device=dev)
+    X = torch.empty_like(R)
+    T = torch.empty_like(R)
+    th = (ctypes.c_double * max(max_pairs, 1))()
+    cnt = ctypes.c_int(0)
+    st = _Stats()
+    c = A._c()
+    _check(_lib.phsvds_harvest(ctypes.byref(c), k, every, max_pairs, tol, cg_tol, cg_maxit,
+                               ctypes.byref(opts), ws.data_ptr(), ws.numel(), _stream(),
+                               R.data_ptr(), X.data_ptr(), T.data_ptr(), th, ctypes.byref(cnt),
+                               ctypes.byref(st)), "harvest")
+    n = cnt.value
+    return R[:n], X[:n], T[:n], np.array(th[:n]), st.as_dict(k)
+
+
+def train_gnn(graphs, pairs, w, epochs=20, lr=1e-3, batch=16, seed=0, log=None):
+    """Adam on the mean loss over mini-batches of harvested pairs.
+
+    graphs: list of GnnGraph; pairs: list of (graph index, r, x, theta, t*)
+    with float32 device vectors.  Returns the per-epoch mean losses."""
+    import numpy as np
+    nw = w.numel()
+    m = torch.zeros_like(w)
+    v = torch.zeros_like(w)
+    grad = torch.zeros(nw, dtype=torch.float64, device=w.device)
+    loss = torch.zeros(1, dtype=torch.float64, device=w.device)
+    rng = np.random.default_rng(seed)
+    step = 0
+    hist = []
+    for ep in range(epochs):
+        order = rng.permutation(len(pairs))
+        tot = 0.0
+        for b0 in range(0, len(order), batch):
+            idx = order[b0:b0 + batch]
+            grad.zero_()
+            loss.zero_()
+            for i in idx:
+                gi, r, x, th, ts = pairs[i]
+                graphs[gi].loss_grad(w, r, x, th, ts, grad, loss)
+            step += 1
+            gnn_adam(w, m, v, grad, step, lr, 1.0 / len(idx))
+            tot += float(loss.item())
+        hist.append(tot / len(pairs))
+        if log:
+            log(f"epoch {ep} mean loss {hist[-1]:.4f}")
+    return hist

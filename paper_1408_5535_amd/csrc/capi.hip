@@ -10,6 +10,8 @@
 #include <numeric>
 #include <string>
 
+#include "gnn.hpp"
+#include "harvest.hpp"
 #include "solver.hpp"
 
 namespace phs {
@@ -40,6 +42,8 @@ struct Dims {
   int64_t m, n, nnz;
   int k, b, bw, pmax, pmin;
   bool fp32, cont, jac;
+  int gw = 0;        // width of the learned preconditioner (0: not used)
+  bool cg = false;   // harvest buffers
 };
 
 int width_for(int b) {
@@ -62,6 +66,8 @@ bool make_dims(int64_t m, int64_t n, int64_t nnz, int k, const phsvds_opts &o, D
   d.fp32 = o.stage1_fp32 != 0;
   d.cont = d.fp32 && o.fp64_continue != 0;
   d.jac = false;
+  d.gw = o.gnn_width;
+  if (d.gw != 0 && d.gw != 8 && d.gw != 16 && d.gw != 32) return false;
   return d.pmax <= 64 && d.pmin >= d.b && d.pmin >= 1 && k >= 1 && k <= 24 && k < d.pmax;
 }
 
@@ -79,6 +85,7 @@ void take_stage1(Arena &ar, const Dims &d, Stage1Bufs<T> &b) {
   b.WTb = ar.take<T>(d.n * d.bw);
   b.Fb = ar.take<T>(d.n * d.bw);
   b.Yb = ar.take<T>(d.m * d.bw);
+  b.Gs = ar.take<T>(3 * d.n);
 }
 
 struct Plan {
@@ -99,6 +106,9 @@ struct Plan {
   TransBufs tb;
   Stage2Bufs s2;
   double *Vf, *Uf, *AV, *RU, *RV, *Fx, *Fy;
+  GnnGraph gg;
+  GnnBufs gb;
+  CgBufs cg;
 };
 
 void carve(Arena &ar, const Dims &d, Plan &p) {
@@ -147,6 +157,8 @@ void carve(Arena &ar, const Dims &d, Plan &p) {
   p.RV = ar.take<double>(m * d.k);
   p.Fx = ar.take<double>(std::max(n, m) * 8);
   p.Fy = ar.take<double>(std::max(n, m) * 8);
+  if (d.gw > 0) gnn_carve(ar, m, n, nnz, d.gw, p.gg, p.gb);
+  if (d.cg) carve_cg(ar, m, n, d.bw, p.cg);
 }
 
 // Y (rows_out x w, column-major) = op(A) X (column-major), in chunks of 8.
@@ -216,12 +228,21 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   PHS_REQUIRE(tol > 0, kEinval, "tol must be positive");
   PHS_REQUIRE(k <= n, kEinval, "k must not exceed n");
   int pkind = Pc ? Pc->kind : PHSVDS_PREC_NONE;
-  PHS_REQUIRE(pkind == PHSVDS_PREC_NONE || pkind == PHSVDS_PREC_JACOBI, kEinval,
-              "unsupported preconditioner kind");
+  PHS_REQUIRE(pkind == PHSVDS_PREC_NONE || pkind == PHSVDS_PREC_JACOBI ||
+                  pkind == PHSVDS_PREC_GNN,
+              kEinval, "unsupported preconditioner kind");
   Dims d;
   PHS_REQUIRE(make_dims(m, n, nnz, k, o, d), kEinval,
               "unsupported sizes: need 1 <= k <= 24, block <= 16, max_basis <= 64");
-  d.jac = pkind == PHSVDS_PREC_JACOBI;
+  d.jac = pkind == PHSVDS_PREC_JACOBI || pkind == PHSVDS_PREC_GNN;
+  if (pkind != PHSVDS_PREC_GNN) d.gw = 0;
+  if (pkind == PHSVDS_PREC_GNN) {
+    PHS_REQUIRE(Pc->gnn_weights && (Pc->gnn_width == 8 || Pc->gnn_width == 16 ||
+                                    Pc->gnn_width == 32),
+                kEinval, "GNN preconditioner needs weights and width 8, 16 or 32");
+    PHS_REQUIRE(o.gnn_width == Pc->gnn_width, kEinval,
+                "opts.gnn_width must equal the preconditioner's width (workspace sizing)");
+  }
   const bool largest = o.which == 1;
   Arena ar;
   ar.base = (char *)ws;
@@ -277,6 +298,7 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
     std::memcpy(At32.bins, At64.bins, sizeof(At64.bins));
   }
   if (d.jac) col_sq_norms(At64, pl.diagC, c.s);
+  if (d.gw && pkind == PHSVDS_PREC_GNN) gnn_prepare(*Ain, pl.gg, c.s);
   c.sync();
   const double t1 = wall();
   stl.t_setup = t1 - t0;
@@ -301,7 +323,19 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   Stage1Result r1;
   const double *Xl64 = nullptr, *Vr64 = nullptr;
   int nvr = 0;
+  auto gnn32 = [&](const void *r, const void *x, double th, void *t) {
+    gnn_forward(*Ain, pl.gg, pl.gb, Pc->gnn_weights, d.gw, (const float *)r, (const float *)x,
+                th, (float *)t, c.s);
+  };
+  auto gnn64 = [&](const void *r, const void *x, double th, void *t) {
+    copy(cm((double *)r, n, 1, n), cm(pl.gb.rf, n, 1, n), c.s);
+    copy(cm((double *)x, n, 1, n), cm(pl.gb.xf, n, 1, n), c.s);
+    gnn_forward(*Ain, pl.gg, pl.gb, Pc->gnn_weights, d.gw, pl.gb.rf, pl.gb.xf, th, pl.gb.tout,
+                c.s);
+    copy(cm(pl.gb.tout, n, 1, n), cm((double *)t, n, 1, n), c.s);
+  };
   if (d.fp32) {
+    if (d.gw && pkind == PHSVDS_PREC_GNN) P1.gnn = gnn32;
     r1 = run_stage1<float>(c, A32, At32, P1, pl.s32, sp);
     stl.fp32_locked = r1.nl;
     stl.iters1 += r1.iters;
@@ -314,6 +348,7 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
       if (extra)
         copy(cm((float *)r1.Vrest, n, extra, n), cm(init + (int64_t)r1.nl * n, n, extra, n), c.s);
       Stage1Params P2 = P1;
+      if (d.gw && pkind == PHSVDS_PREC_GNN) P2.gnn = gnn64;
       P2.init64 = init;
       P2.init_cols = r1.nl + extra;
       P2.sn2_init = r1.sn2;
@@ -331,6 +366,7 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
       nvr = r1.p;
     }
   } else {
+    if (d.gw && pkind == PHSVDS_PREC_GNN) P1.gnn = gnn64;
     r1 = run_stage1<double>(c, A64, At64, P1, pl.s64, sp);
     Xl64 = pl.s64.Xl;
     Vr64 = (const double *)r1.Vrest;
@@ -338,6 +374,9 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   }
   stl.iters1 += d.fp32 && !d.cont ? 0 : r1.iters;
   stl.restarts1 += d.fp32 && !d.cont ? 0 : r1.restarts;
+  stl.fallbacks += r1.fallbacks;
+  stl.refreshes += r1.refreshes;
+  stl.rollbacks += r1.rollbacks;
   c.sync();
   const double t2 = wall();
   stl.t_stage1 = t2 - t1;
@@ -397,7 +436,7 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
     P2.u0 = pl.tb.Ut;
     P2.max_restarts = P1.max_restarts;
     P2.max_iters = 0;
-    P2.jacobi_d = d.jac ? pl.diagC : nullptr;
+    P2.jacobi_d = pkind == PHSVDS_PREC_JACOBI ? pl.diagC : nullptr;
     Stage2Result r2 = run_stage2(c, A64, At64, P2, pl.s2, sp);
     stl.iters2 = r2.iters;
     stl.restarts2 = r2.restarts;
@@ -512,6 +551,81 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   return ok ? PHSVDS_OK : PHSVDS_NOT_CONVERGED;
 }
 
+
+int harvest_impl(const phsvds_csr *Ain, int k, int every, int max_pairs, double tol,
+                 double cg_tol, int cg_maxit, const phsvds_opts *oin, void *ws, size_t ws_bytes,
+                 void *stream, double *Rout, double *Xout, double *Tout, double *theta_out,
+                 int *count_out, phsvds_stats *stats) {
+  PHS_REQUIRE(Ain && Rout && Xout && Tout && theta_out && count_out, kEinval, "null argument");
+  phsvds_opts o;
+  phsvds_default_opts(&o);
+  if (oin) o = *oin;
+  o.stage1_fp32 = 0;
+  const int64_t m = Ain->m, n = Ain->n, nnz = Ain->nnz;
+  PHS_REQUIRE(m >= n && n >= 1 && every >= 1 && max_pairs >= 0, kEinval, "bad harvest sizes");
+  Dims d;
+  PHS_REQUIRE(make_dims(m, n, nnz, k, o, d), kEinval, "unsupported sizes");
+  d.cg = true;
+  Arena ar;
+  ar.base = (char *)ws;
+  ar.size = ws_bytes;
+  Plan pl{};
+  carve(ar, d, pl);
+  phsvds_stats stl;
+  std::memset(&stl, 0, sizeof(stl));
+  Ctx c;
+  c.s = (hipStream_t)stream;
+  c.sc = pl.sc;
+  c.didx = pl.didx;
+  c.seed = o.seed;
+  c.st = &stl;
+  SmallPool sp;
+  sp.base = pl.pool;
+  {
+    std::vector<double> eye((size_t)kSP * kSP, 0.0);
+    for (int i = 0; i < kSP; ++i) eye[i + (size_t)i * kSP] = 1.0;
+    c.h2d(sp.eye(), eye.data(), eye.size() * sizeof(double));
+  }
+  SpMat<double> A64, At64;
+  A64.m = m; A64.n = n; A64.nnz = nnz;
+  A64.rowptr = Ain->rowptr; A64.colind = Ain->colind; A64.val = Ain->val;
+  csr_transpose(m, n, nnz, Ain->rowptr, Ain->colind, Ain->val, pl.trp, pl.tci, pl.tva, pl.tws,
+                pl.tws_bytes, c.s);
+  At64.m = n; At64.n = m; At64.nnz = nnz;
+  At64.rowptr = pl.trp; At64.colind = pl.tci; At64.val = pl.tva;
+  Stage1Params P1{};
+  P1.k = k; P1.b = d.b; P1.bw = d.bw; P1.pmax = d.pmax; P1.pmin = d.pmin;
+  P1.largest = false; P1.tol = tol; P1.floor = 10.0; P1.anorm = o.anorm;
+  P1.max_restarts = o.max_restarts > 0 ? o.max_restarts : 10000;
+  P1.init64 = o.init_block; P1.init_cols = d.b;
+  int count = 0;
+  P1.snap = [&](int64_t it, const void *Xb, const void *Rb, const double *th, int nb,
+                const void *Xl, int nl) {
+    if (it % every || count >= max_pairs) return;
+    std::vector<int> ok = projected_cg_block(c, A64, At64, (const double *)Xl, nl,
+                                             (const double *)Xb, nb, d.bw, th, (const double *)Rb,
+                                             cg_tol, cg_maxit, pl.cg, sp);
+    for (int j = 0; j < nb && count < max_pairs; ++j) {
+      if (!ok[j]) continue;
+      Tall<double> src;
+      src.rows = n; src.cols = 1; src.rs = d.bw; src.cs = 1;
+      src.p = const_cast<double *>((const double *)Rb) + j;
+      copy(src, cm(Rout + (int64_t)count * n, n, 1, n), c.s);
+      src.p = const_cast<double *>((const double *)Xb) + j;
+      copy(src, cm(Xout + (int64_t)count * n, n, 1, n), c.s);
+      src.p = pl.cg.T + j;
+      copy(src, cm(Tout + (int64_t)count * n, n, 1, n), c.s);
+      theta_out[count] = th[j];
+      ++count;
+    }
+  };
+  run_stage1<double>(c, A64, At64, P1, pl.s64, sp);
+  c.sync();
+  *count_out = count;
+  if (stats) *stats = stl;
+  return PHSVDS_OK;
+}
+
 }  // namespace
 }  // namespace phs
 
@@ -548,6 +662,16 @@ int phsvds_spmm_f64(const phsvds_csr *A, int b, const double *X, double *Y, int 
     S.colind = A->colind;
     S.val = A->val;
     spmm(S, b, X, Y, absval != 0, (hipStream_t)stream);
+    return PHSVDS_OK;
+  });
+}
+
+int phsvds_rr_eig(const double *H, int ldh, int p, int nvec, int largest, double *theta,
+                  double *S, int lds, void *stream) {
+  return guarded([&]() {
+    PHS_REQUIRE(H && theta && S, kEinval, "null argument");
+    PHS_REQUIRE(ldh >= p && lds >= p, kEinval, "leading dimension below p");
+    syev_rr(H, ldh, p, nvec, largest != 0, theta, S, lds, (hipStream_t)stream);
     return PHSVDS_OK;
   });
 }
@@ -600,6 +724,102 @@ int phsvds_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int k, const phsvd
     Plan pl{};
     carve(ar, d, pl);
     *bytes = ar.used;
+    return PHSVDS_OK;
+  });
+}
+
+int phsvds_harvest_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int k,
+                                   const phsvds_opts *oin, size_t *bytes) {
+  return guarded([&]() {
+    PHS_REQUIRE(bytes, kEinval, "null argument");
+    phsvds_opts o;
+    phsvds_default_opts(&o);
+    if (oin) o = *oin;
+    o.stage1_fp32 = 0;
+    Dims d;
+    PHS_REQUIRE(m >= n && n >= 1 && make_dims(m, n, nnz, k, o, d), kEinval, "unsupported sizes");
+    d.cg = true;
+    Arena ar;
+    ar.dry = true;
+    Plan pl{};
+    carve(ar, d, pl);
+    *bytes = ar.used;
+    return PHSVDS_OK;
+  });
+}
+
+int phsvds_harvest(const phsvds_csr *A, int k, int every, int max_pairs, double tol,
+                   double cg_tol, int cg_maxit, const phsvds_opts *opts, void *workspace,
+                   size_t ws_bytes, void *stream, double *R, double *X, double *T, double *theta,
+                   int *count, phsvds_stats *stats) {
+  return guarded([&]() {
+    return harvest_impl(A, k, every, max_pairs, tol, cg_tol, cg_maxit, opts, workspace, ws_bytes,
+                        stream, R, X, T, theta, count, stats);
+  });
+}
+
+int64_t phsvds_gnn_nweights(int width) { return gnn_nweights(width); }
+
+size_t phsvds_gnn_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int width) {
+  Arena ar;
+  ar.dry = true;
+  GnnGraph g;
+  GnnBufs b;
+  gnn_carve(ar, m, n, nnz, width, g, b);
+  return ar.used;
+}
+
+static void gnn_views(const phsvds_csr *A, int width, void *gws, size_t bytes, GnnGraph &g,
+                      GnnBufs &b) {
+  PHS_REQUIRE(A && gws, kEinval, "null argument");
+  PHS_REQUIRE(width == 8 || width == 16 || width == 32, kEinval, "width must be 8, 16 or 32");
+  Arena ar;
+  ar.base = (char *)gws;
+  ar.size = bytes;
+  gnn_carve(ar, A->m, A->n, A->nnz, width, g, b);
+}
+
+int phsvds_gnn_prepare(const phsvds_csr *A, int width, void *gws, size_t bytes, void *stream) {
+  return guarded([&]() {
+    GnnGraph g;
+    GnnBufs b;
+    gnn_views(A, width, gws, bytes, g, b);
+    gnn_prepare(*A, g, (hipStream_t)stream);
+    return PHSVDS_OK;
+  });
+}
+
+int phsvds_gnn_forward(const phsvds_csr *A, int width, void *gws, size_t bytes, const float *w,
+                       const float *r, const float *x, double theta, float *t, void *stream) {
+  return guarded([&]() {
+    GnnGraph g;
+    GnnBufs b;
+    gnn_views(A, width, gws, bytes, g, b);
+    PHS_REQUIRE(w && r && x && t, kEinval, "null argument");
+    gnn_forward(*A, g, b, w, width, r, x, theta, t, (hipStream_t)stream);
+    return PHSVDS_OK;
+  });
+}
+
+int phsvds_gnn_loss_grad(const phsvds_csr *A, int width, void *gws, size_t bytes, const float *w,
+                         const float *r, const float *x, double theta, const float *tstar,
+                         double *grad, double *loss, void *stream) {
+  return guarded([&]() {
+    GnnGraph g;
+    GnnBufs b;
+    gnn_views(A, width, gws, bytes, g, b);
+    PHS_REQUIRE(w && r && x && tstar && grad && loss, kEinval, "null argument");
+    gnn_loss_grad(*A, g, b, w, width, r, x, theta, tstar, b.tout, grad, loss,
+                  (hipStream_t)stream);
+    return PHSVDS_OK;
+  });
+}
+
+int phsvds_gnn_adam(float *w, float *m, float *v, const double *grad, int64_t nw, int step,
+                    double lr, double grad_scale, void *stream) {
+  return guarded([&]() {
+    PHS_REQUIRE(w && m && v && grad && nw > 0 && step >= 1, kEinval, "bad Adam arguments");
+    gnn_adam(w, m, v, grad, nw, step, lr, grad_scale, (hipStream_t)stream);
     return PHSVDS_OK;
   });
 }

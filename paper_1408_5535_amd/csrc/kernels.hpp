@@ -115,11 +115,12 @@ template <typename T>
 void row_scale(const T *X, const double *w, int64_t n, int b, bool inv, T *Y, hipStream_t s);
 
 // -------------------------------------------------- small dense (float64)
-// Symmetric eigendecomposition by cyclic Jacobi (one workgroup):
-// H (p x p, ld ldh) -> theta (p), S (p x p, ld lds); ascending, or
-// descending if `descending`.  H is not modified.
-void syevj(const double *H, int ldh, int p, bool descending, double *theta, double *S, int lds,
-           hipStream_t s);
+// Selected eigenpairs of the symmetric H (p x p, ld ldh, p <= 64; one
+// workgroup): the nvec at the wanted end (ascending, or descending if
+// `descending`) in theta[0..nvec), S(:, 0..nvec) (ld lds), and the
+// eigenvalue at the other end in theta[p-1].  H is not modified.
+void syev_rr(const double *H, int ldh, int p, int nvec, bool descending, double *theta,
+             double *S, int lds, hipStream_t s);
 // One-sided Jacobi SVD of M (rows x cols, ld ldm, rows >= cols): singular
 // values ascending in sv, right vectors in Y (cols x cols, ld ldy).
 void svdj(const double *M, int ldm, int rows, int cols, double *sv, double *Y, int ldy,
@@ -131,8 +132,9 @@ void chol_inv(const double *G, int ldg, int w, double shift, double *R, double *
 // C = alpha op(A) op(B) + beta C, all small float64.
 void small_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const double *A, int lda,
                 const double *B, int ldb, double beta, double *C, int ldc, hipStream_t s);
-// Y = [K | orth(P against K)] (rows x (kc + kept)); dependent columns of P
-// are dropped; count[0] = kc + kept.
+// Y = [K | orth(P against K)] (rows x min(kc + pc, rows)); a dependent
+// column of P is replaced by an independent coordinate vector, so
+// count[0] = min(kc + pc, rows) always.
 void restart_basis(const double *K, int ldk, int rows, int kc, const double *P, int ldp, int pc,
                    double *Y, int ldy, int *count, hipStream_t s);
 // Thin QR by two-pass modified Gram-Schmidt: M (rows x cols) = Q R.

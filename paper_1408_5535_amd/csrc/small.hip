@@ -49,102 +49,299 @@ __device__ inline void rr_pair(int P, int r, int k, int &a, int &b) {
   }
 }
 
-// ---------------------------------------------------------- syevj
-__global__ __launch_bounds__(256) void k_syevj(const double *H, int ldh, int p, int P,
-                                               bool desc, double *theta, double *Sout,
-                                               int lds) {
-  __shared__ double a[kSmallMax * kLd];
-  __shared__ double v[kSmallMax * kLd];
-  __shared__ double cs[kSmallMax / 2][2];
-  __shared__ int pr[kSmallMax / 2][2];
-  __shared__ int nrot;
-  const int t = threadIdx.x;
-  for (int idx = t; idx < P * P; idx += blockDim.x) {
-    int i = idx % P, j = idx / P;
-    a[i * kLd + j] = (i < p && j < p) ? 0.5 * (H[i + (int64_t)j * ldh] + H[j + (int64_t)i * ldh])
-                                      : 0.0;
-    v[i * kLd + j] = (i == j) ? 1.0 : 0.0;
+// ---------------------------------------------------------- syev
+// Rayleigh-Ritz eigenproblem H s = theta s of the search space (p <= 64),
+// float64, one workgroup of four wavefronts:
+//  1. Householder reduction H = Q T Q^T to tridiagonal T; the reflectors
+//     stay in the rows of H they annihilate.
+//  2. Selected eigenvalues of T by multisection of Sturm sequences: the
+//     eigenvalue of rank r is bracketed by the L lanes of one group, which
+//     evaluate the count at L interior points per step and keep the
+//     subinterval their ballot selects.
+//  3. Eigenvectors of T by inverse iteration (one lane per vector), with
+//     Gram-Schmidt inside clusters of close eigenvalues after every sweep.
+//  4. s = Q y by applying the reflectors to y (one lane group per vector,
+//     the vector held in registers).
+// Outputs: theta[0..nvec) and S(:, 0..nvec) for the nvec eigenpairs at the
+// wanted end (ascending, or descending if `desc`), and theta[p-1], the
+// eigenvalue at the other end.  Other entries are not written.
+constexpr int kEigThreads = 256;
+constexpr int kEigRegs = 16;  // rows per lane in step 4 (64 rows / 4 lanes)
+
+__device__ inline double wred(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(kEigThreads) void k_syev(const double *H, int ldh, int p, int nvec,
+                                                      bool desc, double *theta, double *Sout,
+                                                      int lds) {
+  __shared__ double a[kSmallMax * kLd];   // H, then the reflectors
+  __shared__ double y[kSmallMax * kLd];   // eigenvectors of T, column per vector
+  __shared__ double uu[kSmallMax * kLd];  // 1 / pivots of T - lambda I
+  __shared__ double ll[kSmallMax * kLd];  // multipliers of T - lambda I
+  __shared__ double pp[4 * kSmallMax];
+  __shared__ double vv[kSmallMax], pq[kSmallMax], hh[kSmallMax];
+  __shared__ double d[kSmallMax], e[kSmallMax], ds[kSmallMax], e2s[kSmallMax];
+  __shared__ double lamv[kSmallMax + 1];
+  __shared__ int cstart[kSmallMax];
+  const int tid = threadIdx.x;
+  const int t = tid & 63, q = tid >> 6;
+  const int n = p;
+  const double eps = 2.220446049250313e-16;
+  for (int r = q; r < n; r += 4)
+    if (t < n) a[r * kLd + t] = 0.5 * (H[r + (int64_t)t * ldh] + H[t + (int64_t)r * ldh]);
+  if (tid < kSmallMax) hh[tid] = 0.0;
+  __syncthreads();
+  // 1. reduction, last row first; every wave computes the reductions of the
+  //    current row itself (identical values), partial products go via LDS
+  for (int i = n - 1; i >= 1; --i) {
+    const int l = i - 1;
+    const double xi = (t <= l) ? a[i * kLd + t] : 0.0;
+    if (l == 0) {
+      if (tid == 0) e[1] = xi;
+      break;
+    }
+    const double scale = wred(fabs(xi));
+    if (scale == 0.0) {
+      if (tid == 0) e[i] = 0.0;
+      continue;  // uniform: every wave saw the same row
+    }
+    const double xs = xi / scale;
+    const double sigma = wred(xs * xs);
+    const double f = a[i * kLd + l] / scale;
+    const double g = f >= 0 ? -sqrt(sigma) : sqrt(sigma);
+    const double h = sigma - f * g;
+    const double v = (t == l) ? f - g : xs;  // reflector I - v v^T / h
+    if (q == 0 && t <= l) vv[t] = v;
+    if (tid == 0) {
+      e[i] = scale * g;
+      hh[i] = h;
+    }
+    __syncthreads();
+    {
+      double part = 0.0;
+      if (t <= l)
+        for (int k = q; k <= l; k += 4) part = fma(a[t * kLd + k], vv[k], part);
+      pp[q * kSmallMax + t] = part;
+    }
+    __syncthreads();
+    double pj = 0.0;
+    if (t <= l)
+      pj = (pp[t] + pp[kSmallMax + t] + pp[2 * kSmallMax + t] + pp[3 * kSmallMax + t]) / h;
+    const double K = wred(t <= l ? v * pj : 0.0) / (2.0 * h);
+    const double qj = pj - K * v;
+    if (q == 0 && t <= l) pq[t] = qj;
+    __syncthreads();
+    if (t <= l) {
+      for (int c = q; c <= l; c += 4) a[t * kLd + c] -= v * pq[c] + qj * vv[c];
+      if (q == 0) a[i * kLd + t] = v;
+    }
+    __syncthreads();
+  }
+  if (tid < n) d[tid] = a[tid * kLd + tid];
+  if (tid == 0) e[0] = 0.0;
+  __syncthreads();
+  // T scaled to unit norm (Gershgorin bound)
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? fabs(e[i]) : 0.0) + (i + 1 < n ? fabs(e[i + 1]) : 0.0);
+    lo = fmin(lo, d[i] - r);
+    hi = fmax(hi, d[i] + r);
+  }
+  double tnorm = fmax(fabs(lo), fabs(hi));
+  if (!(tnorm > 0.0)) tnorm = 1.0;
+  const double sc = 1.0 / tnorm;
+  if (tid < n) {
+    ds[tid] = d[tid] * sc;
+    const double es = e[tid] * sc;
+    e2s[tid] = tid > 0 ? es * es : 0.0;
   }
   __syncthreads();
-  const int half = P / 2;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    if (t == 0) nrot = 0;
-    __syncthreads();
-    for (int r = 0; r < P - 1; ++r) {
-      if (t < half) {
-        int i, j;
-        rr_pair(P, r, t, i, j);
-        pr[t][0] = i;
-        pr[t][1] = j;
-        double aij = a[i * kLd + j], aii = a[i * kLd + i], ajj = a[j * kLd + j];
-        double c = 1.0, s = 0.0;
-        if (aij != 0.0 && fabs(aij) > 1e-300 &&
-            fabs(aij) > 2.220446049250313e-16 * sqrt(fabs(aii) * fabs(ajj))) {
-          double tau = (ajj - aii) / (2.0 * aij);
-          double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          s = tt * c;
-          atomicAdd(&nrot, 1);
-        }
-        cs[t][0] = c;
-        cs[t][1] = s;
+  // 2. multisection.  Slots 0..nvec-1: ranks 0..nvec-1; slot nvec (if
+  //    nvec < n): rank n-1.  Rank r is ascending index r, or n-1-r if desc.
+  //    Count(x) = number of sign changes of the leading principal minors
+  //    p_i = (d_i - x) p_{i-1} - e_i^2 p_{i-2}, the pair rescaled by a power
+  //    of two at every step; an exact zero counts as a sign change.
+  const int ne = nvec < n ? nvec + 1 : n;
+  int L = 64;
+  while (L * ne > kEigThreads) L >>= 1;
+  {
+    const int slot = tid / L, sub = tid % L;
+    const bool act = slot < ne;
+    const int rank = act ? (slot < nvec ? slot : n - 1) : 0;
+    const int jidx = desc ? n - 1 - rank : rank;
+    double a0 = lo * sc - eps, b0 = hi * sc + eps;
+    // width 2 + 2 eps down to below 1e-2 eps: a factor 2^59.7
+    const int nst = (int)ceil(59.8 / log2((double)(L + 1))) + 1;
+    const int base = (tid & 63) - sub;
+    const unsigned long long gmask = (L == 64) ? ~0ull : ((1ull << L) - 1ull);
+    for (int it = 0; it < nst; ++it) {
+      const double w = (b0 - a0) / (double)(L + 1);
+      const double x = a0 + (double)(sub + 1) * w;
+      int cnt = 0;
+      double pm = 1.0, pc = ds[0] - x;
+      cnt += pc <= 0.0;
+      if (pc == 0.0) pc = -1e-290;
+      for (int i = 1; i < n; ++i) {
+        double pn = fma(ds[i] - x, pc, -e2s[i] * pm);
+        if (pn == 0.0) pn = pc < 0.0 ? 1e-290 : -1e-290;
+        cnt += (pn < 0.0) != (pc < 0.0);
+        int ex;
+        frexp(fmax(fabs(pn), fabs(pc)), &ex);
+        pm = ldexp(pc, -ex);
+        pc = ldexp(pn, -ex);
       }
-      __syncthreads();
-      // rows: A <- J^T A
-      for (int idx = t; idx < half * P; idx += blockDim.x) {
-        int k = idx / P, col = idx % P;
-        double c = cs[k][0], s = cs[k][1];
-        if (s == 0.0) continue;
-        int i = pr[k][0], j = pr[k][1];
-        double ai = a[i * kLd + col], aj = a[j * kLd + col];
-        a[i * kLd + col] = c * ai - s * aj;
-        a[j * kLd + col] = s * ai + c * aj;
-      }
-      __syncthreads();
-      // columns: A <- A J, V <- V J
-      for (int idx = t; idx < half * P; idx += blockDim.x) {
-        int k = idx / P, row = idx % P;
-        double c = cs[k][0], s = cs[k][1];
-        if (s == 0.0) continue;
-        int i = pr[k][0], j = pr[k][1];
-        double ai = a[row * kLd + i], aj = a[row * kLd + j];
-        a[row * kLd + i] = c * ai - s * aj;
-        a[row * kLd + j] = s * ai + c * aj;
-        double vi = v[row * kLd + i], vj = v[row * kLd + j];
-        v[row * kLd + i] = c * vi - s * vj;
-        v[row * kLd + j] = s * vi + c * vj;
-      }
-      __syncthreads();
-      if (t < half && cs[t][1] != 0.0) {
-        int i = pr[t][0], j = pr[t][1];
-        a[i * kLd + j] = 0.0;
-        a[j * kLd + i] = 0.0;
-      }
-      __syncthreads();
+      // first point of the group whose count exceeds the rank: the
+      // eigenvalue lies between it and the point before (counts are
+      // monotone in x up to rounding near the eigenvalues themselves)
+      const unsigned long long m = (__ballot(act && cnt > jidx) >> base) & gmask;
+      const int j = m ? __ffsll((long long)m) - 1 : L;
+      const double na = j > 0 ? a0 + (double)j * w : a0;
+      const double nb = j < L ? a0 + (double)(j + 1) * w : b0;
+      a0 = na;
+      b0 = fmax(nb, na);
     }
-    if (nrot == 0) break;
-    __syncthreads();
+    if (act && sub == 0) lamv[slot] = 0.5 * (a0 + b0);
   }
-  // sort: rank of each diagonal entry (ties by index)
-  for (int i = t; i < p; i += blockDim.x) {
-    double di = a[i * kLd + i];
-    int rank = 0;
-    for (int j = 0; j < p; ++j) {
-      double dj = a[j * kLd + j];
-      bool before = desc ? (dj > di || (dj == di && j < i)) : (dj < di || (dj == di && j < i));
-      rank += before;
+  __syncthreads();
+  // 3. inverse iteration on (T - lambda I)/||T|| = L U without pivoting
+  //    (tiny pivots replaced), three sweeps; after every sweep each vector
+  //    in a cluster (eigenvalues within 1e-3 ||T|| of the previous one) is
+  //    orthogonalised against the earlier members by classical Gram-Schmidt
+  //    (wave 0 lanes split the dot products, then the rows), repeated when
+  //    the first pass cancels more than half.  Orthogonalising between
+  //    sweeps keeps vectors of (nearly) equal eigenvalues from converging to
+  //    one direction.
+  if (tid < nvec) {
+    const int c = tid;
+    const double lam = lamv[c];
+    const double tiny = 1e-3 * eps;
+    double u = ds[0] - lam;
+    if (fabs(u) < tiny) u = tiny;
+    uu[c] = 1.0 / u;
+    for (int i = 1; i < n; ++i) {
+      const double li = e[i] * sc / u;
+      ll[i * kLd + c] = li;
+      u = ds[i] - lam - li * (e[i] * sc);
+      if (fabs(u) < tiny) u = tiny;
+      uu[i * kLd + c] = 1.0 / u;
     }
-    theta[rank] = di;
-    for (int row = 0; row < p; ++row) Sout[row + (int64_t)rank * lds] = v[row * kLd + i];
+    for (int i = 0; i < n; ++i) {
+      uint32_t hsh = (uint32_t)(i * kSmallMax + c + 1) * 0x9E3779B9u;
+      hsh ^= hsh >> 16; hsh *= 0x85EBCA6Bu; hsh ^= hsh >> 13; hsh *= 0xC2B2AE35u; hsh ^= hsh >> 16;
+      y[i * kLd + c] = (double)(hsh >> 8) * (2.0 / 16777216.0) - 1.0;
+    }
+    int st = c;
+    while (st > 0 && fabs(lamv[st] - lamv[st - 1]) <= 1e-3) --st;
+    cstart[c] = st;
+  }
+  for (int sweep = 0; sweep < 3; ++sweep) {
+    if (tid < nvec) {
+      const int c = tid;
+      double w = y[c];
+      for (int i = 1; i < n; ++i) {
+        w = y[i * kLd + c] - ll[i * kLd + c] * w;
+        if (fabs(w) > 1e150) {  // rescale the whole system (rare)
+          for (int j2 = 0; j2 < n; ++j2) y[j2 * kLd + c] *= 1e-150;
+          w *= 1e-150;
+        }
+        y[i * kLd + c] = w;
+      }
+      double x = y[(n - 1) * kLd + c] * uu[(n - 1) * kLd + c];
+      y[(n - 1) * kLd + c] = x;
+      for (int i = n - 2; i >= 0; --i) {
+        x = (y[i * kLd + c] - e[i + 1] * sc * x) * uu[i * kLd + c];
+        if (fabs(x) > 1e150) {
+          for (int j2 = 0; j2 < n; ++j2) y[j2 * kLd + c] *= 1e-150;
+          x *= 1e-150;
+        }
+        y[i * kLd + c] = x;
+      }
+      double mx = 0.0;
+      for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(y[i * kLd + c]));
+      const double inv = mx > 0 ? 1.0 / mx : 1.0;
+      double s2 = 0.0;
+      for (int i = 0; i < n; ++i) {
+        const double v = y[i * kLd + c] * inv;
+        y[i * kLd + c] = v;
+        s2 += v * v;
+      }
+      const double in2 = 1.0 / sqrt(s2);
+      for (int i = 0; i < n; ++i) y[i * kLd + c] *= in2;
+    }
+    __syncthreads();
+    for (int c = 1; c < nvec; ++c) {
+      const int st = cstart[c];
+      if (st == c) continue;
+      for (int pass = 0; pass < 2; ++pass) {
+        if (q == 0 && t >= st && t < c) {
+          double dt = 0.0;
+          for (int i = 0; i < n; ++i) dt = fma(y[i * kLd + t], y[i * kLd + c], dt);
+          pq[t] = dt;
+        }
+        __syncthreads();
+        double yi = 0.0;
+        if (t < n) {
+          yi = y[t * kLd + c];
+          for (int k = st; k < c; ++k) yi = fma(-pq[k], y[t * kLd + k], yi);
+        }
+        const double nrm = sqrt(wred(yi * yi));
+        __syncthreads();
+        if (q == 0 && t < n) y[t * kLd + c] = yi / nrm;
+        __syncthreads();
+        if (nrm > 0.5) break;
+      }
+    }
+  }
+  // 4. s = P_{n-1} ... P_2 y: lane group of G lanes per vector, rows
+  //    sub, sub + G, ... of the vector in registers
+  {
+    int G = 64;
+    while (G * nvec > kEigThreads) G >>= 1;
+    const int c = tid / G, sub = tid % G;
+    const bool act = c < nvec;
+    double yr[kEigRegs];
+#pragma unroll
+    for (int r = 0; r < kEigRegs; ++r) {
+      const int k = sub + r * G;
+      yr[r] = (act && k < n) ? y[k * kLd + c] : 0.0;
+    }
+    for (int i = 2; i < n; ++i) {
+      const double h = hh[i];
+      if (h == 0.0) continue;
+      double dt = 0.0;
+#pragma unroll
+      for (int r = 0; r < kEigRegs; ++r) {
+        const int k = sub + r * G;
+        if (k < i) dt = fma(a[i * kLd + k], yr[r], dt);
+      }
+      for (int off = G >> 1; off > 0; off >>= 1) dt += __shfl_xor(dt, off, 64);
+      const double sc2 = dt / h;
+#pragma unroll
+      for (int r = 0; r < kEigRegs; ++r) {
+        const int k = sub + r * G;
+        if (k < i) yr[r] = fma(-sc2, a[i * kLd + k], yr[r]);
+      }
+    }
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < kEigRegs; ++r) {
+        const int k = sub + r * G;
+        if (k < n) Sout[k + (int64_t)c * lds] = yr[r];
+      }
+      if (sub == 0) theta[c] = lamv[c] * tnorm;
+    }
+    if (tid == 0 && nvec < n) theta[n - 1] = lamv[nvec] * tnorm;
   }
 }
 
-void syevj(const double *H, int ldh, int p, bool descending, double *theta, double *S, int lds,
-           hipStream_t s) {
-  PHS_REQUIRE(p >= 1 && p <= kSmallMax, kEinval, "syevj: size out of range");
-  int P = p + (p & 1);
-  if (P < 2) P = 2;
-  k_syevj<<<1, 256, 0, s>>>(H, ldh, p, P, descending, theta, S, lds);
+void syev_rr(const double *H, int ldh, int p, int nvec, bool descending, double *theta,
+             double *S, int lds, hipStream_t s) {
+  PHS_REQUIRE(p >= 1 && p <= kSmallMax && nvec >= 1 && nvec <= p, kEinval,
+              "syev: size out of range");
+  k_syev<<<1, kEigThreads, 0, s>>>(H, ldh, p, nvec, descending, theta, S, lds);
   PHS_CHECK_LAUNCH();
 }
 
@@ -340,103 +537,114 @@ void small_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const doubl
 }
 
 // ------------------------------------------ MGS2 helpers (restart, QR)
-// Orthogonalise column `c` of q (rows x *, ld kSvdRows in LDS) against
-// columns [0, upto) twice; returns the norms before and after.
-__device__ inline void mgs2_col(double *q, int rows, int c, int upto, double *red, double *rcoef,
-                                double &n0, double &n2) {
-  const int t = threadIdx.x;
-  double s = 0.0;
-  for (int k = t; k < rows; k += blockDim.x) s += q[c * kSvdRows + k] * q[c * kSvdRows + k];
-  n0 = sqrt(block_sum(s, red));
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int j = 0; j < upto; ++j) {
-      double d = 0.0;
-      for (int k = t; k < rows; k += blockDim.x) d += q[j * kSvdRows + k] * q[c * kSvdRows + k];
-      d = block_sum(d, red);
-      for (int k = t; k < rows; k += blockDim.x) q[c * kSvdRows + k] -= d * q[j * kSvdRows + k];
-      if (rcoef && t == 0) rcoef[j] += d;
-      __syncthreads();
-    }
-  }
-  s = 0.0;
-  for (int k = t; k < rows; k += blockDim.x) s += q[c * kSvdRows + k] * q[c * kSvdRows + k];
-  n2 = sqrt(block_sum(s, red));
+// Single-wavefront Gram-Schmidt helpers for small coefficient spaces
+// (rows <= 64): lane r owns row r of every column, dot products are wave
+// reductions, so no workgroup barriers are needed.
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
 
-__global__ __launch_bounds__(256) void k_restart_basis(const double *K, int ldk, int rows,
-                                                       int kc, const double *P, int ldp, int pc,
-                                                       double *Y, int ldy, int *count) {
-  __shared__ double q[kSmallMax * kSvdRows];
-  __shared__ double red[256];
-  const int t = threadIdx.x;
-  for (int idx = t; idx < rows * kc; idx += blockDim.x) {
-    int i = idx % rows, j = idx / rows;
-    q[j * kSvdRows + i] = K[i + (int64_t)j * ldk];
-  }
-  __syncthreads();
-  int cur = kc;
-  for (int c = 0; c < pc && cur < kSmallMax; ++c) {
-    for (int k = t; k < rows; k += blockDim.x) q[cur * kSvdRows + k] = P[k + (int64_t)c * ldp];
+// Orthogonalise column c of q (ld kSmallMax, lane r owns row r for the
+// update) against columns [0, c), twice.  The c dot products of a pass are
+// computed in parallel (lane j forms q_j^T x from LDS), then every lane
+// updates its row; coefficients accumulate into rc if given.
+__device__ inline void wave_cgs2(double *q, int rows, int c, double *xs, double *dots, double *rc,
+                                 double &n0, double &n2) {
+  const int r = threadIdx.x;
+  double x = (r < rows) ? q[c * kSmallMax + r] : 0.0;
+  n0 = sqrt(wsum(x * x));
+  for (int pass = 0; pass < 2; ++pass) {
+    xs[r] = x;
     __syncthreads();
-    double n0, n2;
-    mgs2_col(q, rows, cur, cur, red, nullptr, n0, n2);
-    if (n0 > 0.0 && n2 > 1e-8 * n0) {
-      for (int k = t; k < rows; k += blockDim.x) q[cur * kSvdRows + k] /= n2;
-      ++cur;
+    if (r < c) {
+      double d = 0.0;
+      for (int k = 0; k < rows; ++k) d = fma(q[r * kSmallMax + k], xs[k], d);
+      dots[r] = d;
+      if (rc) rc[r] += d;
     }
     __syncthreads();
+    double acc = x;
+    for (int j = 0; j < c; ++j) acc = fma(-dots[j], q[j * kSmallMax + r], acc);
+    x = (r < rows) ? acc : 0.0;
   }
-  for (int idx = t; idx < rows * cur; idx += blockDim.x) {
-    int i = idx % rows, j = idx / rows;
-    Y[i + (int64_t)j * ldy] = q[j * kSvdRows + i];
+  q[c * kSmallMax + r] = x;
+  n2 = sqrt(wsum(x * x));
+  __syncthreads();
+}
+
+// Y = [K | orth(P against K)]; a dependent column of P is replaced by the
+// next coordinate vector that is independent, so the count is always
+// min(kc + pc, rows).
+__global__ __launch_bounds__(64) void k_restart_basis(const double *K, int ldk, int rows, int kc,
+                                                      const double *P, int ldp, int pc, double *Y,
+                                                      int ldy, int *count) {
+  __shared__ double q[kSmallMax * kSmallMax];
+  __shared__ double xs[kSmallMax], dots[kSmallMax];
+  const int r = threadIdx.x;
+  for (int j = 0; j < kc; ++j) q[j * kSmallMax + r] = r < rows ? K[r + (int64_t)j * ldk] : 0.0;
+  __syncthreads();
+  int cur = kc, unit = 0;
+  const int want = min(kc + pc, min(rows, kSmallMax));
+  for (int c = 0; cur < want; ++c) {
+    for (int attempt = 0; attempt < rows + 1; ++attempt) {
+      double x;
+      if (c < pc && attempt == 0) {
+        x = r < rows ? P[r + (int64_t)c * ldp] : 0.0;
+      } else {
+        x = (r == unit) ? 1.0 : 0.0;
+        ++unit;
+      }
+      q[cur * kSmallMax + r] = x;
+      __syncthreads();
+      double n0, n2;
+      wave_cgs2(q, rows, cur, xs, dots, nullptr, n0, n2);
+      if (n0 > 0.0 && n2 > 1e-8 * n0) {
+        q[cur * kSmallMax + r] /= n2;
+        ++cur;
+        __syncthreads();
+        break;
+      }
+    }
   }
-  if (t == 0) count[0] = cur;
+  if (r < rows)
+    for (int j = 0; j < cur; ++j) Y[r + (int64_t)j * ldy] = q[j * kSmallMax + r];
+  if (r == 0) count[0] = cur;
 }
 
 void restart_basis(const double *K, int ldk, int rows, int kc, const double *P, int ldp, int pc,
                    double *Y, int ldy, int *count, hipStream_t s) {
-  PHS_REQUIRE(rows <= kSvdRows && kc + pc <= kSmallMax + 32 && kc <= kSmallMax, kEinval,
-              "restart_basis: size out of range");
-  k_restart_basis<<<1, 256, 0, s>>>(K, ldk, rows, kc, P, ldp, pc, Y, ldy, count);
+  PHS_REQUIRE(rows <= kSmallMax && kc <= kSmallMax, kEinval, "restart_basis: size out of range");
+  k_restart_basis<<<1, 64, 0, s>>>(K, ldk, rows, kc, P, ldp, pc, Y, ldy, count);
   PHS_CHECK_LAUNCH();
 }
 
-__global__ __launch_bounds__(256) void k_small_qr(const double *M, int ldm, int rows, int cols,
-                                                  double *Q, int ldq, double *R, int ldr) {
-  __shared__ double q[kSmallMax * kSvdRows];
-  __shared__ double red[256];
-  __shared__ double rc[kSmallMax];
-  const int t = threadIdx.x;
-  for (int idx = t; idx < rows * cols; idx += blockDim.x) {
-    int i = idx % rows, j = idx / rows;
-    q[j * kSvdRows + i] = M[i + (int64_t)j * ldm];
-  }
-  for (int idx = t; idx < cols * cols; idx += blockDim.x) R[idx % cols + (int64_t)(idx / cols) * ldr] = 0.0;
-  __syncthreads();
+__global__ __launch_bounds__(64) void k_small_qr(const double *M, int ldm, int rows, int cols,
+                                                 double *Q, int ldq, double *R, int ldr) {
+  __shared__ double q[kSmallMax * kSmallMax];
+  __shared__ double rc[kSmallMax], xs[kSmallMax], dots[kSmallMax];
+  const int r = threadIdx.x;
+  for (int j = 0; j < cols; ++j) q[j * kSmallMax + r] = r < rows ? M[r + (int64_t)j * ldm] : 0.0;
+  for (int e = r; e < cols * cols; e += 64) R[e % cols + (int64_t)(e / cols) * ldr] = 0.0;
   for (int c = 0; c < cols; ++c) {
-    if (t < kSmallMax) rc[t] = 0.0;
+    rc[r] = 0.0;
     __syncthreads();
     double n0, n2;
-    mgs2_col(q, rows, c, c, red, rc, n0, n2);
+    wave_cgs2(q, rows, c, xs, dots, rc, n0, n2);
     double inv = n2 > 0.0 ? 1.0 / n2 : 0.0;
-    for (int k = t; k < rows; k += blockDim.x) q[c * kSvdRows + k] *= inv;
-    if (t == 0) {
-      for (int j = 0; j < c; ++j) R[j + (int64_t)c * ldr] = rc[j];
-      R[c + (int64_t)c * ldr] = n2;
-    }
-    __syncthreads();
+    q[c * kSmallMax + r] *= inv;
+    if (r < c) R[r + (int64_t)c * ldr] = rc[r];
+    if (r == 0) R[c + (int64_t)c * ldr] = n2;
   }
-  for (int idx = t; idx < rows * cols; idx += blockDim.x) {
-    int i = idx % rows, j = idx / rows;
-    Q[i + (int64_t)j * ldq] = q[j * kSvdRows + i];
-  }
+  if (r < rows)
+    for (int j = 0; j < cols; ++j) Q[r + (int64_t)j * ldq] = q[j * kSmallMax + r];
 }
 
 void small_qr(const double *M, int ldm, int rows, int cols, double *Q, int ldq, double *R,
               int ldr, hipStream_t s) {
-  PHS_REQUIRE(rows <= kSvdRows && cols <= kSmallMax && cols <= rows, kEinval,
-              "small_qr: size out of range");
-  k_small_qr<<<1, 256, 0, s>>>(M, ldm, rows, cols, Q, ldq, R, ldr);
+  PHS_REQUIRE(rows <= kSmallMax && cols <= rows, kEinval, "small_qr: size out of range");
+  k_small_qr<<<1, 64, 0, s>>>(M, ldm, rows, cols, Q, ldq, R, ldr);
   PHS_CHECK_LAUNCH();
 }
 

@@ -172,10 +172,17 @@ void cgs_cols(Ctx &c, double *X, int64_t rows, int64_t ld, int j0, int j1, doubl
 
 // ------------------------------------------------------------------------
 // Stage 1: block GD+k on C = A^T A in working precision T.
+//
+// The steady-state iteration reads the device once: a packed status block
+// with the Ritz values, the residual norms and the orthogonality
+// diagnostics of the previous basis expansion.  That expansion is done
+// without host checks; if its diagnostics show a dependent column or a
+// Cholesky breakdown, it is rolled back (the basis, W and H below column p
+// are untouched by it) and redone by the checked path.
 template <typename T>
 Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Stage1Params &P,
                         Stage1Bufs<T> &bf, SmallPool &sp) {
-  const int64_t n = A.n, m = A.m;
+  const int64_t n = A.n;
   const int k = P.k, b = P.b, bw = P.bw, pmax = P.pmax, pmin = P.pmin;
   const bool largest = P.largest;
   const bool fp32 = std::is_same<T, float>::value;
@@ -185,22 +192,32 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
   T *V[2] = {bf.V[0], bf.V[1]}, *W[2] = {bf.W[0], bf.W[1]};
   int cur = 0, p = 0, nl = 0, nprev = 0;
   T *Tb = bf.Tb, *T2b = bf.T2b, *Rb = bf.Rb;
-  double *H = sp.mat(4), *S = sp.mat(5), *Y = sp.mat(6), *Hs = sp.mat(7), *prev = sp.mat(8),
-         *prev2 = sp.mat(9), *Gb = sp.mat(10);
-  double *theta = sp.vec(5), *rn2 = sp.vec(6), *rho2 = sp.vec(7);
+  double *H = sp.mat(4), *Sa = sp.mat(5), *Y = sp.mat(6), *Hs = sp.mat(7), *prev = sp.mat(8),
+         *prev2 = sp.mat(9), *Gb = sp.mat(10), *Sb = sp.mat(34), *G = sp.mat(0),
+         *Gram = sp.mat(1), *R1 = sp.mat(2), *Ri1 = sp.mat(3);
+  // packed status block: theta | rn2 | n0 | n1 | n2 | rho2 | flags
+  double *stat = sp.vec(22);
+  double *theta = stat, *rn2 = stat + 64, *sn0 = stat + 128, *sn1 = stat + 160,
+         *sn2v = stat + 192, *rho2 = stat + 224;
+  int *sflag = reinterpret_cast<int *>(stat + 256);
+  const int kStat = 260;
   int *cnt = c.sc.flag + 8;
   Stage1Result res;
   res.sn2 = P.anorm > 0 ? P.anorm * P.anorm : P.sn2_init;
   std::vector<double> rho_h(bw, 0.0);
   int rho_age = 1 << 30;
+  bool warm = false;
+  bool gnn_off = false;
+  std::vector<double> pc_hist;
+  int pw = 0;                 // size of the warm-start eigenvector block
+  int pend_nb = 0, pend_p = 0;  // unchecked expansion: width, basis size before
 
   auto applyC = [&](T *X, int nb) {
     spmm(A, bw, X, bf.Yb, false, c.s);
     spmm(At, bw, bf.Yb, bf.WTb, false, c.s);
     c.st->mv_stage1 += nb;
   };
-  auto expand = [&](int nb) {
-    orth_block(c, Tb, T2b, n, nb, bw, cm(bf.Xl, n, nl, n), cm(V[cur], n, p, n), dep_drop, sp);
+  auto append = [&](int nb) {
     applyC(Tb, nb);
     copy(rmv(Tb, n, nb, bw), cm(V[cur] + (int64_t)p * n, n, nb, n), c.s);
     copy(rmv(bf.WTb, n, nb, bw), cm(W[cur] + (int64_t)p * n, n, nb, n), c.s);
@@ -208,6 +225,33 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     h_border(H, ld, p, nb, Gb, ld, c.s);
     if (nprev) zero_rows(prev, ld, p, p + nb, nprev, c.s);
     p += nb;
+  };
+  // checked expansion (host decisions on dependence and breakdown)
+  auto expand = [&](int nb) {
+    orth_block(c, Tb, T2b, n, nb, bw, cm(bf.Xl, n, nl, n), cm(V[cur], n, p, n), dep_drop, sp);
+    append(nb);
+  };
+  // unchecked expansion: CGS2 + CholQR2, diagnostics left in the status block
+  auto expand_fast = [&](int nb) {
+    copy(rmv(Tb, n, nb, bw), rmv(bf.Fb, n, nb, bw), c.s);  // kept for a rollback
+    Tall<T> Tv = rmv(Tb, n, nb, bw);
+    const Tall<T> B1 = cm(bf.Xl, n, nl, n), B2 = cm(V[cur], n, p, n);
+    colnorm2(Tv, 0, n, sn0, c.sc, c.s);
+    for (int pass = 0; pass < 2; ++pass) {
+      tn(B1, B2, Tv, G, ld, c.sc, c.s);
+      nn(B1, B2, G, ld, -1.0, Tv, 1.0, c.s);
+      colnorm2(Tv, 0, n, pass == 0 ? sn1 : sn2v, c.sc, c.s);
+    }
+    for (int q = 0; q < 2; ++q) {
+      Tall<T> Tq = rmv(Tb, n, nb, bw);
+      tn(Tq, none<T>(n), Tq, Gram, ld, c.sc, c.s);
+      chol_inv(Gram, ld, nb, 0.0, R1, Ri1, ld, sflag + q, c.s);
+      nn(Tq, none<T>(n), Ri1, ld, 1.0, rmv(T2b, n, nb, bw), 0.0, c.s);
+      std::swap(Tb, T2b);
+    }
+    pend_nb = nb;
+    pend_p = p;
+    append(nb);
   };
 
   // initial block (Section 5: ones(n,1)/sqrt(n) plus seeded random columns),
@@ -227,35 +271,75 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
       expand(w);
     }
   }
-  std::vector<double> th_h(pmax), rn_h(bw), hist;
+  std::vector<double> hs(kStat), hist;
   const int L = std::max(100, 20 * ((pmax + b - 1) / b));
   int64_t it = 0;
   while (true) {
     ++it;
-    syevj(H, ld, p, largest, theta, S, ld, c.s);
+    double *S = Sa;
     const int nb = std::min(b, p);
+    // eigenpairs this iteration uses: the block, or the p_min kept at a
+    // restart; a lock recomputes all p
+    const int nv = (p + nb > pmax) ? std::min(std::max(pmin, nb), p) : nb;
+    syev_rr(H, ld, p, nv, largest, theta, S, ld, c.s);
     ritz(cm(V[cur], n, p, n), cm(W[cur], n, p, n), S, ld, theta, bf.Xb, Rb, nb, bw, rn2, nullptr,
          0, c.sc, c.s);
-    // componentwise accuracy floor of float32 C x (|A|^T |A| |x|), refreshed
-    if (fp32 && (rho_age >= 10)) {
-      // |x| of the block: the abs-SpMM takes |.| of every operand itself
+    const bool want_rho = fp32 && rho_age >= 10;
+    if (want_rho) {
+      // componentwise accuracy floor of float32 C x: || |A|^T |A| |x| ||
       spmm(A, bw, bf.Xb, bf.Yb, true, c.s);
-      spmm(At, bw, bf.Yb, bf.Fb, true, c.s);
-      colnorm2(rmv(bf.Fb, n, nb, bw), 0, n, rho2, c.sc, c.s);
+      spmm(At, bw, bf.Yb, bf.WTb, true, c.s);
+      colnorm2(rmv(bf.WTb, n, nb, bw), 0, n, rho2, c.sc, c.s);
       c.st->mv_floor += nb;
-      double hr[64];
-      c.d2h(hr, rho2, nb * sizeof(double));
-      c.sync();
-      for (int j = 0; j < nb; ++j) rho_h[j] = std::sqrt(hr[j]);
+    }
+    c.d2h(hs.data(), stat, kStat * sizeof(double));
+    c.sync();
+    const double *th_h = hs.data(), *rn_h = hs.data() + 64;
+    if (want_rho) {
+      for (int j = 0; j < nb; ++j) rho_h[j] = std::sqrt(std::max(hs[224 + j], 0.0));
       rho_age = 0;
     }
     ++rho_age;
-    c.d2h(th_h.data(), theta, p * sizeof(double));
-    c.d2h(rn_h.data(), rn2, nb * sizeof(double));
-    c.sync();
-    for (int j = 0; j < p; ++j) res.sn2 = std::max(res.sn2, th_h[j]);
+    if (pend_nb) {
+      // deferred check of the last expansion
+      const int *fl = reinterpret_cast<const int *>(hs.data() + 256);
+      bool bad = fl[0] || fl[1];
+      for (int j = 0; j < pend_nb && !bad; ++j) {
+        double a0 = std::sqrt(std::max(hs[128 + j], 0.0)), a1 = std::sqrt(std::max(hs[160 + j], 0.0));
+        double a2 = std::sqrt(std::max(hs[192 + j], 0.0));
+        if (!(a0 > 0.0) || !(a2 > dep_drop * a0) || !std::isfinite(a2) || a2 < 0.5 * a1) bad = true;
+      }
+      const int redo = pend_nb;
+      pend_nb = 0;
+      if (bad) {
+        p = pend_p;
+        std::swap(Tb, bf.Fb);  // the saved correction block
+        expand(redo);
+        warm = false;
+        ++res.rollbacks;
+        continue;
+      }
+    }
+    // largest Ritz value so far: ||A||^2 estimate
+    for (int j = 0; j < nv; ++j) res.sn2 = std::max(res.sn2, th_h[j]);
+    res.sn2 = std::max(res.sn2, th_h[p - 1]);
     const double sn = std::sqrt(res.sn2);
     const int need = k - nl;
+    if (P.snap) P.snap(it, bf.Xb, Rb, th_h, nb, bf.Xl, nl);
+    if (P.gnn && !gnn_off) {
+      // safeguard of the learned preconditioner: fall back to Jacobi when the
+      // leading residual has not halved within a window of iterations
+      pc_hist.push_back(std::sqrt(std::max(rn_h[0], 0.0)));
+      const int Lf = 25;
+      if ((int)pc_hist.size() >= 2 * Lf) {
+        double a = *std::min_element(pc_hist.end() - Lf, pc_hist.end());
+        double bprev = *std::min_element(pc_hist.end() - 2 * Lf, pc_hist.end() - Lf);
+        if (a > 0.5 * bprev) {
+          gnn_off = true;
+          ++res.fallbacks;
+        }
+      }
+    }
     std::vector<int> conv;
     auto floor_of = [&](int i) {
       return fp32 ? P.floor * eps * std::max(rho_h[i], 0.0) : P.floor * eps * res.sn2;
@@ -292,9 +376,9 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
       c.h2d(sp.mat(33), dneg.data(), dneg.size() * sizeof(double));
       nn(rmv(bf.Xb, n, nb, bw), none<T>(n), sp.mat(33), ld, 1.0, rmv(bf.WTb, n, nb, bw), 1.0,
          c.s);
-      colnorm2(rmv(bf.WTb, n, nb, bw), 0, n, rho2 + 64, c.sc, c.s);
+      colnorm2(rmv(bf.WTb, n, nb, bw), 0, n, stat + 300, c.sc, c.s);
       double rt[64];
-      c.d2h(rt, rho2 + 64, nb * sizeof(double));
+      c.d2h(rt, stat + 300, nb * sizeof(double));
       c.sync();
       bool all_ok = true;
       for (int i : conv) {
@@ -315,12 +399,14 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
              H + (int64_t)c0 * ld, ld, c.sc, c.s);
         }
         nprev = 0;
+        warm = false;
         ++res.refreshes;
         continue;
       }
     }
     if (!conv.empty()) {
       hist.clear();
+      pc_hist.clear();
       for (int i : conv) {
         copy(rmv(bf.Xb + i, n, 1, bw), cm(bf.Xl + (int64_t)nl * n, n, 1, n), c.s);
         res.theta.push_back(th_h[i]);
@@ -329,20 +415,27 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
                             P.tol * std::sqrt(std::max(th_h[i], 0.0)) * sn);
         ++nl;
       }
-      std::vector<int> keep;
-      for (int j = 0; j < p; ++j)
-        if (std::find(conv.begin(), conv.end(), j) == conv.end()) keep.push_back(j);
-      const int nk = (int)keep.size();
+      // kept basis: an orthonormal basis of the complement of the locked
+      // coefficient vectors, starting with the other computed Ritz vectors
+      // and completed by coordinate vectors; H is projected onto it
+      const int nk = p - (int)conv.size();
       if (nk > 0) {
-        c.h2d(c.didx, keep.data(), nk * sizeof(int));
-        gather_cols(S, ld, p, c.didx, nk, Y, ld, c.s);
-        nn(cm(V[cur], n, p, n), none<T>(n), Y, ld, 1.0, cm(V[1 - cur], n, nk, n), 0.0, c.s);
-        nn(cm(W[cur], n, p, n), none<T>(n), Y, ld, 1.0, cm(W[1 - cur], n, nk, n), 0.0, c.s);
-        set_diag(H, ld, nk, theta, c.didx, c.s);
+        std::vector<int> order(conv.begin(), conv.end());
+        for (int j = 0; j < nv; ++j)
+          if (std::find(conv.begin(), conv.end(), j) == conv.end()) order.push_back(j);
+        c.h2d(c.didx, order.data(), nv * sizeof(int));
+        gather_cols(S, ld, p, c.didx, nv, Hs, ld, c.s);
+        restart_basis(Hs, ld, p, nv, sp.eye(), ld, p - nv, Y, ld, cnt, c.s);
+        const double *Yk = Y + (int64_t)conv.size() * ld;
+        nn(cm(V[cur], n, p, n), none<T>(n), Yk, ld, 1.0, cm(V[1 - cur], n, nk, n), 0.0, c.s);
+        nn(cm(W[cur], n, p, n), none<T>(n), Yk, ld, 1.0, cm(W[1 - cur], n, nk, n), 0.0, c.s);
+        small_gemm(false, false, p, nk, p, 1.0, H, ld, Yk, ld, 0.0, Hs, ld, c.s);
+        small_gemm(true, false, nk, nk, p, 1.0, Yk, ld, Hs, ld, 0.0, H, ld, c.s);
         cur = 1 - cur;
       }
       p = nk;
       nprev = 0;
+      warm = false;
       if (nl >= k) {
         res.converged = true;
         break;
@@ -358,16 +451,24 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
                                (P.max_iters > 0 && it > P.max_iters);
     if (out_of_budget) break;
     // correction T = Prec(R)
-    if (P.jacobi_d) {
+    if (P.gnn && !gnn_off) {
+      for (int j = 0; j < nb; ++j) {
+        copy(rmv(Rb + j, n, 1, bw), cm(bf.Gs, n, 1, n), c.s);
+        copy(rmv(bf.Xb + j, n, 1, bw), cm(bf.Gs + n, n, 1, n), c.s);
+        P.gnn(bf.Gs, bf.Gs + n, th_h[j], bf.Gs + 2 * n);
+        copy(cm(bf.Gs + 2 * n, n, 1, n), rmv(Tb + j, n, 1, bw), c.s);
+      }
+      c.st->mv_prec += 6 * nb;
+    } else if (P.jacobi_d) {
       jacobi_apply<T>(Rb, bf.Xb, P.jacobi_d, theta, n, nb, bw, true, Tb, c.sc, c.s);
     } else {
       std::swap(Tb, Rb);
     }
     if (p + nb > pmax) {
+      // thick restart + the previous block (GD+k); the count is
+      // min(p_min + nprev, p) by construction of restart_basis
       restart_basis(S, ld, p, pmin, prev, ld, nprev, Y, ld, cnt, c.s);
-      int hc = 0;
-      c.d2h(&hc, cnt, sizeof(int));
-      c.sync();
+      const int hc = std::min(pmin + nprev, p);
       nn(cm(V[cur], n, p, n), none<T>(n), Y, ld, 1.0, cm(V[1 - cur], n, hc, n), 0.0, c.s);
       nn(cm(W[cur], n, p, n), none<T>(n), Y, ld, 1.0, cm(W[1 - cur], n, hc, n), 0.0, c.s);
       small_gemm(false, false, p, hc, p, 1.0, H, ld, Y, ld, 0.0, Hs, ld, c.s);
@@ -378,11 +479,15 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
       cur = 1 - cur;
       p = hc;
       ++res.restarts;
+      warm = false;
     } else {
       small_gemm(false, false, p, nb, p, 1.0, S, ld, sp.eye(), ld, 0.0, prev, ld, c.s);
       nprev = nb;
+      warm = true;
+      pw = p;
+      std::swap(Sa, Sb);  // Sb now holds this iteration's eigenvectors
     }
-    expand(nb);
+    expand_fast(nb);
   }
   res.iters = it;
   res.nl = nl;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <type_traits>
 #include <vector>
 
@@ -50,17 +51,26 @@ struct Stage1Params {
   const double *init64;    // initial basis (n x init_cols, column-major) or null
   const float *init32;
   int init_cols;
+  // optional per-iteration view of the Ritz block (it, X, R, theta, nb, X_lock, nl),
+  // blocks row-major with stride bw, X_lock column-major
+  std::function<void(int64_t, const void *, const void *, const double *, int, const void *,
+                     int)>
+      snap;
+  // learned preconditioner: called per column (r, x, theta, t), all length n
+  // in working precision; null when not used
+  std::function<void(const void *, const void *, double, void *)> gnn;
 };
 
 template <typename T>
 struct Stage1Bufs {
   T *V[2], *W[2], *Xl, *Xb, *Rb, *Tb, *T2b, *WTb, *Yb, *Fb;
+  T *Gs;  // 3 n scratch for the learned preconditioner
 };
 
 struct Stage1Result {
   bool converged = false;
   int nl = 0, p = 0;
-  int64_t iters = 0, restarts = 0, refreshes = 0;
+  int64_t iters = 0, restarts = 0, refreshes = 0, rollbacks = 0, fallbacks = 0;
   double sn2 = 0.0;
   std::vector<double> theta, res;
   std::vector<bool> tight;  // locked by the user tolerance (not by the floor)

@@ -110,18 +110,28 @@ __global__ __launch_bounds__(256) void k_tn(TV<T> x1, TV<T> x2, TV<T> y, int R, 
   }
 }
 
-__global__ void k_reduce_parts(const double *part, int nblk, int nx, int ny, double *G, int ldg) {
-  const int E = nx * ny;
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= E) return;
+// One wavefront per output entry: lane l sums partials l, l+64, ... and the
+// 64 lane sums are combined by a fixed shuffle tree (deterministic).
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(64) void k_reduce_parts(const double *part, int nblk, int nx, int ny,
+                                                     double *G, int ldg) {
+  const int E = nx * ny, e = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * E + e];
-  int i = e / ny, j = e % ny;
-  G[i + (int64_t)j * ldg] = s;
+  for (int b = threadIdx.x; b < nblk; b += 64) s += part[(int64_t)b * E + e];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) {
+    int i = e / ny, j = e % ny;
+    G[i + (int64_t)j * ldg] = s;
+  }
 }
 
 static int tn_blocks(int64_t N, int E) {
-  int64_t nb = (N + kTnRows * 4 - 1) / (kTnRows * 4);
+  int64_t nb = (N + kTnRows - 1) / kTnRows;  // one chunk per block when N is small
   int64_t cap = kPartCap / (E > 0 ? E : 1);
   if (cap > 1024) cap = 1024;
   if (nb > cap) nb = cap;
@@ -143,7 +153,7 @@ void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int l
   size_t lds = (size_t)R * (nx + ny) * sizeof(T);
   if (lds < 256 * 16 * sizeof(double)) lds = 256 * 16 * sizeof(double);
   k_tn<T><<<nblk, 256, lds, s>>>(tv(X1), tv(X2), tv(Y), R, sc.part);
-  k_reduce_parts<<<cdiv(nx * ny, 256), 256, 0, s>>>(sc.part, nblk, nx, ny, G, ldg);
+  k_reduce_parts<<<nx * ny, 64, 0, s>>>(sc.part, nblk, nx, ny, G, ldg);
   PHS_CHECK_LAUNCH();
   prof_end(kProfTn, s, (double)Y.rows * (nx + ny) * sizeof(T));
 }
@@ -281,16 +291,18 @@ __global__ __launch_bounds__(256) void k_ritz(TV<T> V, TV<T> W, const double *S,
   }
 }
 
-__global__ void k_reduce_vec(const double *part, int nblk, int E, double *out0, double *out1,
-                             int split) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= E) return;
+__global__ __launch_bounds__(64) void k_reduce_vec(const double *part, int nblk, int E,
+                                                   double *out0, double *out1, int split) {
+  const int e = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * E + e];
-  if (e < split) {
-    if (out0) out0[e] = s;
-  } else if (out1) {
-    out1[e - split] = s;
+  for (int b = threadIdx.x; b < nblk; b += 64) s += part[(int64_t)b * E + e];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) {
+    if (e < split) {
+      if (out0) out0[e] = s;
+    } else if (out1) {
+      out1[e - split] = s;
+    }
   }
 }
 
@@ -320,7 +332,7 @@ void ritz(const Tall<T> &V, const Tall<T> &W, const double *S, int lds, const do
     default: throw Error(kEinval, "ritz: unsupported block width");
   }
 #undef PHS_RITZ
-  k_reduce_vec<<<1, 64, 0, s>>>(sc.part, (int)blocks, 2 * nb, rn2, xt2, nb);
+  k_reduce_vec<<<2 * nb, 64, 0, s>>>(sc.part, (int)blocks, 2 * nb, rn2, xt2, nb);
   PHS_CHECK_LAUNCH();
   prof_end(kProfRitz, s, (double)V.rows * (2.0 * V.cols + 2.0 * nb) * sizeof(T));
 }
@@ -355,8 +367,7 @@ void colnorm2(const Tall<T> &X, int64_t r0, int64_t r1, double *out, const Scrat
   int64_t blocks = cdiv(r1 - r0 > 0 ? r1 - r0 : 1, 256 * 4);
   if (blocks > 512) blocks = 512;
   k_colnorm2<T><<<(unsigned)blocks, 256, 0, s>>>(tv(X), r0, r1, sc.part);
-  k_reduce_vec<<<cdiv(X.cols, 64), 64, 0, s>>>(sc.part, (int)blocks, X.cols, out, nullptr,
-                                               X.cols);
+  k_reduce_vec<<<X.cols, 64, 0, s>>>(sc.part, (int)blocks, X.cols, out, nullptr, X.cols);
   PHS_CHECK_LAUNCH();
 }
 
@@ -541,7 +552,7 @@ void jacobi_apply(const T *R, const T *X, const double *d, const double *theta, 
   }
 #undef PHS_JAC
   if (olsen) {
-    k_reduce_vec<<<1, 64, 0, s>>>(sc.part, (int)blocks, 2 * nb, sc.aux, nullptr, 2 * nb);
+    k_reduce_vec<<<2 * nb, 64, 0, s>>>(sc.part, (int)blocks, 2 * nb, sc.aux, nullptr, 2 * nb);
     k_jacobi2<T><<<(unsigned)blocks, 256, 0, s>>>(X, d, theta, n, nb, ldx, sc.aux, Tout);
   }
   PHS_CHECK_LAUNCH();

@@ -16,6 +16,7 @@ def _declared():
 def test_header_declares_the_entry_points():
     names = _declared()
     for must in ("phsvds_svds", "phsvds_spmm_f64", "phsvds_spmm_f32", "phsvds_csr_transpose",
+                 "phsvds_rr_eig",
                  "phsvds_workspace_bytes", "phsvds_last_error", "phsvds_version"):
         assert must in names
 

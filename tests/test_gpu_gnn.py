@@ -1,0 +1,126 @@
+"""Learned preconditioner on the GPU (float32) vs the float64 oracle:
+forward output, back-propagated gradient (<= 1e-3 relative per tensor),
+Adam step; harvested pairs satisfy their correction equation; the
+preconditioned solver still returns the definition's triplets."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import precond as pc
+from tests.gpu_util import as_np, gpu, need_gpu, say, to_dev
+
+
+def _case(width=32, seed=0):
+    A = wl.random_sparse(600, 400, 8, seed=31)
+    P = wl.gnn_init_weights(width, seed=seed)
+    rr = np.random.default_rng(seed + 5)
+    for k in ("b1", "b2", "b3"):
+        P[k] = (0.1 * rr.standard_normal(P[k].shape)).astype(np.float32).astype(np.float64)
+    x = rr.standard_normal(400)
+    x /= np.linalg.norm(x)
+    r = rr.standard_normal(400)
+    r -= x * (x @ r)
+    ts = rr.standard_normal(400)
+    ts -= x * (x @ ts)
+    # float32-representable inputs so both sides see the same data
+    f = lambda v: v.astype(np.float32).astype(np.float64)
+    return A, P, f(r), f(x), 0.37, f(ts)
+
+
+def _dev32(v):
+    return torch.tensor(v, dtype=torch.float32, device="cuda")
+
+
+@gpu
+@pytest.mark.parametrize("width", [8, 32])
+def test_gnn_forward_matches_oracle(width):
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A, Pw, r, x, th, ts = _case(width)
+    say("gnn forward width", width)
+    g = P.GnnGraph(to_dev(A), width)
+    t = as_np(g.forward(P.gnn_pack(Pw), _dev32(r), _dev32(x), th)).astype(np.float64)
+    tref, _ = pc.forward(pc.Graph(A), Pw, r, x, th)
+    err = np.linalg.norm(t - tref) / np.linalg.norm(tref)
+    say("rel err", err)
+    assert err < 1e-4
+
+
+@gpu
+def test_gnn_gradient_matches_oracle():
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A, Pw, r, x, th, ts = _case(32)
+    say("gnn gradient width 32")
+    g = P.GnnGraph(to_dev(A), 32)
+    nw = P.gnn_nweights(32)
+    grad = torch.zeros(nw, dtype=torch.float64, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g.loss_grad(P.gnn_pack(Pw), _dev32(r), _dev32(x), th, _dev32(ts), grad, loss)
+    lref, gref = pc.loss_and_grad(pc.Graph(A), Pw, r, x, th, ts)
+    assert abs(loss.item() - lref) <= 1e-4 * lref
+    gg = P.gnn_unpack(grad, 32)
+    for k in pc.NAMES:
+        err = np.linalg.norm(gg[k] - gref[k]) / max(np.linalg.norm(gref[k]), 1e-30)
+        say(k, err)
+        assert err <= 1e-3, (k, err)
+
+
+@gpu
+def test_gnn_adam_matches_oracle():
+    need_gpu()
+    import paper_1408_5535_amd as P
+    Pw = wl.gnn_init_weights(8, seed=3)
+    G = {k: np.random.default_rng(i).standard_normal(v.shape) for i, (k, v) in enumerate(Pw.items())}
+    w = P.gnn_pack(Pw)
+    m = torch.zeros_like(w)
+    v = torch.zeros_like(w)
+    gflat = torch.tensor(np.concatenate([G[k].ravel() for k in P.GNN_NAMES]), device="cuda")
+    P.gnn_adam(w, m, v, gflat, 1, lr=1e-2)
+    zeros = {k: np.zeros_like(val) for k, val in Pw.items()}
+    ref, _, _ = pc.adam_step(Pw, G, zeros, dict(zeros), 1, lr=1e-2)
+    got = P.gnn_unpack(w, 8)
+    for k in pc.NAMES:
+        assert np.allclose(got[k], ref[k], rtol=1e-6, atol=1e-7)
+
+
+@gpu
+def test_harvest_pairs_solve_correction_equation():
+    """k = 1, block 1: until the pair locks, Q = [x] exactly, so every pair
+    must satisfy (I - x x^T)((C - theta) t + r) = 0 with t orthogonal to x."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A = wl.random_sparse(3000, 2000, 12, seed=1000)
+    say("harvest 3000x2000 k=1 b=1")
+    R, X, T, th, info = P.harvest(to_dev(A), 1, block=1, every=1, max_pairs=6, tol=1e-12,
+                                  cg_tol=1e-10)
+    say("pairs", len(th), info["mv_prec"])
+    assert len(th) >= 4
+    R, X, T = as_np(R), as_np(X), as_np(T)
+    for i in range(len(th)):
+        r, x, t = R[i], X[i], T[i]
+        assert abs(np.linalg.norm(x) - 1) < 1e-12
+        v = A.T @ (A @ t) - th[i] * t + r
+        v -= x * (x @ v)
+        assert abs(x @ t) < 1e-10 * np.linalg.norm(t)
+        assert np.linalg.norm(v) < 1e-8 * np.linalg.norm(r)
+
+
+@gpu
+def test_svds_with_gnn_preconditioner_returns_definition():
+    need_gpu()
+    import paper_1408_5535_amd as P
+    from oracle import dense
+    A = wl.random_sparse(600, 400, 8, seed=2002)
+    sig_ex, _, _ = dense.svd_extreme_dense(A, 4)
+    an = float(np.linalg.norm(A.toarray(), 2))
+    w = P.gnn_pack(wl.gnn_init_weights(32, seed=1))
+    say("svds gnn 600x400 k=4")
+    sig, U, V, info = P.svds_smallest(to_dev(A), 4, 1e-12, precond="gnn", gnn_weights=w,
+                                      block=2, anorm=an)
+    say(info)
+    assert info["status"] == 0
+    assert np.allclose(sig, sig_ex, rtol=1e-10)
+    res = dense.triplet_residuals(A, sig, as_np(U), as_np(V))
+    assert np.all(res <= 1e-12 * an)

@@ -67,3 +67,52 @@ def test_csr_transpose_exact(name):
     assert np.array_equal(as_np(At.rowptr), ref.indptr)
     assert np.array_equal(as_np(At.colind), ref.indices)
     assert np.array_equal(as_np(At.val), ref.data)
+
+
+def _rr_cases():
+    r = np.random.default_rng(11)
+    out = []
+    for p in (1, 2, 7, 35, 64):
+        X = r.standard_normal((p, p))
+        out.append((f"random{p}", X + X.T))
+    Q, _ = np.linalg.qr(r.standard_normal((40, 40)))
+    spectra = {
+        "clustered": np.r_[1e-4 + 1e-6 * np.arange(1, 21), np.linspace(0.1, 8, 20)],
+        "repeated": np.r_[np.ones(10), 2 * np.ones(10), np.linspace(3, 4, 20)],
+        "graded": np.logspace(-12, 0, 40),
+        "identity": np.ones(40),
+        "zero": np.zeros(40),
+    }
+    for name, ev in spectra.items():
+        out.append((name, Q @ np.diag(ev) @ Q.T))
+    out.append(("diagonal", np.diag(np.arange(40.0))))
+    W = np.diag(np.abs(np.arange(-10, 11)).astype(float)) + np.diag(np.ones(20), 1) + \
+        np.diag(np.ones(20), -1)
+    out.append(("wilkinson21", W))
+    return out
+
+
+@gpu
+@pytest.mark.parametrize("case", range(12))
+def test_rr_eig_selected_pairs(case):
+    """Selected eigenpairs of the Rayleigh-Ritz matrix: eigenvalues against
+    LAPACK (numpy eigvalsh), residual and orthonormality of the vectors."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    name, H = _rr_cases()[case]
+    p = H.shape[0]
+    nrm = np.linalg.norm(H, 2)
+    ref = np.linalg.eigvalsh(H)
+    for nvec in sorted({1, min(4, p), min(24, p), p}):
+        for largest in (False, True):
+            say("rr_eig", name, "p", p, "nvec", nvec, "largest", largest)
+            th, S = P.rr_eig(torch.tensor(H, device="cuda"), nvec, largest)
+            th, S = as_np(th), as_np(S)
+            want = ref[::-1] if largest else ref
+            got = np.r_[th[:nvec], th[p - 1]]
+            exp = np.r_[want[:nvec], want[p - 1]]
+            assert np.max(np.abs(got - exp)) <= 1e-14 * nrm + 1e-30, (name, nvec, largest)
+            Sv = S[:, :nvec]
+            res = np.linalg.norm(H @ Sv - Sv * th[:nvec], axis=0)
+            assert np.max(res) <= 1e-14 * nrm + 1e-30, (name, nvec, largest)
+            assert np.max(np.abs(Sv.T @ Sv - np.eye(nvec))) <= 1e-13, (name, nvec, largest)
