@@ -51,180 +51,344 @@ __device__ inline void rr_pair(int P, int r, int k, int &a, int &b) {
 
 // ---------------------------------------------------------- syev
 // Rayleigh-Ritz eigenproblem H s = theta s of the search space (p <= 64),
-// float64, one workgroup of four wavefronts:
-//  1. Householder reduction H = Q T Q^T to tridiagonal T; the reflectors
-//     stay in the rows of H they annihilate.
+// float64, one wavefront.  Lane t owns row t of H in LDS.
+//  1. Householder reduction H = Q T Q^T to tridiagonal T, last row first;
+//     the reflectors stay in the rows of H they annihilate.
 //  2. Selected eigenvalues of T by multisection of Sturm sequences: the
-//     eigenvalue of rank r is bracketed by the L lanes of one group, which
-//     evaluate the count at L interior points per step and keep the
-//     subinterval their ballot selects.
-//  3. Eigenvectors of T by inverse iteration (one lane per vector), with
-//     Gram-Schmidt inside clusters of close eigenvalues after every sweep.
-//  4. s = Q y by applying the reflectors to y (one lane group per vector,
-//     the vector held in registers).
+//     eigenvalue of rank r is bracketed by the lanes of one group, each
+//     evaluating the count at up to four interior points per step
+//     (independent recurrences, interleaved); the group keeps the
+//     subinterval below the first point whose count exceeds the rank.
+//  3. Eigenvectors of T by inverse iteration, one lane per vector;
+//     vectors of nearly equal eigenvalues are orthogonalised between
+//     sweeps, those of a cluster (eigenvalues within 1e-3 ||T||) after the
+//     last sweep.
+//  4. s = Q y by applying the reflectors, each vector held in the
+//     registers of a lane group.
 // Outputs: theta[0..nvec) and S(:, 0..nvec) for the nvec eigenpairs at the
 // wanted end (ascending, or descending if `desc`), and theta[p-1], the
 // eigenvalue at the other end.  Other entries are not written.
-constexpr int kEigThreads = 256;
-constexpr int kEigRegs = 16;  // rows per lane in step 4 (64 rows / 4 lanes)
+constexpr int kPadRows = kSmallMax + 8;
 
-__device__ inline double wred(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// DPP move of a double (both halves), all rows and banks enabled.
+template <int CTRL>
+__device__ inline double dpp_mov(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
+  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+// Sum over lane groups of G (1, 2, 4, 8 or 16) lanes inside a DPP row; every
+// lane of the group receives the group sum.
+template <int G>
+__device__ inline double group_sum(double v) {
+  if (G == 16) {
+    v += dpp_mov<0x128>(v);  // row_ror:8: lanes l, l+8 of the row
+    v += dpp_mov<0x124>(v);  // row_ror:4: lanes congruent mod 4
+  } else if (G == 8) {
+    v += dpp_mov<0x141>(v);  // row_half_mirror: lanes l, 7-l of the half row
+  }
+  if (G >= 4) v += dpp_mov<0x4E>(v);  // quad_perm [2,3,0,1]
+  if (G >= 2) v += dpp_mov<0xB1>(v);  // quad_perm [1,0,3,2]
   return v;
 }
+// Sum over the wave, the same value in every lane: row sums by DPP, then
+// the four row sums read from lanes 0, 16, 32, 48 in a fixed order.
+__device__ inline double wave_total(double v) {
+  v = group_sum<16>(v);
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  double r[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    r[k] = __hiloint2double(__builtin_amdgcn_readlane(hi, 16 * k),
+                            __builtin_amdgcn_readlane(lo, 16 * k));
+  return (r[0] + r[1]) + (r[2] + r[3]);
+}
+__device__ inline double wave_max(double v) {
+  v = fmax(v, dpp_mov<0x128>(v));
+  v = fmax(v, dpp_mov<0x124>(v));
+  v = fmax(v, dpp_mov<0x4E>(v));
+  v = fmax(v, dpp_mov<0xB1>(v));
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  double m = v;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    m = fmax(m, __hiloint2double(__builtin_amdgcn_readlane(hi, 16 * k),
+                                 __builtin_amdgcn_readlane(lo, 16 * k)));
+  return m;
+}
 
-__global__ __launch_bounds__(kEigThreads) void k_syev(const double *H, int ldh, int p, int nvec,
-                                                      bool desc, double *theta, double *Sout,
-                                                      int lds) {
+// Step 2 with Q points per lane and L lanes per eigenvalue (Q * L <= 64).
+template <int Q>
+__device__ void multisect(const double *ds, const double *e2s, int n, int ne, int nvec, int L,
+                          bool desc, double lo, double hi, double *lamv) {
+  const double eps = 2.220446049250313e-16;
+  const int t = threadIdx.x;
+  const int slot = t / L, sub = t % L;
+  const bool act = slot < ne;
+  const int rank = act ? (slot < nvec ? slot : n - 1) : 0;
+  const int jidx = desc ? n - 1 - rank : rank;
+  const int P = Q * L;
+  const int base = t - sub;
+  const unsigned long long gmask = (L == 64) ? ~0ull : ((1ull << L) - 1ull);
+  double a0 = lo - eps, b0 = hi + eps;
+  // width 2 + 2 eps down to below 1e-2 eps: a factor 2^59.7
+  const int nst = (int)ceil(59.8 / log2((double)(P + 1))) + 1;
+  for (int it = 0; it < nst; ++it) {
+    const double w = (b0 - a0) / (double)(P + 1);
+    double x[Q], pm[Q], pc[Q];
+    int cnt[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      x[k] = a0 + (double)(k * L + sub + 1) * w;
+      pm[k] = 1.0;
+      pc[k] = ds[0] - x[k];
+      if (pc[k] == 0.0) pc[k] = -1e-290;
+      cnt[k] = pc[k] < 0.0;
+    }
+    // p_i = (d_i - x) p_{i-1} - e_i^2 p_{i-2}; rows past n are padded with
+    // d = 4, e = 0 (no sign change); the pair is rescaled every 8 rows
+    for (int i0 = 1; i0 < n; i0 += 8) {
+      double dv[8], ev[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        dv[u] = ds[i0 + u];
+        ev[u] = e2s[i0 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          double pn = fma(dv[u] - x[k], pc[k], -ev[u] * pm[k]);
+          // an exact zero takes the sign opposite to its predecessor
+          if (pn == 0.0) pn = -copysign(1e-290, pc[k]);
+          // sign change: the sign bits of the high words differ
+          cnt[k] += (int)(((unsigned)__double2hiint(pn) ^ (unsigned)__double2hiint(pc[k])) >> 31);
+          pm[k] = pc[k];
+          pc[k] = pn;
+        }
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        int ex;
+        frexp(fmax(fabs(pm[k]), fabs(pc[k])), &ex);
+        pm[k] = ldexp(pm[k], -ex);
+        pc[k] = ldexp(pc[k], -ex);
+      }
+    }
+    // bit k*L + sub of the group mask: point k*L + sub lies above the
+    // eigenvalue
+    unsigned long long above = 0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      above |= ((__ballot(act && cnt[k] > jidx) >> base) & gmask) << (k * L);
+    const int j = above ? __ffsll((long long)above) - 1 : P;
+    const double na = j > 0 ? a0 + (double)j * w : a0;
+    const double nb = j < P ? a0 + (double)(j + 1) * w : b0;
+    a0 = na;
+    b0 = fmax(nb, na);
+  }
+  if (act && sub == 0) lamv[slot] = 0.5 * (a0 + b0);
+}
+
+// Step 4 with G lanes per vector, R = 64 / G rows per lane in registers.
+template <int G>
+__device__ void apply_reflectors(const double *a, const double *rh, const double *y, int n,
+                                 int nvec, const double *lamv, double tnorm, double *theta,
+                                 double *Sout, int lds) {
+  constexpr int R = kSmallMax / G;
+  const int t = threadIdx.x;
+  const int c = t / G, sub = t % G;
+  const bool act = c < nvec;
+  double yr[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int k = sub + r * G;
+    yr[r] = (act && k < n) ? y[k * kLd + c] : 0.0;
+  }
+  for (int i = 2; i < n; ++i) {
+    const double ih = rh[i];
+    if (ih == 0.0) continue;
+    // reflector entries k < i, masked without branches
+    double av[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int k = sub + r * G;
+      const double x = a[i * kLd + k];
+      av[r] = k < i ? x : 0.0;
+    }
+    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; r += 2) {
+      d0 = fma(av[r], yr[r], d0);
+      if (r + 1 < R) d1 = fma(av[r + 1], yr[r + 1], d1);
+    }
+    const double sc = group_sum<G>(d0 + d1) * ih;
+#pragma unroll
+    for (int r = 0; r < R; ++r) yr[r] = fma(-sc, av[r], yr[r]);
+  }
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int k = sub + r * G;
+      if (k < n) Sout[k + (int64_t)c * lds] = yr[r];
+    }
+    if (sub == 0) theta[c] = lamv[c] * tnorm;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_syev(const double *H, int ldh, int p, int nvec, bool desc,
+                                             double *theta, double *Sout, int lds) {
   __shared__ double a[kSmallMax * kLd];   // H, then the reflectors
-  __shared__ double y[kSmallMax * kLd];   // eigenvectors of T, column per vector
-  __shared__ double uu[kSmallMax * kLd];  // 1 / pivots of T - lambda I
-  __shared__ double ll[kSmallMax * kLd];  // multipliers of T - lambda I
-  __shared__ double pp[4 * kSmallMax];
-  __shared__ double vv[kSmallMax], pq[kSmallMax], hh[kSmallMax];
-  __shared__ double d[kSmallMax], e[kSmallMax], ds[kSmallMax], e2s[kSmallMax];
+  __shared__ double y[kPadRows * kLd];    // eigenvectors of T, column per vector
+  __shared__ double uu[kSmallMax * kLd];  // 1 / pivots of (T - lambda I) / ||T||
+  __shared__ double ll[kPadRows * kLd];   // multipliers
+  __shared__ double vv[kPadRows], pq[kPadRows], hh[kSmallMax], rh[kSmallMax];
+  __shared__ double d[kSmallMax], e[kSmallMax + 1], ds[kPadRows], e2s[kPadRows], es1[kSmallMax];
   __shared__ double lamv[kSmallMax + 1];
-  __shared__ int cstart[kSmallMax];
-  const int tid = threadIdx.x;
-  const int t = tid & 63, q = tid >> 6;
+  __shared__ int cstart[kSmallMax], tstart[kSmallMax];
+  const int t = threadIdx.x;
   const int n = p;
   const double eps = 2.220446049250313e-16;
-  for (int r = q; r < n; r += 4)
-    if (t < n) a[r * kLd + t] = 0.5 * (H[r + (int64_t)t * ldh] + H[t + (int64_t)r * ldh]);
-  if (tid < kSmallMax) hh[tid] = 0.0;
+  // symmetric part of H, lane t writing row t
+  if (t < n) {
+#pragma unroll 8
+    for (int k = 0; k < n; ++k)
+      a[t * kLd + k] = 0.5 * (H[t + (int64_t)k * ldh] + H[k + (int64_t)t * ldh]);
+  }
+  hh[t] = 0.0;
+  rh[t] = 0.0;
+  vv[t] = 0.0;
+  pq[t] = 0.0;
+  if (t < kPadRows - kSmallMax) {
+    vv[kSmallMax + t] = 0.0;
+    pq[kSmallMax + t] = 0.0;
+  }
   __syncthreads();
-  // 1. reduction, last row first; every wave computes the reductions of the
-  //    current row itself (identical values), partial products go via LDS
-  for (int i = n - 1; i >= 1; --i) {
+  // 1. reduction of row i onto position i - 1 (l = i - 1)
+  for (int i = n - 1; i >= 2; --i) {
     const int l = i - 1;
     const double xi = (t <= l) ? a[i * kLd + t] : 0.0;
-    if (l == 0) {
-      if (tid == 0) e[1] = xi;
-      break;
+    double scale = 1.0;
+    double sigma = wave_total(xi * xi);
+    if (!(sigma > 1e-280 && sigma < 1e280)) {  // rare: scale by the 1-norm first
+      scale = wave_total(fabs(xi));
+      if (scale == 0.0) {
+        if (t == 0) e[i] = 0.0;
+        continue;  // hh[i] stays 0: no reflector
+      }
+      sigma = wave_total((xi / scale) * (xi / scale));
     }
-    const double scale = wred(fabs(xi));
-    if (scale == 0.0) {
-      if (tid == 0) e[i] = 0.0;
-      continue;  // uniform: every wave saw the same row
-    }
-    const double xs = xi / scale;
-    const double sigma = wred(xs * xs);
-    const double f = a[i * kLd + l] / scale;
+    const double isc = 1.0 / scale;
+    const double xs = xi * isc;
+    const double f = a[i * kLd + l] * isc;
     const double g = f >= 0 ? -sqrt(sigma) : sqrt(sigma);
     const double h = sigma - f * g;
-    const double v = (t == l) ? f - g : xs;  // reflector I - v v^T / h
-    if (q == 0 && t <= l) vv[t] = v;
-    if (tid == 0) {
+    const double ih = 1.0 / h;
+    const double v = (t == l) ? f - g : xs;  // reflector I - v v^T / h; 0 past l
+    vv[t] = v;
+    if (t == 0) {
       e[i] = scale * g;
       hh[i] = h;
+      rh[i] = ih;
     }
     __syncthreads();
-    {
-      double part = 0.0;
-      if (t <= l)
-        for (int k = q; k <= l; k += 4) part = fma(a[t * kLd + k], vv[k], part);
-      pp[q * kSmallMax + t] = part;
-    }
-    __syncthreads();
+    // p = A v / h over the leading (l+1) x (l+1) block (vv is 0 past l)
     double pj = 0.0;
-    if (t <= l)
-      pj = (pp[t] + pp[kSmallMax + t] + pp[2 * kSmallMax + t] + pp[3 * kSmallMax + t]) / h;
-    const double K = wred(t <= l ? v * pj : 0.0) / (2.0 * h);
-    const double qj = pj - K * v;
-    if (q == 0 && t <= l) pq[t] = qj;
+    if (t <= l) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      for (int k = 0; k <= l; k += 8) {
+        double av[8], vk[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          av[u] = a[t * kLd + k + u];
+          vk[u] = vv[k + u];
+        }
+        s0 = fma(av[0], vk[0], s0); s1 = fma(av[1], vk[1], s1);
+        s2 = fma(av[2], vk[2], s2); s3 = fma(av[3], vk[3], s3);
+        s0 = fma(av[4], vk[4], s0); s1 = fma(av[5], vk[5], s1);
+        s2 = fma(av[6], vk[6], s2); s3 = fma(av[7], vk[7], s3);
+      }
+      pj = ((s0 + s1) + (s2 + s3)) * ih;
+    }
+    const double K = wave_total(v * pj) * (0.5 * ih);
+    const double qj = (t <= l) ? pj - K * v : 0.0;
+    pq[t] = qj;
     __syncthreads();
     if (t <= l) {
-      for (int c = q; c <= l; c += 4) a[t * kLd + c] -= v * pq[c] + qj * vv[c];
-      if (q == 0) a[i * kLd + t] = v;
+      for (int k = 0; k <= l; k += 8) {
+        double qk[8], vk[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          qk[u] = pq[k + u];
+          vk[u] = vv[k + u];
+        }
+        // columns past l (still inside row t) see q = v = 0: unchanged
+        double av[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) av[u] = a[t * kLd + k + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[t * kLd + k + u] = av[u] - (v * qk[u] + qj * vk[u]);
+      }
+      a[i * kLd + t] = v;
     }
     __syncthreads();
   }
-  if (tid < n) d[tid] = a[tid * kLd + tid];
-  if (tid == 0) e[0] = 0.0;
+  if (t == 0) {
+    e[0] = 0.0;
+    e[n] = 0.0;
+    if (n >= 2) e[1] = a[1 * kLd + 0];
+  }
+  if (t < n) d[t] = a[t * kLd + t];
   __syncthreads();
   // T scaled to unit norm (Gershgorin bound)
   double lo = 1e300, hi = -1e300;
-  for (int i = 0; i < n; ++i) {
-    const double r = (i > 0 ? fabs(e[i]) : 0.0) + (i + 1 < n ? fabs(e[i + 1]) : 0.0);
-    lo = fmin(lo, d[i] - r);
-    hi = fmax(hi, d[i] + r);
+  if (t < n) {
+    const double r = fabs(e[t]) + fabs(e[t + 1]);
+    lo = d[t] - r;
+    hi = d[t] + r;
   }
+  lo = -wave_max(-lo);
+  hi = wave_max(hi);
   double tnorm = fmax(fabs(lo), fabs(hi));
   if (!(tnorm > 0.0)) tnorm = 1.0;
   const double sc = 1.0 / tnorm;
-  if (tid < n) {
-    ds[tid] = d[tid] * sc;
-    const double es = e[tid] * sc;
-    e2s[tid] = tid > 0 ? es * es : 0.0;
+  ds[t] = t < n ? d[t] * sc : 4.0;
+  e2s[t] = (t > 0 && t < n) ? (e[t] * sc) * (e[t] * sc) : 0.0;
+  if (t < kPadRows - kSmallMax) {
+    ds[kSmallMax + t] = 4.0;
+    e2s[kSmallMax + t] = 0.0;
   }
   __syncthreads();
   // 2. multisection.  Slots 0..nvec-1: ranks 0..nvec-1; slot nvec (if
   //    nvec < n): rank n-1.  Rank r is ascending index r, or n-1-r if desc.
-  //    Count(x) = number of sign changes of the leading principal minors
-  //    p_i = (d_i - x) p_{i-1} - e_i^2 p_{i-2}, the pair rescaled by a power
-  //    of two at every step; an exact zero counts as a sign change.
-  const int ne = nvec < n ? nvec + 1 : n;
-  int L = 64;
-  while (L * ne > kEigThreads) L >>= 1;
   {
-    const int slot = tid / L, sub = tid % L;
-    const bool act = slot < ne;
-    const int rank = act ? (slot < nvec ? slot : n - 1) : 0;
-    const int jidx = desc ? n - 1 - rank : rank;
-    double a0 = lo * sc - eps, b0 = hi * sc + eps;
-    // width 2 + 2 eps down to below 1e-2 eps: a factor 2^59.7
-    const int nst = (int)ceil(59.8 / log2((double)(L + 1))) + 1;
-    const int base = (tid & 63) - sub;
-    const unsigned long long gmask = (L == 64) ? ~0ull : ((1ull << L) - 1ull);
-    for (int it = 0; it < nst; ++it) {
-      const double w = (b0 - a0) / (double)(L + 1);
-      const double x = a0 + (double)(sub + 1) * w;
-      int cnt = 0;
-      double pm = 1.0, pc = ds[0] - x;
-      cnt += pc <= 0.0;
-      if (pc == 0.0) pc = -1e-290;
-      for (int i = 1; i < n; ++i) {
-        double pn = fma(ds[i] - x, pc, -e2s[i] * pm);
-        if (pn == 0.0) pn = pc < 0.0 ? 1e-290 : -1e-290;
-        cnt += (pn < 0.0) != (pc < 0.0);
-        int ex;
-        frexp(fmax(fabs(pn), fabs(pc)), &ex);
-        pm = ldexp(pc, -ex);
-        pc = ldexp(pn, -ex);
-      }
-      // first point of the group whose count exceeds the rank: the
-      // eigenvalue lies between it and the point before (counts are
-      // monotone in x up to rounding near the eigenvalues themselves)
-      const unsigned long long m = (__ballot(act && cnt > jidx) >> base) & gmask;
-      const int j = m ? __ffsll((long long)m) - 1 : L;
-      const double na = j > 0 ? a0 + (double)j * w : a0;
-      const double nb = j < L ? a0 + (double)(j + 1) * w : b0;
-      a0 = na;
-      b0 = fmax(nb, na);
-    }
-    if (act && sub == 0) lamv[slot] = 0.5 * (a0 + b0);
+    const int ne = nvec < n ? nvec + 1 : n;
+    int L = 64;
+    while (L * ne > 64) L >>= 1;
+    if (L <= 16)
+      multisect<4>(ds, e2s, n, ne, nvec, L, desc, lo * sc, hi * sc, lamv);
+    else if (L == 32)
+      multisect<2>(ds, e2s, n, ne, nvec, L, desc, lo * sc, hi * sc, lamv);
+    else
+      multisect<1>(ds, e2s, n, ne, nvec, L, desc, lo * sc, hi * sc, lamv);
   }
   __syncthreads();
-  // 3. inverse iteration on (T - lambda I)/||T|| = L U without pivoting
-  //    (tiny pivots replaced), three sweeps; after every sweep each vector
-  //    in a cluster (eigenvalues within 1e-3 ||T|| of the previous one) is
-  //    orthogonalised against the earlier members by classical Gram-Schmidt
-  //    (wave 0 lanes split the dot products, then the rows), repeated when
-  //    the first pass cancels more than half.  Orthogonalising between
-  //    sweeps keeps vectors of (nearly) equal eigenvalues from converging to
-  //    one direction.
-  if (tid < nvec) {
-    const int c = tid;
+  // 3. inverse iteration on (T - lambda I)/||T|| = L U without pivoting,
+  //    tiny pivots replaced; three sweeps.  Rows n..n+7 of the column are
+  //    zero padding (multiplier 0), so the chunked loops need no guards.
+  if (t < nvec) {
+    const int c = t;
     const double lam = lamv[c];
     const double tiny = 1e-3 * eps;
     double u = ds[0] - lam;
     if (fabs(u) < tiny) u = tiny;
     uu[c] = 1.0 / u;
+    ll[c] = 0.0;
     for (int i = 1; i < n; ++i) {
-      const double li = e[i] * sc / u;
+      const double es = e[i] * sc;
+      const double li = es / u;
       ll[i * kLd + c] = li;
-      u = ds[i] - lam - li * (e[i] * sc);
+      u = ds[i] - lam - li * es;
       if (fabs(u) < tiny) u = tiny;
       uu[i * kLd + c] = 1.0 / u;
     }
@@ -233,53 +397,139 @@ __global__ __launch_bounds__(kEigThreads) void k_syev(const double *H, int ldh, 
       hsh ^= hsh >> 16; hsh *= 0x85EBCA6Bu; hsh ^= hsh >> 13; hsh *= 0xC2B2AE35u; hsh ^= hsh >> 16;
       y[i * kLd + c] = (double)(hsh >> 8) * (2.0 / 16777216.0) - 1.0;
     }
-    int st = c;
+    for (int i = n; i < n + 8; ++i) {
+      y[i * kLd + c] = 0.0;
+      ll[i * kLd + c] = 0.0;
+    }
+    int st = c, tt = c;
     while (st > 0 && fabs(lamv[st] - lamv[st - 1]) <= 1e-3) --st;
+    while (tt > 0 && fabs(lamv[tt] - lamv[tt - 1]) <= 1e-10) --tt;
     cstart[c] = st;
+    tstart[c] = tt;
   }
+  // superdiagonal of the scaled T, shared: es1[i] = e_{i+1} / ||T||
+  es1[t] = (t + 1 < n) ? e[t + 1] * sc : 0.0;
+  __syncthreads();
   for (int sweep = 0; sweep < 3; ++sweep) {
-    if (tid < nvec) {
-      const int c = tid;
+    if (t < nvec) {
+      const int c = t;
+      // L w = y
       double w = y[c];
-      for (int i = 1; i < n; ++i) {
-        w = y[i * kLd + c] - ll[i * kLd + c] * w;
-        if (fabs(w) > 1e150) {  // rescale the whole system (rare)
-          for (int j2 = 0; j2 < n; ++j2) y[j2 * kLd + c] *= 1e-150;
-          w *= 1e-150;
+      double big = 0.0;
+      for (int i0 = 1; i0 < n; i0 += 8) {
+        double yv[8], lv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          yv[u] = y[(i0 + u) * kLd + c];
+          lv[u] = ll[(i0 + u) * kLd + c];
         }
-        y[i * kLd + c] = w;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          w = yv[u] - lv[u] * w;
+          yv[u] = w;
+          big = fmax(big, fabs(w));
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) y[(i0 + u) * kLd + c] = yv[u];
       }
+      // U x = w, bottom up; rows below 0 go to padding row n + 7
       double x = y[(n - 1) * kLd + c] * uu[(n - 1) * kLd + c];
       y[(n - 1) * kLd + c] = x;
-      for (int i = n - 2; i >= 0; --i) {
-        x = (y[i * kLd + c] - e[i + 1] * sc * x) * uu[i * kLd + c];
-        if (fabs(x) > 1e150) {
-          for (int j2 = 0; j2 < n; ++j2) y[j2 * kLd + c] *= 1e-150;
-          x *= 1e-150;
+      big = fmax(big, fabs(x));
+      for (int i0 = n - 2; i0 >= 0; i0 -= 8) {
+        double yv[8], uv[8], ev[8];
+        int row[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 - u;
+          row[u] = i >= 0 ? i : n + 7;
+          yv[u] = y[row[u] * kLd + c];
+          uv[u] = i >= 0 ? uu[row[u] * kLd + c] : 0.0;
+          ev[u] = es1[i >= 0 ? i : 0];
         }
-        y[i * kLd + c] = x;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          x = (yv[u] - ev[u] * x) * uv[u];
+          yv[u] = x;
+          big = fmax(big, fabs(x));
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) y[row[u] * kLd + c] = i0 - u >= 0 ? yv[u] : 0.0;
       }
-      double mx = 0.0;
-      for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(y[i * kLd + c]));
-      const double inv = mx > 0 ? 1.0 / mx : 1.0;
-      double s2 = 0.0;
-      for (int i = 0; i < n; ++i) {
-        const double v = y[i * kLd + c] * inv;
-        y[i * kLd + c] = v;
-        s2 += v * v;
+      if (!(big < 1e150)) {
+        // growth beyond 1e150 (tiny pivots in a row): the sweep is redone
+        // from the start vector scaled by 1e-200
+        for (int i = 0; i < n; ++i) {
+          uint32_t hsh = (uint32_t)(i * kSmallMax + c + 1) * 0x9E3779B9u;
+          hsh ^= hsh >> 16; hsh *= 0x85EBCA6Bu; hsh ^= hsh >> 13; hsh *= 0xC2B2AE35u;
+          hsh ^= hsh >> 16;
+          y[i * kLd + c] = ((double)(hsh >> 8) * (2.0 / 16777216.0) - 1.0) * 1e-200;
+        }
+        double w2 = y[c];
+        for (int i = 1; i < n; ++i) {
+          w2 = y[i * kLd + c] - ll[i * kLd + c] * w2;
+          y[i * kLd + c] = w2;
+        }
+        double x2 = y[(n - 1) * kLd + c] * uu[(n - 1) * kLd + c];
+        y[(n - 1) * kLd + c] = x2;
+        for (int i = n - 2; i >= 0; --i) {
+          x2 = (y[i * kLd + c] - es1[i] * x2) * uu[i * kLd + c];
+          y[i * kLd + c] = x2;
+        }
       }
-      const double in2 = 1.0 / sqrt(s2);
-      for (int i = 0; i < n; ++i) y[i * kLd + c] *= in2;
+      // normalise (entries below 1e150 after a good sweep: no overflow)
+      double s0 = 0.0, s1 = 0.0;
+      for (int i0 = 0; i0 < n; i0 += 8) {
+        double yv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) yv[u] = y[(i0 + u) * kLd + c];
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+          const double a0 = fabs(yv[u]) < 1e300 ? yv[u] : 0.0;
+          const double a1 = fabs(yv[u + 1]) < 1e300 ? yv[u + 1] : 0.0;
+          s0 = fma(a0, a0, s0);
+          s1 = fma(a1, a1, s1);
+        }
+      }
+      const double s2 = s0 + s1;
+      const bool ok = s2 > 0.0 && s2 < 1e300;
+      const double in2 = ok ? 1.0 / sqrt(s2) : 0.0;
+      for (int i0 = 0; i0 < n; i0 += 8) {
+        double yv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) yv[u] = y[(i0 + u) * kLd + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (i0 + u < n) y[(i0 + u) * kLd + c] = fabs(yv[u]) < 1e300 ? yv[u] * in2 : 0.0;
+      }
+      if (!ok) y[(c % n) * kLd + c] = 1.0;
     }
     __syncthreads();
+    // Gram-Schmidt: between sweeps against vectors of eigenvalues within
+    // 1e-10 ||T||, after the last sweep within 1e-3 ||T||; lanes split the
+    // dot products, then the rows; repeated when the first pass cancels
+    // more than half
+    const int *start = sweep == 2 ? cstart : tstart;
     for (int c = 1; c < nvec; ++c) {
-      const int st = cstart[c];
+      const int st = start[c];
       if (st == c) continue;
       for (int pass = 0; pass < 2; ++pass) {
-        if (q == 0 && t >= st && t < c) {
-          double dt = 0.0;
-          for (int i = 0; i < n; ++i) dt = fma(y[i * kLd + t], y[i * kLd + c], dt);
-          pq[t] = dt;
+        if (t >= st && t < c) {
+          double s0 = 0.0, s1 = 0.0;
+          for (int i0 = 0; i0 < n; i0 += 8) {
+            double yk[8], yc[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              yk[u] = y[(i0 + u) * kLd + t];
+              yc[u] = y[(i0 + u) * kLd + c];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u += 2) {
+              if (i0 + u < n) s0 = fma(yk[u], yc[u], s0);
+              if (i0 + u + 1 < n) s1 = fma(yk[u + 1], yc[u + 1], s1);
+            }
+          }
+          pq[t] = s0 + s1;
         }
         __syncthreads();
         double yi = 0.0;
@@ -287,53 +537,25 @@ __global__ __launch_bounds__(kEigThreads) void k_syev(const double *H, int ldh, 
           yi = y[t * kLd + c];
           for (int k = st; k < c; ++k) yi = fma(-pq[k], y[t * kLd + k], yi);
         }
-        const double nrm = sqrt(wred(yi * yi));
-        __syncthreads();
-        if (q == 0 && t < n) y[t * kLd + c] = yi / nrm;
+        const double nrm = sqrt(wave_total(yi * yi));
+        if (t < n) y[t * kLd + c] = nrm > 0 ? yi / nrm : 0.0;
         __syncthreads();
         if (nrm > 0.5) break;
       }
     }
   }
-  // 4. s = P_{n-1} ... P_2 y: lane group of G lanes per vector, rows
-  //    sub, sub + G, ... of the vector in registers
+  // 4. s = P_{n-1} ... P_2 y
   {
-    int G = 64;
-    while (G * nvec > kEigThreads) G >>= 1;
-    const int c = tid / G, sub = tid % G;
-    const bool act = c < nvec;
-    double yr[kEigRegs];
-#pragma unroll
-    for (int r = 0; r < kEigRegs; ++r) {
-      const int k = sub + r * G;
-      yr[r] = (act && k < n) ? y[k * kLd + c] : 0.0;
+    int G = 16;
+    while (G > 1 && G * nvec > 64) G >>= 1;
+    switch (G) {
+      case 16: apply_reflectors<16>(a, rh, y, n, nvec, lamv, tnorm, theta, Sout, lds); break;
+      case 8: apply_reflectors<8>(a, rh, y, n, nvec, lamv, tnorm, theta, Sout, lds); break;
+      case 4: apply_reflectors<4>(a, rh, y, n, nvec, lamv, tnorm, theta, Sout, lds); break;
+      case 2: apply_reflectors<2>(a, rh, y, n, nvec, lamv, tnorm, theta, Sout, lds); break;
+      default: apply_reflectors<1>(a, rh, y, n, nvec, lamv, tnorm, theta, Sout, lds); break;
     }
-    for (int i = 2; i < n; ++i) {
-      const double h = hh[i];
-      if (h == 0.0) continue;
-      double dt = 0.0;
-#pragma unroll
-      for (int r = 0; r < kEigRegs; ++r) {
-        const int k = sub + r * G;
-        if (k < i) dt = fma(a[i * kLd + k], yr[r], dt);
-      }
-      for (int off = G >> 1; off > 0; off >>= 1) dt += __shfl_xor(dt, off, 64);
-      const double sc2 = dt / h;
-#pragma unroll
-      for (int r = 0; r < kEigRegs; ++r) {
-        const int k = sub + r * G;
-        if (k < i) yr[r] = fma(-sc2, a[i * kLd + k], yr[r]);
-      }
-    }
-    if (act) {
-#pragma unroll
-      for (int r = 0; r < kEigRegs; ++r) {
-        const int k = sub + r * G;
-        if (k < n) Sout[k + (int64_t)c * lds] = yr[r];
-      }
-      if (sub == 0) theta[c] = lamv[c] * tnorm;
-    }
-    if (tid == 0 && nvec < n) theta[n - 1] = lamv[nvec] * tnorm;
+    if (t == 0 && nvec < n) theta[n - 1] = lamv[nvec] * tnorm;
   }
 }
 
@@ -341,7 +563,7 @@ void syev_rr(const double *H, int ldh, int p, int nvec, bool descending, double 
              double *S, int lds, hipStream_t s) {
   PHS_REQUIRE(p >= 1 && p <= kSmallMax && nvec >= 1 && nvec <= p, kEinval,
               "syev: size out of range");
-  k_syev<<<1, kEigThreads, 0, s>>>(H, ldh, p, nvec, descending, theta, S, lds);
+  k_syev<<<1, 64, 0, s>>>(H, ldh, p, nvec, descending, theta, S, lds);
   PHS_CHECK_LAUNCH();
 }
 
