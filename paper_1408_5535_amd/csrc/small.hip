@@ -13,6 +13,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "wave.hpp"
 
 namespace phs {
 
@@ -51,7 +52,9 @@ __device__ inline void rr_pair(int P, int r, int k, int &a, int &b) {
 
 // ---------------------------------------------------------- syev
 // Rayleigh-Ritz eigenproblem H s = theta s of the search space (p <= 64),
-// float64, one wavefront.  Lane t owns row t of H in LDS.
+// float64, one workgroup of four wavefronts.  Wave 0 runs the sequential
+// steps 1 and 3 (lane t owns row t of H in LDS); all four waves run the
+// multisection and the back-transformation.
 //  1. Householder reduction H = Q T Q^T to tridiagonal T, last row first;
 //     the reflectors stay in the rows of H they annihilate.
 //  2. Selected eigenvalues of T by multisection of Sturm sequences: the
@@ -70,54 +73,6 @@ __device__ inline void rr_pair(int P, int r, int k, int &a, int &b) {
 // eigenvalue at the other end.  Other entries are not written.
 constexpr int kPadRows = kSmallMax + 8;
 
-// DPP move of a double (both halves), all rows and banks enabled.
-template <int CTRL>
-__device__ inline double dpp_mov(double v) {
-  int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
-  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
-  return __hiloint2double(hi, lo);
-}
-// Sum over lane groups of G (1, 2, 4, 8 or 16) lanes inside a DPP row; every
-// lane of the group receives the group sum.
-template <int G>
-__device__ inline double group_sum(double v) {
-  if (G == 16) {
-    v += dpp_mov<0x128>(v);  // row_ror:8: lanes l, l+8 of the row
-    v += dpp_mov<0x124>(v);  // row_ror:4: lanes congruent mod 4
-  } else if (G == 8) {
-    v += dpp_mov<0x141>(v);  // row_half_mirror: lanes l, 7-l of the half row
-  }
-  if (G >= 4) v += dpp_mov<0x4E>(v);  // quad_perm [2,3,0,1]
-  if (G >= 2) v += dpp_mov<0xB1>(v);  // quad_perm [1,0,3,2]
-  return v;
-}
-// Sum over the wave, the same value in every lane: row sums by DPP, then
-// the four row sums read from lanes 0, 16, 32, 48 in a fixed order.
-__device__ inline double wave_total(double v) {
-  v = group_sum<16>(v);
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  double r[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    r[k] = __hiloint2double(__builtin_amdgcn_readlane(hi, 16 * k),
-                            __builtin_amdgcn_readlane(lo, 16 * k));
-  return (r[0] + r[1]) + (r[2] + r[3]);
-}
-__device__ inline double wave_max(double v) {
-  v = fmax(v, dpp_mov<0x128>(v));
-  v = fmax(v, dpp_mov<0x124>(v));
-  v = fmax(v, dpp_mov<0x4E>(v));
-  v = fmax(v, dpp_mov<0xB1>(v));
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  double m = v;
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    m = fmax(m, __hiloint2double(__builtin_amdgcn_readlane(hi, 16 * k),
-                                 __builtin_amdgcn_readlane(lo, 16 * k)));
-  return m;
-}
-
 // Step 2 with Q points per lane and L lanes per eigenvalue (Q * L <= 64).
 template <int Q>
 __device__ void multisect(const double *ds, const double *e2s, int n, int ne, int nvec, int L,
@@ -129,7 +84,7 @@ __device__ void multisect(const double *ds, const double *e2s, int n, int ne, in
   const int rank = act ? (slot < nvec ? slot : n - 1) : 0;
   const int jidx = desc ? n - 1 - rank : rank;
   const int P = Q * L;
-  const int base = t - sub;
+  const int base = (t & 63) - sub;  // first lane of the group in its wave
   const unsigned long long gmask = (L == 64) ? ~0ull : ((1ull << L) - 1ull);
   double a0 = lo - eps, b0 = hi + eps;
   // width 2 + 2 eps down to below 1e-2 eps: a factor 2^59.7
@@ -236,7 +191,7 @@ __device__ void apply_reflectors(const double *a, const double *rh, const double
   }
 }
 
-__global__ __launch_bounds__(64) void k_syev(const double *H, int ldh, int p, int nvec, bool desc,
+__global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, int nvec, bool desc,
                                              double *theta, double *Sout, int lds) {
   __shared__ double a[kSmallMax * kLd];   // H, then the reflectors
   __shared__ double y[kPadRows * kLd];    // eigenvectors of T, column per vector
@@ -246,25 +201,30 @@ __global__ __launch_bounds__(64) void k_syev(const double *H, int ldh, int p, in
   __shared__ double d[kSmallMax], e[kSmallMax + 1], ds[kPadRows], e2s[kPadRows], es1[kSmallMax];
   __shared__ double lamv[kSmallMax + 1];
   __shared__ int cstart[kSmallMax], tstart[kSmallMax];
-  const int t = threadIdx.x;
+  // wave 0 runs steps 1 and 3; all four waves run steps 2 and 4
+  const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const bool w0 = w == 0;
   const int n = p;
   const double eps = 2.220446049250313e-16;
   // symmetric part of H, lane t writing row t
-  if (t < n) {
+  if (w0 && t < n) {
 #pragma unroll 8
     for (int k = 0; k < n; ++k)
       a[t * kLd + k] = 0.5 * (H[t + (int64_t)k * ldh] + H[k + (int64_t)t * ldh]);
   }
-  hh[t] = 0.0;
-  rh[t] = 0.0;
-  vv[t] = 0.0;
-  pq[t] = 0.0;
-  if (t < kPadRows - kSmallMax) {
-    vv[kSmallMax + t] = 0.0;
-    pq[kSmallMax + t] = 0.0;
+  if (w0) {
+    hh[t] = 0.0;
+    rh[t] = 0.0;
+    vv[t] = 0.0;
+    pq[t] = 0.0;
+    if (t < kPadRows - kSmallMax) {
+      vv[kSmallMax + t] = 0.0;
+      pq[kSmallMax + t] = 0.0;
+    }
   }
   __syncthreads();
   // 1. reduction of row i onto position i - 1 (l = i - 1)
+  if (w0) {
   for (int i = n - 1; i >= 2; --i) {
     const int l = i - 1;
     const double xi = (t <= l) ? a[i * kLd + t] : 0.0;
@@ -291,7 +251,7 @@ __global__ __launch_bounds__(64) void k_syev(const double *H, int ldh, int p, in
       hh[i] = h;
       rh[i] = ih;
     }
-    __syncthreads();
+    wave_sync();
     // p = A v / h over the leading (l+1) x (l+1) block (vv is 0 past l)
     double pj = 0.0;
     if (t <= l) {
@@ -313,7 +273,7 @@ __global__ __launch_bounds__(64) void k_syev(const double *H, int ldh, int p, in
     const double K = wave_total(v * pj) * (0.5 * ih);
     const double qj = (t <= l) ? pj - K * v : 0.0;
     pq[t] = qj;
-    __syncthreads();
+    wave_sync();
     if (t <= l) {
       for (int k = 0; k <= l; k += 8) {
         double qk[8], vk[8];
@@ -331,7 +291,7 @@ __global__ __launch_bounds__(64) void k_syev(const double *H, int ldh, int p, in
       }
       a[i * kLd + t] = v;
     }
-    __syncthreads();
+    wave_sync();
   }
   if (t == 0) {
     e[0] = 0.0;
@@ -339,6 +299,7 @@ __global__ __launch_bounds__(64) void k_syev(const double *H, int ldh, int p, in
     if (n >= 2) e[1] = a[1 * kLd + 0];
   }
   if (t < n) d[t] = a[t * kLd + t];
+  }  // wave 0
   __syncthreads();
   // T scaled to unit norm (Gershgorin bound)
   double lo = 1e300, hi = -1e300;
@@ -352,11 +313,13 @@ __global__ __launch_bounds__(64) void k_syev(const double *H, int ldh, int p, in
   double tnorm = fmax(fabs(lo), fabs(hi));
   if (!(tnorm > 0.0)) tnorm = 1.0;
   const double sc = 1.0 / tnorm;
-  ds[t] = t < n ? d[t] * sc : 4.0;
-  e2s[t] = (t > 0 && t < n) ? (e[t] * sc) * (e[t] * sc) : 0.0;
-  if (t < kPadRows - kSmallMax) {
-    ds[kSmallMax + t] = 4.0;
-    e2s[kSmallMax + t] = 0.0;
+  if (w0) {
+    ds[t] = t < n ? d[t] * sc : 4.0;
+    e2s[t] = (t > 0 && t < n) ? (e[t] * sc) * (e[t] * sc) : 0.0;
+    if (t < kPadRows - kSmallMax) {
+      ds[kSmallMax + t] = 4.0;
+      e2s[kSmallMax + t] = 0.0;
+    }
   }
   __syncthreads();
   // 2. multisection.  Slots 0..nvec-1: ranks 0..nvec-1; slot nvec (if
@@ -364,7 +327,7 @@ __global__ __launch_bounds__(64) void k_syev(const double *H, int ldh, int p, in
   {
     const int ne = nvec < n ? nvec + 1 : n;
     int L = 64;
-    while (L * ne > 64) L >>= 1;
+    while (L * ne > 256) L >>= 1;
     if (L <= 16)
       multisect<4>(ds, e2s, n, ne, nvec, L, desc, lo * sc, hi * sc, lamv);
     else if (L == 32)
@@ -373,6 +336,7 @@ __global__ __launch_bounds__(64) void k_syev(const double *H, int ldh, int p, in
       multisect<1>(ds, e2s, n, ne, nvec, L, desc, lo * sc, hi * sc, lamv);
   }
   __syncthreads();
+  if (w0) {
   // 3. inverse iteration on (T - lambda I)/||T|| = L U without pivoting,
   //    tiny pivots replaced; three sweeps.  Rows n..n+7 of the column are
   //    zero padding (multiplier 0), so the chunked loops need no guards.
@@ -409,7 +373,7 @@ __global__ __launch_bounds__(64) void k_syev(const double *H, int ldh, int p, in
   }
   // superdiagonal of the scaled T, shared: es1[i] = e_{i+1} / ||T||
   es1[t] = (t + 1 < n) ? e[t + 1] * sc : 0.0;
-  __syncthreads();
+  wave_sync();
   for (int sweep = 0; sweep < 3; ++sweep) {
     if (t < nvec) {
       const int c = t;
@@ -504,7 +468,7 @@ __global__ __launch_bounds__(64) void k_syev(const double *H, int ldh, int p, in
       }
       if (!ok) y[(c % n) * kLd + c] = 1.0;
     }
-    __syncthreads();
+    wave_sync();
     // Gram-Schmidt: between sweeps against vectors of eigenvalues within
     // 1e-10 ||T||, after the last sweep within 1e-3 ||T||; lanes split the
     // dot products, then the rows; repeated when the first pass cancels
@@ -531,7 +495,7 @@ __global__ __launch_bounds__(64) void k_syev(const double *H, int ldh, int p, in
           }
           pq[t] = s0 + s1;
         }
-        __syncthreads();
+        wave_sync();
         double yi = 0.0;
         if (t < n) {
           yi = y[t * kLd + c];
@@ -539,23 +503,23 @@ __global__ __launch_bounds__(64) void k_syev(const double *H, int ldh, int p, in
         }
         const double nrm = sqrt(wave_total(yi * yi));
         if (t < n) y[t * kLd + c] = nrm > 0 ? yi / nrm : 0.0;
-        __syncthreads();
+        wave_sync();
         if (nrm > 0.5) break;
       }
     }
   }
+  }  // wave 0
+  __syncthreads();
   // 4. s = P_{n-1} ... P_2 y
   {
     int G = 16;
-    while (G > 1 && G * nvec > 64) G >>= 1;
+    while (G > 4 && G * nvec > 256) G >>= 1;
     switch (G) {
       case 16: apply_reflectors<16>(a, rh, y, n, nvec, lamv, tnorm, theta, Sout, lds); break;
       case 8: apply_reflectors<8>(a, rh, y, n, nvec, lamv, tnorm, theta, Sout, lds); break;
-      case 4: apply_reflectors<4>(a, rh, y, n, nvec, lamv, tnorm, theta, Sout, lds); break;
-      case 2: apply_reflectors<2>(a, rh, y, n, nvec, lamv, tnorm, theta, Sout, lds); break;
-      default: apply_reflectors<1>(a, rh, y, n, nvec, lamv, tnorm, theta, Sout, lds); break;
+      default: apply_reflectors<4>(a, rh, y, n, nvec, lamv, tnorm, theta, Sout, lds); break;
     }
-    if (t == 0 && nvec < n) theta[n - 1] = lamv[nvec] * tnorm;
+    if (threadIdx.x == 0 && nvec < n) theta[n - 1] = lamv[nvec] * tnorm;
   }
 }
 
@@ -563,7 +527,7 @@ void syev_rr(const double *H, int ldh, int p, int nvec, bool descending, double 
              double *S, int lds, hipStream_t s) {
   PHS_REQUIRE(p >= 1 && p <= kSmallMax && nvec >= 1 && nvec <= p, kEinval,
               "syev: size out of range");
-  k_syev<<<1, 64, 0, s>>>(H, ldh, p, nvec, descending, theta, S, lds);
+  k_syev<<<1, 256, 0, s>>>(H, ldh, p, nvec, descending, theta, S, lds);
   PHS_CHECK_LAUNCH();
 }
 

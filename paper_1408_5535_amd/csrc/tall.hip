@@ -11,6 +11,7 @@
 #include "common.hpp"
 #include "kernels.hpp"
 #include "prof.hpp"
+#include "wave.hpp"
 
 namespace phs {
 
@@ -47,96 +48,97 @@ __device__ inline void stage_rows(const TV<T> &x, int64_t r0, int R, T *lds, int
 }
 
 // ---------------------------------------------------------------- X^T Y
-constexpr int kTnRows = 64;
+// One wavefront per output tile of kTnCX x kTnCY entries; the waves of a
+// workgroup cover all tiles for one slab of rows, so the slab of Y is read
+// from HBM once and served from cache to the other tiles.  Lanes walk the
+// rows (consecutive lanes, consecutive rows: coalesced for column-major X),
+// kTnU rows per lane in flight, products accumulated in T registers.  Each
+// wave reduces its tile over its lanes; one partial per block and entry goes
+// to `part`, which a second kernel adds in a fixed order.
+constexpr int kTnCX = 8, kTnCY = 4, kTnMaxWaves = 8;
+template <typename T>
+struct TnRows {  // rows per lane in flight: float 4, double 2 (register budget)
+  static constexpr int U = sizeof(T) == 4 ? 4 : 2;
+};
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_tn(TV<T> x1, TV<T> x2, TV<T> y, int R, double *part) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  T *xs = reinterpret_cast<T *>(smem);
+__global__ __launch_bounds__(64 * kTnMaxWaves) void k_tn(TV<T> x1, TV<T> x2, TV<T> y,
+                                                         int64_t rpb, double *part) {
+  constexpr int U = TnRows<T>::U;
   const int nx = x1.cols + x2.cols, ny = y.cols;
-  T *ys = xs + R * nx;
+  const int tx = (nx + kTnCX - 1) / kTnCX, ty = (ny + kTnCY - 1) / kTnCY, ntile = tx * ty;
+  const int E = nx * ny;
+  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t N = y.rows;
-  const int ti = (nx + 3) / 4, tj = (ny + 3) / 4, ntile = ti * tj;
-  const int S = max(1, 256 / ntile);
-  const int t = threadIdx.x;
-  const int tile = t % ntile, sg = t / ntile;
-  const bool active = sg < S && t < ntile * S;
-  const int i0 = (tile / tj) * 4, j0 = (tile % tj) * 4;
-  T acc[4][4];
+  const int64_t r0 = (int64_t)blockIdx.x * rpb;
+  const int64_t r1 = r0 + rpb < N ? r0 + rpb : N;
+  const int64_t xrs = x1.rs;  // the host checks x2.rs == x1.rs
+  for (int tile = w; tile < ntile; tile += nw) {
+    const int i0 = (tile / ty) * kTnCX, j0 = (tile % ty) * kTnCY;
+    // column bases (uniform); columns past the operand read as zero
+    const T *xp[kTnCX];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = T(0);
-  for (int64_t r0 = (int64_t)blockIdx.x * R; r0 < N; r0 += (int64_t)gridDim.x * R) {
-    stage_rows(x1, r0, R, xs, nx, 0);
-    if (x2.cols) stage_rows(x2, r0, R, xs, nx, x1.cols);
-    stage_rows(y, r0, R, ys, ny, 0);
-    __syncthreads();
-    if (active) {
-      for (int r = sg; r < R; r += S) {
-        T xv[4], yv[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) xv[a] = (i0 + a < nx) ? xs[r * nx + i0 + a] : T(0);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) yv[c] = (j0 + c < ny) ? ys[r * ny + j0 + c] : T(0);
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) acc[a][c] = fma(xv[a], yv[c], acc[a][c]);
-      }
+    for (int a = 0; a < kTnCX; ++a) {
+      const int i = i0 + a;
+      xp[a] = i < x1.cols ? x1.p + (int64_t)i * x1.cs
+                          : x2.p + (int64_t)(i < nx ? i - x1.cols : 0) * x2.cs;
     }
-    __syncthreads();
-  }
-  // combine the S row groups of each tile in LDS (float64)
-  double *red = reinterpret_cast<double *>(smem);
-  if (active) {
+    const T *yp[kTnCY];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < kTnCY; ++c) yp[c] = y.p + (int64_t)(j0 + c < ny ? j0 + c : 0) * y.cs;
+    T acc[kTnCX][kTnCY];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) red[t * 16 + a * 4 + c] = (double)acc[a][c];
-  }
-  __syncthreads();
-  if (t < ntile) {
-    double sum[16];
-    for (int q = 0; q < 16; ++q) sum[q] = 0.0;
-    for (int g = 0; g < S; ++g)
-      for (int q = 0; q < 16; ++q) sum[q] += red[(g * ntile + t) * 16 + q];
-    const int E = nx * ny;
-    for (int a = 0; a < 4; ++a)
-      for (int c = 0; c < 4; ++c) {
-        int i = i0 + a, j = j0 + c;
-        if (i < nx && j < ny) part[(int64_t)blockIdx.x * E + i * ny + j] = sum[a * 4 + c];
+    for (int a = 0; a < kTnCX; ++a)
+#pragma unroll
+      for (int c = 0; c < kTnCY; ++c) acc[a][c] = T(0);
+    for (int64_t rb = r0 + lane; rb < r1; rb += 64 * U) {
+      T xr[U][kTnCX], yr[U][kTnCY];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = rb + (int64_t)u * 64;
+        const bool in = r < r1;
+        const int64_t ox = r * xrs, oy = r * y.rs;
+#pragma unroll
+        for (int a = 0; a < kTnCX; ++a) xr[u][a] = (in && i0 + a < nx) ? xp[a][ox] : T(0);
+#pragma unroll
+        for (int c = 0; c < kTnCY; ++c) yr[u][c] = (in && j0 + c < ny) ? yp[c][oy] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int a = 0; a < kTnCX; ++a)
+#pragma unroll
+          for (int c = 0; c < kTnCY; ++c) acc[a][c] = fma(xr[u][a], yr[u][c], acc[a][c]);
+    }
+    // wave sums (DPP rows, then the four row sums in a fixed order); lane 0
+    // writes the block's partial of every entry of the tile (float64)
+#pragma unroll
+    for (int a = 0; a < kTnCX; ++a)
+#pragma unroll
+      for (int c = 0; c < kTnCY; ++c) {
+        const double v = wave_total((double)acc[a][c]);
+        const int i = i0 + a, j = j0 + c;
+        if (lane == 0 && i < nx && j < ny) part[(int64_t)blockIdx.x * E + i * ny + j] = v;
       }
   }
 }
 
-// One wavefront per output entry: lane l sums partials l, l+64, ... and the
-// 64 lane sums are combined by a fixed shuffle tree (deterministic).
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-__global__ __launch_bounds__(64) void k_reduce_parts(const double *part, int nblk, int nx, int ny,
+// One wavefront per entry of G: lane l sums partials l, l+64, ... and the
+// lane sums are combined in the fixed order of wave_total.
+__global__ __launch_bounds__(64) void k_reduce_parts(const double *part, int np, int nx, int ny,
                                                      double *G, int ldg) {
   const int E = nx * ny, e = blockIdx.x;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 64) s += part[(int64_t)b * E + e];
-  s = wave_sum(s);
-  if (threadIdx.x == 0) {
-    int i = e / ny, j = e % ny;
-    G[i + (int64_t)j * ldg] = s;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int b = threadIdx.x;
+  for (; b + 192 < np; b += 256) {
+    s0 += part[(int64_t)b * E + e];
+    s1 += part[(int64_t)(b + 64) * E + e];
+    s2 += part[(int64_t)(b + 128) * E + e];
+    s3 += part[(int64_t)(b + 192) * E + e];
   }
-}
-
-static int tn_blocks(int64_t N, int E) {
-  int64_t nb = (N + kTnRows - 1) / kTnRows;  // one chunk per block when N is small
-  int64_t cap = kPartCap / (E > 0 ? E : 1);
-  if (cap > 1024) cap = 1024;
-  if (nb > cap) nb = cap;
-  if (nb < 1) nb = 1;
-  return (int)nb;
+  for (; b < np; b += 64) s0 += part[(int64_t)b * E + e];
+  const double s = wave_total((s0 + s1) + (s2 + s3));
+  if (threadIdx.x == 0) G[e / ny + (int64_t)(e % ny) * ldg] = s;
 }
 
 template <typename T>
@@ -145,18 +147,36 @@ void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int l
   const int nx = X1.cols + X2.cols, ny = Y.cols;
   if (nx == 0 || ny == 0) return;
   PHS_REQUIRE(nx <= 128 && ny <= 32, kEinval, "tn: operand too wide");
-  PHS_REQUIRE(((nx + 3) / 4) * ((ny + 3) / 4) <= 256, kEinval, "tn: too many tiles");
-  const int nblk = tn_blocks(Y.rows, nx * ny);
+  PHS_REQUIRE(X1.rows == Y.rows && (X2.cols == 0 || X2.rows == Y.rows), kEinval,
+              "tn: row counts differ");
+  PHS_REQUIRE(X2.cols == 0 || X2.rs == X1.rs, kEinval, "tn: X1, X2 layouts differ");
+  const int tiles = ((nx + kTnCX - 1) / kTnCX) * ((ny + kTnCY - 1) / kTnCY);
+  const int waves = tiles < kTnMaxWaves ? tiles : kTnMaxWaves;
+  const int64_t N = Y.rows, E = (int64_t)nx * ny;
+  // about 2048 waves in flight, slabs a multiple of 64 * kTnU rows, and the
+  // partials within their buffer
+  int64_t nblk = (2048 + waves - 1) / waves;
+  const int64_t unit = 64 * TnRows<T>::U;
+  int64_t rpb = ((N + nblk - 1) / nblk + unit - 1) / unit * unit;
+  if (rpb < unit) rpb = unit;
+  nblk = (N + rpb - 1) / rpb;
+  const int64_t cap = kPartCap / E;
+  if (nblk > cap) {
+    nblk = cap;
+    rpb = ((N + nblk - 1) / nblk + unit - 1) / unit * unit;
+    nblk = (N + rpb - 1) / rpb;
+  }
+  if (nblk < 1) nblk = 1;
   prof_begin(kProfTn, s);
-  int R = kTnRows;  // rows per LDS chunk, keeping the chunk within 64 KB
-  while (R > 8 && (size_t)R * (nx + ny) * sizeof(T) > 65536) R /= 2;
-  size_t lds = (size_t)R * (nx + ny) * sizeof(T);
-  if (lds < 256 * 16 * sizeof(double)) lds = 256 * 16 * sizeof(double);
-  k_tn<T><<<nblk, 256, lds, s>>>(tv(X1), tv(X2), tv(Y), R, sc.part);
-  k_reduce_parts<<<nx * ny, 64, 0, s>>>(sc.part, nblk, nx, ny, G, ldg);
+  k_tn<T><<<(int)nblk, 64 * waves, 0, s>>>(tv(X1), tv(X2), tv(Y), rpb, sc.part);
+  k_reduce_parts<<<(int)E, 64, 0, s>>>(sc.part, (int)nblk, nx, ny, G, ldg);
   PHS_CHECK_LAUNCH();
   prof_end(kProfTn, s, (double)Y.rows * (nx + ny) * sizeof(T));
 }
+
+// One wavefront per entry: lane l sums partials l, l+64, ... and the 64
+// lane sums are combined by the fixed DPP / lane order of wave_total.
+__device__ inline double wave_sum(double v) { return wave_total(v); }
 
 // ------------------------------------------------------------------ X S
 constexpr int kNnTile = 16;  // output columns per thread
