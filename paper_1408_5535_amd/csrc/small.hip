@@ -52,9 +52,9 @@ __device__ inline void rr_pair(int P, int r, int k, int &a, int &b) {
 
 // ---------------------------------------------------------- syev
 // Rayleigh-Ritz eigenproblem H s = theta s of the search space (p <= 64),
-// float64, one workgroup of four wavefronts.  Wave 0 runs the sequential
-// steps 1 and 3 (lane t owns row t of H in LDS); all four waves run the
-// multisection and the back-transformation.
+// float64, one workgroup of four wavefronts; lane t of each wave works on
+// row t of H in LDS.  Steps 1, 2 and 4 use all four waves, the inverse
+// iteration (step 3) runs on wave 0.
 //  1. Householder reduction H = Q T Q^T to tridiagonal T, last row first;
 //     the reflectors stay in the rows of H they annihilate.
 //  2. Selected eigenvalues of T by multisection of Sturm sequences: the
@@ -198,10 +198,11 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
   __shared__ double uu[kSmallMax * kLd];  // 1 / pivots of (T - lambda I) / ||T||
   __shared__ double ll[kPadRows * kLd];   // multipliers
   __shared__ double vv[kPadRows], pq[kPadRows], hh[kSmallMax], rh[kSmallMax];
+  __shared__ double pp[4 * kSmallMax];  // partial products of the four waves
   __shared__ double d[kSmallMax], e[kSmallMax + 1], ds[kPadRows], e2s[kPadRows], es1[kSmallMax];
   __shared__ double lamv[kSmallMax + 1];
   __shared__ int cstart[kSmallMax], tstart[kSmallMax];
-  // wave 0 runs steps 1 and 3; all four waves run steps 2 and 4
+  // wave 0 runs step 3; all four waves run steps 1, 2 and 4
   const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
   const bool w0 = w == 0;
   const int n = p;
@@ -223,8 +224,11 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
     }
   }
   __syncthreads();
-  // 1. reduction of row i onto position i - 1 (l = i - 1)
-  if (w0) {
+  // 1. reduction of row i onto position i - 1 (l = i - 1).  Every wave
+  //    forms the reflector from row i itself (identical values, so every
+  //    wave takes the same branches); the product A v and the rank-two
+  //    update are split into column blocks of 16, one per wave.
+  const int kb = 16 * w;  // this wave's column block
   for (int i = n - 1; i >= 2; --i) {
     const int l = i - 1;
     const double xi = (t <= l) ? a[i * kLd + t] : 0.0;
@@ -233,7 +237,7 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
     if (!(sigma > 1e-280 && sigma < 1e280)) {  // rare: scale by the 1-norm first
       scale = wave_total(fabs(xi));
       if (scale == 0.0) {
-        if (t == 0) e[i] = 0.0;
+        if (threadIdx.x == 0) e[i] = 0.0;
         continue;  // hh[i] stays 0: no reflector
       }
       sigma = wave_total((xi / scale) * (xi / scale));
@@ -245,61 +249,71 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
     const double h = sigma - f * g;
     const double ih = 1.0 / h;
     const double v = (t == l) ? f - g : xs;  // reflector I - v v^T / h; 0 past l
-    vv[t] = v;
-    if (t == 0) {
+    if (w0) vv[t] = v;
+    if (threadIdx.x == 0) {
       e[i] = scale * g;
       hh[i] = h;
       rh[i] = ih;
     }
-    wave_sync();
-    // p = A v / h over the leading (l+1) x (l+1) block (vv is 0 past l)
-    double pj = 0.0;
-    if (t <= l) {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      for (int k = 0; k <= l; k += 8) {
-        double av[8], vk[8];
+    __syncthreads();
+    // partial (A v)_t over this wave's column block (vv is 0 past l)
+    {
+      double s0 = 0.0, s1 = 0.0;
+      if (t <= l) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          av[u] = a[t * kLd + k + u];
-          vk[u] = vv[k + u];
+        for (int c8 = 0; c8 < 16; c8 += 8) {
+          if (kb + c8 > l) break;
+          double av[8], vk[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            av[u] = a[t * kLd + kb + c8 + u];
+            vk[u] = vv[kb + c8 + u];
+          }
+          s0 = fma(av[0], vk[0], s0); s1 = fma(av[1], vk[1], s1);
+          s0 = fma(av[2], vk[2], s0); s1 = fma(av[3], vk[3], s1);
+          s0 = fma(av[4], vk[4], s0); s1 = fma(av[5], vk[5], s1);
+          s0 = fma(av[6], vk[6], s0); s1 = fma(av[7], vk[7], s1);
         }
-        s0 = fma(av[0], vk[0], s0); s1 = fma(av[1], vk[1], s1);
-        s2 = fma(av[2], vk[2], s2); s3 = fma(av[3], vk[3], s3);
-        s0 = fma(av[4], vk[4], s0); s1 = fma(av[5], vk[5], s1);
-        s2 = fma(av[6], vk[6], s2); s3 = fma(av[7], vk[7], s3);
       }
-      pj = ((s0 + s1) + (s2 + s3)) * ih;
+      pp[w * kSmallMax + t] = s0 + s1;
     }
+    __syncthreads();
+    const double pj = (t <= l) ? ((pp[t] + pp[kSmallMax + t]) +
+                                  (pp[2 * kSmallMax + t] + pp[3 * kSmallMax + t])) * ih
+                               : 0.0;
     const double K = wave_total(v * pj) * (0.5 * ih);
     const double qj = (t <= l) ? pj - K * v : 0.0;
-    pq[t] = qj;
-    wave_sync();
+    if (w0) pq[t] = qj;
+    __syncthreads();
+    // rank-two update of this wave's column block; columns past l see
+    // q = v = 0 and stay unchanged
     if (t <= l) {
-      for (int k = 0; k <= l; k += 8) {
-        double qk[8], vk[8];
+#pragma unroll
+      for (int c8 = 0; c8 < 16; c8 += 8) {
+        if (kb + c8 > l) break;
+        double qk[8], vk[8], av[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          qk[u] = pq[k + u];
-          vk[u] = vv[k + u];
+          qk[u] = pq[kb + c8 + u];
+          vk[u] = vv[kb + c8 + u];
+          av[u] = a[t * kLd + kb + c8 + u];
         }
-        // columns past l (still inside row t) see q = v = 0: unchanged
-        double av[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) av[u] = a[t * kLd + k + u];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) a[t * kLd + k + u] = av[u] - (v * qk[u] + qj * vk[u]);
+        for (int u = 0; u < 8; ++u)
+          a[t * kLd + kb + c8 + u] = av[u] - (v * qk[u] + qj * vk[u]);
       }
-      a[i * kLd + t] = v;
+      if (w0) a[i * kLd + t] = v;
     }
-    wave_sync();
+    __syncthreads();
   }
-  if (t == 0) {
-    e[0] = 0.0;
-    e[n] = 0.0;
-    if (n >= 2) e[1] = a[1 * kLd + 0];
+  if (w0) {
+    if (t == 0) {
+      e[0] = 0.0;
+      e[n] = 0.0;
+      if (n >= 2) e[1] = a[1 * kLd + 0];
+    }
+    if (t < n) d[t] = a[t * kLd + t];
   }
-  if (t < n) d[t] = a[t * kLd + t];
-  }  // wave 0
   __syncthreads();
   // T scaled to unit norm (Gershgorin bound)
   double lo = 1e300, hi = -1e300;
