@@ -197,9 +197,12 @@ int phsvds_harvest(const phsvds_csr *A, int k, int every, int max_pairs, double 
                    int *count, phsvds_stats *stats);
 
 /* Kernel timing for benchmarks: HIP event pairs recorded on the launching
- * stream around each operation of a kind.  phsvds_profile(1) clears the
- * counters and starts recording, phsvds_profile(0) stops.  Kinds:
- * 0 float64 SpMM, 1 float32 SpMM, 2 tall X^T Y, 3 tall X S, 4 Ritz block.
+ * stream around each operation of a kind.  Kinds: 0 float64 SpMM,
+ * 1 float32 SpMM, 2 tall X^T Y, 3 tall X S, 4 Ritz block.
+ * phsvds_profile(enable) clears the counters and starts recording when
+ * enable != 0: enable = 1 records every kind, any other value is a bit mask
+ * of kinds shifted left by one (bit k+1 = kind k, e.g. 2 = float64 SpMM
+ * only); phsvds_profile(0) stops.
  * phsvds_profile_read returns the number of timed operations, their summed
  * device time (s) and their summed algorithmic HBM bytes.  Not thread-safe
  * against concurrent solves. */

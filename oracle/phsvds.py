@@ -32,7 +32,10 @@ Readings where the paper is silent (the same readings bind the GPU path):
     block are tested for convergence; in stage 1 a pair that passes the test
     on its recurrence residual W s - theta x is locked only if its explicit
     residual C x - theta x passes too (one product per candidate); otherwise
-    W = C V and H are recomputed to remove the drift of the restarts;
+    W = C V and H are recomputed to remove the drift of the restarts, at
+    most once in 10 iterations (in between, a failed check just means no
+    lock in that iteration: near the floor the two residuals differ by
+    rounding and could otherwise alternate for ever);
   * floor = 10 in the stage-1 test; a pair whose test is floor-limited, whose
     residual is within 10x of that floor and has not improved by 10% over
     the last L = max(100, 20 p_max / b) iterations is accepted as converged
@@ -225,6 +228,7 @@ def stage1_gdk(A, k, tol, b, pmax, pmin, X0, which="smallest", precond=None, ano
     it = 0
     converged = False
     pc_hist = []
+    last_rebuild = -(10**9)
     stats.fallback = False
     while True:
         it += 1
@@ -271,10 +275,15 @@ def stage1_gdk(A, k, tol, b, pmax, pmin, X0, which="smallest", precond=None, ano
             rt = np.linalg.norm(Rt, axis=0)
             ok = [i for q, i in enumerate(conv) if rt[q] < thr_of(i)]
             if len(ok) < len(conv):
-                W = Cop(V)
-                H = _sym(V.T @ W)
-                prev = None
-                continue
+                if it - last_rebuild > 10:
+                    W = Cop(V)
+                    H = _sym(V.T @ W)
+                    prev = None
+                    last_rebuild = it
+                    continue
+                # rebuilt within the last 10 iterations: the two residuals
+                # differ by rounding only, so iterate on without locking
+                conv = []
         if conv:
             hist = []
             pc_hist = []

@@ -93,9 +93,13 @@ _lib.phsvds_profile_read.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int64
 PROFILE_KINDS = {"spmm_f64": 0, "spmm_f32": 1, "tn": 2, "nn": 3, "ritz": 4}
 
 
-def profile(enable: bool) -> None:
-    """Start (clearing counters) or stop event timing of the library's kernels."""
-    _check(_lib.phsvds_profile(int(enable)), "profile")
+def profile(enable: bool, kinds=None) -> None:
+    """Start (clearing counters) or stop event timing of the library's
+    kernels; ``kinds`` (names or numbers) restricts the timed kinds."""
+    code = int(bool(enable))
+    if enable and kinds is not None:
+        code = sum(1 << ((PROFILE_KINDS[k] if isinstance(k, str) else k) + 1) for k in kinds)
+    _check(_lib.phsvds_profile(code), "profile")
 
 
 def profile_read(kind) -> tuple:

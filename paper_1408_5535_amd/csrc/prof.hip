@@ -21,6 +21,7 @@ struct Rec {
 struct Prof {
   std::mutex mu;
   bool on = false;
+  int mask = 0;  // kinds recorded (bit k = kind k)
   std::vector<hipEvent_t> pool;
   std::vector<Rec> live;
   hipEvent_t pending = nullptr;
@@ -59,7 +60,7 @@ void harvest() {
 bool prof_on() { return g.on; }
 
 void prof_begin(int kind, hipStream_t s) {
-  if (!g.on) return;
+  if (!g.on || !((g.mask >> kind) & 1)) return;
   std::lock_guard<std::mutex> lk(g.mu);
   g.pending = get_event();
   g.pending_kind = kind;
@@ -67,7 +68,7 @@ void prof_begin(int kind, hipStream_t s) {
 }
 
 void prof_end(int kind, hipStream_t s, double bytes) {
-  if (!g.on) return;
+  if (!g.on || !((g.mask >> kind) & 1)) return;
   std::lock_guard<std::mutex> lk(g.mu);
   if (!g.pending || g.pending_kind != kind) return;
   hipEvent_t e = get_event();
@@ -92,6 +93,7 @@ int phsvds_profile(int enable) {
       }
     }
     phs::g.on = enable != 0;
+    phs::g.mask = enable == 1 ? (1 << phs::kProfCount) - 1 : (enable >> 1);
     return PHSVDS_OK;
   } catch (const phs::Error &e) {
     return e.code;

@@ -211,6 +211,7 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
   std::vector<double> pc_hist;
   int pw = 0;                 // size of the warm-start eigenvector block
   int pend_nb = 0, pend_p = 0;  // unchecked expansion: width, basis size before
+  int64_t last_rebuild = -1000000;  // iteration of the last W = C V rebuild
 
   auto applyC = [&](T *X, int nb) {
     spmm(A, bw, X, bf.Yb, false, c.s);
@@ -386,7 +387,12 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
         double thr = std::max(P.tol * si * sn, floor_of(i));
         if (!(std::sqrt(std::max(rt[i], 0.0)) < thr)) all_ok = false;
       }
-      if (!all_ok) {
+      if (!all_ok && it - last_rebuild <= 10) {
+        // rebuilt within the last 10 iterations: the two residuals differ
+        // by rounding only, so iterate on without locking
+        conv.clear();
+      } else if (!all_ok) {
+        last_rebuild = it;
         for (int c0 = 0; c0 < p; c0 += bw) {
           int w = std::min(bw, p - c0);
           copy(cm(V[cur] + (int64_t)c0 * n, n, w, n), rmv(Tb, n, w, bw), c.s);

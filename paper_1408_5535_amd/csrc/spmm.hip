@@ -53,6 +53,12 @@ __device__ inline void store_row(T *__restrict__ p, const T (&o)[B]) {
 }
 
 // rows: optional list of row indices (a length bin); nullptr = all rows.
+// Each lane takes every G-th nonzero of its row, kSpU at a time: the column
+// indices and values of the kSpU nonzeros are loaded first, then their kSpU
+// X-row gathers are issued together, so a lane keeps several independent
+// gathers in flight instead of one dependent chain per nonzero.
+constexpr int kSpU = 4;
+
 template <typename T, int B, int G, bool ABS>
 __global__ __launch_bounds__(256) void k_spmm(int64_t nrows, const int32_t *__restrict__ rows,
                                               const int64_t *__restrict__ rp,
@@ -68,18 +74,30 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nrows, const int32_t *__re
 #pragma unroll
   for (int j = 0; j < B; ++j) acc[j] = T(0);
   const int64_t end = rp[row + 1];
-  for (int64_t p = rp[row] + lane; p < end; p += G) {
-    const int64_t c = ci[p];
-    T a = va[p];
-    T x[B];
-    load_row<T, B>(X + c * B, x);
-    if constexpr (ABS) {
-      a = fabs(a);
+  for (int64_t p0 = rp[row] + lane; p0 < end; p0 += (int64_t)G * kSpU) {
+    int64_t c[kSpU];
+    T a[kSpU];
 #pragma unroll
-      for (int j = 0; j < B; ++j) x[j] = fabs(x[j]);
+    for (int u = 0; u < kSpU; ++u) {
+      const int64_t p = p0 + (int64_t)u * G;
+      const bool in = p < end;
+      c[u] = in ? ci[p] : 0;
+      a[u] = in ? va[p] : T(0);  // zero weight for the padding slots
     }
+    T x[kSpU][B];
 #pragma unroll
-    for (int j = 0; j < B; ++j) acc[j] = fma(a, x[j], acc[j]);
+    for (int u = 0; u < kSpU; ++u) load_row<T, B>(X + c[u] * B, x[u]);
+#pragma unroll
+    for (int u = 0; u < kSpU; ++u) {
+      T au = a[u];
+      if constexpr (ABS) {
+        au = fabs(au);
+#pragma unroll
+        for (int j = 0; j < B; ++j) x[u][j] = fabs(x[u][j]);
+      }
+#pragma unroll
+      for (int j = 0; j < B; ++j) acc[j] = fma(au, x[u][j], acc[j]);
+    }
   }
   if constexpr (G > 1) {
 #pragma unroll
