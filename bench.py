@@ -41,11 +41,39 @@ def grid_workload(N):
 
 
 def spmm_source_hash():
-    h = hashlib.sha256()
-    for f in ("spmm.hip", "common.hpp", "kernels.hpp"):
-        with open(os.path.join(ROOT, "paper_1408_5535_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    """Hash of the SpMM kernel source: stored counter readings apply only to
+    the kernel they were taken on."""
+    with open(os.path.join(ROOT, "paper_1408_5535_amd", "csrc", "spmm.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def copy_calibration(mib=512, reps=5):
+    """A plain device copy of known size, for scaling rocprofv3 FETCH_SIZE /
+    WRITE_SIZE readings (each copy reads and writes mib MiB)."""
+    import torch
+    x = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_dispatch": x.numel() * 4, "reps": reps}))
+
+
+def summarize_pmc(path, kernel):
+    """Mean counter value per dispatch, grouped by kernel name, of the
+    kernels whose name contains `kernel` ("" for all), from a rocprofv3
+    --pmc counter_collection.csv."""
+    import csv
+    vals = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            name = row.get("Kernel_Name", "")
+            if kernel in name:
+                key = (name[:80], row["Counter_Name"])
+                vals.setdefault(key, []).append(float(row["Counter_Value"]))
+    for (name, ctr), v in sorted(vals.items()):
+        print(json.dumps({"kernel": name, "counter": ctr, "dispatches": len(v),
+                          "mean_per_dispatch": sum(v) / len(v)}))
 
 
 def traffic_from_profiles(workload):
@@ -102,7 +130,22 @@ def main():
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--block", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-largest", action="store_true",
+                    help="skip the k largest solve reported beside the metric")
+    ap.add_argument("--max-mv", type=int, default=0,
+                    help="cap the products with A (profiling runs only: a capped solve is "
+                         "not the metric and is flagged in the output)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a device copy of known size (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("CSV", "KERNEL"),
+                    help="only summarise a rocprofv3 counter_collection.csv for one kernel")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path "
               "is a design sketch, not built", file=sys.stderr)
@@ -117,13 +160,13 @@ def main():
     workload = (f"grid gradient N={args.N} (m={m}, n={n}, nnz={A.nnz}), k={k} smallest, "
                 f"block {b}, float64, tol 1e-12")
     Ad = P.DeviceCSR.from_scipy(A)
-    solver = P.Solver(Ad, k, block=b)
+    solver = P.Solver(Ad, k, block=b, max_matvecs=args.max_mv)
     for w in range(args.warmup):
         tw = time.perf_counter()
         solver.solve(1e-12)
         print(f"[bench] warmup {w} {time.perf_counter() - tw:.3f}s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    P.profile(True)
+    P.profile(True, kinds=["spmm_f64"])
     t0 = time.perf_counter()
     infos = []
     for st in range(args.steps):
@@ -171,6 +214,24 @@ def main():
                      "launches": int(launches), "avg_launch_us": avg * 1e6,
                      "algorithmic_bytes_per_launch": per_launch},
     }
+    if args.max_mv:
+        out["capped_profiling_run"] = True
+    if not args.no_largest:
+        # the same operator, k largest (stage 1 only), reported beside the metric
+        lsolver = P.Solver(Ad, k, block=b, which="largest", max_matvecs=args.max_mv)
+        torch.cuda.synchronize()
+        tl = time.perf_counter()
+        lsig, _, _, linfo = lsolver.solve(1e-12)
+        torch.cuda.synchronize()
+        tl = time.perf_counter() - tl
+        lex = exact[::-1][:k]
+        out["largest"] = {"seconds": tl, "status": int(linfo["status"]),
+                          "mv_total": int(linfo["mv_total"]),
+                          "matvecs_per_triplet": linfo["mv_total"] / k,
+                          "max_rel_sigma_err_vs_closed_form":
+                              float(np.max(np.abs(lsig - lex) / lex)),
+                          "max_residual_over_norm": float(np.max(linfo["res"]) / anorm)}
+        print(f"[bench] largest done in {tl:.3f}s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, k, b, anorm, info["mv_total"])
     print(json.dumps(out), flush=True)
