@@ -156,7 +156,9 @@ int phsvds_svds(const phsvds_csr *A, int k, double tol, const phsvds_precond *P,
  *   h0_j = [rh_j, rh_j / max(d_j - tau, d_j/10), d_j, tau],
  *          rh = r sqrt(n)/||r||, d = diag(C)/mean diag(C), tau = theta/mean diag(C)
  *   h^l = relu(h^{l-1} Ws_l + b_l + Ch (h^{l-1} Wm_l)), Ch = D^-1/2 A^T A D^-1/2
- *   t   = (I - x x^T) (h^3 wo) ||r|| / (sqrt(n) mean diag(C))
+ *   t   = (I - x x^T) (h^3 wo + h0_1) ||r|| / (sqrt(n) mean diag(C))
+ * where h0_1, the second input feature, is the Jacobi step in these units:
+ * the network learns a correction to the Jacobi preconditioner.
  * Weights: one float32 array, row-major blocks in the order
  * Ws1, Wm1 (4 x w), b1 (w), Ws2, Wm2 (w x w), b2, Ws3, Wm3, b3, wo (w).
  * A per-matrix workspace `gws` (phsvds_gnn_workspace_bytes) holds the

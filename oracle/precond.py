@@ -17,7 +17,9 @@ Network (width w, three layers):
     h0_j  = [rh_j, rh_j / max(d_j - tau, d_j / 10), d_j, tau]
     h^l   = relu(h^{l-1} Ws_l + b_l + Ch (h^{l-1} Wm_l)),  l = 1..3
     Ch    = D^-1/2 A^T A D^-1/2  (applied as two sparse products)
-    t~    = (h^3 wo) ||r|| / (sqrt(n) mean(diag C))
+    t~    = (h^3 wo + h0[:, 1]) ||r|| / (sqrt(n) mean(diag C))
+            (h0[:, 1] is the Jacobi step in these units: the network learns
+            a correction to the Jacobi preconditioner)
     t     = (I - x x^T) t~
 Loss of one sample: ||t - t*||^2 / ||t*||^2 (t* is orthogonal to x).
 Optimiser: Adam (Kingma & Ba), lr 1e-3, beta1 0.9, beta2 0.999, eps 1e-8.
@@ -95,7 +97,7 @@ def forward(g: Graph, P, r, x, theta):
         pres.append(pre)
         hs.append(h)
     scale = nr / (math.sqrt(n) * g.dmean)
-    traw = (h @ P["wo"]) * scale
+    traw = (h @ P["wo"] + h0[:, 1]) * scale
     t = traw - x * (x @ traw)
     return t, {"hs": hs, "pres": pres, "scale": scale}
 

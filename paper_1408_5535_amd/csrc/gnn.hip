@@ -6,7 +6,9 @@
 //          rh = r sqrt(n)/||r||, d = diag(C)/mean(diag C), tau = theta/mean(diag C)
 //   pre^l = h^{l-1} Ws_l + b_l + Ch (h^{l-1} Wm_l),  h^l = relu(pre^l)
 //   Ch    = D^-1/2 A^T A D^-1/2 (two float32 SpMMs of width w)
-//   t     = (I - x x^T) (h^3 wo) ||r|| / (sqrt(n) mean(diag C))
+//   t     = (I - x x^T) (h^3 wo + h0_1) ||r|| / (sqrt(n) mean(diag C))
+// (h0_1 is the Jacobi step r / max(diag C - theta, diag C / 10) in these
+// units, so the network learns a correction to the Jacobi preconditioner).
 // The node-wise dense layers run one thread per node with the weights in
 // LDS; aggregation reuses the row-major SpMM kernels at width w.
 #include <hip/hip_runtime.h>
@@ -199,13 +201,14 @@ __global__ void k_gnn_combine(const float *S, const float *Z, const float *isd, 
   }
 }
 
-// traw_i = (h3_i . wo) * scale, scale = ||r|| / (sqrt(n) mean(diag C))
-__global__ void k_gnn_readout(const float *h, int64_t n, int w, const float *wo,
-                              const double *nr2, const double *meta, float *traw) {
+// traw_i = (h3_i . wo + h0_i1) * scale, scale = ||r|| / (sqrt(n) mean(diag C))
+__global__ void k_gnn_readout(const float *h, const float *h0, int64_t n, int w,
+                              const float *wo, const double *nr2, const double *meta,
+                              float *traw) {
   const double scale = sqrt(fmax(nr2[0], 0.0)) / (sqrt((double)n) * meta[0]);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    float s = 0.f;
+    float s = h0[i * kGnnIn + 1];
     for (int c = 0; c < w; ++c) s = fmaf(h[i * w + c], wo[c], s);
     traw[i] = (float)(s * scale);
   }
@@ -343,7 +346,8 @@ void gnn_forward(const phsvds_csr &A, const GnnGraph &g, GnnBufs &b, const float
     hin = b.h[l];
     fin = w;
   }
-  k_gnn_readout<<<grid_for(n), 256, 0, s>>>(b.h[2], n, w, wts + o.wo, b.vec, g.meta, b.traw);
+  k_gnn_readout<<<grid_for(n), 256, 0, s>>>(b.h[2], b.h0, n, w, wts + o.wo, b.vec, g.meta,
+                                            b.traw);
   // t = traw - x (x^T traw)
   tn(cm(const_cast<float *>(x), n, 1, n), cm<float>(nullptr, n, 0, n), cm(b.traw, n, 1, n),
      b.vec + 1, 1, b.sc, s);

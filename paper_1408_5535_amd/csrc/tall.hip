@@ -72,16 +72,17 @@ __global__ __launch_bounds__(64 * kTnMaxWaves) void k_tn(TV<T> x1, TV<T> x2, TV<
   const int64_t N = y.rows;
   const int64_t r0 = (int64_t)blockIdx.x * rpb;
   const int64_t r1 = r0 + rpb < N ? r0 + rpb : N;
-  const int64_t xrs = x1.rs;  // the host checks x2.rs == x1.rs
   for (int tile = w; tile < ntile; tile += nw) {
     const int i0 = (tile / ty) * kTnCX, j0 = (tile % ty) * kTnCY;
     // column bases (uniform); columns past the operand read as zero
     const T *xp[kTnCX];
+    bool in1[kTnCX];  // column from x1 (else x2): selects the row stride
 #pragma unroll
     for (int a = 0; a < kTnCX; ++a) {
       const int i = i0 + a;
-      xp[a] = i < x1.cols ? x1.p + (int64_t)i * x1.cs
-                          : x2.p + (int64_t)(i < nx ? i - x1.cols : 0) * x2.cs;
+      in1[a] = i < x1.cols;
+      xp[a] = in1[a] ? x1.p + (int64_t)i * x1.cs
+                     : x2.p + (int64_t)(i < nx ? i - x1.cols : 0) * x2.cs;
     }
     const T *yp[kTnCY];
 #pragma unroll
@@ -97,9 +98,10 @@ __global__ __launch_bounds__(64 * kTnMaxWaves) void k_tn(TV<T> x1, TV<T> x2, TV<
       for (int u = 0; u < U; ++u) {
         const int64_t r = rb + (int64_t)u * 64;
         const bool in = r < r1;
-        const int64_t ox = r * xrs, oy = r * y.rs;
+        const int64_t o1 = r * x1.rs, o2 = r * x2.rs, oy = r * y.rs;
 #pragma unroll
-        for (int a = 0; a < kTnCX; ++a) xr[u][a] = (in && i0 + a < nx) ? xp[a][ox] : T(0);
+        for (int a = 0; a < kTnCX; ++a)
+          xr[u][a] = (in && i0 + a < nx) ? xp[a][in1[a] ? o1 : o2] : T(0);
 #pragma unroll
         for (int c = 0; c < kTnCY; ++c) yr[u][c] = (in && j0 + c < ny) ? yp[c][oy] : T(0);
       }
@@ -149,7 +151,6 @@ void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int l
   PHS_REQUIRE(nx <= 128 && ny <= 32, kEinval, "tn: operand too wide");
   PHS_REQUIRE(X1.rows == Y.rows && (X2.cols == 0 || X2.rows == Y.rows), kEinval,
               "tn: row counts differ");
-  PHS_REQUIRE(X2.cols == 0 || X2.rs == X1.rs, kEinval, "tn: X1, X2 layouts differ");
   const int tiles = ((nx + kTnCX - 1) / kTnCX) * ((ny + kTnCY - 1) / kTnCY);
   const int waves = tiles < kTnMaxWaves ? tiles : kTnMaxWaves;
   const int64_t N = Y.rows, E = (int64_t)nx * ny;
