@@ -185,18 +185,20 @@ int phsvds_gnn_adam(float *w, float *m, float *v, const double *grad, int64_t nw
 
 /* Training pairs from a float64 stage-1 run on A (k smallest, opts->block):
  * every `every` iterations, each targeted Ritz pair (theta, x) with residual
- * r gets the exact correction t of (I-QQ^T)(C - theta I)(I-QQ^T) t = -r,
- * t orthogonal to Q = [locked vectors, Ritz block], by projected CG
- * (relative tolerance cg_tol, at most cg_maxit steps); pairs with
- * non-positive curvature or no convergence are skipped.  Outputs (device,
- * n x max_pairs column-major): R, X, T; theta (host, max_pairs); *count
- * pairs written.  Stage 1 stops at tolerance `tol`. */
+ * r gets the exact correction t of
+ *   (I-QQ^T)(C - rho theta I)(I-QQ^T) t = -r,  t orthogonal to Q,
+ * Q = [locked vectors, Ritz block], by projected CG (relative tolerance
+ * cg_tol, at most cg_maxit steps); pairs with non-positive curvature or no
+ * convergence are skipped.  rho = shift_scale in [0, 1]: 1 is the
+ * Jacobi-Davidson correction equation, 0 the projected C^-1 r.  Outputs
+ * (device, n x max_pairs column-major): R, X, T; theta (host, max_pairs, the
+ * Ritz values); *count pairs written.  Stage 1 stops at tolerance `tol`. */
 int phsvds_harvest_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int k,
                                    const phsvds_opts *opts, size_t *bytes);
 int phsvds_harvest(const phsvds_csr *A, int k, int every, int max_pairs, double tol,
-                   double cg_tol, int cg_maxit, const phsvds_opts *opts, void *workspace,
-                   size_t ws_bytes, void *stream, double *R, double *X, double *T, double *theta,
-                   int *count, phsvds_stats *stats);
+                   double cg_tol, int cg_maxit, double shift_scale, const phsvds_opts *opts,
+                   void *workspace, size_t ws_bytes, void *stream, double *R, double *X,
+                   double *T, double *theta, int *count, phsvds_stats *stats);
 
 /* Kernel timing for benchmarks: HIP event pairs recorded on the launching
  * stream around each operation of a kind.  Kinds: 0 float64 SpMM,

@@ -622,13 +622,16 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
 
 
 def harvest(A, k, b, every=5, max_pairs=64, tol=1e-8, seed=2, cg_tol=1e-8, cg_maxit=2000,
-            max_iters=None):
+            max_iters=None, shift_scale=1.0):
     """Training pairs for the learned preconditioner from a stage-1 run:
-    every ``every`` iterations, each unconverged targeted Ritz pair
-    (theta_i, x_i) with residual r_i gives the exact correction t* of
-    (I-QQ^T)(C - theta_i I)(I-QQ^T) t = -r_i, t orthogonal to
-    Q = [X_lock, x_1..x_i] (projected CG).  Pairs whose CG meets
-    non-positive curvature or does not converge are dropped."""
+    every ``every`` iterations, each targeted Ritz pair (theta_i, x_i) with
+    residual r_i gives the exact correction t* of
+    (I-QQ^T)(C - rho theta_i I)(I-QQ^T) t = -r_i, t orthogonal to
+    Q = [X_lock, Ritz block] (projected CG), rho = shift_scale (1: the
+    Jacobi-Davidson correction equation, 0: the projected C^-1 r).  Pairs
+    whose CG meets non-positive curvature or does not converge are dropped.
+    Returns (r, x, theta, t*, Q) per pair.  Parity unpinned beyond the
+    equation itself (which pairs are taken depends on the iteration path)."""
     import workloads
     from . import precond as pcmod
     n = A.shape[1]
@@ -642,10 +645,11 @@ def harvest(A, k, b, every=5, max_pairs=64, tol=1e-8, seed=2, cg_tol=1e-8, cg_ma
         for i in range(X.shape[1]):
             if len(out) >= max_pairs:
                 return
-            Q = np.column_stack([Xl, X[:, :i + 1]])
-            t, its, ok = pcmod.projected_cg(A, float(theta[i]), Q, R[:, i], cg_tol, cg_maxit)
+            Q = np.column_stack([Xl, X])
+            t, its, ok = pcmod.projected_cg(A, shift_scale * float(theta[i]), Q, R[:, i], cg_tol,
+                                            cg_maxit)
             if ok:
-                out.append((R[:, i].copy(), X[:, i].copy(), float(theta[i]), t))
+                out.append((R[:, i].copy(), X[:, i].copy(), float(theta[i]), t, Q))
 
     stage1_gdk(A, k, tol, b, pmax, pmin, X0, callback=cb, max_iters=max_iters)
     return out

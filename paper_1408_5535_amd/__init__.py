@@ -297,7 +297,7 @@ _lib.phsvds_harvest_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, 
                                                 ctypes.c_int, ctypes.POINTER(_Opts),
                                                 ctypes.POINTER(ctypes.c_size_t)]
 _lib.phsvds_harvest.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                 ctypes.POINTER(_Opts), _P, ctypes.c_size_t, _P, _P, _P, _P,
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(_Stats)]
@@ -362,9 +362,11 @@ def gnn_adam(w, m, v, grad, step, lr=1e-3, grad_scale=1.0):
 
 
 def harvest(A: DeviceCSR, k: int, block: int = 4, every: int = 5, max_pairs: int = 64,
-            tol: float = 1e-8, cg_tol: float = 1e-8, cg_maxit: int = 2000, **opt_kw):
-    """(R, X, T, theta) training pairs from a float64 stage-1 run (columns of
-    n x count float64 device tensors)."""
+            tol: float = 1e-8, cg_tol: float = 1e-8, cg_maxit: int = 2000,
+            shift_scale: float = 1.0, **opt_kw):
+    """(R, X, T, theta) training pairs from a float64 stage-1 run (rows of
+    count x n float64 device tensors); T solves the projected equation with
+    C - shift_scale * theta I."""
     import numpy as np
     opts = make_opts(block=block, **opt_kw)
     nb = ctypes.c_size_t(0)
@@ -380,7 +382,7 @@ def harvest(A: DeviceCSR, k: int, block: int = 4, every: int = 5, max_pairs: int
     st = _Stats()
     c = A._c()
     _check(_lib.phsvds_harvest(ctypes.byref(c), k, every, max_pairs, tol, cg_tol, cg_maxit,
-                               ctypes.byref(opts), ws.data_ptr(), ws.numel(), _stream(),
+                               shift_scale, ctypes.byref(opts), ws.data_ptr(), ws.numel(), _stream(),
                                R.data_ptr(), X.data_ptr(), T.data_ptr(), th, ctypes.byref(cnt),
                                ctypes.byref(st)), "harvest")
     n = cnt.value

@@ -553,7 +553,8 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
 
 
 int harvest_impl(const phsvds_csr *Ain, int k, int every, int max_pairs, double tol,
-                 double cg_tol, int cg_maxit, const phsvds_opts *oin, void *ws, size_t ws_bytes,
+                 double cg_tol, int cg_maxit, double shift_scale, const phsvds_opts *oin,
+                 void *ws, size_t ws_bytes,
                  void *stream, double *Rout, double *Xout, double *Tout, double *theta_out,
                  int *count_out, phsvds_stats *stats) {
   PHS_REQUIRE(Ain && Rout && Xout && Tout && theta_out && count_out, kEinval, "null argument");
@@ -563,6 +564,7 @@ int harvest_impl(const phsvds_csr *Ain, int k, int every, int max_pairs, double 
   o.stage1_fp32 = 0;
   const int64_t m = Ain->m, n = Ain->n, nnz = Ain->nnz;
   PHS_REQUIRE(m >= n && n >= 1 && every >= 1 && max_pairs >= 0, kEinval, "bad harvest sizes");
+  PHS_REQUIRE(shift_scale >= 0.0 && shift_scale <= 1.0, kEinval, "shift_scale must be in [0, 1]");
   Dims d;
   PHS_REQUIRE(make_dims(m, n, nnz, k, o, d), kEinval, "unsupported sizes");
   d.cg = true;
@@ -603,8 +605,8 @@ int harvest_impl(const phsvds_csr *Ain, int k, int every, int max_pairs, double 
                 const void *Xl, int nl) {
     if (it % every || count >= max_pairs) return;
     std::vector<int> ok = projected_cg_block(c, A64, At64, (const double *)Xl, nl,
-                                             (const double *)Xb, nb, d.bw, th, (const double *)Rb,
-                                             cg_tol, cg_maxit, pl.cg, sp);
+                                             (const double *)Xb, nb, d.bw, th, shift_scale,
+                                             (const double *)Rb, cg_tol, cg_maxit, pl.cg, sp);
     for (int j = 0; j < nb && count < max_pairs; ++j) {
       if (!ok[j]) continue;
       Tall<double> src;
@@ -749,12 +751,12 @@ int phsvds_harvest_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int k,
 }
 
 int phsvds_harvest(const phsvds_csr *A, int k, int every, int max_pairs, double tol,
-                   double cg_tol, int cg_maxit, const phsvds_opts *opts, void *workspace,
-                   size_t ws_bytes, void *stream, double *R, double *X, double *T, double *theta,
-                   int *count, phsvds_stats *stats) {
+                   double cg_tol, int cg_maxit, double shift_scale, const phsvds_opts *opts,
+                   void *workspace, size_t ws_bytes, void *stream, double *R, double *X,
+                   double *T, double *theta, int *count, phsvds_stats *stats) {
   return guarded([&]() {
-    return harvest_impl(A, k, every, max_pairs, tol, cg_tol, cg_maxit, opts, workspace, ws_bytes,
-                        stream, R, X, T, theta, count, stats);
+    return harvest_impl(A, k, every, max_pairs, tol, cg_tol, cg_maxit, shift_scale, opts,
+                        workspace, ws_bytes, stream, R, X, T, theta, count, stats);
   });
 }
 

@@ -1,7 +1,7 @@
 // Harvest of training pairs for the learned preconditioner: stage-1 Ritz
 // blocks are snapshotted and their exact corrections computed by a batched
 // projected conjugate-gradient solve of
-//   (I - Q Q^T)(C - theta_j I)(I - Q Q^T) t_j = -r_j,  t_j orthogonal to Q,
+//   (I - Q Q^T)(C - rho theta_j I)(I - Q Q^T) t_j = -r_j,  t_j orthogonal to Q,
 // Q = [X_lock, X_block], one column per Ritz pair with its own theta_j.
 #include <hip/hip_runtime.h>
 
@@ -93,7 +93,8 @@ void carve_cg(Arena &ar, int64_t m, int64_t n, int bw, CgBufs &cb) {
 
 std::vector<int> projected_cg_block(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
                                     const double *Xl, int nl, const double *Xb, int nb, int bw,
-                                    const double *theta, const double *R, double tol, int maxit,
+                                    const double *theta, double shift_scale, const double *R,
+                                    double tol, int maxit,
                                     CgBufs &cb, SmallPool &sp) {
   const int64_t n = A.n;
   const int ld = kSP;
@@ -110,7 +111,7 @@ std::vector<int> projected_cg_block(Ctx &c, const SpMat<double> &A, const SpMat<
   };
   {
     std::vector<double> dn((size_t)kSP * nb, 0.0), mo(nb, -1.0);
-    for (int j = 0; j < nb; ++j) dn[j + (size_t)j * kSP] = -theta[j];
+    for (int j = 0; j < nb; ++j) dn[j + (size_t)j * kSP] = -shift_scale * theta[j];
     c.h2d(Dn, dn.data(), dn.size() * sizeof(double));
     c.h2d(ones, mo.data(), nb * sizeof(double));
     std::vector<int> a(64, 0);

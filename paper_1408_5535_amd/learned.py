@@ -6,9 +6,13 @@ C = A^T A to an approximate correction for (C - theta I), a preconditioner of
 the kind Section 4 admits.  The pipeline runs on the GPU through the C ABI:
 
   harvest   float64 stage-1 runs on the training matrices; every few
-            iterations each targeted pair gets the exact correction of the
-            projected correction equation by conjugate gradients
-            (phsvds_harvest);
+            iterations each targeted pair gets the exact solution of the
+            projected equation (C - rho theta I) t = -r by conjugate
+            gradients (phsvds_harvest).  The default rho = 0 (projected
+            C^-1 r) gives targets a local network can approximate; with
+            rho = 1 (the Jacobi-Davidson equation) the targets are dominated
+            by the next eigenvectors, which three hops of message passing
+            cannot represent;
   train     Adam on the mean loss ||t - t*||^2 / ||t*||^2 over mini-batches
             of harvested pairs, forward and backward by the library's
             kernels (phsvds_gnn_loss_grad, phsvds_gnn_adam);
@@ -45,7 +49,7 @@ def random12(seed: int, m: int = 300_000, n: int = 200_000):
 
 
 def harvest_family(seeds, make, k=10, block=4, every=25, max_pairs=48, tol=1e-10,
-                   cg_tol=1e-6, cg_maxit=1000, width=32):
+                   cg_tol=1e-6, cg_maxit=1000, width=32, shift_scale=0.0):
     """Device matrices, prepared graphs and float32 training pairs
     (graph index, r, x, theta, t*) from stage-1 runs on each matrix."""
     mats, graphs, pairs = [], [], []
@@ -53,7 +57,7 @@ def harvest_family(seeds, make, k=10, block=4, every=25, max_pairs=48, tol=1e-10
         t0 = time.time()
         A = DeviceCSR.from_scipy(make(seed))
         R, X, T, th, st = harvest(A, k, block=block, every=every, max_pairs=max_pairs, tol=tol,
-                                  cg_tol=cg_tol, cg_maxit=cg_maxit)
+                                  cg_tol=cg_tol, cg_maxit=cg_maxit, shift_scale=shift_scale)
         g = GnnGraph(A, width)
         mats.append(A)
         graphs.append(g)
@@ -112,6 +116,8 @@ def main(argv=None):
     ap.add_argument("--max-pairs", type=int, default=48)
     ap.add_argument("--out", default="")
     ap.add_argument("--weights", default="", help="evaluate these weights, skip training")
+    ap.add_argument("--shift-scale", type=float, default=0.0,
+                    help="rho of the harvested equation (C - rho theta I) t = -r")
     args = ap.parse_args(argv)
 
     def make(seed):
@@ -122,7 +128,8 @@ def main(argv=None):
         hist = []
     else:
         mats, graphs, pairs = harvest_family(range(*args.train_seeds), make, every=args.every,
-                                             max_pairs=args.max_pairs, width=args.width)
+                                             max_pairs=args.max_pairs, width=args.width,
+                                             shift_scale=args.shift_scale)
         w, hist = train(graphs, pairs, width=args.width, epochs=args.epochs)
         del mats, graphs, pairs
         torch.cuda.empty_cache()

@@ -86,22 +86,24 @@ def test_gnn_adam_matches_oracle():
 
 
 @gpu
-def test_harvest_pairs_solve_correction_equation():
+@pytest.mark.parametrize("rho", [1.0, 0.0])
+def test_harvest_pairs_solve_correction_equation(rho):
     """k = 1, block 1: until the pair locks, Q = [x] exactly, so every pair
-    must satisfy (I - x x^T)((C - theta) t + r) = 0 with t orthogonal to x."""
+    must satisfy (I - x x^T)((C - rho theta) t + r) = 0 with t orthogonal
+    to x."""
     need_gpu()
     import paper_1408_5535_amd as P
     A = wl.random_sparse(3000, 2000, 12, seed=1000)
-    say("harvest 3000x2000 k=1 b=1")
+    say("harvest 3000x2000 k=1 b=1 rho", rho)
     R, X, T, th, info = P.harvest(to_dev(A), 1, block=1, every=1, max_pairs=6, tol=1e-12,
-                                  cg_tol=1e-10)
+                                  cg_tol=1e-10, shift_scale=rho)
     say("pairs", len(th), info["mv_prec"])
     assert len(th) >= 4
     R, X, T = as_np(R), as_np(X), as_np(T)
     for i in range(len(th)):
         r, x, t = R[i], X[i], T[i]
         assert abs(np.linalg.norm(x) - 1) < 1e-12
-        v = A.T @ (A @ t) - th[i] * t + r
+        v = A.T @ (A @ t) - rho * th[i] * t + r
         v -= x * (x @ v)
         assert abs(x @ t) < 1e-10 * np.linalg.norm(t)
         assert np.linalg.norm(v) < 1e-8 * np.linalg.norm(r)

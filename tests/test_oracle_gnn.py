@@ -101,14 +101,16 @@ def test_projected_cg_matches_dense_solve():
     assert abs(x @ t) < 1e-12 * np.linalg.norm(t)
 
 
-def test_harvest_pairs_solve_their_correction_equation():
+@pytest.mark.parametrize("rho", [1.0, 0.0])
+def test_harvest_pairs_solve_their_correction_equation(rho):
+    """(I-QQ^T)((C - rho theta I) t + r) = 0 and Q^T t = 0 for every pair."""
     A = wl.random_sparse(300, 200, 8, seed=2000)
-    pairs = ph.harvest(A, 4, 2, every=3, max_pairs=6, max_iters=30)
+    pairs = ph.harvest(A, 4, 2, every=3, max_pairs=6, max_iters=30, shift_scale=rho)
     assert len(pairs) >= 3
-    for r, x, th, t in pairs:
-        v = (A.T @ (A @ t) - th * t) + r
-        v -= x * (x @ v)
-        assert abs(x @ t) < 1e-10 * np.linalg.norm(t)
+    for r, x, th, t, Q in pairs:
+        v = (A.T @ (A @ t) - rho * th * t) + r
+        v -= Q @ (Q.T @ v)
+        assert np.max(np.abs(Q.T @ t)) < 1e-10 * np.linalg.norm(t)
         assert np.linalg.norm(v) < 1e-6 * np.linalg.norm(r)
 
 
