@@ -53,14 +53,15 @@ typedef struct {
  * (Olsen form), its B-form [M A^T g; A M f] in stage 2 (Section 4).
  * GNN: the learned message-passing network given by `gnn_weights`
  * (layout below, phsvds_gnn_nweights floats), stage 1 only, with Jacobi as
- * the fallback when the leading residual stops halving within 25
- * iterations. */
+ * the fallback when the leading residual stops halving within
+ * fallback_window iterations. */
 enum { PHSVDS_PREC_NONE = 0, PHSVDS_PREC_JACOBI = 1, PHSVDS_PREC_GNN = 2 };
 
 typedef struct {
   int kind;
   const float *gnn_weights; /* device, phsvds_gnn_nweights() floats, or NULL */
   int gnn_width;            /* hidden width of the network (e.g. 32) */
+  int fallback_window;      /* GNN safeguard window in iterations (0: 25; -1: never) */
 } phsvds_precond;
 
 typedef struct {

@@ -38,7 +38,7 @@ class _Csr(ctypes.Structure):
 
 class _Precond(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("gnn_weights", ctypes.c_void_p),
-                ("gnn_width", ctypes.c_int)]
+                ("gnn_width", ctypes.c_int), ("fallback_window", ctypes.c_int)]
 
 
 class _Opts(ctypes.Structure):
@@ -249,14 +249,15 @@ class Solver:
         self.U = torch.empty((k, A.m), dtype=torch.float64, device=A.rowptr.device)
         self.V = torch.empty((k, A.n), dtype=torch.float64, device=A.rowptr.device)
 
-    def solve(self, tol=1e-12, precond="none", gnn_weights=None, gnn_width=32):
+    def solve(self, tol=1e-12, precond="none", gnn_weights=None, gnn_width=32,
+              fallback_window=0):
         import numpy as np
         k = self.k
         sig = (ctypes.c_double * k)()
         res = (ctypes.c_double * k)()
         st = _Stats()
         pc = _Precond(PREC[precond], gnn_weights.data_ptr() if gnn_weights is not None else None,
-                      gnn_width)
+                      gnn_width, fallback_window)
         c = self.A._c()
         rc = _lib.phsvds_svds(ctypes.byref(c), k, tol, ctypes.byref(pc), ctypes.byref(self.opts),
                               self.ws.data_ptr(), self.ws.numel(), _stream(), sig,

@@ -243,6 +243,7 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
     PHS_REQUIRE(o.gnn_width == Pc->gnn_width, kEinval,
                 "opts.gnn_width must equal the preconditioner's width (workspace sizing)");
   }
+  const int gwin = (Pc && Pc->fallback_window != 0) ? Pc->fallback_window : 25;
   const bool largest = o.which == 1;
   Arena ar;
   ar.base = (char *)ws;
@@ -336,6 +337,7 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   };
   if (d.fp32) {
     if (d.gw && pkind == PHSVDS_PREC_GNN) P1.gnn = gnn32;
+    P1.gnn_window = gwin;
     r1 = run_stage1<float>(c, A32, At32, P1, pl.s32, sp);
     stl.fp32_locked = r1.nl;
     stl.iters1 += r1.iters;
@@ -367,6 +369,7 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
     }
   } else {
     if (d.gw && pkind == PHSVDS_PREC_GNN) P1.gnn = gnn64;
+    P1.gnn_window = gwin;
     r1 = run_stage1<double>(c, A64, At64, P1, pl.s64, sp);
     Xl64 = pl.s64.Xl;
     Vr64 = (const double *)r1.Vrest;

@@ -327,11 +327,11 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     const double sn = std::sqrt(res.sn2);
     const int need = k - nl;
     if (P.snap) P.snap(it, bf.Xb, Rb, th_h, nb, bf.Xl, nl);
-    if (P.gnn && !gnn_off) {
+    if (P.gnn && !gnn_off && P.gnn_window > 0) {
       // safeguard of the learned preconditioner: fall back to Jacobi when the
       // leading residual has not halved within a window of iterations
       pc_hist.push_back(std::sqrt(std::max(rn_h[0], 0.0)));
-      const int Lf = 25;
+      const int Lf = P.gnn_window;
       if ((int)pc_hist.size() >= 2 * Lf) {
         double a = *std::min_element(pc_hist.end() - Lf, pc_hist.end());
         double bprev = *std::min_element(pc_hist.end() - 2 * Lf, pc_hist.end() - Lf);

@@ -59,6 +59,7 @@ struct Stage1Params {
   // learned preconditioner: called per column (r, x, theta, t), all length n
   // in working precision; null when not used
   std::function<void(const void *, const void *, double, void *)> gnn;
+  int gnn_window = 25;  // safeguard window (iterations); <= 0: never fall back
 };
 
 template <typename T>

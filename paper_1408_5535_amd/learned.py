@@ -79,7 +79,8 @@ def train(graphs, pairs, width=32, epochs=30, lr=1e-3, batch=16, seed=0):
     return w, hist
 
 
-def evaluate(seeds, make, w, width=32, k=10, block=4, tol=1e-12, max_matvecs=200_000):
+def evaluate(seeds, make, w, width=32, k=10, block=4, tol=1e-12, max_matvecs=200_000,
+             fallback_window=0):
     """Per held-out matrix: (method, products with A, seconds, status,
     largest residual / ||A||, fallbacks) for none, Jacobi and the network."""
     rows = []
@@ -92,7 +93,7 @@ def evaluate(seeds, make, w, width=32, k=10, block=4, tol=1e-12, max_matvecs=200
             t0 = time.perf_counter()
             sig, U, V, info = s.solve(tol, precond=method,
                                       gnn_weights=w if method == "gnn" else None,
-                                      gnn_width=width)
+                                      gnn_width=width, fallback_window=fallback_window)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             row = {"seed": seed, "method": method, "mv": int(info["mv_total"]),
