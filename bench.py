@@ -76,6 +76,26 @@ def summarize_pmc(path, kernel):
                           "mean_per_dispatch": sum(v) / len(v)}))
 
 
+def spmm_probe(kind, N):
+    """Three float64 SpMM launches on one matrix (rocprofv3 counter runs)."""
+    import torch
+    import paper_1408_5535_amd as P
+    import workloads as wl
+    if kind == "grid":
+        A, b = wl.grid_gradient(N), 4
+    elif kind == "random":
+        A, b = wl.random_sparse(300_000, 200_000, 12, seed=2000), 4
+    else:
+        A, b = wl.powerlaw_sparse(), 8
+    Ad = P.DeviceCSR.from_scipy(A)
+    X = torch.randn(A.shape[1], b, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        P.spmm(Ad, X)
+    torch.cuda.synchronize()
+    print(json.dumps({"spmm_probe": kind, "m": A.shape[0], "n": A.shape[1], "nnz": int(A.nnz),
+                      "b": b}), flush=True)
+
+
 def traffic_from_profiles(workload):
     """HBM bytes per SpMM launch from committed rocprofv3 counter runs, if they
     were taken on the current SpMM source; else None."""
@@ -139,7 +159,14 @@ def main():
                     help="only run a device copy of known size (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("CSV", "KERNEL"),
                     help="only summarise a rocprofv3 counter_collection.csv for one kernel")
+    ap.add_argument("--spmm-probe", choices=["grid", "random", "powerlaw"],
+                    help="only run three float64 A X products on a workload of that family "
+                         "(random: 300000 x 200000, 12 per row, b=4; powerlaw: 4M x 3M, b=8; "
+                         "grid: --N, b=4), for counter runs")
     args = ap.parse_args()
+    if args.spmm_probe:
+        spmm_probe(args.spmm_probe, args.N)
+        return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
         return

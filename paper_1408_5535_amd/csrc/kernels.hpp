@@ -77,11 +77,11 @@ constexpr int64_t kAuxCap = 1 << 16;
 // G (nx x ny, ld ldg, float64) = X^T Y, X = [X1 | X2] (X2 may have 0 cols).
 template <typename T>
 void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int ldg,
-        const Scratch &sc, hipStream_t s);
+        const Scratch &sc, hipStream_t s, const int *skip = nullptr);
 // Y = alpha * [X1 | X2] S + beta * Y, S float64 (nx x ny, ld lds).
 template <typename T>
 void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double alpha,
-        const Tall<T> &Y, double beta, hipStream_t s);
+        const Tall<T> &Y, double beta, hipStream_t s, const int *skip = nullptr);
 // Ritz block: X = V S, R = W S - X diag(theta) (row-major outputs, row stride ldx),
 // rn2[j] = ||R_:,j||^2; if ntop > 0 also xt2[j] = ||X_{0:ntop, j}||^2.
 template <typename T>
@@ -91,7 +91,9 @@ void ritz(const Tall<T> &V, const Tall<T> &W, const double *S, int lds, const do
 // out[j] = sum_i X(i, j)^2 over rows [r0, r1) (float64 result, device).
 template <typename T>
 void colnorm2(const Tall<T> &X, int64_t r0, int64_t r1, double *out, const Scratch &sc,
-              hipStream_t s);
+              hipStream_t s, const int *skip = nullptr);
+// A skip argument (device int, may be null) makes tn, nn and colnorm2 return
+// without work when it is nonzero (work decided on the device).
 // dst = src elementwise (any layouts, same shape), with type conversion.
 template <typename Ti, typename To>
 void copy(const Tall<Ti> &src, const Tall<To> &dst, hipStream_t s);

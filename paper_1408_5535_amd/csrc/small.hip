@@ -717,6 +717,7 @@ __global__ __launch_bounds__(256) void k_small_gemm(bool ta, bool tb, int M, int
        idx += gridDim.x * blockDim.x) {
     int i = idx % M, j = idx / M;
     double s = 0.0;
+#pragma unroll 8
     for (int k = 0; k < K; ++k) {
       double av = ta ? A[k + (int64_t)i * lda] : A[i + (int64_t)k * lda];
       double bv = tb ? B[j + (int64_t)k * ldb] : B[k + (int64_t)j * ldb];
@@ -740,37 +741,44 @@ void small_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const doubl
 // Single-wavefront Gram-Schmidt helpers for small coefficient spaces
 // (rows <= 64): lane r owns row r of every column, dot products are wave
 // reductions, so no workgroup barriers are needed.
-__device__ inline double wsum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
-// Orthogonalise column c of q (ld kSmallMax, lane r owns row r for the
-// update) against columns [0, c), twice.  The c dot products of a pass are
-// computed in parallel (lane j forms q_j^T x from LDS), then every lane
-// updates its row; coefficients accumulate into rc if given.
+// Orthogonalise column c of q (ld kLd, lane r owns row r for the update)
+// against columns [0, c), twice.  The c dot products of a pass are computed
+// in parallel (lane j forms q_j^T x from LDS, rows eight at a time), then
+// every lane updates its row; coefficients accumulate into rc if given.
 __device__ inline void wave_cgs2(double *q, int rows, int c, double *xs, double *dots, double *rc,
                                  double &n0, double &n2) {
   const int r = threadIdx.x;
-  double x = (r < rows) ? q[c * kSmallMax + r] : 0.0;
-  n0 = sqrt(wsum(x * x));
+  double x = (r < rows) ? q[c * kLd + r] : 0.0;
+  n0 = sqrt(wave_total(x * x));
   for (int pass = 0; pass < 2; ++pass) {
-    xs[r] = x;
+    xs[r] = x;  // zero past rows
     __syncthreads();
     if (r < c) {
-      double d = 0.0;
-      for (int k = 0; k < rows; ++k) d = fma(q[r * kSmallMax + k], xs[k], d);
-      dots[r] = d;
-      if (rc) rc[r] += d;
+      double d0 = 0.0, d1 = 0.0;
+      for (int k0 = 0; k0 < rows; k0 += 8) {
+        double qv[8], xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          qv[u] = q[r * kLd + k0 + u];  // rows past `rows` meet xs = 0
+          xv[u] = xs[k0 + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+          d0 = fma(qv[u], xv[u], d0);
+          d1 = fma(qv[u + 1], xv[u + 1], d1);
+        }
+      }
+      dots[r] = d0 + d1;
+      if (rc) rc[r] += d0 + d1;
     }
     __syncthreads();
     double acc = x;
-    for (int j = 0; j < c; ++j) acc = fma(-dots[j], q[j * kSmallMax + r], acc);
+    for (int j = 0; j < c; ++j) acc = fma(-dots[j], q[j * kLd + r], acc);
     x = (r < rows) ? acc : 0.0;
   }
-  q[c * kSmallMax + r] = x;
-  n2 = sqrt(wsum(x * x));
+  q[c * kLd + r] = x;
+  n2 = sqrt(wave_total(x * x));
   __syncthreads();
 }
 
@@ -780,10 +788,13 @@ __device__ inline void wave_cgs2(double *q, int rows, int c, double *xs, double 
 __global__ __launch_bounds__(64) void k_restart_basis(const double *K, int ldk, int rows, int kc,
                                                       const double *P, int ldp, int pc, double *Y,
                                                       int ldy, int *count) {
-  __shared__ double q[kSmallMax * kSmallMax];
-  __shared__ double xs[kSmallMax], dots[kSmallMax];
+  __shared__ double q[kSmallMax * kLd + 8];  // column-major, ld kLd (no bank conflicts)
+  __shared__ double xs[kSmallMax + 8], dots[kSmallMax];
   const int r = threadIdx.x;
-  for (int j = 0; j < kc; ++j) q[j * kSmallMax + r] = r < rows ? K[r + (int64_t)j * ldk] : 0.0;
+  if (r < 8) xs[kSmallMax + r] = 0.0;
+  for (int e = r; e < kSmallMax * kLd + 8; e += 64) q[e] = 0.0;  // padding reads meet zeros
+  __syncthreads();
+  for (int j = 0; j < kc; ++j) q[j * kLd + r] = r < rows ? K[r + (int64_t)j * ldk] : 0.0;
   __syncthreads();
   int cur = kc, unit = 0;
   const int want = min(kc + pc, min(rows, kSmallMax));
@@ -796,12 +807,12 @@ __global__ __launch_bounds__(64) void k_restart_basis(const double *K, int ldk, 
         x = (r == unit) ? 1.0 : 0.0;
         ++unit;
       }
-      q[cur * kSmallMax + r] = x;
+      q[cur * kLd + r] = x;
       __syncthreads();
       double n0, n2;
       wave_cgs2(q, rows, cur, xs, dots, nullptr, n0, n2);
       if (n0 > 0.0 && n2 > 1e-8 * n0) {
-        q[cur * kSmallMax + r] /= n2;
+        q[cur * kLd + r] /= n2;
         ++cur;
         __syncthreads();
         break;
@@ -809,7 +820,7 @@ __global__ __launch_bounds__(64) void k_restart_basis(const double *K, int ldk, 
     }
   }
   if (r < rows)
-    for (int j = 0; j < cur; ++j) Y[r + (int64_t)j * ldy] = q[j * kSmallMax + r];
+    for (int j = 0; j < cur; ++j) Y[r + (int64_t)j * ldy] = q[j * kLd + r];
   if (r == 0) count[0] = cur;
 }
 
@@ -822,10 +833,13 @@ void restart_basis(const double *K, int ldk, int rows, int kc, const double *P, 
 
 __global__ __launch_bounds__(64) void k_small_qr(const double *M, int ldm, int rows, int cols,
                                                  double *Q, int ldq, double *R, int ldr) {
-  __shared__ double q[kSmallMax * kSmallMax];
-  __shared__ double rc[kSmallMax], xs[kSmallMax], dots[kSmallMax];
+  __shared__ double q[kSmallMax * kLd + 8];  // column-major, ld kLd
+  __shared__ double rc[kSmallMax], xs[kSmallMax + 8], dots[kSmallMax];
   const int r = threadIdx.x;
-  for (int j = 0; j < cols; ++j) q[j * kSmallMax + r] = r < rows ? M[r + (int64_t)j * ldm] : 0.0;
+  if (r < 8) xs[kSmallMax + r] = 0.0;
+  for (int e = r; e < kSmallMax * kLd + 8; e += 64) q[e] = 0.0;  // padding reads meet zeros
+  __syncthreads();
+  for (int j = 0; j < cols; ++j) q[j * kLd + r] = r < rows ? M[r + (int64_t)j * ldm] : 0.0;
   for (int e = r; e < cols * cols; e += 64) R[e % cols + (int64_t)(e / cols) * ldr] = 0.0;
   for (int c = 0; c < cols; ++c) {
     rc[r] = 0.0;
@@ -833,12 +847,12 @@ __global__ __launch_bounds__(64) void k_small_qr(const double *M, int ldm, int r
     double n0, n2;
     wave_cgs2(q, rows, c, xs, dots, rc, n0, n2);
     double inv = n2 > 0.0 ? 1.0 / n2 : 0.0;
-    q[c * kSmallMax + r] *= inv;
+    q[c * kLd + r] *= inv;
     if (r < c) R[r + (int64_t)c * ldr] = rc[r];
     if (r == 0) R[c + (int64_t)c * ldr] = n2;
   }
   if (r < rows)
-    for (int j = 0; j < cols; ++j) Q[r + (int64_t)j * ldq] = q[j * kSmallMax + r];
+    for (int j = 0; j < cols; ++j) Q[r + (int64_t)j * ldq] = q[j * kLd + r];
 }
 
 void small_qr(const double *M, int ldm, int rows, int cols, double *Q, int ldq, double *R,

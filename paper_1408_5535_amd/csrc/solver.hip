@@ -238,6 +238,10 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     Tall<T> Tv = rmv(Tb, n, nb, bw);
     const Tall<T> B1 = cm(bf.Xl, n, nl, n), B2 = cm(V[cur], n, p, n);
     colnorm2(Tv, 0, n, sn0, c.sc, c.s);
+    // classical Gram-Schmidt, always twice: a single pass that cancels
+    // little (unpreconditioned corrections are nearly orthogonal to V
+    // already) still left enough of V in T to stall the largest-mode
+    // iteration at the 1e-12 level
     for (int pass = 0; pass < 2; ++pass) {
       tn(B1, B2, Tv, G, ld, c.sc, c.s);
       nn(B1, B2, G, ld, -1.0, Tv, 1.0, c.s);
@@ -487,7 +491,7 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
       ++res.restarts;
       warm = false;
     } else {
-      small_gemm(false, false, p, nb, p, 1.0, S, ld, sp.eye(), ld, 0.0, prev, ld, c.s);
+      copy(cm(S, p, nb, ld), cm(prev, p, nb, ld), c.s);  // this iteration's targets
       nprev = nb;
       warm = true;
       pw = p;

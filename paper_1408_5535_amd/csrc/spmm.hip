@@ -2,9 +2,10 @@
 //
 // Y = A X with A m x n in CSR and X (n x B), Y (m x B) stored row-major, so
 // that every nonzero a_ic gathers one contiguous B-vector x_c (B * sizeof(T)
-// bytes: 32-64 B for B = 8).  G lanes of a wavefront share a row: each lane
-// walks the row's nonzeros with stride G and keeps B partial sums in
-// registers; the G partials are combined with cross-lane shuffles.  G is
+// bytes: 32-64 B for B = 8), loaded by the 16-byte lanes of one slot.  G
+// slots of a wavefront share a row: each walks the row's nonzeros with
+// stride G and keeps partial sums in registers; the G partials are combined
+// with cross-lane shuffles.  G is
 // chosen from the row-length distribution: 1 lane per row for the grid
 // operators (2-4 nonzeros per row), wider groups for random rows, and the
 // rows of a power-law matrix are split into length bins, each launched with
@@ -21,43 +22,45 @@
 
 namespace phs {
 
-template <typename T, int B>
-__device__ inline void load_row(const T *__restrict__ p, T (&o)[B]) {
-  if constexpr ((B * sizeof(T)) % 16 == 0) {
-    const uint4 *q = reinterpret_cast<const uint4 *>(p);
-#pragma unroll
-    for (int i = 0; i < (int)(B * sizeof(T) / 16); ++i) {
-      uint4 u = q[i];
-      __builtin_memcpy(&o[i * 16 / sizeof(T)], &u, 16);
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < B; ++i) o[i] = p[i];
-  }
-}
-
-template <typename T, int B>
-__device__ inline void store_row(T *__restrict__ p, const T (&o)[B]) {
-  if constexpr ((B * sizeof(T)) % 16 == 0) {
-    uint4 *q = reinterpret_cast<uint4 *>(p);
-#pragma unroll
-    for (int i = 0; i < (int)(B * sizeof(T) / 16); ++i) {
-      uint4 u;
-      __builtin_memcpy(&u, &o[i * 16 / sizeof(T)], 16);
-      q[i] = u;
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < B; ++i) p[i] = o[i];
-  }
-}
-
 // rows: optional list of row indices (a length bin); nullptr = all rows.
-// Each lane takes every G-th nonzero of its row, kSpU at a time: the column
-// indices and values of the kSpU nonzeros are loaded first, then their kSpU
-// X-row gathers are issued together, so a lane keeps several independent
-// gathers in flight instead of one dependent chain per nonzero.
+// A row is handled by G nonzero slots x VL vector lanes: the b-vector row of
+// X that a nonzero gathers (b * sizeof(T) bytes) is split into VL chunks of
+// 16 B, one per lane, so the VL lanes of a slot load one contiguous row
+// together (one cache line request per nonzero instead of one per 16 B).
+// Each slot takes every G-th nonzero of the row, kSpU at a time (their
+// indices and values first, then kSpU independent gathers); the G slots'
+// partial sums are combined by shuffles and the VL lanes of slot 0 store
+// their chunks of the Y row.
 constexpr int kSpU = 4;
+
+template <typename T, int B>
+struct SpVec {  // lanes per X row and values per lane
+  static constexpr int VL = (B * (int)sizeof(T)) >= 16 ? (B * (int)sizeof(T)) / 16 : 1;
+  static constexpr int CW = B / VL;
+};
+
+template <typename T, int CW>
+__device__ inline void load_chunk(const T *__restrict__ p, T (&o)[CW]) {
+  if constexpr (CW * sizeof(T) == 16) {
+    const uint4 u = *reinterpret_cast<const uint4 *>(p);
+    __builtin_memcpy(o, &u, 16);
+  } else {
+#pragma unroll
+    for (int i = 0; i < CW; ++i) o[i] = p[i];
+  }
+}
+
+template <typename T, int CW>
+__device__ inline void store_chunk(T *__restrict__ p, const T (&o)[CW]) {
+  if constexpr (CW * sizeof(T) == 16) {
+    uint4 u;
+    __builtin_memcpy(&u, o, 16);
+    *reinterpret_cast<uint4 *>(p) = u;
+  } else {
+#pragma unroll
+    for (int i = 0; i < CW; ++i) p[i] = o[i];
+  }
+}
 
 template <typename T, int B, int G, bool ABS>
 __global__ __launch_bounds__(256) void k_spmm(int64_t nrows, const int32_t *__restrict__ rows,
@@ -65,16 +68,19 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nrows, const int32_t *__re
                                               const int32_t *__restrict__ ci,
                                               const T *__restrict__ va,
                                               const T *__restrict__ X, T *__restrict__ Y) {
+  constexpr int VL = SpVec<T, B>::VL, CW = SpVec<T, B>::CW, GL = G * VL;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t slot = gid / G;
-  const int lane = (int)(threadIdx.x % G);
+  const int64_t slot = gid / GL;
+  const int lig = (int)(threadIdx.x % GL);
+  const int g = lig / VL, part = lig % VL;
   if (slot >= nrows) return;  // a whole group leaves together
   const int64_t row = rows ? (int64_t)rows[slot] : slot;
-  T acc[B];
+  T acc[CW];
 #pragma unroll
-  for (int j = 0; j < B; ++j) acc[j] = T(0);
+  for (int j = 0; j < CW; ++j) acc[j] = T(0);
   const int64_t end = rp[row + 1];
-  for (int64_t p0 = rp[row] + lane; p0 < end; p0 += (int64_t)G * kSpU) {
+  const T *Xp = X + part * CW;
+  for (int64_t p0 = rp[row] + g; p0 < end; p0 += (int64_t)G * kSpU) {
     int64_t c[kSpU];
     T a[kSpU];
 #pragma unroll
@@ -84,45 +90,57 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nrows, const int32_t *__re
       c[u] = in ? ci[p] : 0;
       a[u] = in ? va[p] : T(0);  // zero weight for the padding slots
     }
-    T x[kSpU][B];
+    T x[kSpU][CW];
 #pragma unroll
-    for (int u = 0; u < kSpU; ++u) load_row<T, B>(X + c[u] * B, x[u]);
+    for (int u = 0; u < kSpU; ++u) load_chunk<T, CW>(Xp + c[u] * B, x[u]);
 #pragma unroll
     for (int u = 0; u < kSpU; ++u) {
       T au = a[u];
       if constexpr (ABS) {
         au = fabs(au);
 #pragma unroll
-        for (int j = 0; j < B; ++j) x[u][j] = fabs(x[u][j]);
+        for (int j = 0; j < CW; ++j) x[u][j] = fabs(x[u][j]);
       }
 #pragma unroll
-      for (int j = 0; j < B; ++j) acc[j] = fma(au, x[u][j], acc[j]);
+      for (int j = 0; j < CW; ++j) acc[j] = fma(au, x[u][j], acc[j]);
     }
   }
   if constexpr (G > 1) {
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) {
 #pragma unroll
-      for (int j = 0; j < B; ++j) acc[j] += __shfl_xor(acc[j], off, G);
+      for (int j = 0; j < CW; ++j) acc[j] += __shfl_xor(acc[j], off * VL, GL);
     }
   }
-  if (lane == 0) store_row<T, B>(Y + row * B, acc);
+  if (g == 0) store_chunk<T, CW>(Y + row * B + part * CW, acc);
 }
 
 template <typename T, int B, bool ABS>
 static void launch_g(int G, int64_t nrows, const int32_t *rows, const int64_t *rp,
                      const int32_t *ci, const T *va, const T *X, T *Y, hipStream_t s) {
   if (nrows <= 0) return;
-  const int64_t threads = nrows * G;
+  constexpr int VL = SpVec<T, B>::VL;
+  constexpr int Gmax = 64 / VL;  // a row group stays inside one wavefront
+  if (G > Gmax) G = Gmax;
+  const int64_t threads = nrows * G * VL;
   dim3 grid(cdiv(threads, 256));
   switch (G) {
     case 1: k_spmm<T, B, 1, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
     case 2: k_spmm<T, B, 2, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
     case 4: k_spmm<T, B, 4, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
     case 8: k_spmm<T, B, 8, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
-    case 16: k_spmm<T, B, 16, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
-    case 32: k_spmm<T, B, 32, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
-    default: k_spmm<T, B, 64, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
+    case 16:
+      if constexpr (Gmax >= 16)
+        k_spmm<T, B, 16, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y);
+      break;
+    case 32:
+      if constexpr (Gmax >= 32)
+        k_spmm<T, B, 32, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y);
+      break;
+    default:
+      if constexpr (Gmax >= 64)
+        k_spmm<T, B, 64, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y);
+      break;
   }
   PHS_CHECK_LAUNCH();
 }

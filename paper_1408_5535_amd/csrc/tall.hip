@@ -63,7 +63,9 @@ struct TnRows {  // rows per lane in flight: float 4, double 2 (register budget)
 
 template <typename T>
 __global__ __launch_bounds__(64 * kTnMaxWaves) void k_tn(TV<T> x1, TV<T> x2, TV<T> y,
-                                                         int64_t rpb, double *part) {
+                                                         int64_t rpb, double *part,
+                                                         const int *skip) {
+  if (skip && *skip) return;
   constexpr int U = TnRows<T>::U;
   const int nx = x1.cols + x2.cols, ny = y.cols;
   const int tx = (nx + kTnCX - 1) / kTnCX, ty = (ny + kTnCY - 1) / kTnCY, ntile = tx * ty;
@@ -128,7 +130,8 @@ __global__ __launch_bounds__(64 * kTnMaxWaves) void k_tn(TV<T> x1, TV<T> x2, TV<
 // One wavefront per entry of G: lane l sums partials l, l+64, ... and the
 // lane sums are combined in the fixed order of wave_total.
 __global__ __launch_bounds__(64) void k_reduce_parts(const double *part, int np, int nx, int ny,
-                                                     double *G, int ldg) {
+                                                     double *G, int ldg, const int *skip) {
+  if (skip && *skip) return;
   const int E = nx * ny, e = blockIdx.x;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int b = threadIdx.x;
@@ -145,7 +148,7 @@ __global__ __launch_bounds__(64) void k_reduce_parts(const double *part, int np,
 
 template <typename T>
 void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int ldg,
-        const Scratch &sc, hipStream_t s) {
+        const Scratch &sc, hipStream_t s, const int *skip) {
   const int nx = X1.cols + X2.cols, ny = Y.cols;
   if (nx == 0 || ny == 0) return;
   PHS_REQUIRE(nx <= 128 && ny <= 32, kEinval, "tn: operand too wide");
@@ -169,8 +172,8 @@ void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int l
   }
   if (nblk < 1) nblk = 1;
   prof_begin(kProfTn, s);
-  k_tn<T><<<(int)nblk, 64 * waves, 0, s>>>(tv(X1), tv(X2), tv(Y), rpb, sc.part);
-  k_reduce_parts<<<(int)E, 64, 0, s>>>(sc.part, (int)nblk, nx, ny, G, ldg);
+  k_tn<T><<<(int)nblk, 64 * waves, 0, s>>>(tv(X1), tv(X2), tv(Y), rpb, sc.part, skip);
+  k_reduce_parts<<<(int)E, 64, 0, s>>>(sc.part, (int)nblk, nx, ny, G, ldg, skip);
   PHS_CHECK_LAUNCH();
   prof_end(kProfTn, s, (double)Y.rows * (nx + ny) * sizeof(T));
 }
@@ -185,7 +188,8 @@ constexpr int kNnTile = 16;  // output columns per thread
 template <typename T>
 __global__ __launch_bounds__(256) void k_nn(TV<T> x1, TV<T> x2, const double *S, int lds,
                                             int ny, double alpha, T *yp, int64_t yrs,
-                                            int64_t ycs, double beta) {
+                                            int64_t ycs, double beta, const int *skip) {
+  if (skip && *skip) return;
   extern __shared__ __align__(16) unsigned char smem[];
   T *ss = reinterpret_cast<T *>(smem);
   const int nx = x1.cols + x2.cols;
@@ -227,7 +231,7 @@ __global__ __launch_bounds__(256) void k_nn(TV<T> x1, TV<T> x2, const double *S,
 
 template <typename T>
 void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double alpha,
-        const Tall<T> &Y, double beta, hipStream_t s) {
+        const Tall<T> &Y, double beta, hipStream_t s, const int *skip) {
   const int nx = X1.cols + X2.cols, ny = Y.cols;
   if (ny == 0 || Y.rows == 0) return;
   if (nx == 0 && beta == 1.0) return;
@@ -239,7 +243,7 @@ void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double a
   Tall<T> a = X1, b = X2;
   if (a.cols == 0 && b.cols == 0) a.rows = Y.rows;
   prof_begin(kProfNn, s);
-  k_nn<T><<<grid, 256, shm, s>>>(tv(a), tv(b), S, lds, ny, alpha, Y.p, Y.rs, Y.cs, beta);
+  k_nn<T><<<grid, 256, shm, s>>>(tv(a), tv(b), S, lds, ny, alpha, Y.p, Y.rs, Y.cs, beta, skip);
   PHS_CHECK_LAUNCH();
   prof_end(kProfNn, s, (double)Y.rows * (nx + ny * (beta != 0.0 ? 2 : 1)) * sizeof(T));
 }
@@ -313,7 +317,9 @@ __global__ __launch_bounds__(256) void k_ritz(TV<T> V, TV<T> W, const double *S,
 }
 
 __global__ __launch_bounds__(64) void k_reduce_vec(const double *part, int nblk, int E,
-                                                   double *out0, double *out1, int split) {
+                                                   double *out0, double *out1, int split,
+                                                   const int *skip = nullptr) {
+  if (skip && *skip) return;
   const int e = blockIdx.x;
   double s = 0.0;
   for (int b = threadIdx.x; b < nblk; b += 64) s += part[(int64_t)b * E + e];
@@ -361,7 +367,8 @@ void ritz(const Tall<T> &V, const Tall<T> &W, const double *S, int lds, const do
 // ------------------------------------------------------------ col norms
 template <typename T>
 __global__ __launch_bounds__(256) void k_colnorm2(TV<T> x, int64_t r0, int64_t r1,
-                                                  double *part) {
+                                                  double *part, const int *skip) {
+  if (skip && *skip) return;
   __shared__ double red[256];
   for (int j = 0; j < x.cols; ++j) {
     double acc = 0.0;
@@ -383,12 +390,12 @@ __global__ __launch_bounds__(256) void k_colnorm2(TV<T> x, int64_t r0, int64_t r
 
 template <typename T>
 void colnorm2(const Tall<T> &X, int64_t r0, int64_t r1, double *out, const Scratch &sc,
-              hipStream_t s) {
+              hipStream_t s, const int *skip) {
   if (X.cols == 0) return;
   int64_t blocks = cdiv(r1 - r0 > 0 ? r1 - r0 : 1, 256 * 4);
   if (blocks > 512) blocks = 512;
-  k_colnorm2<T><<<(unsigned)blocks, 256, 0, s>>>(tv(X), r0, r1, sc.part);
-  k_reduce_vec<<<X.cols, 64, 0, s>>>(sc.part, (int)blocks, X.cols, out, nullptr, X.cols);
+  k_colnorm2<T><<<(unsigned)blocks, 256, 0, s>>>(tv(X), r0, r1, sc.part, skip);
+  k_reduce_vec<<<X.cols, 64, 0, s>>>(sc.part, (int)blocks, X.cols, out, nullptr, X.cols, skip);
   PHS_CHECK_LAUNCH();
 }
 
@@ -613,14 +620,14 @@ void row_scale(const T *X, const double *w, int64_t n, int b, bool inv, T *Y, hi
 
 #define PHS_INST(T)                                                                           \
   template void tn<T>(const Tall<T> &, const Tall<T> &, const Tall<T> &, double *, int,      \
-                      const Scratch &, hipStream_t);                                         \
+                      const Scratch &, hipStream_t, const int *);                            \
   template void nn<T>(const Tall<T> &, const Tall<T> &, const double *, int, double,         \
-                      const Tall<T> &, double, hipStream_t);                                 \
+                      const Tall<T> &, double, hipStream_t, const int *);                    \
   template void ritz<T>(const Tall<T> &, const Tall<T> &, const double *, int, const double *, \
                         T *, T *, int, int, double *, double *, int64_t, const Scratch &,     \
                         hipStream_t);                                                         \
   template void colnorm2<T>(const Tall<T> &, int64_t, int64_t, double *, const Scratch &,     \
-                            hipStream_t);                                                     \
+                            hipStream_t, const int *);                                        \
   template void scale_cols<T>(const Tall<T> &, const double *, hipStream_t);                  \
   template void axpby<T>(const Tall<T> &, const Tall<T> &, double, const Tall<T> &,           \
                          hipStream_t);                                                        \

@@ -65,6 +65,25 @@ def test_grid_largest_closed_form():
 
 
 @gpu
+@pytest.mark.parametrize("which", ["smallest", "largest"])
+def test_grid_n128_both_ends_closed_form(which):
+    """N = 128 (m = 33024, n = 16384), k = 10, block 4: the clustered
+    largest end (relative gap 4e-5 after the 10th value) needs an accurate
+    basis; sigma and residuals are checked against the closed form."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    N = 128
+    A = wl.grid_gradient(N)
+    an = cf.grid_norm(N)
+    say("grid N=128 k=10 b=4", which)
+    sig, U, V, info = P.svds_smallest(to_dev(A), 10, 1e-12, block=4, which=which, anorm=an,
+                                      max_matvecs=60000)
+    say(info["mv_total"], info["status"])
+    ex = cf.grid_sigmas(N)
+    _check(A, sig, U, V, info, ex[:10] if which == "smallest" else ex[::-1][:10], an)
+
+
+@gpu
 def test_givens_two_stage_closed_form():
     need_gpu()
     n, m = 200, 240
