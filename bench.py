@@ -96,6 +96,118 @@ def spmm_probe(kind, N):
                       "b": b}), flush=True)
 
 
+COMPARE = {
+    "random": dict(k=10, b=4, cap=200_000,
+                   label="random sparse 300000 x 200000, 12 per row, N(0,1), diagonal shift "
+                         "U[0.01, 0.1], seed 2000",
+                   arms=[("f64", "none"), ("f64", "jacobi"), ("mixed", "jacobi")]),
+    "powerlaw": dict(k=20, b=8, cap=150_000,
+                     label="power-law rows 4000000 x 3000000 (shifted Zipf 2, mean 10, max 2000), "
+                           "N(0,1), diagonal shift U[0.01, 0.1], seed 5",
+                     arms=[("f64", "none"), ("f64", "jacobi"), ("mixed", "jacobi")]),
+    "weighted": dict(k=16, b=8, cap=150_000,
+                     label="grid gradient N=1024, rows scaled by lognormal(0, 1) weights, seed 3",
+                     arms=[("f64", "jacobi"), ("mixed", "jacobi")]),
+}
+
+
+def compare_matrix(family):
+    import workloads as wl
+    if family == "random":
+        return wl.random_sparse(300_000, 200_000, 12, seed=2000)
+    if family == "powerlaw":
+        return wl.powerlaw_sparse()
+    return wl.grid_gradient(1024, weights="lognormal", seed=3)
+
+
+def host_norm_estimate(A, iters=60, seed=0):
+    """Power iteration on A^T A with SciPy in float64: a lower bound on ||A||
+    (so residuals divided by it are not understated)."""
+    x = np.random.default_rng(seed).standard_normal(A.shape[1])
+    AT = A.T.tocsr()
+    s = 0.0
+    for _ in range(iters):
+        y = AT @ (A @ x)
+        s = math.sqrt(np.linalg.norm(y) / np.linalg.norm(x))
+        x = y / np.linalg.norm(y)
+    return s
+
+
+def host_residuals(A, AT, sig, U, V):
+    """sqrt(||A^T u - s v||^2 + ||A v - s u||^2) per triplet, SciPy float64."""
+    ru = AT @ U - V * sig[None, :]
+    rv = A @ V - U * sig[None, :]
+    return np.sqrt(np.sum(ru * ru, axis=0) + np.sum(rv * rv, axis=0))
+
+
+def compare(family, max_mv, gnn_weights, gnn_width, max_restarts=10000):
+    """End-to-end comparison of the method's arms (float64 or float32 stage 1,
+    none / Jacobi / learned preconditioner) on one matrix of a family.  One
+    JSON line per arm, then a summary line.  Residuals are recomputed on the
+    host with SciPy; sigma differences and principal angles are taken against
+    the first converged float64 arm."""
+    import torch
+    import paper_1408_5535_amd as P
+    cfg = COMPARE[family]
+    k, b = cfg["k"], cfg["b"]
+    t0 = time.perf_counter()
+    A = compare_matrix(family)
+    AT = A.T.tocsr()
+    anorm = host_norm_estimate(A)
+    print(json.dumps({"compare": family, "workload": cfg["label"], "m": A.shape[0],
+                      "n": A.shape[1], "nnz": int(A.nnz), "k": k, "block": b,
+                      "anorm_lower_bound": anorm,
+                      "setup_s": time.perf_counter() - t0}), flush=True)
+    Ad = P.DeviceCSR.from_scipy(A)
+    arms = list(cfg["arms"])
+    w = None
+    if gnn_weights:
+        w = torch.tensor(np.load(gnn_weights), dtype=torch.float32, device="cuda")
+        arms += [("mixed", "gnn")]
+    cap = max_mv or cfg["cap"]
+    rows, ref = [], None
+    for prec, pre in arms:
+        kw = {"gnn_width": gnn_width} if pre == "gnn" else {}
+        s = P.Solver(Ad, k, block=b, stage1_fp32=(prec == "mixed"), max_matvecs=cap,
+                     max_restarts=max_restarts, verbose=True, **kw)
+        torch.cuda.synchronize()
+        P.profile(True, kinds=["spmm_f64", "spmm_f32"])
+        t1 = time.perf_counter()
+        sig, U, V, info = s.solve(1e-12, precond=pre, gnn_weights=w, gnn_width=gnn_width)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        gbs = {}
+        for kind in ("spmm_f64", "spmm_f32"):
+            nl, ks, kb = P.profile_read(kind)
+            if nl:
+                gbs[kind] = {"launches": nl, "avg_us": ks / nl * 1e6, "gbs": kb / ks / 1e9}
+        P.profile(False)
+        Uh, Vh = U.cpu().numpy(), V.cpu().numpy()
+        res = host_residuals(A, AT, sig, Uh, Vh) / anorm
+        row = {"arm": f"{prec}+{pre}", "status": int(info["status"]), "seconds": dt,
+               "mv_total": int(info["mv_total"]), "mv_stage1": int(info["mv_stage1"]),
+               "mv_stage2": int(info["mv_stage2"]), "matvecs_per_triplet": info["mv_total"] / k,
+               "mv_prec": int(info["mv_prec"]), "stage2_pairs": int(info["stage2_pairs"]),
+               "converged": int(np.sum(res <= 1e-12)),
+               "max_host_residual_over_norm": float(res.max()), "spmm": gbs,
+               "sigma": [float(x) for x in sig]}
+        if ref is None and prec == "f64" and row["converged"] == k:
+            ref = (sig, Vh)
+        elif ref is not None:
+            # sigma difference and cosines of the principal angles between the
+            # right singular subspaces, against the float64 arm
+            row["max_rel_sigma_diff_vs_f64"] = float(np.max(np.abs(sig - ref[0]) / ref[0]))
+            cos = np.linalg.svd(ref[1].T @ Vh, compute_uv=False)
+            row["min_cos_principal_angle_vs_f64"] = float(cos.min())
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+        del s, U, V
+        torch.cuda.empty_cache()
+    print(json.dumps({"compare": family, "matvec_cap": cap, "max_restarts": max_restarts, "arms": [
+        {key: r[key] for key in ("arm", "status", "seconds", "mv_total", "converged")}
+        for r in rows]}), flush=True)
+
+
 def traffic_from_profiles(workload):
     """HBM bytes per SpMM launch from committed rocprofv3 counter runs, if they
     were taken on the current SpMM source; else None."""
@@ -159,11 +271,21 @@ def main():
                     help="only run a device copy of known size (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("CSV", "KERNEL"),
                     help="only summarise a rocprofv3 counter_collection.csv for one kernel")
+    ap.add_argument("--compare", choices=sorted(COMPARE),
+                    help="only run the end-to-end comparison of float64 / mixed precision and "
+                         "none / Jacobi (/ learned, with --gnn-weights) on one matrix of a family")
+    ap.add_argument("--gnn-weights", default="", help="trained weights (.npy) for --compare")
+    ap.add_argument("--gnn-width", type=int, default=32)
+    ap.add_argument("--max-restarts", type=int, default=10000,
+                    help="restart limit per stage for --compare (Section 5 uses 10000)")
     ap.add_argument("--spmm-probe", choices=["grid", "random", "powerlaw"],
                     help="only run three float64 A X products on a workload of that family "
                          "(random: 300000 x 200000, 12 per row, b=4; powerlaw: 4M x 3M, b=8; "
                          "grid: --N, b=4), for counter runs")
     args = ap.parse_args()
+    if args.compare:
+        compare(args.compare, args.max_mv, args.gnn_weights, args.gnn_width, args.max_restarts)
+        return
     if args.spmm_probe:
         spmm_probe(args.spmm_probe, args.N)
         return

@@ -81,6 +81,8 @@ typedef struct {
   double floor_factor; /* multiple of eps*||C|| that ends stage 1 (default 10) */
   int gnn_width;       /* width of the learned preconditioner the workspace must
                           hold (0: none); must match phsvds_precond.gnn_width */
+  int verbose;         /* 1: a progress line on stderr every 1000 iterations
+                          and at each lock; 0 (default): silent */
 } phsvds_opts;
 
 typedef struct {
@@ -145,8 +147,11 @@ int phsvds_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int k, const phsvd
  *           entry of each v_i is positive
  *   resnorm host, k      explicit float64 residuals of the returned triplets
  *   stats   host, may be NULL
- * Returns PHSVDS_OK, PHSVDS_NOT_CONVERGED (best approximations returned),
- * or an error.  1 <= k <= 24, m >= n, tol > 0. */
+ * Returns PHSVDS_OK, PHSVDS_NOT_CONVERGED, or an error.  1 <= k <= 24,
+ * m >= n, tol > 0.  On PHSVDS_NOT_CONVERGED (restart or product budget
+ * spent) every triplet is still filled: the pairs not locked are the
+ * leading Ritz approximations of the final basis, u = A v / ||A v||, with
+ * their explicit residuals in resnorm. */
 int phsvds_svds(const phsvds_csr *A, int k, double tol, const phsvds_precond *P,
                 const phsvds_opts *opts, void *workspace, size_t ws_bytes, void *stream,
                 double *sigma, double *U, double *V, double *resnorm, phsvds_stats *stats);

@@ -48,7 +48,7 @@ class _Opts(ctypes.Structure):
                 ("max_restarts", ctypes.c_int), ("max_matvecs", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("init_block", ctypes.c_void_p),
                 ("anorm", ctypes.c_double), ("floor_factor", ctypes.c_double),
-                ("gnn_width", ctypes.c_int)]
+                ("gnn_width", ctypes.c_int), ("verbose", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -206,7 +206,7 @@ def csr_transpose(A: DeviceCSR) -> DeviceCSR:
 
 def make_opts(which="smallest", block=1, max_basis=0, min_restart=0, stage1_fp32=False,
               fp64_continue=True, stage2="auto", max_restarts=10000, max_matvecs=0, seed=1,
-              init_block=None, anorm=0.0, floor_factor=10.0, gnn_width=0):
+              init_block=None, anorm=0.0, floor_factor=10.0, gnn_width=0, verbose=False):
     o = _Opts()
     _lib.phsvds_default_opts(ctypes.byref(o))
     o.which = {"smallest": 0, "largest": 1}[which]
@@ -227,6 +227,7 @@ def make_opts(which="smallest", block=1, max_basis=0, min_restart=0, stage1_fp32
     o.anorm = float(anorm)
     o.floor_factor = floor_factor
     o.gnn_width = gnn_width
+    o.verbose = int(verbose)
     o._keep = keep
     return o
 

@@ -257,6 +257,7 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   c.seed = o.seed;
   c.st = &stl;
   c.max_mv = o.max_matvecs;
+  c.verbose = o.verbose;
   SmallPool sp;
   sp.base = pl.pool;
   {
@@ -361,7 +362,7 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
       nvr = r1.p;
     } else {
       // float32 results move to float64 buffers (re-sorted below)
-      copy(cm(pl.s32.Xl, n, r1.nl, n), cm(pl.Xs, n, r1.nl, n), c.s);
+      copy(cm(pl.s32.Xl, n, r1.nl + r1.nbest, n), cm(pl.Xs, n, r1.nl + r1.nbest, n), c.s);
       copy(cm((float *)r1.Vrest, n, r1.p, n), cm(pl.Vr64, n, r1.p, n), c.s);
       Xl64 = pl.Xs;
       Vr64 = pl.Vr64;
@@ -387,6 +388,8 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   stl.anorm_est = sn;
   const double an = o.anorm > 0 ? o.anorm : sn;
   const int nl = r1.nl;
+  // best approximations of the pairs not converged follow the locked ones
+  const int nbest = r1.nbest, ntot = nl + nbest;
   // sort the locked pairs (ascending, or descending for largest)
   std::vector<int> ord(nl);
   std::iota(ord.begin(), ord.end(), 0);
@@ -403,8 +406,11 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
     tight[i] = r1.tight[ord[i]];
     if (i < 64) stl.res_stage1[i] = r1.res[ord[i]];
   }
+  if (nbest)
+    copy(cm(const_cast<double *>(Xl64) + (int64_t)nl * n, n, nbest, n),
+         cm(Xs + (int64_t)nl * n, n, nbest, n), c.s);
   if (Xs == pl.tb.Vt) {  // keep Xs away from the transition outputs
-    copy(cm(pl.tb.Vt, n, nl, n), cm(pl.Vf, n, nl, n), c.s);
+    copy(cm(pl.tb.Vt, n, ntot, n), cm(pl.Vf, n, ntot, n), c.s);
     Xs = pl.Vf;
   }
   // stage-2 entry (Section 3.1): pairs whose stage-1 test was floor-limited
@@ -452,10 +458,12 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
       copy(cm(r2.Xl, n, r2.nl, N), cm(pl.Vf, n, r2.nl, n), c.s);
       copy(cm(r2.Xl + n, m, r2.nl, N), cm(pl.Uf, m, r2.nl, m), c.s);
     }
+    if (nbest && Xs != pl.Vf)
+      copy(cm(Xs + (int64_t)nl * n, n, nbest, n), cm(pl.Vf + (int64_t)nl * n, n, nbest, n), c.s);
     Vsrc = pl.Vf;
     Usrc = pl.Uf;
   } else {
-    if (Xs != pl.Vf) copy(cm(Xs, n, nl, n), cm(pl.Vf, n, nl, n), c.s);
+    if (Xs != pl.Vf) copy(cm(Xs, n, ntot, n), cm(pl.Vf, n, ntot, n), c.s);
     Vsrc = pl.Vf;
   }
   c.sync();
@@ -463,40 +471,43 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   stl.t_stage2 = t3 - t2;
   // ------------------------------------------- final float64 check (Sec. 5)
   double *nrm = sp.vec(20);
-  std::vector<double> f(nl), nh(nl);
-  if (nl > 0) {
-    colnorm2(cm(Vsrc, n, nl, n), 0, n, nrm, c.sc, c.s);
-    c.d2h(nh.data(), nrm, nl * sizeof(double));
+  std::vector<double> f(ntot), nh(ntot);
+  if (ntot > 0) {
+    colnorm2(cm(Vsrc, n, ntot, n), 0, n, nrm, c.sc, c.s);
+    c.d2h(nh.data(), nrm, ntot * sizeof(double));
     c.sync();
-    for (int i = 0; i < nl; ++i) f[i] = nh[i] > 0 ? 1.0 / std::sqrt(nh[i]) : 0.0;
-    c.h2d(sp.vec(21), f.data(), nl * sizeof(double));
-    scale_cols(cm(Vsrc, n, nl, n), sp.vec(21), c.s);
-    apply_cols(c, A64, Vsrc, nl, pl.AV, pl.Fx, pl.Fy);
-    stl.mv_final += nl;
+    for (int i = 0; i < ntot; ++i) f[i] = nh[i] > 0 ? 1.0 / std::sqrt(nh[i]) : 0.0;
+    c.h2d(sp.vec(21), f.data(), ntot * sizeof(double));
+    scale_cols(cm(Vsrc, n, ntot, n), sp.vec(21), c.s);
+    apply_cols(c, A64, Vsrc, ntot, pl.AV, pl.Fx, pl.Fy);
+    stl.mv_final += ntot;
     if (!Usrc) {
-      copy(cm(pl.AV, m, nl, m), cm(pl.Uf, m, nl, m), c.s);
+      copy(cm(pl.AV, m, ntot, m), cm(pl.Uf, m, ntot, m), c.s);
       Usrc = pl.Uf;
     }
-    colnorm2(cm(Usrc, m, nl, m), 0, m, nrm, c.sc, c.s);
-    c.d2h(nh.data(), nrm, nl * sizeof(double));
+    if (nbest)  // left vectors of the best approximations: A v / ||A v||
+      copy(cm(pl.AV + (int64_t)nl * m, m, nbest, m), cm(pl.Uf + (int64_t)nl * m, m, nbest, m),
+           c.s);
+    colnorm2(cm(Usrc, m, ntot, m), 0, m, nrm, c.sc, c.s);
+    c.d2h(nh.data(), nrm, ntot * sizeof(double));
     c.sync();
-    for (int i = 0; i < nl; ++i) f[i] = nh[i] > 0 ? 1.0 / std::sqrt(nh[i]) : 0.0;
-    c.h2d(sp.vec(21), f.data(), nl * sizeof(double));
-    scale_cols(cm(Usrc, m, nl, m), sp.vec(21), c.s);
+    for (int i = 0; i < ntot; ++i) f[i] = nh[i] > 0 ? 1.0 / std::sqrt(nh[i]) : 0.0;
+    c.h2d(sp.vec(21), f.data(), ntot * sizeof(double));
+    scale_cols(cm(Usrc, m, ntot, m), sp.vec(21), c.s);
   }
-  std::vector<double> sig(nl, 0.0), res(nl, 0.0);
-  if (nl > 0) {
+  std::vector<double> sig(ntot, 0.0), res(ntot, 0.0);
+  if (ntot > 0) {
     double *G = sp.mat(31);
-    for (int c0 = 0; c0 < nl; c0 += 32) {
-      int w = std::min(32, nl - c0);
-      tn(cm(Usrc, m, nl, m), cm<double>(nullptr, m, 0, m), cm(pl.AV + (int64_t)c0 * m, m, w, m),
+    for (int c0 = 0; c0 < ntot; c0 += 32) {
+      int w = std::min(32, ntot - c0);
+      tn(cm(Usrc, m, ntot, m), cm<double>(nullptr, m, 0, m), cm(pl.AV + (int64_t)c0 * m, m, w, m),
          G + (int64_t)c0 * kSP, kSP, c.sc, c.s);
     }
-    std::vector<double> gh((size_t)kSP * nl);
+    std::vector<double> gh((size_t)kSP * ntot);
     c.d2h(gh.data(), G, gh.size() * sizeof(double));
     c.sync();
-    std::vector<double> flip(nl, 1.0), dneg((size_t)kSP * kSP, 0.0);
-    for (int i = 0; i < nl; ++i) {
+    std::vector<double> flip(ntot, 1.0), dneg((size_t)kSP * kSP, 0.0);
+    for (int i = 0; i < ntot; ++i) {
       sig[i] = gh[i + (size_t)i * kSP];
       if (sig[i] < 0) {
         flip[i] = -1.0;
@@ -504,32 +515,32 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
       }
       dneg[i + (size_t)i * kSP] = -sig[i];
     }
-    c.h2d(sp.vec(21), flip.data(), nl * sizeof(double));
-    scale_cols(cm(Usrc, m, nl, m), sp.vec(21), c.s);
+    c.h2d(sp.vec(21), flip.data(), ntot * sizeof(double));
+    scale_cols(cm(Usrc, m, ntot, m), sp.vec(21), c.s);
     c.h2d(sp.mat(32), dneg.data(), dneg.size() * sizeof(double));
     // r_v = A v - sigma u ; r_u = A^T u - sigma v
-    copy(cm(pl.AV, m, nl, m), cm(pl.RV, m, nl, m), c.s);
-    nn(cm(Usrc, m, nl, m), cm<double>(nullptr, m, 0, m), sp.mat(32), kSP, 1.0, cm(pl.RV, m, nl, m),
+    copy(cm(pl.AV, m, ntot, m), cm(pl.RV, m, ntot, m), c.s);
+    nn(cm(Usrc, m, ntot, m), cm<double>(nullptr, m, 0, m), sp.mat(32), kSP, 1.0, cm(pl.RV, m, ntot, m),
        1.0, c.s);
-    apply_cols(c, At64, Usrc, nl, pl.RU, pl.Fx, pl.Fy);
-    nn(cm(Vsrc, n, nl, n), cm<double>(nullptr, n, 0, n), sp.mat(32), kSP, 1.0, cm(pl.RU, n, nl, n),
+    apply_cols(c, At64, Usrc, ntot, pl.RU, pl.Fx, pl.Fy);
+    nn(cm(Vsrc, n, ntot, n), cm<double>(nullptr, n, 0, n), sp.mat(32), kSP, 1.0, cm(pl.RU, n, ntot, n),
        1.0, c.s);
-    std::vector<double> a(nl), bq(nl);
-    colnorm2(cm(pl.RV, m, nl, m), 0, m, nrm, c.sc, c.s);
-    c.d2h(a.data(), nrm, nl * sizeof(double));
+    std::vector<double> a(ntot), bq(ntot);
+    colnorm2(cm(pl.RV, m, ntot, m), 0, m, nrm, c.sc, c.s);
+    c.d2h(a.data(), nrm, ntot * sizeof(double));
     c.sync();
-    colnorm2(cm(pl.RU, n, nl, n), 0, n, nrm, c.sc, c.s);
-    c.d2h(bq.data(), nrm, nl * sizeof(double));
+    colnorm2(cm(pl.RU, n, ntot, n), 0, n, nrm, c.sc, c.s);
+    c.d2h(bq.data(), nrm, ntot * sizeof(double));
     c.sync();
-    for (int i = 0; i < nl; ++i) res[i] = std::sqrt(a[i] + bq[i]);
+    for (int i = 0; i < ntot; ++i) res[i] = std::sqrt(a[i] + bq[i]);
   }
   // order, sign convention, outputs
-  std::vector<int> fo(nl);
+  std::vector<int> fo(ntot);
   std::iota(fo.begin(), fo.end(), 0);
   std::stable_sort(fo.begin(), fo.end(),
                    [&](int a, int b) { return largest ? sig[a] > sig[b] : sig[a] < sig[b]; });
   for (int i = 0; i < k; ++i) {
-    if (i < nl) {
+    if (i < ntot) {
       int j = fo[i];
       copy(cm(Vsrc + (int64_t)j * n, n, 1, n), cm(Vout + (int64_t)i * n, n, 1, n), c.s);
       copy(cm(Usrc + (int64_t)j * m, m, 1, m), cm(Uout + (int64_t)i * m, m, 1, m), c.s);
@@ -542,8 +553,8 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
       resnorm[i] = INFINITY;
     }
   }
-  if (nl > 0) {
-    k_sign_fix<<<std::min(nl, k), 256, 0, c.s>>>(Vout, n, Uout, m);
+  if (ntot > 0) {
+    k_sign_fix<<<std::min(ntot, k), 256, 0, c.s>>>(Vout, n, Uout, m);
     PHS_CHECK_LAUNCH();
   }
   c.sync();

@@ -36,8 +36,10 @@ hipEvent_t get_event() {
     g.pool.pop_back();
     return e;
   }
+  // Timing-only events: without the system-scope fence the interval does
+  // not include a cache write-back after the kernel.
   hipEvent_t e;
-  PHS_HIP(hipEventCreate(&e));
+  PHS_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   return e;
 }
 

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 
@@ -330,6 +331,12 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     res.sn2 = std::max(res.sn2, th_h[p - 1]);
     const double sn = std::sqrt(res.sn2);
     const int need = k - nl;
+    if (c.verbose && it % 1000 == 0)
+      std::fprintf(stderr,
+                   "[phsvds] stage 1%s iteration %lld: locked %d/%d, products %lld, "
+                   "theta_0 %.9e, ||r_0|| %.3e\n",
+                   fp32 ? " (float32)" : "", (long long)it, nl, k,
+                   (long long)c.st->mv_stage1, th_h[0], std::sqrt(std::max(rn_h[0], 0.0)));
     if (P.snap) P.snap(it, bf.Xb, Rb, th_h, nb, bf.Xl, nl);
     if (P.gnn && !gnn_off && P.gnn_window > 0) {
       // safeguard of the learned preconditioner: fall back to Jacobi when the
@@ -424,6 +431,9 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
         res.tight.push_back(std::sqrt(std::max(rn_h[i], 0.0)) <
                             P.tol * std::sqrt(std::max(th_h[i], 0.0)) * sn);
         ++nl;
+        if (c.verbose)
+          std::fprintf(stderr, "[phsvds] stage 1 iteration %lld: locked %d/%d, theta %.12e\n",
+                       (long long)it, nl, k, th_h[i]);
       }
       // kept basis: an orthonormal basis of the complement of the locked
       // coefficient vectors, starting with the other computed Ritz vectors
@@ -459,7 +469,21 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     const bool out_of_budget = res.restarts > P.max_restarts ||
                                (c.max_mv > 0 && c.st->mv_stage1 > c.max_mv) ||
                                (P.max_iters > 0 && it > P.max_iters);
-    if (out_of_budget) break;
+    if (out_of_budget) {
+      // the pairs still missing are returned as the leading unlocked Ritz
+      // vectors of the current basis (best approximations)
+      const int nbest = std::min(need, p);
+      if (nbest > 0) {
+        syev_rr(H, ld, p, nbest, largest, theta, S, ld, c.s);
+        nn(cm(V[cur], n, p, n), none<T>(n), S, ld, 1.0, cm(bf.Xl + (int64_t)nl * n, n, nbest, n),
+           0.0, c.s);
+        res.best_theta.resize(nbest);
+        c.d2h(res.best_theta.data(), theta, nbest * sizeof(double));
+        c.sync();
+      }
+      res.nbest = std::max(nbest, 0);
+      break;
+    }
     // correction T = Prec(R)
     if (P.gnn && !gnn_off) {
       for (int j = 0; j < nb; ++j) {
@@ -735,10 +759,18 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
     c.d2h(xt_h.data(), xt2, ns * sizeof(double));
     c.sync();
     const double r0 = std::sqrt(std::max(rn_h[0], 0.0));
+    if (c.verbose && it % 1000 == 0)
+      std::fprintf(stderr,
+                   "[phsvds] stage 2 iteration %lld: locked %d/%d, products %lld, theta %.12e, "
+                   "||r|| %.3e\n",
+                   (long long)it, nl, k2, (long long)c.st->mv_stage2, ths_h[0], r0);
     if (r0 < thr) {
       copy(rmv(bf.Xb, N, 1, bw), cm(bf.Xl + (int64_t)nl * N, N, 1, N), c.s);
       res.theta.push_back(ths_h[0]);
       ++nl;
+      if (c.verbose)
+        std::fprintf(stderr, "[phsvds] stage 2 iteration %lld: locked %d/%d, sigma %.15e\n",
+                     (long long)it, nl, k2, ths_h[0]);
       if (nl >= k2) {
         res.converged = true;
         break;

@@ -36,6 +36,7 @@ struct Ctx {
   uint64_t nrand = 0;
   phsvds_stats *st = nullptr;
   int64_t max_mv = 0;
+  int verbose = 0;  // progress lines on stderr
   void d2h(void *h, const void *d, size_t bytes);
   void h2d(void *d, const void *h, size_t bytes);
   void sync();
@@ -76,6 +77,10 @@ struct Stage1Result {
   std::vector<double> theta, res;
   std::vector<bool> tight;  // locked by the user tolerance (not by the floor)
   void *Vrest = nullptr;
+  // out of budget: the leading unlocked Ritz vectors, stored in Xl after the
+  // nl locked ones (best approximations, not converged)
+  int nbest = 0;
+  std::vector<double> best_theta;
 };
 
 struct TransBufs {

@@ -388,11 +388,59 @@ __global__ __launch_bounds__(256) void k_colnorm2(TV<T> x, int64_t r0, int64_t r
   }
 }
 
+// Row-major block (row stride W a power of two <= 256, unit column
+// stride): the rows [r0, r1) are one contiguous run of (r1 - r0) W values,
+// read in order; with a thread count that is a multiple of W, thread t
+// always meets column t mod W.
+template <typename T>
+__global__ __launch_bounds__(256) void k_colnorm2_rm(TV<T> x, int64_t r0, int64_t r1,
+                                                     double *part, const int *skip) {
+  if (skip && *skip) return;
+  __shared__ double red[256];
+  const int W = (int)x.rs;
+  const int c = threadIdx.x & (W - 1);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (c < x.cols) {
+    const int64_t hi = r1 * W, S = (int64_t)gridDim.x * blockDim.x;
+    int64_t e = r0 * W + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; e + 3 * S < hi; e += 4 * S) {
+      const double v0 = (double)x.p[e], v1 = (double)x.p[e + S];
+      const double v2 = (double)x.p[e + 2 * S], v3 = (double)x.p[e + 3 * S];
+      a0 = fma(v0, v0, a0);
+      a1 = fma(v1, v1, a1);
+      a2 = fma(v2, v2, a2);
+      a3 = fma(v3, v3, a3);
+    }
+    for (; e < hi; e += S) {
+      const double v = (double)x.p[e];
+      a0 = fma(v, v, a0);
+    }
+  }
+  red[threadIdx.x] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  for (int o = 128; o >= W; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < x.cols) part[(int64_t)blockIdx.x * x.cols + threadIdx.x] = red[threadIdx.x];
+}
+
 template <typename T>
 void colnorm2(const Tall<T> &X, int64_t r0, int64_t r1, double *out, const Scratch &sc,
               hipStream_t s, const int *skip) {
   if (X.cols == 0) return;
-  int64_t blocks = cdiv(r1 - r0 > 0 ? r1 - r0 : 1, 256 * 4);
+  const bool rm = X.rs > 1 && X.cs == 1 && X.rs <= 256 && (X.rs & (X.rs - 1)) == 0 &&
+                  X.cols <= X.rs;
+  int64_t blocks;
+  if (rm) {
+    blocks = cdiv((r1 - r0 > 0 ? r1 - r0 : 1) * X.rs, 256 * 8);
+    if (blocks > 2048) blocks = 2048;
+    k_colnorm2_rm<T><<<(unsigned)blocks, 256, 0, s>>>(tv(X), r0, r1, sc.part, skip);
+    k_reduce_vec<<<X.cols, 64, 0, s>>>(sc.part, (int)blocks, X.cols, out, nullptr, X.cols, skip);
+    PHS_CHECK_LAUNCH();
+    return;
+  }
+  blocks = cdiv(r1 - r0 > 0 ? r1 - r0 : 1, 256 * 4);
   if (blocks > 512) blocks = 512;
   k_colnorm2<T><<<(unsigned)blocks, 256, 0, s>>>(tv(X), r0, r1, sc.part, skip);
   k_reduce_vec<<<X.cols, 64, 0, s>>>(sc.part, (int)blocks, X.cols, out, nullptr, X.cols, skip);
@@ -400,20 +448,25 @@ void colnorm2(const Tall<T> &X, int64_t r0, int64_t r1, double *out, const Scrat
 }
 
 // ------------------------------------------------------- element-wise
+// One row per thread, columns in chunks of eight whose loads all precede
+// their stores: consecutive lanes take consecutive rows, so column-major
+// sides are coalesced and a row-major side is read or written one whole row
+// per lane.
 template <typename Ti, typename To>
-__global__ void k_copy(TV<Ti> a, To *bp, int64_t brs, int64_t bcs, bool dst_cm) {
-  const int64_t n = a.rows * a.cols;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    int64_t i, j;
-    if (dst_cm) {
-      i = idx % a.rows;
-      j = idx / a.rows;
-    } else {
-      i = idx / a.cols;
-      j = idx % a.cols;
+__global__ void k_copy(TV<Ti> a, To *bp, int64_t brs, int64_t bcs) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.rows;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const Ti *src = a.p + i * a.rs;
+    To *dst = bp + i * brs;
+    for (int j0 = 0; j0 < a.cols; j0 += 8) {
+      Ti v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (j0 + u < a.cols) v[u] = src[(int64_t)(j0 + u) * a.cs];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (j0 + u < a.cols) dst[(int64_t)(j0 + u) * bcs] = (To)v[u];
     }
-    bp[i * brs + j * bcs] = (To)a.p[i * a.rs + j * a.cs];
   }
 }
 
@@ -422,9 +475,9 @@ void copy(const Tall<Ti> &src, const Tall<To> &dst, hipStream_t s) {
   const int64_t n = src.rows * src.cols;
   if (n == 0) return;
   PHS_REQUIRE(src.rows == dst.rows && src.cols == dst.cols, kEinval, "copy: shape mismatch");
-  int64_t blocks = cdiv(n, 256);
+  int64_t blocks = cdiv(src.rows, 256);
   if (blocks > 8192) blocks = 8192;
-  k_copy<Ti, To><<<(unsigned)blocks, 256, 0, s>>>(tv(src), dst.p, dst.rs, dst.cs, dst.rs == 1);
+  k_copy<Ti, To><<<(unsigned)blocks, 256, 0, s>>>(tv(src), dst.p, dst.rs, dst.cs);
   PHS_CHECK_LAUNCH();
 }
 
@@ -500,27 +553,41 @@ __device__ inline double jac_den(double d, double th) {
   return den;
 }
 
+// Pass 1: T = M r with M = (diag(C) - theta)^-1, or, for the Olsen form,
+// only the block partials of x^T M r and x^T M x.  All loads of a row
+// precede its stores.
 template <typename T, int NB>
-__global__ __launch_bounds__(256) void k_jacobi1(const T *R, const T *X, const double *d,
-                                                 const double *theta, int64_t n, int ldx,
-                                                 bool olsen, T *Tout, double *part) {
-  constexpr int nb = NB;
+__global__ __launch_bounds__(256) void k_jacobi1(const T *__restrict__ R, const T *__restrict__ X,
+                                                 const double *__restrict__ d,
+                                                 const double *__restrict__ theta, int64_t n,
+                                                 int ldx, bool olsen, T *__restrict__ Tout,
+                                                 double *__restrict__ part) {
   __shared__ double red[2][256];
-  double a[NB], b[NB];
+  double th[NB], a[NB], b[NB];
 #pragma unroll
-  for (int c = 0; c < NB; ++c) a[c] = b[c] = 0.0;
+  for (int c = 0; c < NB; ++c) {
+    th[c] = theta[c];
+    a[c] = b[c] = 0.0;
+  }
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
+    const double di = d[i];
+    T rv[NB], xv[NB];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      double den = jac_den(d[i], theta[c]);
-      double mr = (double)R[i * ldx + c] / den;
-      Tout[i * ldx + c] = (T)mr;
-      if (olsen) {
-        double x = (double)X[i * ldx + c];
-        a[c] += x * mr;
-        b[c] += x * x / den;
+    for (int c = 0; c < NB; ++c) rv[c] = R[i * ldx + c];
+    if (olsen) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) xv[c] = X[i * ldx + c];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const double rd = 1.0 / jac_den(di, th[c]);
+        const double x = (double)xv[c];
+        a[c] = fma(x, (double)rv[c] * rd, a[c]);
+        b[c] = fma(x * x, rd, b[c]);
       }
+    } else {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) Tout[i * ldx + c] = (T)((double)rv[c] / jac_den(di, th[c]));
     }
   }
   if (!olsen) return;
@@ -537,23 +604,38 @@ __global__ __launch_bounds__(256) void k_jacobi1(const T *R, const T *X, const d
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      part[(int64_t)blockIdx.x * 2 * nb + c] = red[0][0];
-      part[(int64_t)blockIdx.x * 2 * nb + nb + c] = red[1][0];
+      part[(int64_t)blockIdx.x * 2 * NB + c] = red[0][0];
+      part[(int64_t)blockIdx.x * 2 * NB + NB + c] = red[1][0];
     }
     __syncthreads();
   }
 }
 
-template <typename T>
-__global__ void k_jacobi2(const T *X, const double *d, const double *theta, int64_t n, int nb,
-                          int ldx, const double *dots, T *Tout) {
+// Pass 2 of the Olsen form: T = M (r - e x), e = x^T M r / x^T M x.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_jacobi2(const T *__restrict__ R, const T *__restrict__ X,
+                                                 const double *__restrict__ d,
+                                                 const double *__restrict__ theta, int64_t n,
+                                                 int ldx, const double *__restrict__ dots,
+                                                 T *__restrict__ Tout) {
+  double th[NB], e[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    th[c] = theta[c];
+    e[c] = dots[NB + c] != 0.0 ? dots[c] / dots[NB + c] : 0.0;
+  }
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    for (int c = 0; c < nb; ++c) {
-      double e = dots[nb + c] != 0.0 ? dots[c] / dots[nb + c] : 0.0;
-      double den = jac_den(d[i], theta[c]);
-      Tout[i * ldx + c] = (T)((double)Tout[i * ldx + c] - e * (double)X[i * ldx + c] / den);
+    const double di = d[i];
+    T rv[NB], xv[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      rv[c] = R[i * ldx + c];
+      xv[c] = X[i * ldx + c];
     }
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      Tout[i * ldx + c] = (T)(((double)rv[c] - e[c] * (double)xv[c]) / jac_den(di, th[c]));
   }
 }
 
@@ -561,28 +643,33 @@ template <typename T>
 void jacobi_apply(const T *R, const T *X, const double *d, const double *theta, int64_t n,
                   int nb, int ldx, bool olsen, T *Tout, const Scratch &sc, hipStream_t s) {
   PHS_REQUIRE(nb <= kRitzMax, kEinval, "jacobi: block too wide");
+  PHS_REQUIRE(R != Tout && X != Tout, kEinval, "jacobi: output aliases an input");
   int64_t blocks = cdiv(n, 256);
   if (blocks > 1024) blocks = 1024;
-#define PHS_JAC(NB) \
-  k_jacobi1<T, NB><<<(unsigned)blocks, 256, 0, s>>>(R, X, d, theta, n, ldx, olsen, Tout, sc.part)
+#define PHS_JAC(NB)                                                                         \
+  case NB:                                                                                  \
+    k_jacobi1<T, NB><<<(unsigned)blocks, 256, 0, s>>>(R, X, d, theta, n, ldx, olsen, Tout,  \
+                                                      sc.part);                             \
+    if (olsen) {                                                                            \
+      k_reduce_vec<<<2 * NB, 64, 0, s>>>(sc.part, (int)blocks, 2 * NB, sc.aux, nullptr,     \
+                                         2 * NB);                                           \
+      k_jacobi2<T, NB><<<(unsigned)blocks, 256, 0, s>>>(R, X, d, theta, n, ldx, sc.aux, Tout); \
+    }                                                                                       \
+    break;
   switch (nb) {
-    case 1: PHS_JAC(1); break;
-    case 2: PHS_JAC(2); break;
-    case 3: PHS_JAC(3); break;
-    case 4: PHS_JAC(4); break;
-    case 5: PHS_JAC(5); break;
-    case 6: PHS_JAC(6); break;
-    case 7: PHS_JAC(7); break;
-    case 8: PHS_JAC(8); break;
-    case 16: PHS_JAC(16); break;
-    case 32: PHS_JAC(32); break;
+    PHS_JAC(1)
+    PHS_JAC(2)
+    PHS_JAC(3)
+    PHS_JAC(4)
+    PHS_JAC(5)
+    PHS_JAC(6)
+    PHS_JAC(7)
+    PHS_JAC(8)
+    PHS_JAC(16)
+    PHS_JAC(32)
     default: throw Error(kEinval, "jacobi: unsupported block width");
   }
 #undef PHS_JAC
-  if (olsen) {
-    k_reduce_vec<<<2 * nb, 64, 0, s>>>(sc.part, (int)blocks, 2 * nb, sc.aux, nullptr, 2 * nb);
-    k_jacobi2<T><<<(unsigned)blocks, 256, 0, s>>>(X, d, theta, n, nb, ldx, sc.aux, Tout);
-  }
   PHS_CHECK_LAUNCH();
 }
 

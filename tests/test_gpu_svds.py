@@ -139,3 +139,30 @@ def test_jacobi_random_sparse_vs_dense_definition():
     U, V = _check(A, sig, U, V, info, sigx, an)
     for i in range(4):
         assert abs(abs(V[:, i] @ Vx[:, i]) - 1) < 1e-10
+
+
+@gpu
+@pytest.mark.parametrize("mixed", [False, True])
+def test_out_of_budget_returns_best_approximations(mixed):
+    """A solve stopped by its product budget returns status 1 with every
+    triplet filled: the unlocked pairs are the current Ritz approximations,
+    each with its true float64 residual, and a Ritz value of C bounds the
+    smallest singular value from above."""
+    need_gpu()
+    N = 32
+    A = wl.grid_gradient(N)
+    an = cf.grid_norm(N)
+    k = 6
+    say(f"grid N={N} k={k} b=2 max_matvecs=40 mixed={mixed}")
+    sig, U, V, info = _solve(A, k, b=2, anorm=an, max_matvecs=40, stage1_fp32=mixed)
+    say(info)
+    U, V = as_np(U), as_np(V)
+    assert info["status"] == 1
+    assert np.all(np.isfinite(sig)) and np.all(np.isfinite(info["res"]))
+    assert np.all(np.diff(sig) >= 0)
+    res = dense.triplet_residuals(A, sig, U, V)
+    assert np.allclose(res, info["res"], rtol=1e-6, atol=1e-14 * an)
+    assert np.max(res) > 1e-12 * an
+    assert np.allclose(np.linalg.norm(U, axis=0), 1.0, atol=1e-12)
+    assert np.allclose(np.linalg.norm(V, axis=0), 1.0, atol=1e-12)
+    assert sig[0] >= cf.grid_sigmas(N)[0] * (1 - 1e-12)
