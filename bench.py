@@ -140,7 +140,7 @@ def host_residuals(A, AT, sig, U, V):
     return np.sqrt(np.sum(ru * ru, axis=0) + np.sum(rv * rv, axis=0))
 
 
-def compare(family, max_mv, gnn_weights, gnn_width, max_restarts=10000):
+def compare(family, max_mv, gnn_weights, gnn_width, max_restarts=10000, only=None):
     """End-to-end comparison of the method's arms (float64 or float32 stage 1,
     none / Jacobi / learned preconditioner) on one matrix of a family.  One
     JSON line per arm, then a summary line.  Residuals are recomputed on the
@@ -164,6 +164,8 @@ def compare(family, max_mv, gnn_weights, gnn_width, max_restarts=10000):
     if gnn_weights:
         w = torch.tensor(np.load(gnn_weights), dtype=torch.float32, device="cuda")
         arms += [("mixed", "gnn")]
+    if only:
+        arms = [tuple(a.split("+")) for a in only]
     cap = max_mv or cfg["cap"]
     rows, ref = [], None
     for prec, pre in arms:
@@ -276,6 +278,8 @@ def main():
                          "none / Jacobi (/ learned, with --gnn-weights) on one matrix of a family")
     ap.add_argument("--gnn-weights", default="", help="trained weights (.npy) for --compare")
     ap.add_argument("--gnn-width", type=int, default=32)
+    ap.add_argument("--arms", nargs="*", default=None,
+                    help="arms to run in --compare, e.g. f64+jacobi mixed+gnn")
     ap.add_argument("--max-restarts", type=int, default=10000,
                     help="restart limit per stage for --compare (Section 5 uses 10000)")
     ap.add_argument("--spmm-probe", choices=["grid", "random", "powerlaw"],
@@ -284,7 +288,8 @@ def main():
                          "grid: --N, b=4), for counter runs")
     args = ap.parse_args()
     if args.compare:
-        compare(args.compare, args.max_mv, args.gnn_weights, args.gnn_width, args.max_restarts)
+        compare(args.compare, args.max_mv, args.gnn_weights, args.gnn_width, args.max_restarts,
+                args.arms)
         return
     if args.spmm_probe:
         spmm_probe(args.spmm_probe, args.N)

@@ -151,7 +151,9 @@ int phsvds_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int k, const phsvd
  * m >= n, tol > 0.  On PHSVDS_NOT_CONVERGED (restart or product budget
  * spent) every triplet is still filled: the pairs not locked are the
  * leading Ritz approximations of the final basis, u = A v / ||A v||, with
- * their explicit residuals in resnorm. */
+ * their explicit residuals in resnorm.  Device memory comes only from the
+ * workspace; the call allocates one 64 KB pinned host buffer for its
+ * per-iteration status reads and frees it before returning. */
 int phsvds_svds(const phsvds_csr *A, int k, double tol, const phsvds_precond *P,
                 const phsvds_opts *opts, void *workspace, size_t ws_bytes, void *stream,
                 double *sigma, double *U, double *V, double *resnorm, phsvds_stats *stats);

@@ -225,10 +225,15 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
   }
   __syncthreads();
   // 1. reduction of row i onto position i - 1 (l = i - 1).  Every wave
-  //    forms the reflector from row i itself (identical values, so every
-  //    wave takes the same branches); the product A v and the rank-two
-  //    update are split into column blocks of 16, one per wave.
+  //    forms the reflector from row i itself and, after the cross-wave sum
+  //    of A v, the vector q itself (identical values in every wave, so
+  //    every wave takes the same branches); the product A v and the
+  //    rank-two update are split into column blocks of 16, one per wave.
+  //    Each wave keeps its own copies of v and q (in uu and ll, unused
+  //    until step 3), so a step has two block barriers: after the partial
+  //    products, and after the update.
   const int kb = 16 * w;  // this wave's column block
+  double *vw = uu + w * kSmallMax, *qw = ll + w * kSmallMax;
   for (int i = n - 1; i >= 2; --i) {
     const int l = i - 1;
     const double xi = (t <= l) ? a[i * kLd + t] : 0.0;
@@ -249,14 +254,14 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
     const double h = sigma - f * g;
     const double ih = 1.0 / h;
     const double v = (t == l) ? f - g : xs;  // reflector I - v v^T / h; 0 past l
-    if (w0) vv[t] = v;
+    vw[t] = v;
     if (threadIdx.x == 0) {
       e[i] = scale * g;
       hh[i] = h;
       rh[i] = ih;
     }
-    __syncthreads();
-    // partial (A v)_t over this wave's column block (vv is 0 past l)
+    wave_sync();
+    // partial (A v)_t over this wave's column block (v is 0 past l)
     {
       double s0 = 0.0, s1 = 0.0;
       if (t <= l) {
@@ -267,7 +272,7 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             av[u] = a[t * kLd + kb + c8 + u];
-            vk[u] = vv[kb + c8 + u];
+            vk[u] = vw[kb + c8 + u];
           }
           s0 = fma(av[0], vk[0], s0); s1 = fma(av[1], vk[1], s1);
           s0 = fma(av[2], vk[2], s0); s1 = fma(av[3], vk[3], s1);
@@ -283,8 +288,8 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
                                : 0.0;
     const double K = wave_total(v * pj) * (0.5 * ih);
     const double qj = (t <= l) ? pj - K * v : 0.0;
-    if (w0) pq[t] = qj;
-    __syncthreads();
+    qw[t] = qj;
+    wave_sync();
     // rank-two update of this wave's column block; columns past l see
     // q = v = 0 and stay unchanged
     if (t <= l) {
@@ -294,8 +299,8 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
         double qk[8], vk[8], av[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          qk[u] = pq[kb + c8 + u];
-          vk[u] = vv[kb + c8 + u];
+          qk[u] = qw[kb + c8 + u];
+          vk[u] = vw[kb + c8 + u];
           av[u] = a[t * kLd + kb + c8 + u];
         }
 #pragma unroll

@@ -16,10 +16,29 @@
 
 namespace phs {
 
+constexpr size_t kPinBytes = 64 * 1024;
+
 void Ctx::d2h(void *h, const void *d, size_t bytes) {
-  PHS_HIP(hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s));
+  if (!pin_) PHS_HIP(hipHostMalloc((void **)&pin_, kPinBytes, hipHostMallocDefault));
+  const size_t off = (pin_used_ + 15) & ~(size_t)15;
+  if (off + bytes > kPinBytes) {  // larger than the staging buffer: direct copy
+    PHS_HIP(hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s));
+    PHS_HIP(hipStreamSynchronize(s));
+    return;
+  }
+  PHS_HIP(hipMemcpyAsync(pin_ + off, d, bytes, hipMemcpyDeviceToHost, s));
+  pending_.push_back({h, off, bytes});
+  pin_used_ = off + bytes;
 }
-void Ctx::sync() { PHS_HIP(hipStreamSynchronize(s)); }
+void Ctx::sync() {
+  PHS_HIP(hipStreamSynchronize(s));
+  for (const Pending &q : pending_) std::memcpy(q.h, pin_ + q.off, q.bytes);
+  pending_.clear();
+  pin_used_ = 0;
+}
+Ctx::~Ctx() {
+  if (pin_) (void)hipHostFree(pin_);
+}
 void Ctx::h2d(void *d, const void *h, size_t bytes) {
   // pageable source: the runtime stages it before returning
   PHS_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));

@@ -37,9 +37,25 @@ struct Ctx {
   phsvds_stats *st = nullptr;
   int64_t max_mv = 0;
   int verbose = 0;  // progress lines on stderr
+  // device-to-host reads go through one pinned staging buffer: d2h queues
+  // the copy, sync() waits for the stream and moves the bytes to their
+  // destinations (a destination is valid only after the next sync())
   void d2h(void *h, const void *d, size_t bytes);
   void h2d(void *d, const void *h, size_t bytes);
   void sync();
+  Ctx() = default;
+  Ctx(const Ctx &) = delete;
+  Ctx &operator=(const Ctx &) = delete;
+  ~Ctx();
+
+ private:
+  struct Pending {
+    void *h;
+    size_t off, bytes;
+  };
+  char *pin_ = nullptr;
+  size_t pin_used_ = 0;
+  std::vector<Pending> pending_;
 };
 
 struct Stage1Params {

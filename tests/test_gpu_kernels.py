@@ -116,3 +116,60 @@ def test_rr_eig_selected_pairs(case):
             res = np.linalg.norm(H @ Sv - Sv * th[:nvec], axis=0)
             assert np.max(res) <= 1e-14 * nrm + 1e-30, (name, nvec, largest)
             assert np.max(np.abs(Sv.T @ Sv - np.eye(nvec))) <= 1e-13, (name, nvec, largest)
+
+
+_FULL = {}
+
+
+def _full(family):
+    """Full-size matrices of the benchmark families (built once per session)."""
+    if family not in _FULL:
+        if family == "weighted1024":
+            _FULL[family] = wl.grid_gradient(1024, weights="lognormal", seed=3)
+        else:
+            _FULL[family] = wl.powerlaw_sparse()
+    return _FULL[family]
+
+
+@gpu
+@pytest.mark.parametrize("family", ["weighted1024", "powerlaw"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_spmm_full_size_sampled_rows(family, dtype):
+    """A X and A^T Y at the full sizes of the weighted N=1024 grid
+    (2099200 x 1048576) and the power-law matrix (4M x 3M, rows up to 2000
+    entries), block 8, with the launch configuration the solver uses;
+    sampled rows (seeded, plus the longest row and both ends) against SciPy
+    in float64 within the forward-error bound (len + 2) u sum |a||x|."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A = _full(family)
+    m, n = A.shape
+    b = 8
+    say("spmm full size", family, dtype, A.shape, A.nnz)
+    r = np.random.default_rng(5)
+    X = r.standard_normal((n, b))
+    Ad = to_dev(A)
+    At = P.csr_transpose(Ad)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    u = 2.0 ** -53 if dtype == "f64" else 2.0 ** -24
+    Aref = A if dtype == "f64" else A.astype(np.float32).astype(np.float64)
+    Xd = torch.tensor(X, dtype=tdt, device="cuda")
+    Xref = X if dtype == "f64" else X.astype(np.float32).astype(np.float64)
+    Y = P.spmm(Ad, Xd)
+    lens = np.diff(A.indptr)
+    rows = np.unique(np.r_[r.choice(m, 4096, replace=False), np.argmax(lens), 0, m - 1])
+    Yh = as_np(Y[torch.tensor(rows, device="cuda")]).astype(np.float64)
+    ref = Aref[rows] @ Xref
+    bound = (lens[rows] + 2)[:, None] * u * (abs(Aref[rows]) @ abs(Xref)) + 1e-300
+    assert np.all(np.abs(Yh - ref) <= bound)
+    # A^T Y through the device transpose: columns of A are the rows of A^T
+    Yfull = Y.double().cpu().numpy()
+    Yin = Yfull if dtype == "f64" else Yfull.astype(np.float32).astype(np.float64)
+    Z = P.spmm(At, torch.tensor(Yin, dtype=tdt, device="cuda"))
+    cl = np.bincount(A.indices, minlength=n)
+    cols = np.unique(np.r_[r.choice(n, 4096, replace=False), np.argmax(cl), 0, n - 1])
+    Zh = as_np(Z[torch.tensor(cols, device="cuda")]).astype(np.float64)
+    AcT = Aref.tocsc()[:, cols].T.tocsr()
+    zref = AcT @ Yin
+    zb = (cl[cols] + 2)[:, None] * u * (abs(AcT) @ abs(Yin)) + 1e-300
+    assert np.all(np.abs(Zh - zref) <= zb)

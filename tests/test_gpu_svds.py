@@ -84,6 +84,23 @@ def test_grid_n128_both_ends_closed_form(which):
 
 
 @gpu
+def test_grid_n512_benchmark_configuration():
+    """The benchmark's solve at full size: N = 512 (m = 525312, n = 262144),
+    k = 10 smallest, block 4, float64, the paper's start block; sigma
+    against the closed form and float64 residuals recomputed on the host."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    N = 512
+    A = wl.grid_gradient(N)
+    an = cf.grid_norm(N)
+    say("grid N=512 k=10 b=4 (benchmark configuration)")
+    sig, U, V, info = P.svds_smallest(to_dev(A), 10, 1e-12, block=4)
+    say({k: info[k] for k in ("status", "mv_total", "iters1", "stage2_pairs")})
+    _check(A, sig, U, V, info, cf.grid_sigmas(N)[:10], an)
+    assert info["stage2_pairs"] == 0
+
+
+@gpu
 def test_givens_two_stage_closed_form():
     need_gpu()
     n, m = 200, 240
