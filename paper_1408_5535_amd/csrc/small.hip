@@ -357,7 +357,9 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
   __syncthreads();
   if (w0) {
   // 3. inverse iteration on (T - lambda I)/||T|| = L U without pivoting,
-  //    tiny pivots replaced; three sweeps.  Rows n..n+7 of the column are
+  //    tiny pivots replaced; two sweeps from a pseudo-random start (the
+  //    shift is accurate to rounding, so each sweep reduces every other
+  //    component by gap / rounding).  Rows n..n+7 of the column are
   //    zero padding (multiplier 0), so the chunked loops need no guards.
   if (t < nvec) {
     const int c = t;
@@ -365,15 +367,17 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
     const double tiny = 1e-3 * eps;
     double u = ds[0] - lam;
     if (fabs(u) < tiny) u = tiny;
-    uu[c] = 1.0 / u;
+    double ru = 1.0 / u;  // one division per row: the multiplier reuses it
+    uu[c] = ru;
     ll[c] = 0.0;
     for (int i = 1; i < n; ++i) {
       const double es = e[i] * sc;
-      const double li = es / u;
+      const double li = es * ru;
       ll[i * kLd + c] = li;
       u = ds[i] - lam - li * es;
       if (fabs(u) < tiny) u = tiny;
-      uu[i * kLd + c] = 1.0 / u;
+      ru = 1.0 / u;
+      uu[i * kLd + c] = ru;
     }
     for (int i = 0; i < n; ++i) {
       uint32_t hsh = (uint32_t)(i * kSmallMax + c + 1) * 0x9E3779B9u;
@@ -393,7 +397,8 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
   // superdiagonal of the scaled T, shared: es1[i] = e_{i+1} / ||T||
   es1[t] = (t + 1 < n) ? e[t + 1] * sc : 0.0;
   wave_sync();
-  for (int sweep = 0; sweep < 3; ++sweep) {
+  constexpr int kSweeps = 2;
+  for (int sweep = 0; sweep < kSweeps; ++sweep) {
     if (t < nvec) {
       const int c = t;
       // L w = y
@@ -492,7 +497,7 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
     // 1e-10 ||T||, after the last sweep within 1e-3 ||T||; lanes split the
     // dot products, then the rows; repeated when the first pass cancels
     // more than half
-    const int *start = sweep == 2 ? cstart : tstart;
+    const int *start = sweep == kSweeps - 1 ? cstart : tstart;
     for (int c = 1; c < nvec; ++c) {
       const int st = start[c];
       if (st == c) continue;
