@@ -25,7 +25,8 @@ struct SpMat {
 
 int lanes_for_length(double avg);
 template <typename T>
-void spmm(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, hipStream_t s);
+void spmm(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, hipStream_t s,
+          int64_t ycm = 0, int ycols = 0);
 size_t transpose_ws_bytes(int64_t m, int64_t n, int64_t nnz);
 void csr_transpose(int64_t m, int64_t n, int64_t nnz, const int64_t *rp, const int32_t *ci,
                    const double *va, int64_t *trp, int32_t *tci, double *tva, void *ws,
@@ -77,11 +78,13 @@ constexpr int64_t kAuxCap = 1 << 16;
 // G (nx x ny, ld ldg, float64) = X^T Y, X = [X1 | X2] (X2 may have 0 cols).
 template <typename T>
 void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int ldg,
-        const Scratch &sc, hipStream_t s, const int *skip = nullptr);
-// Y = alpha * [X1 | X2] S + beta * Y, S float64 (nx x ny, ld lds).
+        const Scratch &sc, hipStream_t s);
+// Y = alpha * [X1 | X2] S + beta * Z, S float64 (nx x ny, ld lds); Z is Y
+// itself unless given.  If Y2 is given the result is written there too.
 template <typename T>
 void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double alpha,
-        const Tall<T> &Y, double beta, hipStream_t s, const int *skip = nullptr);
+        const Tall<T> &Y, double beta, hipStream_t s, const Tall<T> *Z = nullptr,
+        const Tall<T> *Y2 = nullptr);
 // Ritz block: X = V S, R = W S - X diag(theta) (row-major outputs, row stride ldx),
 // rn2[j] = ||R_:,j||^2; if ntop > 0 also xt2[j] = ||X_{0:ntop, j}||^2.
 template <typename T>
@@ -91,9 +94,7 @@ void ritz(const Tall<T> &V, const Tall<T> &W, const double *S, int lds, const do
 // out[j] = sum_i X(i, j)^2 over rows [r0, r1) (float64 result, device).
 template <typename T>
 void colnorm2(const Tall<T> &X, int64_t r0, int64_t r1, double *out, const Scratch &sc,
-              hipStream_t s, const int *skip = nullptr);
-// A skip argument (device int, may be null) makes tn, nn and colnorm2 return
-// without work when it is nonzero (work decided on the device).
+              hipStream_t s);
 // dst = src elementwise (any layouts, same shape), with type conversion.
 template <typename Ti, typename To>
 void copy(const Tall<Ti> &src, const Tall<To> &dst, hipStream_t s);
@@ -129,8 +130,17 @@ void svdj(const double *M, int ldm, int rows, int cols, double *sv, double *Y, i
           hipStream_t s);
 // Cholesky G + shift I = R^T R (w x w) and Rinv = R^-1 (upper triangular,
 // ld ldr).  flag[0] = 1 on breakdown (non-positive pivot).
+// Optional diagnostics of a block after two classical Gram-Schmidt passes
+// T1 = T0 - Q H1, T2 = T1 - Q H2 against an orthonormal Q (nh columns) when
+// G = T2^T T2: n2 = diag(G), n1 = n2 + colsum(H2^2), n0 = n1 + colsum(H1^2)
+// (the squared column norms of T2, T1 and T0).
+struct CgsDiag {
+  const double *H1 = nullptr, *H2 = nullptr;
+  int ldh = 0, nh = 0;
+  double *n0 = nullptr, *n1 = nullptr, *n2 = nullptr;
+};
 void chol_inv(const double *G, int ldg, int w, double shift, double *R, double *Rinv, int ldr,
-              int *flag, hipStream_t s);
+              int *flag, hipStream_t s, const CgsDiag *dg = nullptr);
 // C = alpha op(A) op(B) + beta C, all small float64.
 void small_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const double *A, int lda,
                 const double *B, int ldb, double beta, double *C, int ldc, hipStream_t s);

@@ -659,11 +659,26 @@ void svdj(const double *M, int ldm, int rows, int cols, double *sv, double *Y, i
 
 // -------------------------------------------------------- chol_inv
 __global__ __launch_bounds__(256) void k_chol_inv(const double *G, int ldg, int w, double shift,
-                                                  double *Rg, double *Ri, int ldr, int *flag) {
+                                                  double *Rg, double *Ri, int ldr, int *flag,
+                                                  CgsDiag dg) {
   __shared__ double r[kSmallMax * kLd];  // r[i * kLd + j], upper triangle used
   __shared__ int bad;
   const int t = threadIdx.x;
   if (t == 0) bad = 0;
+  if (dg.n2 && t < w) {
+    // squared column norms around two Gram-Schmidt passes from the final
+    // Gram matrix and the two coefficient blocks
+    double h1 = 0.0, h2 = 0.0;
+    for (int i = 0; i < dg.nh; ++i) {
+      const double c1 = dg.H1[i + (int64_t)t * dg.ldh], c2 = dg.H2[i + (int64_t)t * dg.ldh];
+      h1 = fma(c1, c1, h1);
+      h2 = fma(c2, c2, h2);
+    }
+    const double a2 = G[t + (int64_t)t * ldg];
+    dg.n2[t] = a2;
+    dg.n1[t] = a2 + h2;
+    dg.n0[t] = a2 + h2 + h1;
+  }
   for (int idx = t; idx < w * w; idx += blockDim.x) {
     int i = idx % w, j = idx / w;
     r[i * kLd + j] = 0.5 * (G[i + (int64_t)j * ldg] + G[j + (int64_t)i * ldg]) +
@@ -712,9 +727,11 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double *G, int ldg, int 
 }
 
 void chol_inv(const double *G, int ldg, int w, double shift, double *R, double *Rinv, int ldr,
-              int *flag, hipStream_t s) {
+              int *flag, hipStream_t s, const CgsDiag *dg) {
   PHS_REQUIRE(w >= 1 && w <= kSmallMax, kEinval, "chol_inv: size out of range");
-  k_chol_inv<<<1, 256, 0, s>>>(G, ldg, w, shift, R, Rinv, ldr, flag);
+  PHS_REQUIRE(!dg || (dg->nh >= 0 && dg->ldh >= dg->nh), kEinval,
+              "chol_inv: bad diagnostics operands");
+  k_chol_inv<<<1, 256, 0, s>>>(G, ldg, w, shift, R, Rinv, ldr, flag, dg ? *dg : CgsDiag{});
   PHS_CHECK_LAUNCH();
 }
 

@@ -214,7 +214,7 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
   T *Tb = bf.Tb, *T2b = bf.T2b, *Rb = bf.Rb;
   double *H = sp.mat(4), *Sa = sp.mat(5), *Y = sp.mat(6), *Hs = sp.mat(7), *prev = sp.mat(8),
          *prev2 = sp.mat(9), *Gb = sp.mat(10), *Sb = sp.mat(34), *G = sp.mat(0),
-         *Gram = sp.mat(1), *R1 = sp.mat(2), *Ri1 = sp.mat(3);
+         *Gram = sp.mat(1), *R1 = sp.mat(2), *Ri1 = sp.mat(3), *G2 = sp.mat(38);
   // packed status block: theta | rn2 | n0 | n1 | n2 | rho2 | flags
   double *stat = sp.vec(22);
   double *theta = stat, *rn2 = stat + 64, *sn0 = stat + 128, *sn1 = stat + 160,
@@ -238,11 +238,15 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     spmm(At, bw, bf.Yb, bf.WTb, false, c.s);
     c.st->mv_stage1 += nb;
   };
-  auto append = [&](int nb) {
-    applyC(Tb, nb);
-    copy(rmv(Tb, n, nb, bw), cm(V[cur] + (int64_t)p * n, n, nb, n), c.s);
-    copy(rmv(bf.WTb, n, nb, bw), cm(W[cur] + (int64_t)p * n, n, nb, n), c.s);
-    tn(cm(V[cur], n, p + nb, n), none<T>(n), rmv(bf.WTb, n, nb, bw), Gb, ld, c.sc, c.s);
+  // W_T = C T goes straight into the new columns of W; V's new columns are
+  // copied from T unless the caller has written them already
+  auto append = [&](int nb, bool v_written) {
+    spmm(A, bw, Tb, bf.Yb, false, c.s);
+    spmm(At, bw, bf.Yb, W[cur] + (int64_t)p * n, false, c.s, n, nb);
+    c.st->mv_stage1 += nb;
+    if (!v_written) copy(rmv(Tb, n, nb, bw), cm(V[cur] + (int64_t)p * n, n, nb, n), c.s);
+    tn(cm(V[cur], n, p + nb, n), none<T>(n), cm(W[cur] + (int64_t)p * n, n, nb, n), Gb, ld,
+       c.sc, c.s);
     h_border(H, ld, p, nb, Gb, ld, c.s);
     if (nprev) zero_rows(prev, ld, p, p + nb, nprev, c.s);
     p += nb;
@@ -250,33 +254,47 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
   // checked expansion (host decisions on dependence and breakdown)
   auto expand = [&](int nb) {
     orth_block(c, Tb, T2b, n, nb, bw, cm(bf.Xl, n, nl, n), cm(V[cur], n, p, n), dep_drop, sp);
-    append(nb);
+    append(nb, false);
   };
-  // unchecked expansion: CGS2 + CholQR2, diagnostics left in the status block
+  // unchecked expansion: CGS2 + CholQR2, diagnostics left in the status
+  // block.  The correction itself is left untouched (a rollback redoes the
+  // expansion from it); the passes work in the two other block buffers and
+  // the last one also writes the new columns of V.
   auto expand_fast = [&](int nb) {
-    copy(rmv(Tb, n, nb, bw), rmv(bf.Fb, n, nb, bw), c.s);  // kept for a rollback
-    Tall<T> Tv = rmv(Tb, n, nb, bw);
+    T *orig = Tb, *w1 = T2b, *w2 = bf.Fb;
     const Tall<T> B1 = cm(bf.Xl, n, nl, n), B2 = cm(V[cur], n, p, n);
-    colnorm2(Tv, 0, n, sn0, c.sc, c.s);
+    const Tall<T> T0 = rmv(orig, n, nb, bw), T1 = rmv(w1, n, nb, bw), T2 = rmv(w2, n, nb, bw);
     // classical Gram-Schmidt, always twice: a single pass that cancels
     // little (unpreconditioned corrections are nearly orthogonal to V
     // already) still left enough of V in T to stall the largest-mode
     // iteration at the 1e-12 level
-    for (int pass = 0; pass < 2; ++pass) {
-      tn(B1, B2, Tv, G, ld, c.sc, c.s);
-      nn(B1, B2, G, ld, -1.0, Tv, 1.0, c.s);
-      colnorm2(Tv, 0, n, pass == 0 ? sn1 : sn2v, c.sc, c.s);
-    }
-    for (int q = 0; q < 2; ++q) {
-      Tall<T> Tq = rmv(Tb, n, nb, bw);
-      tn(Tq, none<T>(n), Tq, Gram, ld, c.sc, c.s);
-      chol_inv(Gram, ld, nb, 0.0, R1, Ri1, ld, sflag + q, c.s);
-      nn(Tq, none<T>(n), Ri1, ld, 1.0, rmv(T2b, n, nb, bw), 0.0, c.s);
-      std::swap(Tb, T2b);
-    }
+    tn(B1, B2, T0, G, ld, c.sc, c.s);
+    nn(B1, B2, G, ld, -1.0, T1, 1.0, c.s, &T0);
+    tn(B1, B2, T1, G2, ld, c.sc, c.s);
+    nn(B1, B2, G2, ld, -1.0, T1, 1.0, c.s);
+    // CholQR2; the first Cholesky also leaves the squared norms of the
+    // block before, between and after the two passes in the status block
+    CgsDiag dg;
+    dg.H1 = G;
+    dg.H2 = G2;
+    dg.ldh = ld;
+    dg.nh = nl + p;
+    dg.n0 = sn0;
+    dg.n1 = sn1;
+    dg.n2 = sn2v;
+    tn(T1, none<T>(n), T1, Gram, ld, c.sc, c.s);
+    chol_inv(Gram, ld, nb, 0.0, R1, Ri1, ld, sflag, c.s, &dg);
+    nn(T1, none<T>(n), Ri1, ld, 1.0, T2, 0.0, c.s);
+    tn(T2, none<T>(n), T2, Gram, ld, c.sc, c.s);
+    chol_inv(Gram, ld, nb, 0.0, R1, Ri1, ld, sflag + 1, c.s);
+    const Tall<T> Vn = cm(V[cur] + (int64_t)p * n, n, nb, n);
+    nn<T>(T2, none<T>(n), Ri1, ld, 1.0, T1, 0.0, c.s, nullptr, &Vn);
+    Tb = w1;
+    T2b = w2;
+    bf.Fb = orig;
     pend_nb = nb;
     pend_p = p;
-    append(nb);
+    append(nb, true);
   };
 
   // initial block (Section 5: ones(n,1)/sqrt(n) plus seeded random columns),

@@ -30,7 +30,8 @@ namespace phs {
 // Each slot takes every G-th nonzero of the row, kSpU at a time (their
 // indices and values first, then kSpU independent gathers); the G slots'
 // partial sums are combined by shuffles and the VL lanes of slot 0 store
-// their chunks of the Y row.
+// their chunks of the Y row (or, with ycm > 0, the first ycols values of
+// the row into a column-major Y with leading dimension ycm).
 constexpr int kSpU = 4;
 
 template <typename T, int B>
@@ -67,7 +68,8 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nrows, const int32_t *__re
                                               const int64_t *__restrict__ rp,
                                               const int32_t *__restrict__ ci,
                                               const T *__restrict__ va,
-                                              const T *__restrict__ X, T *__restrict__ Y) {
+                                              const T *__restrict__ X, T *__restrict__ Y,
+                                              int64_t ycm, int ycols) {
   constexpr int VL = SpVec<T, B>::VL, CW = SpVec<T, B>::CW, GL = G * VL;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t slot = gid / GL;
@@ -112,12 +114,21 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nrows, const int32_t *__re
       for (int j = 0; j < CW; ++j) acc[j] += __shfl_xor(acc[j], off * VL, GL);
     }
   }
-  if (g == 0) store_chunk<T, CW>(Y + row * B + part * CW, acc);
+  if (g == 0) {
+    if (ycm == 0) {
+      store_chunk<T, CW>(Y + row * B + part * CW, acc);
+    } else {
+#pragma unroll
+      for (int j = 0; j < CW; ++j)
+        if (part * CW + j < ycols) Y[row + (int64_t)(part * CW + j) * ycm] = acc[j];
+    }
+  }
 }
 
 template <typename T, int B, bool ABS>
 static void launch_g(int G, int64_t nrows, const int32_t *rows, const int64_t *rp,
-                     const int32_t *ci, const T *va, const T *X, T *Y, hipStream_t s) {
+                     const int32_t *ci, const T *va, const T *X, T *Y, int64_t ycm, int ycols,
+                     hipStream_t s) {
   if (nrows <= 0) return;
   constexpr int VL = SpVec<T, B>::VL;
   constexpr int Gmax = 64 / VL;  // a row group stays inside one wavefront
@@ -125,21 +136,21 @@ static void launch_g(int G, int64_t nrows, const int32_t *rows, const int64_t *r
   const int64_t threads = nrows * G * VL;
   dim3 grid(cdiv(threads, 256));
   switch (G) {
-    case 1: k_spmm<T, B, 1, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
-    case 2: k_spmm<T, B, 2, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
-    case 4: k_spmm<T, B, 4, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
-    case 8: k_spmm<T, B, 8, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y); break;
+    case 1: k_spmm<T, B, 1, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y, ycm, ycols); break;
+    case 2: k_spmm<T, B, 2, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y, ycm, ycols); break;
+    case 4: k_spmm<T, B, 4, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y, ycm, ycols); break;
+    case 8: k_spmm<T, B, 8, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y, ycm, ycols); break;
     case 16:
       if constexpr (Gmax >= 16)
-        k_spmm<T, B, 16, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y);
+        k_spmm<T, B, 16, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y, ycm, ycols);
       break;
     case 32:
       if constexpr (Gmax >= 32)
-        k_spmm<T, B, 32, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y);
+        k_spmm<T, B, 32, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y, ycm, ycols);
       break;
     default:
       if constexpr (Gmax >= 64)
-        k_spmm<T, B, 64, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y);
+        k_spmm<T, B, 64, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y, ycm, ycols);
       break;
   }
   PHS_CHECK_LAUNCH();
@@ -147,20 +158,22 @@ static void launch_g(int G, int64_t nrows, const int32_t *rows, const int64_t *r
 
 template <typename T, bool ABS>
 static void launch_b(int b, int G, int64_t nrows, const int32_t *rows, const int64_t *rp,
-                     const int32_t *ci, const T *va, const T *X, T *Y, hipStream_t s) {
+                     const int32_t *ci, const T *va, const T *X, T *Y, int64_t ycm, int ycols,
+                     hipStream_t s) {
   switch (b) {
-    case 1: launch_g<T, 1, ABS>(G, nrows, rows, rp, ci, va, X, Y, s); break;
-    case 2: launch_g<T, 2, ABS>(G, nrows, rows, rp, ci, va, X, Y, s); break;
-    case 4: launch_g<T, 4, ABS>(G, nrows, rows, rp, ci, va, X, Y, s); break;
-    case 8: launch_g<T, 8, ABS>(G, nrows, rows, rp, ci, va, X, Y, s); break;
-    case 16: launch_g<T, 16, ABS>(G, nrows, rows, rp, ci, va, X, Y, s); break;
-    case 32: launch_g<T, 32, ABS>(G, nrows, rows, rp, ci, va, X, Y, s); break;
+    case 1: launch_g<T, 1, ABS>(G, nrows, rows, rp, ci, va, X, Y, ycm, ycols, s); break;
+    case 2: launch_g<T, 2, ABS>(G, nrows, rows, rp, ci, va, X, Y, ycm, ycols, s); break;
+    case 4: launch_g<T, 4, ABS>(G, nrows, rows, rp, ci, va, X, Y, ycm, ycols, s); break;
+    case 8: launch_g<T, 8, ABS>(G, nrows, rows, rp, ci, va, X, Y, ycm, ycols, s); break;
+    case 16: launch_g<T, 16, ABS>(G, nrows, rows, rp, ci, va, X, Y, ycm, ycols, s); break;
+    case 32: launch_g<T, 32, ABS>(G, nrows, rows, rp, ci, va, X, Y, ycm, ycols, s); break;
     default: throw Error(kEinval, "spmm: block width must be 1, 2, 4, 8, 16 or 32");
   }
 }
 
 template <typename T>
-void spmm_launch(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, hipStream_t s);
+void spmm_launch(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, int64_t ycm,
+                 int ycols, hipStream_t s);
 
 int lanes_for_length(double avg) {
   if (avg <= 4) return 1;
@@ -173,10 +186,13 @@ int lanes_for_length(double avg) {
 }
 
 template <typename T>
-void spmm(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, hipStream_t s) {
+void spmm(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, hipStream_t s, int64_t ycm,
+          int ycols) {
   const int kind = sizeof(T) == 8 ? kProfSpmm64 : kProfSpmm32;
+  PHS_REQUIRE(ycm == 0 || (ycm >= A.m && ycols >= 1 && ycols <= b), kEinval,
+              "spmm: bad column-major output");
   prof_begin(kind, s);
-  spmm_launch(A, b, X, Y, absval, s);
+  spmm_launch(A, b, X, Y, absval, ycm, ycols, s);
   // algorithmic bytes: values + column indices + row pointers + X + Y
   prof_end(kind, s,
            (double)A.nnz * (sizeof(T) + 4) + (double)(A.m + 1) * 8 +
@@ -184,28 +200,30 @@ void spmm(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, hipStream_t s
 }
 
 template <typename T>
-void spmm_launch(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, hipStream_t s) {
+void spmm_launch(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, int64_t ycm,
+                 int ycols, hipStream_t s) {
   if (A.nbins == 0) {
     const int G = lanes_for_length(A.m ? (double)A.nnz / (double)A.m : 0.0);
     if (absval)
-      launch_b<T, true>(b, G, A.m, nullptr, A.rowptr, A.colind, A.val, X, Y, s);
+      launch_b<T, true>(b, G, A.m, nullptr, A.rowptr, A.colind, A.val, X, Y, ycm, ycols, s);
     else
-      launch_b<T, false>(b, G, A.m, nullptr, A.rowptr, A.colind, A.val, X, Y, s);
+      launch_b<T, false>(b, G, A.m, nullptr, A.rowptr, A.colind, A.val, X, Y, ycm, ycols, s);
     return;
   }
   for (int k = 0; k < A.nbins; ++k) {
     const Bin &bn = A.bins[k];
     if (absval)
       launch_b<T, true>(b, bn.lanes, bn.count, A.binrows + bn.offset, A.rowptr, A.colind, A.val,
-                        X, Y, s);
+                        X, Y, ycm, ycols, s);
     else
       launch_b<T, false>(b, bn.lanes, bn.count, A.binrows + bn.offset, A.rowptr, A.colind, A.val,
-                         X, Y, s);
+                         X, Y, ycm, ycols, s);
   }
 }
-template void spmm<float>(const SpMat<float> &, int, const float *, float *, bool, hipStream_t);
+template void spmm<float>(const SpMat<float> &, int, const float *, float *, bool, hipStream_t,
+                          int64_t, int);
 template void spmm<double>(const SpMat<double> &, int, const double *, double *, bool,
-                           hipStream_t);
+                           hipStream_t, int64_t, int);
 
 // ---------------------------------------------------------------- transpose
 __global__ void k_count_cols(int64_t nnz, const int32_t *__restrict__ ci, int32_t *cnt) {

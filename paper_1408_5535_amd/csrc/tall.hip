@@ -63,9 +63,7 @@ struct TnRows {  // rows per lane in flight: float 4, double 2 (register budget)
 
 template <typename T>
 __global__ __launch_bounds__(64 * kTnMaxWaves) void k_tn(TV<T> x1, TV<T> x2, TV<T> y,
-                                                         int64_t rpb, double *part,
-                                                         const int *skip) {
-  if (skip && *skip) return;
+                                                         int64_t rpb, double *part) {
   constexpr int U = TnRows<T>::U;
   const int nx = x1.cols + x2.cols, ny = y.cols;
   const int tx = (nx + kTnCX - 1) / kTnCX, ty = (ny + kTnCY - 1) / kTnCY, ntile = tx * ty;
@@ -130,8 +128,7 @@ __global__ __launch_bounds__(64 * kTnMaxWaves) void k_tn(TV<T> x1, TV<T> x2, TV<
 // One wavefront per entry of G: lane l sums partials l, l+64, ... and the
 // lane sums are combined in the fixed order of wave_total.
 __global__ __launch_bounds__(64) void k_reduce_parts(const double *part, int np, int nx, int ny,
-                                                     double *G, int ldg, const int *skip) {
-  if (skip && *skip) return;
+                                                     double *G, int ldg) {
   const int E = nx * ny, e = blockIdx.x;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int b = threadIdx.x;
@@ -148,7 +145,7 @@ __global__ __launch_bounds__(64) void k_reduce_parts(const double *part, int np,
 
 template <typename T>
 void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int ldg,
-        const Scratch &sc, hipStream_t s, const int *skip) {
+        const Scratch &sc, hipStream_t s) {
   const int nx = X1.cols + X2.cols, ny = Y.cols;
   if (nx == 0 || ny == 0) return;
   PHS_REQUIRE(nx <= 128 && ny <= 32, kEinval, "tn: operand too wide");
@@ -172,8 +169,8 @@ void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int l
   }
   if (nblk < 1) nblk = 1;
   prof_begin(kProfTn, s);
-  k_tn<T><<<(int)nblk, 64 * waves, 0, s>>>(tv(X1), tv(X2), tv(Y), rpb, sc.part, skip);
-  k_reduce_parts<<<(int)E, 64, 0, s>>>(sc.part, (int)nblk, nx, ny, G, ldg, skip);
+  k_tn<T><<<(int)nblk, 64 * waves, 0, s>>>(tv(X1), tv(X2), tv(Y), rpb, sc.part);
+  k_reduce_parts<<<(int)E, 64, 0, s>>>(sc.part, (int)nblk, nx, ny, G, ldg);
   PHS_CHECK_LAUNCH();
   prof_end(kProfTn, s, (double)Y.rows * (nx + ny) * sizeof(T));
 }
@@ -185,11 +182,21 @@ __device__ inline double wave_sum(double v) { return wave_total(v); }
 // ------------------------------------------------------------------ X S
 constexpr int kNnTile = 16;  // output columns per thread
 
+// Y = alpha X S + beta Z (Z defaults to Y itself), optionally also written
+// to a second output Y2 in another layout.
+template <typename T>
+struct NnOut {
+  T *y;
+  int64_t yrs, ycs;
+  const T *z;
+  int64_t zrs, zcs;
+  T *y2;
+  int64_t y2rs, y2cs;
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_nn(TV<T> x1, TV<T> x2, const double *S, int lds,
-                                            int ny, double alpha, T *yp, int64_t yrs,
-                                            int64_t ycs, double beta, const int *skip) {
-  if (skip && *skip) return;
+                                            int ny, double alpha, double beta, NnOut<T> o) {
   extern __shared__ __align__(16) unsigned char smem[];
   T *ss = reinterpret_cast<T *>(smem);
   const int nx = x1.cols + x2.cols;
@@ -220,10 +227,11 @@ __global__ __launch_bounds__(256) void k_nn(TV<T> x1, TV<T> x2, const double *S,
 #pragma unroll
     for (int c = 0; c < kNnTile; ++c) {
       if (c < nc) {
-        T *dst = yp + r * yrs + (int64_t)(c0 + c) * ycs;
+        const int64_t col = c0 + c;
         T v = (T)alpha * acc[c];
-        if (beta != 0.0) v += (T)beta * *dst;
-        *dst = v;
+        if (beta != 0.0) v += (T)beta * o.z[r * o.zrs + col * o.zcs];
+        o.y[r * o.yrs + col * o.ycs] = v;
+        if (o.y2) o.y2[r * o.y2rs + col * o.y2cs] = v;
       }
     }
   }
@@ -231,19 +239,23 @@ __global__ __launch_bounds__(256) void k_nn(TV<T> x1, TV<T> x2, const double *S,
 
 template <typename T>
 void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double alpha,
-        const Tall<T> &Y, double beta, hipStream_t s, const int *skip) {
+        const Tall<T> &Y, double beta, hipStream_t s, const Tall<T> *Z, const Tall<T> *Y2) {
   const int nx = X1.cols + X2.cols, ny = Y.cols;
   if (ny == 0 || Y.rows == 0) return;
-  if (nx == 0 && beta == 1.0) return;
   PHS_REQUIRE(nx <= 160, kEinval, "nn: operand too wide");
+  PHS_REQUIRE(!Z || (Z->rows == Y.rows && Z->cols == Y.cols), kEinval, "nn: Z shape");
+  PHS_REQUIRE(!Y2 || (Y2->rows == Y.rows && Y2->cols == Y.cols), kEinval, "nn: Y2 shape");
+  if (nx == 0 && beta == 1.0 && !Z && !Y2) return;
   int64_t blocks = cdiv(Y.rows, 256);
   if (blocks > 4096) blocks = 4096;
   dim3 grid((unsigned)blocks, cdiv(ny, kNnTile));
   size_t shm = (size_t)(nx > 0 ? nx : 1) * kNnTile * sizeof(T);
   Tall<T> a = X1, b = X2;
   if (a.cols == 0 && b.cols == 0) a.rows = Y.rows;
+  NnOut<T> o{Y.p, Y.rs, Y.cs, Z ? Z->p : Y.p, Z ? Z->rs : Y.rs, Z ? Z->cs : Y.cs,
+             Y2 ? Y2->p : nullptr, Y2 ? Y2->rs : 0, Y2 ? Y2->cs : 0};
   prof_begin(kProfNn, s);
-  k_nn<T><<<grid, 256, shm, s>>>(tv(a), tv(b), S, lds, ny, alpha, Y.p, Y.rs, Y.cs, beta, skip);
+  k_nn<T><<<grid, 256, shm, s>>>(tv(a), tv(b), S, lds, ny, alpha, beta, o);
   PHS_CHECK_LAUNCH();
   prof_end(kProfNn, s, (double)Y.rows * (nx + ny * (beta != 0.0 ? 2 : 1)) * sizeof(T));
 }
@@ -317,9 +329,7 @@ __global__ __launch_bounds__(256) void k_ritz(TV<T> V, TV<T> W, const double *S,
 }
 
 __global__ __launch_bounds__(64) void k_reduce_vec(const double *part, int nblk, int E,
-                                                   double *out0, double *out1, int split,
-                                                   const int *skip = nullptr) {
-  if (skip && *skip) return;
+                                                   double *out0, double *out1, int split) {
   const int e = blockIdx.x;
   double s = 0.0;
   for (int b = threadIdx.x; b < nblk; b += 64) s += part[(int64_t)b * E + e];
@@ -367,8 +377,7 @@ void ritz(const Tall<T> &V, const Tall<T> &W, const double *S, int lds, const do
 // ------------------------------------------------------------ col norms
 template <typename T>
 __global__ __launch_bounds__(256) void k_colnorm2(TV<T> x, int64_t r0, int64_t r1,
-                                                  double *part, const int *skip) {
-  if (skip && *skip) return;
+                                                  double *part) {
   __shared__ double red[256];
   for (int j = 0; j < x.cols; ++j) {
     double acc = 0.0;
@@ -394,8 +403,7 @@ __global__ __launch_bounds__(256) void k_colnorm2(TV<T> x, int64_t r0, int64_t r
 // always meets column t mod W.
 template <typename T>
 __global__ __launch_bounds__(256) void k_colnorm2_rm(TV<T> x, int64_t r0, int64_t r1,
-                                                     double *part, const int *skip) {
-  if (skip && *skip) return;
+                                                     double *part) {
   __shared__ double red[256];
   const int W = (int)x.rs;
   const int c = threadIdx.x & (W - 1);
@@ -427,7 +435,7 @@ __global__ __launch_bounds__(256) void k_colnorm2_rm(TV<T> x, int64_t r0, int64_
 
 template <typename T>
 void colnorm2(const Tall<T> &X, int64_t r0, int64_t r1, double *out, const Scratch &sc,
-              hipStream_t s, const int *skip) {
+              hipStream_t s) {
   if (X.cols == 0) return;
   const bool rm = X.rs > 1 && X.cs == 1 && X.rs <= 256 && (X.rs & (X.rs - 1)) == 0 &&
                   X.cols <= X.rs;
@@ -435,15 +443,15 @@ void colnorm2(const Tall<T> &X, int64_t r0, int64_t r1, double *out, const Scrat
   if (rm) {
     blocks = cdiv((r1 - r0 > 0 ? r1 - r0 : 1) * X.rs, 256 * 8);
     if (blocks > 2048) blocks = 2048;
-    k_colnorm2_rm<T><<<(unsigned)blocks, 256, 0, s>>>(tv(X), r0, r1, sc.part, skip);
-    k_reduce_vec<<<X.cols, 64, 0, s>>>(sc.part, (int)blocks, X.cols, out, nullptr, X.cols, skip);
+    k_colnorm2_rm<T><<<(unsigned)blocks, 256, 0, s>>>(tv(X), r0, r1, sc.part);
+    k_reduce_vec<<<X.cols, 64, 0, s>>>(sc.part, (int)blocks, X.cols, out, nullptr, X.cols);
     PHS_CHECK_LAUNCH();
     return;
   }
   blocks = cdiv(r1 - r0 > 0 ? r1 - r0 : 1, 256 * 4);
   if (blocks > 512) blocks = 512;
-  k_colnorm2<T><<<(unsigned)blocks, 256, 0, s>>>(tv(X), r0, r1, sc.part, skip);
-  k_reduce_vec<<<X.cols, 64, 0, s>>>(sc.part, (int)blocks, X.cols, out, nullptr, X.cols, skip);
+  k_colnorm2<T><<<(unsigned)blocks, 256, 0, s>>>(tv(X), r0, r1, sc.part);
+  k_reduce_vec<<<X.cols, 64, 0, s>>>(sc.part, (int)blocks, X.cols, out, nullptr, X.cols);
   PHS_CHECK_LAUNCH();
 }
 
@@ -707,14 +715,15 @@ void row_scale(const T *X, const double *w, int64_t n, int b, bool inv, T *Y, hi
 
 #define PHS_INST(T)                                                                           \
   template void tn<T>(const Tall<T> &, const Tall<T> &, const Tall<T> &, double *, int,      \
-                      const Scratch &, hipStream_t, const int *);                            \
+                      const Scratch &, hipStream_t);                                         \
   template void nn<T>(const Tall<T> &, const Tall<T> &, const double *, int, double,         \
-                      const Tall<T> &, double, hipStream_t, const int *);                    \
+                      const Tall<T> &, double, hipStream_t, const Tall<T> *,                 \
+                      const Tall<T> *);                                                      \
   template void ritz<T>(const Tall<T> &, const Tall<T> &, const double *, int, const double *, \
                         T *, T *, int, int, double *, double *, int64_t, const Scratch &,     \
                         hipStream_t);                                                         \
   template void colnorm2<T>(const Tall<T> &, int64_t, int64_t, double *, const Scratch &,     \
-                            hipStream_t, const int *);                                        \
+                            hipStream_t);                                                     \
   template void scale_cols<T>(const Tall<T> &, const double *, hipStream_t);                  \
   template void axpby<T>(const Tall<T> &, const Tall<T> &, double, const Tall<T> &,           \
                          hipStream_t);                                                        \
