@@ -75,10 +75,18 @@ struct Scratch {
 constexpr int64_t kPartCap = 1 << 21;
 constexpr int64_t kAuxCap = 1 << 16;
 
+// Block partials of a product X^T Y left for a consumer kernel to reduce:
+// np blocks of nx * ny doubles, entry (i, j) at offset i * ny + j.
+struct TnParts {
+  const double *part = nullptr;
+  int np = 0, nx = 0, ny = 0;
+};
 // G (nx x ny, ld ldg, float64) = X^T Y, X = [X1 | X2] (X2 may have 0 cols).
+// With keep, the final reduction is left to the consumer: G is not written
+// and keep describes the partials (valid until the next use of sc.part).
 template <typename T>
 void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int ldg,
-        const Scratch &sc, hipStream_t s);
+        const Scratch &sc, hipStream_t s, TnParts *keep = nullptr);
 // Y = alpha * [X1 | X2] S + beta * Z, S float64 (nx x ny, ld lds); Z is Y
 // itself unless given.  If Y2 is given the result is written there too.
 template <typename T>
@@ -139,8 +147,11 @@ struct CgsDiag {
   int ldh = 0, nh = 0;
   double *n0 = nullptr, *n1 = nullptr, *n2 = nullptr;
 };
+// With pt, G is the reduction of the partials pt (X^T X) and the G argument
+// is not read.
 void chol_inv(const double *G, int ldg, int w, double shift, double *R, double *Rinv, int ldr,
-              int *flag, hipStream_t s, const CgsDiag *dg = nullptr);
+              int *flag, hipStream_t s, const CgsDiag *dg = nullptr,
+              const TnParts *pt = nullptr);
 // C = alpha op(A) op(B) + beta C, all small float64.
 void small_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const double *A, int lda,
                 const double *B, int ldb, double beta, double *C, int ldc, hipStream_t s);

@@ -660,11 +660,37 @@ void svdj(const double *M, int ldm, int rows, int cols, double *sv, double *Y, i
 // -------------------------------------------------------- chol_inv
 __global__ __launch_bounds__(256) void k_chol_inv(const double *G, int ldg, int w, double shift,
                                                   double *Rg, double *Ri, int ldr, int *flag,
-                                                  CgsDiag dg) {
+                                                  CgsDiag dg, const double *part, int np) {
   __shared__ double r[kSmallMax * kLd];  // r[i * kLd + j], upper triangle used
   __shared__ int bad;
   const int t = threadIdx.x;
   if (t == 0) bad = 0;
+  if (part) {
+    // G from the block partials of X^T X (entry i * w + j of each block):
+    // groups of tpe lanes per entry, fixed summation order
+    const int E = w * w;
+    int tpe = 1;
+    while (tpe * 2 * E <= 256 && tpe < 64) tpe *= 2;
+    const int grp = t / tpe, sub = t % tpe, ngrp = 256 / tpe;
+    for (int e0 = 0; e0 < E; e0 += ngrp) {
+      const int e = e0 + grp;
+      double s0 = 0.0, s1 = 0.0;
+      if (e < E) {
+        int b = sub;
+        for (; b + tpe < np; b += 2 * tpe) {
+          s0 += part[(int64_t)b * E + e];
+          s1 += part[(int64_t)(b + tpe) * E + e];
+        }
+        if (b < np) s0 += part[(int64_t)b * E + e];
+      }
+      double sv = s0 + s1;
+      for (int o = tpe / 2; o > 0; o >>= 1) sv += __shfl_xor(sv, o, tpe);
+      if (sub == 0 && e < E) r[(e / w) * kLd + e % w] = sv;
+    }
+    __syncthreads();
+  }
+  // G(i, j): from the partials (in r) or from global memory
+  auto gij = [&](int i, int j) { return part ? r[i * kLd + j] : G[i + (int64_t)j * ldg]; };
   if (dg.n2 && t < w) {
     // squared column norms around two Gram-Schmidt passes from the final
     // Gram matrix and the two coefficient blocks
@@ -674,15 +700,29 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double *G, int ldg, int 
       h1 = fma(c1, c1, h1);
       h2 = fma(c2, c2, h2);
     }
-    const double a2 = G[t + (int64_t)t * ldg];
+    const double a2 = gij(t, t);
     dg.n2[t] = a2;
     dg.n1[t] = a2 + h2;
     dg.n0[t] = a2 + h2 + h1;
   }
-  for (int idx = t; idx < w * w; idx += blockDim.x) {
-    int i = idx % w, j = idx / w;
-    r[i * kLd + j] = 0.5 * (G[i + (int64_t)j * ldg] + G[j + (int64_t)i * ldg]) +
-                     (i == j ? shift : 0.0);
+  if (part) {
+    // symmetrise in place: pairs (i < j) by one thread each
+    for (int idx = t; idx < w * w; idx += blockDim.x) {
+      int i = idx % w, j = idx / w;
+      if (i < j) {
+        const double v = 0.5 * (r[i * kLd + j] + r[j * kLd + i]);
+        r[i * kLd + j] = v;
+        r[j * kLd + i] = v;
+      } else if (i == j) {
+        r[i * kLd + i] += shift;
+      }
+    }
+  } else {
+    for (int idx = t; idx < w * w; idx += blockDim.x) {
+      int i = idx % w, j = idx / w;
+      r[i * kLd + j] = 0.5 * (G[i + (int64_t)j * ldg] + G[j + (int64_t)i * ldg]) +
+                       (i == j ? shift : 0.0);
+    }
   }
   __syncthreads();
   // right-looking: after step k, row k holds R(k, k:w)
@@ -727,11 +767,14 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double *G, int ldg, int 
 }
 
 void chol_inv(const double *G, int ldg, int w, double shift, double *R, double *Rinv, int ldr,
-              int *flag, hipStream_t s, const CgsDiag *dg) {
+              int *flag, hipStream_t s, const CgsDiag *dg, const TnParts *pt) {
+  PHS_REQUIRE(!pt || (pt->nx == w && pt->ny == w && pt->np >= 1), kEinval,
+              "chol_inv: partials do not match");
   PHS_REQUIRE(w >= 1 && w <= kSmallMax, kEinval, "chol_inv: size out of range");
   PHS_REQUIRE(!dg || (dg->nh >= 0 && dg->ldh >= dg->nh), kEinval,
               "chol_inv: bad diagnostics operands");
-  k_chol_inv<<<1, 256, 0, s>>>(G, ldg, w, shift, R, Rinv, ldr, flag, dg ? *dg : CgsDiag{});
+  k_chol_inv<<<1, 256, 0, s>>>(G, ldg, w, shift, R, Rinv, ldr, flag, dg ? *dg : CgsDiag{},
+                               pt ? pt->part : nullptr, pt ? pt->np : 0);
   PHS_CHECK_LAUNCH();
 }
 

@@ -403,27 +403,56 @@ void csr_transpose(int64_t m, int64_t n, int64_t nnz, const int64_t *rp, const i
 
 // Row-length bins for skewed matrices: rows are grouped by the lane count
 // their length calls for, so that each launch has uniform work per group.
-__global__ void k_bin_count(int64_t m, const int64_t *__restrict__ rp, int32_t *cnt) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= m) return;
-  int64_t len = rp[r + 1] - rp[r];
+__device__ inline int bin_of(int64_t len) {
   int g = 0;
   for (int lim = 4; g < 6 && len > lim; lim *= 2) ++g;  // 0..6 -> 1..64 lanes
-  atomicAdd(&cnt[g], 1);
+  return g;
 }
 
-__global__ void k_bin_fill(int64_t m, const int64_t *__restrict__ rp, const int32_t *offs,
-                           int32_t *fill, int32_t *rows) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= m) return;
-  int64_t len = rp[r + 1] - rp[r];
-  int g = 0;
-  for (int lim = 4; g < 6 && len > lim; lim *= 2) ++g;
-  rows[offs[g] + atomicAdd(&fill[g], 1)] = (int32_t)r;
+// Per-block counts in LDS, one global atomic per bin and block.
+__global__ __launch_bounds__(256) void k_bin_count(int64_t m, const int64_t *__restrict__ rp,
+                                                   int32_t *cnt) {
+  __shared__ int32_t h[8];
+  if (threadIdx.x < 8) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < m) atomicAdd(&h[bin_of(rp[r + 1] - rp[r])], 1);
+  __syncthreads();
+  if (threadIdx.x < 7 && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
 }
 
-// The order of rows inside a bin comes from atomics, but every row is
-// computed by one group in a fixed order, so results are deterministic.
+// Each block places its rows of a bin contiguously and in ascending order
+// (ranks from wavefront ballots), at an offset taken by one atomic per bin.
+__global__ __launch_bounds__(256) void k_bin_fill(int64_t m, const int64_t *__restrict__ rp,
+                                                  const int32_t *offs, int32_t *fill,
+                                                  int32_t *rows) {
+  __shared__ int32_t wc[4][8], base[8];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = r < m ? bin_of(rp[r + 1] - rp[r]) : -1;
+  int rank = 0;
+  for (int b = 0; b < 7; ++b) {
+    const unsigned long long bal = __ballot(g == b);
+    if (g == b) rank = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wc[w][b] = __popcll(bal);
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    const int b = threadIdx.x;
+    const int tot = wc[0][b] + wc[1][b] + wc[2][b] + wc[3][b];
+    base[b] = tot ? atomicAdd(&fill[b], tot) : 0;
+  }
+  __syncthreads();
+  if (g >= 0) {
+    int pre = 0;
+    for (int v = 0; v < w; ++v) pre += wc[v][g];
+    rows[offs[g] + base[g] + pre + rank] = (int32_t)r;
+  }
+}
+
+// Rows of a bin come in block chunks (in the order the atomics hand out);
+// every row is computed by one group in a fixed order, so results are
+// deterministic.
 void build_bins(int64_t m, const int64_t *rp, int32_t *rows, int32_t *scratch, Bin *bins,
                 int *nbins, hipStream_t s) {
   // scratch: 16 int32 (counts, offsets, fill)

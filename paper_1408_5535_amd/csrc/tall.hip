@@ -50,16 +50,66 @@ __device__ inline void stage_rows(const TV<T> &x, int64_t r0, int R, T *lds, int
 // ---------------------------------------------------------------- X^T Y
 // One wavefront per output tile of kTnCX x kTnCY entries; the waves of a
 // workgroup cover all tiles for one slab of rows, so the slab of Y is read
-// from HBM once and served from cache to the other tiles.  Lanes walk the
-// rows (consecutive lanes, consecutive rows: coalesced for column-major X),
-// kTnU rows per lane in flight, products accumulated in T registers.  Each
-// wave reduces its tile over its lanes; one partial per block and entry goes
-// to `part`, which a second kernel adds in a fixed order.
+// from HBM once and served from cache to the other tiles.  With fewer tiles
+// than waves, reps = waves / tiles waves share a tile and split its rows;
+// their sums are added in LDS in a fixed order.  Lanes walk the rows
+// (consecutive lanes, consecutive rows: coalesced for column-major X), kTnU
+// rows per lane in flight, products accumulated in T registers.  Each wave
+// reduces its tile over its lanes; one partial per block and entry goes to
+// `part`, which a second kernel (or the consumer) adds in a fixed order.
 constexpr int kTnCX = 8, kTnCY = 4, kTnMaxWaves = 8;
 template <typename T>
 struct TnRows {  // rows per lane in flight: float 4, double 2 (register budget)
   static constexpr int U = sizeof(T) == 4 ? 4 : 2;
 };
+
+// acc += X(rows, tile columns)^T Y(rows, tile columns) over the rows
+// r = rs + lane + 64 U q (q = 0, 1, ...) below r1, taken U at a time with
+// stride `step` between groups.
+template <typename T>
+__device__ inline void tn_tile(const TV<T> &x1, const TV<T> &x2, const TV<T> &y, int i0, int j0,
+                               int64_t rs, int64_t r1, int64_t step, int lane,
+                               T (&acc)[kTnCX][kTnCY]) {
+  constexpr int U = TnRows<T>::U;
+  const int nx = x1.cols + x2.cols, ny = y.cols;
+  // column bases (uniform); columns past the operand read as zero
+  const T *xp[kTnCX];
+  bool in1[kTnCX];  // column from x1 (else x2): selects the row stride
+#pragma unroll
+  for (int a = 0; a < kTnCX; ++a) {
+    const int i = i0 + a;
+    in1[a] = i < x1.cols;
+    xp[a] = in1[a] ? x1.p + (int64_t)i * x1.cs
+                   : x2.p + (int64_t)(i < nx ? i - x1.cols : 0) * x2.cs;
+  }
+  const T *yp[kTnCY];
+#pragma unroll
+  for (int c = 0; c < kTnCY; ++c) yp[c] = y.p + (int64_t)(j0 + c < ny ? j0 + c : 0) * y.cs;
+#pragma unroll
+  for (int a = 0; a < kTnCX; ++a)
+#pragma unroll
+    for (int c = 0; c < kTnCY; ++c) acc[a][c] = T(0);
+  for (int64_t rb = rs + lane; rb < r1; rb += step) {
+    T xr[U][kTnCX], yr[U][kTnCY];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = rb + (int64_t)u * 64;
+      const bool in = r < r1;
+      const int64_t o1 = r * x1.rs, o2 = r * x2.rs, oy = r * y.rs;
+#pragma unroll
+      for (int a = 0; a < kTnCX; ++a)
+        xr[u][a] = (in && i0 + a < nx) ? xp[a][in1[a] ? o1 : o2] : T(0);
+#pragma unroll
+      for (int c = 0; c < kTnCY; ++c) yr[u][c] = (in && j0 + c < ny) ? yp[c][oy] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int a = 0; a < kTnCX; ++a)
+#pragma unroll
+        for (int c = 0; c < kTnCY; ++c) acc[a][c] = fma(xr[u][a], yr[u][c], acc[a][c]);
+  }
+}
 
 template <typename T>
 __global__ __launch_bounds__(64 * kTnMaxWaves) void k_tn(TV<T> x1, TV<T> x2, TV<T> y,
@@ -72,46 +122,32 @@ __global__ __launch_bounds__(64 * kTnMaxWaves) void k_tn(TV<T> x1, TV<T> x2, TV<
   const int64_t N = y.rows;
   const int64_t r0 = (int64_t)blockIdx.x * rpb;
   const int64_t r1 = r0 + rpb < N ? r0 + rpb : N;
-  for (int tile = w; tile < ntile; tile += nw) {
+  T acc[kTnCX][kTnCY];
+  if (ntile < nw) {
+    // reps waves per tile (the launch makes nw a multiple of ntile)
+    __shared__ double red[kTnMaxWaves][kTnCX * kTnCY];
+    const int reps = nw / ntile, tile = w % ntile, sub = w / ntile;
     const int i0 = (tile / ty) * kTnCX, j0 = (tile % ty) * kTnCY;
-    // column bases (uniform); columns past the operand read as zero
-    const T *xp[kTnCX];
-    bool in1[kTnCX];  // column from x1 (else x2): selects the row stride
-#pragma unroll
-    for (int a = 0; a < kTnCX; ++a) {
-      const int i = i0 + a;
-      in1[a] = i < x1.cols;
-      xp[a] = in1[a] ? x1.p + (int64_t)i * x1.cs
-                     : x2.p + (int64_t)(i < nx ? i - x1.cols : 0) * x2.cs;
-    }
-    const T *yp[kTnCY];
-#pragma unroll
-    for (int c = 0; c < kTnCY; ++c) yp[c] = y.p + (int64_t)(j0 + c < ny ? j0 + c : 0) * y.cs;
-    T acc[kTnCX][kTnCY];
+    tn_tile(x1, x2, y, i0, j0, r0 + (int64_t)sub * 64 * U, r1, (int64_t)64 * U * reps, lane, acc);
 #pragma unroll
     for (int a = 0; a < kTnCX; ++a)
 #pragma unroll
-      for (int c = 0; c < kTnCY; ++c) acc[a][c] = T(0);
-    for (int64_t rb = r0 + lane; rb < r1; rb += 64 * U) {
-      T xr[U][kTnCX], yr[U][kTnCY];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t r = rb + (int64_t)u * 64;
-        const bool in = r < r1;
-        const int64_t o1 = r * x1.rs, o2 = r * x2.rs, oy = r * y.rs;
-#pragma unroll
-        for (int a = 0; a < kTnCX; ++a)
-          xr[u][a] = (in && i0 + a < nx) ? xp[a][in1[a] ? o1 : o2] : T(0);
-#pragma unroll
-        for (int c = 0; c < kTnCY; ++c) yr[u][c] = (in && j0 + c < ny) ? yp[c][oy] : T(0);
+      for (int c = 0; c < kTnCY; ++c) {
+        const double v = wave_total((double)acc[a][c]);
+        if (lane == 0) red[w][a * kTnCY + c] = v;
       }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int a = 0; a < kTnCX; ++a)
-#pragma unroll
-          for (int c = 0; c < kTnCY; ++c) acc[a][c] = fma(xr[u][a], yr[u][c], acc[a][c]);
+    __syncthreads();
+    if (sub == 0 && lane < kTnCX * kTnCY) {
+      const int a = lane / kTnCY, c = lane % kTnCY, i = i0 + a, j = j0 + c;
+      double v = red[tile][lane];
+      for (int q = 1; q < reps; ++q) v += red[tile + q * ntile][lane];
+      if (i < nx && j < ny) part[(int64_t)blockIdx.x * E + i * ny + j] = v;
     }
+    return;
+  }
+  for (int tile = w; tile < ntile; tile += nw) {
+    const int i0 = (tile / ty) * kTnCX, j0 = (tile % ty) * kTnCY;
+    tn_tile(x1, x2, y, i0, j0, r0, r1, (int64_t)64 * U, lane, acc);
     // wave sums (DPP rows, then the four row sums in a fixed order); lane 0
     // writes the block's partial of every entry of the tile (float64)
 #pragma unroll
@@ -145,19 +181,20 @@ __global__ __launch_bounds__(64) void k_reduce_parts(const double *part, int np,
 
 template <typename T>
 void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int ldg,
-        const Scratch &sc, hipStream_t s) {
+        const Scratch &sc, hipStream_t s, TnParts *keep) {
   const int nx = X1.cols + X2.cols, ny = Y.cols;
   if (nx == 0 || ny == 0) return;
   PHS_REQUIRE(nx <= 128 && ny <= 32, kEinval, "tn: operand too wide");
   PHS_REQUIRE(X1.rows == Y.rows && (X2.cols == 0 || X2.rows == Y.rows), kEinval,
               "tn: row counts differ");
   const int tiles = ((nx + kTnCX - 1) / kTnCX) * ((ny + kTnCY - 1) / kTnCY);
-  const int waves = tiles < kTnMaxWaves ? tiles : kTnMaxWaves;
+  // fewer tiles than waves: several waves per tile (a multiple of the tiles)
+  const int waves = tiles < kTnMaxWaves ? tiles * (kTnMaxWaves / tiles) : kTnMaxWaves;
   const int64_t N = Y.rows, E = (int64_t)nx * ny;
   // about 2048 waves in flight, slabs a multiple of 64 * kTnU rows, and the
   // partials within their buffer
   int64_t nblk = (2048 + waves - 1) / waves;
-  const int64_t unit = 64 * TnRows<T>::U;
+  const int64_t unit = 64 * TnRows<T>::U * (tiles < kTnMaxWaves ? waves / tiles : 1);
   int64_t rpb = ((N + nblk - 1) / nblk + unit - 1) / unit * unit;
   if (rpb < unit) rpb = unit;
   nblk = (N + rpb - 1) / rpb;
@@ -170,7 +207,11 @@ void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int l
   if (nblk < 1) nblk = 1;
   prof_begin(kProfTn, s);
   k_tn<T><<<(int)nblk, 64 * waves, 0, s>>>(tv(X1), tv(X2), tv(Y), rpb, sc.part);
-  k_reduce_parts<<<(int)E, 64, 0, s>>>(sc.part, (int)nblk, nx, ny, G, ldg);
+  if (keep) {
+    *keep = TnParts{sc.part, (int)nblk, nx, ny};
+  } else {
+    k_reduce_parts<<<(int)E, 64, 0, s>>>(sc.part, (int)nblk, nx, ny, G, ldg);
+  }
   PHS_CHECK_LAUNCH();
   prof_end(kProfTn, s, (double)Y.rows * (nx + ny) * sizeof(T));
 }
@@ -715,7 +756,7 @@ void row_scale(const T *X, const double *w, int64_t n, int b, bool inv, T *Y, hi
 
 #define PHS_INST(T)                                                                           \
   template void tn<T>(const Tall<T> &, const Tall<T> &, const Tall<T> &, double *, int,      \
-                      const Scratch &, hipStream_t);                                         \
+                      const Scratch &, hipStream_t, TnParts *);                              \
   template void nn<T>(const Tall<T> &, const Tall<T> &, const double *, int, double,         \
                       const Tall<T> &, double, hipStream_t, const Tall<T> *,                 \
                       const Tall<T> *);                                                      \
