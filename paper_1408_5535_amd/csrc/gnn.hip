@@ -152,41 +152,62 @@ __global__ void k_gnn_feat(const float *r, int64_t n, const float *dn, const dou
   }
 }
 
-// S = h Ws + b ; M = D^-1/2 (h Wm)   (h: n x fin, outputs n x W)
-template <int W>
-__global__ __launch_bounds__(256) void k_gnn_dense(const float *h, int64_t n, int fin,
-                                                   const float *Ws, const float *Wm,
-                                                   const float *bias, const float *isd, float *S,
-                                                   float *M) {
-  __shared__ float ws[kGnnMaxW * W], wm[kGnnMaxW * W], bb[W];
-  for (int e = threadIdx.x; e < fin * W; e += blockDim.x) {
-    ws[e] = Ws[e];
-    wm[e] = Wm[e];
+// Rows of K floats (K a multiple of 4, 16-byte aligned) moved as float4.
+template <int K>
+__device__ inline void load_row(const float *__restrict__ p, float (&o)[K]) {
+  static_assert(K % 4 == 0, "row width must be a multiple of 4");
+#pragma unroll
+  for (int q = 0; q < K / 4; ++q) {
+    const float4 u = reinterpret_cast<const float4 *>(p)[q];
+    o[4 * q] = u.x;
+    o[4 * q + 1] = u.y;
+    o[4 * q + 2] = u.z;
+    o[4 * q + 3] = u.w;
   }
-  if (threadIdx.x < W) bb[threadIdx.x] = bias[threadIdx.x];
-  __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+}
+template <int K>
+__device__ inline void store_row(float *__restrict__ p, const float (&o)[K]) {
+#pragma unroll
+  for (int q = 0; q < K / 4; ++q)
+    reinterpret_cast<float4 *>(p)[q] =
+        make_float4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+}
+
+// S = h Ws + b ; M = D^-1/2 (h Wm)   (h: n x FIN, outputs n x W).  One
+// thread per node: its input row is loaded whole before the products; the
+// weights are wavefront-uniform reads (scalar loads, no LDS traffic).  One
+// node per thread and no loop over nodes, so the weight loads stay next to
+// their products instead of being hoisted (2 W FIN values would not fit in
+// scalar registers).
+template <int W, int FIN>
+__global__ __launch_bounds__(256) void k_gnn_dense(const float *__restrict__ h, int64_t n,
+                                                   const float *__restrict__ Ws,
+                                                   const float *__restrict__ Wm,
+                                                   const float *__restrict__ bias,
+                                                   const float *__restrict__ isd,
+                                                   float *__restrict__ S, float *__restrict__ M) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    float hv[FIN];
+    load_row<FIN>(h + i * FIN, hv);
+    const float sc = isd[i];
     float as[W], am[W];
 #pragma unroll
     for (int c = 0; c < W; ++c) {
-      as[c] = bb[c];
+      as[c] = bias[c];
       am[c] = 0.f;
     }
-    for (int k = 0; k < fin; ++k) {
-      const float hv = h[i * fin + k];
+#pragma unroll
+    for (int k = 0; k < FIN; ++k)
 #pragma unroll
       for (int c = 0; c < W; ++c) {
-        as[c] = fmaf(hv, ws[k * W + c], as[c]);
-        am[c] = fmaf(hv, wm[k * W + c], am[c]);
+        as[c] = fmaf(hv[k], Ws[k * W + c], as[c]);
+        am[c] = fmaf(hv[k], Wm[k * W + c], am[c]);
       }
-    }
-    const float s = isd[i];
 #pragma unroll
-    for (int c = 0; c < W; ++c) {
-      S[i * W + c] = as[c];
-      M[i * W + c] = am[c] * s;
-    }
+    for (int c = 0; c < W; ++c) am[c] *= sc;
+    store_row<W>(S + i * W, as);
+    store_row<W>(M + i * W, am);
   }
 }
 
@@ -202,14 +223,23 @@ __global__ void k_gnn_combine(const float *S, const float *Z, const float *isd, 
 }
 
 // traw_i = (h3_i . wo + h0_i1) * scale, scale = ||r|| / (sqrt(n) mean(diag C))
-__global__ void k_gnn_readout(const float *h, const float *h0, int64_t n, int w,
-                              const float *wo, const double *nr2, const double *meta,
-                              float *traw) {
+template <int W>
+__global__ __launch_bounds__(256) void k_gnn_readout(const float *__restrict__ h,
+                                                     const float *__restrict__ h0, int64_t n,
+                                                     const float *__restrict__ wo,
+                                                     const double *nr2, const double *meta,
+                                                     float *__restrict__ traw) {
   const double scale = sqrt(fmax(nr2[0], 0.0)) / (sqrt((double)n) * meta[0]);
+  float wv[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) wv[c] = wo[c];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
+    float hr[W];
+    load_row<W>(h + i * W, hr);
     float s = h0[i * kGnnIn + 1];
-    for (int c = 0; c < w; ++c) s = fmaf(h[i * w + c], wo[c], s);
+#pragma unroll
+    for (int c = 0; c < W; ++c) s = fmaf(hr[c], wv[c], s);
     traw[i] = (float)(s * scale);
   }
 }
@@ -245,33 +275,31 @@ __global__ void k_gnn_delta_top(const float *graw, const float *wo, const double
   }
 }
 
-// dh_prev = delta Ws^T + dM Wm^T   (outputs n x fin); then masked by the
-// previous layer's pre-activation into delta_prev
+// dh_prev = delta Ws^T + dM Wm^T (n x W: the previous layer has width W),
+// then masked by the previous layer's pre-activation into delta_prev.  Rows
+// are loaded whole before the products; weights are wavefront-uniform reads.
 template <int W>
-__global__ __launch_bounds__(256) void k_gnn_back_dense(const float *delta, const float *dM,
-                                                        int64_t n, int fin, const float *Ws,
-                                                        const float *Wm, const float *pre_prev,
-                                                        float *delta_prev) {
-  __shared__ float ws[kGnnMaxW * W], wm[kGnnMaxW * W];
-  for (int e = threadIdx.x; e < fin * W; e += blockDim.x) {
-    ws[e] = Ws[e];
-    wm[e] = Wm[e];
-  }
-  __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    float dl[W], dm[W];
+__global__ __launch_bounds__(256) void k_gnn_back_dense(const float *__restrict__ delta,
+                                                        const float *__restrict__ dM, int64_t n,
+                                                        const float *__restrict__ Ws,
+                                                        const float *__restrict__ Wm,
+                                                        const float *__restrict__ pre_prev,
+                                                        float *__restrict__ delta_prev) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    float dl[W], dm[W], pp[W], out[W];
+    load_row<W>(delta + i * W, dl);
+    load_row<W>(dM + i * W, dm);
+    load_row<W>(pre_prev + i * W, pp);
 #pragma unroll
-    for (int c = 0; c < W; ++c) {
-      dl[c] = delta[i * W + c];
-      dm[c] = dM[i * W + c];
-    }
-    for (int k = 0; k < fin; ++k) {
-      float s = 0.f;
+    for (int k = 0; k < W; ++k) {
+      float sacc = 0.f;
 #pragma unroll
-      for (int c = 0; c < W; ++c) s = fmaf(dl[c], ws[k * W + c], fmaf(dm[c], wm[k * W + c], s));
-      delta_prev[i * fin + k] = pre_prev[i * fin + k] > 0.f ? s : 0.f;
+      for (int c = 0; c < W; ++c)
+        sacc = fmaf(dl[c], Ws[k * W + c], fmaf(dm[c], Wm[k * W + c], sacc));
+      out[k] = pp[k] > 0.f ? sacc : 0.f;
     }
+    store_row<W>(delta_prev + i * W, out);
   }
 }
 
@@ -307,6 +335,12 @@ static unsigned grid_for(int64_t work) {
   return (unsigned)std::min<int64_t>(b, 8192);
 }
 
+// one thread per node (kernels without a loop over nodes)
+static unsigned node_grid(int64_t n) {
+  PHS_REQUIRE(n <= (int64_t)256 * 0x7fffffff, kEinval, "gnn: too many nodes");
+  return (unsigned)cdiv(std::max<int64_t>(n, 1), 256);
+}
+
 template <typename F>
 static void dispatch_w(int w, F &&f) {
   switch (w) {
@@ -338,16 +372,24 @@ void gnn_forward(const phsvds_csr &A, const GnnGraph &g, GnnBufs &b, const float
   for (int l = 0; l < 3; ++l) {
     dispatch_w(w, [&](auto WW) {
       constexpr int W = decltype(WW)::value;
-      k_gnn_dense<W><<<grid_for(n), 256, 0, s>>>(hin, n, fin, wts + o.Ws[l], wts + o.Wm[l],
-                                                wts + o.b[l], g.isd, b.S, b.M);
+      if (l == 0)
+        k_gnn_dense<W, kGnnIn><<<node_grid(n), 256, 0, s>>>(hin, n, wts + o.Ws[l],
+                                                           wts + o.Wm[l], wts + o.b[l], g.isd,
+                                                           b.S, b.M);
+      else
+        k_gnn_dense<W, W><<<node_grid(n), 256, 0, s>>>(hin, n, wts + o.Ws[l], wts + o.Wm[l],
+                                                      wts + o.b[l], g.isd, b.S, b.M);
     });
     apply_Ch(A32, At32, g, b, w, b.M, b.Z, s);
     k_gnn_combine<<<grid_for(n * w), 256, 0, s>>>(b.S, b.Z, g.isd, n, w, b.pre[l], b.h[l]);
     hin = b.h[l];
     fin = w;
   }
-  k_gnn_readout<<<grid_for(n), 256, 0, s>>>(b.h[2], b.h0, n, w, wts + o.wo, b.vec, g.meta,
-                                            b.traw);
+  dispatch_w(w, [&](auto WW) {
+    constexpr int W = decltype(WW)::value;
+    k_gnn_readout<W><<<grid_for(n), 256, 0, s>>>(b.h[2], b.h0, n, wts + o.wo, b.vec, g.meta,
+                                                 b.traw);
+  });
   // t = traw - x (x^T traw)
   tn(cm(const_cast<float *>(x), n, 1, n), cm<float>(nullptr, n, 0, n), cm(b.traw, n, 1, n),
      b.vec + 1, 1, b.sc, s);
@@ -398,7 +440,7 @@ void gnn_loss_grad(const phsvds_csr &A, const GnnGraph &g, GnnBufs &b, const flo
     if (l > 0) {
       dispatch_w(w, [&](auto WW) {
         constexpr int W = decltype(WW)::value;
-        k_gnn_back_dense<W><<<grid_for(n), 256, 0, s>>>(b.delta, b.Z, n, fin, wts + o.Ws[l],
+        k_gnn_back_dense<W><<<node_grid(n), 256, 0, s>>>(b.delta, b.Z, n, wts + o.Ws[l],
                                                         wts + o.Wm[l], b.pre[l - 1], b.dh);
       });
       std::swap(b.delta, b.dh);

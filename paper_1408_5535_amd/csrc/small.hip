@@ -237,7 +237,7 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
   for (int i = n - 1; i >= 2; --i) {
     const int l = i - 1;
     const double xi = (t <= l) ? a[i * kLd + t] : 0.0;
-    double scale = 1.0;
+    double scale = 1.0, xs = xi, f = a[i * kLd + l];
     double sigma = wave_total(xi * xi);
     if (!(sigma > 1e-280 && sigma < 1e280)) {  // rare: scale by the 1-norm first
       scale = wave_total(fabs(xi));
@@ -245,11 +245,11 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
         if (threadIdx.x == 0) e[i] = 0.0;
         continue;  // hh[i] stays 0: no reflector
       }
-      sigma = wave_total((xi / scale) * (xi / scale));
+      const double isc = 1.0 / scale;
+      xs = xi * isc;
+      f *= isc;
+      sigma = wave_total(xs * xs);
     }
-    const double isc = 1.0 / scale;
-    const double xs = xi * isc;
-    const double f = a[i * kLd + l] * isc;
     const double g = f >= 0 ? -sqrt(sigma) : sqrt(sigma);
     const double h = sigma - f * g;
     const double ih = 1.0 / h;

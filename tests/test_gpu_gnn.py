@@ -126,3 +126,37 @@ def test_svds_with_gnn_preconditioner_returns_definition():
     assert np.allclose(sig, sig_ex, rtol=1e-10)
     res = dense.triplet_residuals(A, sig, as_np(U), as_np(V))
     assert np.all(res <= 1e-12 * an)
+
+
+@gpu
+def test_learned_pipeline_against_none_and_jacobi():
+    """The whole learned-preconditioner pipeline on a small member of the
+    random family (6000 x 4000, 12 per row): harvest from stage-1 runs on
+    four matrices, train with the library's forward/backward/Adam, then solve
+    two held-out matrices with no preconditioner, Jacobi and the network.
+    Training must lower the loss; every arm must reach 1e-12 ||A|| (the
+    network arm through its Jacobi safeguard if it stops helping).  The
+    products of each arm are printed: that comparison is the measured
+    outcome, not a pass criterion."""
+    need_gpu()
+    from paper_1408_5535_amd import learned as L
+
+    def make(seed):
+        return wl.random_sparse(6000, 4000, 12, seed=seed)
+
+    say("learned pipeline: harvest")
+    mats, graphs, pairs = L.harvest_family(range(1000, 1004), make, k=4, block=2, every=10,
+                                           max_pairs=24, width=8)
+    assert len(pairs) >= 40
+    say("train", len(pairs), "pairs")
+    w, hist = L.train(graphs, pairs, width=8, epochs=6, lr=1e-3, batch=8)
+    say("loss per epoch", hist)
+    assert np.all(np.isfinite(hist)) and hist[-1] < hist[0]
+    del mats, graphs, pairs
+    rows = L.evaluate(range(2000, 2002), make, w, width=8, k=4, block=2)
+    for r in rows:
+        say(r)
+        assert r["status"] == 0 and r["max_res_over_norm"] <= 1e-12 * (1 + 1e-8)
+    mv = {(r["seed"], r["method"]): r["mv"] for r in rows}
+    say("products (none, jacobi, network):",
+        [(s, mv[(s, "none")], mv[(s, "jacobi")], mv[(s, "gnn")]) for s in (2000, 2001)])
