@@ -128,10 +128,11 @@ void row_scale(const T *X, const double *w, int64_t n, int b, bool inv, T *Y, hi
 // -------------------------------------------------- small dense (float64)
 // Selected eigenpairs of the symmetric H (p x p, ld ldh, p <= 64; one
 // workgroup): the nvec at the wanted end (ascending, or descending if
-// `descending`) in theta[0..nvec), S(:, 0..nvec) (ld lds), and the
-// eigenvalue at the other end in theta[p-1].  H is not modified.
+// `descending`) in theta[0..nvec), S(:, 0..nvec) (ld lds), and, if
+// other_end, the eigenvalue at the other end in theta[p-1] (without it the
+// multisection has one group fewer to run).  H is not modified.
 void syev_rr(const double *H, int ldh, int p, int nvec, bool descending, double *theta,
-             double *S, int lds, hipStream_t s);
+             double *S, int lds, hipStream_t s, bool other_end = true);
 // One-sided Jacobi SVD of M (rows x cols, ld ldm, rows >= cols): singular
 // values ascending in sv, right vectors in Y (cols x cols, ld ldy).
 void svdj(const double *M, int ldm, int rows, int cols, double *sv, double *Y, int ldy,

@@ -69,8 +69,9 @@ __device__ inline void rr_pair(int P, int r, int k, int &a, int &b) {
 //  4. s = Q y by applying the reflectors, each vector held in the
 //     registers of a lane group.
 // Outputs: theta[0..nvec) and S(:, 0..nvec) for the nvec eigenpairs at the
-// wanted end (ascending, or descending if `desc`), and theta[p-1], the
-// eigenvalue at the other end.  Other entries are not written.
+// wanted end (ascending, or descending if `desc`), and (if other_end)
+// theta[p-1], the eigenvalue at the other end.  Other entries are not
+// written.
 constexpr int kPadRows = kSmallMax + 8;
 
 // Step 2 with Q points per lane and L lanes per eigenvalue (Q * L <= 64).
@@ -192,7 +193,8 @@ __device__ void apply_reflectors(const double *a, const double *rh, const double
 }
 
 __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, int nvec, bool desc,
-                                             double *theta, double *Sout, int lds) {
+                                             bool other_end, double *theta, double *Sout,
+                                             int lds) {
   __shared__ double a[kSmallMax * kLd];   // H, then the reflectors
   __shared__ double y[kPadRows * kLd];    // eigenvectors of T, column per vector
   __shared__ double uu[kSmallMax * kLd];  // 1 / pivots of (T - lambda I) / ||T||
@@ -344,7 +346,7 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
   // 2. multisection.  Slots 0..nvec-1: ranks 0..nvec-1; slot nvec (if
   //    nvec < n): rank n-1.  Rank r is ascending index r, or n-1-r if desc.
   {
-    const int ne = nvec < n ? nvec + 1 : n;
+    const int ne = (other_end && nvec < n) ? nvec + 1 : nvec;
     int L = 64;
     while (L * ne > 256) L >>= 1;
     if (L <= 16)
@@ -543,15 +545,15 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
       case 8: apply_reflectors<8>(a, rh, y, n, nvec, lamv, tnorm, theta, Sout, lds); break;
       default: apply_reflectors<4>(a, rh, y, n, nvec, lamv, tnorm, theta, Sout, lds); break;
     }
-    if (threadIdx.x == 0 && nvec < n) theta[n - 1] = lamv[nvec] * tnorm;
+    if (threadIdx.x == 0 && other_end && nvec < n) theta[n - 1] = lamv[nvec] * tnorm;
   }
 }
 
 void syev_rr(const double *H, int ldh, int p, int nvec, bool descending, double *theta,
-             double *S, int lds, hipStream_t s) {
+             double *S, int lds, hipStream_t s, bool other_end) {
   PHS_REQUIRE(p >= 1 && p <= kSmallMax && nvec >= 1 && nvec <= p, kEinval,
               "syev: size out of range");
-  k_syev<<<1, 256, 0, s>>>(H, ldh, p, nvec, descending, theta, S, lds);
+  k_syev<<<1, 256, 0, s>>>(H, ldh, p, nvec, descending, other_end, theta, S, lds);
   PHS_CHECK_LAUNCH();
 }
 

@@ -325,7 +325,11 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     // eigenpairs this iteration uses: the block, or the p_min kept at a
     // restart; a lock recomputes all p
     const int nv = (p + nb > pmax) ? std::min(std::max(pmin, nb), p) : nb;
-    syev_rr(H, ld, p, nv, largest, theta, S, ld, c.s);
+    // the largest Ritz value (the ||A|| estimate) in smallest mode: at
+    // restarts and locks, and every eighth iteration; the running maximum
+    // changes slowly and is only used for the stopping thresholds
+    const bool want_top = !largest && (nv > nb || it % 8 == 1);
+    syev_rr(H, ld, p, nv, largest, theta, S, ld, c.s, want_top);
     ritz(cm(V[cur], n, p, n), cm(W[cur], n, p, n), S, ld, theta, bf.Xb, Rb, nb, bw, rn2, nullptr,
          0, c.sc, c.s);
     const bool want_rho = fp32 && rho_age >= 10;
@@ -366,7 +370,7 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     }
     // largest Ritz value so far: ||A||^2 estimate
     for (int j = 0; j < nv; ++j) res.sn2 = std::max(res.sn2, th_h[j]);
-    res.sn2 = std::max(res.sn2, th_h[p - 1]);
+    if (want_top || nv >= p) res.sn2 = std::max(res.sn2, th_h[p - 1]);
     const double sn = std::sqrt(res.sn2);
     const int need = k - nl;
     if (c.verbose && it % 1000 == 0)
