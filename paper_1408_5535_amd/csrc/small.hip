@@ -567,9 +567,19 @@ __global__ __launch_bounds__(256) void k_svdj(const double *M, int ldm, int rows
   __shared__ double cs[kSmallMax / 2][2];
   __shared__ int nrot;
   const int t = threadIdx.x;
-  for (int idx = t; idx < P * kSvdRows; idx += blockDim.x) {
-    int i = idx % kSvdRows, j = idx / kSvdRows;
-    g[j * kSvdRows + i] = (i < rows && j < cols) ? M[i + (int64_t)j * ldm] : 0.0;
+  // eight loads in flight per thread before their stores
+  for (int idx0 = t; idx0 < P * kSvdRows; idx0 += 8 * blockDim.x) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = idx0 + u * blockDim.x, i = idx % kSvdRows, j = idx / kSvdRows;
+      v[u] = (idx < P * kSvdRows && i < rows && j < cols) ? M[i + (int64_t)j * ldm] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = idx0 + u * blockDim.x;
+      if (idx < P * kSvdRows) g[idx] = v[u];
+    }
   }
   for (int idx = t; idx < P * kSmallMax; idx += blockDim.x) {
     int i = idx % kSmallMax, j = idx / kSmallMax;
@@ -854,6 +864,21 @@ __device__ inline void wave_cgs2(double *q, int rows, int c, double *xs, double 
   __syncthreads();
 }
 
+// Columns [0, nc) of a column-major global matrix into LDS (ld kLd), row r
+// per lane: eight loads in flight before their stores.
+__device__ inline void load_cols_lds(double *q, const double *src, int ld, int rows, int nc,
+                                     int r) {
+  for (int j0 = 0; j0 < nc; j0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      v[u] = (j0 + u < nc && r < rows) ? src[r + (int64_t)(j0 + u) * ld] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (j0 + u < nc) q[(j0 + u) * kLd + r] = v[u];
+  }
+}
+
 // Y = [K | orth(P against K)]; a dependent column of P is replaced by the
 // next coordinate vector that is independent, so the count is always
 // min(kc + pc, rows).
@@ -866,7 +891,7 @@ __global__ __launch_bounds__(64) void k_restart_basis(const double *K, int ldk, 
   if (r < 8) xs[kSmallMax + r] = 0.0;
   for (int e = r; e < kSmallMax * kLd + 8; e += 64) q[e] = 0.0;  // padding reads meet zeros
   __syncthreads();
-  for (int j = 0; j < kc; ++j) q[j * kLd + r] = r < rows ? K[r + (int64_t)j * ldk] : 0.0;
+  load_cols_lds(q, K, ldk, rows, kc, r);
   __syncthreads();
   int cur = kc, unit = 0;
   const int want = min(kc + pc, min(rows, kSmallMax));
@@ -911,7 +936,7 @@ __global__ __launch_bounds__(64) void k_small_qr(const double *M, int ldm, int r
   if (r < 8) xs[kSmallMax + r] = 0.0;
   for (int e = r; e < kSmallMax * kLd + 8; e += 64) q[e] = 0.0;  // padding reads meet zeros
   __syncthreads();
-  for (int j = 0; j < cols; ++j) q[j * kLd + r] = r < rows ? M[r + (int64_t)j * ldm] : 0.0;
+  load_cols_lds(q, M, ldm, rows, cols, r);
   for (int e = r; e < cols * cols; e += 64) R[e % cols + (int64_t)(e / cols) * ldr] = 0.0;
   for (int c = 0; c < cols; ++c) {
     rc[r] = 0.0;

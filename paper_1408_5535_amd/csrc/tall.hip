@@ -27,26 +27,6 @@ static TV<T> tv(const Tall<T> &t) {
   return TV<T>{t.p, t.rows, t.cols, t.rs, t.cs};
 }
 
-// Load rows [r0, r0+R) of a tall view into LDS (row-major, width w, column
-// offset j0 inside a row of width ld); rows past `rows` read as zero.
-template <typename T>
-__device__ inline void stage_rows(const TV<T> &x, int64_t r0, int R, T *lds, int ld, int j0) {
-  const int n = R * x.cols;
-  if (x.rs == 1) {  // column-major: consecutive threads walk a column
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-      int r = idx % R, j = idx / R;
-      int64_t gr = r0 + r;
-      lds[r * ld + j0 + j] = gr < x.rows ? x.p[gr + (int64_t)j * x.cs] : T(0);
-    }
-  } else {  // row-major: consecutive threads walk a row
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-      int r = idx / x.cols, j = idx % x.cols;
-      int64_t gr = r0 + r;
-      lds[r * ld + j0 + j] = gr < x.rows ? x.p[gr * x.rs + (int64_t)j * x.cs] : T(0);
-    }
-  }
-}
-
 // ---------------------------------------------------------------- X^T Y
 // One wavefront per output tile of kTnCX x kTnCY entries; the waves of a
 // workgroup cover all tiles for one slab of rows, so the slab of Y is read
@@ -243,9 +223,17 @@ __global__ __launch_bounds__(256) void k_nn(TV<T> x1, TV<T> x2, const double *S,
   const int nx = x1.cols + x2.cols;
   const int c0 = blockIdx.y * kNnTile;
   const int nc = min(kNnTile, ny - c0);
-  for (int idx = threadIdx.x; idx < nx * kNnTile; idx += blockDim.x) {
-    int j = idx / kNnTile, c = idx % kNnTile;
-    ss[idx] = c < nc ? (T)S[j + (int64_t)(c0 + c) * lds] : T(0);
+  // S tile into LDS, four loads in flight per thread before their stores
+  for (int idx0 = threadIdx.x; idx0 < nx * kNnTile; idx0 += 4 * blockDim.x) {
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = idx0 + u * blockDim.x, j = idx / kNnTile, c = idx % kNnTile;
+      v[u] = (idx < nx * kNnTile && c < nc) ? (T)S[j + (int64_t)(c0 + c) * lds] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (idx0 + u * blockDim.x < nx * kNnTile) ss[idx0 + u * blockDim.x] = v[u];
   }
   __syncthreads();
   const int64_t N = x1.cols ? x1.rows : x2.rows;
@@ -313,9 +301,17 @@ __global__ __launch_bounds__(256) void k_ritz(TV<T> V, TV<T> W, const double *S,
   const int p = V.cols;
   T *ss = reinterpret_cast<T *>(smem);
   double *red = reinterpret_cast<double *>(smem + ((p * kRitzMax * sizeof(T) + 15) & ~15));
-  for (int idx = threadIdx.x; idx < p * kRitzMax; idx += blockDim.x) {
-    int j = idx / kRitzMax, c = idx % kRitzMax;
-    ss[idx] = c < nb ? (T)S[j + (int64_t)c * lds] : T(0);
+  // S block into LDS, eight loads in flight per thread before their stores
+  for (int idx0 = threadIdx.x; idx0 < p * kRitzMax; idx0 += 8 * blockDim.x) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = idx0 + u * blockDim.x, j = idx / kRitzMax, c = idx % kRitzMax;
+      v[u] = (idx < p * kRitzMax && c < nb) ? (T)S[j + (int64_t)c * lds] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (idx0 + u * blockDim.x < p * kRitzMax) ss[idx0 + u * blockDim.x] = v[u];
   }
   __shared__ T th[kRitzMax];
   if (threadIdx.x < kRitzMax) th[threadIdx.x] = threadIdx.x < nb ? (T)theta[threadIdx.x] : T(0);
