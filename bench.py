@@ -196,9 +196,15 @@ def compare(family, max_mv, gnn_weights, gnn_width, max_restarts=10000, only=Non
         if ref is None and prec == "f64" and row["converged"] == k:
             ref = (sig, Vh)
         elif ref is not None:
-            # sigma difference and cosines of the principal angles between the
-            # right singular subspaces, against the float64 arm
-            row["max_rel_sigma_diff_vs_f64"] = float(np.max(np.abs(sig - ref[0]) / ref[0]))
+            # sigma differences and angles against the float64 arm: per
+            # triplet (sine of the angle between the right vectors) and for
+            # the whole right singular subspace (cosines of its principal
+            # angles)
+            rel = np.abs(sig - ref[0]) / ref[0]
+            row["max_rel_sigma_diff_vs_f64"] = float(np.max(rel))
+            row["rel_sigma_diff_vs_f64"] = [float(x) for x in rel]
+            c1 = np.abs(np.sum(ref[1] * Vh, axis=0))
+            row["sin_angle_vs_f64"] = [float(np.sqrt(max(0.0, 1.0 - c * c))) for c in c1]
             cos = np.linalg.svd(ref[1].T @ Vh, compute_uv=False)
             row["min_cos_principal_angle_vs_f64"] = float(cos.min())
         rows.append(row)

@@ -132,16 +132,34 @@ def test_forced_stage2_grid():
 
 @gpu
 def test_mixed_precision_weighted_grid_vs_oracle():
+    """Float32 stage 1 (with and without the float64 continuation) then
+    float64 stage 2, per triplet against the float64 oracle's two-stage
+    result: sigma within 1e-10 relative, and the sine of the angle between
+    the right singular vectors within max(1e-8, 4 r / gap), r the float64
+    residual bound and gap the distance to the nearest other singular value
+    (the sin-theta bound)."""
     need_gpu()
     N = 24
     A = wl.grid_gradient(N, weights="lognormal", seed=3)
     an = float(np.linalg.norm(A.toarray(), 2))
-    sig_ex, _, V_ex = dense.svd_extreme_dense(A, 6)
+    k = 6
+    sig_all = np.sort(np.linalg.svd(A.toarray(), compute_uv=False))
+    sig_ex = sig_all[:k]
+    gap = np.array([np.min(np.abs(np.delete(sig_all, i) - sig_all[i])) for i in range(k)])
+    out = ph.phsvds(A, k, 1e-12, block=4, anorm=an)
+    assert np.allclose(out["sigma"], sig_ex, rtol=1e-10, atol=0)
     say("mixed precision weighted grid N=24 k=6 b=4")
     for cont in (True, False):
-        sig, U, V, info = _solve(A, 6, b=4, anorm=an, stage1_fp32=True, fp64_continue=cont)
+        sig, U, V, info = _solve(A, k, b=4, anorm=an, stage1_fp32=True, fp64_continue=cont)
         say(cont, info)
-        _check(A, sig, U, V, info, sig_ex, an)
+        U, V = _check(A, sig, U, V, info, sig_ex, an)
+        for i in range(k):
+            err = abs(sig[i] - out["sigma"][i]) / out["sigma"][i]
+            ang = cf.principal_angles(V[:, [i]], out["V"][:, [i]])
+            say(f"  continue={cont} triplet {i}: sigma {sig[i]:.15e}, rel. error vs the "
+                f"float64 oracle {err:.1e}, sin angle {ang:.1e} (gap {gap[i]:.1e})")
+            assert err <= 1e-10
+            assert ang <= max(1e-8, 4 * 1e-12 * an / gap[i])
 
 
 @gpu
