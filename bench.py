@@ -203,8 +203,9 @@ def compare(family, max_mv, gnn_weights, gnn_width, max_restarts=10000, only=Non
             rel = np.abs(sig - ref[0]) / ref[0]
             row["max_rel_sigma_diff_vs_f64"] = float(np.max(rel))
             row["rel_sigma_diff_vs_f64"] = [float(x) for x in rel]
-            c1 = np.abs(np.sum(ref[1] * Vh, axis=0))
-            row["sin_angle_vs_f64"] = [float(np.sqrt(max(0.0, 1.0 - c * c))) for c in c1]
+            c1 = np.sum(ref[1] * Vh, axis=0)
+            row["sin_angle_vs_f64"] = [float(x) for x in
+                                       np.linalg.norm(Vh - ref[1] * c1[None, :], axis=0)]
             cos = np.linalg.svd(ref[1].T @ Vh, compute_uv=False)
             row["min_cos_principal_angle_vs_f64"] = float(cos.min())
         rows.append(row)
