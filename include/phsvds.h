@@ -161,12 +161,16 @@ int phsvds_svds(const phsvds_csr *A, int k, double tol, const phsvds_precond *P,
 /* ---- Learned preconditioner (message-passing network over the graph of
  * C = A^T A, float32).  Not in the paper: a preconditioner for C of the kind
  * Section 4 admits.  Per node j, width w in {8, 16, 32}, three layers:
- *   h0_j = [rh_j, rh_j / max(d_j - tau, d_j/10), d_j, tau],
+ *   h0_j = [u_j, u_j d_j / max(d_j - tau, d_j/10), d_j, tau],  u = rh / sqrt(d),
  *          rh = r sqrt(n)/||r||, d = diag(C)/mean diag(C), tau = theta/mean diag(C)
  *   h^l = relu(h^{l-1} Ws_l + b_l + Ch (h^{l-1} Wm_l)), Ch = D^-1/2 A^T A D^-1/2
- *   t   = (I - x x^T) (h^3 wo + h0_1) ||r|| / (sqrt(n) mean diag(C))
- * where h0_1, the second input feature, is the Jacobi step in these units:
- * the network learns a correction to the Jacobi preconditioner.
+ *   t   = (I - x x^T) t~,
+ *   t~_j = (h^3 wo + h0_1)_j ||r|| / (sqrt(n) mean diag(C) sqrt(d_j))
+ * Input and output both carry D^-1/2, so the linear part of the network (a
+ * polynomial q in Ch) acts as the symmetric operator D^-1/2 q(Ch) D^-1/2.
+ * h0_1 through the readout is the Jacobi step r / max(C_jj - theta,
+ * C_jj / 10): the zero network is the Jacobi preconditioner and the network
+ * learns a correction to it.
  * Weights: one float32 array, row-major blocks in the order
  * Ws1, Wm1 (4 x w), b1 (w), Ws2, Wm2 (w x w), b2, Ws3, Wm3, b3, wo (w).
  * A per-matrix workspace `gws` (phsvds_gnn_workspace_bytes) holds the

@@ -13,14 +13,18 @@ equation
 
 Network (width w, three layers):
     d_j   = C_jj / mean(diag C),  tau = theta / mean(diag C)
-    rh    = r sqrt(n) / ||r||
-    h0_j  = [rh_j, rh_j / max(d_j - tau, d_j / 10), d_j, tau]
+    rh    = r sqrt(n) / ||r||,    u = rh / sqrt(d)
+    h0_j  = [u_j, u_j d_j / max(d_j - tau, d_j / 10), d_j, tau]
     h^l   = relu(h^{l-1} Ws_l + b_l + Ch (h^{l-1} Wm_l)),  l = 1..3
     Ch    = D^-1/2 A^T A D^-1/2  (applied as two sparse products)
-    t~    = (h^3 wo + h0[:, 1]) ||r|| / (sqrt(n) mean(diag C))
-            (h0[:, 1] is the Jacobi step in these units: the network learns
-            a correction to the Jacobi preconditioner)
+    t~_j  = (h^3 wo + h0[:, 1])_j ||r|| / (sqrt(n) mean(diag C) sqrt(d_j))
     t     = (I - x x^T) t~
+The input is scaled by D^-1/2 and the output again by D^-1/2, so that the
+linear part of the network, a polynomial q in Ch, acts as the symmetric
+operator D^-1/2 q(Ch) D^-1/2 (a nonsymmetric form such as q(Ch) D^-1 makes
+the GD+k iteration stall); h0[:, 1] through the readout is exactly the
+Jacobi step r / max(C_jj - theta, C_jj / 10), so the zero network is the
+Jacobi preconditioner and the network learns a correction to it.
 Loss of one sample: ||t - t*||^2 / ||t*||^2 (t* is orthogonal to x).
 Optimiser: Adam (Kingma & Ba), lr 1e-3, beta1 0.9, beta2 0.999, eps 1e-8.
 
@@ -79,7 +83,8 @@ def features(g: Graph, r, theta):
     d = g.d / g.dmean
     tau = theta / g.dmean
     den = np.maximum(d - tau, 0.1 * d)
-    return np.column_stack([rh, rh / den, d, np.full(n, tau)]), nr
+    u = rh / np.sqrt(d)
+    return np.column_stack([u, u * d / den, d, np.full(n, tau)]), nr
 
 
 def forward(g: Graph, P, r, x, theta):
@@ -97,9 +102,10 @@ def forward(g: Graph, P, r, x, theta):
         pres.append(pre)
         hs.append(h)
     scale = nr / (math.sqrt(n) * g.dmean)
-    traw = (h @ P["wo"] + h0[:, 1]) * scale
+    osc = scale / np.sqrt(g.d / g.dmean)  # per-node output scale
+    traw = (h @ P["wo"] + h0[:, 1]) * osc
     t = traw - x * (x @ traw)
-    return t, {"hs": hs, "pres": pres, "scale": scale}
+    return t, {"hs": hs, "pres": pres, "scale": scale, "osc": osc}
 
 
 def loss_and_grad(g: Graph, P, r, x, theta, tstar):
@@ -110,10 +116,11 @@ def loss_and_grad(g: Graph, P, r, x, theta, tstar):
     loss = float(diff @ diff) / nt
     gt = 2.0 * diff / nt
     graw = gt - x * (x @ gt)  # through the projection (I - x x^T)
-    hs, pres, scale = cache["hs"], cache["pres"], cache["scale"]
+    hs, pres, osc = cache["hs"], cache["pres"], cache["osc"]
     grads = {}
-    grads["wo"] = scale * (hs[3].T @ graw)
-    dh = scale * np.outer(graw, P["wo"])
+    go = graw * osc
+    grads["wo"] = hs[3].T @ go
+    dh = np.outer(go, P["wo"])
     for l in (3, 2, 1):
         delta = dh * (pres[l - 1] > 0)
         hin = hs[l - 1]

@@ -391,11 +391,12 @@ def harvest(A: DeviceCSR, k: int, block: int = 4, every: int = 5, max_pairs: int
     return R[:n], X[:n], T[:n], np.array(th[:n]), st.as_dict(k)
 
 
-def train_gnn(graphs, pairs, w, epochs=20, lr=1e-3, batch=16, seed=0, log=None):
+def train_gnn(graphs, pairs, w, epochs=20, lr=1e-3, batch=16, seed=0, log=None, on_epoch=None):
     """Adam on the mean loss over mini-batches of harvested pairs.
 
     graphs: list of GnnGraph; pairs: list of (graph index, r, x, theta, t*)
-    with float32 device vectors.  Returns the per-epoch mean losses."""
+    with float32 device vectors.  ``on_epoch(epoch, w)`` sees the weights
+    after every epoch.  Returns the per-epoch mean losses."""
     import numpy as np
     nw = w.numel()
     m = torch.zeros_like(w)
@@ -421,4 +422,6 @@ def train_gnn(graphs, pairs, w, epochs=20, lr=1e-3, batch=16, seed=0, log=None):
         hist.append(tot / len(pairs))
         if log:
             log(f"epoch {ep} mean loss {hist[-1]:.4f}")
+        if on_epoch:
+            on_epoch(ep, w)
     return hist

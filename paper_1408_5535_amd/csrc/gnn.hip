@@ -2,13 +2,15 @@
 // C = A^T A, float32 on the device (forward, back-propagation, Adam).
 //
 // Per node j (width w, three layers):
-//   h0_j = [rh_j, rh_j / max(d_j - tau, d_j/10), d_j, tau],
+//   h0_j = [u_j, u_j d_j / max(d_j - tau, d_j/10), d_j, tau],  u = rh / sqrt(d),
 //          rh = r sqrt(n)/||r||, d = diag(C)/mean(diag C), tau = theta/mean(diag C)
 //   pre^l = h^{l-1} Ws_l + b_l + Ch (h^{l-1} Wm_l),  h^l = relu(pre^l)
 //   Ch    = D^-1/2 A^T A D^-1/2 (two float32 SpMMs of width w)
-//   t     = (I - x x^T) (h^3 wo + h0_1) ||r|| / (sqrt(n) mean(diag C))
-// (h0_1 is the Jacobi step r / max(diag C - theta, diag C / 10) in these
-// units, so the network learns a correction to the Jacobi preconditioner).
+//   t_j   = ((I - x x^T) t~)_j,  t~_j = (h^3 wo + h0_1)_j ||r|| / (sqrt(n) mean(diag C) sqrt(d_j))
+// Input and output both carry D^-1/2, so the network's linear part, a
+// polynomial q in Ch, acts as the symmetric D^-1/2 q(Ch) D^-1/2; h0_1 through
+// the readout is exactly the Jacobi step r / max(diag C - theta, diag C / 10),
+// so the network learns a correction to the Jacobi preconditioner.
 // The node-wise dense layers run one thread per node with the weights in
 // LDS; aggregation reuses the row-major SpMM kernels at width w.
 #include <hip/hip_runtime.h>
@@ -143,10 +145,10 @@ __global__ void k_gnn_feat(const float *r, int64_t n, const float *dn, const dou
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const double d = dn[i];
-    const double rh = r[i] * sc;
+    const double u = r[i] * sc / sqrt(d);
     const double den = fmax(d - tau, 0.1 * d);
-    h0[i * kGnnIn + 0] = (float)rh;
-    h0[i * kGnnIn + 1] = (float)(rh / den);
+    h0[i * kGnnIn + 0] = (float)u;
+    h0[i * kGnnIn + 1] = (float)(u * d / den);
     h0[i * kGnnIn + 2] = (float)d;
     h0[i * kGnnIn + 3] = (float)tau;
   }
@@ -225,7 +227,8 @@ __global__ void k_gnn_combine(const float *S, const float *Z, const float *isd, 
 // traw_i = (h3_i . wo + h0_i1) * scale, scale = ||r|| / (sqrt(n) mean(diag C))
 template <int W>
 __global__ __launch_bounds__(256) void k_gnn_readout(const float *__restrict__ h,
-                                                     const float *__restrict__ h0, int64_t n,
+                                                     const float *__restrict__ h0,
+                                                     const float *__restrict__ dn, int64_t n,
                                                      const float *__restrict__ wo,
                                                      const double *nr2, const double *meta,
                                                      float *__restrict__ traw) {
@@ -240,8 +243,15 @@ __global__ __launch_bounds__(256) void k_gnn_readout(const float *__restrict__ h
     float s = h0[i * kGnnIn + 1];
 #pragma unroll
     for (int c = 0; c < W; ++c) s = fmaf(hr[c], wv[c], s);
-    traw[i] = (float)(s * scale);
+    traw[i] = (float)(s * scale / sqrt((double)dn[i]));
   }
+}
+
+// g_j /= sqrt(d_j)
+__global__ void k_scale_isd(float *g, const float *dn, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    g[i] = (float)((double)g[i] / sqrt((double)dn[i]));
 }
 
 // y = a - coef[0] * x   (coef on the device, scaled by mul)
@@ -387,8 +397,8 @@ void gnn_forward(const phsvds_csr &A, const GnnGraph &g, GnnBufs &b, const float
   }
   dispatch_w(w, [&](auto WW) {
     constexpr int W = decltype(WW)::value;
-    k_gnn_readout<W><<<grid_for(n), 256, 0, s>>>(b.h[2], b.h0, n, wts + o.wo, b.vec, g.meta,
-                                                 b.traw);
+    k_gnn_readout<W><<<grid_for(n), 256, 0, s>>>(b.h[2], b.h0, g.dn, n, wts + o.wo, b.vec,
+                                                 g.meta, b.traw);
   });
   // t = traw - x (x^T traw)
   tn(cm(const_cast<float *>(x), n, 1, n), cm<float>(nullptr, n, 0, n), cm(b.traw, n, 1, n),
@@ -413,6 +423,8 @@ void gnn_loss_grad(const phsvds_csr &A, const GnnGraph &g, GnnBufs &b, const flo
   tn(cm(const_cast<float *>(x), n, 1, n), cm<float>(nullptr, n, 0, n), cm(b.g, n, 1, n),
      b.vec + 4, 1, b.sc, s);
   k_axpy_dev<<<grid_for(n), 256, 0, s>>>(b.g, x, b.vec + 4, 1.0, n, b.g);
+  // through the per-node output scale 1 / sqrt(d_j)
+  k_scale_isd<<<grid_for(n), 256, 0, s>>>(b.g, g.dn, n);
   // dwo = scale * h3^T graw
   {
     tn(rm(b.h[2], n, w), cm<float>(nullptr, n, 0, n), cm(b.g, n, 1, n), b.G, 64, b.sc, s);

@@ -13,13 +13,24 @@ the kind Section 4 admits.  The pipeline runs on the GPU through the C ABI:
             rho = 1 (the Jacobi-Davidson equation) the targets are dominated
             by the next eigenvectors, which three hops of message passing
             cannot represent;
+  init      the network starts as the polynomial preconditioner
+            D^-1/2 p(Ch) D^-1/2 with p a degree-3 least-squares fit of 1/x on
+            (0, 1.05 ||A D^-1/2||^2] (the norm from the library's own
+            largest-mode solve), written into the weights (channels carry
+            the positive and negative parts of Ch^k u), or from Glorot
+            weights (--init glorot);
   train     Adam on the mean loss ||t - t*||^2 / ||t*||^2 over mini-batches
             of harvested pairs, forward and backward by the library's
             kernels (phsvds_gnn_loss_grad, phsvds_gnn_adam);
+  select    among the start and the checkpoints at a quarter, half and
+            the end of training, the network with the fewest products on a
+            validation matrix (the loss measures the distance to exact
+            corrections, not the quality inside the iteration);
   evaluate  k smallest triplets of held-out matrices with no
-            preconditioner, with Jacobi, and with the trained network (which
-            falls back to Jacobi when it stops helping), reporting products
-            with A and time to a residual of tol * ||A||.
+            preconditioner, with Jacobi, with the network at its start, the
+            last checkpoint and the selected one (each falls back to Jacobi
+            when it stops helping), reporting products with A and time to a
+            residual of tol * ||A||.
 
 Command line (one GPU):
   python -m paper_1408_5535_amd.learned --out weights.npy
@@ -61,39 +72,91 @@ def harvest_family(seeds, make, k=10, block=4, every=25, max_pairs=48, tol=1e-10
         g = GnnGraph(A, width)
         mats.append(A)
         graphs.append(g)
+        # the network is trained toward M r with M ~ (projected C)^-1 positive
+        # definite, the sign convention of the Jacobi step it starts from:
+        # the target is the harvested correction with its sign flipped (the
+        # correction equation has -r on its right-hand side; the span is
+        # the same)
         for j in range(R.shape[0]):
             pairs.append((gi, R[j].float().contiguous(), X[j].float().contiguous(), float(th[j]),
-                          T[j].float().contiguous()))
+                          (-T[j]).float().contiguous()))
         _say(f"[learned] harvest seed {seed}: {R.shape[0]} pairs, {st['mv_stage1']} products, "
              f"{time.time() - t0:.1f}s")
     return mats, graphs, pairs
 
 
-def train(graphs, pairs, width=32, epochs=30, lr=1e-3, batch=16, seed=0):
+def ch_norm_bound(A_host):
+    """||A D^-1/2||^2 = the largest eigenvalue of Ch = D^-1/2 A^T A D^-1/2
+    (D = diag(A^T A)), from the library's largest-mode solve (k = 1)."""
+    import scipy.sparse as sp
+    from . import svds_smallest
+    d = np.asarray(A_host.multiply(A_host).sum(axis=0)).ravel()
+    B = (A_host @ sp.diags(1.0 / np.sqrt(np.maximum(d, 1e-300)))).tocsr()
+    sig, _, _, info = svds_smallest(DeviceCSR.from_scipy(B), 1, 1e-10, which="largest", block=1)
+    return float(sig[0]) ** 2
+
+
+def poly_init(A_host, width=32, degree=3, margin=1.05):
+    """Initial weights: the polynomial preconditioner D^-1/2 p(Ch) D^-1/2,
+    p fitted to 1/x on (0, margin ||A D^-1/2||^2]."""
     import workloads as wl
-    w = gnn_pack(wl.gnn_init_weights(width=width, seed=seed))
+    hi = margin * ch_norm_bound(A_host)
+    coeffs = wl.inverse_poly_coeffs(hi, degree)
+    return gnn_pack(wl.gnn_poly_weights(coeffs, width)), hi, coeffs
+
+
+def train(graphs, pairs, width=32, epochs=30, lr=1e-3, batch=16, seed=0, init=None,
+          checkpoints=()):
+    """Adam from `init` (or Glorot weights); returns (final weights, loss per
+    epoch, {epoch: weights} for the epochs in `checkpoints`)."""
+    import workloads as wl
+    w = (init.clone() if init is not None
+         else gnn_pack(wl.gnn_init_weights(width=width, seed=seed)))
     assert w.numel() == gnn_nweights(width)
     t0 = time.time()
+    snaps = {}
+
+    def keep(ep, cur):
+        if ep in checkpoints:
+            snaps[ep] = cur.clone()
+
     hist = train_gnn(graphs, pairs, w, epochs=epochs, lr=lr, batch=batch, seed=seed,
-                     log=lambda s: _say(f"[learned] {s} ({time.time() - t0:.0f}s)"))
-    return w, hist
+                     log=lambda s: _say(f"[learned] {s} ({time.time() - t0:.0f}s)"),
+                     on_epoch=keep)
+    return w, hist, snaps
 
 
-def evaluate(seeds, make, w, width=32, k=10, block=4, tol=1e-12, max_matvecs=200_000,
-             fallback_window=0):
+def select_by_validation(cands, make, seed, width=32, k=10, block=4):
+    """The candidate network (name -> weights) with the fewest products with
+    A on one validation matrix (ties: the first), and the products of each.
+    The training loss measures the distance to exact corrections, which is
+    not what makes a preconditioner good inside the iteration; the
+    validation solve measures that directly."""
+    rows = evaluate([seed], make, cands, width=width, k=k, block=block, baselines=False)
+    mv = {r["method"]: r["mv"] for r in rows if r["status"] == 0}
+    best = min(mv, key=lambda name: (mv[name], list(cands).index(name))) if mv else list(cands)[0]
+    return best, {r["method"]: (r["mv"], r["status"]) for r in rows}
+
+
+def evaluate(seeds, make, nets, width=32, k=10, block=4, tol=1e-12, max_matvecs=200_000,
+             fallback_window=0, baselines=True):
     """Per held-out matrix: (method, products with A, seconds, status,
-    largest residual / ||A||, fallbacks) for none, Jacobi and the network."""
+    largest residual / ||A||, fallbacks) for none, Jacobi and each network
+    (``nets``: name -> weights, or one weight tensor named 'gnn')."""
+    if isinstance(nets, torch.Tensor):
+        nets = {"gnn": nets}
     rows = []
     for seed in seeds:
         A = DeviceCSR.from_scipy(make(seed))
-        for method in ("none", "jacobi", "gnn"):
-            kw = {"gnn_width": width} if method == "gnn" else {}
+        for method in (["none", "jacobi"] if baselines else []) + list(nets):
+            net = nets.get(method)
+            kw = {"gnn_width": width} if net is not None else {}
             s = Solver(A, k, block=block, max_matvecs=max_matvecs, **kw)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            sig, U, V, info = s.solve(tol, precond=method,
-                                      gnn_weights=w if method == "gnn" else None,
-                                      gnn_width=width, fallback_window=fallback_window)
+            sig, U, V, info = s.solve(tol, precond="gnn" if net is not None else method,
+                                      gnn_weights=net, gnn_width=width,
+                                      fallback_window=fallback_window)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             row = {"seed": seed, "method": method, "mv": int(info["mv_total"]),
@@ -119,25 +182,48 @@ def main(argv=None):
     ap.add_argument("--weights", default="", help="evaluate these weights, skip training")
     ap.add_argument("--shift-scale", type=float, default=0.0,
                     help="rho of the harvested equation (C - rho theta I) t = -r")
+    ap.add_argument("--init", choices=["poly", "glorot"], default="poly")
+    ap.add_argument("--val-seed", type=int, default=1500,
+                    help="validation matrix for choosing among the checkpoints")
+    ap.add_argument("--lr", type=float, default=1e-3)
     args = ap.parse_args(argv)
 
     def make(seed):
         return random12(seed, args.m, args.n)
 
+    nets, meta = {}, {}
     if args.weights:
-        w = torch.tensor(np.load(args.weights), dtype=torch.float32, device="cuda")
+        nets["gnn"] = torch.tensor(np.load(args.weights), dtype=torch.float32, device="cuda")
         hist = []
     else:
+        init = None
+        if args.init == "poly":
+            init, hi, coeffs = poly_init(make(args.train_seeds[0]), args.width)
+            nets["gnn_init"] = init
+            meta = {"ch_bound": hi, "poly_coeffs": [float(c) for c in coeffs]}
+            _say(f"[learned] polynomial start: bound {hi:.4f}, coefficients {meta['poly_coeffs']}")
         mats, graphs, pairs = harvest_family(range(*args.train_seeds), make, every=args.every,
                                              max_pairs=args.max_pairs, width=args.width,
                                              shift_scale=args.shift_scale)
-        w, hist = train(graphs, pairs, width=args.width, epochs=args.epochs)
+        marks = sorted({args.epochs // 4 - 1, args.epochs // 2 - 1, args.epochs - 1} - {-1})
+        w, hist, snaps = train(graphs, pairs, width=args.width, epochs=args.epochs, lr=args.lr,
+                               init=init, checkpoints=marks)
         del mats, graphs, pairs
         torch.cuda.empty_cache()
+        # checkpoint selection on a validation matrix (not a training or
+        # evaluation seed)
+        cands = ({"start": init} if init is not None else {})
+        cands.update({f"epoch{e + 1}": snaps[e] for e in marks})
+        best, val = select_by_validation(cands, make, args.val_seed, width=args.width)
+        meta["validation"] = {name: v[0] for name, v in val.items()}
+        meta["selected"] = best
+        _say(f"[learned] validation products {meta['validation']}, selected {best}")
+        nets["gnn_last"] = w
+        nets["gnn"] = cands[best]
         if args.out:
-            np.save(args.out, w.cpu().numpy())
-    rows = evaluate(range(*args.eval_seeds), make, w, width=args.width)
-    print(json.dumps({"loss_per_epoch": hist, "evaluation": rows}), flush=True)
+            np.save(args.out, cands[best].cpu().numpy())
+    rows = evaluate(range(*args.eval_seeds), make, nets, width=args.width)
+    print(json.dumps({"loss_per_epoch": hist, "init": meta, "evaluation": rows}), flush=True)
 
 
 if __name__ == "__main__":

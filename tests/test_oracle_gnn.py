@@ -125,3 +125,42 @@ def test_gnn_preconditioned_oracle_converges_with_fallback():
     assert out["converged"]
     assert np.allclose(out["sigma"], sig, rtol=1e-10)
     assert np.all(out["res"] <= 1e-12 * an)
+
+
+def test_polynomial_weights_give_the_symmetric_polynomial_preconditioner():
+    """With the polynomial weights of workloads.gnn_poly_weights and theta = 0
+    the network is, by construction, the operator
+    t = (I - x x^T) D^-1/2 p(Ch) D^-1/2 r / mean(diag C) with Ch =
+    D^-1/2 A^T A D^-1/2 (D = diag C / mean diag C); checked against that
+    closed form built from dense matrices (width 8 and 32, degree 1 to 3)."""
+    A = wl.random_sparse(300, 200, 6, seed=9)
+    Cd = (A.T @ A).toarray()
+    dC = np.diag(Cd).copy()
+    dm = dC.mean()
+    Dn = dC / dm
+    Chd = Cd / np.sqrt(np.outer(dC, dC))
+    g = pc.Graph(A)
+    r = np.random.default_rng(1).standard_normal(200)
+    x = np.random.default_rng(2).standard_normal(200)
+    x /= np.linalg.norm(x)
+    for width in (8, 32):
+        for coeffs in ([0.7], [2.0, -0.5], [3.0, -2.5, 0.6], [3.67, -3.94, 1.61, -0.22]):
+            P = wl.gnn_poly_weights(coeffs, width)
+            t, _ = pc.forward(g, P, r, x, 0.0)
+            pC = sum(c * np.linalg.matrix_power(Chd, k) for k, c in enumerate(coeffs))
+            ref = (pC @ (r / np.sqrt(Dn))) / np.sqrt(Dn) / dm
+            ref -= x * (x @ ref)
+            assert np.allclose(t, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+
+
+def test_inverse_poly_coeffs_fit():
+    """x p(x) approximates 1 on (0, hi]: the fit error falls with the degree
+    and p is positive on the interval for degree 3."""
+    errs = []
+    xs = np.linspace(0.01, 3.0, 500)
+    for deg in (1, 2, 3):
+        c = wl.inverse_poly_coeffs(3.0, deg)
+        p = np.polyval(c[::-1], xs)
+        errs.append(np.sqrt(np.mean((xs * p - 1) ** 2)))
+    assert errs[0] > errs[1] > errs[2]
+    assert np.all(np.polyval(wl.inverse_poly_coeffs(3.0, 3)[::-1], xs) > 0)

@@ -241,3 +241,44 @@ def gnn_init_weights(width: int = 32, nin: int = 4, seed: int = 0) -> dict:
         P[f"b{l}"] = np.zeros(w)
     P["wo"] = glorot(w, 1)[:, 0]
     return P
+
+
+def inverse_poly_coeffs(hi: float, deg: int = 3, npts: int = 2000) -> np.ndarray:
+    """Coefficients c_0..c_deg of the polynomial p minimising the sum of
+    (x p(x) - 1)^2 over npts points spread evenly on (0, hi]: a polynomial
+    approximation of 1/x on the spectrum of a positive operator whose largest
+    eigenvalue is at most hi.  (With hi below the largest eigenvalue, p can
+    turn negative there.)"""
+    xs = np.linspace(hi / npts, hi, npts)
+    V = np.vander(xs, deg + 1, increasing=True)
+    return np.linalg.lstsq(V * xs[:, None], np.ones_like(xs), rcond=None)[0]
+
+
+def gnn_poly_weights(coeffs, width: int = 32, nin: int = 4) -> dict:
+    """Weights that make the message-passing preconditioner the polynomial
+    p(Ch) = sum_k coeffs[k] Ch^k applied to its first input feature u (at
+    most degree 3: one power of Ch per layer).  Channels 2k and 2k+1 of the
+    layers carry relu(Ch^k u) and relu(-Ch^k u), so every layer stays linear
+    in u; the readout takes coeffs[k] (relu(Ch^k u) - relu(-Ch^k u)) and
+    coeffs[0] is lowered by one for the Jacobi feature the readout adds.
+    Other channels, all biases and the d, tau inputs are zero."""
+    c = [float(x) for x in coeffs]
+    assert 1 <= len(c) <= 4 and width >= 2 * len(c)
+    P = {"Ws1": np.zeros((nin, width)), "Wm1": np.zeros((nin, width)), "b1": np.zeros(width)}
+    for l in (2, 3):
+        P[f"Ws{l}"] = np.zeros((width, width))
+        P[f"Wm{l}"] = np.zeros((width, width))
+        P[f"b{l}"] = np.zeros(width)
+    P["Ws1"][0, 0], P["Ws1"][0, 1] = 1.0, -1.0          # u, -u
+    P["Wm1"][0, 2], P["Wm1"][0, 3] = 1.0, -1.0          # Ch u, -Ch u
+    for l, top in ((2, 4), (3, 6)):
+        for ch in range(top):                            # carry the lower powers
+            P[f"Ws{l}"][ch, ch] = 1.0
+        a = top - 2                                      # the highest power so far
+        P[f"Wm{l}"][a, top], P[f"Wm{l}"][a + 1, top] = 1.0, -1.0
+        P[f"Wm{l}"][a, top + 1], P[f"Wm{l}"][a + 1, top + 1] = -1.0, 1.0
+    P["wo"] = np.zeros(width)
+    c[0] -= 1.0
+    for k, ck in enumerate(c):
+        P["wo"][2 * k], P["wo"][2 * k + 1] = ck, -ck
+    return P
