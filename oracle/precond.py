@@ -28,7 +28,7 @@ Jacobi preconditioner and the network learns a correction to it.
 Loss of one sample: ||t - t*||^2 / ||t*||^2 (t* is orthogonal to x).
 Optimiser: Adam (Kingma & Ba), lr 1e-3, beta1 0.9, beta2 0.999, eps 1e-8.
 
-Parity of the trained network's quality: unpinned (judged by product counts
+Parity of the trained network's quality: unpinned (measured by product counts
 and time against Jacobi and no preconditioner on held-out matrices).
 """
 from __future__ import annotations

@@ -21,8 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libphsvds.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run paper_1408_5535_amd/build.py "
-                      "(or __graft_entry__.build()) first")
+    raise ImportError(f"{LIB_PATH} is not built; run python paper_1408_5535_amd/build.py first")
 _lib = ctypes.CDLL(LIB_PATH)
 
 PHSVDS_OK = 0
