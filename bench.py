@@ -140,7 +140,8 @@ def host_residuals(A, AT, sig, U, V):
     return np.sqrt(np.sum(ru * ru, axis=0) + np.sum(rv * rv, axis=0))
 
 
-def compare(family, max_mv, gnn_weights, gnn_width, max_restarts=10000, only=None):
+def compare(family, max_mv, gnn_weights, gnn_width, max_restarts=10000, only=None,
+            gnn_poly=False):
     """End-to-end comparison of the method's arms (float64 or float32 stage 1,
     none / Jacobi / learned preconditioner) on one matrix of a family.  One
     JSON line per arm, then a summary line.  Residuals are recomputed on the
@@ -164,6 +165,14 @@ def compare(family, max_mv, gnn_weights, gnn_width, max_restarts=10000, only=Non
     if gnn_weights:
         w = torch.tensor(np.load(gnn_weights), dtype=torch.float32, device="cuda")
         arms += [("mixed", "gnn")]
+    elif gnn_poly:
+        # the learned preconditioner at its polynomial start, built for this
+        # matrix (degree-3 fit of 1/x on the spectrum of D^-1/2 A^T A D^-1/2)
+        from paper_1408_5535_amd import learned
+        w, hi, coeffs = learned.poly_init(A, gnn_width)
+        print(json.dumps({"gnn_poly_start": {"width": gnn_width, "ch_bound": hi,
+                                             "coeffs": [float(c) for c in coeffs]}}), flush=True)
+        arms += [("f64", "gnn"), ("mixed", "gnn")]
     if only:
         arms = [tuple(a.split("+")) for a in only]
     cap = max_mv or cfg["cap"]
@@ -285,6 +294,8 @@ def main():
                          "none / Jacobi (/ learned, with --gnn-weights) on one matrix of a family")
     ap.add_argument("--gnn-weights", default="", help="trained weights (.npy) for --compare")
     ap.add_argument("--gnn-width", type=int, default=32)
+    ap.add_argument("--gnn-poly", action="store_true",
+                    help="--compare also with the learned preconditioner at its polynomial start")
     ap.add_argument("--arms", nargs="*", default=None,
                     help="arms to run in --compare, e.g. f64+jacobi mixed+gnn")
     ap.add_argument("--max-restarts", type=int, default=10000,
@@ -296,7 +307,7 @@ def main():
     args = ap.parse_args()
     if args.compare:
         compare(args.compare, args.max_mv, args.gnn_weights, args.gnn_width, args.max_restarts,
-                args.arms)
+                args.arms, args.gnn_poly)
         return
     if args.spmm_probe:
         spmm_probe(args.spmm_probe, args.N)

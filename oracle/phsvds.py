@@ -198,7 +198,7 @@ def _pad(Sc, rows):
 # --------------------------------------------------------------------------
 def stage1_gdk(A, k, tol, b, pmax, pmin, X0, which="smallest", precond=None, anorm=None,
                max_restarts=10000, floor=10.0, eps=EPS64, seed=11, stats: Stats | None = None,
-               max_iters=None, callback=None, fallback=None, fallback_window=25):
+               max_iters=None, callback=None, fallback=None, fallback_window=25, sn2_init=0.0):
     """Block GD+k on C for k extreme eigenpairs (Sections 2.2, 2.4, 3.1).
 
     ``precond(R, theta, X) -> T`` maps the residual block to the correction
@@ -221,7 +221,7 @@ def stage1_gdk(A, k, tol, b, pmax, pmin, X0, which="smallest", precond=None, ano
     H = _sym(V.T @ W)
     Xl = np.zeros((n, 0))
     thl = []
-    sn2 = float(anorm) ** 2 if anorm else 0.0
+    sn2 = float(anorm) ** 2 if anorm else float(sn2_init)
     prev = None
     hist = []
     L = max(100, 20 * int(math.ceil(pmax / b)))
@@ -573,10 +573,27 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
                                     for i in range(R.shape[1])])
     elif precond != "none":
         raise ValueError(precond)
+    sn2_init = 0.0
+    if precond == "gnn" and not anorm:
+        # the learned preconditioner smooths, so the basis does not reach
+        # the top of the spectrum: start the ||A||^2 estimate from twelve
+        # steps of power iteration on C (a lower bound)
+        x = _Rand(seed + 7).vec(A.shape[1])
+        for it in range(13):
+            nx = float(np.linalg.norm(x))
+            if not nx > 0:
+                break
+            if it > 0:
+                sn2_init = nx
+            if it == 12:
+                break
+            x = A.T @ (A @ (x / nx))
+            stats.mv_prec += 1
     Xl, thl, Vr, sn2, info = stage1_gdk(A, k, tol, b, pmax, pmin, X0, which, pc1, anorm,
                                         max_restarts, floor, EPS64, stats=stats,
                                         max_iters=max_iters,
-                                        fallback=fb if precond == "gnn" else None)
+                                        fallback=fb if precond == "gnn" else None,
+                                        sn2_init=sn2_init)
     sn = math.sqrt(sn2)
     stats.anorm_est = sn
     an = float(anorm) if anorm else sn

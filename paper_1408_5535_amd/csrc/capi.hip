@@ -322,6 +322,13 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   P1.init64 = o.init_block;
   P1.init32 = nullptr;
   P1.init_cols = d.b;
+  if (pkind == PHSVDS_PREC_GNN && !(o.anorm > 0)) {
+    // a smoothing preconditioner keeps the top of the spectrum out of the
+    // basis, so the largest Ritz value no longer estimates ||A||^2: start
+    // the running maximum from power iteration on C (a lower bound)
+    P1.sn2_init = power_norm2(c, A64, At64, pl.tb.Xn, pl.tb.Ym, pl.tb.Z, 12, sp);
+    stl.mv_prec += 12;
+  }
   Stage1Result r1;
   const double *Xl64 = nullptr, *Vr64 = nullptr;
   int nvr = 0;

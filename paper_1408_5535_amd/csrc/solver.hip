@@ -581,6 +581,34 @@ template Stage1Result run_stage1<double>(Ctx &, const SpMat<double> &, const SpM
                                          SmallPool &);
 
 // ------------------------------------------------------------------------
+// ||C x|| after `iters` steps of power iteration on C = A^T A from a
+// counter-based random start, float64: a lower bound on ||A||^2.  x and z
+// are n-vectors, y an m-vector (work space).
+double power_norm2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At, double *x, double *y,
+                   double *z, int iters, SmallPool &sp) {
+  const int64_t n = A.n;
+  double *nrm = sp.vec(23), *f = sp.vec(23) + 8;
+  fill_random(cm(x, n, 1, n), c.seed, 5000000 + (c.nrand++) * 64, c.s);
+  double lam = 0.0, h[1];
+  for (int it = 0; it <= iters; ++it) {
+    colnorm2(cm(x, n, 1, n), 0, n, nrm, c.sc, c.s);
+    c.d2h(h, nrm, sizeof(double));
+    c.sync();
+    const double nx = std::sqrt(std::max(h[0], 0.0));
+    if (!(nx > 0.0)) break;
+    if (it > 0) lam = nx;  // ||C x_prev||, x_prev of unit norm
+    if (it == iters) break;
+    const double inv = 1.0 / nx;
+    c.h2d(f, &inv, sizeof(double));
+    scale_cols(cm(x, n, 1, n), f, c.s);
+    spmm(A, 1, x, y, false, c.s);
+    spmm(At, 1, y, z, false, c.s);
+    std::swap(x, z);
+  }
+  return lam;
+}
+
+// ------------------------------------------------------------------------
 // Transition Rayleigh-Ritz on C over Z = orth([X_lock, leading restart
 // vectors]), evaluated as the SVD of A Z (same Ritz pairs, no squaring).
 void run_transition(Ctx &c, const SpMat<double> &A, const double *Xl, int k, const double *Vr,

@@ -85,6 +85,9 @@ struct Stage1Bufs {
   T *Gs;  // 3 n scratch for the learned preconditioner
 };
 
+double power_norm2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At, double *x, double *y,
+                   double *z, int iters, SmallPool &sp);
+
 struct Stage1Result {
   bool converged = false;
   int nl = 0, p = 0;
