@@ -59,9 +59,8 @@ __device__ inline void rr_pair(int P, int r, int k, int &a, int &b) {
 //     the reflectors stay in the rows of H they annihilate.
 //  2. Selected eigenvalues of T by multisection of Sturm sequences: the
 //     eigenvalue of rank r is bracketed by the lanes of one group, each
-//     evaluating the count at up to four interior points per step
-//     (independent recurrences, interleaved); the group keeps the
-//     subinterval below the first point whose count exceeds the rank.
+//     evaluating the count at one interior point per step; the group keeps
+//     the subinterval below the first point whose count exceeds the rank.
 //  3. Eigenvectors of T by inverse iteration, one lane per vector;
 //     vectors of nearly equal eigenvalues are orthogonalised between
 //     sweeps, those of a cluster (eigenvalues within 1e-3 ||T||) after the
@@ -347,14 +346,13 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
   //    nvec < n): rank n-1.  Rank r is ascending index r, or n-1-r if desc.
   {
     const int ne = (other_end && nvec < n) ? nvec + 1 : nvec;
+    // one point per lane: the recurrences are issue-bound, so a second or
+    // fourth interleaved point per lane costs nearly its full time while
+    // adding under one bit per step (p = 35: 4 + 1 eigenvalues 24.5 -> 17.6
+    // us, 21 + 1 eigenvalues 53.1 -> 26.7 us against 2 and 4 points per lane)
     int L = 64;
     while (L * ne > 256) L >>= 1;
-    if (L <= 16)
-      multisect<4>(ds, e2s, n, ne, nvec, L, desc, lo * sc, hi * sc, lamv);
-    else if (L == 32)
-      multisect<2>(ds, e2s, n, ne, nvec, L, desc, lo * sc, hi * sc, lamv);
-    else
-      multisect<1>(ds, e2s, n, ne, nvec, L, desc, lo * sc, hi * sc, lamv);
+    multisect<1>(ds, e2s, n, ne, nvec, L, desc, lo * sc, hi * sc, lamv);
   }
   __syncthreads();
   if (w0) {
@@ -372,14 +370,28 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
     double ru = 1.0 / u;  // one division per row: the multiplier reuses it
     uu[c] = ru;
     ll[c] = 0.0;
-    for (int i = 1; i < n; ++i) {
-      const double es = e[i] * sc;
-      const double li = es * ru;
-      ll[i * kLd + c] = li;
-      u = ds[i] - lam - li * es;
-      if (fabs(u) < tiny) u = tiny;
-      ru = 1.0 / u;
-      uu[i * kLd + c] = ru;
+    // rows eight at a time (e and ds of the chunk loaded together; rows
+    // past n are padding: ds = 4, e = 0, results unused)
+    for (int i0 = 1; i0 < n; i0 += 8) {
+      double ev[8], dv[8];
+#pragma unroll
+      for (int u8 = 0; u8 < 8; ++u8) {
+        ev[u8] = i0 + u8 < n ? e[i0 + u8] : 0.0;
+        dv[u8] = ds[i0 + u8];
+      }
+#pragma unroll
+      for (int u8 = 0; u8 < 8; ++u8) {
+        const int i = i0 + u8;
+        const double es = ev[u8] * sc;
+        const double li = es * ru;
+        u = dv[u8] - lam - li * es;
+        if (fabs(u) < tiny) u = tiny;
+        ru = 1.0 / u;
+        if (i < n) {
+          ll[i * kLd + c] = li;
+          uu[i * kLd + c] = ru;
+        }
+      }
     }
     for (int i = 0; i < n; ++i) {
       uint32_t hsh = (uint32_t)(i * kSmallMax + c + 1) * 0x9E3779B9u;
@@ -525,7 +537,17 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
         double yi = 0.0;
         if (t < n) {
           yi = y[t * kLd + c];
-          for (int k = st; k < c; ++k) yi = fma(-pq[k], y[t * kLd + k], yi);
+          for (int k0 = st; k0 < c; k0 += 8) {
+            double pv[8], yv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int k = k0 + u < c ? k0 + u : c - 1;
+              pv[u] = k0 + u < c ? pq[k] : 0.0;
+              yv[u] = y[t * kLd + k];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) yi = fma(-pv[u], yv[u], yi);
+          }
         }
         const double nrm = sqrt(wave_total(yi * yi));
         if (t < n) y[t * kLd + c] = nrm > 0 ? yi / nrm : 0.0;
@@ -673,7 +695,8 @@ void svdj(const double *M, int ldm, int rows, int cols, double *sv, double *Y, i
 __global__ __launch_bounds__(256) void k_chol_inv(const double *G, int ldg, int w, double shift,
                                                   double *Rg, double *Ri, int ldr, int *flag,
                                                   CgsDiag dg, const double *part, int np) {
-  __shared__ double r[kSmallMax * kLd];  // r[i * kLd + j], upper triangle used
+  __shared__ double r[kSmallMax * kLd];   // r[i * kLd + j], upper triangle used
+  __shared__ double ri[kSmallMax * kLd];  // R^{-1}, same layout
   __shared__ int bad;
   const int t = threadIdx.x;
   if (t == 0) bad = 0;
@@ -686,16 +709,21 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double *G, int ldg, int 
     const int grp = t / tpe, sub = t % tpe, ngrp = 256 / tpe;
     for (int e0 = 0; e0 < E; e0 += ngrp) {
       const int e = e0 + grp;
-      double s0 = 0.0, s1 = 0.0;
+      // eight partials per lane in flight at a time (the padding past np
+      // rereads the last partial with weight 0)
+      double sv = 0.0;
       if (e < E) {
-        int b = sub;
-        for (; b + tpe < np; b += 2 * tpe) {
-          s0 += part[(int64_t)b * E + e];
-          s1 += part[(int64_t)(b + tpe) * E + e];
+        for (int b0 = sub; b0 < np; b0 += 8 * tpe) {
+          double pv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int b = b0 + u * tpe;
+            pv[u] = part[(int64_t)(b < np ? b : np - 1) * E + e];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) sv += b0 + u * tpe < np ? pv[u] : 0.0;
         }
-        if (b < np) s0 += part[(int64_t)b * E + e];
       }
-      double sv = s0 + s1;
       for (int o = tpe / 2; o > 0; o >>= 1) sv += __shfl_xor(sv, o, tpe);
       if (sub == 0 && e < E) r[(e / w) * kLd + e % w] = sv;
     }
@@ -707,10 +735,20 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double *G, int ldg, int 
     // squared column norms around two Gram-Schmidt passes from the final
     // Gram matrix and the two coefficient blocks
     double h1 = 0.0, h2 = 0.0;
-    for (int i = 0; i < dg.nh; ++i) {
-      const double c1 = dg.H1[i + (int64_t)t * dg.ldh], c2 = dg.H2[i + (int64_t)t * dg.ldh];
-      h1 = fma(c1, c1, h1);
-      h2 = fma(c2, c2, h2);
+    for (int i0 = 0; i0 < dg.nh; i0 += 8) {
+      double c1[8], c2[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t i = i0 + u < dg.nh ? i0 + u : dg.nh - 1;
+        c1[u] = dg.H1[i + (int64_t)t * dg.ldh];
+        c2[u] = dg.H2[i + (int64_t)t * dg.ldh];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double m = i0 + u < dg.nh ? 1.0 : 0.0;
+        h1 = fma(m * c1[u], c1[u], h1);
+        h2 = fma(m * c2[u], c2[u], h2);
+      }
     }
     const double a2 = gij(t, t);
     dg.n2[t] = a2;
@@ -757,24 +795,26 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double *G, int ldg, int 
     }
     __syncthreads();
   }
-  // write R, then Rinv column by column (thread per column, back substitution)
-  for (int idx = t; idx < w * w; idx += blockDim.x) {
-    int i = idx % w, j = idx / w;
-    Rg[i + (int64_t)j * ldr] = (j >= i) ? r[i * kLd + j] : 0.0;
-  }
+  // Rinv column by column in LDS (thread per column, back substitution),
+  // then R and Rinv to global memory
   for (int j = t; j < w; j += blockDim.x) {
     // solve R x = e_j; x_i = 0 for i > j
     for (int i = w - 1; i >= 0; --i) {
       double x = 0.0;
       if (i <= j) {
         double sacc = (i == j) ? 1.0 : 0.0;
-        for (int q = i + 1; q <= j; ++q) sacc -= r[i * kLd + q] * Ri[q + (int64_t)j * ldr];
+        for (int q = i + 1; q <= j; ++q) sacc -= r[i * kLd + q] * ri[q * kLd + j];
         x = sacc / r[i * kLd + i];
       }
-      Ri[i + (int64_t)j * ldr] = x;
+      ri[i * kLd + j] = x;
     }
   }
   __syncthreads();
+  for (int idx = t; idx < w * w; idx += blockDim.x) {
+    int i = idx % w, j = idx / w;
+    Rg[i + (int64_t)j * ldr] = (j >= i) ? r[i * kLd + j] : 0.0;
+    Ri[i + (int64_t)j * ldr] = ri[i * kLd + j];
+  }
   if (t == 0) flag[0] = bad;
 }
 
@@ -855,8 +895,20 @@ __device__ inline void wave_cgs2(double *q, int rows, int c, double *xs, double 
       if (rc) rc[r] += d0 + d1;
     }
     __syncthreads();
+    // eight coefficients at a time, their loads in flight together; the
+    // padding past c reads column c - 1 with coefficient 0
     double acc = x;
-    for (int j = 0; j < c; ++j) acc = fma(-dots[j], q[j * kLd + r], acc);
+    for (int j0 = 0; j0 < c; j0 += 8) {
+      double dv[8], qv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = j0 + u < c ? j0 + u : c - 1;
+        dv[u] = j0 + u < c ? dots[j] : 0.0;
+        qv[u] = q[j * kLd + r];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = fma(-dv[u], qv[u], acc);
+    }
     x = (r < rows) ? acc : 0.0;
   }
   q[c * kLd + r] = x;
