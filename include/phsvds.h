@@ -219,10 +219,16 @@ int phsvds_harvest(const phsvds_csr *A, int k, int every, int max_pairs, double 
  * enable != 0: enable = 1 records every kind, any other value is a bit mask
  * of kinds shifted left by one (bit k+1 = kind k, e.g. 2 = float64 SpMM
  * only); phsvds_profile(0) stops.
+ * phsvds_profile_sample(every), called after phsvds_profile, times only
+ * the first pair of consecutive operations of a kind in every `every` pairs
+ * (each event record idles the stream for a few microseconds, so sampling
+ * keeps the timed run close to an untimed one); phsvds_profile resets it to
+ * 1, and every < 1 is PHSVDS_EINVAL.
  * phsvds_profile_read returns the number of timed operations, their summed
  * device time (s) and their summed algorithmic HBM bytes.  Not thread-safe
  * against concurrent solves. */
 int phsvds_profile(int enable);
+int phsvds_profile_sample(int every);
 int phsvds_profile_read(int kind, int64_t *launches, double *seconds, double *bytes);
 
 #ifdef __cplusplus

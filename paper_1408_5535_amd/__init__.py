@@ -86,19 +86,23 @@ _lib.phsvds_svds.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, ctypes.c_double
 
 
 _lib.phsvds_profile.argtypes = [ctypes.c_int]
+_lib.phsvds_profile_sample.argtypes = [ctypes.c_int]
 _lib.phsvds_profile_read.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]
 PROFILE_KINDS = {"spmm_f64": 0, "spmm_f32": 1, "tn": 2, "nn": 3, "ritz": 4}
 
 
-def profile(enable: bool, kinds=None) -> None:
+def profile(enable: bool, kinds=None, every: int = 1) -> None:
     """Start (clearing counters) or stop event timing of the library's
-    kernels; ``kinds`` (names or numbers) restricts the timed kinds."""
+    kernels; ``kinds`` (names or numbers) restricts the timed kinds, and
+    ``every`` > 1 times one pair of consecutive operations in ``every``."""
     code = int(bool(enable))
     if enable and kinds is not None:
         code = sum(1 << ((PROFILE_KINDS[k] if isinstance(k, str) else k) + 1) for k in kinds)
     _check(_lib.phsvds_profile(code), "profile")
+    if enable:
+        _check(_lib.phsvds_profile_sample(int(every)), "profile")
 
 
 def profile_read(kind) -> tuple:

@@ -21,7 +21,9 @@ struct Rec {
 struct Prof {
   std::mutex mu;
   bool on = false;
-  int mask = 0;  // kinds recorded (bit k = kind k)
+  int mask = 0;   // kinds recorded (bit k = kind k)
+  int every = 1;  // time one pair of consecutive operations in `every`
+  int64_t calls[kProfCount] = {};
   std::vector<hipEvent_t> pool;
   std::vector<Rec> live;
   hipEvent_t pending = nullptr;
@@ -64,6 +66,12 @@ bool prof_on() { return g.on; }
 void prof_begin(int kind, hipStream_t s) {
   if (!g.on || !((g.mask >> kind) & 1)) return;
   std::lock_guard<std::mutex> lk(g.mu);
+  // sampling by pairs keeps A X and the A^T Y that follows it together
+  const int64_t c = g.calls[kind]++;
+  if ((c / 2) % g.every != 0) {
+    g.pending = nullptr;
+    return;
+  }
   g.pending = get_event();
   g.pending_kind = kind;
   PHS_HIP(hipEventRecord(g.pending, s));
@@ -91,8 +99,10 @@ int phsvds_profile(int enable) {
     if (enable) {
       for (int k = 0; k < phs::kProfCount; ++k) {
         phs::g.n[k] = 0;
+        phs::g.calls[k] = 0;
         phs::g.sec[k] = phs::g.bytes[k] = 0.0;
       }
+      phs::g.every = 1;
     }
     phs::g.on = enable != 0;
     phs::g.mask = enable == 1 ? (1 << phs::kProfCount) - 1 : (enable >> 1);
@@ -100,6 +110,14 @@ int phsvds_profile(int enable) {
   } catch (const phs::Error &e) {
     return e.code;
   }
+}
+
+int phsvds_profile_sample(int every) {
+  if (every < 1) return PHSVDS_EINVAL;
+  std::lock_guard<std::mutex> lk(phs::g.mu);
+  phs::g.every = every;
+  for (int k = 0; k < phs::kProfCount; ++k) phs::g.calls[k] = 0;
+  return PHSVDS_OK;
 }
 
 int phsvds_profile_read(int kind, int64_t *launches, double *seconds, double *bytes) {
