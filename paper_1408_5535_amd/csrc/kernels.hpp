@@ -161,11 +161,17 @@ void small_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const doubl
 // count[0] = min(kc + pc, rows) always.
 void restart_basis(const double *K, int ldk, int rows, int kc, const double *P, int ldp, int pc,
                    double *Y, int ldy, int *count, hipStream_t s);
+// H <- Y^T H Y (p x p -> hc x hc) and, with S given, Q = Y^T S (hc x ns),
+// in one launch (the restart projection of the Rayleigh-Ritz matrix).
+void restart_project(double *H, int ldh, int p, const double *Y, int ldy, int hc,
+                     const double *S, int lds, int ns, double *Q, int ldq, hipStream_t s);
 // Thin QR by two-pass modified Gram-Schmidt: M (rows x cols) = Q R.
 void small_qr(const double *M, int ldm, int rows, int cols, double *Q, int ldq, double *R,
               int ldr, hipStream_t s);
-// H(0:p+nb, p:p+nb) = G, H(p:p+nb, 0:p) = G(0:p)^T, symmetrised diagonal block.
-void h_border(double *H, int ldh, int p, int nb, const double *G, int ldg, hipStream_t s);
+// H(0:p+nb, p:p+nb) = G, H(p:p+nb, 0:p) = G(0:p)^T, symmetrised diagonal block;
+// with Z given, rows p..p+nb-1 of Z (nz columns) are zeroed in the same launch.
+void h_border(double *H, int ldh, int p, int nb, const double *G, int ldg, hipStream_t s,
+              double *Z = nullptr, int ldz = 0, int nz = 0);
 // Copy columns idx[0..nc) of A (rows x *) into B; idx on device.
 void gather_cols(const double *A, int lda, int rows, const int *idx, int nc, double *B, int ldb,
                  hipStream_t s);

@@ -859,6 +859,54 @@ void small_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const doubl
   PHS_CHECK_LAUNCH();
 }
 
+// Projection of the Rayleigh-Ritz matrix onto a restart basis, one launch:
+// H <- Y^T (H Y) (H p x p in, hc x hc out, Y p x hc) and, if S is given,
+// Q = Y^T S (hc x ns).  Same arithmetic as the two or three small_gemm
+// calls it replaces (each entry one fma chain in index order).
+__global__ __launch_bounds__(256) void k_restart_project(double *H, int ldh, int p,
+                                                         const double *Y, int ldy, int hc,
+                                                         const double *S, int lds, int ns,
+                                                         double *Q, int ldq) {
+  __shared__ double h[kSmallMax * kLd], y[kSmallMax * kLd], hy[kSmallMax * kLd];
+  const int t = threadIdx.x;
+  for (int e = t; e < p * p; e += 256) h[(e % p) + (e / p) * kLd] = H[e % p + (int64_t)(e / p) * ldh];
+  for (int e = t; e < p * hc; e += 256)
+    y[(e % p) + (e / p) * kLd] = Y[e % p + (int64_t)(e / p) * ldy];
+  __syncthreads();
+  // HY = H Y
+  for (int e = t; e < p * hc; e += 256) {
+    const int i = e % p, j = e / p;
+    double acc = 0.0;
+    for (int k = 0; k < p; ++k) acc = fma(h[i + k * kLd], y[k + j * kLd], acc);
+    hy[i + j * kLd] = acc;
+  }
+  __syncthreads();
+  // H = Y^T (H Y); Q = Y^T S
+  for (int e = t; e < hc * hc; e += 256) {
+    const int i = e % hc, j = e / hc;
+    double acc = 0.0;
+    for (int k = 0; k < p; ++k) acc = fma(y[k + i * kLd], hy[k + j * kLd], acc);
+    H[i + (int64_t)j * ldh] = acc;
+  }
+  if (S) {
+    for (int e = t; e < hc * ns; e += 256) {
+      const int i = e % hc, j = e / hc;
+      double acc = 0.0;
+      for (int k = 0; k < p; ++k) acc = fma(y[k + i * kLd], S[k + (int64_t)j * lds], acc);
+      Q[i + (int64_t)j * ldq] = acc;
+    }
+  }
+}
+
+void restart_project(double *H, int ldh, int p, const double *Y, int ldy, int hc,
+                     const double *S, int lds, int ns, double *Q, int ldq, hipStream_t s) {
+  PHS_REQUIRE(p >= 1 && p <= kSmallMax && hc >= 0 && hc <= p && (!S || (ns >= 0 && Q)),
+              kEinval, "restart_project: size out of range");
+  if (hc == 0) return;
+  k_restart_project<<<1, 256, 0, s>>>(H, ldh, p, Y, ldy, hc, S, lds, ns, Q, ldq);
+  PHS_CHECK_LAUNCH();
+}
+
 // ------------------------------------------ MGS2 helpers (restart, QR)
 // Single-wavefront Gram-Schmidt helpers for small coefficient spaces
 // (rows <= 64): lane r owns row r of every column, dot products are wave
@@ -1012,10 +1060,19 @@ void small_qr(const double *M, int ldm, int rows, int cols, double *Q, int ldq, 
 }
 
 // ------------------------------------------------------------ misc
-__global__ void k_h_border(double *H, int ldh, int p, int nb, const double *G, int ldg) {
-  const int tot = (p + nb) * nb;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+// Border of H from G = V^T W_new ((p + nb) x nb): columns and rows p..p+nb-1,
+// the new diagonal block symmetrised.  With Z given, also zeroes rows
+// p..p+nb-1 of Z (nz columns, leading dimension ldz) in the same launch.
+__global__ void k_h_border(double *H, int ldh, int p, int nb, const double *G, int ldg,
+                           double *Z, int ldz, int nz) {
+  const int tot = (p + nb) * nb, totz = Z ? nb * nz : 0;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot + totz;
        idx += gridDim.x * blockDim.x) {
+    if (idx >= tot) {
+      const int e = idx - tot;
+      Z[(p + e % nb) + (int64_t)(e / nb) * ldz] = 0.0;
+      continue;
+    }
     int i = idx % (p + nb), c = idx / (p + nb);
     double gv = G[i + (int64_t)c * ldg];
     if (i < p) {
@@ -1029,8 +1086,10 @@ __global__ void k_h_border(double *H, int ldh, int p, int nb, const double *G, i
   }
 }
 
-void h_border(double *H, int ldh, int p, int nb, const double *G, int ldg, hipStream_t s) {
-  k_h_border<<<cdiv((int64_t)(p + nb) * nb, 256), 256, 0, s>>>(H, ldh, p, nb, G, ldg);
+void h_border(double *H, int ldh, int p, int nb, const double *G, int ldg, hipStream_t s,
+              double *Z, int ldz, int nz) {
+  const int64_t tot = (int64_t)(p + nb) * nb + (Z ? (int64_t)nb * nz : 0);
+  k_h_border<<<cdiv(tot, 256), 256, 0, s>>>(H, ldh, p, nb, G, ldg, Z, ldz, nz);
   PHS_CHECK_LAUNCH();
 }
 

@@ -247,8 +247,8 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     if (!v_written) copy(rmv(Tb, n, nb, bw), cm(V[cur] + (int64_t)p * n, n, nb, n), c.s);
     tn(cm(V[cur], n, p + nb, n), none<T>(n), cm(W[cur] + (int64_t)p * n, n, nb, n), Gb, ld,
        c.sc, c.s);
-    h_border(H, ld, p, nb, Gb, ld, c.s);
-    if (nprev) zero_rows(prev, ld, p, p + nb, nprev, c.s);
+    // the previous block's coefficients have no component on the new columns
+    h_border(H, ld, p, nb, Gb, ld, c.s, nprev ? prev : nullptr, ld, nprev);
     p += nb;
   };
   // checked expansion (host decisions on dependence and breakdown)
@@ -491,8 +491,7 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
         const double *Yk = Y + (int64_t)conv.size() * ld;
         nn(cm(V[cur], n, p, n), none<T>(n), Yk, ld, 1.0, cm(V[1 - cur], n, nk, n), 0.0, c.s);
         nn(cm(W[cur], n, p, n), none<T>(n), Yk, ld, 1.0, cm(W[1 - cur], n, nk, n), 0.0, c.s);
-        small_gemm(false, false, p, nk, p, 1.0, H, ld, Yk, ld, 0.0, Hs, ld, c.s);
-        small_gemm(true, false, nk, nk, p, 1.0, Yk, ld, Hs, ld, 0.0, H, ld, c.s);
+        restart_project(H, ld, p, Yk, ld, nk, nullptr, ld, 0, nullptr, ld, c.s);
         cur = 1 - cur;
       }
       p = nk;
@@ -547,9 +546,7 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
       const int hc = std::min(pmin + nprev, p);
       nn(cm(V[cur], n, p, n), none<T>(n), Y, ld, 1.0, cm(V[1 - cur], n, hc, n), 0.0, c.s);
       nn(cm(W[cur], n, p, n), none<T>(n), Y, ld, 1.0, cm(W[1 - cur], n, hc, n), 0.0, c.s);
-      small_gemm(false, false, p, hc, p, 1.0, H, ld, Y, ld, 0.0, Hs, ld, c.s);
-      small_gemm(true, false, hc, hc, p, 1.0, Y, ld, Hs, ld, 0.0, H, ld, c.s);
-      small_gemm(true, false, hc, nb, p, 1.0, Y, ld, S, ld, 0.0, prev2, ld, c.s);
+      restart_project(H, ld, p, Y, ld, hc, S, ld, nb, prev2, ld, c.s);
       std::swap(prev, prev2);
       nprev = nb;
       cur = 1 - cur;
@@ -681,7 +678,7 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
   int cur = 0, p = 0, nl = 0, nprev = 0;
   double *Tb = bf.Tb, *T2b = bf.T2b, *Rb = bf.Rb;
   double *H = sp.mat(13), *Rq = sp.mat(14), *Ys = sp.mat(15), *Ysl = sp.mat(16),
-         *Yr = sp.mat(17), *Hs = sp.mat(18), *prev = sp.mat(19), *prev2 = sp.mat(20),
+         *Yr = sp.mat(17), *prev = sp.mat(19), *prev2 = sp.mat(20),
          *Gb = sp.mat(21), *Mq = sp.mat(22), *Qt = sp.mat(23), *Rt = sp.mat(24),
          *G1 = sp.mat(25), *Rc1 = sp.mat(26), *Rci1 = sp.mat(27), *Rc2 = sp.mat(28),
          *Rci2 = sp.mat(29), *Gram = sp.mat(30);
@@ -850,8 +847,7 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
          c.s);
       nn(cm(W[cur], N, p, N), none<double>(N), Ys + ld, ld, 1.0, cm(W[1 - cur], N, p - 1, N), 0.0,
          c.s);
-      small_gemm(false, false, p, p - 1, p, 1.0, H, ld, Ys + ld, ld, 0.0, Hs, ld, c.s);
-      small_gemm(true, false, p - 1, p - 1, p, 1.0, Ys + ld, ld, Hs, ld, 0.0, H, ld, c.s);
+      restart_project(H, ld, p, Ys + ld, ld, p - 1, nullptr, ld, 0, nullptr, ld, c.s);
       cur = 1 - cur;
       p -= 1;
       shift = P.shifts[nl];
@@ -902,9 +898,7 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
       c.sync();
       nn(cm(V[cur], N, p, N), none<double>(N), Yr, ld, 1.0, cm(V[1 - cur], N, hc, N), 0.0, c.s);
       nn(cm(W[cur], N, p, N), none<double>(N), Yr, ld, 1.0, cm(W[1 - cur], N, hc, N), 0.0, c.s);
-      small_gemm(false, false, p, hc, p, 1.0, H, ld, Yr, ld, 0.0, Hs, ld, c.s);
-      small_gemm(true, false, hc, hc, p, 1.0, Yr, ld, Hs, ld, 0.0, H, ld, c.s);
-      small_gemm(true, false, hc, ns, p, 1.0, Yr, ld, Ysl, ld, 0.0, prev2, ld, c.s);
+      restart_project(H, ld, p, Yr, ld, hc, Ysl, ld, ns, prev2, ld, c.s);
       std::swap(prev, prev2);
       nprev = ns;
       // same shift: W - s V = Q (R Yr); R Yr = Qt Rt gives the new factors
