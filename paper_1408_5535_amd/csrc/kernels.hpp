@@ -87,12 +87,21 @@ struct TnParts {
 template <typename T>
 void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int ldg,
         const Scratch &sc, hipStream_t s, TnParts *keep = nullptr);
+// The border of H from the partials of G = V^T W_new ((p + nb) x nb, kept by
+// tn): H(0:p+nb, p:p+nb) = G, H(p:p+nb, 0:p) = G(0:p)^T, the new diagonal
+// block symmetrised; with Z given, rows p..p+nb-1 of Z (nz columns) are
+// zeroed in the same launch (reduction and border copy in one kernel).
+void reduce_border(const TnParts &pt, double *H, int ldh, double *Z, int ldz, int nz,
+                   hipStream_t s);
 // Y = alpha * [X1 | X2] S + beta * Z, S float64 (nx x ny, ld lds); Z is Y
 // itself unless given.  If Y2 is given the result is written there too.
+// With gram (and gsc), the launch also leaves the block partials of the Gram
+// matrix Y^T Y (float64, ny of 1, 2 or 4) in gsc->part and describes them in
+// *gram, as tn does with keep.
 template <typename T>
 void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double alpha,
         const Tall<T> &Y, double beta, hipStream_t s, const Tall<T> *Z = nullptr,
-        const Tall<T> *Y2 = nullptr);
+        const Tall<T> *Y2 = nullptr, const Scratch *gsc = nullptr, TnParts *gram = nullptr);
 // Ritz block: X = V S, R = W S - X diag(theta) (row-major outputs, row stride ldx),
 // rn2[j] = ||R_:,j||^2; if ntop > 0 also xt2[j] = ||X_{0:ntop, j}||^2.
 template <typename T>
@@ -168,10 +177,6 @@ void restart_project(double *H, int ldh, int p, const double *Y, int ldy, int hc
 // Thin QR by two-pass modified Gram-Schmidt: M (rows x cols) = Q R.
 void small_qr(const double *M, int ldm, int rows, int cols, double *Q, int ldq, double *R,
               int ldr, hipStream_t s);
-// H(0:p+nb, p:p+nb) = G, H(p:p+nb, 0:p) = G(0:p)^T, symmetrised diagonal block;
-// with Z given, rows p..p+nb-1 of Z (nz columns) are zeroed in the same launch.
-void h_border(double *H, int ldh, int p, int nb, const double *G, int ldg, hipStream_t s,
-              double *Z = nullptr, int ldz = 0, int nz = 0);
 // Copy columns idx[0..nc) of A (rows x *) into B; idx on device.
 void gather_cols(const double *A, int lda, int rows, const int *idx, int nc, double *B, int ldb,
                  hipStream_t s);

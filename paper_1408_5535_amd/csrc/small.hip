@@ -709,19 +709,19 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double *G, int ldg, int 
     const int grp = t / tpe, sub = t % tpe, ngrp = 256 / tpe;
     for (int e0 = 0; e0 < E; e0 += ngrp) {
       const int e = e0 + grp;
-      // eight partials per lane in flight at a time (the padding past np
+      // sixteen partials per lane in flight at a time (the padding past np
       // rereads the last partial with weight 0)
       double sv = 0.0;
       if (e < E) {
-        for (int b0 = sub; b0 < np; b0 += 8 * tpe) {
-          double pv[8];
+        for (int b0 = sub; b0 < np; b0 += 16 * tpe) {
+          double pv[16];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
+          for (int u = 0; u < 16; ++u) {
             const int b = b0 + u * tpe;
             pv[u] = part[(int64_t)(b < np ? b : np - 1) * E + e];
           }
 #pragma unroll
-          for (int u = 0; u < 8; ++u) sv += b0 + u * tpe < np ? pv[u] : 0.0;
+          for (int u = 0; u < 16; ++u) sv += b0 + u * tpe < np ? pv[u] : 0.0;
         }
       }
       for (int o = tpe / 2; o > 0; o >>= 1) sv += __shfl_xor(sv, o, tpe);
@@ -735,16 +735,16 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double *G, int ldg, int 
     // squared column norms around two Gram-Schmidt passes from the final
     // Gram matrix and the two coefficient blocks
     double h1 = 0.0, h2 = 0.0;
-    for (int i0 = 0; i0 < dg.nh; i0 += 8) {
-      double c1[8], c2[8];
+    for (int i0 = 0; i0 < dg.nh; i0 += 16) {
+      double c1[16], c2[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const int64_t i = i0 + u < dg.nh ? i0 + u : dg.nh - 1;
         c1[u] = dg.H1[i + (int64_t)t * dg.ldh];
         c2[u] = dg.H2[i + (int64_t)t * dg.ldh];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const double m = i0 + u < dg.nh ? 1.0 : 0.0;
         h1 = fma(m * c1[u], c1[u], h1);
         h2 = fma(m * c2[u], c2[u], h2);
@@ -1060,39 +1060,6 @@ void small_qr(const double *M, int ldm, int rows, int cols, double *Q, int ldq, 
 }
 
 // ------------------------------------------------------------ misc
-// Border of H from G = V^T W_new ((p + nb) x nb): columns and rows p..p+nb-1,
-// the new diagonal block symmetrised.  With Z given, also zeroes rows
-// p..p+nb-1 of Z (nz columns, leading dimension ldz) in the same launch.
-__global__ void k_h_border(double *H, int ldh, int p, int nb, const double *G, int ldg,
-                           double *Z, int ldz, int nz) {
-  const int tot = (p + nb) * nb, totz = Z ? nb * nz : 0;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot + totz;
-       idx += gridDim.x * blockDim.x) {
-    if (idx >= tot) {
-      const int e = idx - tot;
-      Z[(p + e % nb) + (int64_t)(e / nb) * ldz] = 0.0;
-      continue;
-    }
-    int i = idx % (p + nb), c = idx / (p + nb);
-    double gv = G[i + (int64_t)c * ldg];
-    if (i < p) {
-      H[i + (int64_t)(p + c) * ldh] = gv;
-      H[(p + c) + (int64_t)i * ldh] = gv;
-    } else {
-      int r = i - p;
-      double sym = 0.5 * (gv + G[(p + c) + (int64_t)r * ldg]);
-      H[i + (int64_t)(p + c) * ldh] = sym;
-    }
-  }
-}
-
-void h_border(double *H, int ldh, int p, int nb, const double *G, int ldg, hipStream_t s,
-              double *Z, int ldz, int nz) {
-  const int64_t tot = (int64_t)(p + nb) * nb + (Z ? (int64_t)nb * nz : 0);
-  k_h_border<<<cdiv(tot, 256), 256, 0, s>>>(H, ldh, p, nb, G, ldg, Z, ldz, nz);
-  PHS_CHECK_LAUNCH();
-}
-
 __global__ void k_gather_cols(const double *A, int lda, int rows, const int *idx, int nc,
                               double *B, int ldb) {
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < rows * nc;

@@ -245,10 +245,12 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     spmm(At, bw, bf.Yb, W[cur] + (int64_t)p * n, false, c.s, n, nb);
     c.st->mv_stage1 += nb;
     if (!v_written) copy(rmv(Tb, n, nb, bw), cm(V[cur] + (int64_t)p * n, n, nb, n), c.s);
+    // border of H; the previous block's coefficients have no component on
+    // the new columns
+    TnParts gp;
     tn(cm(V[cur], n, p + nb, n), none<T>(n), cm(W[cur] + (int64_t)p * n, n, nb, n), Gb, ld,
-       c.sc, c.s);
-    // the previous block's coefficients have no component on the new columns
-    h_border(H, ld, p, nb, Gb, ld, c.s, nprev ? prev : nullptr, ld, nprev);
+       c.sc, c.s, &gp);
+    reduce_border(gp, H, ld, nprev ? prev : nullptr, ld, nprev, c.s);
     p += nb;
   };
   // checked expansion (host decisions on dependence and breakdown)
@@ -268,10 +270,15 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     // little (unpreconditioned corrections are nearly orthogonal to V
     // already) still left enough of V in T to stall the largest-mode
     // iteration at the 1e-12 level
+    // widths 1, 2 and 4: the second update and the first CholQR product
+    // also leave the Gram partials of their output (no separate X^T X pass;
+    // at width 8 the 64 float64 accumulators would not fit the registers)
+    const bool fused = nb == 1 || nb == 2 || nb == 4;
+    TnParts gp;
     tn(B1, B2, T0, G, ld, c.sc, c.s);
     nn(B1, B2, G, ld, -1.0, T1, 1.0, c.s, &T0);
     tn(B1, B2, T1, G2, ld, c.sc, c.s);
-    nn(B1, B2, G2, ld, -1.0, T1, 1.0, c.s);
+    nn<T>(B1, B2, G2, ld, -1.0, T1, 1.0, c.s, nullptr, nullptr, &c.sc, fused ? &gp : nullptr);
     // CholQR2; the first Cholesky also leaves the squared norms of the
     // block before, between and after the two passes in the status block
     CgsDiag dg;
@@ -282,11 +289,11 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     dg.n0 = sn0;
     dg.n1 = sn1;
     dg.n2 = sn2v;
-    TnParts gp;
-    tn(T1, none<T>(n), T1, Gram, ld, c.sc, c.s, &gp);
+    if (!fused) tn(T1, none<T>(n), T1, Gram, ld, c.sc, c.s, &gp);
     chol_inv(Gram, ld, nb, 0.0, R1, Ri1, ld, sflag, c.s, &dg, &gp);
-    nn(T1, none<T>(n), Ri1, ld, 1.0, T2, 0.0, c.s);
-    tn(T2, none<T>(n), T2, Gram, ld, c.sc, c.s, &gp);
+    nn<T>(T1, none<T>(n), Ri1, ld, 1.0, T2, 0.0, c.s, nullptr, nullptr, &c.sc,
+          fused ? &gp : nullptr);
+    if (!fused) tn(T2, none<T>(n), T2, Gram, ld, c.sc, c.s, &gp);
     chol_inv(Gram, ld, nb, 0.0, R1, Ri1, ld, sflag + 1, c.s, nullptr, &gp);
     const Tall<T> Vn = cm(V[cur] + (int64_t)p * n, n, nb, n);
     nn<T>(T2, none<T>(n), Ri1, ld, 1.0, T1, 0.0, c.s, nullptr, &Vn);
@@ -745,10 +752,10 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
     applyB(Tb, nb);
     copy(rmv(Tb, N, nb, bw), cm(V[cur] + (int64_t)p * N, N, nb, N), c.s);
     copy(rmv(bf.WTb, N, nb, bw), cm(W[cur] + (int64_t)p * N, N, nb, N), c.s);
-    tn(cm(V[cur], N, p + nb, N), none<double>(N), rmv(bf.WTb, N, nb, bw), Gb, ld, c.sc, c.s);
-    h_border(H, ld, p, nb, Gb, ld, c.s);
+    TnParts gp;
+    tn(cm(V[cur], N, p + nb, N), none<double>(N), rmv(bf.WTb, N, nb, bw), Gb, ld, c.sc, c.s, &gp);
+    reduce_border(gp, H, ld, nprev ? prev : nullptr, ld, nprev, c.s);
     if (!qr_full) qr_update(nb);
-    if (nprev) zero_rows(prev, ld, p, p + nb, nprev, c.s);
     p += nb;
   };
 

@@ -141,11 +141,10 @@ __global__ __launch_bounds__(64 * kTnMaxWaves) void k_tn(TV<T> x1, TV<T> x2, TV<
   }
 }
 
-// One wavefront per entry of G: lane l sums partials l, l+64, ... and the
-// lane sums are combined in the fixed order of wave_total.
-__global__ __launch_bounds__(64) void k_reduce_parts(const double *part, int np, int nx, int ny,
-                                                     double *G, int ldg) {
-  const int E = nx * ny, e = blockIdx.x;
+// Entry e of G from the block partials, one wavefront: lane l sums partials
+// l, l+64, ... and the lane sums are combined in the fixed order of
+// wave_total.
+__device__ inline double sum_parts(const double *part, int np, int E, int e) {
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int b = threadIdx.x;
   for (; b + 192 < np; b += 256) {
@@ -155,8 +154,49 @@ __global__ __launch_bounds__(64) void k_reduce_parts(const double *part, int np,
     s3 += part[(int64_t)(b + 192) * E + e];
   }
   for (; b < np; b += 64) s0 += part[(int64_t)b * E + e];
-  const double s = wave_total((s0 + s1) + (s2 + s3));
+  return wave_total((s0 + s1) + (s2 + s3));
+}
+
+__global__ __launch_bounds__(64) void k_reduce_parts(const double *part, int np, int nx, int ny,
+                                                     double *G, int ldg) {
+  const int E = nx * ny, e = blockIdx.x;
+  const double s = sum_parts(part, np, E, e);
   if (threadIdx.x == 0) G[e / ny + (int64_t)(e % ny) * ldg] = s;
+}
+
+// G = V^T W_new ((p + nb) x nb, from the partials) written as the border of
+// H: H(i, p+c) = H(p+c, i) = G(i, c) for i < p, and the new diagonal block
+// symmetrised, H(p+r, p+c) = (G(p+r, c) + G(p+c, r)) / 2.  The extra last
+// block zeroes rows p..p+nb-1 of Z (nz columns), if given.
+__global__ __launch_bounds__(64) void k_reduce_border(const double *part, int np, int nx, int nb,
+                                                      double *H, int ldh, double *Z, int ldz,
+                                                      int nz) {
+  const int E = nx * nb, e = blockIdx.x, p = nx - nb;
+  if (e == E) {
+    for (int q = threadIdx.x; q < nb * nz; q += 64) Z[(p + q % nb) + (int64_t)(q / nb) * ldz] = 0.0;
+    return;
+  }
+  const int i = e / nb, c = e % nb;
+  const double g = sum_parts(part, np, E, e);
+  if (i < p) {
+    if (threadIdx.x == 0) {
+      H[i + (int64_t)(p + c) * ldh] = g;
+      H[(p + c) + (int64_t)i * ldh] = g;
+    }
+  } else {
+    const int r = i - p;
+    const double gm = sum_parts(part, np, E, (p + c) * nb + r);
+    if (threadIdx.x == 0) H[i + (int64_t)(p + c) * ldh] = 0.5 * (g + gm);
+  }
+}
+
+void reduce_border(const TnParts &pt, double *H, int ldh, double *Z, int ldz, int nz,
+                   hipStream_t s) {
+  PHS_REQUIRE(pt.nx >= pt.ny && pt.ny >= 1, kEinval, "reduce_border: partials do not match");
+  const int E = pt.nx * pt.ny;
+  k_reduce_border<<<E + (Z && nz > 0 ? 1 : 0), 64, 0, s>>>(pt.part, pt.np, pt.nx, pt.ny, H, ldh,
+                                                         Z, ldz, nz);
+  PHS_CHECK_LAUNCH();
 }
 
 template <typename T>
@@ -201,7 +241,6 @@ void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int l
 __device__ inline double wave_sum(double v) { return wave_total(v); }
 
 // ------------------------------------------------------------------ X S
-constexpr int kNnTile = 16;  // output columns per thread
 
 // Y = alpha X S + beta Z (Z defaults to Y itself), optionally also written
 // to a second output Y2 in another layout.
@@ -215,76 +254,141 @@ struct NnOut {
   int64_t y2rs, y2cs;
 };
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_nn(TV<T> x1, TV<T> x2, const double *S, int lds,
-                                            int ny, double alpha, double beta, NnOut<T> o) {
+// NT output columns per thread (4, 8 or 16: the narrowest tile that holds
+// ny, or 16 with several column tiles; a 32-column tile for the restart
+// products measured no faster than two 16-column tiles).  With NG > 0 (then ny == NG and one
+// column tile) the kernel also forms the Gram matrix Y^T Y of its output:
+// each thread accumulates its rows in float64, and every block writes its
+// partial (entry (i, j) at i * NG + j) to gpart for the consumer to reduce.
+template <typename T, int NG, int NT>
+__global__ __launch_bounds__(NG > 0 ? 1024 : 256) void k_nn(TV<T> x1, TV<T> x2, const double *S,
+                                                             int lds,
+                                            int ny, double alpha, double beta, NnOut<T> o,
+                                            double *gpart) {
   extern __shared__ __align__(16) unsigned char smem[];
   T *ss = reinterpret_cast<T *>(smem);
   const int nx = x1.cols + x2.cols;
-  const int c0 = blockIdx.y * kNnTile;
-  const int nc = min(kNnTile, ny - c0);
+  const int c0 = blockIdx.y * NT;
+  const int nc = min(NT, ny - c0);
   // S tile into LDS, four loads in flight per thread before their stores
-  for (int idx0 = threadIdx.x; idx0 < nx * kNnTile; idx0 += 4 * blockDim.x) {
+  for (int idx0 = threadIdx.x; idx0 < nx * NT; idx0 += 4 * blockDim.x) {
     T v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int idx = idx0 + u * blockDim.x, j = idx / kNnTile, c = idx % kNnTile;
-      v[u] = (idx < nx * kNnTile && c < nc) ? (T)S[j + (int64_t)(c0 + c) * lds] : T(0);
+      const int idx = idx0 + u * blockDim.x, j = idx / NT, c = idx % NT;
+      v[u] = (idx < nx * NT && c < nc) ? (T)S[j + (int64_t)(c0 + c) * lds] : T(0);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (idx0 + u * blockDim.x < nx * kNnTile) ss[idx0 + u * blockDim.x] = v[u];
+      if (idx0 + u * blockDim.x < nx * NT) ss[idx0 + u * blockDim.x] = v[u];
   }
   __syncthreads();
   const int64_t N = x1.cols ? x1.rows : x2.rows;
+  double g[NG > 0 ? NG : 1][NG > 0 ? NG : 1];
+  if constexpr (NG > 0) {
+#pragma unroll
+    for (int a = 0; a < NG; ++a)
+#pragma unroll
+      for (int c = 0; c < NG; ++c) g[a][c] = 0.0;
+  }
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N;
        r += (int64_t)gridDim.x * blockDim.x) {
-    T acc[kNnTile];
+    T acc[NT];
 #pragma unroll
-    for (int c = 0; c < kNnTile; ++c) acc[c] = T(0);
+    for (int c = 0; c < NT; ++c) acc[c] = T(0);
     for (int j = 0; j < x1.cols; ++j) {
       T xv = x1.p[r * x1.rs + (int64_t)j * x1.cs];
 #pragma unroll
-      for (int c = 0; c < kNnTile; ++c) acc[c] = fma(xv, ss[j * kNnTile + c], acc[c]);
+      for (int c = 0; c < NT; ++c) acc[c] = fma(xv, ss[j * NT + c], acc[c]);
     }
     for (int j = 0; j < x2.cols; ++j) {
       T xv = x2.p[r * x2.rs + (int64_t)j * x2.cs];
 #pragma unroll
-      for (int c = 0; c < kNnTile; ++c)
-        acc[c] = fma(xv, ss[(x1.cols + j) * kNnTile + c], acc[c]);
+      for (int c = 0; c < NT; ++c)
+        acc[c] = fma(xv, ss[(x1.cols + j) * NT + c], acc[c]);
     }
 #pragma unroll
-    for (int c = 0; c < kNnTile; ++c) {
+    for (int c = 0; c < NT; ++c) {
       if (c < nc) {
         const int64_t col = c0 + c;
         T v = (T)alpha * acc[c];
         if (beta != 0.0) v += (T)beta * o.z[r * o.zrs + col * o.zcs];
         o.y[r * o.yrs + col * o.ycs] = v;
         if (o.y2) o.y2[r * o.y2rs + col * o.y2cs] = v;
+        acc[c] = v;
       }
+    }
+    if constexpr (NG > 0) {
+#pragma unroll
+      for (int a = 0; a < NG; ++a)
+#pragma unroll
+        for (int c = 0; c < NG; ++c) g[a][c] = fma((double)acc[a], (double)acc[c], g[a][c]);
+    }
+  }
+  if constexpr (NG > 0) {
+    // block partial: wave sums, then the waves in a fixed order
+    __shared__ double red[16][NG * NG];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int a = 0; a < NG; ++a)
+#pragma unroll
+      for (int c = 0; c < NG; ++c) {
+        const double v = wave_total(g[a][c]);
+        if (lane == 0) red[w][a * NG + c] = v;
+      }
+    __syncthreads();
+    if (threadIdx.x < NG * NG) {
+      const int e = threadIdx.x;
+      double v = red[0][e];
+      for (int q = 1; q < nw; ++q) v += red[q][e];
+      gpart[(int64_t)blockIdx.x * NG * NG + e] = v;
     }
   }
 }
 
 template <typename T>
 void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double alpha,
-        const Tall<T> &Y, double beta, hipStream_t s, const Tall<T> *Z, const Tall<T> *Y2) {
+        const Tall<T> &Y, double beta, hipStream_t s, const Tall<T> *Z, const Tall<T> *Y2,
+        const Scratch *gsc, TnParts *gram) {
   const int nx = X1.cols + X2.cols, ny = Y.cols;
   if (ny == 0 || Y.rows == 0) return;
   PHS_REQUIRE(nx <= 160, kEinval, "nn: operand too wide");
   PHS_REQUIRE(!Z || (Z->rows == Y.rows && Z->cols == Y.cols), kEinval, "nn: Z shape");
   PHS_REQUIRE(!Y2 || (Y2->rows == Y.rows && Y2->cols == Y.cols), kEinval, "nn: Y2 shape");
-  if (nx == 0 && beta == 1.0 && !Z && !Y2) return;
-  int64_t blocks = cdiv(Y.rows, 256);
+  PHS_REQUIRE(!gram || (gsc && (ny == 1 || ny == 2 || ny == 4)), kEinval,
+              "nn: the Gram output needs 1, 2 or 4 columns");
+  if (nx == 0 && beta == 1.0 && !Z && !Y2 && !gram) return;
+  // with the Gram partials: blocks of 1024 threads, at most 256 of them (each
+  // thread then takes several rows), so that the consumer adds few partials
+  // while as many waves are in flight as with 1024 blocks of 256
+  const int threads = gram ? 1024 : 256;
+  int64_t blocks = cdiv(Y.rows, threads);
   if (blocks > 4096) blocks = 4096;
-  dim3 grid((unsigned)blocks, cdiv(ny, kNnTile));
-  size_t shm = (size_t)(nx > 0 ? nx : 1) * kNnTile * sizeof(T);
+  if (gram && blocks > 256) blocks = 256;
+  const int nt = ny <= 4 ? 4 : ny <= 8 ? 8 : 16;
+  dim3 grid((unsigned)blocks, cdiv(ny, nt));
+  size_t shm = (size_t)(nx > 0 ? nx : 1) * nt * sizeof(T);
   Tall<T> a = X1, b = X2;
   if (a.cols == 0 && b.cols == 0) a.rows = Y.rows;
   NnOut<T> o{Y.p, Y.rs, Y.cs, Z ? Z->p : Y.p, Z ? Z->rs : Y.rs, Z ? Z->cs : Y.cs,
              Y2 ? Y2->p : nullptr, Y2 ? Y2->rs : 0, Y2 ? Y2->cs : 0};
   prof_begin(kProfNn, s);
-  k_nn<T><<<grid, 256, shm, s>>>(tv(a), tv(b), S, lds, ny, alpha, beta, o);
+  double *gp = gram ? gsc->part : nullptr;
+#define PHS_NN(NG, NT) \
+  k_nn<T, NG, NT><<<grid, threads, shm, s>>>(tv(a), tv(b), S, lds, ny, alpha, beta, o, gp)
+  if (!gram) {
+    if (nt == 4) PHS_NN(0, 4);
+    else if (nt == 8) PHS_NN(0, 8);
+    else PHS_NN(0, 16);
+  } else {
+    switch (ny) {
+      case 1: PHS_NN(1, 4); break;
+      case 2: PHS_NN(2, 4); break;
+      default: PHS_NN(4, 4); break;
+    }
+  }
+#undef PHS_NN
+  if (gram) *gram = TnParts{gp, (int)blocks, ny, ny};
   PHS_CHECK_LAUNCH();
   prof_end(kProfNn, s, (double)Y.rows * (nx + ny * (beta != 0.0 ? 2 : 1)) * sizeof(T));
 }
@@ -755,7 +859,7 @@ void row_scale(const T *X, const double *w, int64_t n, int b, bool inv, T *Y, hi
                       const Scratch &, hipStream_t, TnParts *);                              \
   template void nn<T>(const Tall<T> &, const Tall<T> &, const double *, int, double,         \
                       const Tall<T> &, double, hipStream_t, const Tall<T> *,                 \
-                      const Tall<T> *);                                                      \
+                      const Tall<T> *, const Scratch *, TnParts *);                          \
   template void ritz<T>(const Tall<T> &, const Tall<T> &, const double *, int, const double *, \
                         T *, T *, int, int, double *, double *, int64_t, const Scratch &,     \
                         hipStream_t);                                                         \
