@@ -37,7 +37,7 @@ static TV<T> tv(const Tall<T> &t) {
 // rows per lane in flight, products accumulated in T registers.  Each wave
 // reduces its tile over its lanes; one partial per block and entry goes to
 // `part`, which a second kernel (or the consumer) adds in a fixed order.
-constexpr int kTnCX = 8, kTnCY = 4, kTnMaxWaves = 8;
+constexpr int kTnCX = 4, kTnCY = 4, kTnMaxWaves = 4;
 template <typename T>
 struct TnRows {  // rows per lane in flight: float 4, double 2 (register budget)
   static constexpr int U = sizeof(T) == 4 ? 4 : 2;
