@@ -264,11 +264,23 @@ template <typename T, int NG, int NT>
 __global__ __launch_bounds__(NG > 0 ? 1024 : 256) void k_nn(TV<T> x1, TV<T> x2, const double *S,
                                                              int lds,
                                             int ny, double alpha, double beta, NnOut<T> o,
-                                            double *gpart) {
+                                            double *gpart, int ntl) {
   extern __shared__ __align__(16) unsigned char smem[];
   T *ss = reinterpret_cast<T *>(smem);
   const int nx = x1.cols + x2.cols;
-  const int c0 = blockIdx.y * NT;
+  // row block and column tile: with several tiles the 1-D grid gives the
+  // tiles of one row block to consecutive blocks of one XCD (blocks go to
+  // the eight XCDs round robin), so that the rows of X they all read are
+  // fetched into that XCD's L2 once; the row-block count is a multiple of 8
+  int64_t rb = blockIdx.x, nrb = gridDim.x;
+  int tb = 0;
+  if (ntl > 1) {
+    const int64_t x = blockIdx.x % 8, k = blockIdx.x / 8;
+    tb = (int)(k % ntl);
+    rb = (k / ntl) * 8 + x;
+    nrb = gridDim.x / ntl;
+  }
+  const int c0 = tb * NT;
   const int nc = min(NT, ny - c0);
   // S tile into LDS, four loads in flight per thread before their stores
   for (int idx0 = threadIdx.x; idx0 < nx * NT; idx0 += 4 * blockDim.x) {
@@ -291,8 +303,7 @@ __global__ __launch_bounds__(NG > 0 ? 1024 : 256) void k_nn(TV<T> x1, TV<T> x2, 
 #pragma unroll
       for (int c = 0; c < NG; ++c) g[a][c] = 0.0;
   }
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N;
-       r += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t r = rb * blockDim.x + threadIdx.x; r < N; r += nrb * blockDim.x) {
     T acc[NT];
 #pragma unroll
     for (int c = 0; c < NT; ++c) acc[c] = T(0);
@@ -366,7 +377,9 @@ void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double a
   if (blocks > 4096) blocks = 4096;
   if (gram && blocks > 256) blocks = 256;
   const int nt = ny <= 4 ? 4 : ny <= 8 ? 8 : 16;
-  dim3 grid((unsigned)blocks, cdiv(ny, nt));
+  const int ntl = (int)cdiv(ny, nt);
+  if (ntl > 1) blocks = cdiv(blocks, 8) * 8;
+  const unsigned grid = (unsigned)(blocks * ntl);
   size_t shm = (size_t)(nx > 0 ? nx : 1) * nt * sizeof(T);
   Tall<T> a = X1, b = X2;
   if (a.cols == 0 && b.cols == 0) a.rows = Y.rows;
@@ -375,7 +388,7 @@ void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double a
   prof_begin(kProfNn, s);
   double *gp = gram ? gsc->part : nullptr;
 #define PHS_NN(NG, NT) \
-  k_nn<T, NG, NT><<<grid, threads, shm, s>>>(tv(a), tv(b), S, lds, ny, alpha, beta, o, gp)
+  k_nn<T, NG, NT><<<grid, threads, shm, s>>>(tv(a), tv(b), S, lds, ny, alpha, beta, o, gp, ntl)
   if (!gram) {
     if (nt == 4) PHS_NN(0, 4);
     else if (nt == 8) PHS_NN(0, 8);
