@@ -916,8 +916,11 @@ void restart_project(double *H, int ldh, int p, const double *Y, int ldy, int hc
 // against columns [0, c), twice.  The c dot products of a pass are computed
 // in parallel (lane j forms q_j^T x from LDS, rows eight at a time), then
 // every lane updates its row; coefficients accumulate into rc if given.
+// With reject > 0, a column whose norm after the first pass is at most
+// reject * n0 is returned after that pass (n2 = that norm): the second pass
+// could only shrink it further, and the caller discards such a column.
 __device__ inline void wave_cgs2(double *q, int rows, int c, double *xs, double *dots, double *rc,
-                                 double &n0, double &n2) {
+                                 double &n0, double &n2, double reject = 0.0) {
   const int r = threadIdx.x;
   double x = (r < rows) ? q[c * kLd + r] : 0.0;
   n0 = sqrt(wave_total(x * x));
@@ -958,6 +961,15 @@ __device__ inline void wave_cgs2(double *q, int rows, int c, double *xs, double 
       for (int u = 0; u < 8; ++u) acc = fma(-dv[u], qv[u], acc);
     }
     x = (r < rows) ? acc : 0.0;
+    if (pass == 0 && reject > 0.0) {
+      const double n1 = sqrt(wave_total(x * x));
+      if (!(n1 > reject * n0)) {
+        q[c * kLd + r] = x;
+        n2 = n1;
+        __syncthreads();
+        return;
+      }
+    }
   }
   q[c * kLd + r] = x;
   n2 = sqrt(wave_total(x * x));
@@ -1007,7 +1019,7 @@ __global__ __launch_bounds__(64) void k_restart_basis(const double *K, int ldk, 
       q[cur * kLd + r] = x;
       __syncthreads();
       double n0, n2;
-      wave_cgs2(q, rows, cur, xs, dots, nullptr, n0, n2);
+      wave_cgs2(q, rows, cur, xs, dots, nullptr, n0, n2, 1e-8);
       if (n0 > 0.0 && n2 > 1e-8 * n0) {
         q[cur * kLd + r] /= n2;
         ++cur;
