@@ -208,10 +208,10 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
   const bool w0 = w == 0;
   const int n = p;
   const double eps = 2.220446049250313e-16;
-  // symmetric part of H, lane t writing row t
-  if (w0 && t < n) {
-#pragma unroll 8
-    for (int k = 0; k < n; ++k)
+  // symmetric part of H: lane t writes row t, wave w the columns k = w mod 4
+  if (t < n) {
+#pragma unroll 4
+    for (int k = w; k < n; k += 4)
       a[t * kLd + k] = 0.5 * (H[t + (int64_t)k * ldh] + H[k + (int64_t)t * ldh]);
   }
   if (w0) {
@@ -1001,7 +1001,10 @@ __global__ __launch_bounds__(64) void k_restart_basis(const double *K, int ldk, 
   __shared__ double xs[kSmallMax + 8], dots[kSmallMax];
   const int r = threadIdx.x;
   if (r < 8) xs[kSmallMax + r] = 0.0;
-  for (int e = r; e < kSmallMax * kLd + 8; e += 64) q[e] = 0.0;  // padding reads meet zeros
+  // every column the kernel reads has its 64 rows written first; the reads
+  // past them (row 64 of a column, and the tail of the array) meet zeros
+  q[r * kLd + kSmallMax] = 0.0;
+  if (r < 8) q[kSmallMax * kLd + r] = 0.0;
   __syncthreads();
   load_cols_lds(q, K, ldk, rows, kc, r);
   __syncthreads();
@@ -1046,7 +1049,10 @@ __global__ __launch_bounds__(64) void k_small_qr(const double *M, int ldm, int r
   __shared__ double rc[kSmallMax], xs[kSmallMax + 8], dots[kSmallMax];
   const int r = threadIdx.x;
   if (r < 8) xs[kSmallMax + r] = 0.0;
-  for (int e = r; e < kSmallMax * kLd + 8; e += 64) q[e] = 0.0;  // padding reads meet zeros
+  // the columns read are written first (64 rows each); row 64 of a column
+  // and the tail of the array meet zeros
+  q[r * kLd + kSmallMax] = 0.0;
+  if (r < 8) q[kSmallMax * kLd + r] = 0.0;
   __syncthreads();
   load_cols_lds(q, M, ldm, rows, cols, r);
   for (int e = r; e < cols * cols; e += 64) R[e % cols + (int64_t)(e / cols) * ldr] = 0.0;
