@@ -84,6 +84,23 @@ def test_grid_n128_both_ends_closed_form(which):
 
 
 @gpu
+@pytest.mark.parametrize("b", [3, 8])
+def test_grid_block_widths_without_fused_gram(b):
+    """Block widths whose CholQR Grams take the separate X^T X pass (3, 8)
+    and whose X S products use the 4- and 8-column tiles: N = 24 grid,
+    k = 8 smallest, sigma against the closed form, float64 residuals."""
+    need_gpu()
+    N = 24
+    A = wl.grid_gradient(N)
+    an = cf.grid_norm(N)
+    say("grid N=24 k=8 b", b)
+    sig, U, V, info = _solve(A, 8, b=b, anorm=an)
+    say({k: info[k] for k in ("status", "mv_total", "iters1", "rollbacks1")
+         if k in info})
+    _check(A, sig, U, V, info, cf.grid_sigmas(N)[:8], an)
+
+
+@gpu
 def test_grid_n512_benchmark_configuration():
     """The benchmark's solve at full size: N = 512 (m = 525312, n = 262144),
     k = 10 smallest, block 4, float64, the paper's start block; sigma
