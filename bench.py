@@ -28,9 +28,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time to k smallest triplets at ‖r‖≤1e-12‖A‖; SpMM HBM GB/s; matvecs/triplet"
 HBM_PEAK_GBS = 8000.0
-# SpMM launches are timed by event pairs on the solver stream; each record
-# idles the stream for a few microseconds, so one A X / A^T Y pair in
-# SPMM_SAMPLE is timed (the average over the sample stands for all launches)
+# SpMM launches are timed by events on the solver stream: one event pair
+# around an A X / A^T Y pair of launches (its interval counts as two
+# launches), for one pair in SPMM_SAMPLE, since each record idles the stream
+# for a few microseconds (the average over the sample stands for all
+# launches)
 SPMM_SAMPLE = 8
 
 
@@ -388,7 +390,8 @@ def main():
                      "traffic": traffic_from_profiles(f"grid{args.N}_b{b}"),
                      "kernel": "float64 SpMM (A X and A^T Y, row-major blocks)",
                      "launches": int(launches), "avg_launch_us": avg * 1e6,
-                     "timed_sample": f"one A X / A^T Y launch pair in {SPMM_SAMPLE}",
+                     "timed_sample": f"one A X / A^T Y launch pair in {SPMM_SAMPLE}, "
+                                     "one event pair around both launches",
                      "algorithmic_bytes_per_launch": per_launch},
     }
     if args.max_mv:

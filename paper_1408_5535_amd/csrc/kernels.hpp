@@ -27,6 +27,14 @@ int lanes_for_length(double avg);
 template <typename T>
 void spmm(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, hipStream_t s,
           int64_t ycm = 0, int ycols = 0);
+// Algorithmic HBM bytes of one Y = A X at block width b: values and column
+// indices once, row pointers once, X once, Y once (the count spmm records
+// for each launch it times).
+template <typename T>
+inline double spmm_bytes(const SpMat<T> &A, int b) {
+  return (double)A.nnz * (sizeof(T) + 4) + (double)(A.m + 1) * 8 +
+         (double)A.n * b * sizeof(T) + (double)A.m * b * sizeof(T);
+}
 size_t transpose_ws_bytes(int64_t m, int64_t n, int64_t nnz);
 void csr_transpose(int64_t m, int64_t n, int64_t nnz, const int64_t *rp, const int32_t *ci,
                    const double *va, int64_t *trp, int32_t *tci, double *tva, void *ws,

@@ -14,7 +14,7 @@ namespace {
 
 struct Rec {
   hipEvent_t a, b;
-  int kind;
+  int kind, count;
   double bytes;
 };
 
@@ -28,6 +28,7 @@ struct Prof {
   std::vector<Rec> live;
   hipEvent_t pending = nullptr;
   int pending_kind = -1;
+  int group_kind = -1, group_count = 0;  // an open group (prof_group_begin)
   int64_t n[kProfCount] = {};
   double sec[kProfCount] = {}, bytes[kProfCount] = {};
 } g;
@@ -50,7 +51,7 @@ void harvest() {
     PHS_HIP(hipEventSynchronize(r.b));
     float ms = 0.f;
     PHS_HIP(hipEventElapsedTime(&ms, r.a, r.b));
-    g.n[r.kind] += 1;
+    g.n[r.kind] += r.count;
     g.sec[r.kind] += ms * 1e-3;
     g.bytes[r.kind] += r.bytes;
     g.pool.push_back(r.a);
@@ -64,7 +65,7 @@ void harvest() {
 bool prof_on() { return g.on; }
 
 void prof_begin(int kind, hipStream_t s) {
-  if (!g.on || !((g.mask >> kind) & 1)) return;
+  if (!g.on || !((g.mask >> kind) & 1) || g.group_kind == kind) return;
   std::lock_guard<std::mutex> lk(g.mu);
   // sampling by pairs keeps A X and the A^T Y that follows it together
   const int64_t c = g.calls[kind]++;
@@ -78,12 +79,42 @@ void prof_begin(int kind, hipStream_t s) {
 }
 
 void prof_end(int kind, hipStream_t s, double bytes) {
-  if (!g.on || !((g.mask >> kind) & 1)) return;
+  if (!g.on || !((g.mask >> kind) & 1) || g.group_kind == kind) return;
   std::lock_guard<std::mutex> lk(g.mu);
   if (!g.pending || g.pending_kind != kind) return;
   hipEvent_t e = get_event();
   PHS_HIP(hipEventRecord(e, s));
-  g.live.push_back({g.pending, e, kind, bytes});
+  g.live.push_back({g.pending, e, kind, 1, bytes});
+  g.pending = nullptr;
+  if (g.live.size() >= 4096) harvest();
+}
+
+void prof_group_begin(int kind, hipStream_t s, int count) {
+  if (!g.on || !((g.mask >> kind) & 1)) return;
+  std::lock_guard<std::mutex> lk(g.mu);
+  g.group_kind = kind;
+  g.group_count = count;
+  const int64_t c = g.calls[kind];
+  g.calls[kind] += count;
+  if ((c / 2) % g.every != 0) {
+    g.pending = nullptr;
+    return;
+  }
+  g.pending = get_event();
+  g.pending_kind = kind;
+  PHS_HIP(hipEventRecord(g.pending, s));
+}
+
+void prof_group_end(int kind, hipStream_t s, double bytes) {
+  if (!g.on || !((g.mask >> kind) & 1)) return;
+  std::lock_guard<std::mutex> lk(g.mu);
+  const int count = g.group_count;
+  g.group_kind = -1;
+  g.group_count = 0;
+  if (!g.pending || g.pending_kind != kind) return;
+  hipEvent_t e = get_event();
+  PHS_HIP(hipEventRecord(e, s));
+  g.live.push_back({g.pending, e, kind, count, bytes});
   g.pending = nullptr;
   if (g.live.size() >= 4096) harvest();
 }
@@ -104,6 +135,8 @@ int phsvds_profile(int enable) {
       }
       phs::g.every = 1;
     }
+    phs::g.group_kind = -1;
+    phs::g.group_count = 0;
     phs::g.on = enable != 0;
     phs::g.mask = enable == 1 ? (1 << phs::kProfCount) - 1 : (enable >> 1);
     return PHSVDS_OK;

@@ -14,6 +14,8 @@
 #include <cstring>
 #include <numeric>
 
+#include "prof.hpp"
+
 namespace phs {
 
 constexpr size_t kPinBytes = 64 * 1024;
@@ -233,16 +235,23 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
   int pend_nb = 0, pend_p = 0;  // unchecked expansion: width, basis size before
   int64_t last_rebuild = -1000000;  // iteration of the last W = C V rebuild
 
+  // the two products of C X are timed as one group when profiling
+  const int pkind = fp32 ? kProfSpmm32 : kProfSpmm64;
+  const double cbytes = spmm_bytes(A, bw) + spmm_bytes(At, bw);
   auto applyC = [&](T *X, int nb) {
+    prof_group_begin(pkind, c.s, 2);
     spmm(A, bw, X, bf.Yb, false, c.s);
     spmm(At, bw, bf.Yb, bf.WTb, false, c.s);
+    prof_group_end(pkind, c.s, cbytes);
     c.st->mv_stage1 += nb;
   };
   // W_T = C T goes straight into the new columns of W; V's new columns are
   // copied from T unless the caller has written them already
   auto append = [&](int nb, bool v_written) {
+    prof_group_begin(pkind, c.s, 2);
     spmm(A, bw, Tb, bf.Yb, false, c.s);
     spmm(At, bw, bf.Yb, W[cur] + (int64_t)p * n, false, c.s, n, nb);
+    prof_group_end(pkind, c.s, cbytes);
     c.st->mv_stage1 += nb;
     if (!v_written) copy(rmv(Tb, n, nb, bw), cm(V[cur] + (int64_t)p * n, n, nb, n), c.s);
     // border of H; the previous block's coefficients have no component on
