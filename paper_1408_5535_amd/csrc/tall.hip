@@ -256,15 +256,16 @@ struct NnOut {
 
 // NT output columns per thread (4, 8 or 16: the narrowest tile that holds
 // ny, or 16 with several column tiles; a 32-column tile for the restart
-// products measured no faster than two 16-column tiles).  With NG > 0 (then ny == NG and one
-// column tile) the kernel also forms the Gram matrix Y^T Y of its output:
-// each thread accumulates its rows in float64, and every block writes its
-// partial (entry (i, j) at i * NG + j) to gpart for the consumer to reduce.
+// products measured no faster than two 16-column tiles).  With NG > 0 (then
+// ny == NG and one column tile) the kernel also forms the Gram matrix Y^T Y
+// of its output: each thread accumulates its rows in float64, and every
+// block writes its partial (entry (i, j) at i * NG + j) to gpart for the
+// consumer to reduce.
 template <typename T, int NG, int NT>
 __global__ __launch_bounds__(NG > 0 ? 1024 : 256) void k_nn(TV<T> x1, TV<T> x2, const double *S,
-                                                             int lds,
-                                            int ny, double alpha, double beta, NnOut<T> o,
-                                            double *gpart, int ntl) {
+                                                             int lds, int ny, double alpha,
+                                                             double beta, NnOut<T> o,
+                                                             double *gpart, int ntl) {
   extern __shared__ __align__(16) unsigned char smem[];
   T *ss = reinterpret_cast<T *>(smem);
   const int nx = x1.cols + x2.cols;
