@@ -223,7 +223,9 @@ int phsvds_harvest(const phsvds_csr *A, int k, int every, int max_pairs, double 
  * the first pair of consecutive operations of a kind in every `every` pairs
  * (each event record idles the stream for a few microseconds, so sampling
  * keeps the timed run close to an untimed one); phsvds_profile resets it to
- * 1, and every < 1 is PHSVDS_EINVAL.
+ * 1, and every < 1 is PHSVDS_EINVAL.  Inside the solver the two SpMM
+ * launches of one product with C = A^T A (A X, then A^T Y) are timed by a
+ * single event pair and counted as two operations.
  * phsvds_profile_read returns the number of timed operations, their summed
  * device time (s) and their summed algorithmic HBM bytes.  Not thread-safe
  * against concurrent solves. */
