@@ -147,6 +147,20 @@ __global__ __launch_bounds__(64 * kTnMaxWaves) void k_tn(TV<T> x1, TV<T> x2, TV<
 __device__ inline double sum_parts(const double *part, int np, int E, int e) {
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int b = threadIdx.x;
+  // two rounds of four at a time (eight loads in flight), same order
+  for (; b + 448 < np; b += 512) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + 64 * u) * E + e];
+    s0 += v[0];
+    s1 += v[1];
+    s2 += v[2];
+    s3 += v[3];
+    s0 += v[4];
+    s1 += v[5];
+    s2 += v[6];
+    s3 += v[7];
+  }
   for (; b + 192 < np; b += 256) {
     s0 += part[(int64_t)b * E + e];
     s1 += part[(int64_t)(b + 64) * E + e];
@@ -486,8 +500,19 @@ __global__ __launch_bounds__(256) void k_ritz(TV<T> V, TV<T> W, const double *S,
 __global__ __launch_bounds__(64) void k_reduce_vec(const double *part, int nblk, int E,
                                                    double *out0, double *out1, int split) {
   const int e = blockIdx.x;
+  // lane l adds partials l, l + 64, ... in order; eight loads in flight
   double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 64) s += part[(int64_t)b * E + e];
+  for (int b0 = threadIdx.x; b0 < nblk; b0 += 8 * 64) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int b = b0 + u * 64;
+      v[u] = part[(int64_t)(b < nblk ? b : b0) * E + e];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (b0 + u * 64 < nblk) s += v[u];
+  }
   s = wave_sum(s);
   if (threadIdx.x == 0) {
     if (e < split) {
