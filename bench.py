@@ -267,9 +267,9 @@ def cpu_baseline(A, k, b, anorm, mv_total, budget_s=20.0):
         t0 = time.perf_counter()
         ph.stage1_gdk(A, k, 1e-12, b, pmax, pmin, X0, anorm=anorm, stats=st, max_iters=iters)
         t = time.perf_counter() - t0
-        if t > budget_s / 3 or iters >= 4000:
+        if t > budget_s / 2 or iters >= 4000:
             break
-        iters = int(iters * max(2.0, min(8.0, (budget_s / 3) / max(t, 1e-3))))
+        iters = int(iters * max(2.0, min(8.0, (budget_s / 2) / max(t, 1e-3))))
     per_mv = t / max(st.mv_stage1, 1)
     return {"value": per_mv * mv_total, "unit": "s", "cores": cores, "kind": "oracle",
             "sample": f"oracle stage-1 GD+k, first {st.iters1} iterations ({st.mv_stage1} products "
