@@ -59,6 +59,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from . import jdqmr as _jd
 from . import rng as _rng
 
 EPS64 = 2.0 ** -52
@@ -85,6 +86,7 @@ class Stats:
     iters2: int = 0
     restarts1: int = 0
     restarts2: int = 0
+    inner2: int = 0
     stage2_pairs: int = 0
     fallback: bool = False
     anorm_est: float = 0.0
@@ -229,6 +231,7 @@ def stage1_gdk(A, k, tol, b, pmax, pmin, X0, which="smallest", precond=None, ano
     converged = False
     pc_hist = []
     last_rebuild = -(10**9)
+    best = (np.zeros(0), np.zeros((n, 0)))
     stats.fallback = False
     while True:
         it += 1
@@ -307,6 +310,10 @@ def stage1_gdk(A, k, tol, b, pmax, pmin, X0, which="smallest", precond=None, ano
                 H = _sym(V.T @ W)
             continue
         if stats.restarts1 > max_restarts or (max_iters and it > max_iters):
+            # out of budget: the pairs still missing are returned as the
+            # leading Ritz vectors of the final basis (best approximations)
+            nbest = min(need, p)
+            best = (np.asarray(theta[:nbest], dtype=np.float64), V @ S[:, :nbest])
             break
         T = R if precond is None else precond(R, theta[:nb], X)
         if p + nb > pmax:
@@ -334,7 +341,7 @@ def stage1_gdk(A, k, tol, b, pmax, pmin, X0, which="smallest", precond=None, ano
     order = np.argsort(thl) if which == "smallest" else np.argsort(thl)[::-1]
     thl = np.asarray(thl)[order]
     Xl = Xl[:, order]
-    return Xl, thl, V, sn2, {"converged": converged, "iters": it}
+    return Xl, thl, V, sn2, {"converged": converged, "iters": it, "best": best}
 
 
 # --------------------------------------------------------------------------
@@ -369,11 +376,37 @@ def transition_rr(A, Xl, Vrest, k, pmin, anorm, seed=13, stats: Stats | None = N
 # --------------------------------------------------------------------------
 # Stage 2: GD+k with refined projection on B (Algorithm 2)
 # --------------------------------------------------------------------------
+def _triplet_residual(x, bx, theta, n):
+    """sqrt(||A^T u - theta v||^2 + ||A v - theta u||^2) for the normalised
+    halves v = x_top / ||x_top||, u = x_bot / ||x_bot|| of x, from x and
+    B x = [A^T x_bot; A x_top] (the stopping test of Section 5).  For a
+    balanced unit x it equals sqrt(2) ||B x - theta x||; an unbalanced x
+    (one half nearly zero) can pass the B test while its triplet fails."""
+    nv = float(np.linalg.norm(x[:n]))
+    nu = float(np.linalg.norm(x[n:]))
+    if not (nv > 0.0 and nu > 0.0):
+        return math.inf
+    ru = bx[:n] / nu - theta * x[:n] / nv
+    rv = bx[n:] / nv - theta * x[n:] / nu
+    return math.sqrt(float(ru @ ru) + float(rv @ rv))
+
+
 def stage2_refined(A, shifts, v0, u0, tol, anorm, b, pmax, pmin, precondB=None,
-                   max_restarts=10000, seed=17, stats: Stats | None = None, max_iters=None):
+                   max_restarts=10000, seed=17, stats: Stats | None = None, max_iters=None,
+                   method="gdk", max_inner=50, trace=None):
     """Interior eigenpairs of B near the given shifts (Algorithm 2).
 
-    Returns (sigma, X) with X = [v; u] unit vectors of B, in target order."""
+    ``method`` 'gdk' takes the (preconditioned) residual block as the
+    correction (GD+k); 'jdqmr' solves the projected correction equation of
+    the target, P (B - s I) P t = -r with s its shift and P the projector
+    orthogonal to [locked vectors, x], by symmetric QMR with dynamic stopping
+    (oracle.jdqmr; ``precondB`` then preconditions the inner solver) and
+    expands by that one direction.  Inner products with B count as stage-2
+    products.  ``trace``, if a list, receives (iteration, basis size, theta,
+    ||r||, sigma_min(R), shift) per iteration.
+
+    Returns (sigma, X) with X = [v; u] unit vectors of B, in target order;
+    len(sigma) < len(shifts) when the budget ran out first."""
     stats = stats if stats is not None else Stats()
     m, n = A.shape
     N = m + n
@@ -428,9 +461,12 @@ def stage2_refined(A, shifts, v0, u0, tol, anorm, b, pmax, pmin, precondB=None,
         y = Ys[:, 0]
         theta = float(y @ H @ y)
         x = V @ y
-        r = W @ y - theta * x
+        wy = W @ y
+        r = wy - theta * x
         rn = float(np.linalg.norm(r))
-        if rn < thr:
+        if trace is not None:
+            trace.append((it, p, theta, rn, float(sv[order[0]]), shift))
+        if rn < thr and _triplet_residual(x, wy, theta, n) <= tol * anorm:
             Xl = np.column_stack([Xl, x])
             thl.append(theta)
             j += 1
@@ -449,7 +485,7 @@ def stage2_refined(A, shifts, v0, u0, tol, anorm, b, pmax, pmin, precondB=None,
         slots = [0]
         thetas = [theta]
         for c in range(1, p):
-            if len(slots) >= b or c > 2 * b:
+            if len(slots) >= b or c > 2 * b or method == "jdqmr":
                 break
             yc = Ys[:, c]
             thc = float(yc @ H @ yc)
@@ -462,7 +498,18 @@ def stage2_refined(A, shifts, v0, u0, tol, anorm, b, pmax, pmin, precondB=None,
         X = V @ Ysl
         Rr = W @ Ysl - X * np.asarray(thetas)[None, :]
         nb = len(slots)
-        T = Rr if precondB is None else precondB(Rr, np.asarray(thetas), X)
+        if method == "jdqmr":
+            def Bvec(w):
+                stats.mv_stage2 += 1
+                return np.concatenate([A.T @ w[n:], A @ w[:n]])
+
+            pc = None if precondB is None else (lambda g: precondB(g[:, None], None, None)[:, 0])
+            t, steps, _ = _jd.jd_correction(Bvec, x, r, theta, shift, np.column_stack([Xl, x]),
+                                           thr, pc, max_inner)
+            stats.inner2 += steps
+            T = t[:, None]
+        else:
+            T = Rr if precondB is None else precondB(Rr, np.asarray(thetas), X)
         if p + nb > pmax:
             Yr = Ys[:, :pmin]
             if prev is not None:
@@ -541,12 +588,17 @@ def _final(A, V, U, stats, AV=None):
 
 def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, anorm=None,
            stage2="auto", max_basis=None, min_restart=None, max_restarts=10000, floor=10.0,
-           seed=2, max_iters=None, gnn_params=None):
+           seed=2, max_iters=None, gnn_params=None, stage2_method="gdk", max_inner=50):
     """k smallest (or largest) singular triplets of A by PHSVDS.
 
-    Returns dict(sigma, U, V, res, stats, stage1_sigma).  ``precond`` is
-    'none', 'jacobi' (stage 1: Olsen-Jacobi on C; stage 2: its B-form) or
-    'gnn' (stage 1: the learned network of oracle.precond with gnn_params)."""
+    Returns dict(sigma, U, V, res, stats, stage1_sigma, converged, anorm).
+    ``precond`` is 'none', 'jacobi' (stage 1: Olsen-Jacobi on C; stage 2: its
+    B-form) or 'gnn' (stage 1: the learned network of oracle.precond with
+    gnn_params).  ``stage2_method`` is 'gdk' (GD+k with the refined
+    projection) or 'jdqmr' (the same outer iteration with the correction
+    equation solved by symmetric QMR, Section 3.2).  ``converged`` holds
+    only if every pair locked in its last stage and every final residual
+    sqrt(||r_u||^2 + ||r_v||^2) is at most tol ||A|| (Section 5)."""
     import workloads  # seeded inputs only
 
     m, n = A.shape
@@ -605,8 +657,10 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
         need2 = kk
     else:
         need2 = int(np.sum(tol * s1 < floor * EPS64 * sn))
+    locked2 = need2
+    Xbest = info["best"][1]
     if need2 == 0:
-        V = Xl.copy()
+        V = np.column_stack([Xl, Xbest])
         AV = A @ V
         stats.mv_final += V.shape[1]
         nv = np.linalg.norm(AV, axis=0)
@@ -617,12 +671,15 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
         stats.stage2_pairs = need2
         th2, X2 = stage2_refined(A, sig_rr[:need2], v_rr[:, :need2], u_rr[:, :need2], tol, an,
                                  b, pmax, pmin, pcB, max_restarts, stats=stats,
-                                 max_iters=max_iters)
+                                 max_iters=max_iters, method=stage2_method, max_inner=max_inner)
         got = X2.shape[1]
-        V = np.column_stack([X2[:n], v_rr[:, got:]])
-        U = np.column_stack([X2[n:], u_rr[:, got:]])
+        locked2 = got
+        Ub = A @ Xbest
+        stats.mv_rr += Xbest.shape[1]
+        V = np.column_stack([X2[:n], v_rr[:, got:], Xbest])
+        U = np.column_stack([X2[n:], u_rr[:, got:], Ub])
         V = V / np.linalg.norm(V, axis=0)
-        U = U / np.linalg.norm(U, axis=0)
+        U = U / np.where(np.linalg.norm(U, axis=0) > 0, np.linalg.norm(U, axis=0), 1.0)
         sigma, res, U = _final(A, V, U, stats)
     order = np.argsort(sigma, kind="stable")
     if which == "largest":
@@ -633,9 +690,10 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
         if V[jmax, i] < 0:
             V[:, i] *= -1.0
             U[:, i] *= -1.0
+    converged = (bool(info["converged"]) and len(sigma) == k and locked2 == need2
+                 and bool(np.all(res <= tol * an * (1.0 + 1e-8))))
     return {"sigma": sigma, "U": U, "V": V, "res": res, "stats": stats,
-            "stage1_sigma": s1, "converged": bool(info["converged"]) and len(sigma) == k,
-            "anorm": an}
+            "stage1_sigma": s1, "converged": converged, "anorm": an}
 
 
 def harvest(A, k, b, every=5, max_pairs=64, tol=1e-8, seed=2, cg_tol=1e-8, cg_maxit=2000,

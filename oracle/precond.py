@@ -181,16 +181,3 @@ def projected_cg(A, theta, Q, r, tol=1e-8, maxit=2000):
         p = res + (rr_new / rr) * p
         rr = rr_new
     return proj(t), maxit, False
-
-
-def jacobi_apply(d, R, theta, X=None, olsen=False, clamp=1e-3):
-    T = np.empty_like(R)
-    for i in range(R.shape[1]):
-        den = d - theta[i]
-        den = np.where(np.abs(den) < clamp * d, np.where(den >= 0, clamp * d, -clamp * d), den)
-        T[:, i] = R[:, i] / den
-        if olsen and X is not None:
-            Mx = X[:, i] / den
-            e = (X[:, i] @ T[:, i]) / (X[:, i] @ Mx)
-            T[:, i] = T[:, i] - e * Mx
-    return T
