@@ -83,6 +83,14 @@ typedef struct {
                           hold (0: none); must match phsvds_precond.gnn_width */
   int verbose;         /* 1: a progress line on stderr every 1000 iterations
                           and at each lock; 0 (default): silent */
+  int stage2_method;   /* second stage (Section 3.2): 0 GD+k with the refined
+                          projection, the residual block as correction;
+                          1 (default) JDQMR: the same outer iteration, expanded
+                          by the target's correction equation
+                          P (B - s I) P t = -r (P orthogonal to the locked
+                          vectors and the refined vector, s the target shift)
+                          solved by symmetric QMR with dynamic inner stopping */
+  int max_inner;       /* JDQMR inner step cap (0: 50) */
 } phsvds_opts;
 
 typedef struct {
@@ -94,6 +102,7 @@ typedef struct {
   int64_t fallbacks;  /* learned preconditioner replaced by Jacobi (safeguard) */
   int64_t refreshes;  /* W = C V rebuilt after a failed explicit-residual check */
   int64_t rollbacks;  /* basis expansions undone after a failed deferred check */
+  int64_t inner2;     /* JDQMR inner steps (each one product with B, in mv_stage2) */
   double t_setup, t_stage1, t_stage2, t_total; /* seconds (host wall clock) */
   double anorm_est;
   double res_stage1[64]; /* residual ||r_C|| of each pair on leaving stage 1 */

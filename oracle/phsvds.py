@@ -439,6 +439,7 @@ def stage2_refined(A, shifts, v0, u0, tol, anorm, b, pmax, pmin, precondB=None,
     prev = None
     it = 0
     thr = tol * anorm / math.sqrt(2.0)
+    last_rebuild = -(10**9)
     while True:
         if pend is not None:
             T = orth_block(pend, [Xl, V], rnd)
@@ -466,7 +467,22 @@ def stage2_refined(A, shifts, v0, u0, tol, anorm, b, pmax, pmin, precondB=None,
         rn = float(np.linalg.norm(r))
         if trace is not None:
             trace.append((it, p, theta, rn, float(sv[order[0]]), shift))
-        if rn < thr and _triplet_residual(x, wy, theta, n) <= tol * anorm:
+        lock = rn < thr and _triplet_residual(x, wy, theta, n) <= tol * anorm
+        if lock:
+            # confirm on the explicit product B x: the recurrence W y drifts
+            # from it over restarts; on a mismatch W = B V and H are rebuilt,
+            # at most once in 10 iterations (as in stage 1)
+            bx = Bop(x[:, None])[:, 0]
+            rx = bx - theta * x
+            lock = (float(np.linalg.norm(rx)) < thr
+                    and _triplet_residual(x, bx, theta, n) <= tol * anorm)
+            if not lock and it - last_rebuild > 10:
+                W = Bop(V)
+                H = _sym(V.T @ W)
+                prev = None
+                last_rebuild = it
+                continue
+        if lock:
             Xl = np.column_stack([Xl, x])
             thl.append(theta)
             j += 1
@@ -588,7 +604,7 @@ def _final(A, V, U, stats, AV=None):
 
 def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, anorm=None,
            stage2="auto", max_basis=None, min_restart=None, max_restarts=10000, floor=10.0,
-           seed=2, max_iters=None, gnn_params=None, stage2_method="gdk", max_inner=50):
+           seed=2, max_iters=None, gnn_params=None, stage2_method="jdqmr", max_inner=50):
     """k smallest (or largest) singular triplets of A by PHSVDS.
 
     Returns dict(sigma, U, V, res, stats, stage1_sigma, converged, anorm).

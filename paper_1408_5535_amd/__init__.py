@@ -47,14 +47,15 @@ class _Opts(ctypes.Structure):
                 ("max_restarts", ctypes.c_int), ("max_matvecs", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("init_block", ctypes.c_void_p),
                 ("anorm", ctypes.c_double), ("floor_factor", ctypes.c_double),
-                ("gnn_width", ctypes.c_int), ("verbose", ctypes.c_int)]
+                ("gnn_width", ctypes.c_int), ("verbose", ctypes.c_int),
+                ("stage2_method", ctypes.c_int), ("max_inner", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in
                 ("mv_stage1", "mv_rr", "mv_stage2", "mv_final", "mv_prec", "mv_floor",
                  "iters1", "iters2", "restarts1", "restarts2", "stage2_pairs", "fp32_locked",
-                 "fallbacks", "refreshes", "rollbacks")] + \
+                 "fallbacks", "refreshes", "rollbacks", "inner2")] + \
                [(f, ctypes.c_double) for f in
                 ("t_setup", "t_stage1", "t_stage2", "t_total", "anorm_est")] + \
                [("res_stage1", ctypes.c_double * 64)]
@@ -209,7 +210,8 @@ def csr_transpose(A: DeviceCSR) -> DeviceCSR:
 
 def make_opts(which="smallest", block=1, max_basis=0, min_restart=0, stage1_fp32=False,
               fp64_continue=True, stage2="auto", max_restarts=10000, max_matvecs=0, seed=1,
-              init_block=None, anorm=0.0, floor_factor=10.0, gnn_width=0, verbose=False):
+              init_block=None, anorm=0.0, floor_factor=10.0, gnn_width=0, verbose=False,
+              stage2_method="jdqmr", max_inner=50):
     o = _Opts()
     _lib.phsvds_default_opts(ctypes.byref(o))
     o.which = {"smallest": 0, "largest": 1}[which]
@@ -231,6 +233,8 @@ def make_opts(which="smallest", block=1, max_basis=0, min_restart=0, stage1_fp32
     o.floor_factor = floor_factor
     o.gnn_width = gnn_width
     o.verbose = int(verbose)
+    o.stage2_method = {"gdk": 0, "jdqmr": 1}[stage2_method]
+    o.max_inner = max_inner
     o._keep = keep
     return o
 

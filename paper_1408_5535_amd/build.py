@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = ["spmm.hip", "tall.hip", "small.hip", "solver.hip", "capi.hip", "prof.hip", "gnn.hip",
-       "harvest.hip"]
+       "harvest.hip", "jdqmr.hip"]
 LIB = os.path.join(HERE, "libphsvds.so")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

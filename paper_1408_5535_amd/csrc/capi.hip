@@ -12,6 +12,7 @@
 
 #include "gnn.hpp"
 #include "harvest.hpp"
+#include "jdqmr.hpp"
 #include "solver.hpp"
 
 namespace phs {
@@ -44,6 +45,7 @@ struct Dims {
   bool fp32, cont, jac;
   int gw = 0;        // width of the learned preconditioner (0: not used)
   bool cg = false;   // harvest buffers
+  bool jd = false;   // JDQMR work vectors
 };
 
 int width_for(int b) {
@@ -67,6 +69,9 @@ bool make_dims(int64_t m, int64_t n, int64_t nnz, int k, const phsvds_opts &o, D
   d.cont = d.fp32 && o.fp64_continue != 0;
   d.jac = false;
   d.gw = o.gnn_width;
+  d.jd = o.stage2_method == 1;
+  if (o.stage2_method != 0 && o.stage2_method != 1) return false;
+  if (o.max_inner < 0) return false;
   if (d.gw != 0 && d.gw != 8 && d.gw != 16 && d.gw != 32) return false;
   return d.pmax <= 64 && d.pmin >= d.b && d.pmin >= 1 && k >= 1 && k <= 24 && k < d.pmax;
 }
@@ -106,6 +111,7 @@ struct Plan {
   TransBufs tb;
   Stage2Bufs s2;
   double *Vf, *Uf, *AV, *RU, *RV, *Fx, *Fy;
+  double *jd;  // JDQMR work vectors
   GnnGraph gg;
   GnnBufs gb;
   CgBufs cg;
@@ -157,6 +163,7 @@ void carve(Arena &ar, const Dims &d, Plan &p) {
   p.RV = ar.take<double>(m * d.k);
   p.Fx = ar.take<double>(std::max(n, m) * 8);
   p.Fy = ar.take<double>(std::max(n, m) * 8);
+  p.jd = d.jd ? ar.take<double>(N * kJdVectors) : nullptr;
   if (d.gw > 0) gnn_carve(ar, m, n, nnz, d.gw, p.gg, p.gb);
   if (d.cg) carve_cg(ar, m, n, d.bw, p.cg);
 }
@@ -453,9 +460,13 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
     P2.max_restarts = P1.max_restarts;
     P2.max_iters = 0;
     P2.jacobi_d = pkind == PHSVDS_PREC_JACOBI ? pl.diagC : nullptr;
+    P2.method = o.stage2_method;
+    P2.max_inner = o.max_inner > 0 ? o.max_inner : 50;
+    P2.jd_work = pl.jd;
     Stage2Result r2 = run_stage2(c, A64, At64, P2, pl.s2, sp);
     stl.iters2 = r2.iters;
     stl.restarts2 = r2.restarts;
+    stl.refreshes += r2.refreshes;
     conv = conv && r2.converged;
     // assemble: stage-2 pairs from [v; u], the rest from the transition
     const int64_t N = m + n;
@@ -667,6 +678,8 @@ void phsvds_default_opts(phsvds_opts *o) {
   o->max_restarts = 10000;
   o->seed = 1;
   o->floor_factor = 10.0;
+  o->stage2_method = 1;
+  o->max_inner = 50;
 }
 
 const char *phsvds_version(void) { return "phsvds-mi355x 0.1 (gfx950)"; }

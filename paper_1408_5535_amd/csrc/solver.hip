@@ -14,6 +14,7 @@
 #include <cstring>
 #include <numeric>
 
+#include "jdqmr.hpp"
 #include "prof.hpp"
 
 namespace phs {
@@ -695,7 +696,7 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
   double *Tb = bf.Tb, *T2b = bf.T2b, *Rb = bf.Rb;
   double *H = sp.mat(13), *Rq = sp.mat(14), *Ys = sp.mat(15), *Ysl = sp.mat(16),
          *Yr = sp.mat(17), *prev = sp.mat(19), *prev2 = sp.mat(20),
-         *Gb = sp.mat(21), *Mq = sp.mat(22), *Qt = sp.mat(23), *Rt = sp.mat(24),
+         *Gb = sp.mat(21),
          *G1 = sp.mat(25), *Rc1 = sp.mat(26), *Rci1 = sp.mat(27), *Rc2 = sp.mat(28),
          *Rci2 = sp.mat(29), *Gram = sp.mat(30);
   double *sv = sp.vec(11), *thc = sp.vec(12), *ths = sp.vec(13), *rn2 = sp.vec(14),
@@ -704,6 +705,7 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
   Stage2Result res;
   double shift = P.shifts[0];
   bool qr_full = true;
+  int64_t last_rebuild = -1000000;  // iteration of the last W = B V rebuild
   const double thr = P.tol * P.anorm / std::sqrt(2.0);
 
   auto applyB = [&](double *X, int nb) {
@@ -827,8 +829,10 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
     rayleigh_small(H, ld, p, Ys, ld, ncand, thc, c.s);
     c.d2h(th_h.data(), thc, ncand * sizeof(double));
     c.sync();
+    // JDQMR expands by the correction of the target alone
+    const int bsel = P.method == 1 ? 1 : b;
     std::vector<int> slots = {0};
-    for (int q = 1; q < ncand && (int)slots.size() < b; ++q)
+    for (int q = 1; q < ncand && (int)slots.size() < bsel; ++q)
       if (th_h[q] > 0.5 * shift) slots.push_back(q);
     int ns = (int)slots.size();
     std::vector<double> ths_h(ns);
@@ -847,7 +851,44 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
                    "[phsvds] stage 2 iteration %lld: locked %d/%d, products %lld, theta %.12e, "
                    "||r|| %.3e\n",
                    (long long)it, nl, k2, (long long)c.st->mv_stage2, ths_h[0], r0);
-    if (r0 < thr) {
+    // lock on the B residual test of Section 3.1 and on the triplet
+    // residual of the normalised halves (Section 5): for sigma below
+    // tol ||A|| an unbalanced x = [v; u] can pass the first alone
+    bool lock =
+        r0 < thr && triplet_residual(c, bf.Xb, Rb, bw, n, N, ths_h[0], sp) <= P.tol * P.anorm;
+    if (lock) {
+      // confirm on the explicit product B x: the recurrence W y drifts from
+      // it over restarts; on a mismatch rebuild W = B V and H = V^T W, at
+      // most once in 10 iterations (as in stage 1)
+      applyB(bf.Xb, 1);
+      axpby(rmv(bf.WTb, N, 1, bw), rmv(bf.Xb, N, 1, bw), ths_h[0], rmv(bf.Cb, N, 1, bw), c.s);
+      double *rx2 = sp.vec(17);
+      colnorm2(rmv(bf.Cb, N, 1, bw), 0, N, rx2, c.sc, c.s);
+      double hx = 0.0;
+      c.d2h(&hx, rx2, sizeof(double));
+      c.sync();
+      lock = std::sqrt(std::max(hx, 0.0)) < thr &&
+             triplet_residual(c, bf.Xb, bf.Cb, bw, n, N, ths_h[0], sp) <= P.tol * P.anorm;
+      if (!lock && it - last_rebuild > 10) {
+        last_rebuild = it;
+        for (int c0 = 0; c0 < p; c0 += bw) {
+          const int w = std::min(bw, p - c0);
+          copy(cm(V[cur] + (int64_t)c0 * N, N, w, N), rmv(Tb, N, w, bw), c.s);
+          applyB(Tb, w);
+          copy(rmv(bf.WTb, N, w, bw), cm(W[cur] + (int64_t)c0 * N, N, w, N), c.s);
+        }
+        for (int c0 = 0; c0 < p; c0 += 32) {
+          const int w = std::min(32, p - c0);
+          tn(cm(V[cur], N, p, N), none<double>(N), cm(W[cur] + (int64_t)c0 * N, N, w, N),
+             H + (int64_t)c0 * ld, ld, c.sc, c.s);
+        }
+        nprev = 0;
+        qr_full = true;
+        ++res.refreshes;
+        continue;
+      }
+    }
+    if (lock) {
       copy(rmv(bf.Xb, N, 1, bw), cm(bf.Xl + (int64_t)nl * N, N, 1, N), c.s);
       res.theta.push_back(ths_h[0]);
       ++nl;
@@ -897,7 +938,19 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
       ns = (int)acc.size();
     }
     // correction t = Prec(r) (step 13)
-    if (P.jacobi_d) {
+    if (P.method == 1) {
+      // JDQMR: the projected correction equation of the target, by sQMR
+      JdInput in;
+      in.Q1 = cm(bf.Xl, N, nl, N);
+      in.Q2 = rmv(bf.Xb, N, 1, bw);
+      in.r = rmv(Rb, N, 1, bw);
+      in.theta = ths_h[0];
+      in.eta = shift;
+      in.thr = thr;
+      in.max_inner = P.max_inner;
+      in.jacobi_d = P.jacobi_d;
+      jd_correction(c, A, At, in, P.jd_work, rmv(Tb, N, 1, bw), sp);
+    } else if (P.jacobi_d) {
       // B-form of the Jacobi preconditioner of C: [f; g] -> [M A^T g; A M f]
       row_scale(Rb, P.jacobi_d, n, bw, true, bf.Cb, c.s);  // M f (top rows)
       spmm(At, bw, Rb + n * bw, Tb, false, c.s);           // A^T g -> top
@@ -917,15 +970,14 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
       restart_project(H, ld, p, Yr, ld, hc, Ysl, ld, ns, prev2, ld, c.s);
       std::swap(prev, prev2);
       nprev = ns;
-      // same shift: W - s V = Q (R Yr); R Yr = Qt Rt gives the new factors
-      small_gemm(false, false, p, hc, p, 1.0, Rq, ld, Yr, ld, 0.0, Mq, ld, c.s);
-      small_qr(Mq, ld, p, hc, Qt, ld, Rt, ld, c.s);
-      nn(cm(Q[cur], N, p, N), none<double>(N), Qt, ld, 1.0, cm(Q[1 - cur], N, hc, N), 0.0, c.s);
-      zero_rows(Rq, ld, 0, pmax, pmax, c.s);
-      small_gemm(false, false, hc, hc, hc, 1.0, Rt, ld, sp.eye(), ld, 0.0, Rq, ld, c.s);
       cur = 1 - cur;
       p = hc;
       ++res.restarts;
+      // a full QR of W - s V at every restart (Algorithm 2 step 12): updating
+      // the factors through a small QR of R Yr carries the rounding of every
+      // earlier restart into R, about eps ||W|| each time, which swamps
+      // sigma_min(R) when the shift is within 1e-14 ||A|| of the target
+      qr_full = true;
     } else {
       small_gemm(false, false, p, ns, ns, 1.0, Ysl, ld, sp.eye(), ld, 0.0, prev, ld, c.s);
       nprev = ns;

@@ -114,6 +114,9 @@ struct Stage2Params {
   int max_restarts;
   int64_t max_iters;
   const double *jacobi_d;
+  int method = 0;             // 0: GD+k, 1: JDQMR (correction equation by sQMR)
+  int max_inner = 50;         // JDQMR inner step cap
+  double *jd_work = nullptr;  // JDQMR: kJdVectors N-vectors
 };
 
 struct Stage2Bufs {
@@ -123,7 +126,7 @@ struct Stage2Bufs {
 struct Stage2Result {
   bool converged = false;
   int nl = 0;
-  int64_t iters = 0, restarts = 0;
+  int64_t iters = 0, restarts = 0, refreshes = 0;
   std::vector<double> theta;
   double *Xl = nullptr;
 };
