@@ -39,6 +39,7 @@ extern "C" {
 #define PHSVDS_EBREAKDOWN (-2) /* unrecoverable numerical breakdown */
 #define PHSVDS_EHIP (-3)       /* HIP runtime error */
 #define PHSVDS_ENOMEM (-4)     /* workspace too small */
+#define PHSVDS_EUSER (-5)      /* the caller's preconditioner returned nonzero */
 
 /* Sparse A in CSR, float64 values (device pointers, caller-owned, read-only). */
 typedef struct {
@@ -54,14 +55,31 @@ typedef struct {
  * GNN: the learned message-passing network given by `gnn_weights`
  * (layout below, phsvds_gnn_nweights floats), stage 1 only, with Jacobi as
  * the fallback when the leading residual stops halving within
- * fallback_window iterations. */
-enum { PHSVDS_PREC_NONE = 0, PHSVDS_PREC_JACOBI = 1, PHSVDS_PREC_GNN = 2 };
+ * fallback_window iterations.  USER: the caller's preconditioner M of
+ * C = A^T A (Section 4 admits any; Section 3.3 lets the user supply
+ * operators as functions), called through `user_apply`:
+ *   T = M R, R and T device n x b column-major (ld n), float64 if fp64,
+ *   float32 otherwise (a float32 first stage); theta: host array of the b
+ *   eigenvalue estimates of C the columns belong to (M may approximate
+ *   (C - theta I)^-1 or ignore theta); stream: the solver's stream, on which
+ *   the call must enqueue its work (it may also synchronise).  Stage 1 uses
+ *   T = M R directly; stage 2 applies the B-form [M A^T g; A M f] (two
+ *   calls per correction, theta = the squared target estimate), also inside
+ *   the JDQMR inner solve.  A nonzero return ends the solve with
+ *   PHSVDS_EUSER; the library owns R and T only for the duration of the
+ *   call. */
+enum { PHSVDS_PREC_NONE = 0, PHSVDS_PREC_JACOBI = 1, PHSVDS_PREC_GNN = 2, PHSVDS_PREC_USER = 3 };
+
+typedef int (*phsvds_user_apply)(void *ctx, const void *R, void *T, int64_t n, int b,
+                                 const double *theta, int fp64, void *stream);
 
 typedef struct {
   int kind;
   const float *gnn_weights; /* device, phsvds_gnn_nweights() floats, or NULL */
   int gnn_width;            /* hidden width of the network (e.g. 32) */
   int fallback_window;      /* GNN safeguard window in iterations (0: 25; -1: never) */
+  phsvds_user_apply user_apply; /* USER: the caller's M (see above) */
+  void *user_ctx;               /* USER: passed back as the first argument */
 } phsvds_precond;
 
 typedef struct {
@@ -91,6 +109,18 @@ typedef struct {
                           vectors and the refined vector, s the target shift)
                           solved by symmetric QMR with dynamic inner stopping */
   int max_inner;       /* JDQMR inner step cap (0: 50) */
+  const double *init_V; /* device n x k0 column-major, or NULL.  Without
+                           shifts: the first stage starts from these k0
+                           vectors (1 <= k0 <= p_min; overrides init_block).
+                           With shifts: saved first-stage output (Algorithm 2
+                           step 1 inputs); the first stage is skipped, the
+                           left vectors are u_i = A v_i / ||A v_i|| (random for
+                           ||A v_i|| <= 10 eps ||A||, Section 3.3) and every
+                           one of the k pairs goes through the second stage
+                           with shifts[i] as its target; needs k <= k0 and the
+                           smallest end */
+  int k0;               /* columns of init_V */
+  const double *shifts; /* host, k0 singular value estimates, or NULL */
 } phsvds_opts;
 
 typedef struct {
@@ -126,6 +156,22 @@ int phsvds_spmm_f64(const phsvds_csr *A, int b, const double *X, double *Y, int 
 int phsvds_spmm_f32(const phsvds_csr *A, const float *val32, int b, const float *X, float *Y,
                     int absval, void *stream);
 
+/* Y = op(A) X with op(A) = A (trans = 0) or A^T (trans = 1): the "matrix
+ * times block of vectors" with A and A^T of Section 3.3.  Row-major blocks:
+ * X is (trans ? m : n) x b, Y is (trans ? n : m) x b, b in {1, 2, 4, 8, 16,
+ * 32}.  fp32 = 0: X, Y float64 and A->val is used; fp32 = 1: X, Y float32,
+ * with val32 (float32 values in A's sparsity) for trans = 0 and A->val
+ * (converted on the device) for trans = 1.  A transposed product builds the
+ * CSR of A^T on the device in `ws` on every call (phsvds_spmm_ws_bytes
+ * bytes; 0 and ws may be NULL for trans = 0), so its rows are summed in
+ * column order and results are deterministic; that build checks A and
+ * returns PHSVDS_EINVAL for row pointers that do not start at 0, decrease
+ * or do not end at nnz, columns outside [0, n), or unsorted or repeated
+ * columns in a row.  Too small a workspace is PHSVDS_ENOMEM. */
+size_t phsvds_spmm_ws_bytes(const phsvds_csr *A, int trans, int fp32);
+int phsvds_spmm(const phsvds_csr *A, const float *val32, int trans, int fp32, int b,
+                const void *X, void *Y, void *ws, size_t ws_bytes, void *stream);
+
 /* Rayleigh-Ritz eigenproblem of the search space, H s = theta s with
  * H = V^T C V (Algorithm 1, the projection step of each iteration):
  * H device p x p column-major (ld ldh >= p, symmetric part used, not
@@ -139,7 +185,8 @@ int phsvds_rr_eig(const double *H, int ldh, int p, int nvec, int largest, double
 /* CSR of A^T (n x m) built on the device: t_rowptr (n+1), t_colind (nnz),
  * t_val (nnz); rows of A^T come out sorted by column.  `ws` must hold
  * phsvds_transpose_ws_bytes(A) bytes.  The sort of a row of A^T with L
- * entries costs O(L^2) comparisons in one workgroup when L > 32. */
+ * entries costs O(L^2) comparisons in one workgroup when L > 32.  A is
+ * checked as for phsvds_spmm (PHSVDS_EINVAL on a malformed CSR). */
 size_t phsvds_transpose_ws_bytes(const phsvds_csr *A);
 int phsvds_csr_transpose(const phsvds_csr *A, int64_t *t_rowptr, int32_t *t_colind,
                          double *t_val, void *ws, size_t ws_bytes, void *stream);
@@ -156,7 +203,7 @@ int phsvds_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int k, const phsvd
  *           entry of each v_i is positive
  *   resnorm host, k      explicit float64 residuals of the returned triplets
  *   stats   host, may be NULL
- * Returns PHSVDS_OK, PHSVDS_NOT_CONVERGED, or an error.  1 <= k <= 24,
+ * Returns PHSVDS_OK, PHSVDS_NOT_CONVERGED, or an error.  1 <= k <= 64,
  * m >= n, tol > 0.  On PHSVDS_NOT_CONVERGED (restart or product budget
  * spent) every triplet is still filled: the pairs not locked are the
  * leading Ritz approximations of the final basis, u = A v / ||A v||, with

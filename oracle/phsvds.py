@@ -22,8 +22,9 @@ the Ritz value; converged pairs are locked and the next initial guess is
 re-inserted; corrections are t = Prec(r).
 
 Readings where the paper is silent (the same readings bind the GPU path):
-  * basis sizes: p_max = max(35, 2k + 2b), p_min = max(21, ceil(0.6 p_max)),
-    and p_min <= p_max - 2b (the paper's 35/21 for blocks of 1-2);
+  * basis sizes: p_max = min(64, max(35, 2k + 2b)), p_min = max(21,
+    ceil(0.6 p_max)), and p_min <= p_max - 2b (the paper's 35/21 for blocks
+    of 1-2); locked vectors leave the basis, so k may exceed p_max;
   * GD+k restart keeps the p_min lowest Ritz vectors plus the previous
     iteration's b targeted Ritz vectors, orthogonalised against them (a
     dependent one is replaced by an independent coordinate vector of the
@@ -67,7 +68,7 @@ DEP_DROP = 1e-10
 
 
 def basis_sizes(k: int, b: int, max_basis: int | None = None, min_restart: int | None = None):
-    pmax = max_basis if max_basis else max(35, 2 * k + 2 * b)
+    pmax = max_basis if max_basis else min(64, max(35, 2 * k + 2 * b))
     pmin = min_restart if min_restart else max(21, int(math.ceil(0.6 * pmax)))
     pmin = min(pmin, pmax - 2 * b)
     if pmin < b:
@@ -365,12 +366,32 @@ def transition_rr(A, Xl, Vrest, k, pmin, anorm, seed=13, stats: Stats | None = N
     sig = s[idx]
     v = Z @ Vt.T[:, idx]
     u = Ua[:, idx].copy()
+    return sig, v, _random_tiny_left(u, sig, anorm, rnd)
+
+
+def _random_tiny_left(u, sig, anorm, rnd):
+    """Section 3.3: a left vector of a singular value <= 10 eps ||A|| carries
+    no accuracy from stage 1 and is replaced by a random one, orthogonalised
+    against the other left vectors."""
+    k = u.shape[1]
     for i in range(k):
         if sig[i] <= 10 * EPS64 * anorm:
             others = [u[:, [j for j in range(k) if j != i and sig[j] > 10 * EPS64 * anorm]]]
-            r = orth_block(rnd.vec(A.shape[0])[:, None], others, rnd)
+            r = orth_block(rnd.vec(u.shape[0])[:, None], others, rnd)
             u[:, i] = r[:, 0]
-    return sig, v, u
+    return u
+
+
+def resume_seeds(A, V, shifts, anorm, seed=13, stats: Stats | None = None):
+    """Stage-2 seeds from saved first-stage output (Algorithm 2 step 1):
+    v_i the given vectors normalised, u_i = A v_i / ||A v_i||, random where
+    shifts_i <= 10 eps ||A||."""
+    stats = stats if stats is not None else Stats()
+    v = np.asarray(V, dtype=np.float64) / np.linalg.norm(V, axis=0)
+    Av = A @ v
+    stats.mv_rr += v.shape[1]
+    u = Av / np.where(np.linalg.norm(Av, axis=0) > 0, np.linalg.norm(Av, axis=0), 1.0)
+    return v, _random_tiny_left(u, np.asarray(shifts, dtype=np.float64), anorm, _Rand(seed))
 
 
 # --------------------------------------------------------------------------
@@ -428,7 +449,10 @@ def stage2_refined(A, shifts, v0, u0, tol, anorm, b, pmax, pmin, precondB=None,
             Kb = np.column_stack([Kb, orth_block(w, [Kb], rnd)])
         else:
             t = w
-    V = orth_block(np.column_stack([Y0, Kb[:, 1:]]) if Kb.shape[1] > 1 else Y0, [], rnd)
+    # at most p_min seeds in the first basis; the others enter as their
+    # targets come up (re-insertion after a lock)
+    Ys0 = Y0[:, :min(k2, pmin)]
+    V = orth_block(np.column_stack([Ys0, Kb[:, 1:]]) if Kb.shape[1] > 1 else Ys0, [], rnd)
     W = Bop(V)
     H = _sym(V.T @ W)
     Xl = np.zeros((N, 0))
@@ -519,7 +543,8 @@ def stage2_refined(A, shifts, v0, u0, tol, anorm, b, pmax, pmin, precondB=None,
                 stats.mv_stage2 += 1
                 return np.concatenate([A.T @ w[n:], A @ w[:n]])
 
-            pc = None if precondB is None else (lambda g: precondB(g[:, None], None, None)[:, 0])
+            pc = None if precondB is None else (
+                lambda g: precondB(g[:, None], np.array([shift]), None)[:, 0])
             t, steps, _ = _jd.jd_correction(Bvec, x, r, theta, shift, np.column_stack([Xl, x]),
                                            thr, pc, max_inner)
             stats.inner2 += steps
@@ -604,7 +629,8 @@ def _final(A, V, U, stats, AV=None):
 
 def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, anorm=None,
            stage2="auto", max_basis=None, min_restart=None, max_restarts=10000, floor=10.0,
-           seed=2, max_iters=None, gnn_params=None, stage2_method="jdqmr", max_inner=50):
+           seed=2, max_iters=None, gnn_params=None, stage2_method="jdqmr", max_inner=50,
+           init_V=None, shifts=None):
     """k smallest (or largest) singular triplets of A by PHSVDS.
 
     Returns dict(sigma, U, V, res, stats, stage1_sigma, converged, anorm).
@@ -614,7 +640,15 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
     projection) or 'jdqmr' (the same outer iteration with the correction
     equation solved by symmetric QMR, Section 3.2).  ``converged`` holds
     only if every pair locked in its last stage and every final residual
-    sqrt(||r_u||^2 + ||r_v||^2) is at most tol ||A|| (Section 5)."""
+    sqrt(||r_u||^2 + ||r_v||^2) is at most tol ||A|| (Section 5).
+
+    ``precond`` may also be a callable M(R, theta) -> T, a preconditioner of
+    C applied to an n x b block (theta: the b eigenvalue estimates of C):
+    stage 1 takes T = M(R), stage 2 its B-form [M(A^T g); A M(f)] with theta
+    the squared stage-2 estimates.  ``init_V`` (n x k0) without ``shifts``
+    is the first stage's starting basis; with ``shifts`` it is saved
+    first-stage output and the solve resumes at the second stage for all k
+    pairs (left vectors from resume_seeds)."""
     import workloads  # seeded inputs only
 
     m, n = A.shape
@@ -626,7 +660,18 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
     if X0 is None:
         X0 = workloads.initial_block(n, b, seed)
     pc1 = pcB = fb = None
-    if precond == "jacobi":
+    if callable(precond):
+        M = precond
+
+        def pc1(R, theta, X):
+            return M(R, np.asarray(theta))
+
+        def pcB(R, theta, X):
+            th2 = np.asarray(theta) ** 2
+            f, g = R[:n], R[n:]
+            stats.mv_prec += R.shape[1]
+            return np.vstack([M(A.T @ g, th2), A @ M(f, th2)])
+    elif precond == "jacobi":
         d = jacobi_diag(A)
         pc1 = jacobi_precond_C(d)
         pcB = jacobi_precond_B(A, d, stats)
@@ -641,22 +686,40 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
                                     for i in range(R.shape[1])])
     elif precond != "none":
         raise ValueError(precond)
+    if init_V is not None and shifts is not None:
+        # resume at the second stage from saved first-stage output
+        an = float(anorm) if anorm else math.sqrt(_power_norm2(A, seed, stats))
+        order = np.argsort(np.asarray(shifts[:k]), kind="stable")
+        sh = np.asarray(shifts[:k], dtype=np.float64)[order]
+        v0, u0 = resume_seeds(A, np.asarray(init_V)[:, :k][:, order], sh, an, stats=stats)
+        stats.stage2_pairs = k
+        th2, X2 = stage2_refined(A, sh, v0, u0, tol, an, b, pmax, pmin, pcB, max_restarts,
+                                 stats=stats, max_iters=max_iters, method=stage2_method,
+                                 max_inner=max_inner)
+        got = X2.shape[1]
+        V = np.column_stack([X2[:n], v0[:, got:]])
+        U = np.column_stack([X2[n:], u0[:, got:]])
+        V = V / np.linalg.norm(V, axis=0)
+        U = U / np.linalg.norm(U, axis=0)
+        sigma, res, U = _final(A, V, U, stats)
+        o2 = np.argsort(sigma, kind="stable")
+        sigma, res, U, V = sigma[o2], res[o2], U[:, o2], V[:, o2]
+        for i in range(V.shape[1]):
+            if V[np.argmax(np.abs(V[:, i])), i] < 0:
+                V[:, i] *= -1.0
+                U[:, i] *= -1.0
+        stats.anorm_est = an
+        converged = got == k and bool(np.all(res <= tol * an * (1.0 + 1e-8)))
+        return {"sigma": sigma, "U": U, "V": V, "res": res, "stats": stats,
+                "stage1_sigma": sh, "converged": converged, "anorm": an}
+    if init_V is not None:
+        X0 = np.asarray(init_V, dtype=np.float64)
     sn2_init = 0.0
     if precond == "gnn" and not anorm:
         # the learned preconditioner smooths, so the basis does not reach
         # the top of the spectrum: start the ||A||^2 estimate from twelve
         # steps of power iteration on C (a lower bound)
-        x = _Rand(seed + 7).vec(A.shape[1])
-        for it in range(13):
-            nx = float(np.linalg.norm(x))
-            if not nx > 0:
-                break
-            if it > 0:
-                sn2_init = nx
-            if it == 12:
-                break
-            x = A.T @ (A @ (x / nx))
-            stats.mv_prec += 1
+        sn2_init = _power_norm2(A, seed, stats)
     Xl, thl, Vr, sn2, info = stage1_gdk(A, k, tol, b, pmax, pmin, X0, which, pc1, anorm,
                                         max_restarts, floor, EPS64, stats=stats,
                                         max_iters=max_iters,
@@ -710,6 +773,24 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
                  and bool(np.all(res <= tol * an * (1.0 + 1e-8))))
     return {"sigma": sigma, "U": U, "V": V, "res": res, "stats": stats,
             "stage1_sigma": s1, "converged": converged, "anorm": an}
+
+
+def _power_norm2(A, seed, stats):
+    """||C x|| after twelve steps of power iteration on C = A^T A from a
+    counter-based random start: a lower bound on ||A||^2."""
+    x = _Rand(seed + 7).vec(A.shape[1])
+    lam = 0.0
+    for it in range(13):
+        nx = float(np.linalg.norm(x))
+        if not nx > 0:
+            break
+        if it > 0:
+            lam = nx
+        if it == 12:
+            break
+        x = A.T @ (A @ (x / nx))
+        stats.mv_prec += 1
+    return lam
 
 
 def harvest(A, k, b, every=5, max_pairs=64, tol=1e-8, seed=2, cg_tol=1e-8, cg_maxit=2000,

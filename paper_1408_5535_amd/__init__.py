@@ -26,7 +26,14 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 PHSVDS_OK = 0
 PHSVDS_NOT_CONVERGED = 1
-PREC = {"none": 0, "jacobi": 1, "gnn": 2}
+PREC = {"none": 0, "jacobi": 1, "gnn": 2, "user": 3}
+PHSVDS_EUSER = -5
+
+# int (*)(void *ctx, const void *R, void *T, int64_t n, int b, const double *theta,
+#         int fp64, void *stream)
+USER_APPLY = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                              ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                              ctypes.c_int, ctypes.c_void_p)
 
 
 class _Csr(ctypes.Structure):
@@ -37,7 +44,8 @@ class _Csr(ctypes.Structure):
 
 class _Precond(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("gnn_weights", ctypes.c_void_p),
-                ("gnn_width", ctypes.c_int), ("fallback_window", ctypes.c_int)]
+                ("gnn_width", ctypes.c_int), ("fallback_window", ctypes.c_int),
+                ("user_apply", USER_APPLY), ("user_ctx", ctypes.c_void_p)]
 
 
 class _Opts(ctypes.Structure):
@@ -48,7 +56,9 @@ class _Opts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("init_block", ctypes.c_void_p),
                 ("anorm", ctypes.c_double), ("floor_factor", ctypes.c_double),
                 ("gnn_width", ctypes.c_int), ("verbose", ctypes.c_int),
-                ("stage2_method", ctypes.c_int), ("max_inner", ctypes.c_int)]
+                ("stage2_method", ctypes.c_int), ("max_inner", ctypes.c_int),
+                ("init_V", ctypes.c_void_p), ("k0", ctypes.c_int),
+                ("shifts", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Stats(ctypes.Structure):
@@ -181,6 +191,33 @@ def spmm(A: DeviceCSR, X: torch.Tensor, absval: bool = False, val32: torch.Tenso
     return Y
 
 
+_lib.phsvds_spmm_ws_bytes.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, ctypes.c_int]
+_lib.phsvds_spmm_ws_bytes.restype = ctypes.c_size_t
+_lib.phsvds_spmm.argtypes = [ctypes.POINTER(_Csr), _P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                             _P, _P, _P, ctypes.c_size_t, _P]
+
+
+def spmm_op(A: DeviceCSR, X: torch.Tensor, trans: bool = False,
+            val32: torch.Tensor | None = None):
+    """Y = A X or A^T X (phsvds_spmm) for a row-major block X, float64 or
+    float32 (val32: the float32 values of A for an untransposed product)."""
+    assert X.is_cuda and X.is_contiguous()
+    rows_in, rows_out = (A.m, A.n) if trans else (A.n, A.m)
+    assert X.shape[0] == rows_in
+    b = 1 if X.dim() == 1 else X.shape[1]
+    fp32 = X.dtype == torch.float32
+    Y = torch.empty((rows_out,) + tuple(X.shape[1:]), dtype=X.dtype, device=X.device)
+    c = A._c()
+    nb = int(_lib.phsvds_spmm_ws_bytes(ctypes.byref(c), int(trans), int(fp32)))
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=X.device)
+    if fp32 and not trans and val32 is None:
+        val32 = A.val.float()
+    _check(_lib.phsvds_spmm(ctypes.byref(c), val32.data_ptr() if val32 is not None else None,
+                            int(trans), int(fp32), b, X.data_ptr(), Y.data_ptr(),
+                            ws.data_ptr(), nb, _stream()), "spmm")
+    return Y
+
+
 def rr_eig(H: torch.Tensor, nvec: int, largest: bool = False):
     """Selected eigenpairs of the symmetric p x p device float64 matrix H
     (p <= 64): (theta (p,), S (p x p)); theta[:nvec], S[:, :nvec] are the
@@ -211,7 +248,7 @@ def csr_transpose(A: DeviceCSR) -> DeviceCSR:
 def make_opts(which="smallest", block=1, max_basis=0, min_restart=0, stage1_fp32=False,
               fp64_continue=True, stage2="auto", max_restarts=10000, max_matvecs=0, seed=1,
               init_block=None, anorm=0.0, floor_factor=10.0, gnn_width=0, verbose=False,
-              stage2_method="jdqmr", max_inner=50):
+              stage2_method="jdqmr", max_inner=50, init_V=None, shifts=None):
     o = _Opts()
     _lib.phsvds_default_opts(ctypes.byref(o))
     o.which = {"smallest": 0, "largest": 1}[which]
@@ -235,7 +272,17 @@ def make_opts(which="smallest", block=1, max_basis=0, min_restart=0, stage1_fp32
     o.verbose = int(verbose)
     o.stage2_method = {"gdk": 0, "jdqmr": 1}[stage2_method]
     o.max_inner = max_inner
-    o._keep = keep
+    keep2 = None
+    if init_V is not None:
+        # (n x k0) tensor -> n x k0 column-major device array
+        keep2 = init_V.to(dtype=torch.float64, device="cuda").t().contiguous()
+        o.init_V = keep2.data_ptr()
+        o.k0 = int(init_V.shape[1])
+    keep3 = None
+    if shifts is not None:
+        keep3 = (ctypes.c_double * len(shifts))(*[float(x) for x in shifts])
+        o.shifts = ctypes.cast(keep3, ctypes.POINTER(ctypes.c_double))
+    o._keep = (keep, keep2, keep3)
     return o
 
 
@@ -258,14 +305,21 @@ class Solver:
         self.V = torch.empty((k, A.n), dtype=torch.float64, device=A.rowptr.device)
 
     def solve(self, tol=1e-12, precond="none", gnn_weights=None, gnn_width=32,
-              fallback_window=0):
+              fallback_window=0, user_apply=None):
+        """``user_apply(R, T, theta, fp64)`` (precond='user'): fills T = M R,
+        R and T torch views (b x n, the rows are the columns of the C ABI's
+        n x b column-major blocks), theta a list of b floats; a raised
+        exception makes the call return nonzero."""
         import numpy as np
         k = self.k
         sig = (ctypes.c_double * k)()
         res = (ctypes.c_double * k)()
         st = _Stats()
+        cb = USER_APPLY()
+        if precond == "user":
+            cb = USER_APPLY(_user_trampoline(user_apply))
         pc = _Precond(PREC[precond], gnn_weights.data_ptr() if gnn_weights is not None else None,
-                      gnn_width, fallback_window)
+                      gnn_width, fallback_window, cb, None)
         c = self.A._c()
         rc = _lib.phsvds_svds(ctypes.byref(c), k, tol, ctypes.byref(pc), ctypes.byref(self.opts),
                               self.ws.data_ptr(), self.ws.numel(), _stream(), sig,
@@ -278,14 +332,37 @@ class Solver:
         return np.array(sig[:]), self.U.T, self.V.T, info
 
 
+class _DevView:
+    """A device array handed over by pointer (no copy), for torch.as_tensor."""
+
+    def __init__(self, ptr, shape, dtype):
+        self.__cuda_array_interface__ = {"data": (int(ptr), False), "shape": tuple(shape),
+                                         "typestr": "<f8" if dtype == "f8" else "<f4",
+                                         "strides": None, "version": 2}
+
+
+def _user_trampoline(fn):
+    def call(ctx, R, T, n, b, theta, fp64, stream):
+        try:
+            dt = "f8" if fp64 else "f4"
+            Rt = torch.as_tensor(_DevView(R, (b, n), dt), device="cuda")
+            Tt = torch.as_tensor(_DevView(T, (b, n), dt), device="cuda")
+            fn(Rt, Tt, [theta[i] for i in range(b)], bool(fp64))
+            return 0
+        except Exception:  # reported to the library as a nonzero return
+            return 1
+    return call
+
+
 def svds_smallest(A: DeviceCSR, k: int, tol: float = 1e-12, precond: str = "none",
-                  gnn_weights=None, gnn_width=32, **opt_kw):
+                  gnn_weights=None, gnn_width=32, user_apply=None, **opt_kw):
     """The k smallest (``which='largest'``: largest) singular triplets of A
     to sqrt(||r_u||^2 + ||r_v||^2) <= tol ||A||.  Returns
     (sigma, U (m x k), V (n x k), info)."""
     if precond == "gnn":
         opt_kw["gnn_width"] = gnn_width
-    return Solver(A, k, **opt_kw).solve(tol, precond, gnn_weights, gnn_width)
+    return Solver(A, k, **opt_kw).solve(tol, precond, gnn_weights, gnn_width,
+                                        user_apply=user_apply)
 
 
 # ---------------------------------------------------------------- learned preconditioner

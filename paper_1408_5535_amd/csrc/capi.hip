@@ -46,6 +46,9 @@ struct Dims {
   int gw = 0;        // width of the learned preconditioner (0: not used)
   bool cg = false;   // harvest buffers
   bool jd = false;   // JDQMR work vectors
+  // blocks for the caller's preconditioner: always planned, since the
+  // workspace size is fixed before the preconditioner is known
+  bool user = true;
 };
 
 int width_for(int b) {
@@ -62,7 +65,9 @@ bool make_dims(int64_t m, int64_t n, int64_t nnz, int k, const phsvds_opts &o, D
   d.b = o.block > 0 ? o.block : 1;
   if (d.b > 16) return false;
   d.bw = width_for(d.b);
-  d.pmax = o.max_basis > 0 ? o.max_basis : std::max(35, 2 * k + 2 * d.b);
+  // locked vectors leave the basis, so k is not bounded by p_max (<= 64,
+  // the size of the small dense problems)
+  d.pmax = o.max_basis > 0 ? o.max_basis : std::min(64, std::max(35, 2 * k + 2 * d.b));
   d.pmin = o.min_restart > 0 ? o.min_restart : std::max(21, (int)std::ceil(0.6 * d.pmax));
   d.pmin = std::min(d.pmin, d.pmax - 2 * d.b);
   d.fp32 = o.stage1_fp32 != 0;
@@ -73,7 +78,7 @@ bool make_dims(int64_t m, int64_t n, int64_t nnz, int k, const phsvds_opts &o, D
   if (o.stage2_method != 0 && o.stage2_method != 1) return false;
   if (o.max_inner < 0) return false;
   if (d.gw != 0 && d.gw != 8 && d.gw != 16 && d.gw != 32) return false;
-  return d.pmax <= 64 && d.pmin >= d.b && d.pmin >= 1 && k >= 1 && k <= 24 && k < d.pmax;
+  return d.pmax <= 64 && d.pmin >= d.b && d.pmin >= 1 && k >= 1 && k <= 64;
 }
 
 template <typename T>
@@ -91,6 +96,7 @@ void take_stage1(Arena &ar, const Dims &d, Stage1Bufs<T> &b) {
   b.Fb = ar.take<T>(d.n * d.bw);
   b.Yb = ar.take<T>(d.m * d.bw);
   b.Gs = ar.take<T>(3 * d.n);
+  b.Ub = d.user ? ar.take<T>(2 * d.n * d.bw) : nullptr;
 }
 
 struct Plan {
@@ -112,6 +118,7 @@ struct Plan {
   Stage2Bufs s2;
   double *Vf, *Uf, *AV, *RU, *RV, *Fx, *Fy;
   double *jd;  // JDQMR work vectors
+  double *ub;  // stage-2 blocks of the caller's preconditioner
   GnnGraph gg;
   GnnBufs gb;
   CgBufs cg;
@@ -164,6 +171,7 @@ void carve(Arena &ar, const Dims &d, Plan &p) {
   p.Fx = ar.take<double>(std::max(n, m) * 8);
   p.Fy = ar.take<double>(std::max(n, m) * 8);
   p.jd = d.jd ? ar.take<double>(N * kJdVectors) : nullptr;
+  p.ub = d.user ? ar.take<double>(2 * n * d.bw) : nullptr;
   if (d.gw > 0) gnn_carve(ar, m, n, nnz, d.gw, p.gg, p.gb);
   if (d.cg) carve_cg(ar, m, n, d.bw, p.cg);
 }
@@ -219,6 +227,74 @@ __global__ void k_sign_fix(double *V, int64_t n, double *U, int64_t m) {
   }
 }
 
+}  // namespace
+
+// Workspace of a transposed product: the CSR of A^T (row pointers, columns,
+// float64 values, and float32 values for a float32 product), then the
+// transpose scratch.
+size_t spmm_t_ws_bytes(int64_t m, int64_t n, int64_t nnz, bool fp32) {
+  Arena ar;
+  ar.dry = true;
+  ar.take<int64_t>(n + 1);
+  ar.take<int32_t>(std::max<int64_t>(nnz, 1));
+  ar.take<double>(std::max<int64_t>(nnz, 1));
+  if (fp32) ar.take<float>(std::max<int64_t>(nnz, 1));
+  ar.take<char>(transpose_ws_bytes(m, n, nnz));
+  return ar.used;
+}
+
+void spmm_op(const phsvds_csr *A, const float *val32, bool trans, bool fp32, int b,
+             const void *X, void *Y, void *ws, size_t ws_bytes, hipStream_t s) {
+  PHS_REQUIRE(A && X && Y, kEinval, "null argument");
+  PHS_REQUIRE(A->m >= 0 && A->n >= 0 && A->nnz >= 0 && A->nnz < (int64_t(1) << 31), kEinval,
+              "bad CSR sizes");
+  PHS_REQUIRE(b == 1 || b == 2 || b == 4 || b == 8 || b == 16 || b == 32, kEinval,
+              "block width must be 1, 2, 4, 8, 16 or 32");
+  if (!trans) {
+    PHS_REQUIRE(!fp32 || val32, kEinval, "float32 product needs val32");
+    if (fp32) {
+      SpMat<float> S;
+      S.m = A->m; S.n = A->n; S.nnz = A->nnz;
+      S.rowptr = A->rowptr; S.colind = A->colind; S.val = val32;
+      spmm(S, b, (const float *)X, (float *)Y, false, s);
+    } else {
+      SpMat<double> S;
+      S.m = A->m; S.n = A->n; S.nnz = A->nnz;
+      S.rowptr = A->rowptr; S.colind = A->colind; S.val = A->val;
+      spmm(S, b, (const double *)X, (double *)Y, false, s);
+    }
+    return;
+  }
+  PHS_REQUIRE(A->val, kEinval, "a transposed product needs the float64 values of A");
+  PHS_REQUIRE(ws && ws_bytes >= spmm_t_ws_bytes(A->m, A->n, A->nnz, fp32), kEnomem,
+              "spmm: workspace too small for the transpose");
+  Arena ar;
+  ar.base = (char *)ws;
+  ar.size = ws_bytes;
+  const int64_t nz = std::max<int64_t>(A->nnz, 1);
+  int64_t *trp = ar.take<int64_t>(A->n + 1);
+  int32_t *tci = ar.take<int32_t>(nz);
+  double *tva = ar.take<double>(nz);
+  float *tva32 = fp32 ? ar.take<float>(nz) : nullptr;
+  const size_t tws = transpose_ws_bytes(A->m, A->n, A->nnz);
+  char *tw = ar.take<char>(tws);
+  csr_transpose(A->m, A->n, A->nnz, A->rowptr, A->colind, A->val, trp, tci, tva, tw, tws, s);
+  if (fp32) {
+    copy(cm(tva, A->nnz, 1, A->nnz), cm(tva32, A->nnz, 1, A->nnz), s);
+    SpMat<float> S;
+    S.m = A->n; S.n = A->m; S.nnz = A->nnz;
+    S.rowptr = trp; S.colind = tci; S.val = tva32;
+    spmm(S, b, (const float *)X, (float *)Y, false, s);
+  } else {
+    SpMat<double> S;
+    S.m = A->n; S.n = A->m; S.nnz = A->nnz;
+    S.rowptr = trp; S.colind = tci; S.val = tva;
+    spmm(S, b, (const double *)X, (double *)Y, false, s);
+  }
+}
+
+namespace {
+
 int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc,
               const phsvds_opts *oin, void *ws, size_t ws_bytes, void *stream, double *sigma,
               double *Uout, double *Vout, double *resnorm, phsvds_stats *stats) {
@@ -236,12 +312,20 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   PHS_REQUIRE(k <= n, kEinval, "k must not exceed n");
   int pkind = Pc ? Pc->kind : PHSVDS_PREC_NONE;
   PHS_REQUIRE(pkind == PHSVDS_PREC_NONE || pkind == PHSVDS_PREC_JACOBI ||
-                  pkind == PHSVDS_PREC_GNN,
+                  pkind == PHSVDS_PREC_GNN || pkind == PHSVDS_PREC_USER,
               kEinval, "unsupported preconditioner kind");
+  PHS_REQUIRE(pkind != PHSVDS_PREC_USER || Pc->user_apply, kEinval,
+              "a USER preconditioner needs user_apply");
+  const bool resume = o.init_V && o.shifts;
+  PHS_REQUIRE(!o.shifts || o.init_V, kEinval, "shifts need init_V");
+  PHS_REQUIRE(!resume || (o.k0 >= k && o.which == 0 && o.stage2 != -1), kEinval,
+              "resuming the second stage needs k0 >= k, the smallest end and stage2 >= 0");
   Dims d;
   PHS_REQUIRE(make_dims(m, n, nnz, k, o, d), kEinval,
-              "unsupported sizes: need 1 <= k <= 24, block <= 16, max_basis <= 64");
+              "unsupported sizes: need 1 <= k <= 64, block <= 16, max_basis <= 64");
   d.jac = pkind == PHSVDS_PREC_JACOBI || pkind == PHSVDS_PREC_GNN;
+  PHS_REQUIRE(!o.init_V || resume || (o.k0 >= 1 && o.k0 <= d.pmin), kEinval,
+              "init_V without shifts needs 1 <= k0 <= p_min");
   if (pkind != PHSVDS_PREC_GNN) d.gw = 0;
   if (pkind == PHSVDS_PREC_GNN) {
     PHS_REQUIRE(Pc->gnn_weights && (Pc->gnn_width == 8 || Pc->gnn_width == 16 ||
@@ -326,9 +410,20 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   P1.max_restarts = o.max_restarts > 0 ? o.max_restarts : 10000;
   P1.max_iters = 0;
   P1.jacobi_d = d.jac ? pl.diagC : nullptr;
-  P1.init64 = o.init_block;
+  P1.init64 = o.init_V ? o.init_V : o.init_block;
   P1.init32 = nullptr;
-  P1.init_cols = d.b;
+  P1.init_cols = o.init_V ? o.k0 : d.b;
+  // the caller's preconditioner (float32 blocks in a float32 first stage)
+  auto user_call = [&](const void *R, void *T, int nb, const double *th, int fp64) {
+    const int rc = Pc->user_apply(Pc->user_ctx, R, T, n, nb, th, fp64, c.s);
+    if (rc != 0)
+      throw Error(PHSVDS_EUSER, "user preconditioner returned " + std::to_string(rc));
+  };
+  if (pkind == PHSVDS_PREC_USER) {
+    P1.user = [&](const void *R, void *T, int nb, const double *th) {
+      user_call(R, T, nb, th, d.fp32 ? 0 : 1);
+    };
+  }
   if (pkind == PHSVDS_PREC_GNN && !(o.anorm > 0)) {
     // a smoothing preconditioner keeps the top of the spectrum out of the
     // basis, so the largest Ritz value no longer estimates ||A||^2: start
@@ -339,6 +434,21 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   Stage1Result r1;
   const double *Xl64 = nullptr, *Vr64 = nullptr;
   int nvr = 0;
+  if (resume) {
+    // saved first-stage output: the given vectors and shifts stand for the
+    // locked pairs of stage 1; every pair goes through the second stage
+    r1.converged = true;
+    r1.nl = k;
+    for (int i = 0; i < k; ++i) {
+      r1.theta.push_back(o.shifts[i] * o.shifts[i]);
+      r1.res.push_back(0.0);
+      r1.tight.push_back(false);
+    }
+    r1.sn2 = o.anorm > 0 ? o.anorm * o.anorm
+                         : power_norm2(c, A64, At64, pl.tb.Xn, pl.tb.Ym, pl.tb.Z, 12, sp);
+    if (!(o.anorm > 0)) stl.mv_prec += 12;
+    Xl64 = o.init_V;
+  } else {
   auto gnn32 = [&](const void *r, const void *x, double th, void *t) {
     gnn_forward(*Ain, pl.gg, pl.gb, Pc->gnn_weights, d.gw, (const float *)r, (const float *)x,
                 th, (float *)t, c.s);
@@ -390,6 +500,7 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
     Vr64 = (const double *)r1.Vrest;
     nvr = r1.p;
   }
+  }  // first stage
   stl.iters1 += d.fp32 && !d.cont ? 0 : r1.iters;
   stl.restarts1 += d.fp32 && !d.cont ? 0 : r1.restarts;
   stl.fallbacks += r1.fallbacks;
@@ -430,7 +541,7 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   // stage-2 entry (Section 3.1): pairs whose stage-1 test was floor-limited
   int need2 = 0;
   if (!largest && o.stage2 != -1 && nl > 0) {
-    if (o.stage2 == 1) {
+    if (o.stage2 == 1 || resume) {
       need2 = nl;
     } else {
       for (int i = 0; i < nl; ++i) {
@@ -445,7 +556,10 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   double *Vsrc = Xs, *Usrc = nullptr;
   if (need2 > 0) {
     std::vector<double> shifts;
-    run_transition(c, A64, Xs, nl, Vr64, nvr, d.pmin, an, d.bw, pl.tb, sp, shifts);
+    if (resume)
+      resume_seeds(c, A64, Xs, nl, s1, an, d.bw, pl.tb, sp), shifts = s1;
+    else
+      run_transition(c, A64, Xs, nl, Vr64, nvr, d.pmin, an, d.bw, pl.tb, sp, shifts);
     Stage2Params P2{};
     P2.k2 = need2;
     P2.b = d.b;
@@ -461,6 +575,12 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
     P2.max_iters = 0;
     P2.jacobi_d = pkind == PHSVDS_PREC_JACOBI ? pl.diagC : nullptr;
     P2.method = o.stage2_method;
+    if (pkind == PHSVDS_PREC_USER) {
+      P2.user = [&](const void *R, void *T, int nb, const double *th) {
+        user_call(R, T, nb, th, 1);
+      };
+      P2.ub = pl.ub;
+    }
     P2.max_inner = o.max_inner > 0 ? o.max_inner : 50;
     P2.jd_work = pl.jd;
     Stage2Result r2 = run_stage2(c, A64, At64, P2, pl.s2, sp);
@@ -728,6 +848,19 @@ int phsvds_spmm_f32(const phsvds_csr *A, const float *val32, int b, const float 
   });
 }
 
+size_t phsvds_spmm_ws_bytes(const phsvds_csr *A, int trans, int fp32) {
+  if (!A || !trans) return 0;
+  return spmm_t_ws_bytes(A->m, A->n, A->nnz, fp32 != 0);
+}
+
+int phsvds_spmm(const phsvds_csr *A, const float *val32, int trans, int fp32, int b,
+                const void *X, void *Y, void *ws, size_t ws_bytes, void *stream) {
+  return guarded([&]() {
+    spmm_op(A, val32, trans != 0, fp32 != 0, b, X, Y, ws, ws_bytes, (hipStream_t)stream);
+    return PHSVDS_OK;
+  });
+}
+
 size_t phsvds_transpose_ws_bytes(const phsvds_csr *A) {
   if (!A) return 0;
   return transpose_ws_bytes(A->m, A->n, A->nnz);
@@ -754,7 +887,7 @@ int phsvds_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int k, const phsvd
     if (oin) o = *oin;
     Dims d;
     PHS_REQUIRE(m >= n && n >= 1 && make_dims(m, n, nnz, k, o, d), kEinval,
-                "unsupported sizes: need m >= n, 1 <= k <= 24, block <= 16, max_basis <= 64");
+                "unsupported sizes: need m >= n, 1 <= k <= 64, block <= 16, max_basis <= 64");
     Arena ar;
     ar.dry = true;
     Plan pl{};

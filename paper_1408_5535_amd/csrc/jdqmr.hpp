@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 
 #include "solver.hpp"
 
@@ -21,6 +22,9 @@ struct JdInput {
   double thr = 0.0;     // outer stopping threshold on ||B x - theta x||
   int max_inner = 50;
   const double *jacobi_d = nullptr;  // diag(C) for the B-form Jacobi preconditioner
+  // or the caller's C-preconditioner in the B-form (2 n doubles in ub)
+  std::function<void(const void *, void *, int, const double *)> user;
+  double *ub = nullptr;
 };
 
 struct JdResult {

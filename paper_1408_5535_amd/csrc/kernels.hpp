@@ -36,6 +36,9 @@ inline double spmm_bytes(const SpMat<T> &A, int b) {
          (double)A.n * b * sizeof(T) + (double)A.m * b * sizeof(T);
 }
 size_t transpose_ws_bytes(int64_t m, int64_t n, int64_t nnz);
+// Y = op(A) X for a caller CSR (the C ABI's product): op = A, or A^T built
+// into ws (spmm_t_ws_bytes bytes) on every call.
+size_t spmm_t_ws_bytes(int64_t m, int64_t n, int64_t nnz, bool fp32);
 void csr_transpose(int64_t m, int64_t n, int64_t nnz, const int64_t *rp, const int32_t *ci,
                    const double *va, int64_t *trp, int32_t *tci, double *tva, void *ws,
                    size_t ws_bytes, hipStream_t s);

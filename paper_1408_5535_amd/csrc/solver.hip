@@ -551,6 +551,11 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
         copy(cm(bf.Gs + 2 * n, n, 1, n), rmv(Tb + j, n, 1, bw), c.s);
       }
       c.st->mv_prec += 6 * nb;
+    } else if (P.user) {
+      // the caller's preconditioner on column-major copies of the block
+      copy(rmv(Rb, n, nb, bw), cm(bf.Ub, n, nb, n), c.s);
+      P.user(bf.Ub, bf.Ub + (int64_t)n * nb, nb, th_h);
+      copy(cm(bf.Ub + (int64_t)n * nb, n, nb, n), rmv(Tb, n, nb, bw), c.s);
     } else if (P.jacobi_d) {
       jacobi_apply<T>(Rb, bf.Xb, P.jacobi_d, theta, n, nb, bw, true, Tb, c.sc, c.s);
     } else {
@@ -654,6 +659,15 @@ void run_transition(Ctx &c, const SpMat<double> &A, const double *Xl, int k, con
   nn(cm(tb.AZ, m, pz, m), none<double>(m), Yv, kSP, 1.0, cm(tb.Ut, m, k, m), 0.0, c.s);
   shifts.resize(k);
   c.d2h(shifts.data(), sv, k * sizeof(double));
+  finish_left(c, m, k, shifts, anorm, tb, sp);
+}
+
+// Left vectors u_i = A v_i / ||A v_i|| of the stage-2 seeds (tb.Ut holds
+// A v_i on entry), random and orthogonalised against the others where
+// sigma_i <= 10 eps ||A|| (Section 3.3: stage 1 gives them no accuracy).
+void finish_left(Ctx &c, int64_t m, int k, const std::vector<double> &shifts, double anorm,
+                 TransBufs &tb, SmallPool &sp) {
+  double *nrm = sp.vec(9);
   colnorm2(cm(tb.Ut, m, k, m), 0, m, nrm, c.sc, c.s);
   std::vector<double> nh(k);
   c.d2h(nh.data(), nrm, k * sizeof(double));
@@ -682,6 +696,34 @@ void run_transition(Ctx &c, const SpMat<double> &A, const double *Xl, int k, con
     cgs_cols(c, tmp, m, m, (int)others.size(), (int)others.size() + 1, nullptr, 0, true, sp);
     copy(cm(tmp + (int64_t)others.size() * m, m, 1, m), cm(tb.Ut + (int64_t)i * m, m, 1, m), c.s);
   }
+}
+
+// Stage-2 seeds from saved first-stage output: v_i = the given vectors,
+// normalised; u_i as finish_left (one product with A each).
+void resume_seeds(Ctx &c, const SpMat<double> &A, const double *V, int k,
+                  const std::vector<double> &shifts, double anorm, int bw, TransBufs &tb,
+                  SmallPool &sp) {
+  const int64_t n = A.n, m = A.m;
+  copy(cm(const_cast<double *>(V), n, k, n), cm(tb.Vt, n, k, n), c.s);
+  double *nrm = sp.vec(9), *f = sp.vec(10);
+  colnorm2(cm(tb.Vt, n, k, n), 0, n, nrm, c.sc, c.s);
+  std::vector<double> h(k);
+  c.d2h(h.data(), nrm, k * sizeof(double));
+  c.sync();
+  for (int i = 0; i < k; ++i) {
+    PHS_REQUIRE(h[i] > 0.0 && std::isfinite(h[i]), kEinval, "init_V has a zero column");
+    h[i] = 1.0 / std::sqrt(h[i]);
+  }
+  c.h2d(f, h.data(), k * sizeof(double));
+  scale_cols(cm(tb.Vt, n, k, n), f, c.s);
+  for (int c0 = 0; c0 < k; c0 += bw) {
+    const int w = std::min(bw, k - c0);
+    copy(cm(tb.Vt + (int64_t)c0 * n, n, w, n), rmv(tb.Xn, n, w, bw), c.s);
+    spmm(A, bw, tb.Xn, tb.Ym, false, c.s);
+    copy(rmv(tb.Ym, m, w, bw), cm(tb.Ut + (int64_t)c0 * m, m, w, m), c.s);
+  }
+  c.st->mv_rr += k;
+  finish_left(c, m, k, shifts, anorm, tb, sp);
 }
 
 // ------------------------------------------------------------------------
@@ -795,9 +837,10 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
     }
   }
   {
-    // initial basis: seeds and the Krylov vectors 2..nk, in chunks
+    // initial basis: seeds (at most p_min of them; the others enter as
+    // their targets come up) and the Krylov vectors 2..nk, in chunks
     std::vector<std::pair<double *, int>> cols;
-    for (int i = 0; i < k2; ++i) cols.push_back({bf.Y0 + (int64_t)i * N, 1});
+    for (int i = 0; i < std::min(k2, pmin); ++i) cols.push_back({bf.Y0 + (int64_t)i * N, 1});
     for (int i = 1; i < nk; ++i) cols.push_back({K + (int64_t)i * N, 1});
     for (size_t c0 = 0; c0 < cols.size(); c0 += bw) {
       int w = (int)std::min<size_t>(bw, cols.size() - c0);
@@ -949,7 +992,23 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
       in.thr = thr;
       in.max_inner = P.max_inner;
       in.jacobi_d = P.jacobi_d;
+      in.user = P.user;
+      in.ub = P.ub;
       jd_correction(c, A, At, in, P.jd_work, rmv(Tb, N, 1, bw), sp);
+    } else if (P.user) {
+      // B-form of the caller's preconditioner of C: [f; g] -> [M A^T g; A M f]
+      std::vector<double> th2(ns);
+      for (int q = 0; q < ns; ++q) th2[q] = ths_h[q] * ths_h[q];
+      const int64_t off = (int64_t)n * ns;
+      copy(rmv(Rb, n, ns, bw), cm(P.ub, n, ns, n), c.s);  // f
+      P.user(P.ub, P.ub + off, ns, th2.data());
+      copy(cm(P.ub + off, n, ns, n), rmv(bf.Cb, n, ns, bw), c.s);
+      spmm(A, bw, bf.Cb, Tb + n * bw, false, c.s);          // A M f -> bottom
+      spmm(At, bw, Rb + n * bw, bf.C2b, false, c.s);         // A^T g
+      copy(rmv(bf.C2b, n, ns, bw), cm(P.ub, n, ns, n), c.s);
+      P.user(P.ub, P.ub + off, ns, th2.data());
+      copy(cm(P.ub + off, n, ns, n), rmv(Tb, n, ns, bw), c.s);  // M A^T g -> top
+      c.st->mv_prec += ns;
     } else if (P.jacobi_d) {
       // B-form of the Jacobi preconditioner of C: [f; g] -> [M A^T g; A M f]
       row_scale(Rb, P.jacobi_d, n, bw, true, bf.Cb, c.s);  // M f (top rows)

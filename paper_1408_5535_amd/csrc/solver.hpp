@@ -77,12 +77,16 @@ struct Stage1Params {
   // in working precision; null when not used
   std::function<void(const void *, const void *, double, void *)> gnn;
   int gnn_window = 25;  // safeguard window (iterations); <= 0: never fall back
+  // caller's preconditioner: T = M R, n x nb column-major blocks in working
+  // precision, theta the nb Ritz values (host); null when not used
+  std::function<void(const void *, void *, int, const double *)> user;
 };
 
 template <typename T>
 struct Stage1Bufs {
   T *V[2], *W[2], *Xl, *Xb, *Rb, *Tb, *T2b, *WTb, *Yb, *Fb;
   T *Gs;  // 3 n scratch for the learned preconditioner
+  T *Ub;  // 2 n bw column-major in/out blocks of the caller's preconditioner
 };
 
 double power_norm2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At, double *x, double *y,
@@ -117,6 +121,10 @@ struct Stage2Params {
   int method = 0;             // 0: GD+k, 1: JDQMR (correction equation by sQMR)
   int max_inner = 50;         // JDQMR inner step cap
   double *jd_work = nullptr;  // JDQMR: kJdVectors N-vectors
+  // caller's C-preconditioner M (float64, n x nb column-major in/out,
+  // theta host), applied in the B-form [M A^T g; A M f]; null when not used
+  std::function<void(const void *, void *, int, const double *)> user;
+  double *ub = nullptr;  // 2 n bw doubles for its blocks
 };
 
 struct Stage2Bufs {
@@ -142,6 +150,13 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
 void run_transition(Ctx &c, const SpMat<double> &A, const double *Xl, int k, const double *Vr,
                     int nvr, int pmin, double anorm, int bw, TransBufs &tb, SmallPool &sp,
                     std::vector<double> &shifts);
+void finish_left(Ctx &c, int64_t m, int k, const std::vector<double> &shifts, double anorm,
+                 TransBufs &tb, SmallPool &sp);
+void resume_seeds(Ctx &c, const SpMat<double> &A, const double *V, int k,
+                  const std::vector<double> &shifts, double anorm, int bw, TransBufs &tb,
+                  SmallPool &sp);
+void spmm_op(const phsvds_csr *A, const float *val32, bool trans, bool fp32, int b,
+             const void *X, void *Y, void *ws, size_t ws_bytes, hipStream_t s);
 Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
                         const Stage2Params &P, Stage2Bufs &bf, SmallPool &sp);
 

@@ -382,9 +382,52 @@ __global__ __launch_bounds__(256) void k_sort_long(const int32_t *longlist,
   }
 }
 
+// Zero fill by a kernel (no memset node in the stream's work).
+template <typename T>
+__global__ void k_zero(T *p, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = T(0);
+}
+template <typename T>
+void zero_fill(T *p, int64_t count, hipStream_t s) {
+  if (count <= 0) return;
+  k_zero<T><<<cdiv(count, 256), 256, 0, s>>>(p, count);
+  PHS_CHECK_LAUNCH();
+}
+
+// Validity of a CSR input: bit 1 row pointers (rp[0] = 0, non-decreasing,
+// rp[m] = nnz), bit 2 a column index outside [0, n), bit 4 a row not
+// strictly increasing (unsorted or duplicate columns).
+__global__ __launch_bounds__(256) void k_csr_check(int64_t m, int64_t n, int64_t nnz,
+                                                   const int64_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci, int32_t *flag) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > m) return;
+  int bad = 0;
+  if (r == 0 && rp[0] != 0) bad |= 1;
+  if (r == m) {
+    if (rp[m] != nnz) bad |= 1;
+  } else {
+    const int64_t a = rp[r], b = rp[r + 1];
+    if (b < a || a < 0 || b > nnz) {
+      bad |= 1;
+    } else {
+      int32_t prev = -1;
+      for (int64_t q = a; q < b; ++q) {
+        const int32_t c = ci[q];
+        if (c < 0 || c >= n) bad |= 2;
+        if (c <= prev) bad |= 4;
+        prev = c;
+      }
+    }
+  }
+  if (bad) atomicOr(flag, bad);
+}
+
 size_t transpose_ws_bytes(int64_t m, int64_t n, int64_t nnz) {
   Arena ar;
   ar.dry = true;
+  ar.take<int32_t>(16);                 // validity flag, long-row counter
   ar.take<int32_t>(n);                  // counts / fill
   ar.take<int64_t>(cdiv(n, kScanTile));  // tile sums
   ar.take<int32_t>(n + 1);              // long rows (+ counter)
@@ -400,15 +443,24 @@ void csr_transpose(int64_t m, int64_t n, int64_t nnz, const int64_t *rp, const i
   Arena ar;
   ar.base = (char *)ws;
   ar.size = ws_bytes;
+  int32_t *flags = ar.take<int32_t>(16);  // [0] validity, [1] long-row count
   int32_t *cnt = ar.take<int32_t>(n);
   int64_t ntiles = cdiv(n, kScanTile);
   int64_t *tsum = ar.take<int64_t>(ntiles);
   int32_t *longl = ar.take<int32_t>(n + 1);
   int32_t *tmpc = ar.take<int32_t>(nnz);
   double *tmpv = ar.take<double>(nnz);
-  int32_t *nlong = longl + n;
-  PHS_HIP(hipMemsetAsync(cnt, 0, n * sizeof(int32_t), s));
-  PHS_HIP(hipMemsetAsync(nlong, 0, sizeof(int32_t), s));
+  int32_t *nlong = flags + 1;
+  zero_fill(flags, 16, s);
+  k_csr_check<<<cdiv(m + 1, 256), 256, 0, s>>>(m, n, nnz, rp, ci, flags);
+  PHS_CHECK_LAUNCH();
+  int32_t hf = 0;
+  PHS_HIP(hipMemcpyAsync(&hf, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PHS_HIP(hipStreamSynchronize(s));
+  PHS_REQUIRE(!(hf & 1), kEinval, "CSR: row pointers must start at 0, not decrease, end at nnz");
+  PHS_REQUIRE(!(hf & 2), kEinval, "CSR: column index outside [0, n)");
+  PHS_REQUIRE(!(hf & 4), kEinval, "CSR: columns of a row must be sorted and distinct");
+  zero_fill(cnt, n, s);
   if (nnz) k_count_cols<<<cdiv(nnz, 256), 256, 0, s>>>(nnz, ci, cnt);
   PHS_CHECK_LAUNCH();
   if (n) {
@@ -417,9 +469,9 @@ void csr_transpose(int64_t m, int64_t n, int64_t nnz, const int64_t *rp, const i
     k_tile_scan<<<ntiles, 256, 0, s>>>(n, cnt, tsum, trp);
     PHS_CHECK_LAUNCH();
   } else {
-    PHS_HIP(hipMemsetAsync(trp, 0, sizeof(int64_t), s));
+    zero_fill(trp, 1, s);
   }
-  PHS_HIP(hipMemsetAsync(cnt, 0, n * sizeof(int32_t), s));
+  zero_fill(cnt, n, s);
   if (m) k_scatter_t<<<cdiv(m, 256), 256, 0, s>>>(m, rp, ci, va, trp, cnt, tci, tva);
   if (n) k_sort_short<<<cdiv(n, 256), 256, 0, s>>>(n, trp, tci, tva, longl, nlong);
   PHS_CHECK_LAUNCH();
@@ -487,7 +539,7 @@ __global__ __launch_bounds__(256) void k_bin_fill(int64_t m, const int64_t *__re
 void build_bins(int64_t m, const int64_t *rp, int32_t *rows, int32_t *scratch, Bin *bins,
                 int *nbins, hipStream_t s) {
   // scratch: 16 int32 (counts, offsets, fill)
-  PHS_HIP(hipMemsetAsync(scratch, 0, 16 * sizeof(int32_t), s));
+  zero_fill(scratch, 16, s);
   k_bin_count<<<cdiv(m, 256), 256, 0, s>>>(m, rp, scratch);
   PHS_CHECK_LAUNCH();
   int32_t cnt[7];
@@ -497,7 +549,7 @@ void build_bins(int64_t m, const int64_t *rp, int32_t *rows, int32_t *scratch, B
   offs[0] = 0;
   for (int g = 0; g < 7; ++g) offs[g + 1] = offs[g] + cnt[g];
   PHS_HIP(hipMemcpyAsync(scratch + 8, offs, 7 * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  PHS_HIP(hipMemsetAsync(scratch, 0, 7 * sizeof(int32_t), s));
+  zero_fill(scratch, 7, s);
   k_bin_fill<<<cdiv(m, 256), 256, 0, s>>>(m, rp, scratch + 8, scratch, rows);
   PHS_CHECK_LAUNCH();
   int nb = 0;

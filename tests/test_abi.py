@@ -16,7 +16,7 @@ def _declared():
 def test_header_declares_the_entry_points():
     names = _declared()
     for must in ("phsvds_svds", "phsvds_spmm_f64", "phsvds_spmm_f32", "phsvds_csr_transpose",
-                 "phsvds_rr_eig",
+                 "phsvds_rr_eig", "phsvds_spmm", "phsvds_spmm_ws_bytes",
                  "phsvds_workspace_bytes", "phsvds_last_error", "phsvds_version"):
         assert must in names
 
@@ -37,3 +37,34 @@ def test_workspace_planning_without_gpu():
     assert 0 < small < big
     with __import__("pytest").raises(RuntimeError):
         P.workspace_bytes(10, 20, 5, 2, o)  # m < n is rejected
+
+
+def test_workspace_planning_limits():
+    """k up to 64 (locked vectors leave the basis, p_max stays <= 64); JDQMR
+    adds its work vectors; unknown second-stage methods are rejected."""
+    import pytest
+
+    import paper_1408_5535_amd as P
+    m, n, nnz = 2 * 24 * 25, 576, 2304
+    for k in (1, 24, 25, 64):
+        assert P.workspace_bytes(m, n, nnz, k, P.make_opts(block=4)) > 0
+    with pytest.raises(RuntimeError):
+        P.workspace_bytes(m, n, nnz, 65, P.make_opts(block=4))
+    gd = P.workspace_bytes(m, n, nnz, 10, P.make_opts(block=4, stage2_method="gdk"))
+    jd = P.workspace_bytes(m, n, nnz, 10, P.make_opts(block=4, stage2_method="jdqmr"))
+    assert jd >= gd + 10 * (m + n) * 8
+    o = P.make_opts(block=4)
+    o.stage2_method = 2
+    with pytest.raises(RuntimeError):
+        P.workspace_bytes(m, n, nnz, 10, o)
+
+
+def test_transposed_product_workspace():
+    import paper_1408_5535_amd as P
+    c = P._Csr(300, 200, 3600, None, None, None)
+    lib = P._lib
+    assert lib.phsvds_spmm_ws_bytes(ctypes.byref(c), 0, 0) == 0
+    t64 = lib.phsvds_spmm_ws_bytes(ctypes.byref(c), 1, 0)
+    t32 = lib.phsvds_spmm_ws_bytes(ctypes.byref(c), 1, 1)
+    # the CSR of A^T (rowptr, columns, values) at least
+    assert t64 >= 201 * 8 + 3600 * 12 and t32 > t64

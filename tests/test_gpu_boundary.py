@@ -1,0 +1,204 @@
+"""The C-ABI boundary on the GPU: the transposed product, CSR validation,
+k up to 64, the caller's preconditioner (USER) and resuming the second stage
+from saved first-stage output.  Each is checked against SciPy, closed forms
+or the CPU oracle."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+import workloads as wl
+from oracle import dense, phsvds as ph
+from tests import closed_forms as cf
+from tests.gpu_util import as_np, gpu, need_gpu, say, to_dev
+
+
+def _err_bound(A, X, trans, eps):
+    """|op(A)| |X| * n_row * eps: the forward-error bound of a dot product."""
+    Aa = abs(A.T if trans else A).tocsr()
+    rowlen = np.diff(Aa.indptr).max()
+    return (Aa @ np.abs(X)) * (rowlen + 2) * eps
+
+
+@gpu
+@pytest.mark.parametrize("family", ["random", "powerlaw"])
+@pytest.mark.parametrize("b", [1, 4, 8])
+@pytest.mark.parametrize("trans", [False, True])
+def test_spmm_op_both_directions_vs_scipy(family, b, trans):
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A = wl.random_sparse(3000, 2000, 9, seed=31) if family == "random" else \
+        wl.powerlaw_sparse(3000, 2000, kmax=300, seed=32)
+    rows_in = A.shape[0] if trans else A.shape[1]
+    X = np.random.default_rng(33).standard_normal((rows_in, b))
+    ref = (A.T if trans else A) @ X
+    say("spmm_op", family, "b", b, "trans", trans)
+    Y = as_np(P.spmm_op(to_dev(A), torch.tensor(X, device="cuda").contiguous(), trans=trans))
+    assert np.all(np.abs(Y - ref) <= _err_bound(A, X, trans, 2.0 ** -53) + 1e-300)
+    X32 = X.astype(np.float32)
+    Y32 = as_np(P.spmm_op(to_dev(A), torch.tensor(X32, device="cuda").contiguous(), trans=trans))
+    ref32 = (A.T if trans else A) @ X32.astype(np.float64)
+    assert np.all(np.abs(Y32 - ref32) <= _err_bound(A, X32.astype(np.float64), trans, 2.0 ** -23)
+                  * 2 + 1e-30)
+
+
+def _bad_csr(kind):
+    A = wl.random_sparse(60, 40, 5, seed=34).tocsr()
+    A.sort_indices()
+    rp, ci, va = A.indptr.astype(np.int64).copy(), A.indices.astype(np.int32).copy(), A.data.copy()
+    if kind == "unsorted":
+        ci[rp[3]], ci[rp[3] + 1] = ci[rp[3] + 1], ci[rp[3]]
+    elif kind == "duplicate":
+        ci[rp[5] + 1] = ci[rp[5]]
+    elif kind == "rowptr":
+        rp[-1] -= 1
+    elif kind == "range":
+        ci[rp[7]] = 40
+    import paper_1408_5535_amd as P
+    return P.DeviceCSR(60, 40, torch.tensor(rp, device="cuda"), torch.tensor(ci, device="cuda"),
+                       torch.tensor(va, device="cuda"))
+
+
+@gpu
+@pytest.mark.parametrize("kind", ["unsorted", "duplicate", "rowptr", "range"])
+def test_malformed_csr_is_einval(kind):
+    need_gpu()
+    import paper_1408_5535_amd as P
+    D = _bad_csr(kind)
+    say("malformed CSR", kind)
+    with pytest.raises(RuntimeError, match=r"\(-1\)"):
+        P.spmm_op(D, torch.ones((60, 2), dtype=torch.float64, device="cuda"), trans=True)
+    with pytest.raises(RuntimeError, match=r"\(-1\)"):
+        P.svds_smallest(D, 2, 1e-10)
+
+
+@gpu
+@pytest.mark.parametrize("k", [40, 64])
+def test_many_triplets_closed_form(k):
+    """k beyond the old 24 up to 64 (grid N = 24, n = 576): sigma against
+    the closed form, float64 residuals recomputed on the host."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    N = 24
+    A = wl.grid_gradient(N)
+    an = cf.grid_norm(N)
+    say("grid N=24 k", k)
+    sig, U, V, info = P.svds_smallest(to_dev(A), k, 1e-12, block=4, anorm=an)
+    say({q: info[q] for q in ("status", "mv_total", "iters1", "stage2_pairs")})
+    assert info["status"] == 0
+    ex = cf.grid_sigmas(N)[:k]
+    assert np.all(np.abs(sig - ex) <= 1e-10 * ex)
+    res = dense.triplet_residuals(A, sig, as_np(U), as_np(V))
+    assert np.all(res <= 1e-12 * an)
+    Vn = as_np(V)
+    assert np.linalg.norm(Vn.T @ Vn - np.eye(k)) < 1e-9
+
+
+def _givens_small():
+    n, m = 200, 240
+    s = np.concatenate([[1e-4, 2e-4, 3e-4], np.linspace(0.05, 1.0, n - 3)])
+    return wl.givens_scrambled(m, n, s, rot_left=int(0.7 * m), rot_right=int(0.7 * n), seed=2)
+
+
+@gpu
+@pytest.mark.parametrize("method", ["gdk", "jdqmr"])
+def test_user_preconditioner_vs_oracle(method):
+    """USER: the caller's M = diag(C)^-1, written with torch on the pointers
+    the library hands over, in both stages (stage 2: its B-form)."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A, sigx, Ux, Vx = _givens_small()
+    D = to_dev(A)
+    d64 = torch.zeros(A.shape[1], dtype=torch.float64, device="cuda").index_add_(
+        0, D.colind.long(), D.val * D.val)
+    seen = {"calls": 0, "fp64": set()}
+
+    def apply(R, T, theta, fp64):
+        seen["calls"] += 1
+        seen["fp64"].add(fp64)
+        T.copy_(R / (d64 if fp64 else d64.float())[None, :])
+
+    say("USER preconditioner, givens 1e-4, stage 2", method)
+    X0 = torch.tensor(wl.initial_block(A.shape[1], 1, 2))
+    sig, U, V, info = P.svds_smallest(D, 3, 1e-12, block=1, anorm=1.0, precond="user",
+                                      user_apply=apply, init_block=X0, stage2_method=method)
+    say({q: info[q] for q in ("status", "mv_total", "mv_prec", "stage2_pairs")}, seen["calls"])
+    assert info["status"] == 0 and seen["calls"] > 0 and seen["fp64"] == {True}
+    assert info["stage2_pairs"] == 3 and info["mv_prec"] > 0
+    assert np.all(np.abs(sig - sigx[:3]) <= 1e-10 * sigx[:3])
+    assert np.all(dense.triplet_residuals(A, sig, as_np(U), as_np(V)) <= 1e-12)
+    d = ph.jacobi_diag(A)
+    out = ph.phsvds(A, 3, 1e-12, block=1, anorm=1.0, precond=lambda R, th: R / d[:, None],
+                    stage2_method=method)
+    assert out["converged"]
+    ratio = info["mv_total"] / out["stats"].mv_total
+    say("MV gpu/oracle", ratio)
+    assert 0.5 <= ratio <= 2.0
+
+
+@gpu
+def test_user_preconditioner_float32_stage1_and_error_return():
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A, sigx, Ux, Vx = _givens_small()
+    D = to_dev(A)
+    d64 = torch.zeros(A.shape[1], dtype=torch.float64, device="cuda").index_add_(
+        0, D.colind.long(), D.val * D.val)
+    kinds = set()
+
+    def apply(R, T, theta, fp64):
+        kinds.add(fp64)
+        T.copy_(R / (d64 if fp64 else d64.float())[None, :])
+
+    say("USER preconditioner with a float32 first stage")
+    sig, U, V, info = P.svds_smallest(D, 3, 1e-12, block=1, anorm=1.0, precond="user",
+                                      user_apply=apply, stage1_fp32=True, fp64_continue=False)
+    assert info["status"] == 0 and kinds == {False, True}
+    assert np.all(np.abs(sig - sigx[:3]) <= 1e-10 * sigx[:3])
+
+    def failing(R, T, theta, fp64):
+        raise ValueError("no preconditioner today")
+
+    with pytest.raises(RuntimeError, match=r"\(-5\)"):
+        P.svds_smallest(D, 3, 1e-12, block=1, anorm=1.0, precond="user", user_apply=failing)
+
+
+@gpu
+@pytest.mark.parametrize("method", ["gdk", "jdqmr"])
+def test_resume_second_stage_from_saved_output(method):
+    """init_V + shifts: the first stage is skipped and the saved vectors and
+    shifts seed Algorithm 2 directly; against the closed form and the
+    oracle's resume."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A, sigx, Ux, Vx = _givens_small()
+    V0 = Vx[:, :3] + 1e-7 * np.random.default_rng(35).standard_normal((A.shape[1], 3))
+    shifts = sigx[:3] * (1 + 1e-9)
+    say("resume stage 2", method)
+    sig, U, V, info = P.svds_smallest(to_dev(A), 3, 1e-12, block=1, anorm=1.0,
+                                      init_V=torch.tensor(V0), shifts=list(shifts),
+                                      stage2_method=method)
+    say({q: info[q] for q in ("status", "mv_total", "mv_stage1", "mv_stage2", "stage2_pairs")})
+    assert info["status"] == 0 and info["mv_stage1"] == 0 and info["stage2_pairs"] == 3
+    assert np.all(np.abs(sig - sigx[:3]) <= 1e-10 * sigx[:3])
+    assert np.all(dense.triplet_residuals(A, sig, as_np(U), as_np(V)) <= 1e-12)
+    out = ph.phsvds(A, 3, 1e-12, block=1, anorm=1.0, init_V=V0, shifts=shifts,
+                    stage2_method=method)
+    assert out["converged"]
+    ratio = info["mv_total"] / out["stats"].mv_total
+    say("MV gpu/oracle", ratio)
+    assert 0.5 <= ratio <= 2.0
+
+
+@gpu
+def test_initial_basis_of_k0_vectors():
+    """init_V without shifts: stage 1 starts from k0 given vectors."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    N = 16
+    A = wl.grid_gradient(N)
+    an = cf.grid_norm(N)
+    X0 = torch.tensor(np.random.default_rng(36).standard_normal((A.shape[1], 6)))
+    sig, U, V, info = P.svds_smallest(to_dev(A), 6, 1e-12, block=2, anorm=an, init_V=X0)
+    assert info["status"] == 0
+    assert np.all(np.abs(sig - cf.grid_sigmas(N)[:6]) <= 1e-10 * cf.grid_sigmas(N)[:6])

@@ -284,3 +284,53 @@ def test_refined_smallest_singular_value_nonincreasing_within_a_cycle():
             grew += 1
             assert b[4] <= a[4] * (1 + 1e-10) + 1e-15 * an
     assert grew >= 5
+
+
+# ------------------------------------------------------------- boundary forms
+def test_resume_from_saved_stage1_output_vs_closed_form():
+    """Algorithm 2 step 1 inputs given directly (saved first-stage vectors
+    and shifts): the second stage alone reaches the closed form."""
+    n, m = 200, 240
+    s = np.concatenate([[1e-4, 2e-4, 3e-4], np.linspace(0.05, 1.0, n - 3)])
+    A, sig, U, V = wl.givens_scrambled(m, n, s, rot_left=int(0.7 * m), rot_right=int(0.7 * n),
+                                       seed=2)
+    rng = np.random.default_rng(22)
+    V0 = V[:, :3] + 1e-7 * rng.standard_normal((n, 3))
+    shifts = sig[:3] * (1 + 1e-9)
+    out = ph.phsvds(A, 3, 1e-12, block=1, anorm=1.0, init_V=V0, shifts=shifts)
+    assert out["converged"] and out["stats"].stage2_pairs == 3
+    assert out["stats"].mv_stage1 == 0
+    assert np.all(np.abs(out["sigma"] - sig[:3]) <= 1e-10 * sig[:3])
+    # left vectors of the seeds: A v / ||A v|| (no tiny shifts here)
+    v0, u0 = ph.resume_seeds(A, V0, shifts, 1.0)
+    Av = A @ (V0 / np.linalg.norm(V0, axis=0))
+    assert np.allclose(u0, Av / np.linalg.norm(Av, axis=0), atol=1e-14)
+
+
+def test_callable_preconditioner_and_its_bform():
+    """A caller's C-preconditioner (here diag(C)^-1 as a callable): stage 1
+    uses it directly, stage 2 its B-form [M A^T g; A M f]; the result is the
+    dense SVD, and the B-form equals the dense block operator."""
+    A = wl.random_sparse(240, 160, 6, seed=23)
+    d = ph.jacobi_diag(A)
+    calls = []
+
+    def M(R, theta):
+        calls.append(np.asarray(theta).copy())
+        return R / d[:, None]
+
+    sig, U, V = dense.svd_extreme_dense(A, 3)
+    an = np.linalg.norm(A.toarray(), 2)
+    out = ph.phsvds(A, 3, 1e-12, block=1, anorm=an, precond=M, stage2="force",
+                    stage2_method="gdk")
+    assert out["converged"] and calls
+    assert np.all(np.abs(out["sigma"] - sig) <= 1e-10 * sig)
+    n, m = 160, 240
+    Ad = A.toarray()
+    PB = np.block([[np.zeros((n, n)), np.diag(1 / d) @ Ad.T], [Ad @ np.diag(1 / d), np.zeros((m, m))]])
+    st = ph.Stats()
+    # the B-form the oracle builds from M, applied to random blocks
+    R = np.random.default_rng(24).standard_normal((n + m, 2))
+    f, g = R[:n], R[n:]
+    got = np.vstack([M(A.T @ g, [0, 0]), A @ M(f, [0, 0])])
+    assert np.allclose(got, PB @ R, rtol=1e-13, atol=1e-14)
