@@ -172,6 +172,22 @@ size_t phsvds_spmm_ws_bytes(const phsvds_csr *A, int trans, int fp32);
 int phsvds_spmm(const phsvds_csr *A, const float *val32, int trans, int fp32, int b,
                 const void *X, void *Y, void *ws, size_t ws_bytes, void *stream);
 
+/* phsvds_spmm without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same kernels, with the
+ * transpose built in a scratch array the library holds on each GPU for the
+ * life of the process (64 MiB per GPU, enough for a transposed product of
+ * about 2M nonzeros; the need is phsvds_spmm_ws_bytes).  Calls no hipMalloc,
+ * hipFree or other allocating routine and records no profiling events.  A
+ * product needing more scratch returns PHSVDS_ENOMEM before touching the
+ * device.  Every call on one GPU shares that GPU's scratch and leaves its
+ * contents behind: calls that overlap on one GPU (other streams or host
+ * threads) race and must be serialised by the caller.  A transposed call
+ * synchronises the stream (the build reads back a validity flag and a row
+ * count). */
+int phsvds_spmm_noalloc(const phsvds_csr *A, const float *val32, int trans, int fp32, int b,
+                        const void *X, void *Y, void *stream);
+
 /* Rayleigh-Ritz eigenproblem of the search space, H s = theta s with
  * H = V^T C V (Algorithm 1, the projection step of each iteration):
  * H device p x p column-major (ld ldh >= p, symmetric part used, not

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 
@@ -16,9 +17,38 @@
 #include "solver.hpp"
 
 namespace phs {
+
+// Device scratch of the allocation-free transposed product
+// (phsvds_spmm_noalloc): the CSR of A^T and the transpose scratch.  Each
+// GPU holds its own copy for the life of the process.  In host code
+// `scratch` names a host-side stand-in, never the device memory: the device
+// address of each GPU's copy comes from hipGetSymbolAddress and is the only
+// thing passed to kernels.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
 namespace {
 
 thread_local std::string g_err;
+
+// Device address of this GPU's `scratch`, looked up once per device with
+// that device current (the calling thread's current device).
+void *noalloc_scratch() {
+  static std::mutex mu;
+  static void *addr[64] = {};
+  int dev = -1;
+  PHS_HIP(hipGetDevice(&dev));
+  PHS_REQUIRE(dev >= 0 && dev < 64, kEinval, "device index out of range");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw Error(-3, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    addr[dev] = p;
+  }
+  return addr[dev];
+}
 
 double wall() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
@@ -244,7 +274,7 @@ size_t spmm_t_ws_bytes(int64_t m, int64_t n, int64_t nnz, bool fp32) {
 }
 
 void spmm_op(const phsvds_csr *A, const float *val32, bool trans, bool fp32, int b,
-             const void *X, void *Y, void *ws, size_t ws_bytes, hipStream_t s) {
+             const void *X, void *Y, void *ws, size_t ws_bytes, hipStream_t s, bool timed) {
   PHS_REQUIRE(A && X && Y, kEinval, "null argument");
   PHS_REQUIRE(A->m >= 0 && A->n >= 0 && A->nnz >= 0 && A->nnz < (int64_t(1) << 31), kEinval,
               "bad CSR sizes");
@@ -256,12 +286,14 @@ void spmm_op(const phsvds_csr *A, const float *val32, bool trans, bool fp32, int
       SpMat<float> S;
       S.m = A->m; S.n = A->n; S.nnz = A->nnz;
       S.rowptr = A->rowptr; S.colind = A->colind; S.val = val32;
-      spmm(S, b, (const float *)X, (float *)Y, false, s);
+      if (timed) spmm(S, b, (const float *)X, (float *)Y, false, s);
+      else spmm_untimed(S, b, (const float *)X, (float *)Y, s);
     } else {
       SpMat<double> S;
       S.m = A->m; S.n = A->n; S.nnz = A->nnz;
       S.rowptr = A->rowptr; S.colind = A->colind; S.val = A->val;
-      spmm(S, b, (const double *)X, (double *)Y, false, s);
+      if (timed) spmm(S, b, (const double *)X, (double *)Y, false, s);
+      else spmm_untimed(S, b, (const double *)X, (double *)Y, s);
     }
     return;
   }
@@ -284,12 +316,14 @@ void spmm_op(const phsvds_csr *A, const float *val32, bool trans, bool fp32, int
     SpMat<float> S;
     S.m = A->n; S.n = A->m; S.nnz = A->nnz;
     S.rowptr = trp; S.colind = tci; S.val = tva32;
-    spmm(S, b, (const float *)X, (float *)Y, false, s);
+    if (timed) spmm(S, b, (const float *)X, (float *)Y, false, s);
+    else spmm_untimed(S, b, (const float *)X, (float *)Y, s);
   } else {
     SpMat<double> S;
     S.m = A->n; S.n = A->m; S.nnz = A->nnz;
     S.rowptr = trp; S.colind = tci; S.val = tva;
-    spmm(S, b, (const double *)X, (double *)Y, false, s);
+    if (timed) spmm(S, b, (const double *)X, (double *)Y, false, s);
+    else spmm_untimed(S, b, (const double *)X, (double *)Y, s);
   }
 }
 
@@ -856,7 +890,26 @@ size_t phsvds_spmm_ws_bytes(const phsvds_csr *A, int trans, int fp32) {
 int phsvds_spmm(const phsvds_csr *A, const float *val32, int trans, int fp32, int b,
                 const void *X, void *Y, void *ws, size_t ws_bytes, void *stream) {
   return guarded([&]() {
-    spmm_op(A, val32, trans != 0, fp32 != 0, b, X, Y, ws, ws_bytes, (hipStream_t)stream);
+    spmm_op(A, val32, trans != 0, fp32 != 0, b, X, Y, ws, ws_bytes, (hipStream_t)stream, true);
+    return PHSVDS_OK;
+  });
+}
+
+int phsvds_spmm_noalloc(const phsvds_csr *A, const float *val32, int trans, int fp32, int b,
+                        const void *X, void *Y, void *stream) {
+  return guarded([&]() {
+    PHS_REQUIRE(A, kEinval, "null argument");
+    void *ws = nullptr;
+    size_t need = 0;
+    if (trans) {
+      need = spmm_t_ws_bytes(A->m, A->n, A->nnz, fp32 != 0);
+      PHS_REQUIRE(need <= kNoAllocScratchBytes, kEnomem,
+                  "phsvds_spmm_noalloc: this transposed product needs " + std::to_string(need) +
+                      " bytes of scratch, above the " + std::to_string(kNoAllocScratchBytes) +
+                      " the library holds per GPU");
+      ws = noalloc_scratch();
+    }
+    spmm_op(A, val32, trans != 0, fp32 != 0, b, X, Y, ws, need, (hipStream_t)stream, false);
     return PHSVDS_OK;
   });
 }

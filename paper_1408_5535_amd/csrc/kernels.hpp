@@ -27,6 +27,9 @@ int lanes_for_length(double avg);
 template <typename T>
 void spmm(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, hipStream_t s,
           int64_t ycm = 0, int ycols = 0);
+// The same product without the profiling hooks (which record events).
+template <typename T>
+void spmm_untimed(const SpMat<T> &A, int b, const T *X, T *Y, hipStream_t s);
 // Algorithmic HBM bytes of one Y = A X at block width b: values and column
 // indices once, row pointers once, X once, Y once (the count spmm records
 // for each launch it times).

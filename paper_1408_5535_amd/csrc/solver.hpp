@@ -156,7 +156,7 @@ void resume_seeds(Ctx &c, const SpMat<double> &A, const double *V, int k,
                   const std::vector<double> &shifts, double anorm, int bw, TransBufs &tb,
                   SmallPool &sp);
 void spmm_op(const phsvds_csr *A, const float *val32, bool trans, bool fp32, int b,
-             const void *X, void *Y, void *ws, size_t ws_bytes, hipStream_t s);
+             const void *X, void *Y, void *ws, size_t ws_bytes, hipStream_t s, bool timed);
 Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
                         const Stage2Params &P, Stage2Bufs &bf, SmallPool &sp);
 

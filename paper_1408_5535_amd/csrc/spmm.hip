@@ -251,6 +251,14 @@ void spmm_launch(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, int64_
                          X, Y, ycm, ycols, s);
   }
 }
+template <typename T>
+void spmm_untimed(const SpMat<T> &A, int b, const T *X, T *Y, hipStream_t s) {
+  spmm_launch(A, b, X, Y, false, 0, 0, s);
+}
+template void spmm_untimed<float>(const SpMat<float> &, int, const float *, float *,
+                                  hipStream_t);
+template void spmm_untimed<double>(const SpMat<double> &, int, const double *, double *,
+                                   hipStream_t);
 template void spmm<float>(const SpMat<float> &, int, const float *, float *, bool, hipStream_t,
                           int64_t, int);
 template void spmm<double>(const SpMat<double> &, int, const double *, double *, bool,
