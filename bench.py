@@ -4,14 +4,19 @@ One step = one full solve (stage 1, and stage 2 when the Section 3.1 rule
 asks for it, plus the final float64 residual check) of the k smallest
 singular triplets on a synthetic matrix already resident in HBM.
 
-Default workload: the 2-D grid gradient operator [I (x) D1; D1 (x) I] with
-N = 512 (m = 525312, n = 262144, nnz = 1048576), k = 10 smallest, block 4,
-float64, tolerance 1e-12 ||A||.
+Default workload (the largest configuration): power-law rows, m = 4M,
+n = 3M, about 43M nonzeros, k = 20 smallest, block 8, float32 stage 1 then
+float64, Jacobi preconditioner, tolerance 1e-12 ||A||, under a product cap
+(the solve does not reach the tolerance within it; the line says so in
+"status" and reports the residuals reached).  --workload grid runs the 2-D
+grid gradient operator N = 512, k = 10, block 4, float64 instead.
 
 Prints one JSON line (see the repository's benchmark contract): value is the
-mean time per solve in seconds; roofline is the float64 SpMM, timed live
-with HIP events on the solver's stream during the timed steps; cpu_baseline
-is the CPU oracle timed on a bounded sample of the same solve.
+mean time per solve in seconds; roofline is the dominant SpMM, timed live
+with HIP events on the solver's stream during the timed steps;
+iteration_roofline the algorithmic bytes of a whole stage-1 iteration over
+its time; cpu_baseline the CPU oracle timed on a bounded sample of the same
+workload.
 """
 import argparse
 import hashlib
@@ -100,6 +105,40 @@ def spmm_probe(kind, N):
     torch.cuda.synchronize()
     print(json.dumps({"spmm_probe": kind, "m": A.shape[0], "n": A.shape[1], "nnz": int(A.nnz),
                       "b": b}), flush=True)
+
+
+def tall_probe(kind, rows, nx, ny, dtype, reps=10):
+    """Event-timed tall-skinny products at a given shape (and a target for
+    counter runs): X^T Y (tn, Y row-major as the solver's blocks) or X S
+    (nn); algorithmic bytes = the operands read once and the output
+    written once."""
+    import torch
+    import paper_1408_5535_amd as P
+    dt = torch.float32 if dtype == "f32" else torch.float64
+    s = 4 if dtype == "f32" else 8
+    X = torch.rand(nx, rows, dtype=dt, device="cuda")
+    if kind == "tn":
+        Y = torch.rand(rows, ny, dtype=dt, device="cuda")
+        run = lambda: P.tsgemm_tn(X, Y, y_row_major=True)
+        nbytes = rows * (nx + ny) * s
+    else:
+        S = torch.rand(nx, ny, dtype=torch.float64, device="cuda")
+        Y = torch.empty(ny, rows, dtype=dt, device="cuda")
+        run = lambda: P.tsgemm_nn(X, S, Y)
+        nbytes = rows * (nx + ny) * s
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    print(json.dumps({"tall_probe": kind, "rows": rows, "nx": nx, "ny": ny, "dtype": dtype,
+                      "us_per_call": sec * 1e6, "algorithmic_bytes": nbytes,
+                      "gbs": nbytes / sec / 1e9, "note": "event pair around all calls, incl. "
+                      "the partial reduction for tn"}), flush=True)
 
 
 COMPARE = {
@@ -277,15 +316,232 @@ def cpu_baseline(A, k, b, anorm, mv_total, budget_s=20.0):
                       f"{mv_total} products"}
 
 
+HEADLINE = dict(k=20, b=8, cap=24_000, tol=1e-12,
+                label="power-law rows 4000000 x 3000000 (shifted Zipf 2, mean 10, max 2000), "
+                      "N(0,1), diagonal shift U[0.01, 0.1], seed 5; k=20 smallest, block 8, "
+                      "float32 stage 1 then float64, Jacobi preconditioner, JDQMR stage 2, "
+                      "tol 1e-12 ||A||")
+
+
+def iteration_bytes(m, n, nnz, b, p, s):
+    """Algorithmic HBM bytes of one stage-1 block iteration (fused ideal):
+    the two SpMMs of C X, V and W streamed once each for the projection,
+    Ritz block and residual, and about eight passes over the n x b block for
+    the orthogonalisation and casts."""
+    spmm = nnz * (s + 4) + (m + 1) * 8 + n * b * s + m * b * s
+    spmmt = nnz * (s + 4) + (n + 1) * 8 + m * b * s + n * b * s
+    return spmm + spmmt + 2.0 * n * p * s + 8.0 * n * b * s
+
+
+def grid_extra(P, torch, N=512, k=10, b=4):
+    """The grid N=512 solve (the earlier headline), reported beside the metric."""
+    A, exact, anorm = grid_workload(N)
+    Ad = P.DeviceCSR.from_scipy(A)
+    solver = P.Solver(Ad, k, block=b)
+    solver.solve(1e-12)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sig, U, V, info = solver.solve(1e-12)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lsolver = P.Solver(Ad, k, block=b, which="largest")
+    torch.cuda.synchronize()
+    tl = time.perf_counter()
+    lsig, _, _, linfo = lsolver.solve(1e-12)
+    torch.cuda.synchronize()
+    tl = time.perf_counter() - tl
+    lex = exact[::-1][:k]
+    return {"workload": f"grid gradient N={N} (m={A.shape[0]}, n={A.shape[1]}, nnz={A.nnz}), "
+                        f"k={k} smallest, block {b}, float64, tol 1e-12",
+            "seconds": dt, "status": int(info["status"]), "mv_total": int(info["mv_total"]),
+            "matvecs_per_triplet": info["mv_total"] / k,
+            "max_rel_sigma_err_vs_closed_form": float(np.max(np.abs(sig - exact[:k]) / exact[:k])),
+            "max_residual_over_norm": float(np.max(info["res"]) / anorm),
+            "largest": {"seconds": tl, "status": int(linfo["status"]),
+                        "mv_total": int(linfo["mv_total"]),
+                        "max_rel_sigma_err_vs_closed_form":
+                            float(np.max(np.abs(lsig - lex) / lex))}}
+
+
+def host_info():
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["nproc"] = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu"] = line.split(":", 1)[1].strip()
+                    break
+    except Exception:
+        pass
+    return info
+
+
+def oracle_sample(A, k, b, budget_s, threads):
+    """Oracle stage-1 iterations on A for about budget_s seconds under a
+    BLAS thread limit; returns (seconds per product with A, iterations,
+    products, seconds, threads used)."""
+    from oracle import phsvds as ph
+    import workloads as wl
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+    except Exception:
+        threadpool_info = threadpool_limits = None
+    pmax, pmin = ph.basis_sizes(k, b)
+    X0 = wl.initial_block(A.shape[1], b, 2)
+    ctx = threadpool_limits(limits=threads) if (threadpool_limits and threads) else None
+    try:
+        used = 1
+        if threadpool_info:
+            used = max([int(i.get("num_threads", 1)) for i in threadpool_info()] + [1])
+        iters = 2
+        while True:
+            st = ph.Stats()
+            t0 = time.perf_counter()
+            ph.stage1_gdk(A, k, 1e-12, b, pmax, pmin, X0, stats=st, max_iters=iters,
+                          precond=ph.jacobi_precond_C(ph.jacobi_diag(A)))
+            t = time.perf_counter() - t0
+            if t > budget_s / 2 or iters >= 4000:
+                break
+            iters = int(iters * max(2.0, min(8.0, (budget_s / 2) / max(t, 1e-3))))
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    return t / max(st.mv_stage1, 1), st.iters1, st.mv_stage1, t, used
+
+
+def cpu_baseline_sample(A, k, b, mv_total, budget_s=16.0):
+    """The oracle (float64 NumPy/SciPy, as it stands) on a bounded sample of
+    the same workload: Jacobi-preconditioned stage-1 iterations for about
+    budget_s seconds with all host threads, and again with one; seconds per
+    product with A scaled to the GPU solve's product count."""
+    per_mv, it, mv, t, used = oracle_sample(A, k, b, budget_s, None)
+    per1, it1, mv1, t1, _ = oracle_sample(A, k, b, budget_s / 2, 1)
+    out = {"value": per_mv * mv_total, "unit": "s", "cores": used, "kind": "oracle",
+           "sample": f"oracle stage-1 GD+k with Jacobi on the same matrix in float64, first "
+                     f"{it} iterations ({mv} products with A, {t:.1f} s, {used} BLAS threads; "
+                     f"SciPy's sparse products run on one thread), seconds per product scaled "
+                     f"by the GPU solve's {mv_total} products",
+           "one_thread": {"value": per1 * mv_total, "cores": 1,
+                          "sample": f"first {it1} iterations ({mv1} products, {t1:.1f} s)"}}
+    out.update({"host": host_info()})
+    return out
+
+
+def headline(args):
+    import torch
+    import paper_1408_5535_amd as P
+    import workloads as wl
+    cfg = dict(HEADLINE)
+    cap = args.max_mv or cfg["cap"]
+    k, b = cfg["k"], cfg["b"]
+    tg = time.perf_counter()
+    A = wl.powerlaw_sparse()
+    m, n = A.shape
+    Ad = P.DeviceCSR.from_scipy(A)
+    torch.cuda.synchronize()
+    print(f"[bench] matrix {m}x{n} nnz={A.nnz} ready in {time.perf_counter() - tg:.1f}s",
+          file=sys.stderr, flush=True)
+    solver = P.Solver(Ad, k, block=b, stage1_fp32=True, fp64_continue=False,
+                      max_matvecs=cap, stage2_method="jdqmr")
+    for w in range(args.warmup):
+        tw = time.perf_counter()
+        solver.solve(cfg["tol"], precond="jacobi")
+        print(f"[bench] warmup {w} {time.perf_counter() - tw:.3f}s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    P.profile(True, kinds=["spmm_f32", "spmm_f64"], every=SPMM_SAMPLE)
+    t0 = time.perf_counter()
+    infos = []
+    for st in range(args.steps):
+        sig, U, V, info = solver.solve(cfg["tol"], precond="jacobi")
+        infos.append(info)
+        print(f"[bench] step {st} done at {time.perf_counter() - t0:.3f}s mv={info['mv_total']} "
+              f"status={info['status']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {kind: P.profile_read(kind) for kind in ("spmm_f32", "spmm_f64")}
+    P.profile(False)
+    sec = (t1 - t0) / args.steps
+    info = infos[-1]
+    an = float(info["anorm_est"])
+    res = np.asarray(info["res"]) / an
+    iters = int(info["iters1"] + info["iters2"])
+    # the dominant kernel: the float32 SpMM of stage 1 (most launches)
+    kind = max(prof, key=lambda q: prof[q][0])
+    launches, ksec, kbytes = prof[kind]
+    avg = ksec / max(launches, 1)
+    per_launch = kbytes / max(launches, 1)
+    achieved = per_launch / avg / 1e9 if avg > 0 else 0.0
+    pmax = min(64, max(35, 2 * k + 2 * b))
+    it_bytes = iteration_bytes(m, n, A.nnz, b, pmax, 4)
+    it_sec = info["t_stage1"] / max(int(info["iters1"]), 1)
+    out = {
+        "metric": METRIC,
+        "value": sec,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["label"], "m": m, "n": n, "nnz": int(A.nnz), "k": k,
+                   "block": b, "tol": cfg["tol"], "matvec_cap": cap},
+        "status": int(info["status"]),
+        "status_note": "1 = the product cap ended the solve before every pair met tol ||A||; "
+                       "value is the time of the capped solve",
+        "matvecs_per_triplet": info["mv_total"] / k,
+        "mv_total": int(info["mv_total"]),
+        "iterations": iters,
+        "pairs_at_tol": int(np.sum(res <= cfg["tol"])),
+        "best_residual_over_norm": float(res.min()),
+        "max_residual_over_norm": float(res.max()),
+        "anorm_estimate": an,
+        "sigma": [float(x) for x in sig],
+        "spmm_gbs": achieved,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profiles(f"powerlaw_b{b}_{kind}"),
+                     "kernel": f"{kind.replace('spmm_', '')} SpMM (A X and A^T Y, row-major "
+                               f"blocks of {b})",
+                     "launches": int(launches), "avg_launch_us": avg * 1e6,
+                     "timed_sample": f"one A X / A^T Y launch pair in {SPMM_SAMPLE}, "
+                                     "one event pair around both launches",
+                     "algorithmic_bytes_per_launch": per_launch},
+        "iteration_roofline": {"bytes_per_iteration": it_bytes, "seconds_per_iteration": it_sec,
+                               "achieved_gbs": it_bytes / it_sec / 1e9,
+                               "frac": it_bytes / it_sec / 1e9 / HBM_PEAK_GBS,
+                               "note": "stage-1 float32 iterations: two SpMMs, V and W streamed "
+                                       "once, eight passes over the block (fused ideal)"},
+    }
+    if not args.no_grid:
+        out["grid512"] = grid_extra(P, torch)
+        print("[bench] grid extra done", file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_sample(A, k, b, info["mv_total"])
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=512)
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--block", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["powerlaw", "grid"], default="powerlaw",
+                    help="powerlaw: the 4M x 3M headline (capped, see HEADLINE); grid: the "
+                         "N=512 grid solve as the JSON line")
+    ap.add_argument("--no-grid", action="store_true",
+                    help="skip the grid N=512 solve reported beside the headline")
     ap.add_argument("--no-largest", action="store_true",
                     help="skip the k largest solve reported beside the metric")
     ap.add_argument("--max-mv", type=int, default=0,
@@ -310,7 +566,13 @@ def main():
                     help="only run three float64 A X products on a workload of that family "
                          "(random: 300000 x 200000, 12 per row, b=4; powerlaw: 4M x 3M, b=8; "
                          "grid: --N, b=4), for counter runs")
+    ap.add_argument("--tall-probe", nargs=5, metavar=("KIND", "ROWS", "NX", "NY", "DTYPE"),
+                    help="only time a tall-skinny product: tn|nn rows nx ny f32|f64")
     args = ap.parse_args()
+    if args.tall_probe:
+        kd, r, x, y, d = args.tall_probe
+        tall_probe(kd, int(r), int(x), int(y), d)
+        return
     if args.compare:
         compare(args.compare, args.max_mv, args.gnn_weights, args.gnn_width, args.max_restarts,
                 args.arms, args.gnn_poly)
@@ -328,6 +590,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path "
               "is a design sketch, not built", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "powerlaw":
+        headline(args)
+        return
 
     import torch
     import paper_1408_5535_amd as P

@@ -198,6 +198,29 @@ int phsvds_spmm_noalloc(const phsvds_csr *A, const float *val32, int trans, int 
 int phsvds_rr_eig(const double *H, int ldh, int p, int nvec, int largest, double *theta,
                   double *S, int lds, void *stream);
 
+/* Tall-skinny products of the block iteration (Algorithm 1: the
+ * Rayleigh-Ritz border V^T W, the Gram-Schmidt coefficients [X_lock V]^T T
+ * and the CholQR Gram matrices are X^T Y; the basis updates and restarts are
+ * X S).  Long operands (rows >= 65536, ny <= 16) run on the matrix cores.
+ *   tsgemm_tn: G = X^T Y, X device rows x nx column-major (ld ldx >= rows),
+ *     Y device rows x ny, column-major with ld ldy >= rows if ycm, else
+ *     row-major with row stride ldy >= ny; G device nx x ny float64
+ *     column-major (ld ldg >= nx).  1 <= nx <= 128, 1 <= ny <= 32.  fp32:
+ *     X, Y float32, products accumulated in float32 within a block of rows
+ *     and the blocks added in float64, in a fixed order (deterministic).
+ *     ws: phsvds_tsgemm_ws_bytes() bytes of device scratch for the partials.
+ *   tsgemm_nn: Y = alpha X S + beta Y, X rows x nx column-major, S device
+ *     nx x ny float64 column-major (ld lds >= nx), Y rows x ny column-major
+ *     (ld ldy >= rows), X and Y float32 if fp32; 1 <= nx <= 160,
+ *     1 <= ny <= 64. */
+size_t phsvds_tsgemm_ws_bytes(void);
+int phsvds_tsgemm_tn(int fp32, int64_t rows, int nx, int ny, const void *X, int64_t ldx,
+                     const void *Y, int64_t ldy, int ycm, double *G, int ldg, void *ws,
+                     size_t ws_bytes, void *stream);
+int phsvds_tsgemm_nn(int fp32, int64_t rows, int nx, int ny, double alpha, const void *X,
+                     int64_t ldx, const double *S, int lds, double beta, void *Y, int64_t ldy,
+                     void *stream);
+
 /* CSR of A^T (n x m) built on the device: t_rowptr (n+1), t_colind (nnz),
  * t_val (nnz); rows of A^T come out sorted by column.  `ws` must hold
  * phsvds_transpose_ws_bytes(A) bytes.  The sort of a row of A^T with L

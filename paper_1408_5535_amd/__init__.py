@@ -218,6 +218,46 @@ def spmm_op(A: DeviceCSR, X: torch.Tensor, trans: bool = False,
     return Y
 
 
+_lib.phsvds_tsgemm_ws_bytes.restype = ctypes.c_size_t
+_lib.phsvds_tsgemm_tn.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _P,
+                                  ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int, _P,
+                                  ctypes.c_int, _P, ctypes.c_size_t, _P]
+_lib.phsvds_tsgemm_nn.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_double, _P, ctypes.c_int64, _P, ctypes.c_int,
+                                  ctypes.c_double, _P, ctypes.c_int64, _P]
+
+
+def tsgemm_tn(X: torch.Tensor, Y: torch.Tensor, y_row_major: bool = False) -> torch.Tensor:
+    """G = X^T Y (float64, nx x ny) for X (nx x rows storage: X[i] is column
+    i, i.e. a column-major rows x nx matrix) and Y given the same way (or,
+    with y_row_major, as a rows x ny row-major tensor)."""
+    fp32 = X.dtype == torch.float32
+    nx, rows = X.shape
+    if y_row_major:
+        ny, ldy, ycm = Y.shape[1], Y.stride(0), 0
+    else:
+        ny, ldy, ycm = Y.shape[0], Y.stride(0), 1
+    G = torch.empty((ny, nx), dtype=torch.float64, device=X.device)  # column-major nx x ny
+    ws = torch.empty(int(_lib.phsvds_tsgemm_ws_bytes()), dtype=torch.uint8, device=X.device)
+    _check(_lib.phsvds_tsgemm_tn(int(fp32), rows, nx, ny, X.data_ptr(), X.stride(0),
+                                 Y.data_ptr(), ldy, ycm, G.data_ptr(), nx, ws.data_ptr(),
+                                 ws.numel(), _stream()), "tsgemm_tn")
+    return G.t()
+
+
+def tsgemm_nn(X: torch.Tensor, S: torch.Tensor, Y: torch.Tensor, alpha=1.0, beta=0.0):
+    """Y = alpha X S + beta Y in place, X (nx x rows storage, column-major),
+    S (nx x ny float64), Y (ny x rows storage, column-major)."""
+    fp32 = X.dtype == torch.float32
+    nx, rows = X.shape
+    ny = Y.shape[0]
+    Sc = S.to(dtype=torch.float64).t().contiguous()  # column-major nx x ny
+    _check(_lib.phsvds_tsgemm_nn(int(fp32), rows, nx, ny, float(alpha), X.data_ptr(),
+                                 X.stride(0), Sc.data_ptr(), nx, float(beta), Y.data_ptr(),
+                                 Y.stride(0), _stream()), "tsgemm_nn")
+    return Y
+
+
 def rr_eig(H: torch.Tensor, nvec: int, largest: bool = False):
     """Selected eigenpairs of the symmetric p x p device float64 matrix H
     (p <= 64): (theta (p,), S (p x p)); theta[:nvec], S[:, :nvec] are the

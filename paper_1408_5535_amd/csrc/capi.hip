@@ -914,6 +914,58 @@ int phsvds_spmm_noalloc(const phsvds_csr *A, const float *val32, int trans, int 
   });
 }
 
+size_t phsvds_tsgemm_ws_bytes(void) { return (size_t)kPartCap * sizeof(double); }
+
+int phsvds_tsgemm_tn(int fp32, int64_t rows, int nx, int ny, const void *X, int64_t ldx,
+                     const void *Y, int64_t ldy, int ycm, double *G, int ldg, void *ws,
+                     size_t ws_bytes, void *stream) {
+  return guarded([&]() {
+    PHS_REQUIRE(X && Y && G && ws, kEinval, "null argument");
+    PHS_REQUIRE(rows >= 1 && nx >= 1 && nx <= 128 && ny >= 1 && ny <= 32, kEinval,
+                "tsgemm_tn: need rows >= 1, 1 <= nx <= 128, 1 <= ny <= 32");
+    PHS_REQUIRE(ldx >= rows && ldg >= nx && (ycm ? ldy >= rows : ldy >= ny), kEinval,
+                "tsgemm_tn: leading dimension too small");
+    PHS_REQUIRE(ws_bytes >= (size_t)kPartCap * sizeof(double), kEnomem,
+                "tsgemm_tn: workspace too small");
+    Scratch sc;
+    sc.part = (double *)ws;
+    const hipStream_t s = (hipStream_t)stream;
+    if (fp32) {
+      Tall<float> x = cm((float *)const_cast<void *>(X), rows, nx, ldx);
+      Tall<float> y = ycm ? cm((float *)const_cast<void *>(Y), rows, ny, ldy)
+                          : Tall<float>{(float *)const_cast<void *>(Y), rows, ny, ldy, 1};
+      tn(x, cm<float>(nullptr, rows, 0, rows), y, G, ldg, sc, s);
+    } else {
+      Tall<double> x = cm((double *)const_cast<void *>(X), rows, nx, ldx);
+      Tall<double> y = ycm ? cm((double *)const_cast<void *>(Y), rows, ny, ldy)
+                           : Tall<double>{(double *)const_cast<void *>(Y), rows, ny, ldy, 1};
+      tn(x, cm<double>(nullptr, rows, 0, rows), y, G, ldg, sc, s);
+    }
+    return PHSVDS_OK;
+  });
+}
+
+int phsvds_tsgemm_nn(int fp32, int64_t rows, int nx, int ny, double alpha, const void *X,
+                     int64_t ldx, const double *S, int lds, double beta, void *Y, int64_t ldy,
+                     void *stream) {
+  return guarded([&]() {
+    PHS_REQUIRE(X && S && Y, kEinval, "null argument");
+    PHS_REQUIRE(rows >= 1 && nx >= 1 && nx <= 160 && ny >= 1 && ny <= 64, kEinval,
+                "tsgemm_nn: need rows >= 1, 1 <= nx <= 160, 1 <= ny <= 64");
+    PHS_REQUIRE(ldx >= rows && ldy >= rows && lds >= nx, kEinval,
+                "tsgemm_nn: leading dimension too small");
+    const hipStream_t s = (hipStream_t)stream;
+    if (fp32) {
+      nn(cm((float *)const_cast<void *>(X), rows, nx, ldx), cm<float>(nullptr, rows, 0, rows), S,
+         lds, alpha, cm((float *)Y, rows, ny, ldy), beta, s);
+    } else {
+      nn(cm((double *)const_cast<void *>(X), rows, nx, ldx), cm<double>(nullptr, rows, 0, rows),
+         S, lds, alpha, cm((double *)Y, rows, ny, ldy), beta, s);
+    }
+    return PHSVDS_OK;
+  });
+}
+
 size_t phsvds_transpose_ws_bytes(const phsvds_csr *A) {
   if (!A) return 0;
   return transpose_ws_bytes(A->m, A->n, A->nnz);

@@ -8,6 +8,8 @@
 // second pass in float64, in a fixed order, so results are deterministic.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "prof.hpp"
@@ -213,6 +215,122 @@ void reduce_border(const TnParts &pt, double *H, int ldh, double *Z, int ldz, in
   PHS_CHECK_LAUNCH();
 }
 
+// ----------------------------------------------------- X^T Y on MFMA
+// For long operands (the basis spills out of the caches) the contraction
+// runs on the matrix cores: 16 x 16 x 4 MFMA tiles (float32 or float64),
+// wave w of a block owning columns 16w..16w+15 of X and all (<= 16) columns
+// of Y.  Rows are staged through LDS in chunks of 64: each lane loads its
+// row of the wave's 16 X columns (every load instruction a coalesced run of
+// 64 consecutive rows of one column), the block loads the Y chunk, and the
+// 16 K-steps of the chunk read their operands from LDS (row pitch 17, no
+// bank conflicts); the next chunk's global loads are issued before the
+// MFMAs of the current one.  Operand layout of the 16x16x4 instructions:
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives
+// D[r][l % 16] in accumulator v = 0..3 with r = 4 (l / 16) + v (float32) or
+// r = l / 16 + 4 v (float64).  One partial per block and entry, as k_tn
+// leaves them.
+template <typename T>
+struct Mfma16;
+template <>
+struct Mfma16<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // row of D held in accumulator v of lane l (column l % 16)
+  __device__ static int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+template <>
+struct Mfma16<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // the float64 instruction interleaves the lane groups over D's rows
+  __device__ static int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+
+constexpr int kTmRows = 64, kTmPitch = 17, kTmMaxWaves = 8;
+
+template <typename T>
+__device__ inline T tall_at(const TV<T> &x1, const TV<T> &x2, int64_t r, int i) {
+  return i < x1.cols ? x1.p[r * x1.rs + (int64_t)i * x1.cs]
+                     : x2.p[r * x2.rs + (int64_t)(i - x1.cols) * x2.cs];
+}
+
+template <typename T>
+__global__ __launch_bounds__(64 * kTmMaxWaves) void k_tn_mfma(TV<T> x1, TV<T> x2, TV<T> y,
+                                                               int64_t rpb, double *part) {
+  extern __shared__ char tm_lds[];
+  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  T *ys = reinterpret_cast<T *>(tm_lds);
+  T *xs = ys + kTmRows * kTmPitch + w * kTmRows * kTmPitch;
+  const int nx = x1.cols + x2.cols, ny = y.cols;
+  const int i0 = 16 * w;
+  const bool active = i0 < nx;
+  const int64_t N = y.rows;
+  const int64_t r0 = (int64_t)blockIdx.x * rpb;
+  const int64_t r1 = r0 + rpb < N ? r0 + rpb : N;
+  // Y chunk loads: 64 x 16 values over the block, consecutive threads on
+  // consecutive rows (column-major Y) or on consecutive columns (row-major)
+  const bool ycm = y.rs == 1;
+  const int per = (kTmRows * 16 + blockDim.x - 1) / blockDim.x;  // <= 4 (>= 256 threads)
+  T xr[16], yr[4];
+  auto load = [&](int64_t rc) {
+    const int64_t r = rc + lane;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int i = i0 + c;
+      xr[c] = (active && r < r1 && i < nx) ? tall_at(x1, x2, r, i) : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + q * (int)blockDim.x;
+      if (q < per && e < kTmRows * 16) {
+        const int rr = ycm ? e % kTmRows : e / 16, cc = ycm ? e / kTmRows : e % 16;
+        const int64_t ry = rc + rr;
+        yr[q] = (ry < r1 && cc < ny) ? y.p[ry * y.rs + (int64_t)cc * y.cs] : T(0);
+      }
+    }
+  };
+  typename Mfma16<T>::v4 acc = {T(0), T(0), T(0), T(0)};
+  if (r0 < r1) load(r0);
+  for (int64_t rc = r0; rc < r1; rc += kTmRows) {
+    __syncthreads();  // the previous chunk's operands are consumed
+#pragma unroll
+    for (int c = 0; c < 16; ++c) xs[lane * kTmPitch + c] = xr[c];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + q * (int)blockDim.x;
+      if (q < per && e < kTmRows * 16) {
+        const int rr = ycm ? e % kTmRows : e / 16, cc = ycm ? e / kTmRows : e % 16;
+        ys[rr * kTmPitch + cc] = yr[q];
+      }
+    }
+    __syncthreads();
+    if (rc + kTmRows < r1) load(rc + kTmRows);
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < kTmRows / 4; ++k) {
+        const int row = 4 * k + (lane >> 4), col = lane & 15;
+        acc = Mfma16<T>::op(xs[row * kTmPitch + col], ys[row * kTmPitch + col], acc);
+      }
+    }
+  }
+  (void)nw;
+  if (active) {
+    const int E = nx * ny, j = lane & 15;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + Mfma16<T>::row(lane, v);
+      if (i < nx && j < ny) part[(int64_t)blockIdx.x * E + i * ny + j] = (double)acc[v];
+    }
+  }
+}
+
+// Row count from which X^T Y takes the MFMA kernel.
+constexpr int64_t kTnMfmaRows = 65536;
+
 template <typename T>
 void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int ldg,
         const Scratch &sc, hipStream_t s, TnParts *keep) {
@@ -221,6 +339,37 @@ void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int l
   PHS_REQUIRE(nx <= 128 && ny <= 32, kEinval, "tn: operand too wide");
   PHS_REQUIRE(X1.rows == Y.rows && (X2.cols == 0 || X2.rows == Y.rows), kEinval,
               "tn: row counts differ");
+  static int lds_max = -1;
+  if (lds_max < 0) {
+    int dev = 0, v = 65536;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+      lds_max = v;
+    else
+      lds_max = 65536;
+  }
+  const int waves_m = std::max(4, (nx + 15) / 16);
+  const size_t shm_m = (size_t)(1 + waves_m) * kTmRows * kTmPitch * sizeof(T);
+  if (ny <= 16 && Y.rows >= kTnMfmaRows && shm_m <= (size_t)lds_max) {
+    const int64_t N = Y.rows, E = (int64_t)nx * ny;
+    const int waves = waves_m;
+    // about four blocks per compute unit, slabs a multiple of the chunk,
+    // and the partials within their buffer
+    int64_t nblk = std::min<int64_t>(1024, kPartCap / E);
+    int64_t rpb = ((N + nblk - 1) / nblk + kTmRows - 1) / kTmRows * kTmRows;
+    nblk = (N + rpb - 1) / rpb;
+    const size_t shm = shm_m;
+    prof_begin(kProfTn, s);
+    k_tn_mfma<T><<<(int)nblk, 64 * waves, shm, s>>>(tv(X1), tv(X2), tv(Y), rpb, sc.part);
+    if (keep) {
+      *keep = TnParts{sc.part, (int)nblk, nx, ny};
+    } else {
+      k_reduce_parts<<<(int)E, 64, 0, s>>>(sc.part, (int)nblk, nx, ny, G, ldg);
+    }
+    PHS_CHECK_LAUNCH();
+    prof_end(kProfTn, s, (double)Y.rows * (nx + ny) * sizeof(T));
+    return;
+  }
   const int tiles = ((nx + kTnCX - 1) / kTnCX) * ((ny + kTnCY - 1) / kTnCY);
   // fewer tiles than waves: several waves per tile (a multiple of the tiles)
   const int waves = tiles < kTnMaxWaves ? tiles * (kTnMaxWaves / tiles) : kTnMaxWaves;

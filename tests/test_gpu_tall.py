@@ -1,0 +1,85 @@
+"""Tall-skinny products of the block iteration through the C ABI
+(phsvds_tsgemm_tn / _nn): X^T Y on the matrix cores for long operands, the
+vector kernels below 65536 rows, and X S, against NumPy in float64.
+
+Inputs are drawn from U(0.5, 1.5), so every entry of the result is of the
+size of |X|^T |Y| and a wrong operand layout shows as an O(1) relative
+error; the bars are the forward-error bounds of the accumulation precision
+(float32: partial sums over a block of rows in float32, blocks in float64)."""
+import numpy as np
+import pytest
+import torch
+
+from tests.gpu_util import as_np, gpu, need_gpu, say
+
+TN_CASES = [
+    # rows, nx, ny, y row-major
+    (1000, 8, 8, True), (70000, 1, 1, False), (70000, 8, 8, True), (70000, 17, 3, False),
+    (300001, 40, 8, True), (300001, 76, 8, True), (300001, 128, 16, False),
+    (300001, 64, 16, True), (200003, 33, 24, False),
+]
+
+
+@gpu
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+@pytest.mark.parametrize("rows,nx,ny,yrm", TN_CASES)
+def test_tsgemm_tn_vs_numpy(rows, nx, ny, yrm, dtype):
+    need_gpu()
+    import paper_1408_5535_amd as P
+    rng = np.random.default_rng(rows + nx + ny)
+    X = rng.uniform(0.5, 1.5, (nx, rows))
+    Y = rng.uniform(0.5, 1.5, (rows, ny) if yrm else (ny, rows))
+    dt = torch.float32 if dtype == "float32" else torch.float64
+    Xd = torch.tensor(X, dtype=dt, device="cuda")
+    Yd = torch.tensor(Y, dtype=dt, device="cuda")
+    say("tsgemm_tn", rows, nx, ny, "row-major Y" if yrm else "column-major Y", dtype)
+    G = as_np(P.tsgemm_tn(Xd, Yd, y_row_major=yrm))
+    Xr = Xd.double().cpu().numpy()
+    Yr = Yd.double().cpu().numpy()
+    ref = Xr @ (Yr if yrm else Yr.T)
+    rel = np.max(np.abs(G - ref) / ref)
+    say("  max relative error", rel)
+    assert rel < (2e-4 if dtype == "float32" else 1e-12)
+
+
+@gpu
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_tsgemm_tn_signed_data_and_ragged_tail(dtype):
+    """Signed N(0,1) data, a tail of rows below one LDS chunk: within the
+    forward-error bound n eps |X|^T |Y| with n the rows."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    rows, nx, ny = 65536 + 37, 50, 8
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((nx, rows))
+    Y = rng.standard_normal((rows, ny))
+    dt = torch.float32 if dtype == "float32" else torch.float64
+    Xd = torch.tensor(X, dtype=dt, device="cuda")
+    Yd = torch.tensor(Y, dtype=dt, device="cuda")
+    G = as_np(P.tsgemm_tn(Xd, Yd, y_row_major=True))
+    Xr, Yr = Xd.double().cpu().numpy(), Yd.double().cpu().numpy()
+    eps = 2.0 ** -24 if dtype == "float32" else 2.0 ** -53
+    bound = np.abs(Xr) @ np.abs(Yr) * rows * eps
+    assert np.all(np.abs(G - Xr @ Yr) <= bound)
+
+
+@gpu
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+@pytest.mark.parametrize("rows,nx,ny", [(70000, 8, 8), (300001, 56, 42), (300001, 76, 8)])
+def test_tsgemm_nn_vs_numpy(rows, nx, ny, dtype):
+    need_gpu()
+    import paper_1408_5535_amd as P
+    rng = np.random.default_rng(rows + nx)
+    X = rng.uniform(0.5, 1.5, (nx, rows))
+    S = rng.uniform(0.5, 1.5, (nx, ny))
+    Y0 = rng.uniform(0.5, 1.5, (ny, rows))
+    dt = torch.float32 if dtype == "float32" else torch.float64
+    Xd = torch.tensor(X, dtype=dt, device="cuda")
+    Yd = torch.tensor(Y0, dtype=dt, device="cuda")
+    Sd = torch.tensor(S, dtype=torch.float64, device="cuda")
+    Y0r = Yd.double().cpu().numpy()
+    P.tsgemm_nn(Xd, Sd, Yd, alpha=0.75, beta=-0.5)
+    ref = 0.75 * (S.T @ Xd.double().cpu().numpy()) - 0.5 * Y0r
+    got = Yd.double().cpu().numpy()
+    scale = 0.75 * (S.T @ np.abs(Xd.double().cpu().numpy())) + 0.5 * np.abs(Y0r)
+    assert np.max(np.abs(got - ref) / scale) < (2e-6 * nx if dtype == "float32" else 1e-14 * nx)
