@@ -87,8 +87,10 @@ def summarize_pmc(path, kernel):
                           "mean_per_dispatch": sum(v) / len(v)}))
 
 
-def spmm_probe(kind, N):
-    """Three float64 SpMM launches on one matrix (rocprofv3 counter runs)."""
+def spmm_probe(kind, N, dtype="f64"):
+    """Three SpMM launch pairs A X, A^T Y on one matrix (rocprofv3 counter
+    runs), float64 or float32 values and blocks, A^T built once on the
+    device as the solver builds it."""
     import torch
     import paper_1408_5535_amd as P
     import workloads as wl
@@ -99,12 +101,20 @@ def spmm_probe(kind, N):
     else:
         A, b = wl.powerlaw_sparse(), 8
     Ad = P.DeviceCSR.from_scipy(A)
-    X = torch.randn(A.shape[1], b, dtype=torch.float64, device="cuda")
+    At = P.csr_transpose(Ad)
+    dt = torch.float32 if dtype == "f32" else torch.float64
+    X = torch.randn(A.shape[1], b, dtype=dt, device="cuda")
+    v32, t32 = (Ad.val.float(), At.val.float()) if dtype == "f32" else (None, None)
     for _ in range(3):
-        P.spmm(Ad, X)
+        Y = P.spmm(Ad, X, val32=v32)
+        P.spmm(At, Y, val32=t32)
     torch.cuda.synchronize()
-    print(json.dumps({"spmm_probe": kind, "m": A.shape[0], "n": A.shape[1], "nnz": int(A.nnz),
-                      "b": b}), flush=True)
+    s = 4 if dtype == "f32" else 8
+    m, n, nnz = A.shape[0], A.shape[1], int(A.nnz)
+    alg = [nnz * (s + 4) + (m + 1) * 8 + n * b * s + m * b * s,
+           nnz * (s + 4) + (n + 1) * 8 + m * b * s + n * b * s]
+    print(json.dumps({"spmm_probe": kind, "dtype": dtype, "m": m, "n": n, "nnz": nnz, "b": b,
+                      "algorithmic_bytes_AX_AtY": alg, "mean": sum(alg) / 2}), flush=True)
 
 
 def tall_probe(kind, rows, nx, ny, dtype, reps=10):
@@ -566,6 +576,8 @@ def main():
                     help="only run three float64 A X products on a workload of that family "
                          "(random: 300000 x 200000, 12 per row, b=4; powerlaw: 4M x 3M, b=8; "
                          "grid: --N, b=4), for counter runs")
+    ap.add_argument("--probe-dtype", choices=["f64", "f32"], default="f64",
+                    help="value and block precision of --spmm-probe")
     ap.add_argument("--tall-probe", nargs=5, metavar=("KIND", "ROWS", "NX", "NY", "DTYPE"),
                     help="only time a tall-skinny product: tn|nn rows nx ny f32|f64")
     args = ap.parse_args()
@@ -578,7 +590,7 @@ def main():
                 args.arms, args.gnn_poly)
         return
     if args.spmm_probe:
-        spmm_probe(args.spmm_probe, args.N)
+        spmm_probe(args.spmm_probe, args.N, args.probe_dtype)
         return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)

@@ -328,6 +328,20 @@ __global__ __launch_bounds__(64 * kTmMaxWaves) void k_tn_mfma(TV<T> x1, TV<T> x2
   }
 }
 
+// LDS bytes a workgroup may use on the current device (read once).
+int device_lds_max() {
+  static int lds_max = -1;
+  if (lds_max < 0) {
+    int dev = 0, v = 65536;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+      lds_max = v;
+    else
+      lds_max = 65536;
+  }
+  return lds_max;
+}
+
 // Row count from which X^T Y takes the MFMA kernel.
 constexpr int64_t kTnMfmaRows = 65536;
 
@@ -339,15 +353,7 @@ void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int l
   PHS_REQUIRE(nx <= 128 && ny <= 32, kEinval, "tn: operand too wide");
   PHS_REQUIRE(X1.rows == Y.rows && (X2.cols == 0 || X2.rows == Y.rows), kEinval,
               "tn: row counts differ");
-  static int lds_max = -1;
-  if (lds_max < 0) {
-    int dev = 0, v = 65536;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
-      lds_max = v;
-    else
-      lds_max = 65536;
-  }
+  const int lds_max = device_lds_max();
   const int waves_m = std::max(4, (nx + 15) / 16);
   const size_t shm_m = (size_t)(1 + waves_m) * kTmRows * kTmPitch * sizeof(T);
   if (ny <= 16 && Y.rows >= kTnMfmaRows && shm_m <= (size_t)lds_max) {
@@ -521,6 +527,77 @@ __global__ __launch_bounds__(NG > 0 ? 1024 : 256) void k_nn(TV<T> x1, TV<T> x2, 
   }
 }
 
+// X S on the matrix cores for long operands, computed as (X S)^T = S^T X^T
+// with 16 x 16 x 4 MFMA tiles: lane l supplies S(k0 + l/16, 16t + l%16)
+// (from LDS) and X(r0 + l%16, k0 + l/16), so each X load instruction reads
+// four runs of 16 consecutive rows, and receives (X S)(r0 + l%16, 16t + r)
+// with r the accumulator's row of D: every store instruction writes runs of
+// 16 consecutive rows of one output column.  A wave owns 16 rows at a time
+// and all NT column tiles of the output (one X operand feeds NT MFMAs);
+// eight K-steps of X loads are issued before their MFMAs.
+constexpr int kNmKU = 8;
+
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void k_nn_mfma(TV<T> x1, TV<T> x2, const double *S, int lds,
+                                                  int ny, double alpha, double beta,
+                                                  NnOut<T> o) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T *ss = reinterpret_cast<T *>(smem);  // S(k, c) at k * 16 NT + c, zero padded
+  const int nx = x1.cols + x2.cols, W = 16 * NT;
+  const int nk = (nx + 3) / 4 * 4;
+  for (int idx = threadIdx.x; idx < nk * W; idx += blockDim.x) {
+    const int k = idx / W, c = idx % W;
+    ss[idx] = (k < nx && c < ny) ? (T)S[k + (int64_t)c * lds] : T(0);
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t N = x1.cols ? x1.rows : x2.rows;
+  const int64_t ntile = (N + 15) / 16;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + w; tile < ntile; tile += (int64_t)gridDim.x * 4) {
+    const int64_t r = tile * 16 + lr;
+    const bool rin = r < N;
+    typename Mfma16<T>::v4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = typename Mfma16<T>::v4{T(0), T(0), T(0), T(0)};
+    for (int k0 = 0; k0 < nx; k0 += 4 * kNmKU) {
+      T xb[kNmKU];
+#pragma unroll
+      for (int u = 0; u < kNmKU; ++u) {
+        const int k = k0 + 4 * u + lk;
+        xb[u] = (rin && k < nx) ? tall_at(x1, x2, r, k) : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kNmKU; ++u) {
+        const int k = k0 + 4 * u + lk;
+        if (k0 + 4 * u < nk) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            acc[t] = Mfma16<T>::op(ss[k * W + 16 * t + lr], xb[u], acc[t]);
+        }
+      }
+    }
+    if (rin) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t col = 16 * t + Mfma16<T>::row(lane, v);
+          if (col < ny) {
+            T y = (T)alpha * acc[t][v];
+            if (beta != 0.0) y += (T)beta * o.z[r * o.zrs + col * o.zcs];
+            o.y[r * o.yrs + col * o.ycs] = y;
+            if (o.y2) o.y2[r * o.y2rs + col * o.y2cs] = y;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Row count from which X S (without the Gram output) takes the MFMA kernel.
+constexpr int64_t kNnMfmaRows = 65536;
+
 template <typename T>
 void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double alpha,
         const Tall<T> &Y, double beta, hipStream_t s, const Tall<T> *Z, const Tall<T> *Y2,
@@ -533,6 +610,29 @@ void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double a
   PHS_REQUIRE(!gram || (gsc && (ny == 1 || ny == 2 || ny == 4)), kEinval,
               "nn: the Gram output needs 1, 2 or 4 columns");
   if (nx == 0 && beta == 1.0 && !Z && !Y2 && !gram) return;
+  const int nt_m = (ny + 15) / 16;
+  const size_t shm_m = (size_t)((nx + 3) / 4 * 4) * 16 * nt_m * sizeof(T);
+  // (up to 16 output columns the vector kernel streams X faster: its loads
+  // are runs of 64 rows, the MFMA operand's runs of 16)
+  if (!gram && nx > 0 && ny > 16 && ny <= 64 && Y.rows >= kNnMfmaRows &&
+      shm_m <= (size_t)device_lds_max()) {
+    const int nt = nt_m;
+    const size_t shm = shm_m;
+    NnOut<T> o{Y.p, Y.rs, Y.cs, Z ? Z->p : Y.p, Z ? Z->rs : Y.rs, Z ? Z->cs : Y.cs,
+               Y2 ? Y2->p : nullptr, Y2 ? Y2->rs : 0, Y2 ? Y2->cs : 0};
+    const int64_t tiles = (Y.rows + 15) / 16;
+    const unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, 2048);
+    prof_begin(kProfNn, s);
+    switch (nt) {
+      case 1: k_nn_mfma<T, 1><<<grid, 256, shm, s>>>(tv(X1), tv(X2), S, lds, ny, alpha, beta, o); break;
+      case 2: k_nn_mfma<T, 2><<<grid, 256, shm, s>>>(tv(X1), tv(X2), S, lds, ny, alpha, beta, o); break;
+      case 3: k_nn_mfma<T, 3><<<grid, 256, shm, s>>>(tv(X1), tv(X2), S, lds, ny, alpha, beta, o); break;
+      default: k_nn_mfma<T, 4><<<grid, 256, shm, s>>>(tv(X1), tv(X2), S, lds, ny, alpha, beta, o); break;
+    }
+    PHS_CHECK_LAUNCH();
+    prof_end(kProfNn, s, (double)Y.rows * (nx + ny * (beta != 0.0 ? 2 : 1)) * sizeof(T));
+    return;
+  }
   // with the Gram partials: blocks of 1024 threads, at most 256 of them (each
   // thread then takes several rows), so that the consumer adds few partials
   // while as many waves are in flight as with 1024 blocks of 256

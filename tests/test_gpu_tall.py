@@ -65,7 +65,8 @@ def test_tsgemm_tn_signed_data_and_ragged_tail(dtype):
 
 @gpu
 @pytest.mark.parametrize("dtype", ["float32", "float64"])
-@pytest.mark.parametrize("rows,nx,ny", [(70000, 8, 8), (300001, 56, 42), (300001, 76, 8)])
+@pytest.mark.parametrize("rows,nx,ny", [(70000, 8, 8), (300001, 56, 42), (300001, 76, 8),
+                                         (65536 + 37, 64, 64), (100003, 80, 20), (99999, 5, 17)])
 def test_tsgemm_nn_vs_numpy(rows, nx, ny, dtype):
     need_gpu()
     import paper_1408_5535_amd as P
