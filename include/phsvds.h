@@ -292,8 +292,11 @@ int phsvds_gnn_adam(float *w, float *m, float *v, const double *grad, int64_t nw
 
 /* Training pairs from a float64 stage-1 run on A (k smallest, opts->block):
  * every `every` iterations, each targeted Ritz pair (theta, x) with residual
- * r gets the exact correction t of
- *   (I-QQ^T)(C - rho theta I)(I-QQ^T) t = -r,  t orthogonal to Q,
+ * r gets the exact target t of
+ *   (I-QQ^T)(C - rho theta I)(I-QQ^T) t = r,  t orthogonal to Q,
+ * i.e. t = M r for M the inverse of the projected operator: the sign of a
+ * preconditioned residual, which the network's output takes (the
+ * Jacobi-Davidson correction is -t),
  * Q = [locked vectors, Ritz block], by projected CG (relative tolerance
  * cg_tol, at most cg_maxit steps); pairs with non-positive curvature or no
  * convergence are skipped.  rho = shift_scale in [0, 1]: 1 is the
@@ -306,6 +309,17 @@ int phsvds_harvest(const phsvds_csr *A, int k, int every, int max_pairs, double 
                    double cg_tol, int cg_maxit, double shift_scale, const phsvds_opts *opts,
                    void *workspace, size_t ws_bytes, void *stream, double *R, double *X,
                    double *T, double *theta, int *count, phsvds_stats *stats);
+
+/* Values of A D^-1/2, D = diag(A^T A) (the squared column norms; a zero
+ * column keeps its values): the symmetric Jacobi scaling of C, whose
+ * largest singular value squared bounds the spectrum of the learned
+ * preconditioner's operator Ch = D^-1/2 A^T A D^-1/2.  val_out (device,
+ * nnz) in A's sparsity; `ws` holds phsvds_jacobi_ws_bytes(A) bytes (D is
+ * formed from the CSR of A^T, rows summed in column order); A is checked as
+ * for phsvds_spmm. */
+size_t phsvds_jacobi_ws_bytes(const phsvds_csr *A);
+int phsvds_jacobi_scaled_values(const phsvds_csr *A, double *val_out, void *ws, size_t ws_bytes,
+                                void *stream);
 
 /* Kernel timing for benchmarks: HIP event pairs recorded on the launching
  * stream around each operation of a kind.  Kinds: 0 float64 SpMM,

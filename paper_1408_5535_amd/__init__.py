@@ -258,6 +258,24 @@ def tsgemm_nn(X: torch.Tensor, S: torch.Tensor, Y: torch.Tensor, alpha=1.0, beta
     return Y
 
 
+_lib.phsvds_jacobi_ws_bytes.argtypes = [ctypes.POINTER(_Csr)]
+_lib.phsvds_jacobi_ws_bytes.restype = ctypes.c_size_t
+_lib.phsvds_jacobi_scaled_values.argtypes = [ctypes.POINTER(_Csr), _P, _P, ctypes.c_size_t, _P]
+
+
+def jacobi_scaled(A: DeviceCSR) -> DeviceCSR:
+    """A D^-1/2 with D = diag(A^T A), formed on the device (the operator
+    whose squared largest singular value bounds the spectrum of the learned
+    preconditioner's Ch)."""
+    c = A._c()
+    nb = int(_lib.phsvds_jacobi_ws_bytes(ctypes.byref(c)))
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=A.val.device)
+    out = torch.empty_like(A.val)
+    _check(_lib.phsvds_jacobi_scaled_values(ctypes.byref(c), out.data_ptr(), ws.data_ptr(), nb,
+                                            _stream()), "jacobi_scaled_values")
+    return DeviceCSR(A.m, A.n, A.rowptr, A.colind, out)
+
+
 def rr_eig(H: torch.Tensor, nvec: int, largest: bool = False):
     """Selected eigenpairs of the symmetric p x p device float64 matrix H
     (p <= 64): (theta (p,), S (p x p)); theta[:nvec], S[:, :nvec] are the

@@ -327,6 +327,44 @@ void spmm_op(const phsvds_csr *A, const float *val32, bool trans, bool fp32, int
   }
 }
 
+__global__ void k_scale_by_cols(int64_t nnz, const int32_t *ci, const double *va,
+                                const double *d, double *out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  const double dj = d[ci[p]];
+  out[p] = dj > 0.0 ? va[p] / sqrt(dj) : va[p];
+}
+
+void jacobi_scaled_values(const phsvds_csr *A, double *val_out, void *ws, size_t ws_bytes,
+                          hipStream_t s) {
+  PHS_REQUIRE(ws && ws_bytes >= spmm_t_ws_bytes(A->m, A->n, A->nnz, false) +
+                                    (size_t)A->n * sizeof(double) + 256,
+              kEnomem, "jacobi_scaled_values: workspace too small");
+  Arena ar;
+  ar.base = (char *)ws;
+  ar.size = ws_bytes;
+  const int64_t nz = std::max<int64_t>(A->nnz, 1);
+  int64_t *trp = ar.take<int64_t>(A->n + 1);
+  int32_t *tci = ar.take<int32_t>(nz);
+  double *tva = ar.take<double>(nz);
+  const size_t tws = transpose_ws_bytes(A->m, A->n, A->nnz);
+  char *tw = ar.take<char>(tws);
+  double *d = ar.take<double>(A->n);
+  csr_transpose(A->m, A->n, A->nnz, A->rowptr, A->colind, A->val, trp, tci, tva, tw, tws, s);
+  SpMat<double> At;
+  At.m = A->n;
+  At.n = A->m;
+  At.nnz = A->nnz;
+  At.rowptr = trp;
+  At.colind = tci;
+  At.val = tva;
+  col_sq_norms(At, d, s);
+  if (A->nnz) {
+    k_scale_by_cols<<<cdiv(A->nnz, 256), 256, 0, s>>>(A->nnz, A->colind, A->val, d, val_out);
+    PHS_CHECK_LAUNCH();
+  }
+}
+
 namespace {
 
 int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc,
@@ -891,6 +929,20 @@ int phsvds_spmm(const phsvds_csr *A, const float *val32, int trans, int fp32, in
                 const void *X, void *Y, void *ws, size_t ws_bytes, void *stream) {
   return guarded([&]() {
     spmm_op(A, val32, trans != 0, fp32 != 0, b, X, Y, ws, ws_bytes, (hipStream_t)stream, true);
+    return PHSVDS_OK;
+  });
+}
+
+size_t phsvds_jacobi_ws_bytes(const phsvds_csr *A) {
+  if (!A) return 0;
+  return spmm_t_ws_bytes(A->m, A->n, A->nnz, false) + (size_t)A->n * sizeof(double) + 256;
+}
+
+int phsvds_jacobi_scaled_values(const phsvds_csr *A, double *val_out, void *ws,
+                                size_t ws_bytes, void *stream) {
+  return guarded([&]() {
+    PHS_REQUIRE(A && val_out && A->val, kEinval, "null argument");
+    jacobi_scaled_values(A, val_out, ws, ws_bytes, (hipStream_t)stream);
     return PHSVDS_OK;
   });
 }

@@ -1,7 +1,7 @@
 // Harvest of training pairs for the learned preconditioner: stage-1 Ritz
 // blocks are snapshotted and their exact corrections computed by a batched
 // projected conjugate-gradient solve of
-//   (I - Q Q^T)(C - rho theta_j I)(I - Q Q^T) t_j = -r_j,  t_j orthogonal to Q,
+//   (I - Q Q^T)(C - rho theta_j I)(I - Q Q^T) t_j = r_j,  t_j orthogonal to Q,
 // Q = [X_lock, X_block], one column per Ritz pair with its own theta_j.
 #include <hip/hip_runtime.h>
 
@@ -110,7 +110,9 @@ std::vector<int> projected_cg_block(Ctx &c, const SpMat<double> &A, const SpMat<
     nn(Q1, Q2, G, ld, -1.0, Vv, 1.0, c.s);
   };
   {
-    std::vector<double> dn((size_t)kSP * nb, 0.0), mo(nb, -1.0);
+    // right-hand side +r: T = M r with M the inverse of the projected
+    // operator (the sign of a preconditioned residual)
+    std::vector<double> dn((size_t)kSP * nb, 0.0), mo(nb, 1.0);
     for (int j = 0; j < nb; ++j) dn[j + (size_t)j * kSP] = -shift_scale * theta[j];
     c.h2d(Dn, dn.data(), dn.size() * sizeof(double));
     c.h2d(ones, mo.data(), nb * sizeof(double));
@@ -120,7 +122,7 @@ std::vector<int> projected_cg_block(Ctx &c, const SpMat<double> &A, const SpMat<
     std::vector<int> z(128, 0);
     c.h2d(fail, z.data(), 128 * sizeof(int));
   }
-  // Res = -proj(R), T = 0, P = Res
+  // Res = proj(R), T = 0, P = Res
   copy(rmv_(const_cast<double *>(R), n, nb, bw), rmv_(cb.Res, n, nb, bw), c.s);
   proj(cb.Res);
   scale_cols(rmv_(cb.Res, n, nb, bw), ones, c.s);

@@ -72,14 +72,11 @@ def harvest_family(seeds, make, k=10, block=4, every=25, max_pairs=48, tol=1e-10
         g = GnnGraph(A, width)
         mats.append(A)
         graphs.append(g)
-        # the network is trained toward M r with M ~ (projected C)^-1 positive
-        # definite, the sign convention of the Jacobi step it starts from:
-        # the target is the harvested correction with its sign flipped (the
-        # correction equation has -r on its right-hand side; the span is
-        # the same)
+        # the harvested targets are M r with M ~ (projected C - rho theta)^-1,
+        # the sign of the Jacobi step the network starts from
         for j in range(R.shape[0]):
             pairs.append((gi, R[j].float().contiguous(), X[j].float().contiguous(), float(th[j]),
-                          (-T[j]).float().contiguous()))
+                          T[j].float().contiguous()))
         _say(f"[learned] harvest seed {seed}: {R.shape[0]} pairs, {st['mv_stage1']} products, "
              f"{time.time() - t0:.1f}s")
     return mats, graphs, pairs
@@ -87,12 +84,11 @@ def harvest_family(seeds, make, k=10, block=4, every=25, max_pairs=48, tol=1e-10
 
 def ch_norm_bound(A_host):
     """||A D^-1/2||^2 = the largest eigenvalue of Ch = D^-1/2 A^T A D^-1/2
-    (D = diag(A^T A)), from the library's largest-mode solve (k = 1)."""
-    import scipy.sparse as sp
-    from . import svds_smallest
-    d = np.asarray(A_host.multiply(A_host).sum(axis=0)).ravel()
-    B = (A_host @ sp.diags(1.0 / np.sqrt(np.maximum(d, 1e-300)))).tocsr()
-    sig, _, _, info = svds_smallest(DeviceCSR.from_scipy(B), 1, 1e-10, which="largest", block=1)
+    (D = diag(A^T A)): the scaling and the largest-mode solve (k = 1) both
+    run in the library."""
+    from . import jacobi_scaled, svds_smallest
+    B = jacobi_scaled(DeviceCSR.from_scipy(A_host))
+    sig, _, _, info = svds_smallest(B, 1, 1e-10, which="largest", block=1)
     return float(sig[0]) ** 2
 
 

@@ -1,5 +1,6 @@
 """Learned preconditioner on the GPU (float32) vs the float64 oracle:
-forward output, back-propagated gradient (<= 1e-3 relative per tensor),
+forward output (every entry within 1e-5 of the largest), back-propagated
+gradient (every entry within 1e-3 of its tensor's largest),
 Adam step; harvested pairs satisfy their correction equation; the
 preconditioned solver still returns the definition's triplets."""
 import numpy as np
@@ -42,9 +43,11 @@ def test_gnn_forward_matches_oracle(width):
     g = P.GnnGraph(to_dev(A), width)
     t = as_np(g.forward(P.gnn_pack(Pw), _dev32(r), _dev32(x), th)).astype(np.float64)
     tref, _ = pc.forward(pc.Graph(A), Pw, r, x, th)
-    err = np.linalg.norm(t - tref) / np.linalg.norm(tref)
-    say("rel err", err)
-    assert err < 1e-4
+    # element by element, against the largest entry (float32 kernels vs the
+    # float64 oracle through three layers)
+    err = np.max(np.abs(t - tref)) / np.max(np.abs(tref))
+    say("max elementwise error / max |t|", err)
+    assert err < 1e-5
 
 
 @gpu
@@ -62,7 +65,9 @@ def test_gnn_gradient_matches_oracle():
     assert abs(loss.item() - lref) <= 1e-4 * lref
     gg = P.gnn_unpack(grad, 32)
     for k in pc.NAMES:
-        err = np.linalg.norm(gg[k] - gref[k]) / max(np.linalg.norm(gref[k]), 1e-30)
+        # every entry of every weight tensor, against the tensor's largest
+        scale = max(np.max(np.abs(gref[k])), 1e-30)
+        err = np.max(np.abs(gg[k] - gref[k])) / scale
         say(k, err)
         assert err <= 1e-3, (k, err)
 
@@ -89,8 +94,8 @@ def test_gnn_adam_matches_oracle():
 @pytest.mark.parametrize("rho", [1.0, 0.0])
 def test_harvest_pairs_solve_correction_equation(rho):
     """k = 1, block 1: until the pair locks, Q = [x] exactly, so every pair
-    must satisfy (I - x x^T)((C - rho theta) t + r) = 0 with t orthogonal
-    to x."""
+    must satisfy (I - x x^T)((C - rho theta) t - r) = 0 with t orthogonal
+    to x (the target t = M r, minus the Jacobi-Davidson correction)."""
     need_gpu()
     import paper_1408_5535_amd as P
     A = wl.random_sparse(3000, 2000, 12, seed=1000)
@@ -103,7 +108,7 @@ def test_harvest_pairs_solve_correction_equation(rho):
     for i in range(len(th)):
         r, x, t = R[i], X[i], T[i]
         assert abs(np.linalg.norm(x) - 1) < 1e-12
-        v = A.T @ (A @ t) - rho * th[i] * t + r
+        v = A.T @ (A @ t) - rho * th[i] * t - r
         v -= x * (x @ v)
         assert abs(x @ t) < 1e-10 * np.linalg.norm(t)
         assert np.linalg.norm(v) < 1e-8 * np.linalg.norm(r)
@@ -182,6 +187,19 @@ def test_gnn_forward_polynomial_weights_match_oracle():
     g = P.GnnGraph(to_dev(A), 8)
     t = as_np(g.forward(P.gnn_pack(Pw), _dev32(r), _dev32(x), th)).astype(np.float64)
     tref, _ = pc.forward(pc.Graph(A), Pw, r, x, th)
-    err = np.linalg.norm(t - tref) / np.linalg.norm(tref)
-    say("poly weights rel err", err)
-    assert err < 1e-4
+    err = np.max(np.abs(t - tref)) / np.max(np.abs(tref))
+    say("poly weights max elementwise error / max |t|", err)
+    assert err < 1e-5
+
+
+@gpu
+def test_jacobi_scaled_values_match_the_definition():
+    """A D^-1/2 formed by the library: every value equals a_ij / ||A_:,j||."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A = wl.random_sparse(3000, 2000, 12, seed=1001)
+    B = P.jacobi_scaled(to_dev(A))
+    d = np.sqrt(np.asarray(A.multiply(A).sum(axis=0)).ravel())
+    ref = A.data / d[A.indices]
+    got = as_np(B.val)
+    assert np.all(np.abs(got - ref) <= 4 * 2.0 ** -53 * np.abs(ref))
