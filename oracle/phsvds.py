@@ -414,7 +414,7 @@ def _triplet_residual(x, bx, theta, n):
 
 def stage2_refined(A, shifts, v0, u0, tol, anorm, b, pmax, pmin, precondB=None,
                    max_restarts=10000, seed=17, stats: Stats | None = None, max_iters=None,
-                   method="gdk", max_inner=50, trace=None):
+                   method="gdk", max_inner=50, trace=None, best=None, extract="refined"):
     """Interior eigenpairs of B near the given shifts (Algorithm 2).
 
     ``method`` 'gdk' takes the (preconditioned) residual block as the
@@ -424,7 +424,20 @@ def stage2_refined(A, shifts, v0, u0, tol, anorm, b, pmax, pmin, precondB=None,
     (oracle.jdqmr; ``precondB`` then preconditions the inner solver) and
     expands by that one direction.  Inner products with B count as stage-2
     products.  ``trace``, if a list, receives (iteration, basis size, theta,
-    ||r||, sigma_min(R), shift) per iteration.
+    ||r||, sigma_min(R), shift) per iteration.  ``best``, if a list, receives
+    on a spent budget the approximations of the targets not locked: the
+    current refined vector of the target, then the seeds of the others.
+
+    ``extract`` 'refined' is Algorithm 2's refined projection at the
+    target's shift.  'harmonic0' is for approximations without accurate
+    shifts (the dynamic switching runs of Section 4.1, where the paper notes
+    that only accurate shifts make a harmonic procedure unnecessary):
+    harmonic Ritz pairs for the target 0, W^T W y = mu^-1 ... i.e. the pencil
+    (V^T B V, (BV)^T (BV)) with W^T W = R^T R from the QR of W, taken in
+    descending mu = 1 / theta_harm; the target is the first candidate with
+    mu > 0 and balanced halves (|2 ||x_top||^2 - 1| < 0.1), which excludes
+    the null vectors [0; w] of B that m > n brings; the shifts then only
+    order the seeds.
 
     Returns (sigma, X) with X = [v; u] unit vectors of B, in target order;
     len(sigma) < len(shifts) when the budget ran out first."""
@@ -477,12 +490,16 @@ def stage2_refined(A, shifts, v0, u0, tol, anorm, b, pmax, pmin, precondB=None,
             pend = None
         it += 1
         p = V.shape[1]
-        # R factor of W - shift V (steps 5-7; the incremental update gives the
-        # same R up to column signs), then its SVD (step 9)
-        Rf = np.linalg.qr(W - shift * V, mode="r")
-        _, sv, Yt = np.linalg.svd(Rf)
-        order = np.argsort(sv, kind="stable")
-        Ys = Yt.T[:, order]
+        if extract == "harmonic0":
+            Ys, smin = _harmonic0(V, W, H, n)
+        else:
+            # R factor of W - shift V (steps 5-7; the incremental update gives
+            # the same R up to column signs), then its SVD (step 9)
+            Rf = np.linalg.qr(W - shift * V, mode="r")
+            _, sv, Yt = np.linalg.svd(Rf)
+            order = np.argsort(sv, kind="stable")
+            Ys = Yt.T[:, order]
+            smin = float(sv[order[0]])
         y = Ys[:, 0]
         theta = float(y @ H @ y)
         x = V @ y
@@ -490,7 +507,7 @@ def stage2_refined(A, shifts, v0, u0, tol, anorm, b, pmax, pmin, precondB=None,
         r = wy - theta * x
         rn = float(np.linalg.norm(r))
         if trace is not None:
-            trace.append((it, p, theta, rn, float(sv[order[0]]), shift))
+            trace.append((it, p, theta, rn, smin, shift))
         lock = rn < thr and _triplet_residual(x, wy, theta, n) <= tol * anorm
         if lock:
             # confirm on the explicit product B x: the recurrence W y drifts
@@ -513,6 +530,10 @@ def stage2_refined(A, shifts, v0, u0, tol, anorm, b, pmax, pmin, precondB=None,
             if j >= k2:
                 break
             rest = Ys[:, 1:]
+            if extract == "harmonic0":
+                # the harmonic vectors are not orthonormal: an orthonormal
+                # basis of the complement of y, in the candidates' order
+                rest = np.linalg.qr(Ys)[0][:, 1:]
             V = V @ rest
             W = W @ rest
             H = _sym(rest.T @ H @ rest)
@@ -521,12 +542,24 @@ def stage2_refined(A, shifts, v0, u0, tol, anorm, b, pmax, pmin, precondB=None,
             prev = None
             continue
         if stats.restarts2 > max_restarts or (max_iters and it > max_iters):
+            if best is not None:
+                best.append((theta, x.copy()))
+                for jj in range(j + 1, k2):
+                    best.append((float(shifts[jj]), Y0[:, jj].copy()))
             break
         slots = [0]
         thetas = [theta]
         for c in range(1, p):
             if len(slots) >= b or c > 2 * b or method == "jdqmr":
                 break
+            if extract == "harmonic0":
+                # candidates come ordered, balanced ones first
+                yc = Ys[:, c] / np.linalg.norm(Ys[:, c])
+                xc = V @ yc
+                if abs(2.0 * float(xc[:n] @ xc[:n]) - 1.0) < 0.1:
+                    slots.append(c)
+                    thetas.append(float(yc @ H @ yc))
+                continue
             yc = Ys[:, c]
             thc = float(yc @ H @ yc)
             xc = V @ yc
@@ -553,6 +586,8 @@ def stage2_refined(A, shifts, v0, u0, tol, anorm, b, pmax, pmin, precondB=None,
             T = Rr if precondB is None else precondB(Rr, np.asarray(thetas), X)
         if p + nb > pmax:
             Yr = Ys[:, :pmin]
+            if extract == "harmonic0":
+                Yr = np.linalg.qr(Yr)[0]
             if prev is not None:
                 Yr = np.column_stack([Yr, _small_orth_against(prev, Yr)])
             V = V @ Yr
@@ -565,6 +600,29 @@ def stage2_refined(A, shifts, v0, u0, tol, anorm, b, pmax, pmin, precondB=None,
         pend = T
     stats.iters2 += it
     return np.asarray(thl), Xl
+
+
+def _harmonic0(V, W, H, n):
+    """Harmonic Ritz vectors of B for the target 0 over span(V): with
+    W = B V = Q R, the pairs of H y = mu R^T R y, i.e. the eigenpairs
+    (mu, z) of R^-T H R^-1 with y = R^-1 z; mu = 1 / theta_harm.  Returns
+    the coefficient vectors (unit columns) ordered by: balanced with mu > 0
+    first, by descending mu, then the rest by descending mu; and the
+    leading 1 / mu."""
+    import scipy.linalg as sla
+
+    p = V.shape[1]
+    R = np.linalg.qr(W, mode="r")
+    Ri = sla.solve_triangular(R, np.eye(p))
+    mu, Z = np.linalg.eigh(_sym(Ri.T @ H @ Ri))
+    Y = Ri @ Z
+    Y = Y / np.linalg.norm(Y, axis=0)
+    X = V @ Y
+    bal = np.abs(2.0 * np.einsum("ij,ij->j", X[:n], X[:n]) - 1.0) < 0.1
+    good = bal & (mu > 0)
+    order = sorted(range(p), key=lambda i: (0 if good[i] else 1, -mu[i]))
+    lead = mu[order[0]]
+    return Y[:, order], (1.0 / lead if lead != 0 else math.inf)
 
 
 # --------------------------------------------------------------------------
@@ -630,7 +688,7 @@ def _final(A, V, U, stats, AV=None):
 def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, anorm=None,
            stage2="auto", max_basis=None, min_restart=None, max_restarts=10000, floor=10.0,
            seed=2, max_iters=None, gnn_params=None, stage2_method="jdqmr", max_inner=50,
-           init_V=None, shifts=None):
+           init_V=None, shifts=None, stage2_extract="refined"):
     """k smallest (or largest) singular triplets of A by PHSVDS.
 
     Returns dict(sigma, U, V, res, stats, stage1_sigma, converged, anorm).
@@ -642,13 +700,23 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
     only if every pair locked in its last stage and every final residual
     sqrt(||r_u||^2 + ||r_v||^2) is at most tol ||A|| (Section 5).
 
+    ``precond`` may be ("inverse_A", Minv, MinvT) for a preconditioner
+    M ~ A given by its solves Minv(Y) = M^-1 Y (m rows -> n rows) and
+    MinvT(X) = M^-T X (n -> m): stage 1 takes M^-1 M^-T R, stage 2
+    [f; g] -> [M^-1 g; M^-T f] (Section 4, approx_A_forms).
+    ``precond`` may be ("B", MB) for a preconditioner of B alone,
+    MB(R, theta) -> T on (m + n) x b blocks with theta the b estimates of
+    sigma (Section 4: a preconditioner directly for B); stage 1 then runs
+    without one.
     ``precond`` may also be a callable M(R, theta) -> T, a preconditioner of
     C applied to an n x b block (theta: the b eigenvalue estimates of C):
     stage 1 takes T = M(R), stage 2 its B-form [M(A^T g); A M(f)] with theta
     the squared stage-2 estimates.  ``init_V`` (n x k0) without ``shifts``
     is the first stage's starting basis; with ``shifts`` it is saved
     first-stage output and the solve resumes at the second stage for all k
-    pairs (left vectors from resume_seeds)."""
+    pairs (left vectors from resume_seeds); ``stage2_extract`` then picks
+    the second stage's extraction ('refined' at the shifts, or 'harmonic0'
+    for estimates too rough to serve as shifts, see stage2_refined)."""
     import workloads  # seeded inputs only
 
     m, n = A.shape
@@ -660,7 +728,14 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
     if X0 is None:
         X0 = workloads.initial_block(n, b, seed)
     pc1 = pcB = fb = None
-    if callable(precond):
+    if isinstance(precond, tuple) and precond[0] == "inverse_A":
+        pc1, pcB = approx_A_forms(precond[1], precond[2], n)
+    elif isinstance(precond, tuple) and precond[0] == "B":
+        fB = precond[1]
+
+        def pcB(R, theta, X):
+            return fB(R, np.asarray(theta))
+    elif callable(precond):
         M = precond
 
         def pc1(R, theta, X):
@@ -695,7 +770,7 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
         stats.stage2_pairs = k
         th2, X2 = stage2_refined(A, sh, v0, u0, tol, an, b, pmax, pmin, pcB, max_restarts,
                                  stats=stats, max_iters=max_iters, method=stage2_method,
-                                 max_inner=max_inner)
+                                 max_inner=max_inner, extract=stage2_extract)
         got = X2.shape[1]
         V = np.column_stack([X2[:n], v0[:, got:]])
         U = np.column_stack([X2[n:], u0[:, got:]])
@@ -773,6 +848,20 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
                  and bool(np.all(res <= tol * an * (1.0 + 1e-8))))
     return {"sigma": sigma, "U": U, "V": V, "res": res, "stats": stats,
             "stage1_sigma": s1, "converged": converged, "anorm": an}
+
+
+def approx_A_forms(Minv, MinvT, n):
+    """Section 4: from M ~ A (solves with M and M^T), the preconditioner of
+    C = A^T A is M^-1 M^-T and that of B = [0 A^T; A 0] is
+    [0 M^-1; M^-T 0], i.e. [f; g] -> [M^-1 g; M^-T f] (no product with A)."""
+
+    def pc1(R, theta, X):
+        return Minv(MinvT(R))
+
+    def pcB(R, theta, X):
+        return np.vstack([Minv(R[n:]), MinvT(R[:n])])
+
+    return pc1, pcB
 
 
 def _power_norm2(A, seed, stats):
