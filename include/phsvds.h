@@ -68,18 +68,45 @@ typedef struct {
  *   the JDQMR inner solve.  A nonzero return ends the solve with
  *   PHSVDS_EUSER; the library owns R and T only for the duration of the
  *   call. */
-enum { PHSVDS_PREC_NONE = 0, PHSVDS_PREC_JACOBI = 1, PHSVDS_PREC_GNN = 2, PHSVDS_PREC_USER = 3 };
+enum {
+  PHSVDS_PREC_NONE = 0,
+  PHSVDS_PREC_JACOBI = 1,
+  PHSVDS_PREC_GNN = 2,
+  PHSVDS_PREC_USER = 3,
+  PHSVDS_PREC_USER_A = 4
+};
 
 typedef int (*phsvds_user_apply)(void *ctx, const void *R, void *T, int64_t n, int b,
                                  const double *theta, int fp64, void *stream);
+
+/* USER_A: a preconditioner M ~ A (Section 4: an incomplete LU of a square A,
+ * say) given by its solves, from which the library forms M^-1 M^-T for C in
+ * stage 1 and [0 M^-1; M^-T 0], i.e. [f; g] -> [M^-1 g; M^-T f], for B in
+ * stage 2 (no product with A):
+ *   trans = 0: Y = M^-1 X, X device m x b, Y device n x b;
+ *   trans = 1: Y = M^-T X, X device n x b, Y device m x b;
+ * column-major blocks (ld = their row count), float64 if fp64, float32 in a
+ * float32 first stage; stream as for user_apply.  A nonzero return ends the
+ * solve with PHSVDS_EUSER. */
+typedef int (*phsvds_user_solve)(void *ctx, const void *X, void *Y, int b, int trans, int fp64,
+                                 void *stream);
 
 typedef struct {
   int kind;
   const float *gnn_weights; /* device, phsvds_gnn_nweights() floats, or NULL */
   int gnn_width;            /* hidden width of the network (e.g. 32) */
   int fallback_window;      /* GNN safeguard window in iterations (0: 25; -1: never) */
-  phsvds_user_apply user_apply; /* USER: the caller's M (see above) */
-  void *user_ctx;               /* USER: passed back as the first argument */
+  phsvds_user_apply user_apply; /* USER: the caller's M of C (see above), or NULL
+                                   (stage 1 then runs without one) */
+  void *user_ctx;               /* USER, USER_A: passed back as the first argument */
+  phsvds_user_solve user_solve; /* USER_A: the solves with M ~ A (see above) */
+  /* USER: a preconditioner of B itself (Section 4 admits one "directly for
+   * B"), or NULL for the B-form of user_apply: T = M_B R with R and T device
+   * N x b column-major float64 (N = m + n, rows 0..n-1 the v part), theta
+   * the b singular value estimates; used by the second stage instead of the
+   * B-form, also inside JDQMR.  user_apply and user_apply_B may not both be
+   * NULL. */
+  phsvds_user_apply user_apply_B;
 } phsvds_precond;
 
 typedef struct {
@@ -121,6 +148,25 @@ typedef struct {
                            smallest end */
   int k0;               /* columns of init_V */
   const double *shifts; /* host, k0 singular value estimates, or NULL */
+  int dynamic;          /* 1: choose between C and B at run time (Section 4.1,
+                           Algorithm 3): short GD+k runs alternate between
+                           C (Algorithm 1's iteration) and B (harmonic Ritz
+                           vectors for the target 0, the estimates being too
+                           rough to serve as shifts), each from the other's
+                           latest approximations, and the measured mean
+                           per-iteration residual reduction decides; run
+                           lengths start at init_iter and double while the
+                           same approach wins, halve (j -> floor(j/2)) when it
+                           changes; switching stops once a pair converged in
+                           the first two runs or two later, or after
+                           max_switch switches.  C then finishes as the
+                           two-stage method from the approximations, B as
+                           GD+k on B (harmonic) without an iteration limit.
+                           Needs the smallest end, float64 (stage1_fp32 = 0),
+                           stage2_method 0, k <= p_min, no init_V and a
+                           preconditioner other than GNN */
+  int init_iter;        /* dynamic: length of the first runs (0: 50) */
+  int max_switch;       /* dynamic: switch limit (0: 8) */
 } phsvds_opts;
 
 typedef struct {
@@ -136,6 +182,13 @@ typedef struct {
   double t_setup, t_stage1, t_stage2, t_total; /* seconds (host wall clock) */
   double anorm_est;
   double res_stage1[64]; /* residual ||r_C|| of each pair on leaving stage 1 */
+  /* dynamic mode: the approach chosen (1 C, 2 B; 0 when not dynamic), how
+   * (1: a run locked all k pairs, 0: the faster one), and up to 16 runs:
+   * the approach (1 C, 2 B), the iteration limit, the pairs locked and the
+   * measured rate (mean one-step reduction factor of the residual) */
+  int64_t dyn_choice, dyn_found, dyn_runs;
+  int64_t dyn_on[16], dyn_iters[16], dyn_locked[16];
+  double dyn_rate[16];
 } phsvds_stats;
 
 /* Defaults of every field (paper parameters of Section 5). */

@@ -613,6 +613,13 @@ def _harmonic0(V, W, H, n):
 
     p = V.shape[1]
     R = np.linalg.qr(W, mode="r")
+    # a nearly singular R (B V rank-deficient) is regularised: diagonal
+    # entries below 1e-14 max|R_jj| are raised to that size, sign kept
+    d = np.diag(R).copy()
+    fl = 1e-14 * np.max(np.abs(d))
+    small = np.abs(d) < fl
+    d[small] = np.where(d[small] < 0, -fl, fl)
+    R = np.triu(R, 1) + np.diag(d)
     Ri = sla.solve_triangular(R, np.eye(p))
     mu, Z = np.linalg.eigh(_sym(Ri.T @ H @ Ri))
     Y = Ri @ Z

@@ -26,7 +26,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 PHSVDS_OK = 0
 PHSVDS_NOT_CONVERGED = 1
-PREC = {"none": 0, "jacobi": 1, "gnn": 2, "user": 3}
+PREC = {"none": 0, "jacobi": 1, "gnn": 2, "user": 3, "user_A": 4}
 PHSVDS_EUSER = -5
 
 # int (*)(void *ctx, const void *R, void *T, int64_t n, int b, const double *theta,
@@ -34,6 +34,11 @@ PHSVDS_EUSER = -5
 USER_APPLY = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                               ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                               ctypes.c_int, ctypes.c_void_p)
+
+
+# int (*)(void *ctx, const void *X, void *Y, int b, int trans, int fp64, void *stream)
+USER_SOLVE = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                              ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p)
 
 
 class _Csr(ctypes.Structure):
@@ -45,7 +50,8 @@ class _Csr(ctypes.Structure):
 class _Precond(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("gnn_weights", ctypes.c_void_p),
                 ("gnn_width", ctypes.c_int), ("fallback_window", ctypes.c_int),
-                ("user_apply", USER_APPLY), ("user_ctx", ctypes.c_void_p)]
+                ("user_apply", USER_APPLY), ("user_ctx", ctypes.c_void_p),
+                ("user_solve", USER_SOLVE), ("user_apply_B", USER_APPLY)]
 
 
 class _Opts(ctypes.Structure):
@@ -58,7 +64,8 @@ class _Opts(ctypes.Structure):
                 ("gnn_width", ctypes.c_int), ("verbose", ctypes.c_int),
                 ("stage2_method", ctypes.c_int), ("max_inner", ctypes.c_int),
                 ("init_V", ctypes.c_void_p), ("k0", ctypes.c_int),
-                ("shifts", ctypes.POINTER(ctypes.c_double))]
+                ("shifts", ctypes.POINTER(ctypes.c_double)), ("dynamic", ctypes.c_int),
+                ("init_iter", ctypes.c_int), ("max_switch", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -68,12 +75,23 @@ class _Stats(ctypes.Structure):
                  "fallbacks", "refreshes", "rollbacks", "inner2")] + \
                [(f, ctypes.c_double) for f in
                 ("t_setup", "t_stage1", "t_stage2", "t_total", "anorm_est")] + \
-               [("res_stage1", ctypes.c_double * 64)]
+               [("res_stage1", ctypes.c_double * 64)] + \
+               [(f, ctypes.c_int64) for f in ("dyn_choice", "dyn_found", "dyn_runs")] + \
+               [(f, ctypes.c_int64 * 16) for f in ("dyn_on", "dyn_iters", "dyn_locked")] + \
+               [("dyn_rate", ctypes.c_double * 16)]
+
+    _ARRAYS = ("res_stage1", "dyn_on", "dyn_iters", "dyn_locked", "dyn_rate")
 
     def as_dict(self, k):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "res_stage1"}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in self._ARRAYS}
         d["res_stage1"] = list(self.res_stage1[:k])
         d["mv_total"] = self.mv_stage1 + self.mv_rr + self.mv_stage2 + self.mv_final
+        if self.dyn_choice:
+            nr = min(self.dyn_runs, 16)
+            d["dynamic"] = {
+                "choice": "CB"[self.dyn_choice - 1], "how": "found" if self.dyn_found else "faster",
+                "runs": [("CB"[self.dyn_on[i] - 1], self.dyn_iters[i], self.dyn_rate[i],
+                          self.dyn_locked[i]) for i in range(nr)]}
         return d
 
 
@@ -306,7 +324,8 @@ def csr_transpose(A: DeviceCSR) -> DeviceCSR:
 def make_opts(which="smallest", block=1, max_basis=0, min_restart=0, stage1_fp32=False,
               fp64_continue=True, stage2="auto", max_restarts=10000, max_matvecs=0, seed=1,
               init_block=None, anorm=0.0, floor_factor=10.0, gnn_width=0, verbose=False,
-              stage2_method="jdqmr", max_inner=50, init_V=None, shifts=None):
+              stage2_method="jdqmr", max_inner=50, init_V=None, shifts=None, dynamic=False,
+              init_iter=0, max_switch=0):
     o = _Opts()
     _lib.phsvds_default_opts(ctypes.byref(o))
     o.which = {"smallest": 0, "largest": 1}[which]
@@ -330,6 +349,9 @@ def make_opts(which="smallest", block=1, max_basis=0, min_restart=0, stage1_fp32
     o.verbose = int(verbose)
     o.stage2_method = {"gdk": 0, "jdqmr": 1}[stage2_method]
     o.max_inner = max_inner
+    o.dynamic = int(dynamic)
+    o.init_iter = init_iter
+    o.max_switch = max_switch
     keep2 = None
     if init_V is not None:
         # (n x k0) tensor -> n x k0 column-major device array
@@ -363,21 +385,29 @@ class Solver:
         self.V = torch.empty((k, A.n), dtype=torch.float64, device=A.rowptr.device)
 
     def solve(self, tol=1e-12, precond="none", gnn_weights=None, gnn_width=32,
-              fallback_window=0, user_apply=None):
+              fallback_window=0, user_apply=None, user_solve=None, user_apply_B=None):
         """``user_apply(R, T, theta, fp64)`` (precond='user'): fills T = M R,
         R and T torch views (b x n, the rows are the columns of the C ABI's
         n x b column-major blocks), theta a list of b floats; a raised
-        exception makes the call return nonzero."""
+        exception makes the call return nonzero.  ``user_apply_B(R, T,
+        theta, fp64)`` (precond='user'): the same for a preconditioner of B
+        itself, views b x (m + n).  ``user_solve(X, Y, trans, fp64)``
+        (precond='user_A'): Y = M^-1 X (trans False; X b x m, Y b x n) or
+        M^-T X (trans True; X b x n, Y b x m) for M ~ A."""
         import numpy as np
         k = self.k
         sig = (ctypes.c_double * k)()
         res = (ctypes.c_double * k)()
         st = _Stats()
-        cb = USER_APPLY()
-        if precond == "user":
+        cb, cbs, cbB = USER_APPLY(), USER_SOLVE(), USER_APPLY()
+        if precond == "user" and user_apply is not None:
             cb = USER_APPLY(_user_trampoline(user_apply))
+        if precond == "user" and user_apply_B is not None:
+            cbB = USER_APPLY(_user_trampoline(user_apply_B))
+        if precond == "user_A":
+            cbs = USER_SOLVE(_solve_trampoline(user_solve, self.A.m, self.A.n))
         pc = _Precond(PREC[precond], gnn_weights.data_ptr() if gnn_weights is not None else None,
-                      gnn_width, fallback_window, cb, None)
+                      gnn_width, fallback_window, cb, None, cbs, cbB)
         c = self.A._c()
         rc = _lib.phsvds_svds(ctypes.byref(c), k, tol, ctypes.byref(pc), ctypes.byref(self.opts),
                               self.ws.data_ptr(), self.ws.numel(), _stream(), sig,
@@ -412,15 +442,31 @@ def _user_trampoline(fn):
     return call
 
 
+def _solve_trampoline(fn, m, n):
+    def call(ctx, X, Y, b, trans, fp64, stream):
+        try:
+            dt = "f8" if fp64 else "f4"
+            rin, rout = (n, m) if trans else (m, n)
+            Xt = torch.as_tensor(_DevView(X, (b, rin), dt), device="cuda")
+            Yt = torch.as_tensor(_DevView(Y, (b, rout), dt), device="cuda")
+            fn(Xt, Yt, bool(trans), bool(fp64))
+            return 0
+        except Exception:  # reported to the library as a nonzero return
+            return 1
+    return call
+
+
 def svds_smallest(A: DeviceCSR, k: int, tol: float = 1e-12, precond: str = "none",
-                  gnn_weights=None, gnn_width=32, user_apply=None, **opt_kw):
+                  gnn_weights=None, gnn_width=32, user_apply=None, user_solve=None,
+                  user_apply_B=None, **opt_kw):
     """The k smallest (``which='largest'``: largest) singular triplets of A
     to sqrt(||r_u||^2 + ||r_v||^2) <= tol ||A||.  Returns
     (sigma, U (m x k), V (n x k), info)."""
     if precond == "gnn":
         opt_kw["gnn_width"] = gnn_width
     return Solver(A, k, **opt_kw).solve(tol, precond, gnn_weights, gnn_width,
-                                        user_apply=user_apply)
+                                        user_apply=user_apply, user_solve=user_solve,
+                                        user_apply_B=user_apply_B)
 
 
 # ---------------------------------------------------------------- learned preconditioner

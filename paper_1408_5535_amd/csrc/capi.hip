@@ -76,10 +76,23 @@ struct Dims {
   int gw = 0;        // width of the learned preconditioner (0: not used)
   bool cg = false;   // harvest buffers
   bool jd = false;   // JDQMR work vectors
+  bool dyn = false;  // dynamic switching: the current approximations
   // blocks for the caller's preconditioner: always planned, since the
   // workspace size is fixed before the preconditioner is known
   bool user = true;
 };
+
+// row-major view with row stride ld
+template <typename T>
+Tall<T> rmv_(T *p, int64_t rows, int cols, int ld) {
+  Tall<T> t;
+  t.p = p;
+  t.rows = rows;
+  t.cols = cols;
+  t.rs = ld;
+  t.cs = 1;
+  return t;
+}
 
 int width_for(int b) {
   int w = 1;
@@ -105,6 +118,7 @@ bool make_dims(int64_t m, int64_t n, int64_t nnz, int k, const phsvds_opts &o, D
   d.jac = false;
   d.gw = o.gnn_width;
   d.jd = o.stage2_method == 1;
+  d.dyn = o.dynamic != 0;
   if (o.stage2_method != 0 && o.stage2_method != 1) return false;
   if (o.max_inner < 0) return false;
   if (d.gw != 0 && d.gw != 8 && d.gw != 16 && d.gw != 32) return false;
@@ -149,6 +163,7 @@ struct Plan {
   double *Vf, *Uf, *AV, *RU, *RV, *Fx, *Fy;
   double *jd;  // JDQMR work vectors
   double *ub;  // stage-2 blocks of the caller's preconditioner
+  double *dynV;  // dynamic switching: the latest approximations (n x k)
   GnnGraph gg;
   GnnBufs gb;
   CgBufs cg;
@@ -202,6 +217,7 @@ void carve(Arena &ar, const Dims &d, Plan &p) {
   p.Fy = ar.take<double>(std::max(n, m) * 8);
   p.jd = d.jd ? ar.take<double>(N * kJdVectors) : nullptr;
   p.ub = d.user ? ar.take<double>(2 * n * d.bw) : nullptr;
+  p.dynV = d.dyn ? ar.take<double>(n * d.k) : nullptr;
   if (d.gw > 0) gnn_carve(ar, m, n, nnz, d.gw, p.gg, p.gb);
   if (d.cg) carve_cg(ar, m, n, d.bw, p.cg);
 }
@@ -384,12 +400,20 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   PHS_REQUIRE(k <= n, kEinval, "k must not exceed n");
   int pkind = Pc ? Pc->kind : PHSVDS_PREC_NONE;
   PHS_REQUIRE(pkind == PHSVDS_PREC_NONE || pkind == PHSVDS_PREC_JACOBI ||
-                  pkind == PHSVDS_PREC_GNN || pkind == PHSVDS_PREC_USER,
+                  pkind == PHSVDS_PREC_GNN || pkind == PHSVDS_PREC_USER ||
+                  pkind == PHSVDS_PREC_USER_A,
               kEinval, "unsupported preconditioner kind");
-  PHS_REQUIRE(pkind != PHSVDS_PREC_USER || Pc->user_apply, kEinval,
-              "a USER preconditioner needs user_apply");
-  const bool resume = o.init_V && o.shifts;
+  PHS_REQUIRE(pkind != PHSVDS_PREC_USER || Pc->user_apply || Pc->user_apply_B, kEinval,
+              "a USER preconditioner needs user_apply or user_apply_B");
+  PHS_REQUIRE(pkind != PHSVDS_PREC_USER_A || Pc->user_solve, kEinval,
+              "a USER_A preconditioner needs user_solve");
+  bool resume = o.init_V && o.shifts;
   PHS_REQUIRE(!o.shifts || o.init_V, kEinval, "shifts need init_V");
+  PHS_REQUIRE(!o.dynamic || (o.which == 0 && !o.stage1_fp32 && o.stage2_method == 0 &&
+                             !o.init_V && pkind != PHSVDS_PREC_GNN),
+              kEinval,
+              "dynamic switching needs the smallest end, float64, stage2_method 0, no init_V "
+              "and no GNN preconditioner");
   PHS_REQUIRE(!resume || (o.k0 >= k && o.which == 0 && o.stage2 != -1), kEinval,
               "resuming the second stage needs k0 >= k, the smallest end and stage2 >= 0");
   Dims d;
@@ -398,6 +422,7 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   d.jac = pkind == PHSVDS_PREC_JACOBI || pkind == PHSVDS_PREC_GNN;
   PHS_REQUIRE(!o.init_V || resume || (o.k0 >= 1 && o.k0 <= d.pmin), kEinval,
               "init_V without shifts needs 1 <= k0 <= p_min");
+  PHS_REQUIRE(!o.dynamic || k <= d.pmin, kEinval, "dynamic switching needs k <= p_min");
   if (pkind != PHSVDS_PREC_GNN) d.gw = 0;
   if (pkind == PHSVDS_PREC_GNN) {
     PHS_REQUIRE(Pc->gnn_weights && (Pc->gnn_width == 8 || Pc->gnn_width == 16 ||
@@ -491,10 +516,210 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
     if (rc != 0)
       throw Error(PHSVDS_EUSER, "user preconditioner returned " + std::to_string(rc));
   };
-  if (pkind == PHSVDS_PREC_USER) {
-    P1.user = [&](const void *R, void *T, int nb, const double *th) {
-      user_call(R, T, nb, th, d.fp32 ? 0 : 1);
+  auto solve_call = [&](const void *X, void *Y, int nb, int trans, int fp64) {
+    const int rc = Pc->user_solve(Pc->user_ctx, X, Y, nb, trans, fp64, c.s);
+    if (rc != 0) throw Error(PHSVDS_EUSER, "user solve returned " + std::to_string(rc));
+  };
+  // stage-1 hook in the working precision fp64: M R, or M^-1 (M^-T R) for
+  // M ~ A through the m-row intermediate Ym (free while the correction is
+  // formed)
+  auto stage1_hook = [&](bool fp64, void *Ym) -> std::function<void(const void *, void *, int,
+                                                                    const double *)> {
+    if (pkind == PHSVDS_PREC_USER && Pc->user_apply)
+      return [&, fp64](const void *R, void *T, int nb, const double *th) {
+        user_call(R, T, nb, th, fp64 ? 1 : 0);
+      };
+    if (pkind == PHSVDS_PREC_USER_A)
+      return [&, fp64, Ym](const void *R, void *T, int nb, const double *) {
+        solve_call(R, Ym, nb, 1, fp64 ? 1 : 0);
+        solve_call(Ym, T, nb, 0, fp64 ? 1 : 0);
+      };
+    return nullptr;
+  };
+  P1.user = d.fp32 ? stage1_hook(false, pl.s32.Yb) : stage1_hook(true, pl.s64.Yb);
+  // stage-2 preconditioner of B on row-major N x ns blocks (row stride ldr),
+  // through the column-major scratch blocks Cb and C2b (free while the
+  // correction is formed, also inside JDQMR)
+  const int64_t Nt = m + n;
+  double *cb1 = pl.s2.Cb, *cb2 = pl.s2.C2b, *ub = pl.ub;
+  auto stage2_hook =
+      [&]() -> std::function<void(const double *, double *, int, int, const double *)> {
+    if (pkind == PHSVDS_PREC_USER && Pc->user_apply_B)
+      // the caller's own preconditioner of B
+      return [&](const double *R, double *T, int ns, int ldr, const double *th) {
+        copy(rmv_(const_cast<double *>(R), Nt, ns, ldr), cm(cb1, Nt, ns, Nt), c.s);
+        const int rc = Pc->user_apply_B(Pc->user_ctx, cb1, cb2, Nt, ns, th, 1, c.s);
+        if (rc != 0)
+          throw Error(PHSVDS_EUSER, "user B-preconditioner returned " + std::to_string(rc));
+        copy(cm(cb2, Nt, ns, Nt), rmv_(T, Nt, ns, ldr), c.s);
+      };
+    if (pkind == PHSVDS_PREC_USER)
+      // B-form of the caller's M of C: [f; g] -> [M A^T g; A M f], theta of
+      // C the squared estimates
+      return [&](const double *R, double *T, int ns, int ldr, const double *th) {
+        std::vector<double> th2(ns);
+        for (int q = 0; q < ns; ++q) th2[q] = th[q] * th[q];
+        const int64_t off = n * ns;
+        copy(rmv_(const_cast<double *>(R), n, ns, ldr), cm(ub, n, ns, n), c.s);  // f
+        user_call(ub, ub + off, ns, th2.data(), 1);                               // M f
+        copy(cm(ub + off, n, ns, n), rmv_(cb1, n, ns, ldr), c.s);
+        spmm(A64, ldr, cb1, T + n * ldr, false, c.s);                  // A M f -> bottom
+        spmm(At64, ldr, R + n * ldr, cb2, false, c.s);                 // A^T g
+        copy(rmv_(cb2, n, ns, ldr), cm(ub, n, ns, n), c.s);
+        user_call(ub, ub + off, ns, th2.data(), 1);
+        copy(cm(ub + off, n, ns, n), rmv_(T, n, ns, ldr), c.s);        // M A^T g -> top
+        stl.mv_prec += ns;
+      };
+    if (pkind == PHSVDS_PREC_USER_A)
+      // M ~ A: [f; g] -> [M^-1 g; M^-T f] (Section 4)
+      return [&](const double *R, double *T, int ns, int ldr, const double *) {
+        copy(rmv_(const_cast<double *>(R) + n * ldr, m, ns, ldr), cm(cb1, m, ns, m), c.s);
+        solve_call(cb1, cb2, ns, 0, 1);                                // M^-1 g
+        copy(cm(cb2, n, ns, n), rmv_(T, n, ns, ldr), c.s);
+        copy(rmv_(const_cast<double *>(R), n, ns, ldr), cm(cb1, n, ns, n), c.s);
+        solve_call(cb1, cb2, ns, 1, 1);                                // M^-T f
+        copy(cm(cb2, m, ns, m), rmv_(T + n * ldr, m, ns, ldr), c.s);
+      };
+    return nullptr;
+  };
+  // saved first-stage output for a second stage alone: the caller's, or
+  // the dynamic phase's when it chose B
+  const double *resume_V = o.init_V;
+  std::vector<double> resume_shifts;
+  if (resume) resume_shifts.assign(o.shifts, o.shifts + k);
+  int s2_extract = 0;
+  if (o.dynamic) {
+    // ------------------------------------ dynamic switching (Section 4.1)
+    const double an0 = o.anorm > 0 ? o.anorm
+                                   : std::sqrt(power_norm2(c, A64, At64, pl.tb.Xn, pl.tb.Ym,
+                                                           pl.tb.Z, 12, sp));
+    if (!(o.anorm > 0)) stl.mv_prec += 12;
+    P1.anorm = an0;
+    const int init_iter = o.init_iter > 0 ? o.init_iter : 50;
+    const int max_switch = o.max_switch > 0 ? o.max_switch : 8;
+    std::vector<double> sig;  // estimates of the columns of dynV, ascending
+    int ncols = 0;
+    bool first = true;
+    auto seg_rate = [](const std::vector<double> &h) {
+      double sum = 0.0;
+      int cnt = 0;
+      for (size_t i = 1; i < h.size(); ++i)
+        if (!std::isnan(h[i]) && !std::isnan(h[i - 1])) sum += h[i] - h[i - 1], ++cnt;
+      return cnt ? std::exp(sum / cnt) : 1.0;
     };
+    // dynV <- the given columns of X (ld ldx) in ascending order of |est|
+    auto take = [&](const double *X, int64_t ldx, std::vector<double> est, bool normalise) {
+      const int nc = (int)est.size();
+      std::vector<int> ord(nc);
+      std::iota(ord.begin(), ord.end(), 0);
+      for (double &e : est) e = std::fabs(e);
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int q) { return est[a] < est[q]; });
+      for (int i = 0; i < nc; ++i)
+        copy(cm(const_cast<double *>(X) + (int64_t)ord[i] * ldx, n, 1, n),
+             cm(pl.dynV + (int64_t)i * n, n, 1, n), c.s);
+      if (normalise && nc) {
+        double *nrm = sp.vec(7);
+        colnorm2(cm(pl.dynV, n, nc, n), 0, n, nrm, c.sc, c.s);
+        std::vector<double> nh(nc);
+        c.d2h(nh.data(), nrm, nc * sizeof(double));
+        c.sync();
+        for (double &x : nh) x = x > 0 ? 1.0 / std::sqrt(x) : 0.0;
+        c.h2d(sp.vec(7), nh.data(), nc * sizeof(double));
+        scale_cols(cm(pl.dynV, n, nc, n), sp.vec(7), c.s);
+      }
+      sig.assign(nc, 0.0);
+      for (int i = 0; i < nc; ++i) sig[i] = est[ord[i]];
+      ncols = nc;
+    };
+    auto run = [&](bool onB, int iters) -> std::pair<double, int> {
+      std::vector<double> h;
+      if (!onB) {
+        Stage1Params Q = P1;
+        Q.max_iters = iters;
+        Q.hist = &h;
+        Q.init64 = first ? o.init_block : pl.dynV;
+        Q.init_cols = first ? d.b : ncols;
+        Stage1Result r = run_stage1<double>(c, A64, At64, Q, pl.s64, sp);
+        stl.iters1 += r.iters;
+        stl.restarts1 += r.restarts;
+        stl.refreshes += r.refreshes;
+        stl.rollbacks += r.rollbacks;
+        std::vector<double> th(r.theta);
+        th.insert(th.end(), r.best_theta.begin(), r.best_theta.end());
+        for (double &t : th) t = std::sqrt(std::max(t, 0.0));
+        take(pl.s64.Xl, n, th, false);
+        first = false;
+        return {seg_rate(h), r.nl};
+      }
+      resume_seeds(c, A64, pl.dynV, ncols, sig, an0, d.bw, pl.tb, sp);
+      Stage2Params Q{};
+      Q.k2 = ncols;
+      Q.b = d.b;
+      Q.bw = d.bw;
+      Q.pmax = d.pmax;
+      Q.pmin = d.pmin;
+      Q.tol = tol;
+      Q.anorm = an0;
+      Q.shifts = sig.data();
+      Q.v0 = pl.tb.Vt;
+      Q.u0 = pl.tb.Ut;
+      Q.max_restarts = P1.max_restarts;
+      Q.max_iters = iters;
+      Q.jacobi_d = pkind == PHSVDS_PREC_JACOBI ? pl.diagC : nullptr;
+      Q.method = 0;
+      Q.extract = 1;
+      Q.precB = stage2_hook();
+      Q.hist = &h;
+      Stage2Result r = run_stage2(c, A64, At64, Q, pl.s2, sp);
+      stl.iters2 += r.iters;
+      stl.restarts2 += r.restarts;
+      stl.refreshes += r.refreshes;
+      std::vector<double> th(r.theta);
+      th.insert(th.end(), r.best_theta.begin(), r.best_theta.end());
+      take(r.Xl, m + n, th, true);
+      return {seg_rate(h), r.nl};
+    };
+    // Algorithm 3: first tests on C and on B, then runs of the faster one
+    double rate[2] = {1.0, 1.0};
+    int num_conv = 0, last = 0, found = -1;
+    auto record = [&](int on, int iters, std::pair<double, int> out) {
+      rate[on] = out.first;
+      num_conv += out.second;
+      if (stl.dyn_runs < 16) {
+        stl.dyn_on[stl.dyn_runs] = on + 1;
+        stl.dyn_iters[stl.dyn_runs] = iters;
+        stl.dyn_locked[stl.dyn_runs] = out.second;
+        stl.dyn_rate[stl.dyn_runs] = out.first;
+      }
+      ++stl.dyn_runs;
+      last = on;
+      if (out.second >= k) found = on;
+    };
+    record(0, init_iter, run(false, init_iter));
+    if (found < 0) record(1, init_iter, run(true, init_iter));
+    int nsw = 0, j = 0;
+    while (found < 0 && nsw < max_switch) {
+      const int choice = rate[0] <= rate[1] ? 0 : 1;
+      if ((nsw == 0 && num_conv > 0) || num_conv > 1) break;
+      j = choice == last ? j + 1 : j / 2;
+      const int iters = init_iter << std::min(j, 20);
+      ++nsw;
+      record(choice, iters, run(choice == 1, iters));
+    }
+    const int choice = found >= 0 ? found : (rate[0] <= rate[1] ? 0 : 1);
+    stl.dyn_choice = choice + 1;
+    stl.dyn_found = found >= 0 ? 1 : 0;
+    if (choice == 0) {
+      // the two-stage method from the latest approximations
+      P1.init64 = pl.dynV;
+      P1.init_cols = ncols;
+    } else {
+      // GD+k on B (harmonic) from them, as a second stage alone
+      resume = true;
+      resume_V = pl.dynV;
+      resume_shifts = sig;
+      s2_extract = 1;
+    }
   }
   if (pkind == PHSVDS_PREC_GNN && !(o.anorm > 0)) {
     // a smoothing preconditioner keeps the top of the spectrum out of the
@@ -512,14 +737,18 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
     r1.converged = true;
     r1.nl = k;
     for (int i = 0; i < k; ++i) {
-      r1.theta.push_back(o.shifts[i] * o.shifts[i]);
+      r1.theta.push_back(resume_shifts[i] * resume_shifts[i]);
       r1.res.push_back(0.0);
       r1.tight.push_back(false);
     }
-    r1.sn2 = o.anorm > 0 ? o.anorm * o.anorm
-                         : power_norm2(c, A64, At64, pl.tb.Xn, pl.tb.Ym, pl.tb.Z, 12, sp);
-    if (!(o.anorm > 0)) stl.mv_prec += 12;
-    Xl64 = o.init_V;
+    if (o.dynamic) {
+      r1.sn2 = P1.anorm * P1.anorm;
+    } else {
+      r1.sn2 = o.anorm > 0 ? o.anorm * o.anorm
+                           : power_norm2(c, A64, At64, pl.tb.Xn, pl.tb.Ym, pl.tb.Z, 12, sp);
+      if (!(o.anorm > 0)) stl.mv_prec += 12;
+    }
+    Xl64 = resume_V;
   } else {
   auto gnn32 = [&](const void *r, const void *x, double th, void *t) {
     gnn_forward(*Ain, pl.gg, pl.gb, Pc->gnn_weights, d.gw, (const float *)r, (const float *)x,
@@ -548,6 +777,7 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
         copy(cm((float *)r1.Vrest, n, extra, n), cm(init + (int64_t)r1.nl * n, n, extra, n), c.s);
       Stage1Params P2 = P1;
       if (d.gw && pkind == PHSVDS_PREC_GNN) P2.gnn = gnn64;
+      P2.user = stage1_hook(true, pl.s64.Yb);
       P2.init64 = init;
       P2.init_cols = r1.nl + extra;
       P2.sn2_init = r1.sn2;
@@ -583,7 +813,7 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   stl.t_stage1 = t2 - t1;
   const double sn = std::sqrt(r1.sn2);
   stl.anorm_est = sn;
-  const double an = o.anorm > 0 ? o.anorm : sn;
+  const double an = o.anorm > 0 ? o.anorm : (o.dynamic ? P1.anorm : sn);
   const int nl = r1.nl;
   // best approximations of the pairs not converged follow the locked ones
   const int nbest = r1.nbest, ntot = nl + nbest;
@@ -647,12 +877,8 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
     P2.max_iters = 0;
     P2.jacobi_d = pkind == PHSVDS_PREC_JACOBI ? pl.diagC : nullptr;
     P2.method = o.stage2_method;
-    if (pkind == PHSVDS_PREC_USER) {
-      P2.user = [&](const void *R, void *T, int nb, const double *th) {
-        user_call(R, T, nb, th, 1);
-      };
-      P2.ub = pl.ub;
-    }
+    P2.extract = s2_extract;
+    P2.precB = stage2_hook();
     P2.max_inner = o.max_inner > 0 ? o.max_inner : 50;
     P2.jd_work = pl.jd;
     Stage2Result r2 = run_stage2(c, A64, At64, P2, pl.s2, sp);

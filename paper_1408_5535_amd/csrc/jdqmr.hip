@@ -243,28 +243,23 @@ JdResult jd_correction(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
     double init[J_COUNT] = {};
     init[J_THETA] = in.theta;
     init[J_ETA] = in.eta;
-    init[J_PREC] = (in.jacobi_d || in.user) ? 1.0 : 0.0;
+    init[J_PREC] = (in.jacobi_d || in.precB) ? 1.0 : 0.0;
     c.h2d(sc, init, sizeof(init));
   }
-  const bool prec = in.jacobi_d != nullptr || bool(in.user);
-  const double th2 = in.eta * in.eta;
-  // z = P K g with K [f; g] = [M A^T g; A M f], M = D^-1 (the B-form Jacobi)
-  // or the caller's preconditioner of C
+  const bool prec = in.jacobi_d != nullptr || bool(in.precB);
+  // z = P K g with K the preconditioner of B: the B-form [M A^T g; A M f]
+  // of M = D^-1 (Jacobi), or the given one
   auto apply_prec = [&]() {
-    if (in.user) {
-      copy(col(p.g, n), col(in.ub, n), c.s);
-      in.user(in.ub, in.ub + n, 1, &th2);
-      spmm(A, 1, in.ub + n, p.z + n, false, c.s);  // A M f
-      spmm(At, 1, p.g + n, in.ub, false, c.s);     // A^T g
-      in.user(in.ub, in.ub + n, 1, &th2);
-      copy(col(in.ub + n, n), col(p.z, n), c.s);   // M A^T g
+    if (in.precB) {
+      const double eta = in.eta;
+      in.precB(p.g, p.z, 1, 1, &eta);
     } else {
       row_scale(p.g, in.jacobi_d, n, 1, true, p.q, c.s);  // D^-1 g_top (q is free here)
       spmm(A, 1, p.q, p.z + n, false, c.s);
       spmm(At, 1, p.g + n, p.z, false, c.s);
       row_scale(p.z, in.jacobi_d, n, 1, true, p.z, c.s);
+      c.st->mv_prec += 1;
     }
-    c.st->mv_prec += 1;
     project(c, in, p.z, N, sp);
   };
   // right-hand side -P r, then the sQMR start

@@ -22,9 +22,9 @@ struct JdInput {
   double thr = 0.0;     // outer stopping threshold on ||B x - theta x||
   int max_inner = 50;
   const double *jacobi_d = nullptr;  // diag(C) for the B-form Jacobi preconditioner
-  // or the caller's C-preconditioner in the B-form (2 n doubles in ub)
-  std::function<void(const void *, void *, int, const double *)> user;
-  double *ub = nullptr;
+  // or another preconditioner of B (Stage2Params::precB; called with one
+  // contiguous N-vector, ld 1, and theta = eta)
+  std::function<void(const double *, double *, int, int, const double *)> precB;
 };
 
 struct JdResult {

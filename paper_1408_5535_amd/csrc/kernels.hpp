@@ -202,6 +202,12 @@ void zero_rows(double *A, int lda, int r0, int r1, int nc, hipStream_t s);
 void rayleigh_small(const double *H, int ldh, int p, const double *Y, int ldy, int nc,
                     double *theta, hipStream_t s);
 
+// Ri = R^-1 for upper-triangular R (p x p, p <= 64); diagonal entries below
+// 1e-14 max|R_jj| are raised to that size (sign kept).
+void tri_inv(const double *R, int ldr, int p, double *Ri, int ldri, hipStream_t s);
+// Scale columns 0..nc-1 of Y (p rows) to unit 2-norm (zero columns stay).
+void normalize_small(double *Y, int ldy, int p, int nc, hipStream_t s);
+
 // B += alpha A (small).
 void small_add(int M, int N, double alpha, const double *A, int lda, double *B, int ldb,
                hipStream_t s);

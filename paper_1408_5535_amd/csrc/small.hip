@@ -1140,6 +1140,67 @@ void rayleigh_small(const double *H, int ldh, int p, const double *Y, int ldy, i
   PHS_CHECK_LAUNCH();
 }
 
+// Inverse of an upper-triangular R (p x p, p <= 64) by back substitution,
+// one column per thread; diagonal entries below 1e-14 max|R_jj| in size are
+// raised to that size (keeping their sign) so a nearly singular R gives a
+// large but finite inverse.
+__global__ __launch_bounds__(64) void k_tri_inv(const double *R, int ldr, int p, double *Ri,
+                                                 int ldri) {
+  __shared__ double dmax;
+  const int j = threadIdx.x;
+  if (j == 0) {
+    double mx = 0.0;
+    for (int i = 0; i < p; ++i) mx = fmax(mx, fabs(R[i + (int64_t)i * ldr]));
+    dmax = mx;
+  }
+  __syncthreads();
+  if (j >= p) return;
+  const double fl = 1e-14 * dmax;
+  auto diag = [&](int i) {
+    double d = R[i + (int64_t)i * ldr];
+    if (fabs(d) < fl) d = d < 0.0 ? -fl : fl;
+    return d;
+  };
+  double *x = Ri + (int64_t)j * ldri;
+  for (int i = p - 1; i >= 0; --i) {
+    if (i > j) {
+      x[i] = 0.0;
+      continue;
+    }
+    double sacc = (i == j) ? 1.0 : 0.0;
+    for (int l = i + 1; l <= j; ++l) sacc -= R[i + (int64_t)l * ldr] * x[l];
+    x[i] = dmax > 0.0 ? sacc / diag(i) : 0.0;
+  }
+}
+
+void tri_inv(const double *R, int ldr, int p, double *Ri, int ldri, hipStream_t s) {
+  PHS_REQUIRE(p >= 1 && p <= kSmallMax, kEinval, "tri_inv: size out of range");
+  k_tri_inv<<<1, 64, 0, s>>>(R, ldr, p, Ri, ldri);
+  PHS_CHECK_LAUNCH();
+}
+
+// Columns 0..nc-1 of Y (p rows) scaled to unit 2-norm (zero columns stay).
+__global__ void k_normalize_small(double *Y, int ldy, int p, int nc) {
+  __shared__ double red[256];
+  for (int c = 0; c < nc; ++c) {
+    double sacc = 0.0;
+    for (int i = threadIdx.x; i < p; i += blockDim.x) {
+      const double v = Y[i + (int64_t)c * ldy];
+      sacc += v * v;
+    }
+    const double tot = block_sum(sacc, red);
+    const double f = tot > 0.0 ? 1.0 / sqrt(tot) : 0.0;
+    for (int i = threadIdx.x; i < p; i += blockDim.x) Y[i + (int64_t)c * ldy] *= (tot > 0.0 ? f : 1.0);
+    __syncthreads();
+  }
+}
+
+void normalize_small(double *Y, int ldy, int p, int nc, hipStream_t s) {
+  if (nc <= 0 || p <= 0) return;
+  k_normalize_small<<<1, 256, 0, s>>>(Y, ldy, p, nc);
+  PHS_CHECK_LAUNCH();
+}
+
 }  // namespace phs
 
 namespace phs {

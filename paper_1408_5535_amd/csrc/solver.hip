@@ -235,6 +235,7 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
   int pw = 0;                 // size of the warm-start eigenvector block
   int pend_nb = 0, pend_p = 0;  // unchecked expansion: width, basis size before
   int64_t last_rebuild = -1000000;  // iteration of the last W = C V rebuild
+  int hist_nl = -1;
 
   // the two products of C X are timed as one group when profiling
   const int pkind = fp32 ? kProfSpmm32 : kProfSpmm64;
@@ -397,6 +398,12 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
                    fp32 ? " (float32)" : "", (long long)it, nl, k,
                    (long long)c.st->mv_stage1, th_h[0], std::sqrt(std::max(rn_h[0], 0.0)));
     if (P.snap) P.snap(it, bf.Xb, Rb, th_h, nb, bf.Xl, nl);
+    if (P.hist) {
+      if (hist_nl >= 0 && nl != hist_nl) P.hist->push_back(NAN);
+      hist_nl = nl;
+      const double s0 = std::sqrt(std::max(th_h[0], 1e-300));
+      P.hist->push_back(std::log(std::max(std::sqrt(std::max(rn_h[0], 0.0)) / s0, 1e-300)));
+    }
     if (P.gnn && !gnn_off && P.gnn_window > 0) {
       // safeguard of the learned preconditioner: fall back to Jacobi when the
       // leading residual has not halved within a window of iterations
@@ -745,8 +752,12 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
          *xt2 = sp.vec(15);
   int *cnt = c.sc.flag + 8;
   Stage2Result res;
-  double shift = P.shifts[0];
+  // harmonic mode: the QR is of W itself (target 0), the shifts only order
+  // the seeds
+  const bool harm = P.extract == 1;
+  double shift = harm ? 0.0 : P.shifts[0];
   bool qr_full = true;
+  int hist_nl = -1;
   int64_t last_rebuild = -1000000;  // iteration of the last W = B V rebuild
   const double thr = P.tol * P.anorm / std::sqrt(2.0);
 
@@ -867,7 +878,48 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
       cgs_cols(c, Q[cur], N, N, 0, p, Rq, ld, false, sp);
       qr_full = false;
     }
-    svdj(Rq, ld, p, p, sv, Ys, ld, c.s);
+    int nbal = 0;
+    if (harm) {
+      // harmonic Ritz vectors for the target 0: with W = Q R, the pencil
+      // H y = mu R^T R y, i.e. the eigenpairs (mu, z) of R^-T H R^-1 and
+      // y = R^-1 z (mu = 1 / theta_harm), descending in mu; candidates with
+      // mu > 0 and balanced halves, |2 ||x_top||^2 - 1| < 0.1 (B's null
+      // vectors [0; w] fail it), come first
+      double *Ri = sp.mat(18), *Mh = sp.mat(22), *Z = sp.mat(23), *Yh = sp.mat(24),
+             *Gt = sp.mat(25);
+      double *mu = sp.vec(5), *bal = sp.vec(6);
+      tri_inv(Rq, ld, p, Ri, ld, c.s);
+      small_gemm(true, false, p, p, p, 1.0, Ri, ld, H, ld, 0.0, Z, ld, c.s);
+      small_gemm(false, false, p, p, p, 1.0, Z, ld, Ri, ld, 0.0, Mh, ld, c.s);
+      syev_rr(Mh, ld, p, p, true, mu, Z, ld, c.s, false);
+      small_gemm(false, false, p, p, p, 1.0, Ri, ld, Z, ld, 0.0, Yh, ld, c.s);
+      normalize_small(Yh, ld, p, p, c.s);
+      for (int c0 = 0; c0 < p; c0 += 32) {  // Gram of the top halves, 32 columns a launch
+        const int w = std::min(32, p - c0);
+        tn(cm(V[cur], n, p, N), none<double>(n), cm(V[cur] + (int64_t)c0 * N, n, w, N),
+           Gt + (int64_t)c0 * ld, ld, c.sc, c.s);
+      }
+      rayleigh_small(Gt, ld, p, Yh, ld, p, bal, c.s);
+      std::vector<double> mu_h(p), bal_h(p);
+      c.d2h(mu_h.data(), mu, p * sizeof(double));
+      c.d2h(bal_h.data(), bal, p * sizeof(double));
+      c.sync();
+      std::vector<int> order(p);
+      std::iota(order.begin(), order.end(), 0);
+      auto good = [&](int i) { return mu_h[i] > 0.0 && std::fabs(2.0 * bal_h[i] - 1.0) < 0.1; };
+      std::stable_sort(order.begin(), order.end(), [&](int a, int q) {
+        if (good(a) != good(q)) return good(a);
+        return mu_h[a] > mu_h[q];
+      });
+      for (int i = 0; i < p; ++i) nbal += good(i) ? 1 : 0;
+      c.h2d(c.didx, order.data(), p * sizeof(int));
+      gather_cols(Yh, ld, p, c.didx, p, Ys, ld, c.s);
+      const double lead = mu_h[order[0]];
+      std::vector<double> sv0 = {lead != 0.0 ? 1.0 / lead : INFINITY};
+      c.h2d(sv, sv0.data(), sizeof(double));
+    } else {
+      svdj(Rq, ld, p, p, sv, Ys, ld, c.s);
+    }
     const int ncand = std::min(p, 2 * b + 1);
     rayleigh_small(H, ld, p, Ys, ld, ncand, thc, c.s);
     c.d2h(th_h.data(), thc, ncand * sizeof(double));
@@ -876,7 +928,7 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
     const int bsel = P.method == 1 ? 1 : b;
     std::vector<int> slots = {0};
     for (int q = 1; q < ncand && (int)slots.size() < bsel; ++q)
-      if (th_h[q] > 0.5 * shift) slots.push_back(q);
+      if (harm ? q < nbal : th_h[q] > 0.5 * shift) slots.push_back(q);
     int ns = (int)slots.size();
     std::vector<double> ths_h(ns);
     for (int q = 0; q < ns; ++q) ths_h[q] = th_h[slots[q]];
@@ -889,6 +941,11 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
     c.d2h(xt_h.data(), xt2, ns * sizeof(double));
     c.sync();
     const double r0 = std::sqrt(std::max(rn_h[0], 0.0));
+    if (P.hist) {
+      if (hist_nl >= 0 && nl != hist_nl) P.hist->push_back(NAN);
+      hist_nl = nl;
+      P.hist->push_back(std::log(std::max(r0, 1e-300)));
+    }
     if (c.verbose && it % 1000 == 0)
       std::fprintf(stderr,
                    "[phsvds] stage 2 iteration %lld: locked %d/%d, products %lld, theta %.12e, "
@@ -942,15 +999,21 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
         res.converged = true;
         break;
       }
-      // drop the locked direction: V <- V Ys(:, 1:p)
-      nn(cm(V[cur], N, p, N), none<double>(N), Ys + ld, ld, 1.0, cm(V[1 - cur], N, p - 1, N), 0.0,
+      // drop the locked direction: V <- V Ys(:, 1:p); the harmonic vectors
+      // are not orthonormal, so their orthonormal basis is taken, in order
+      double *Yo = Ys;
+      if (harm) {
+        Yo = sp.mat(26);
+        small_qr(Ys, ld, p, p, Yo, ld, sp.mat(27), ld, c.s);
+      }
+      nn(cm(V[cur], N, p, N), none<double>(N), Yo + ld, ld, 1.0, cm(V[1 - cur], N, p - 1, N), 0.0,
          c.s);
-      nn(cm(W[cur], N, p, N), none<double>(N), Ys + ld, ld, 1.0, cm(W[1 - cur], N, p - 1, N), 0.0,
+      nn(cm(W[cur], N, p, N), none<double>(N), Yo + ld, ld, 1.0, cm(W[1 - cur], N, p - 1, N), 0.0,
          c.s);
-      restart_project(H, ld, p, Ys + ld, ld, p - 1, nullptr, ld, 0, nullptr, ld, c.s);
+      restart_project(H, ld, p, Yo + ld, ld, p - 1, nullptr, ld, 0, nullptr, ld, c.s);
       cur = 1 - cur;
       p -= 1;
-      shift = P.shifts[nl];
+      if (!harm) shift = P.shifts[nl];
       // re-introduce the next initial guess (Algorithm 2 step 11)
       copy(cm(bf.Y0 + (int64_t)nl * N, N, 1, N), rmv(Tb, N, 1, bw), c.s);
       npend = 1;
@@ -961,7 +1024,18 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
     const bool out_of_budget = res.restarts > P.max_restarts ||
                                (c.max_mv > 0 && c.st->mv_stage2 > c.max_mv) ||
                                (P.max_iters > 0 && it > P.max_iters);
-    if (out_of_budget) break;
+    if (out_of_budget) {
+      // best approximations: the target's current vector, then the seeds of
+      // the targets not reached
+      copy(rmv(bf.Xb, N, 1, bw), cm(bf.Xl + (int64_t)nl * N, N, 1, N), c.s);
+      res.best_theta.push_back(ths_h[0]);
+      if (k2 - nl - 1 > 0)
+        copy(cm(bf.Y0 + (int64_t)(nl + 1) * N, N, k2 - nl - 1, N),
+             cm(bf.Xl + (int64_t)(nl + 1) * N, N, k2 - nl - 1, N), c.s);
+      for (int j = nl + 1; j < k2; ++j) res.best_theta.push_back(P.shifts[j]);
+      res.nbest = k2 - nl;
+      break;
+    }
     // balance guard for the non-target block members (B's zero and
     // negative eigenvalues must not be taken for singular values)
     std::vector<int> acc = {0};
@@ -976,6 +1050,7 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
       }
       std::vector<int> idx2(acc.size());
       for (size_t q = 0; q < acc.size(); ++q) idx2[q] = slots[acc[q]];
+      for (size_t q = 0; q < acc.size(); ++q) ths_h[q] = ths_h[acc[q]];
       c.h2d(c.didx, idx2.data(), idx2.size() * sizeof(int));
       gather_cols(Ys, ld, p, c.didx, (int)idx2.size(), Ysl, ld, c.s);
       ns = (int)acc.size();
@@ -992,23 +1067,10 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
       in.thr = thr;
       in.max_inner = P.max_inner;
       in.jacobi_d = P.jacobi_d;
-      in.user = P.user;
-      in.ub = P.ub;
+      in.precB = P.precB;
       jd_correction(c, A, At, in, P.jd_work, rmv(Tb, N, 1, bw), sp);
-    } else if (P.user) {
-      // B-form of the caller's preconditioner of C: [f; g] -> [M A^T g; A M f]
-      std::vector<double> th2(ns);
-      for (int q = 0; q < ns; ++q) th2[q] = ths_h[q] * ths_h[q];
-      const int64_t off = (int64_t)n * ns;
-      copy(rmv(Rb, n, ns, bw), cm(P.ub, n, ns, n), c.s);  // f
-      P.user(P.ub, P.ub + off, ns, th2.data());
-      copy(cm(P.ub + off, n, ns, n), rmv(bf.Cb, n, ns, bw), c.s);
-      spmm(A, bw, bf.Cb, Tb + n * bw, false, c.s);          // A M f -> bottom
-      spmm(At, bw, Rb + n * bw, bf.C2b, false, c.s);         // A^T g
-      copy(rmv(bf.C2b, n, ns, bw), cm(P.ub, n, ns, n), c.s);
-      P.user(P.ub, P.ub + off, ns, th2.data());
-      copy(cm(P.ub + off, n, ns, n), rmv(Tb, n, ns, bw), c.s);  // M A^T g -> top
-      c.st->mv_prec += ns;
+    } else if (P.precB) {
+      P.precB(Rb, Tb, ns, bw, ths_h.data());
     } else if (P.jacobi_d) {
       // B-form of the Jacobi preconditioner of C: [f; g] -> [M A^T g; A M f]
       row_scale(Rb, P.jacobi_d, n, bw, true, bf.Cb, c.s);  // M f (top rows)
@@ -1020,7 +1082,12 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
       std::swap(Tb, Rb);
     }
     if (p + ns > pmax) {
-      restart_basis(Ys, ld, p, pmin, prev, ld, nprev, Yr, ld, cnt, c.s);
+      const double *Yk = Ys;
+      if (harm) {
+        small_qr(Ys, ld, p, pmin, sp.mat(26), ld, sp.mat(27), ld, c.s);
+        Yk = sp.mat(26);
+      }
+      restart_basis(Yk, ld, p, pmin, prev, ld, nprev, Yr, ld, cnt, c.s);
       int hc = 0;
       c.d2h(&hc, cnt, sizeof(int));
       c.sync();

@@ -80,6 +80,9 @@ struct Stage1Params {
   // caller's preconditioner: T = M R, n x nb column-major blocks in working
   // precision, theta the nb Ritz values (host); null when not used
   std::function<void(const void *, void *, int, const double *)> user;
+  // optional per-iteration history of log(||r_1|| / sqrt(theta_1)) of the
+  // leading unlocked pair, NaN where it changed (a lock)
+  std::vector<double> *hist = nullptr;
 };
 
 template <typename T>
@@ -121,10 +124,15 @@ struct Stage2Params {
   int method = 0;             // 0: GD+k, 1: JDQMR (correction equation by sQMR)
   int max_inner = 50;         // JDQMR inner step cap
   double *jd_work = nullptr;  // JDQMR: kJdVectors N-vectors
-  // caller's C-preconditioner M (float64, n x nb column-major in/out,
-  // theta host), applied in the B-form [M A^T g; A M f]; null when not used
-  std::function<void(const void *, void *, int, const double *)> user;
-  double *ub = nullptr;  // 2 n bw doubles for its blocks
+  // a preconditioner of B other than Jacobi (the B-form of the caller's M
+  // of C, the form [M^-1 g; M^-T f] of M ~ A, or the caller's own M of B):
+  // T = M_B R for row-major N x ns blocks with row stride ld, theta the ns
+  // estimates of B (host); null when not used.  Also used inside JDQMR.
+  std::function<void(const double *, double *, int, int, const double *)> precB;
+  int extract = 0;  // 0: refined projection at the shifts; 1: harmonic Ritz for target 0
+  // optional per-iteration history of log ||r|| of the target, NaN where
+  // the target changed (a lock)
+  std::vector<double> *hist = nullptr;
 };
 
 struct Stage2Bufs {
@@ -137,6 +145,10 @@ struct Stage2Result {
   int64_t iters = 0, restarts = 0, refreshes = 0;
   std::vector<double> theta;
   double *Xl = nullptr;
+  // out of budget: the target's current vector, then the seeds of the
+  // targets not reached, stored in Xl after the nl locked ones
+  int nbest = 0;
+  std::vector<double> best_theta;
 };
 
 template <typename T>

@@ -68,3 +68,32 @@ def test_transposed_product_workspace():
     t32 = lib.phsvds_spmm_ws_bytes(ctypes.byref(c), 1, 1)
     # the CSR of A^T (rowptr, columns, values) at least
     assert t64 >= 201 * 8 + 3600 * 12 and t32 > t64
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof and field offsets of the option, statistics and preconditioner
+    structs as gcc lays them out from include/phsvds.h, against the ctypes
+    mirrors the binding passes."""
+    import subprocess
+
+    import paper_1408_5535_amd as P
+    checks = {"phsvds_opts": (P._Opts, ["dynamic", "max_switch", "shifts", "k0"]),
+              "phsvds_stats": (P._Stats, ["dyn_choice", "dyn_rate", "res_stage1", "inner2"]),
+              "phsvds_precond": (P._Precond, ["user_solve", "user_apply_B", "user_ctx"])}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "phsvds.h"', "int main(void) {"]
+    for st, (_, fields) in checks.items():
+        lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
+        for f in fields:
+            lines.append(f'printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    for st, (cls, fields) in checks.items():
+        assert int(got[st]) == ctypes.sizeof(cls), st
+        for f in fields:
+            assert int(got[f"{st}.{f}"]) == getattr(cls, f).offset, (st, f)

@@ -202,3 +202,116 @@ def test_initial_basis_of_k0_vectors():
     sig, U, V, info = P.svds_smallest(to_dev(A), 6, 1e-12, block=2, anorm=an, init_V=X0)
     assert info["status"] == 0
     assert np.all(np.abs(sig - cf.grid_sigmas(N)[:6]) <= 1e-10 * cf.grid_sigmas(N)[:6])
+
+
+def _scrambled_pair(sm_scale, seed=0, n=300):
+    """A = Q1 diag(s) Q2^T (s: 1e-3, 2e-3, 3e-3, then linspace(0.01, 1)) and
+    the dense M^-1 of M = Q1 diag(sm) Q2^T, sm = s with the given entries
+    scaled."""
+    rng = np.random.default_rng(seed)
+    Q1 = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    Q2 = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    s = np.concatenate([[1e-3, 2e-3, 3e-3], np.linspace(0.01, 1, n - 3)])
+    sm = s.copy()
+    for j, f in sm_scale.items():
+        sm[j] *= f
+    A = Q1 @ np.diag(s) @ Q2.T
+    return sp.csr_matrix(A), s, Q2 @ np.diag(1.0 / sm) @ Q1.T
+
+
+@gpu
+@pytest.mark.parametrize("method", ["gdk", "jdqmr"])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_user_A_preconditioner_vs_oracle(method, mixed):
+    """USER_A: solves with M ~ A (here M = A up to sigma_10 scaled by 2),
+    formed by the library into M^-1 M^-T for C and [M^-1 g; M^-T f] for B
+    (Section 4); float64, and a float32 first stage."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A, s, Mi = _scrambled_pair({10: 2.0})
+    Mi_d = torch.tensor(Mi, device="cuda")
+    calls = {"fp64": set(), "trans": set()}
+
+    def solve(X, Y, trans, fp64):
+        calls["fp64"].add(fp64)
+        calls["trans"].add(trans)
+        M = Mi_d.T if trans else Mi_d  # rows: X (b x rows_in) @ op(M)^T
+        Y.copy_((X.double() @ M.T).to(Y.dtype))
+
+    say("USER_A, scrambled n=300, method", method, "float32 stage 1", mixed)
+    sig, U, V, info = P.svds_smallest(to_dev(A), 3, 1e-12, block=1, anorm=1.0,
+                                      precond="user_A", user_solve=solve, stage2_method=method,
+                                      stage1_fp32=mixed, fp64_continue=False, stage2="force")
+    say({q: info[q] for q in ("status", "mv_total", "stage2_pairs", "iters1", "iters2")}, calls)
+    assert info["status"] == 0 and info["stage2_pairs"] == 3
+    assert calls["trans"] == {False, True}
+    assert calls["fp64"] == ({False, True} if mixed else {True})
+    assert np.all(np.abs(sig - s[:3]) <= 1e-10 * s[:3])
+    assert np.all(dense.triplet_residuals(A, sig, as_np(U), as_np(V)) <= 1e-12)
+    if not mixed:
+        out = ph.phsvds(A, 3, 1e-12, block=1, anorm=1.0, stage2="force", stage2_method=method,
+                        precond=("inverse_A", lambda Y: Mi @ Y, lambda X: Mi.T @ X))
+        assert out["converged"]
+        ratio = info["mv_total"] / out["stats"].mv_total
+        say("MV gpu/oracle", ratio)
+        assert 0.5 <= ratio <= 2.0
+
+
+@gpu
+@pytest.mark.parametrize("method", ["gdk", "jdqmr"])
+def test_user_preconditioner_of_B_directly(method):
+    """USER with user_apply_B only: no preconditioner in stage 1, the
+    caller's M_B = [0 M^-1; M^-T 0] in stage 2 (also inside JDQMR)."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A, s, Mi = _scrambled_pair({10: 2.0})
+    n = A.shape[1]
+    Mi_d = torch.tensor(Mi, device="cuda")
+    seen = []
+
+    def applyB(R, T, theta, fp64):
+        seen.append(len(theta))
+        f, g = R[:, :n], R[:, n:]
+        T[:, :n] = g @ Mi_d.T
+        T[:, n:] = f @ Mi_d
+
+    def MB(R, theta):
+        return np.vstack([Mi @ R[n:], Mi.T @ R[:n]])
+
+    say("USER direct B-preconditioner, method", method)
+    sig, U, V, info = P.svds_smallest(to_dev(A), 3, 1e-12, block=1, anorm=1.0, precond="user",
+                                      user_apply_B=applyB, stage2_method=method, stage2="force")
+    say({q: info[q] for q in ("status", "mv_total", "stage2_pairs")}, len(seen))
+    assert info["status"] == 0 and info["stage2_pairs"] == 3 and len(seen) > 0
+    assert np.all(np.abs(sig - s[:3]) <= 1e-10 * s[:3])
+    assert np.all(dense.triplet_residuals(A, sig, as_np(U), as_np(V)) <= 1e-12)
+    out = ph.phsvds(A, 3, 1e-12, block=1, anorm=1.0, stage2="force", stage2_method=method,
+                    precond=("B", MB))
+    assert out["converged"]
+    ratio = info["mv_total"] / out["stats"].mv_total
+    say("MV gpu/oracle", ratio)
+    assert 0.5 <= ratio <= 2.0
+
+
+@gpu
+def test_user_preconditioner_float64_continuation_gets_float64_blocks():
+    """A float32 first stage continued in float64: the continuation calls
+    the caller's M with float64 blocks (fp64 = 1)."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A, sigx, Ux, Vx = _givens_small()
+    D = to_dev(A)
+    d64 = torch.zeros(A.shape[1], dtype=torch.float64, device="cuda").index_add_(
+        0, D.colind.long(), D.val * D.val)
+    pairs = set()
+
+    def apply(R, T, theta, fp64):
+        pairs.add((R.dtype, fp64))
+        T.copy_(R / (d64 if fp64 else d64.float())[None, :])
+
+    sig, U, V, info = P.svds_smallest(D, 3, 1e-12, block=1, anorm=1.0, precond="user",
+                                      user_apply=apply, stage1_fp32=True, fp64_continue=True)
+    say(info["status"], pairs)
+    assert info["status"] == 0
+    assert pairs == {(torch.float32, False), (torch.float64, True)}
+    assert np.all(np.abs(sig - sigx[:3]) <= 1e-10 * sigx[:3])
