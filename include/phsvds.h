@@ -167,6 +167,20 @@ typedef struct {
                            preconditioner other than GNN */
   int init_iter;        /* dynamic: length of the first runs (0: 50) */
   int max_switch;       /* dynamic: switch limit (0: 8) */
+  /* The caller's operator in place of C = A^T A in the first stage (Section
+   * 3.3 accepts a function for C): Y = C X, or with c_inverse Y = C^-1 X
+   * (shift-invert, Section 4: the largest eigenvalues mu of C^-1 give
+   * sigma = mu^-1/2), on row-major n x b device blocks (b the padded block
+   * width), float64, work on `stream`; NULL: C X = A^T (A X).  The
+   * transition, the second stage and the final check still use A.  With
+   * c_inverse the first stage locks on ||C^-1 x - mu x|| < tol sqrt(mu) /
+   * ||A||, the image of its test on C, with ||A|| = anorm or twelve power
+   * steps on A^T A; it needs the smallest end and no preconditioner.  With
+   * either, stage1_fp32 and dynamic must be 0.  A nonzero return ends the
+   * solve with PHSVDS_EUSER. */
+  int (*c_apply)(void *ctx, const void *X, void *Y, int b, int fp64, void *stream);
+  void *c_ctx;
+  int c_inverse;
 } phsvds_opts;
 
 typedef struct {
@@ -190,6 +204,24 @@ typedef struct {
   int64_t dyn_on[16], dyn_iters[16], dyn_locked[16];
   double dyn_rate[16];
 } phsvds_stats;
+
+/* The caller's operator in place of a CSR A (Section 3.3 accepts a matrix
+ * function for the products with A and A^T):
+ *   trans = 0: Y = A X, X device n x b, Y device m x b;
+ *   trans = 1: Y = A^T X, X device m x b, Y device n x b;
+ * row-major blocks (element (i, j) at X[i * b + j]) with b the block width
+ * padded to a power of two (extra columns are products like the others),
+ * float64 (fp64 is always 1: the first stage cannot run in float32 with an
+ * operator).  Work goes on `stream` (the call may also synchronise); the
+ * library owns X and Y only for the duration of the call.  A nonzero
+ * return ends the solve with PHSVDS_EUSER. */
+typedef int (*phsvds_op_apply)(void *ctx, const void *X, void *Y, int b, int trans, int fp64,
+                               void *stream);
+typedef struct {
+  int64_t m, n; /* m >= n */
+  phsvds_op_apply apply;
+  void *ctx;    /* passed back as the first argument */
+} phsvds_operator;
 
 /* Defaults of every field (paper parameters of Section 5). */
 void phsvds_default_opts(phsvds_opts *opts);
@@ -305,6 +337,16 @@ int phsvds_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int k, const phsvd
 int phsvds_svds(const phsvds_csr *A, int k, double tol, const phsvds_precond *P,
                 const phsvds_opts *opts, void *workspace, size_t ws_bytes, void *stream,
                 double *sigma, double *U, double *V, double *resnorm, phsvds_stats *stats);
+
+/* phsvds_svds with the caller's operator for A instead of a CSR (Section
+ * 3.3): every product with A and A^T of both stages, the transition and the
+ * final check goes through A->apply.  Workspace: phsvds_workspace_bytes(
+ * A->m, A->n, 0, k, opts).  Preconditioners NONE, USER and USER_A (JACOBI
+ * and GNN need the entries of A) and float64 only (stage1_fp32 = 1);
+ * otherwise PHSVDS_EINVAL. */
+int phsvds_svds_op(const phsvds_operator *A, int k, double tol, const phsvds_precond *P,
+                   const phsvds_opts *opts, void *workspace, size_t ws_bytes, void *hip_stream,
+                   double *sigma, double *U, double *V, double *resnorm, phsvds_stats *stats);
 
 /* ---- Learned preconditioner (message-passing network over the graph of
  * C = A^T A, float32).  Not in the paper: a preconditioner for C of the kind

@@ -201,12 +201,17 @@ def _pad(Sc, rows):
 # --------------------------------------------------------------------------
 def stage1_gdk(A, k, tol, b, pmax, pmin, X0, which="smallest", precond=None, anorm=None,
                max_restarts=10000, floor=10.0, eps=EPS64, seed=11, stats: Stats | None = None,
-               max_iters=None, callback=None, fallback=None, fallback_window=25, sn2_init=0.0):
+               max_iters=None, callback=None, fallback=None, fallback_window=25, sn2_init=0.0,
+               c_apply=None, si_anorm=None):
     """Block GD+k on C for k extreme eigenpairs (Sections 2.2, 2.4, 3.1).
 
     ``precond(R, theta, X) -> T`` maps the residual block to the correction
     block (None: T = R).  ``callback(it, X, R, theta, X_lock)`` sees every
-    iteration's Ritz block (used to harvest training pairs).  With a
+    iteration's Ritz block (used to harvest training pairs).  ``c_apply``
+    replaces the product with C by the caller's operator (C itself, or C^-1
+    for shift-invert; then ``si_anorm`` = ||A|| sets the test
+    ||C^-1 x - mu x|| < delta sqrt(mu) / ||A||, the image of the test on C,
+    since C r' = -mu r_C for r' = C^-1 x - mu x).  With a
     ``fallback`` preconditioner, ``precond`` is replaced by it for the rest
     of the run when the leading residual has not halved within a window of
     ``fallback_window`` iterations (the learned preconditioner's safeguard).  Returns (X_lock, theta_lock, V_rest, s_n^2, info)
@@ -217,6 +222,8 @@ def stage1_gdk(A, k, tol, b, pmax, pmin, X0, which="smallest", precond=None, ano
 
     def Cop(X):
         stats.mv_stage1 += X.shape[1]
+        if c_apply is not None:
+            return c_apply(X)
         return A.T @ (A @ X)
 
     V = orth_block(X0, [], rnd)
@@ -256,15 +263,17 @@ def stage1_gdk(A, k, tol, b, pmax, pmin, X0, which="smallest", precond=None, ano
                 stats.fallback = True
         need = k - len(thl)
 
-        def thr_of(i):
+        def rel_of(i):
             si = math.sqrt(max(theta[i], 0.0))
-            return max(tol * si * sn, floor * eps * sn2)
+            return tol * si / si_anorm if si_anorm else tol * si * sn
+
+        def thr_of(i):
+            return max(rel_of(i), floor * eps * sn2)
 
         conv = [i for i in range(min(nb, need)) if rn[i] < thr_of(i)]
         stag = None
         # floor-limited stagnation acceptance for the leading target
-        si0 = math.sqrt(max(theta[0], 0.0))
-        if not conv and need > 0 and tol * si0 * sn < floor * eps * sn2:
+        if not conv and need > 0 and rel_of(0) < floor * eps * sn2:
             hist.append(rn[0])
             if len(hist) > 2 * L and rn[0] < 10.0 * floor * eps * sn2:
                 if min(hist[-L:]) > 0.9 * min(hist[:-L]):
@@ -695,7 +704,7 @@ def _final(A, V, U, stats, AV=None):
 def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, anorm=None,
            stage2="auto", max_basis=None, min_restart=None, max_restarts=10000, floor=10.0,
            seed=2, max_iters=None, gnn_params=None, stage2_method="jdqmr", max_inner=50,
-           init_V=None, shifts=None, stage2_extract="refined"):
+           init_V=None, shifts=None, stage2_extract="refined", c_apply=None, c_inverse=False):
     """k smallest (or largest) singular triplets of A by PHSVDS.
 
     Returns dict(sigma, U, V, res, stats, stage1_sigma, converged, anorm).
@@ -723,7 +732,13 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
     first-stage output and the solve resumes at the second stage for all k
     pairs (left vectors from resume_seeds); ``stage2_extract`` then picks
     the second stage's extraction ('refined' at the shifts, or 'harmonic0'
-    for estimates too rough to serve as shifts, see stage2_refined)."""
+    for estimates too rough to serve as shifts, see stage2_refined).
+
+    ``c_apply(X)`` replaces the first stage's products with C by the
+    caller's operator: C itself, or with ``c_inverse`` C^-1 (shift-invert,
+    Section 4: the largest eigenvalues mu of C^-1 give sigma = mu^-1/2);
+    the transition, the second stage and the final check still use A.  In
+    shift-invert mode ||A|| is the given anorm or twelve power steps on C."""
     import workloads  # seeded inputs only
 
     m, n = A.shape
@@ -802,11 +817,25 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
         # the top of the spectrum: start the ||A||^2 estimate from twelve
         # steps of power iteration on C (a lower bound)
         sn2_init = _power_norm2(A, seed, stats)
-    Xl, thl, Vr, sn2, info = stage1_gdk(A, k, tol, b, pmax, pmin, X0, which, pc1, anorm,
-                                        max_restarts, floor, EPS64, stats=stats,
-                                        max_iters=max_iters,
-                                        fallback=fb if precond == "gnn" else None,
-                                        sn2_init=sn2_init)
+    if c_inverse:
+        if c_apply is None or which != "smallest" or pc1 is not None:
+            raise ValueError("shift-invert needs c_apply, the smallest end and no preconditioner")
+        sn2 = float(anorm) ** 2 if anorm else _power_norm2(A, seed, stats)
+        Xl, thl, Vr, _, info = stage1_gdk(A, k, tol, b, pmax, pmin, X0, "largest", None, None,
+                                          max_restarts, floor, EPS64, stats=stats,
+                                          max_iters=max_iters, c_apply=c_apply,
+                                          si_anorm=math.sqrt(sn2))
+        # eigenvalues mu of C^-1 -> theta = 1 / mu of C, ascending
+        thl = 1.0 / np.asarray(thl)[::-1]
+        Xl = Xl[:, ::-1]
+        bth, bX = info["best"]
+        info["best"] = (1.0 / bth if bth.size else bth, bX)
+    else:
+        Xl, thl, Vr, sn2, info = stage1_gdk(A, k, tol, b, pmax, pmin, X0, which, pc1, anorm,
+                                            max_restarts, floor, EPS64, stats=stats,
+                                            max_iters=max_iters,
+                                            fallback=fb if precond == "gnn" else None,
+                                            sn2_init=sn2_init, c_apply=c_apply)
     sn = math.sqrt(sn2)
     stats.anorm_est = sn
     an = float(anorm) if anorm else sn

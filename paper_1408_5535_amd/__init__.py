@@ -54,6 +54,11 @@ class _Precond(ctypes.Structure):
                 ("user_solve", USER_SOLVE), ("user_apply_B", USER_APPLY)]
 
 
+# int (*)(void *ctx, const void *X, void *Y, int b, int fp64, void *stream)
+C_APPLY = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                           ctypes.c_int, ctypes.c_int, ctypes.c_void_p)
+
+
 class _Opts(ctypes.Structure):
     _fields_ = [("which", ctypes.c_int), ("block", ctypes.c_int), ("max_basis", ctypes.c_int),
                 ("min_restart", ctypes.c_int), ("stage1_fp32", ctypes.c_int),
@@ -65,7 +70,8 @@ class _Opts(ctypes.Structure):
                 ("stage2_method", ctypes.c_int), ("max_inner", ctypes.c_int),
                 ("init_V", ctypes.c_void_p), ("k0", ctypes.c_int),
                 ("shifts", ctypes.POINTER(ctypes.c_double)), ("dynamic", ctypes.c_int),
-                ("init_iter", ctypes.c_int), ("max_switch", ctypes.c_int)]
+                ("init_iter", ctypes.c_int), ("max_switch", ctypes.c_int),
+                ("c_apply", C_APPLY), ("c_ctx", ctypes.c_void_p), ("c_inverse", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -112,6 +118,19 @@ _lib.phsvds_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c
 _lib.phsvds_svds.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, ctypes.c_double,
                              ctypes.POINTER(_Precond), ctypes.POINTER(_Opts), _P, ctypes.c_size_t,
                              _P, _P, _P, _P, _P, ctypes.POINTER(_Stats)]
+# int (*)(void *ctx, const void *X, void *Y, int b, int trans, int fp64, void *stream)
+OP_APPLY = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p)
+
+
+class _Operator(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("apply", OP_APPLY),
+                ("ctx", ctypes.c_void_p)]
+
+
+_lib.phsvds_svds_op.argtypes = [ctypes.POINTER(_Operator), ctypes.c_int, ctypes.c_double,
+                                ctypes.POINTER(_Precond), ctypes.POINTER(_Opts), _P,
+                                ctypes.c_size_t, _P, _P, _P, _P, _P, ctypes.POINTER(_Stats)]
 
 
 _lib.phsvds_profile.argtypes = [ctypes.c_int]
@@ -158,6 +177,33 @@ def _check(rc, what):
 
 def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Operator:
+    """A given by its products (Section 3.3): ``apply(X, Y, trans)`` fills
+    Y = A X (trans False; X n x b, Y m x b) or A^T X (trans True; X m x b,
+    Y n x b), torch float64 views of the library's row-major blocks."""
+
+    nnz = 0
+
+    def __init__(self, m, n, apply):
+        self.m, self.n, self.apply = int(m), int(n), apply
+        self.rowptr = torch.empty(0, device="cuda")  # device of the workspace
+
+    def _c(self):
+        m, n, fn = self.m, self.n, self.apply
+
+        def call(ctx, X, Y, b, trans, fp64, stream):
+            try:
+                rin, rout = (m, n) if trans else (n, m)
+                Xt = torch.as_tensor(_DevView(X, (rin, b), "f8"), device="cuda")
+                Yt = torch.as_tensor(_DevView(Y, (rout, b), "f8"), device="cuda")
+                fn(Xt, Yt, bool(trans))
+                return 0
+            except Exception:  # reported to the library as a nonzero return
+                return 1
+        self._cb = OP_APPLY(call)
+        return _Operator(m, n, self._cb, None)
 
 
 @dataclass
@@ -325,7 +371,10 @@ def make_opts(which="smallest", block=1, max_basis=0, min_restart=0, stage1_fp32
               fp64_continue=True, stage2="auto", max_restarts=10000, max_matvecs=0, seed=1,
               init_block=None, anorm=0.0, floor_factor=10.0, gnn_width=0, verbose=False,
               stage2_method="jdqmr", max_inner=50, init_V=None, shifts=None, dynamic=False,
-              init_iter=0, max_switch=0):
+              init_iter=0, max_switch=0, c_apply=None, c_inverse=False, n=None):
+    """Options of phsvds_svds.  ``c_apply(X, Y)`` (with ``n``, the columns
+    of A) fills Y = C X, or C^-1 X with ``c_inverse`` (shift-invert), X and
+    Y torch float64 views n x b of the library's row-major blocks."""
     o = _Opts()
     _lib.phsvds_default_opts(ctypes.byref(o))
     o.which = {"smallest": 0, "largest": 1}[which]
@@ -352,6 +401,19 @@ def make_opts(which="smallest", block=1, max_basis=0, min_restart=0, stage1_fp32
     o.dynamic = int(dynamic)
     o.init_iter = init_iter
     o.max_switch = max_switch
+    keep4 = None
+    if c_apply is not None:
+        def call(ctx, X, Y, b, fp64, stream):
+            try:
+                Xt = torch.as_tensor(_DevView(X, (n, b), "f8"), device="cuda")
+                Yt = torch.as_tensor(_DevView(Y, (n, b), "f8"), device="cuda")
+                c_apply(Xt, Yt)
+                return 0
+            except Exception:  # reported to the library as a nonzero return
+                return 1
+        keep4 = C_APPLY(call)
+        o.c_apply = keep4
+        o.c_inverse = int(c_inverse)
     keep2 = None
     if init_V is not None:
         # (n x k0) tensor -> n x k0 column-major device array
@@ -362,7 +424,7 @@ def make_opts(which="smallest", block=1, max_basis=0, min_restart=0, stage1_fp32
     if shifts is not None:
         keep3 = (ctypes.c_double * len(shifts))(*[float(x) for x in shifts])
         o.shifts = ctypes.cast(keep3, ctypes.POINTER(ctypes.c_double))
-    o._keep = (keep, keep2, keep3)
+    o._keep = (keep, keep2, keep3, keep4)
     return o
 
 
@@ -378,6 +440,8 @@ class Solver:
 
     def __init__(self, A: DeviceCSR, k: int, **opt_kw):
         self.A, self.k = A, k
+        if opt_kw.get("c_apply") is not None:
+            opt_kw["n"] = A.n
         self.opts = make_opts(**opt_kw)
         nbytes = workspace_bytes(A.m, A.n, A.nnz, k, self.opts)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=A.rowptr.device)
@@ -409,9 +473,10 @@ class Solver:
         pc = _Precond(PREC[precond], gnn_weights.data_ptr() if gnn_weights is not None else None,
                       gnn_width, fallback_window, cb, None, cbs, cbB)
         c = self.A._c()
-        rc = _lib.phsvds_svds(ctypes.byref(c), k, tol, ctypes.byref(pc), ctypes.byref(self.opts),
-                              self.ws.data_ptr(), self.ws.numel(), _stream(), sig,
-                              self.U.data_ptr(), self.V.data_ptr(), res, ctypes.byref(st))
+        entry = _lib.phsvds_svds_op if isinstance(self.A, Operator) else _lib.phsvds_svds
+        rc = entry(ctypes.byref(c), k, tol, ctypes.byref(pc), ctypes.byref(self.opts),
+                   self.ws.data_ptr(), self.ws.numel(), _stream(), sig,
+                   self.U.data_ptr(), self.V.data_ptr(), res, ctypes.byref(st))
         _check(rc, "svds")
         info = st.as_dict(k)
         info["status"] = rc

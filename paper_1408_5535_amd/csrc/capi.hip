@@ -383,17 +383,25 @@ void jacobi_scaled_values(const phsvds_csr *A, double *val_out, void *ws, size_t
 
 namespace {
 
-int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc,
-              const phsvds_opts *oin, void *ws, size_t ws_bytes, void *stream, double *sigma,
-              double *Uout, double *Vout, double *resnorm, phsvds_stats *stats) {
+int svds_impl(const phsvds_csr *Ain, const phsvds_operator *Aop, int k, double tol,
+              const phsvds_precond *Pc, const phsvds_opts *oin, void *ws, size_t ws_bytes,
+              void *stream, double *sigma, double *Uout, double *Vout, double *resnorm,
+              phsvds_stats *stats) {
   const double t0 = wall();
-  PHS_REQUIRE(Ain && sigma && Uout && Vout && resnorm, kEinval, "null argument");
+  PHS_REQUIRE((Ain || (Aop && Aop->apply)) && sigma && Uout && Vout && resnorm, kEinval,
+              "null argument");
   phsvds_opts o;
   phsvds_default_opts(&o);
   if (oin) o = *oin;
   phsvds_stats stl;
   std::memset(&stl, 0, sizeof(stl));
-  const int64_t m = Ain->m, n = Ain->n, nnz = Ain->nnz;
+  const int64_t m = Ain ? Ain->m : Aop->m, n = Ain ? Ain->n : Aop->n, nnz = Ain ? Ain->nnz : 0;
+  if (!Ain) {
+    const int pk = Pc ? Pc->kind : PHSVDS_PREC_NONE;
+    PHS_REQUIRE(pk == PHSVDS_PREC_NONE || pk == PHSVDS_PREC_USER || pk == PHSVDS_PREC_USER_A,
+                kEinval, "an operator for A takes no JACOBI or GNN preconditioner");
+    PHS_REQUIRE(!o.stage1_fp32, kEinval, "an operator for A runs in float64 only");
+  }
   PHS_REQUIRE(m >= n && n >= 1 && nnz >= 0 && nnz < (int64_t(1) << 31), kEinval,
               "need m >= n >= 1 and nnz < 2^31");
   PHS_REQUIRE(tol > 0, kEinval, "tol must be positive");
@@ -409,6 +417,11 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
               "a USER_A preconditioner needs user_solve");
   bool resume = o.init_V && o.shifts;
   PHS_REQUIRE(!o.shifts || o.init_V, kEinval, "shifts need init_V");
+  PHS_REQUIRE(!o.c_apply || (!o.stage1_fp32 && !o.dynamic), kEinval,
+              "an operator for C needs stage1_fp32 = 0 and dynamic = 0");
+  PHS_REQUIRE(!o.c_inverse || (o.c_apply && o.which == 0 && pkind == PHSVDS_PREC_NONE &&
+                               !resume),
+              kEinval, "shift-invert needs c_apply, the smallest end and no preconditioner");
   PHS_REQUIRE(!o.dynamic || (o.which == 0 && !o.stage1_fp32 && o.stage2_method == 0 &&
                              !o.init_V && pkind != PHSVDS_PREC_GNN),
               kEinval,
@@ -459,23 +472,36 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   A64.m = m;
   A64.n = n;
   A64.nnz = nnz;
-  A64.rowptr = Ain->rowptr;
-  A64.colind = Ain->colind;
-  A64.val = Ain->val;
-  csr_transpose(m, n, nnz, Ain->rowptr, Ain->colind, Ain->val, pl.trp, pl.tci, pl.tva, pl.tws,
-                pl.tws_bytes, c.s);
   At64.m = n;
   At64.n = m;
   At64.nnz = nnz;
-  At64.rowptr = pl.trp;
-  At64.colind = pl.tci;
-  At64.val = pl.tva;
-  build_bins(m, A64.rowptr, pl.binA, pl.binScr, A64.bins, &A64.nbins, c.s);
-  A64.binrows = pl.binA;
-  if (A64.nbins == 1) A64.nbins = 0;
-  build_bins(n, At64.rowptr, pl.binAt, pl.binScr, At64.bins, &At64.nbins, c.s);
-  At64.binrows = pl.binAt;
-  if (At64.nbins == 1) At64.nbins = 0;
+  OpHook hook;
+  if (Aop) {
+    // the caller's operator (Section 3.3): every product of the path goes
+    // through it, on the solver's stream
+    hook.f = [&](const void *X, void *Y, int b, bool trans, bool fp64) {
+      const int rc = Aop->apply(Aop->ctx, X, Y, b, trans ? 1 : 0, fp64 ? 1 : 0, c.s);
+      if (rc != 0) throw Error(PHSVDS_EUSER, "operator returned " + std::to_string(rc));
+    };
+    A64.op = &hook;
+    At64.op = &hook;
+    At64.op_trans = true;
+  } else {
+    A64.rowptr = Ain->rowptr;
+    A64.colind = Ain->colind;
+    A64.val = Ain->val;
+    csr_transpose(m, n, nnz, Ain->rowptr, Ain->colind, Ain->val, pl.trp, pl.tci, pl.tva,
+                  pl.tws, pl.tws_bytes, c.s);
+    At64.rowptr = pl.trp;
+    At64.colind = pl.tci;
+    At64.val = pl.tva;
+    build_bins(m, A64.rowptr, pl.binA, pl.binScr, A64.bins, &A64.nbins, c.s);
+    A64.binrows = pl.binA;
+    if (A64.nbins == 1) A64.nbins = 0;
+    build_bins(n, At64.rowptr, pl.binAt, pl.binScr, At64.bins, &At64.nbins, c.s);
+    At64.binrows = pl.binAt;
+    if (At64.nbins == 1) At64.nbins = 0;
+  }
   SpMat<float> A32, At32;
   if (d.fp32) {
     copy(cm(const_cast<double *>(Ain->val), nnz, 1, nnz), cm(pl.va32, nnz, 1, nnz), c.s);
@@ -499,7 +525,7 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
   P1.bw = d.bw;
   P1.pmax = d.pmax;
   P1.pmin = d.pmin;
-  P1.largest = largest;
+  P1.largest = largest || o.c_inverse;
   P1.tol = tol;
   P1.floor = o.floor_factor > 0 ? o.floor_factor : 10.0;
   P1.anorm = o.anorm;
@@ -537,6 +563,23 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
     return nullptr;
   };
   P1.user = d.fp32 ? stage1_hook(false, pl.s32.Yb) : stage1_hook(true, pl.s64.Yb);
+  double si_anorm = 0.0;
+  if (o.c_apply) {
+    P1.opC = [&](const void *X, void *Y, int b) {
+      const int rc = o.c_apply(o.c_ctx, X, Y, b, 1, c.s);
+      if (rc != 0) throw Error(PHSVDS_EUSER, "C operator returned " + std::to_string(rc));
+    };
+    if (o.c_inverse) {
+      // shift-invert: the running maximum is of C^-1's spectrum, ||A||
+      // comes from the caller or from power iteration on A^T A
+      si_anorm = o.anorm > 0 ? o.anorm
+                             : std::sqrt(power_norm2(c, A64, At64, pl.tb.Xn, pl.tb.Ym, pl.tb.Z,
+                                                     12, sp));
+      if (!(o.anorm > 0)) stl.mv_prec += 12;
+      P1.si_anorm = si_anorm;
+      P1.anorm = 0.0;
+    }
+  }
   // stage-2 preconditioner of B on row-major N x ns blocks (row stride ldr),
   // through the column-major scratch blocks Cb and C2b (free while the
   // correction is formed, also inside JDQMR)
@@ -803,6 +846,12 @@ int svds_impl(const phsvds_csr *Ain, int k, double tol, const phsvds_precond *Pc
     nvr = r1.p;
   }
   }  // first stage
+  if (o.c_inverse) {
+    // eigenvalues mu of C^-1 -> theta = 1 / mu of C (sorted below)
+    for (double &t : r1.theta) t = 1.0 / std::max(t, 1e-300);
+    for (double &t : r1.best_theta) t = 1.0 / std::max(t, 1e-300);
+    r1.sn2 = si_anorm * si_anorm;
+  }
   stl.iters1 += d.fp32 && !d.cont ? 0 : r1.iters;
   stl.restarts1 += d.fp32 && !d.cont ? 0 : r1.restarts;
   stl.fallbacks += r1.fallbacks;
@@ -1380,8 +1429,18 @@ int phsvds_svds(const phsvds_csr *A, int k, double tol, const phsvds_precond *P,
                 const phsvds_opts *opts, void *workspace, size_t ws_bytes, void *stream,
                 double *sigma, double *U, double *V, double *resnorm, phsvds_stats *stats) {
   return guarded([&]() {
-    return svds_impl(A, k, tol, P, opts, workspace, ws_bytes, stream, sigma, U, V, resnorm,
-                     stats);
+    return svds_impl(A, nullptr, k, tol, P, opts, workspace, ws_bytes, stream, sigma, U, V,
+                     resnorm, stats);
+  });
+}
+
+int phsvds_svds_op(const phsvds_operator *A, int k, double tol, const phsvds_precond *P,
+                   const phsvds_opts *opts, void *workspace, size_t ws_bytes, void *stream,
+                   double *sigma, double *U, double *V, double *resnorm, phsvds_stats *stats) {
+  return guarded([&]() {
+    PHS_REQUIRE(A, kEinval, "null operator");
+    return svds_impl(nullptr, A, k, tol, P, opts, workspace, ws_bytes, stream, sigma, U, V,
+                     resnorm, stats);
   });
 }
 

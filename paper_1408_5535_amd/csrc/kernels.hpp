@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 
 namespace phs {
 
@@ -11,7 +12,15 @@ struct Bin {
   int32_t offset, count, lanes;
 };
 
-// CSR matrix on the device in working precision T.
+// The caller's operator in place of a CSR (Section 3.3: products with A
+// and A^T given as functions): Y = op(A) X for row-major blocks of width b,
+// X n x b and Y m x b for A (trans false), the other way round for A^T.
+struct OpHook {
+  std::function<void(const void *X, void *Y, int b, bool trans, bool fp64)> f;
+};
+
+// CSR matrix on the device in working precision T, or the caller's
+// operator (op set: only m, n and op_trans are meaningful).
 template <typename T>
 struct SpMat {
   int64_t m = 0, n = 0, nnz = 0;
@@ -21,6 +30,8 @@ struct SpMat {
   int nbins = 0;  // 0: one launch over all rows
   Bin bins[8];
   const int32_t *binrows = nullptr;
+  const OpHook *op = nullptr;
+  bool op_trans = false;  // this SpMat is A^T of the operator
 };
 
 int lanes_for_length(double avg);

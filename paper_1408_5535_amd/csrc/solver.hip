@@ -241,19 +241,33 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
   const int pkind = fp32 ? kProfSpmm32 : kProfSpmm64;
   const double cbytes = spmm_bytes(A, bw) + spmm_bytes(At, bw);
   auto applyC = [&](T *X, int nb) {
-    prof_group_begin(pkind, c.s, 2);
-    spmm(A, bw, X, bf.Yb, false, c.s);
-    spmm(At, bw, bf.Yb, bf.WTb, false, c.s);
-    prof_group_end(pkind, c.s, cbytes);
+    if (P.opC) {
+      P.opC(X, bf.WTb, bw);
+    } else {
+      prof_group_begin(pkind, c.s, 2);
+      spmm(A, bw, X, bf.Yb, false, c.s);
+      spmm(At, bw, bf.Yb, bf.WTb, false, c.s);
+      prof_group_end(pkind, c.s, cbytes);
+    }
     c.st->mv_stage1 += nb;
   };
   // W_T = C T goes straight into the new columns of W; V's new columns are
   // copied from T unless the caller has written them already
   auto append = [&](int nb, bool v_written) {
-    prof_group_begin(pkind, c.s, 2);
-    spmm(A, bw, Tb, bf.Yb, false, c.s);
-    spmm(At, bw, bf.Yb, W[cur] + (int64_t)p * n, false, c.s, n, nb);
-    prof_group_end(pkind, c.s, cbytes);
+    if (P.opC) {
+      P.opC(Tb, bf.WTb, bw);
+      copy(rmv(bf.WTb, n, nb, bw), cm(W[cur] + (int64_t)p * n, n, nb, n), c.s);
+    } else {
+      prof_group_begin(pkind, c.s, 2);
+      spmm(A, bw, Tb, bf.Yb, false, c.s);
+      if (At.op) {  // an operator writes row-major blocks only
+        spmm(At, bw, bf.Yb, bf.WTb, false, c.s);
+        copy(rmv(bf.WTb, n, nb, bw), cm(W[cur] + (int64_t)p * n, n, nb, n), c.s);
+      } else {
+        spmm(At, bw, bf.Yb, W[cur] + (int64_t)p * n, false, c.s, n, nb);
+      }
+      prof_group_end(pkind, c.s, cbytes);
+    }
     c.st->mv_stage1 += nb;
     if (!v_written) copy(rmv(Tb, n, nb, bw), cm(V[cur] + (int64_t)p * n, n, nb, n), c.s);
     // border of H; the previous block's coefficients have no component on
@@ -422,16 +436,20 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     auto floor_of = [&](int i) {
       return fp32 ? P.floor * eps * std::max(rho_h[i], 0.0) : P.floor * eps * res.sn2;
     };
+    // the user-tolerance part of the test (Section 3.1); in shift-invert
+    // its image on C^-1: C r' = -mu r_C for r' = C^-1 x - mu x
+    auto rel_of = [&](int i) {
+      const double si = std::sqrt(std::max(th_h[i], 0.0));
+      return P.si_anorm > 0 ? P.tol * si / P.si_anorm : P.tol * si * sn;
+    };
     for (int i = 0; i < std::min(nb, need); ++i) {
-      double si = std::sqrt(std::max(th_h[i], 0.0));
-      double thr = std::max(P.tol * si * sn, floor_of(i));
+      double thr = std::max(rel_of(i), floor_of(i));
       if (std::sqrt(std::max(rn_h[i], 0.0)) < thr) conv.push_back(i);
     }
     bool stag = false;
     if (conv.empty() && need > 0) {
-      double si0 = std::sqrt(std::max(th_h[0], 0.0));
       double fl0 = floor_of(0);
-      if (P.tol * si0 * sn < fl0) {
+      if (rel_of(0) < fl0) {
         double r0 = std::sqrt(std::max(rn_h[0], 0.0));
         hist.push_back(r0);
         if ((int)hist.size() > 2 * L && r0 < 10.0 * fl0) {
@@ -460,8 +478,7 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
       c.sync();
       bool all_ok = true;
       for (int i : conv) {
-        double si = std::sqrt(std::max(th_h[i], 0.0));
-        double thr = std::max(P.tol * si * sn, floor_of(i));
+        double thr = std::max(rel_of(i), floor_of(i));
         if (!(std::sqrt(std::max(rt[i], 0.0)) < thr)) all_ok = false;
       }
       if (!all_ok && it - last_rebuild <= 10) {

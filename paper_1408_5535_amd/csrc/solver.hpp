@@ -83,6 +83,11 @@ struct Stage1Params {
   // optional per-iteration history of log(||r_1|| / sqrt(theta_1)) of the
   // leading unlocked pair, NaN where it changed (a lock)
   std::vector<double> *hist = nullptr;
+  // the caller's operator in place of C = A^T A (C itself, or C^-1 for
+  // shift-invert): Y = op X on row-major n x b blocks; null: A^T (A X)
+  std::function<void(const void *, void *, int)> opC;
+  // shift-invert: ||A||; the test becomes ||C^-1 x - mu x|| < tol sqrt(mu) / ||A||
+  double si_anorm = 0.0;
 };
 
 template <typename T>

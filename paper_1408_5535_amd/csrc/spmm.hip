@@ -222,6 +222,12 @@ void spmm(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, hipStream_t s
   const int kind = sizeof(T) == 8 ? kProfSpmm64 : kProfSpmm32;
   PHS_REQUIRE(ycm == 0 || (ycm >= A.m && ycols >= 1 && ycols <= b), kEinval,
               "spmm: bad column-major output");
+  if (A.op) {
+    // the caller's operator: row-major blocks only, no |A|
+    PHS_REQUIRE(ycm == 0 && !absval, kEinval, "spmm: operator products are plain row-major");
+    A.op->f(X, Y, b, A.op_trans, sizeof(T) == 8);
+    return;
+  }
   prof_begin(kind, s);
   spmm_launch(A, b, X, Y, absval, ycm, ycols, s);
   // algorithmic bytes: values + column indices + row pointers + X + Y
@@ -253,6 +259,10 @@ void spmm_launch(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, int64_
 }
 template <typename T>
 void spmm_untimed(const SpMat<T> &A, int b, const T *X, T *Y, hipStream_t s) {
+  if (A.op) {
+    A.op->f(X, Y, b, A.op_trans, sizeof(T) == 8);
+    return;
+  }
   spmm_launch(A, b, X, Y, false, 0, 0, s);
 }
 template void spmm_untimed<float>(const SpMat<float> &, int, const float *, float *,

@@ -315,3 +315,116 @@ def test_user_preconditioner_float64_continuation_gets_float64_blocks():
     assert info["status"] == 0
     assert pairs == {(torch.float32, False), (torch.float64, True)}
     assert np.all(np.abs(sig - sigx[:3]) <= 1e-10 * sigx[:3])
+
+
+@gpu
+@pytest.mark.parametrize("method", ["gdk", "jdqmr"])
+def test_operator_for_A_matches_the_csr_path(method):
+    """phsvds_svds_op: the products of the whole path through the caller's
+    operator (here torch's dense float64 product) give the CSR path's
+    triplets; sigma against the closed form."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A, sigx, Ux, Vx = _givens_small()
+    Ad = torch.tensor(A.toarray(), device="cuda")
+    calls = {"A": 0, "At": 0}
+
+    def apply(X, Y, trans):
+        calls["At" if trans else "A"] += 1
+        Y.copy_((Ad.T if trans else Ad) @ X)
+
+    say("operator for A, givens 240 x 200, method", method)
+    op = P.Operator(A.shape[0], A.shape[1], apply)
+    sig, U, V, info = P.svds_smallest(op, 3, 1e-12, block=1, anorm=1.0, stage2_method=method)
+    say({q: info[q] for q in ("status", "mv_total", "stage2_pairs")}, calls)
+    assert info["status"] == 0 and calls["A"] > 0 and calls["At"] > 0
+    assert np.all(np.abs(sig - sigx[:3]) <= 1e-10 * sigx[:3])
+    assert np.all(dense.triplet_residuals(A, sig, as_np(U), as_np(V)) <= 1e-12)
+    sig2, _, _, info2 = P.svds_smallest(to_dev(A), 3, 1e-12, block=1, anorm=1.0,
+                                        stage2_method=method)
+    say("csr path", info2["mv_total"])
+    assert np.all(np.abs(sig - sig2) <= 1e-12 * sig2)
+    assert abs(info["mv_total"] - info2["mv_total"]) <= 0.2 * info2["mv_total"]
+
+
+@gpu
+def test_operator_largest_end_block_and_errors():
+    need_gpu()
+    import paper_1408_5535_amd as P
+    N = 16
+    A = wl.grid_gradient(N)
+    An = torch.tensor(A.toarray(), device="cuda")
+
+    def apply(X, Y, trans):
+        Y.copy_((An.T if trans else An) @ X)
+
+    op = P.Operator(A.shape[0], A.shape[1], apply)
+    sig, U, V, info = P.svds_smallest(op, 4, 1e-12, block=4, which="largest",
+                                      anorm=cf.grid_norm(N))
+    ex = cf.grid_sigmas(N)[::-1][:4]
+    assert info["status"] == 0 and np.all(np.abs(sig - ex) <= 1e-10 * ex)
+    with pytest.raises(RuntimeError, match=r"\(-1\)"):
+        P.svds_smallest(op, 2, 1e-10, precond="jacobi")
+    with pytest.raises(RuntimeError, match=r"\(-1\)"):
+        P.svds_smallest(op, 2, 1e-10, stage1_fp32=True)
+
+    def bad(X, Y, trans):
+        raise ValueError("no products today")
+
+    with pytest.raises(RuntimeError, match=r"\(-5\)"):
+        P.svds_smallest(P.Operator(A.shape[0], A.shape[1], bad), 2, 1e-10)
+
+
+@gpu
+@pytest.mark.parametrize("method", ["gdk", "jdqmr"])
+def test_shift_invert_vs_oracle(method):
+    """c_apply with c_inverse: the first stage on the caller's C^-1 (largest
+    end), then the transition and the second stage on A; sigma against the
+    closed form, products against the oracle's shift-invert."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A, sigx, Ux, Vx = _givens_small()
+    Ci = (Vx / sigx ** 2) @ Vx.T
+    Ci_d = torch.tensor(Ci, device="cuda")
+    calls = []
+
+    def cinv(X, Y):
+        calls.append(X.shape[1])
+        Y.copy_(Ci_d @ X)
+
+    say("shift-invert, givens 240 x 200, method", method)
+    sig, U, V, info = P.svds_smallest(to_dev(A), 3, 1e-12, block=1, anorm=1.0, c_apply=cinv,
+                                      c_inverse=True, stage2_method=method)
+    say({q: info[q] for q in ("status", "mv_total", "mv_stage1", "stage2_pairs")}, len(calls))
+    assert info["status"] == 0 and info["stage2_pairs"] == 3 and len(calls) > 0
+    assert np.all(np.abs(sig - sigx[:3]) <= 1e-10 * sigx[:3])
+    assert np.all(dense.triplet_residuals(A, sig, as_np(U), as_np(V)) <= 1e-12)
+    out = ph.phsvds(A, 3, 1e-12, block=1, anorm=1.0, c_apply=lambda X: Ci @ X, c_inverse=True,
+                    stage2_method=method)
+    assert out["converged"]
+    ratio = info["mv_total"] / out["stats"].mv_total
+    say("MV gpu/oracle", ratio, "stage 1", info["mv_stage1"], out["stats"].mv_stage1)
+    assert 0.5 <= ratio <= 2.0
+
+
+@gpu
+def test_C_operator_and_shift_invert_grid():
+    need_gpu()
+    import paper_1408_5535_amd as P
+    N = 16
+    A = wl.grid_gradient(N)
+    C = (A.T @ A).toarray()
+    C_d = torch.tensor(C, device="cuda")
+    Ci_d = torch.tensor(np.linalg.inv(C), device="cuda")
+    ex = cf.grid_sigmas(N)[:4]
+    # block 4 (with block 2 the first stage on C^-1 stalls on the double
+    # pair sigma = 0.411 at 1.4e-12 relative, above the shift-invert test)
+    for M, inv in ((C_d, False), (Ci_d, True)):
+        sig, U, V, info = P.svds_smallest(to_dev(A), 4, 1e-12, block=4, anorm=cf.grid_norm(N),
+                                          c_apply=lambda X, Y, M=M: Y.copy_(M @ X),
+                                          c_inverse=inv)
+        say("grid N=16 k=4, C operator, inverse", inv, info["status"], info["mv_stage1"])
+        assert info["status"] == 0 and np.all(np.abs(sig - ex) <= 1e-10 * ex)
+    with pytest.raises(RuntimeError, match=r"\(-1\)"):
+        P.svds_smallest(to_dev(A), 4, 1e-12, c_apply=lambda X, Y: Y.copy_(X), c_inverse=True,
+                        precond="jacobi")
