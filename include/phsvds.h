@@ -379,6 +379,15 @@ int phsvds_gnn_forward(const phsvds_csr *A, int width, void *gws, size_t gws_byt
 int phsvds_gnn_loss_grad(const phsvds_csr *A, int width, void *gws, size_t gws_bytes,
                          const float *w, const float *r, const float *x, double theta,
                          const float *tstar, double *grad, double *loss, void *stream);
+/* Adds ||C t - r||^2 / ||r||^2 for the network's output t = M(r) to *loss
+ * and its gradient with respect to the weights to grad: how far the
+ * correction is from solving C t = r, the criterion the polynomial start
+ * fits (Section 4 leaves the preconditioner open; this objective needs no
+ * exact corrections).  C t uses the float32 values of A.  Arguments as
+ * for phsvds_gnn_loss_grad without tstar. */
+int phsvds_gnn_residual_loss_grad(const phsvds_csr *A, int width, void *gws, size_t gws_bytes,
+                                  const float *w, const float *r, const float *x, double theta,
+                                  double *grad, double *loss, void *stream);
 /* One Adam step (Kingma & Ba; beta1 0.9, beta2 0.999, eps 1e-8) on the
  * float32 weights w with moments m, v (device, nw floats), gradient
  * grad * grad_scale; step counts from 1. */

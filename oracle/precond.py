@@ -108,13 +108,23 @@ def forward(g: Graph, P, r, x, theta):
     return t, {"hs": hs, "pres": pres, "scale": scale, "osc": osc}
 
 
-def loss_and_grad(g: Graph, P, r, x, theta, tstar):
-    """Loss ||t - t*||^2 / ||t*||^2 and its gradient by back-propagation."""
+def loss_and_grad(g: Graph, P, r, x, theta, tstar, kind="target"):
+    """Loss and its gradient by back-propagation.  kind 'target':
+    ||t - t*||^2 / ||t*||^2, the distance to the exact correction; kind
+    'residual': ||C t - r||^2 / ||r||^2, how far t is from solving C t = r
+    (tstar unused), whose gradient with respect to t is 2 C (C t - r) /
+    ||r||^2."""
     t, cache = forward(g, P, r, x, theta)
-    nt = float(tstar @ tstar)
-    diff = t - tstar
-    loss = float(diff @ diff) / nt
-    gt = 2.0 * diff / nt
+    if kind == "residual":
+        nr2 = float(r @ r)
+        e = g.At @ (g.A @ t) - r
+        loss = float(e @ e) / nr2
+        gt = 2.0 * (g.At @ (g.A @ e)) / nr2
+    else:
+        nt = float(tstar @ tstar)
+        diff = t - tstar
+        loss = float(diff @ diff) / nt
+        gt = 2.0 * diff / nt
     graw = gt - x * (x @ gt)  # through the projection (I - x x^T)
     hs, pres, osc = cache["hs"], cache["pres"], cache["osc"]
     grads = {}

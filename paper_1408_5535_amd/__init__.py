@@ -546,6 +546,9 @@ _lib.phsvds_gnn_forward.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, _P, ctyp
                                     _P, _P, ctypes.c_double, _P, _P]
 _lib.phsvds_gnn_loss_grad.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, _P, ctypes.c_size_t,
                                       _P, _P, _P, ctypes.c_double, _P, _P, _P, _P]
+_lib.phsvds_gnn_residual_loss_grad.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, _P,
+                                               ctypes.c_size_t, _P, _P, _P, ctypes.c_double, _P,
+                                               _P, _P]
 _lib.phsvds_gnn_adam.argtypes = [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
                                  ctypes.c_double, _P]
 _lib.phsvds_harvest_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
@@ -601,9 +604,16 @@ class GnnGraph:
                                        float(theta), t.data_ptr(), _stream()), "gnn_forward")
         return t
 
-    def loss_grad(self, w, r, x, theta, tstar, grad, loss):
+    def loss_grad(self, w, r, x, theta, tstar, grad, loss, kind="target"):
         """Accumulates the sample's loss into loss (float64 [1]) and its
-        gradient into grad (float64 [nweights])."""
+        gradient into grad (float64 [nweights]): kind 'target' the distance
+        to tstar, 'residual' ||C t - r||^2 / ||r||^2 (tstar unused)."""
+        if kind == "residual":
+            _check(_lib.phsvds_gnn_residual_loss_grad(
+                ctypes.byref(self.c), self.width, self.ws.data_ptr(), self.ws.numel(),
+                w.data_ptr(), r.data_ptr(), x.data_ptr(), float(theta), grad.data_ptr(),
+                loss.data_ptr(), _stream()), "gnn_residual_loss_grad")
+            return
         _check(_lib.phsvds_gnn_loss_grad(ctypes.byref(self.c), self.width, self.ws.data_ptr(),
                                          self.ws.numel(), w.data_ptr(), r.data_ptr(),
                                          x.data_ptr(), float(theta), tstar.data_ptr(),
@@ -644,7 +654,8 @@ def harvest(A: DeviceCSR, k: int, block: int = 4, every: int = 5, max_pairs: int
     return R[:n], X[:n], T[:n], np.array(th[:n]), st.as_dict(k)
 
 
-def train_gnn(graphs, pairs, w, epochs=20, lr=1e-3, batch=16, seed=0, log=None, on_epoch=None):
+def train_gnn(graphs, pairs, w, epochs=20, lr=1e-3, batch=16, seed=0, log=None, on_epoch=None,
+              loss_kind="target"):
     """Adam on the mean loss over mini-batches of harvested pairs.
 
     graphs: list of GnnGraph; pairs: list of (graph index, r, x, theta, t*)
@@ -668,7 +679,7 @@ def train_gnn(graphs, pairs, w, epochs=20, lr=1e-3, batch=16, seed=0, log=None, 
             loss.zero_()
             for i in idx:
                 gi, r, x, th, ts = pairs[i]
-                graphs[gi].loss_grad(w, r, x, th, ts, grad, loss)
+                graphs[gi].loss_grad(w, r, x, th, ts, grad, loss, loss_kind)
             step += 1
             gnn_adam(w, m, v, grad, step, lr, 1.0 / len(idx))
             tot += float(loss.item())

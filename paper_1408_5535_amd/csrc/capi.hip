@@ -1416,6 +1416,20 @@ int phsvds_gnn_loss_grad(const phsvds_csr *A, int width, void *gws, size_t bytes
   });
 }
 
+int phsvds_gnn_residual_loss_grad(const phsvds_csr *A, int width, void *gws, size_t bytes,
+                                  const float *w, const float *r, const float *x, double theta,
+                                  double *grad, double *loss, void *stream) {
+  return guarded([&]() {
+    GnnGraph g;
+    GnnBufs b;
+    gnn_views(A, width, gws, bytes, g, b);
+    PHS_REQUIRE(w && r && x && grad && loss, kEinval, "null argument");
+    gnn_loss_grad(*A, g, b, w, width, r, x, theta, nullptr, b.tout, grad, loss,
+                  (hipStream_t)stream, 1);
+    return PHSVDS_OK;
+  });
+}
+
 int phsvds_gnn_adam(float *w, float *m, float *v, const double *grad, int64_t nw, int step,
                     double lr, double grad_scale, void *stream) {
   return guarded([&]() {

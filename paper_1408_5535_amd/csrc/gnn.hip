@@ -407,19 +407,56 @@ void gnn_forward(const phsvds_csr &A, const GnnGraph &g, GnnBufs &b, const float
   PHS_CHECK_LAUNCH();
 }
 
+// e = a - c (float32)
+__global__ void k_sub_f(const float *a, const float *c, int64_t n, float *e) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    e[i] = a[i] - c[i];
+}
+
+// g *= f / den[0]
+__global__ void k_scale_by(float *g, int64_t n, const double *den, double f) {
+  const double c = f / fmax(den[0], 1e-300);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    g[i] = (float)(c * (double)g[i]);
+}
+
+// loss[0] += num[0] / den[0]
+__global__ void k_ratio_acc(const double *num, const double *den, double *loss) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) loss[0] += num[0] / fmax(den[0], 1e-300);
+}
+
 void gnn_loss_grad(const phsvds_csr &A, const GnnGraph &g, GnnBufs &b, const float *wts, int w,
                    const float *r, const float *x, double theta, const float *tstar, float *t,
-                   double *grad, double *loss_dev, hipStream_t s) {
+                   double *grad, double *loss_dev, hipStream_t s, int kind) {
   const int64_t n = A.n;
   SpMat<float> A32, At32;
   views(A, g, A32, At32);
   const GnnOffsets o = gnn_offsets(w, kGnnIn);
   gnn_forward(A, g, b, wts, w, r, x, theta, t, s);
-  // loss = ||t - t*||^2 / ||t*||^2 ; g = 2 (t - t*)/||t*||^2 ; graw = (I - x x^T) g
-  colnorm2(cm(const_cast<float *>(tstar), n, 1, n), 0, n, b.vec + 2, b.sc, s);
-  k_gnn_lossgrad<<<grid_for(n), 256, 0, s>>>(t, tstar, b.vec + 2, n, b.g);
-  // loss_dev[0] += ||g||^2 ||t*||^2 / 4  (= ||t - t*||^2 / ||t*||^2)
-  colnorm2(cm(b.g, n, 1, n), 0, n, b.vec + 3, b.sc, s);
+  if (kind == 1) {
+    // loss = ||C t - r||^2 / ||r||^2 ; g = 2 C (C t - r) / ||r||^2, with
+    // C t from two float32 products (b.M holds e until the backward pass)
+    spmm(A32, 1, t, b.Ym, false, s);
+    spmm(At32, 1, b.Ym, b.M, false, s);
+    k_sub_f<<<grid_for(n), 256, 0, s>>>(b.M, r, n, b.M);
+    colnorm2(cm(b.M, n, 1, n), 0, n, b.vec + 3, b.sc, s);
+    colnorm2(cm(const_cast<float *>(r), n, 1, n), 0, n, b.vec + 2, b.sc, s);
+    k_ratio_acc<<<1, 64, 0, s>>>(b.vec + 3, b.vec + 2, loss_dev);
+    spmm(A32, 1, b.M, b.Ym, false, s);
+    spmm(At32, 1, b.Ym, b.g, false, s);
+    k_scale_by<<<grid_for(n), 256, 0, s>>>(b.g, n, b.vec + 2, 2.0);
+    PHS_CHECK_LAUNCH();
+  } else {
+    // loss = ||t - t*||^2 / ||t*||^2 ; g = 2 (t - t*)/||t*||^2
+    colnorm2(cm(const_cast<float *>(tstar), n, 1, n), 0, n, b.vec + 2, b.sc, s);
+    k_gnn_lossgrad<<<grid_for(n), 256, 0, s>>>(t, tstar, b.vec + 2, n, b.g);
+    // loss_dev[0] += ||g||^2 ||t*||^2 / 4  (= ||t - t*||^2 / ||t*||^2)
+    colnorm2(cm(b.g, n, 1, n), 0, n, b.vec + 3, b.sc, s);
+    gnn_loss_acc(b.vec + 3, b.vec + 2, loss_dev, s);
+  }
+  // graw = (I - x x^T) g
   tn(cm(const_cast<float *>(x), n, 1, n), cm<float>(nullptr, n, 0, n), cm(b.g, n, 1, n),
      b.vec + 4, 1, b.sc, s);
   k_axpy_dev<<<grid_for(n), 256, 0, s>>>(b.g, x, b.vec + 4, 1.0, n, b.g);
@@ -459,7 +496,6 @@ void gnn_loss_grad(const phsvds_csr &A, const GnnGraph &g, GnnBufs &b, const flo
     }
     PHS_CHECK_LAUNCH();
   }
-  gnn_loss_acc(b.vec + 3, b.vec + 2, loss_dev, s);
 }
 
 void gnn_adam(float *w, float *m, float *v, const double *g, int64_t nw, int step, double lr,

@@ -43,7 +43,7 @@ void gnn_forward(const phsvds_csr &A, const GnnGraph &g, GnnBufs &b, const float
                  const float *r, const float *x, double theta, float *t, hipStream_t s);
 void gnn_loss_grad(const phsvds_csr &A, const GnnGraph &g, GnnBufs &b, const float *wts, int w,
                    const float *r, const float *x, double theta, const float *tstar, float *t,
-                   double *grad, double *loss_dev, hipStream_t s);
+                   double *grad, double *loss_dev, hipStream_t s, int kind = 0);
 void gnn_adam(float *w, float *m, float *v, const double *g, int64_t nw, int step, double lr,
               double gscale, hipStream_t s);
 void gnn_scale_acc(const double *G, int ldg, int w, const double *nr2, const double *meta,

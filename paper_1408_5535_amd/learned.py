@@ -17,15 +17,22 @@ the kind Section 4 admits.  The pipeline runs on the GPU through the C ABI:
             D^-1/2 p(Ch) D^-1/2 with p a degree-3 least-squares fit of 1/x on
             (0, 1.05 ||A D^-1/2||^2] (the norm from the library's own
             largest-mode solve), written into the weights (channels carry
-            the positive and negative parts of Ch^k u), or from Glorot
-            weights (--init glorot);
-  train     Adam on the mean loss ||t - t*||^2 / ||t*||^2 over mini-batches
-            of harvested pairs, forward and backward by the library's
-            kernels (phsvds_gnn_loss_grad, phsvds_gnn_adam);
+            the positive and negative parts of Ch^k u); or as exactly the
+            Jacobi preconditioner (--init jacobi: Glorot layers, zero
+            readout); or from Glorot weights (--init glorot);
+  train     Adam on the mean loss over mini-batches of harvested pairs,
+            forward and backward by the library's kernels: by default
+            ||C t - r||^2 / ||r||^2, how far the correction is from solving
+            C t = r (phsvds_gnn_residual_loss_grad), the criterion the
+            polynomial start fits, here weighted by the residuals the
+            iteration produces; or (--loss target) ||t - t*||^2 / ||t*||^2,
+            the distance to the exact corrections (phsvds_gnn_loss_grad),
+            which the lowest modes dominate and a three-hop network cannot
+            follow: it trains the network away from good preconditioners;
   select    among the start and the checkpoints at a quarter, half and
             the end of training, the network with the fewest products on a
-            validation matrix (the loss measures the distance to exact
-            corrections, not the quality inside the iteration);
+            validation matrix (neither loss is the quality inside the
+            iteration itself);
   evaluate  k smallest triplets of held-out matrices with no
             preconditioner, with Jacobi, with the network at its start, the
             last checkpoint and the selected one (each falls back to Jacobi
@@ -101,8 +108,18 @@ def poly_init(A_host, width=32, degree=3, margin=1.05):
     return gnn_pack(wl.gnn_poly_weights(coeffs, width)), hi, coeffs
 
 
+def jacobi_init(width=32, seed=0):
+    """Initial weights whose network is exactly the Jacobi preconditioner:
+    Glorot layers and a zero readout (the readout adds the Jacobi feature),
+    so training starts from Jacobi with live hidden channels."""
+    import workloads as wl
+    P = wl.gnn_init_weights(width=width, seed=seed)
+    P["wo"][:] = 0.0
+    return gnn_pack(P)
+
+
 def train(graphs, pairs, width=32, epochs=30, lr=1e-3, batch=16, seed=0, init=None,
-          checkpoints=()):
+          checkpoints=(), loss_kind="residual"):
     """Adam from `init` (or Glorot weights); returns (final weights, loss per
     epoch, {epoch: weights} for the epochs in `checkpoints`)."""
     import workloads as wl
@@ -118,7 +135,7 @@ def train(graphs, pairs, width=32, epochs=30, lr=1e-3, batch=16, seed=0, init=No
 
     hist = train_gnn(graphs, pairs, w, epochs=epochs, lr=lr, batch=batch, seed=seed,
                      log=lambda s: _say(f"[learned] {s} ({time.time() - t0:.0f}s)"),
-                     on_epoch=keep)
+                     on_epoch=keep, loss_kind=loss_kind)
     return w, hist, snaps
 
 
@@ -178,10 +195,14 @@ def main(argv=None):
     ap.add_argument("--weights", default="", help="evaluate these weights, skip training")
     ap.add_argument("--shift-scale", type=float, default=0.0,
                     help="rho of the harvested equation (C - rho theta I) t = -r")
-    ap.add_argument("--init", choices=["poly", "glorot"], default="poly")
+    ap.add_argument("--init", choices=["poly", "jacobi", "glorot"], default="poly",
+                    help="polynomial preconditioner, Jacobi (Glorot layers, zero readout), "
+                         "or Glorot weights")
     ap.add_argument("--val-seed", type=int, default=1500,
                     help="validation matrix for choosing among the checkpoints")
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--loss", choices=["target", "residual"], default="residual",
+                    help="distance to the exact corrections, or ||C t - r|| / ||r||")
     args = ap.parse_args(argv)
 
     def make(seed):
@@ -198,12 +219,15 @@ def main(argv=None):
             nets["gnn_init"] = init
             meta = {"ch_bound": hi, "poly_coeffs": [float(c) for c in coeffs]}
             _say(f"[learned] polynomial start: bound {hi:.4f}, coefficients {meta['poly_coeffs']}")
+        elif args.init == "jacobi":
+            init = jacobi_init(args.width)
+            nets["gnn_init"] = init
         mats, graphs, pairs = harvest_family(range(*args.train_seeds), make, every=args.every,
                                              max_pairs=args.max_pairs, width=args.width,
                                              shift_scale=args.shift_scale)
         marks = sorted({args.epochs // 4 - 1, args.epochs // 2 - 1, args.epochs - 1} - {-1})
         w, hist, snaps = train(graphs, pairs, width=args.width, epochs=args.epochs, lr=args.lr,
-                               init=init, checkpoints=marks)
+                               init=init, checkpoints=marks, loss_kind=args.loss)
         del mats, graphs, pairs
         torch.cuda.empty_cache()
         # checkpoint selection on a validation matrix (not a training or

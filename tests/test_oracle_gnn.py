@@ -27,13 +27,14 @@ def _setup(width=8, seed=0):
     return A, g, P, rv, x, 0.3, tstar
 
 
-def test_gradient_matches_central_differences():
+@pytest.mark.parametrize("kind", ["target", "residual"])
+def test_gradient_matches_central_differences(kind):
     A, g, P, r, x, th, ts = _setup()
     # biases are zero at init: move them off zero so relu masks are generic
     rr = np.random.default_rng(5)
     for k in ("b1", "b2", "b3"):
         P[k] = 0.1 * rr.standard_normal(P[k].shape)
-    loss, grads = pc.loss_and_grad(g, P, r, x, th, ts)
+    loss, grads = pc.loss_and_grad(g, P, r, x, th, ts, kind)
     h = 1e-6
     for k in pc.NAMES:
         flat = P[k].ravel()
@@ -42,8 +43,8 @@ def test_gradient_matches_central_differences():
             Pm = {kk: v.copy() for kk, v in P.items()}
             Pp[k].ravel()[idx] += h
             Pm[k].ravel()[idx] -= h
-            lp, _ = pc.loss_and_grad(g, Pp, r, x, th, ts)
-            lm, _ = pc.loss_and_grad(g, Pm, r, x, th, ts)
+            lp, _ = pc.loss_and_grad(g, Pp, r, x, th, ts, kind)
+            lm, _ = pc.loss_and_grad(g, Pm, r, x, th, ts, kind)
             fd = (lp - lm) / (2 * h)
             an = grads[k].ravel()[idx]
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (k, idx, fd, an)
@@ -164,3 +165,13 @@ def test_inverse_poly_coeffs_fit():
         errs.append(np.sqrt(np.mean((xs * p - 1) ** 2)))
     assert errs[0] > errs[1] > errs[2]
     assert np.all(np.polyval(wl.inverse_poly_coeffs(3.0, 3)[::-1], xs) > 0)
+
+
+def test_residual_loss_definition():
+    """The residual loss is ||A^T A t - r||^2 / ||r||^2 of the network's
+    output, formed here from the dense C."""
+    A, g, P, r, x, th, ts = _setup()
+    t, _ = pc.forward(g, P, r, x, th)
+    C = (A.T @ A).toarray()
+    loss, _ = pc.loss_and_grad(g, P, r, x, th, None, "residual")
+    assert loss == pytest.approx(float(np.sum((C @ t - r) ** 2) / (r @ r)), rel=1e-12)
