@@ -118,7 +118,9 @@ typedef struct {
   int fp64_continue; /* with stage1_fp32: continue stage 1 in float64 before B */
   int stage2;      /* 0: automatic (Section 3.1 rule), 1: force, -1: never */
   int max_restarts;   /* per stage (default 10000, Section 5) */
-  int64_t max_matvecs; /* 0: unlimited */
+  int64_t max_matvecs; /* budget of products with A (stage 1, transition and
+                          stage 2 together; 0: unlimited): the solve stops
+                          with PHSVDS_NOT_CONVERGED once it is spent */
   uint64_t seed;      /* counter-based stream for random vectors */
   const double *init_block; /* device n x b column-major initial block, or NULL
                                for [ones/sqrt(n), random] (Section 5) */

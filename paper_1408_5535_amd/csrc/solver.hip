@@ -549,7 +549,7 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
       continue;
     }
     const bool out_of_budget = res.restarts > P.max_restarts ||
-                               (c.max_mv > 0 && c.st->mv_stage1 > c.max_mv) ||
+                               c.over_budget() ||
                                (P.max_iters > 0 && it > P.max_iters);
     if (out_of_budget) {
       // the pairs still missing are returned as the leading unlocked Ritz
@@ -1039,7 +1039,7 @@ Stage2Result run_stage2(Ctx &c, const SpMat<double> &A, const SpMat<double> &At,
       continue;
     }
     const bool out_of_budget = res.restarts > P.max_restarts ||
-                               (c.max_mv > 0 && c.st->mv_stage2 > c.max_mv) ||
+                               c.over_budget() ||
                                (P.max_iters > 0 && it > P.max_iters);
     if (out_of_budget) {
       // best approximations: the target's current vector, then the seeds of

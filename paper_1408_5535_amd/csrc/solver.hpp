@@ -35,7 +35,10 @@ struct Ctx {
   uint64_t seed = 0;
   uint64_t nrand = 0;
   phsvds_stats *st = nullptr;
-  int64_t max_mv = 0;
+  int64_t max_mv = 0;  // budget of products with A over the whole solve (0: none)
+  bool over_budget() const {
+    return max_mv > 0 && st->mv_stage1 + st->mv_rr + st->mv_stage2 > max_mv;
+  }
   int verbose = 0;  // progress lines on stderr
   // device-to-host reads go through one pinned staging buffer: d2h queues
   // the copy, sync() waits for the stream and moves the bytes to their
