@@ -1,14 +1,17 @@
 // Small dense float64 kernels, one workgroup each (p <= 64).
 //
-// The projected problems of the method -- the eigendecomposition of the
-// Rayleigh-Ritz matrix H (Algorithm 2 step 8), the SVD of the refined
-// projection factor R (step 9), Cholesky factors for CholQR, restart
-// rotations -- are at most 64 x 64.  They run in LDS inside one workgroup:
-// cyclic Jacobi for the symmetric eigenproblem and one-sided (Hestenes)
-// Jacobi for the SVD, both with round-robin pair ordering so that the p/2
-// rotations of a round are applied in parallel.  Jacobi methods compute
-// small eigenvalues and singular values to high relative accuracy, which
-// the refined projection needs near convergence.
+// The projected problems of the method -- the eigenpairs of the
+// Rayleigh-Ritz matrix H (Algorithm 1; Algorithm 2 step 8), the SVD of the
+// refined projection factor R (step 9), Cholesky factors for CholQR, QR and
+// triangular inverses, restart rotations -- are at most 64 x 64 and run in
+// LDS inside one workgroup.  The symmetric eigenproblem computes only the
+// eigenpairs an iteration uses: Householder tridiagonalisation, Sturm
+// multisection for the wanted eigenvalues (one point per lane), inverse
+// iteration with Gram-Schmidt inside clusters, and the reflectors applied
+// back.  The SVD is one-sided (Hestenes) Jacobi with round-robin pair
+// ordering, so the p/2 rotations of a round run in parallel; it computes
+// small singular values to high relative accuracy, which the refined
+// projection needs near convergence.
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"

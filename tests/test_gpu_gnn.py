@@ -145,14 +145,14 @@ def test_learned_pipeline_training_gains():
     trained network needs at most 0.8x the products of its start and of
     Jacobi on each held-out matrix; from the polynomial start (already far
     ahead of Jacobi) the trained network needs fewer products in total than
-    its start."""
+    its start.  Width 32, the network's size; times are printed."""
     need_gpu()
     from paper_1408_5535_amd import learned as L
 
     def make(seed):
         return wl.random_sparse(6000, 4000, 12, seed=seed)
 
-    W = 8
+    W = 32
     say("learned pipeline: starts")
     poly, hi, coeffs = L.poly_init(make(1000), width=W)
     jac = L.jacobi_init(W)
@@ -179,6 +179,7 @@ def test_learned_pipeline_training_gains():
     say("products (none, jacobi, jacobi start, trained from it, polynomial, trained from it):",
         [(s, mv[(s, "none")], mv[(s, "jacobi")], mv[(s, "jac")], mv[(s, "jac_trained")],
           mv[(s, "poly")], mv[(s, "poly_trained")]) for s in seeds])
+    say("seconds:", [(r["seed"], r["method"], round(r["seconds"], 3)) for r in rows])
     for s in seeds:
         assert mv[(s, "jac_trained")] <= 0.8 * mv[(s, "jacobi")]
         assert mv[(s, "jac_trained")] <= 0.8 * mv[(s, "jac")]
