@@ -537,7 +537,7 @@ __global__ __launch_bounds__(NG > 0 ? 1024 : 256) void k_nn(TV<T> x1, TV<T> x2, 
 // eight K-steps of X loads are issued before their MFMAs.
 constexpr int kNmKU = 8;
 
-template <typename T, int NT>
+template <typename T, int NT, bool PLAIN>
 __global__ __launch_bounds__(256) void k_nn_mfma(TV<T> x1, TV<T> x2, const double *S, int lds,
                                                   int ny, double alpha, double beta,
                                                   NnOut<T> o) {
@@ -585,9 +585,11 @@ __global__ __launch_bounds__(256) void k_nn_mfma(TV<T> x1, TV<T> x2, const doubl
           const int64_t col = 16 * t + Mfma16<T>::row(lane, v);
           if (col < ny) {
             T y = (T)alpha * acc[t][v];
-            if (beta != 0.0) y += (T)beta * o.z[r * o.zrs + col * o.zcs];
+            if constexpr (!PLAIN) {
+              if (beta != 0.0) y += (T)beta * o.z[r * o.zrs + col * o.zcs];
+              if (o.y2) o.y2[r * o.y2rs + col * o.y2cs] = y;
+            }
             o.y[r * o.yrs + col * o.ycs] = y;
-            if (o.y2) o.y2[r * o.y2rs + col * o.y2cs] = y;
           }
         }
       }
@@ -623,12 +625,24 @@ void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double a
     const int64_t tiles = (Y.rows + 15) / 16;
     const unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, 2048);
     prof_begin(kProfNn, s);
+    // plain products (Y = alpha X S, the restarts) store one output only,
+    // which keeps the hoisted store offsets out of the registers
+    const bool plain = beta == 0.0 && !Z && !Y2;
+#define PHS_NNM(NT_)                                                                            \
+  do {                                                                                          \
+    if (plain)                                                                                  \
+      k_nn_mfma<T, NT_, true><<<grid, 256, shm, s>>>(tv(X1), tv(X2), S, lds, ny, alpha, beta, o); \
+    else                                                                                        \
+      k_nn_mfma<T, NT_, false><<<grid, 256, shm, s>>>(tv(X1), tv(X2), S, lds, ny, alpha, beta,   \
+                                                      o);                                       \
+  } while (0)
     switch (nt) {
-      case 1: k_nn_mfma<T, 1><<<grid, 256, shm, s>>>(tv(X1), tv(X2), S, lds, ny, alpha, beta, o); break;
-      case 2: k_nn_mfma<T, 2><<<grid, 256, shm, s>>>(tv(X1), tv(X2), S, lds, ny, alpha, beta, o); break;
-      case 3: k_nn_mfma<T, 3><<<grid, 256, shm, s>>>(tv(X1), tv(X2), S, lds, ny, alpha, beta, o); break;
-      default: k_nn_mfma<T, 4><<<grid, 256, shm, s>>>(tv(X1), tv(X2), S, lds, ny, alpha, beta, o); break;
+      case 1: PHS_NNM(1); break;
+      case 2: PHS_NNM(2); break;
+      case 3: PHS_NNM(3); break;
+      default: PHS_NNM(4); break;
     }
+#undef PHS_NNM
     PHS_CHECK_LAUNCH();
     prof_end(kProfNn, s, (double)Y.rows * (nx + ny * (beta != 0.0 ? 2 : 1)) * sizeof(T));
     return;
