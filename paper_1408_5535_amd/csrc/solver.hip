@@ -362,8 +362,24 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     // changes slowly and is only used for the stopping thresholds
     const bool want_top = !largest && (nv > nb || it % 8 == 1);
     syev_rr(H, ld, p, nv, largest, theta, S, ld, c.s, want_top);
-    ritz(cm(V[cur], n, p, n), cm(W[cur], n, p, n), S, ld, theta, bf.Xb, Rb, nb, bw, rn2, nullptr,
-         0, c.sc, c.s);
+    // a restart due this iteration goes first: the restarted basis starts
+    // with this iteration's Ritz vectors (Y = [S(:, 0:p_min) | prev]), so
+    // the Ritz block is its first nb columns and the Ritz kernel reads nb
+    // columns of V and W instead of p.  The products go to the other
+    // buffers; a lock, rebuild or rollback below discards them.
+    const bool restart_due = p + nb > pmax;
+    int hc = 0;
+    if (restart_due) {
+      restart_basis(S, ld, p, pmin, prev, ld, nprev, Y, ld, cnt, c.s);
+      hc = std::min(pmin + nprev, p);  // restart_basis fills every column
+      nn(cm(V[cur], n, p, n), none<T>(n), Y, ld, 1.0, cm(V[1 - cur], n, hc, n), 0.0, c.s);
+      nn(cm(W[cur], n, p, n), none<T>(n), Y, ld, 1.0, cm(W[1 - cur], n, hc, n), 0.0, c.s);
+      ritz(cm(V[1 - cur], n, nb, n), cm(W[1 - cur], n, nb, n), sp.eye(), ld, theta, bf.Xb, Rb,
+           nb, bw, rn2, nullptr, 0, c.sc, c.s);
+    } else {
+      ritz(cm(V[cur], n, p, n), cm(W[cur], n, p, n), S, ld, theta, bf.Xb, Rb, nb, bw, rn2,
+           nullptr, 0, c.sc, c.s);
+    }
     const bool want_rho = fp32 && rho_age >= 10;
     if (want_rho) {
       // componentwise accuracy floor of float32 C x: || |A|^T |A| |x| ||
@@ -585,13 +601,10 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     } else {
       std::swap(Tb, Rb);
     }
-    if (p + nb > pmax) {
-      // thick restart + the previous block (GD+k); the count is
-      // min(p_min + nprev, p) by construction of restart_basis
-      restart_basis(S, ld, p, pmin, prev, ld, nprev, Y, ld, cnt, c.s);
-      const int hc = std::min(pmin + nprev, p);
-      nn(cm(V[cur], n, p, n), none<T>(n), Y, ld, 1.0, cm(V[1 - cur], n, hc, n), 0.0, c.s);
-      nn(cm(W[cur], n, p, n), none<T>(n), Y, ld, 1.0, cm(W[1 - cur], n, hc, n), 0.0, c.s);
+    if (restart_due) {
+      // thick restart + the previous block (GD+k), its products formed
+      // before the Ritz block; the count is min(p_min + nprev, p) by
+      // construction of restart_basis
       restart_project(H, ld, p, Y, ld, hc, S, ld, nb, prev2, ld, c.s);
       std::swap(prev, prev2);
       nprev = nb;
