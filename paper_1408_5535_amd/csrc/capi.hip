@@ -1099,6 +1099,9 @@ int harvest_impl(const phsvds_csr *Ain, int k, int every, int max_pairs, double 
   P1.largest = false; P1.tol = tol; P1.floor = 10.0; P1.anorm = o.anorm;
   P1.max_restarts = o.max_restarts > 0 ? o.max_restarts : 10000;
   P1.init64 = o.init_block; P1.init_cols = d.b;
+  // enough iterations to fill max_pairs twice over at `every`, then stop
+  // (the solve itself need not converge)
+  P1.max_iters = (int64_t)every * (2 * ((max_pairs + d.b - 1) / d.b) + 2);
   int count = 0;
   P1.snap = [&](int64_t it, const void *Xb, const void *Rb, const double *th, int nb,
                 const void *Xl, int nl) {

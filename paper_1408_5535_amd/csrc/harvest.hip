@@ -131,6 +131,9 @@ std::vector<int> projected_cg_block(Ctx &c, const SpMat<double> &A, const SpMat<
   copy(rmv_(cb.Res, n, nb, bw), rmv_(cb.P, n, nb, bw), c.s);
   colnorm2(rmv_(cb.Res, n, nb, bw), 0, n, rr, c.sc, c.s);
   copy(cm(rr, nb, 1, nb), cm(rr0, nb, 1, nb), c.s);
+  // no iterations asked: pairs without exact targets (T = 0), for training
+  // objectives that need none
+  if (maxit == 0) return std::vector<int>(nb, 1);
   const unsigned grid = (unsigned)std::min<int64_t>(cdiv(n * nb, 256), 4096);
   for (int it = 1; it <= maxit; ++it) {
     proj(cb.P);

@@ -183,6 +183,13 @@ def evaluate(seeds, make, nets, width=32, k=10, block=4, tol=1e-12, max_matvecs=
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--family", choices=["random", "powerlaw"], default="random",
+                    help="random: 12 per row at uniform columns; powerlaw: shifted Zipf(2) row "
+                         "lengths with mean 10 and at most 2000 (both with the diagonal shift)")
+    ap.add_argument("--k", type=int, default=10)
+    ap.add_argument("--block", type=int, default=4)
+    ap.add_argument("--max-mv", type=int, default=200_000,
+                    help="product budget of each evaluation solve")
     ap.add_argument("--train-seeds", type=int, nargs=2, default=(1000, 1020))
     ap.add_argument("--eval-seeds", type=int, nargs=2, default=(2000, 2005))
     ap.add_argument("--m", type=int, default=300_000)
@@ -206,6 +213,9 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     def make(seed):
+        if args.family == "powerlaw":
+            import workloads as wl
+            return wl.powerlaw_sparse(args.m, args.n, seed=seed)
         return random12(seed, args.m, args.n)
 
     nets, meta = {}, {}
@@ -222,9 +232,11 @@ def main(argv=None):
         elif args.init == "jacobi":
             init = jacobi_init(args.width)
             nets["gnn_init"] = init
+        # the residual objective needs no exact corrections: no CG
         mats, graphs, pairs = harvest_family(range(*args.train_seeds), make, every=args.every,
                                              max_pairs=args.max_pairs, width=args.width,
-                                             shift_scale=args.shift_scale)
+                                             shift_scale=args.shift_scale,
+                                             cg_maxit=0 if args.loss == "residual" else 1000)
         marks = sorted({args.epochs // 4 - 1, args.epochs // 2 - 1, args.epochs - 1} - {-1})
         w, hist, snaps = train(graphs, pairs, width=args.width, epochs=args.epochs, lr=args.lr,
                                init=init, checkpoints=marks, loss_kind=args.loss)
@@ -234,7 +246,8 @@ def main(argv=None):
         # evaluation seed)
         cands = ({"start": init} if init is not None else {})
         cands.update({f"epoch{e + 1}": snaps[e] for e in marks})
-        best, val = select_by_validation(cands, make, args.val_seed, width=args.width)
+        best, val = select_by_validation(cands, make, args.val_seed, width=args.width, k=args.k,
+                                         block=args.block)
         meta["validation"] = {name: v[0] for name, v in val.items()}
         meta["selected"] = best
         _say(f"[learned] validation products {meta['validation']}, selected {best}")
@@ -242,7 +255,8 @@ def main(argv=None):
         nets["gnn"] = cands[best]
         if args.out:
             np.save(args.out, cands[best].cpu().numpy())
-    rows = evaluate(range(*args.eval_seeds), make, nets, width=args.width)
+    rows = evaluate(range(*args.eval_seeds), make, nets, width=args.width, k=args.k,
+                    block=args.block, max_matvecs=args.max_mv)
     print(json.dumps({"loss_per_epoch": hist, "init": meta, "evaluation": rows}), flush=True)
 
 
