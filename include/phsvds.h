@@ -409,8 +409,8 @@ int phsvds_gnn_adam(float *w, float *m, float *v, const double *grad, int64_t nw
  * Jacobi-Davidson correction equation, 0 the projected C^-1 r.  Outputs
  * (device, n x max_pairs column-major): R, X, T; theta (host, max_pairs, the
  * Ritz values); *count pairs written.  Stage 1 stops at tolerance `tol`,
- * or after every * (2 ceil(max_pairs / block) + 2) iterations (it need not
- * converge).  cg_maxit = 0 runs no CG: every sampled pair is written with
+ * once max_pairs are written, or after 50 every (ceil(max_pairs / block) + 1)
+ * iterations (it need not converge).  cg_maxit = 0 runs no CG: every sampled pair is written with
  * T = 0, for training objectives that need no exact targets
  * (phsvds_gnn_residual_loss_grad). */
 int phsvds_harvest_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int k,

@@ -95,7 +95,7 @@ def phsvds_dynamic(A, k, tol=1e-12, block=1, precond="none", anorm=None, init_it
     m, n = A.shape
     b = block
     stats = ph.Stats()
-    pmax, pmin = ph.basis_sizes(k, b)
+    pmax, pmin = ph.basis_sizes(k, b, n=n)
     if isinstance(precond, tuple) and precond[0] == "inverse_A":
         pc1, pcB = ph.approx_A_forms(precond[1], precond[2], n)
     elif precond == "jacobi":

@@ -67,8 +67,14 @@ EPS64 = 2.0 ** -52
 DEP_DROP = 1e-10
 
 
-def basis_sizes(k: int, b: int, max_basis: int | None = None, min_restart: int | None = None):
+def basis_sizes(k: int, b: int, max_basis: int | None = None, min_restart: int | None = None,
+                n: int | None = None):
+    """(p_max, p_min): p_max = min(64, max(35, 2k + 2b)) capped at n (a basis
+    cannot outgrow the space), p_min = max(21, ceil(0.6 p_max)) capped at
+    p_max - 2b; p_min must hold a block (so n >= 3b)."""
     pmax = max_basis if max_basis else min(64, max(35, 2 * k + 2 * b))
+    if n is not None:
+        pmax = min(pmax, n)
     pmin = min_restart if min_restart else max(21, int(math.ceil(0.6 * pmax)))
     pmin = min(pmin, pmax - 2 * b)
     if pmin < b:
@@ -746,7 +752,7 @@ def phsvds(A, k, tol=1e-12, which="smallest", block=1, precond="none", X0=None, 
         raise ValueError("A must have m >= n")
     stats = Stats()
     b = block
-    pmax, pmin = basis_sizes(k, b, max_basis, min_restart)
+    pmax, pmin = basis_sizes(k, b, max_basis, min_restart, n)
     if X0 is None:
         X0 = workloads.initial_block(n, b, seed)
     pc1 = pcB = fb = None

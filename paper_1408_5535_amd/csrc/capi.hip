@@ -111,6 +111,7 @@ bool make_dims(int64_t m, int64_t n, int64_t nnz, int k, const phsvds_opts &o, D
   // locked vectors leave the basis, so k is not bounded by p_max (<= 64,
   // the size of the small dense problems)
   d.pmax = o.max_basis > 0 ? o.max_basis : std::min(64, std::max(35, 2 * k + 2 * d.b));
+  d.pmax = (int)std::min<int64_t>(d.pmax, n);  // a basis cannot outgrow the space
   d.pmin = o.min_restart > 0 ? o.min_restart : std::max(21, (int)std::ceil(0.6 * d.pmax));
   d.pmin = std::min(d.pmin, d.pmax - 2 * d.b);
   d.fp32 = o.stage1_fp32 != 0;
@@ -431,7 +432,8 @@ int svds_impl(const phsvds_csr *Ain, const phsvds_operator *Aop, int k, double t
               "resuming the second stage needs k0 >= k, the smallest end and stage2 >= 0");
   Dims d;
   PHS_REQUIRE(make_dims(m, n, nnz, k, o, d), kEinval,
-              "unsupported sizes: need 1 <= k <= 64, block <= 16, max_basis <= 64");
+              "unsupported sizes: need 1 <= k <= 64, block <= 16, max_basis <= 64 and "
+              "n >= 3 block (the basis is capped at n and must hold a restart plus a block)");
   d.jac = pkind == PHSVDS_PREC_JACOBI || pkind == PHSVDS_PREC_GNN;
   PHS_REQUIRE(!o.init_V || resume || (o.k0 >= 1 && o.k0 <= d.pmin), kEinval,
               "init_V without shifts needs 1 <= k0 <= p_min");
@@ -1099,10 +1101,11 @@ int harvest_impl(const phsvds_csr *Ain, int k, int every, int max_pairs, double 
   P1.largest = false; P1.tol = tol; P1.floor = 10.0; P1.anorm = o.anorm;
   P1.max_restarts = o.max_restarts > 0 ? o.max_restarts : 10000;
   P1.init64 = o.init_block; P1.init_cols = d.b;
-  // enough iterations to fill max_pairs twice over at `every`, then stop
-  // (the solve itself need not converge)
-  P1.max_iters = (int64_t)every * (2 * ((max_pairs + d.b - 1) / d.b) + 2);
   int count = 0;
+  // stop once max_pairs are written (the solve itself need not converge),
+  // or after 50 times the iterations that could fill them
+  P1.stop = [&]() { return count >= max_pairs; };
+  P1.max_iters = (int64_t)every * 50 * ((max_pairs + d.b - 1) / d.b + 1);
   P1.snap = [&](int64_t it, const void *Xb, const void *Rb, const double *th, int nb,
                 const void *Xl, int nl) {
     if (it % every || count >= max_pairs) return;

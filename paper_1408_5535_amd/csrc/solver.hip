@@ -566,7 +566,7 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     }
     const bool out_of_budget = res.restarts > P.max_restarts ||
                                c.over_budget() ||
-                               (P.max_iters > 0 && it > P.max_iters);
+                               (P.max_iters > 0 && it > P.max_iters) || (P.stop && P.stop());
     if (out_of_budget) {
       // the pairs still missing are returned as the leading unlocked Ritz
       // vectors of the current basis (best approximations)

@@ -91,6 +91,9 @@ struct Stage1Params {
   std::function<void(const void *, void *, int)> opC;
   // shift-invert: ||A||; the test becomes ||C^-1 x - mu x|| < tol sqrt(mu) / ||A||
   double si_anorm = 0.0;
+  // optional early stop, asked before each iteration's budget test (the
+  // run then ends as on a spent budget)
+  std::function<bool()> stop;
 };
 
 template <typename T>

@@ -251,3 +251,15 @@ def test_table1_stage1_and_rr_accuracy():
     paper_err = np.abs(printed - exact)
     # sigma >= 1e-8: at least as accurate as the paper's final values
     assert np.all(np.abs(s_rr[2:] - exact[2:]) <= np.maximum(paper_err[2:], 1e-18) * 4)
+
+
+def test_basis_capped_at_n_and_every_triplet():
+    """p_max is capped at n; with k = n the oracle returns every singular
+    value (dense SVD); n < 3b is refused."""
+    assert ph.basis_sizes(6, 1, n=6) == (6, 4)
+    A = wl.random_sparse(12, 6, 4, seed=3)
+    out = ph.phsvds(A, 6, 1e-12, block=1)
+    s = np.sort(np.linalg.svd(A.toarray(), compute_uv=False))
+    assert out["converged"] and np.allclose(out["sigma"], s, rtol=1e-12, atol=0)
+    with pytest.raises(ValueError):
+        ph.basis_sizes(4, 4, n=10)
