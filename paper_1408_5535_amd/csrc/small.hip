@@ -211,11 +211,14 @@ __global__ __launch_bounds__(256) void k_syev(const double *H, int ldh, int p, i
   const bool w0 = w == 0;
   const int n = p;
   const double eps = 2.220446049250313e-16;
-  // symmetric part of H: lane t writes row t, wave w the columns k = w mod 4
+  // symmetric part of H: lane t writes row t, wave w the columns k = w mod 4;
+  // columns n..63 are zero (the chunks of step 1 read up to column 63 with
+  // weight 0, and LDS left by an earlier kernel may hold NaN patterns)
   if (t < n) {
 #pragma unroll 4
     for (int k = w; k < n; k += 4)
       a[t * kLd + k] = 0.5 * (H[t + (int64_t)k * ldh] + H[k + (int64_t)t * ldh]);
+    for (int k = n + w; k < kSmallMax; k += 4) a[t * kLd + k] = 0.0;
   }
   if (w0) {
     hh[t] = 0.0;

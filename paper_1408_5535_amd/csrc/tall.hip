@@ -534,8 +534,9 @@ __global__ __launch_bounds__(NG > 0 ? 1024 : 256) void k_nn(TV<T> x1, TV<T> x2, 
 // with r the accumulator's row of D: every store instruction writes runs of
 // 16 consecutive rows of one output column.  A wave owns 16 rows at a time
 // and all NT column tiles of the output (one X operand feeds NT MFMAs);
-// eight K-steps of X loads are issued before their MFMAs.
-constexpr int kNmKU = 8;
+// sixteen K-steps of X loads (64 columns: every restart in one pass) are
+// issued before their MFMAs.
+constexpr int kNmKU = 16;
 
 template <typename T, int NT, bool PLAIN>
 __global__ __launch_bounds__(256) void k_nn_mfma(TV<T> x1, TV<T> x2, const double *S, int lds,
