@@ -721,14 +721,26 @@ __global__ __launch_bounds__(256) void k_ritz(TV<T> V, TV<T> W, const double *S,
     T ax[NB], aw[NB];
 #pragma unroll
     for (int c = 0; c < NB; ++c) ax[c] = aw[c] = T(0);
-    for (int j = 0; j < p; ++j) {
-      T v = V.p[r + (int64_t)j * V.cs];
-      T w = W.p[r + (int64_t)j * W.cs];
+    // eight columns of V and W (sixteen loads) in flight before their
+    // products; columns past p are not read
+    for (int j0 = 0; j0 < p; j0 += 8) {
+      T v[8], w[8];
 #pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        T sv = ss[j * kRitzMax + c];
-        ax[c] = fma(v, sv, ax[c]);
-        aw[c] = fma(w, sv, aw[c]);
+      for (int u = 0; u < 8; ++u) {
+        const int j = j0 + u;
+        v[u] = j < p ? V.p[r + (int64_t)j * V.cs] : T(0);
+        w[u] = j < p ? W.p[r + (int64_t)j * W.cs] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (j0 + u < p) {
+#pragma unroll
+          for (int c = 0; c < NB; ++c) {
+            const T sv = ss[(j0 + u) * kRitzMax + c];
+            ax[c] = fma(v[u], sv, ax[c]);
+            aw[c] = fma(w[u], sv, aw[c]);
+          }
+        }
       }
     }
 #pragma unroll
