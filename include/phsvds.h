@@ -205,6 +205,8 @@ typedef struct {
   int64_t dyn_choice, dyn_found, dyn_runs;
   int64_t dyn_on[16], dyn_iters[16], dyn_locked[16];
   double dyn_rate[16];
+  int64_t dep_cols; /* new basis columns that Gram-Schmidt found dependent on the
+                       basis and replaced by seeded random vectors */
 } phsvds_stats;
 
 /* The caller's operator in place of a CSR A (Section 3.3 accepts a matrix
@@ -284,6 +286,18 @@ int phsvds_spmm_noalloc(const phsvds_csr *A, const float *val32, int trans, int 
  * eigenvalue at the other end to theta[p-1]; other entries are untouched. */
 int phsvds_rr_eig(const double *H, int ldh, int p, int nvec, int largest, double *theta,
                   double *S, int lds, void *stream);
+
+/* Small singular value decomposition of the refined projection (Section
+ * 3.2; Algorithm 2 step 9: the smallest right singular vector of the R
+ * factor of W - sigma V): M device rows x cols column-major (ld ldm >=
+ * rows, not modified), 1 <= cols <= 64, cols <= rows <= 128.  One-sided
+ * (Hestenes) Jacobi; writes the cols singular values in ascending order to
+ * sv[0..cols) and the matching right singular vectors to the columns of Y
+ * (device cols x cols, ld ldy >= cols).  Small singular values have high
+ * relative accuracy when M is a well-conditioned matrix times a diagonal
+ * scaling of its columns.  PHSVDS_EINVAL for sizes out of range. */
+int phsvds_small_svd(const double *M, int ldm, int rows, int cols, double *sv, double *Y, int ldy,
+                     void *stream);
 
 /* Tall-skinny products of the block iteration (Algorithm 1: the
  * Rayleigh-Ritz border V^T W, the Gram-Schmidt coefficients [X_lock V]^T T

@@ -84,7 +84,8 @@ class _Stats(ctypes.Structure):
                [("res_stage1", ctypes.c_double * 64)] + \
                [(f, ctypes.c_int64) for f in ("dyn_choice", "dyn_found", "dyn_runs")] + \
                [(f, ctypes.c_int64 * 16) for f in ("dyn_on", "dyn_iters", "dyn_locked")] + \
-               [("dyn_rate", ctypes.c_double * 16)]
+               [("dyn_rate", ctypes.c_double * 16)] + \
+               [("dep_cols", ctypes.c_int64)]
 
     _ARRAYS = ("res_stage1", "dyn_on", "dyn_iters", "dyn_locked", "dyn_rate")
 
@@ -109,6 +110,8 @@ _lib.phsvds_spmm_f64.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int, _P, _P, cty
 _lib.phsvds_spmm_f32.argtypes = [ctypes.POINTER(_Csr), _P, ctypes.c_int, _P, _P, ctypes.c_int, _P]
 _lib.phsvds_rr_eig.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P,
                                _P, ctypes.c_int, _P]
+_lib.phsvds_small_svd.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P,
+                                  ctypes.c_int, _P]
 _lib.phsvds_transpose_ws_bytes.argtypes = [ctypes.POINTER(_Csr)]
 _lib.phsvds_transpose_ws_bytes.restype = ctypes.c_size_t
 _lib.phsvds_csr_transpose.argtypes = [ctypes.POINTER(_Csr), _P, _P, _P, _P, ctypes.c_size_t, _P]
@@ -352,6 +355,19 @@ def rr_eig(H: torch.Tensor, nvec: int, largest: bool = False):
     _check(_lib.phsvds_rr_eig(Hc.data_ptr(), p, p, nvec, int(largest), theta.data_ptr(),
                               S.data_ptr(), p, _stream()), "rr_eig")
     return theta, S.t()
+
+
+def small_svd(M: torch.Tensor):
+    """Singular values (ascending, (cols,)) and right singular vectors
+    (cols x cols, column j for sv[j]) of the small device float64 matrix M
+    (rows x cols, cols <= 64, cols <= rows <= 128)."""
+    rows, cols = M.shape
+    Mc = M.to(dtype=torch.float64).t().contiguous()  # column-major
+    sv = torch.empty(cols, dtype=torch.float64, device=M.device)
+    Y = torch.empty((cols, cols), dtype=torch.float64, device=M.device)
+    _check(_lib.phsvds_small_svd(Mc.data_ptr(), rows, rows, cols, sv.data_ptr(), Y.data_ptr(),
+                                 cols, _stream()), "small_svd")
+    return sv, Y.t()
 
 
 def csr_transpose(A: DeviceCSR) -> DeviceCSR:

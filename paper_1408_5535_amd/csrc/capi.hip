@@ -1185,6 +1185,16 @@ int phsvds_rr_eig(const double *H, int ldh, int p, int nvec, int largest, double
   });
 }
 
+int phsvds_small_svd(const double *M, int ldm, int rows, int cols, double *sv, double *Y, int ldy,
+                     void *stream) {
+  return guarded([&]() {
+    PHS_REQUIRE(M && sv && Y, kEinval, "null argument");
+    PHS_REQUIRE(ldm >= rows && ldy >= cols, kEinval, "leading dimension too small");
+    svdj(M, ldm, rows, cols, sv, Y, ldy, (hipStream_t)stream);
+    return PHSVDS_OK;
+  });
+}
+
 int phsvds_spmm_f32(const phsvds_csr *A, const float *val32, int b, const float *X, float *Y,
                     int absval, void *stream) {
   return guarded([&]() {

@@ -116,6 +116,7 @@ void orth_block(Ctx &c, T *&Tb, T *&T2b, int64_t n, int nb, int bw, const Tall<T
       for (int j : dep) {
         Tall<T> col = rmv(Tb + j, n, 1, bw);
         fill_random(col, c.seed, 1000000 + (c.nrand++) * 64, c.s);
+        ++c.st->dep_cols;
       }
       continue;
     }
@@ -184,6 +185,7 @@ void cgs_cols(Ctx &c, double *X, int64_t rows, int64_t ld, int j0, int j1, doubl
         c.sync();
         if (!(h[0] > 0.0) || !(std::sqrt(h[1]) > kDepDropF64 * std::sqrt(h[0]))) {
           fill_random(xj, c.seed, 2000000 + (c.nrand++) * 64, c.s);
+          ++c.st->dep_cols;
           continue;
         }
       }

@@ -79,7 +79,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     import paper_1408_5535_amd as P
     checks = {"phsvds_opts": (P._Opts, ["dynamic", "max_switch", "shifts", "k0", "c_apply",
                                         "c_inverse"]),
-              "phsvds_stats": (P._Stats, ["dyn_choice", "dyn_rate", "res_stage1", "inner2"]),
+              "phsvds_stats": (P._Stats, ["dyn_choice", "dyn_rate", "res_stage1", "inner2",
+                                          "dep_cols"]),
               "phsvds_precond": (P._Precond, ["user_solve", "user_apply_B", "user_ctx"])}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "phsvds.h"', "int main(void) {"]
     for st, (_, fields) in checks.items():

@@ -85,3 +85,32 @@ def test_space_too_small_for_the_block_is_einval():
         P.svds_smallest(to_dev(A), 4, 1e-12, block=4)
     with pytest.raises(ValueError):
         ph.phsvds(A, 4, 1e-12, block=4)
+
+
+@gpu
+def test_initial_columns_dependent_on_the_basis_are_replaced():
+    """A caller's start block [x, y, x, z] at block 2: after the first chunk
+    [x, y] the repeated x of the second chunk has no component left outside
+    the basis, so Gram-Schmidt replaces it by a seeded random vector
+    (stats dep_cols) and the solve still finds the closed-form values."""
+    need_gpu()
+    import torch
+
+    import paper_1408_5535_amd as P
+    A = wl.grid_gradient(16)
+    N = 16
+    i = np.arange(1, N + 1)
+    s2 = 4 * np.sin(i * np.pi / (2 * (N + 1))) ** 2
+    ex = np.sort(np.sqrt((s2[:, None] + s2[None, :]).ravel()))[:4]
+    r = np.random.default_rng(5)
+    x, y, z = (r.standard_normal(A.shape[1]) for _ in range(3))
+    X0 = np.column_stack([x, y, x, z])
+    say("dependent start columns", A.shape, "k0", X0.shape[1])
+    sig, U, V, info = P.svds_smallest(to_dev(A), 4, 1e-12, block=2, anorm=float(np.sqrt(8.0)),
+                                      init_V=torch.tensor(X0))
+    say({q: info[q] for q in ("status", "mv_total", "dep_cols")})
+    assert info["dep_cols"] >= 1
+    assert info["status"] == 0
+    assert np.all(np.abs(sig - ex) <= 1e-10 * ex), (sig, ex)
+    res = dense.triplet_residuals(A, sig, as_np(U), as_np(V))
+    assert np.all(res <= 1e-12 * np.sqrt(8.0)), res

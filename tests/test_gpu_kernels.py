@@ -173,3 +173,61 @@ def test_spmm_full_size_sampled_rows(family, dtype):
     zref = AcT @ Yin
     zb = (cl[cols] + 2)[:, None] * u * (abs(AcT) @ abs(Yin)) + 1e-300
     assert np.all(np.abs(Zh - zref) <= zb)
+
+
+def _svd_cases():
+    r = np.random.default_rng(11)
+    out = [("random 20x10", r.standard_normal((20, 10))),
+           ("square 64", r.standard_normal((64, 64))),
+           ("128x64", r.standard_normal((128, 64))),
+           ("odd 33x7", r.standard_normal((33, 7))),
+           ("1x1", np.array([[-3.0]]))]
+    # two equal columns: a zero singular value
+    M = r.standard_normal((16, 8))
+    M[:, 5] = M[:, 2]
+    out.append(("rank-deficient", M))
+    # singular value 1 of multiplicity three
+    Q1, _ = np.linalg.qr(r.standard_normal((30, 12)))
+    Q2, _ = np.linalg.qr(r.standard_normal((12, 12)))
+    out.append(("repeated", (Q1 * np.r_[1.0, 1.0, 1.0, np.linspace(0.1, 0.9, 9)]) @ Q2.T))
+    # column-graded: well-conditioned B times diag(1 .. 1e-12)
+    out.append(("graded", r.standard_normal((40, 12)) * np.logspace(0, -12, 12)))
+    return out
+
+
+@gpu
+@pytest.mark.parametrize("case", range(8))
+def test_small_svd_vs_lapack_and_jacobi(case):
+    """The refined projection's small SVD (one-sided Jacobi on the GPU):
+    singular values against LAPACK (numpy) within 1e-14 sigma_max; for the
+    column-graded case against the oracle's float64 one-sided Jacobi within
+    1e-12 relative, since there LAPACK's absolute accuracy says nothing of
+    the small values; right vectors orthonormal and ||M y_j|| = sigma_j."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    from oracle.dense import jacobi_svd
+    name, M = _svd_cases()[case]
+    rows, cols = M.shape
+    say("small_svd", name, rows, "x", cols)
+    sv, Y = P.small_svd(torch.tensor(M, device="cuda"))
+    sv, Y = as_np(sv), as_np(Y)
+    smax = np.linalg.norm(M, 2)
+    assert np.all(np.diff(sv) >= 0), sv
+    ref = np.sort(np.linalg.svd(M, compute_uv=False))
+    assert np.max(np.abs(sv - ref)) <= 1e-14 * smax + 1e-300, (name, sv, ref)
+    if name == "graded":
+        _, sj, _ = jacobi_svd(M)
+        sj = np.sort(sj)
+        assert np.all(np.abs(sv - sj) <= 1e-12 * sj), (sv, sj)
+    assert np.max(np.abs(Y.T @ Y - np.eye(cols))) <= 1e-13, name
+    got = np.linalg.norm(M @ Y, axis=0)
+    assert np.all(np.abs(got - sv) <= 1e-14 * smax + 1e-12 * sv), (name, got, sv)
+
+
+@gpu
+def test_small_svd_rejects_sizes_out_of_range():
+    need_gpu()
+    import paper_1408_5535_amd as P
+    for shape in ((10, 20), (200, 10), (70, 65)):
+        with pytest.raises(RuntimeError):
+            P.small_svd(torch.zeros(shape, dtype=torch.float64, device="cuda"))
