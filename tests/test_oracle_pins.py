@@ -263,3 +263,25 @@ def test_basis_capped_at_n_and_every_triplet():
     assert out["converged"] and np.allclose(out["sigma"], s, rtol=1e-12, atol=0)
     with pytest.raises(ValueError):
         ph.basis_sizes(4, 4, n=10)
+
+
+def test_triplet_residual_checker_closed_forms():
+    """The residual every solver test applies, pinned by hand-made triplets
+    of A = [diag(s); 0] (m > n): exact triplets give 0; moving u by delta
+    along another coordinate j gives delta sqrt(s_i^2 + s_j^2) for j < n
+    and delta s_i for a zero row j >= n (where A^T e_j = 0, which a
+    transposition mistake would miss); flipping the sign of u gives
+    2 sqrt(2) s_i (which a sign mistake would not)."""
+    import scipy.sparse as sp
+    m, n = 9, 5
+    s = np.array([0.3, 1.0, 2.0, 2.5, 4.0])
+    A = sp.csr_matrix(np.vstack([np.diag(s), np.zeros((m - n, n))]))
+    U, V = np.eye(m)[:, :n], np.eye(n)
+    assert np.all(dense.triplet_residuals(A, s, U, V) == 0.0)
+    delta, i = 1e-3, 1
+    for j, want in ((3, delta * np.hypot(s[i], s[3])), (7, delta * s[i])):
+        u = np.eye(m)[:, i] + delta * np.eye(m)[:, j]
+        got = dense.triplet_residuals(A, [s[i]], u[:, None], V[:, i:i + 1])[0]
+        assert abs(got - want) <= 1e-15, (j, got, want)
+    got = dense.triplet_residuals(A, s, -U, V)
+    assert np.allclose(got, 2 * np.sqrt(2) * s, rtol=1e-15)
