@@ -150,7 +150,9 @@ struct Plan {
   double *tva;
   char *tws;
   size_t tws_bytes;
-  int32_t *binA, *binAt, *binScr;
+  int32_t *binA, *binAt, *pinv;
+  char *binWs;
+  size_t binWs_bytes;
   float *va32, *tva32;
   double *diagC;
   Scratch sc;
@@ -180,7 +182,9 @@ void carve(Arena &ar, const Dims &d, Plan &p) {
   p.tws = ar.take<char>(p.tws_bytes);
   p.binA = ar.take<int32_t>(m);
   p.binAt = ar.take<int32_t>(n);
-  p.binScr = ar.take<int32_t>(16);
+  p.pinv = ar.take<int32_t>(std::max<int64_t>(m, 1));
+  p.binWs_bytes = bin_ws_bytes(std::max(m, n));
+  p.binWs = ar.take<char>(p.binWs_bytes);
   p.va32 = d.fp32 ? ar.take<float>(nnz) : nullptr;
   p.tva32 = d.fp32 ? ar.take<float>(nnz) : nullptr;
   p.diagC = ar.take<double>(n);
@@ -478,6 +482,7 @@ int svds_impl(const phsvds_csr *Ain, const phsvds_operator *Aop, int k, double t
   At64.n = m;
   At64.nnz = nnz;
   OpHook hook;
+  bool row_perm = false;  // row space in bin order (set below)
   if (Aop) {
     // the caller's operator (Section 3.3): every product of the path goes
     // through it, on the solver's stream
@@ -497,12 +502,23 @@ int svds_impl(const phsvds_csr *Ain, const phsvds_operator *Aop, int k, double t
     At64.rowptr = pl.trp;
     At64.colind = pl.tci;
     At64.val = pl.tva;
-    build_bins(m, A64.rowptr, pl.binA, pl.binScr, A64.bins, &A64.nbins, c.s);
+    build_bins(m, A64.rowptr, pl.binA, pl.binWs, pl.binWs_bytes, A64.bins, &A64.nbins, c.s);
     A64.binrows = pl.binA;
     if (A64.nbins == 1) A64.nbins = 0;
-    build_bins(n, At64.rowptr, pl.binAt, pl.binScr, At64.bins, &At64.nbins, c.s);
+    build_bins(n, At64.rowptr, pl.binAt, pl.binWs, pl.binWs_bytes, At64.bins, &At64.nbins, c.s);
     At64.binrows = pl.binAt;
     if (At64.nbins == 1) At64.nbins = 0;
+    // rows of A of several length classes: the row space (A X, the left
+    // vectors, the top of B's vectors) is kept in bin order, so that the
+    // long rows, which A^T gathers most often, share cache lines.  Products
+    // and sums over the columns are unchanged (A^T takes each row in its
+    // original order); U is returned in the caller's order.  Not with the
+    // preconditioner forms that take row-space vectors from the caller.
+    row_perm = A64.nbins >= 2 && pkind != PHSVDS_PREC_USER_A && !(Pc && Pc->user_apply_B);
+    if (row_perm) {
+      permute_row_space(m, nnz, pl.binA, pl.pinv, pl.tci, c.s);
+      A64.slot_out = true;
+    }
   }
   SpMat<float> A32, At32;
   if (d.fp32) {
@@ -510,6 +526,7 @@ int svds_impl(const phsvds_csr *Ain, const phsvds_operator *Aop, int k, double t
     copy(cm(pl.tva, nnz, 1, nnz), cm(pl.tva32, nnz, 1, nnz), c.s);
     A32.m = m; A32.n = n; A32.nnz = nnz; A32.rowptr = A64.rowptr; A32.colind = A64.colind;
     A32.val = pl.va32; A32.nbins = A64.nbins; A32.binrows = A64.binrows;
+    A32.slot_out = A64.slot_out;
     std::memcpy(A32.bins, A64.bins, sizeof(A64.bins));
     At32.m = n; At32.n = m; At32.nnz = nnz; At32.rowptr = At64.rowptr; At32.colind = At64.colind;
     At32.val = pl.tva32; At32.nbins = At64.nbins; At32.binrows = At64.binrows;
@@ -1030,7 +1047,10 @@ int svds_impl(const phsvds_csr *Ain, const phsvds_operator *Aop, int k, double t
     if (i < ntot) {
       int j = fo[i];
       copy(cm(Vsrc + (int64_t)j * n, n, 1, n), cm(Vout + (int64_t)i * n, n, 1, n), c.s);
-      copy(cm(Usrc + (int64_t)j * m, m, 1, m), cm(Uout + (int64_t)i * m, m, 1, m), c.s);
+      if (row_perm)
+        unpermute_rows(m, 1, pl.binA, Usrc + (int64_t)j * m, Uout + (int64_t)i * m, c.s);
+      else
+        copy(cm(Usrc + (int64_t)j * m, m, 1, m), cm(Uout + (int64_t)i * m, m, 1, m), c.s);
       sigma[i] = sig[j];
       resnorm[i] = res[j];
     } else {

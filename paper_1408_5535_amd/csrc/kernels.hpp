@@ -30,6 +30,9 @@ struct SpMat {
   int nbins = 0;  // 0: one launch over all rows
   Bin bins[8];
   const int32_t *binrows = nullptr;
+  // binned products write the result of row binrows[q] to row q (the row
+  // space of the result is in bin order)
+  bool slot_out = false;
   const OpHook *op = nullptr;
   bool op_trans = false;  // this SpMat is A^T of the operator
 };
@@ -56,8 +59,19 @@ size_t spmm_t_ws_bytes(int64_t m, int64_t n, int64_t nnz, bool fp32);
 void csr_transpose(int64_t m, int64_t n, int64_t nnz, const int64_t *rp, const int32_t *ci,
                    const double *va, int64_t *trp, int32_t *tci, double *tva, void *ws,
                    size_t ws_bytes, hipStream_t s);
-void build_bins(int64_t m, const int64_t *rp, int32_t *rows, int32_t *scratch, Bin *bins,
+// Row-length bins: rows lists the rows of each bin in ascending order, the
+// bins one after another (bin_ws_bytes(m) bytes of scratch).
+size_t bin_ws_bytes(int64_t m);
+void build_bins(int64_t m, const int64_t *rp, int32_t *rows, void *ws, size_t ws_bytes, Bin *bins,
                 int *nbins, hipStream_t s);
+// Row space in bin order: inv = rows^-1, and the column indices of A^T
+// (rows of A) renumbered through it, so that products A X written by slot
+// (SpMat::slot_out) feed A^T directly.
+void permute_row_space(int64_t m, int64_t nnz, const int32_t *rows, int32_t *inv, int32_t *tci,
+                       hipStream_t s);
+// dst[rows[q], j] = src[q, j] for w columns of length m (ld m).
+void unpermute_rows(int64_t m, int w, const int32_t *rows, const double *src, double *dst,
+                    hipStream_t s);
 
 // ------------------------------------------------------------- tall blocks
 // A tall matrix view: element (i, j) at p[i * rs + j * cs].  Column-major

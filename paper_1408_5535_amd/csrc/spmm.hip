@@ -87,7 +87,7 @@ __device__ inline int64_t xcd_block() {
 
 template <typename T, int B, int G, bool ABS>
 __global__ __launch_bounds__(256) void k_spmm(int64_t nrows, const int32_t *__restrict__ rows,
-                                              const int64_t *__restrict__ rp,
+                                              int64_t yslot, const int64_t *__restrict__ rp,
                                               const int32_t *__restrict__ ci,
                                               const T *__restrict__ va,
                                               const T *__restrict__ X, T *__restrict__ Y,
@@ -146,18 +146,21 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nrows, const int32_t *__re
     }
   }
   if (g == 0) {
+    // the result row goes to the row's own index, or (yslot >= 0) to its
+    // position yslot + slot in the order of the bins
+    const int64_t yr = yslot >= 0 ? yslot + slot : row;
     if (ycm == 0) {
-      store_chunk<T, CW>(Y + row * B + part * CW, acc);
+      store_chunk<T, CW>(Y + yr * B + part * CW, acc);
     } else {
 #pragma unroll
       for (int j = 0; j < CW; ++j)
-        if (part * CW + j < ycols) Y[row + (int64_t)(part * CW + j) * ycm] = acc[j];
+        if (part * CW + j < ycols) Y[yr + (int64_t)(part * CW + j) * ycm] = acc[j];
     }
   }
 }
 
 template <typename T, int B, bool ABS>
-static void launch_g(int G, int64_t nrows, const int32_t *rows, const int64_t *rp,
+static void launch_g(int G, int64_t nrows, const int32_t *rows, int64_t yslot, const int64_t *rp,
                      const int32_t *ci, const T *va, const T *X, T *Y, int64_t ycm, int ycols,
                      hipStream_t s) {
   if (nrows <= 0) return;
@@ -167,37 +170,38 @@ static void launch_g(int G, int64_t nrows, const int32_t *rows, const int64_t *r
   const int64_t threads = nrows * G * VL;
   dim3 grid(cdiv(threads, 256));
   switch (G) {
-    case 1: k_spmm<T, B, 1, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y, ycm, ycols); break;
-    case 2: k_spmm<T, B, 2, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y, ycm, ycols); break;
-    case 4: k_spmm<T, B, 4, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y, ycm, ycols); break;
-    case 8: k_spmm<T, B, 8, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y, ycm, ycols); break;
+    case 1: k_spmm<T, B, 1, ABS><<<grid, 256, 0, s>>>(nrows, rows, yslot, rp, ci, va, X, Y, ycm, ycols); break;
+    case 2: k_spmm<T, B, 2, ABS><<<grid, 256, 0, s>>>(nrows, rows, yslot, rp, ci, va, X, Y, ycm, ycols); break;
+    case 4: k_spmm<T, B, 4, ABS><<<grid, 256, 0, s>>>(nrows, rows, yslot, rp, ci, va, X, Y, ycm, ycols); break;
+    case 8: k_spmm<T, B, 8, ABS><<<grid, 256, 0, s>>>(nrows, rows, yslot, rp, ci, va, X, Y, ycm, ycols); break;
     case 16:
       if constexpr (Gmax >= 16)
-        k_spmm<T, B, 16, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y, ycm, ycols);
+        k_spmm<T, B, 16, ABS><<<grid, 256, 0, s>>>(nrows, rows, yslot, rp, ci, va, X, Y, ycm, ycols);
       break;
     case 32:
       if constexpr (Gmax >= 32)
-        k_spmm<T, B, 32, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y, ycm, ycols);
+        k_spmm<T, B, 32, ABS><<<grid, 256, 0, s>>>(nrows, rows, yslot, rp, ci, va, X, Y, ycm, ycols);
       break;
     default:
       if constexpr (Gmax >= 64)
-        k_spmm<T, B, 64, ABS><<<grid, 256, 0, s>>>(nrows, rows, rp, ci, va, X, Y, ycm, ycols);
+        k_spmm<T, B, 64, ABS><<<grid, 256, 0, s>>>(nrows, rows, yslot, rp, ci, va, X, Y, ycm, ycols);
       break;
   }
   PHS_CHECK_LAUNCH();
 }
 
 template <typename T, bool ABS>
-static void launch_b(int b, int G, int64_t nrows, const int32_t *rows, const int64_t *rp,
+static void launch_b(int b, int G, int64_t nrows, const int32_t *rows, int64_t yslot,
+                     const int64_t *rp,
                      const int32_t *ci, const T *va, const T *X, T *Y, int64_t ycm, int ycols,
                      hipStream_t s) {
   switch (b) {
-    case 1: launch_g<T, 1, ABS>(G, nrows, rows, rp, ci, va, X, Y, ycm, ycols, s); break;
-    case 2: launch_g<T, 2, ABS>(G, nrows, rows, rp, ci, va, X, Y, ycm, ycols, s); break;
-    case 4: launch_g<T, 4, ABS>(G, nrows, rows, rp, ci, va, X, Y, ycm, ycols, s); break;
-    case 8: launch_g<T, 8, ABS>(G, nrows, rows, rp, ci, va, X, Y, ycm, ycols, s); break;
-    case 16: launch_g<T, 16, ABS>(G, nrows, rows, rp, ci, va, X, Y, ycm, ycols, s); break;
-    case 32: launch_g<T, 32, ABS>(G, nrows, rows, rp, ci, va, X, Y, ycm, ycols, s); break;
+    case 1: launch_g<T, 1, ABS>(G, nrows, rows, yslot, rp, ci, va, X, Y, ycm, ycols, s); break;
+    case 2: launch_g<T, 2, ABS>(G, nrows, rows, yslot, rp, ci, va, X, Y, ycm, ycols, s); break;
+    case 4: launch_g<T, 4, ABS>(G, nrows, rows, yslot, rp, ci, va, X, Y, ycm, ycols, s); break;
+    case 8: launch_g<T, 8, ABS>(G, nrows, rows, yslot, rp, ci, va, X, Y, ycm, ycols, s); break;
+    case 16: launch_g<T, 16, ABS>(G, nrows, rows, yslot, rp, ci, va, X, Y, ycm, ycols, s); break;
+    case 32: launch_g<T, 32, ABS>(G, nrows, rows, yslot, rp, ci, va, X, Y, ycm, ycols, s); break;
     default: throw Error(kEinval, "spmm: block width must be 1, 2, 4, 8, 16 or 32");
   }
 }
@@ -242,19 +246,20 @@ void spmm_launch(const SpMat<T> &A, int b, const T *X, T *Y, bool absval, int64_
   if (A.nbins == 0) {
     const int G = lanes_for_length(A.m ? (double)A.nnz / (double)A.m : 0.0);
     if (absval)
-      launch_b<T, true>(b, G, A.m, nullptr, A.rowptr, A.colind, A.val, X, Y, ycm, ycols, s);
+      launch_b<T, true>(b, G, A.m, nullptr, -1, A.rowptr, A.colind, A.val, X, Y, ycm, ycols, s);
     else
-      launch_b<T, false>(b, G, A.m, nullptr, A.rowptr, A.colind, A.val, X, Y, ycm, ycols, s);
+      launch_b<T, false>(b, G, A.m, nullptr, -1, A.rowptr, A.colind, A.val, X, Y, ycm, ycols, s);
     return;
   }
   for (int k = 0; k < A.nbins; ++k) {
     const Bin &bn = A.bins[k];
+    const int64_t ys = A.slot_out ? bn.offset : -1;
     if (absval)
-      launch_b<T, true>(b, bn.lanes, bn.count, A.binrows + bn.offset, A.rowptr, A.colind, A.val,
-                        X, Y, ycm, ycols, s);
+      launch_b<T, true>(b, bn.lanes, bn.count, A.binrows + bn.offset, ys, A.rowptr, A.colind,
+                        A.val, X, Y, ycm, ycols, s);
     else
-      launch_b<T, false>(b, bn.lanes, bn.count, A.binrows + bn.offset, A.rowptr, A.colind, A.val,
-                         X, Y, ycm, ycols, s);
+      launch_b<T, false>(b, bn.lanes, bn.count, A.binrows + bn.offset, ys, A.rowptr, A.colind,
+                         A.val, X, Y, ycm, ycols, s);
   }
 }
 template <typename T>
@@ -510,7 +515,7 @@ __device__ inline int bin_of(int64_t len) {
   return g;
 }
 
-// Per-block counts in LDS, one global atomic per bin and block.
+// Per-block counts in LDS, one global atomic per bin and block (the totals).
 __global__ __launch_bounds__(256) void k_bin_count(int64_t m, const int64_t *__restrict__ rp,
                                                    int32_t *cnt) {
   __shared__ int32_t h[8];
@@ -522,12 +527,25 @@ __global__ __launch_bounds__(256) void k_bin_count(int64_t m, const int64_t *__r
   if (threadIdx.x < 7 && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
 }
 
-// Each block places its rows of a bin contiguously and in ascending order
-// (ranks from wavefront ballots), at an offset taken by one atomic per bin.
-__global__ __launch_bounds__(256) void k_bin_fill(int64_t m, const int64_t *__restrict__ rp,
-                                                  const int32_t *offs, int32_t *fill,
-                                                  int32_t *rows) {
-  __shared__ int32_t wc[4][8], base[8];
+// Each block's count per bin, bin-major: bc[g * nblk + block].
+__global__ __launch_bounds__(256) void k_bin_blkcount(int64_t m, const int64_t *__restrict__ rp,
+                                                      int64_t nblk, int32_t *bc) {
+  __shared__ int32_t h[8];
+  if (threadIdx.x < 8) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < m) atomicAdd(&h[bin_of(rp[r + 1] - rp[r])], 1);
+  __syncthreads();
+  if (threadIdx.x < 7) bc[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// Places each row at the exclusive scan of the block counts (bin-major)
+// plus its rank among the block's rows of its bin (wavefront ballots), so
+// that the rows of every bin come in ascending order.
+__global__ __launch_bounds__(256) void k_bin_place(int64_t m, const int64_t *__restrict__ rp,
+                                                   int64_t nblk, const int64_t *off,
+                                                   int32_t *rows) {
+  __shared__ int32_t wc[4][8];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int g = r < m ? bin_of(rp[r + 1] - rp[r]) : -1;
@@ -538,48 +556,97 @@ __global__ __launch_bounds__(256) void k_bin_fill(int64_t m, const int64_t *__re
     if (lane == 0) wc[w][b] = __popcll(bal);
   }
   __syncthreads();
-  if (threadIdx.x < 7) {
-    const int b = threadIdx.x;
-    const int tot = wc[0][b] + wc[1][b] + wc[2][b] + wc[3][b];
-    base[b] = tot ? atomicAdd(&fill[b], tot) : 0;
-  }
-  __syncthreads();
   if (g >= 0) {
     int pre = 0;
     for (int v = 0; v < w; ++v) pre += wc[v][g];
-    rows[offs[g] + base[g] + pre + rank] = (int32_t)r;
+    rows[off[g * nblk + blockIdx.x] + pre + rank] = (int32_t)r;
   }
 }
 
-// Rows of a bin come in block chunks (in the order the atomics hand out);
-// every row is computed by one group in a fixed order, so results are
-// deterministic.
-void build_bins(int64_t m, const int64_t *rp, int32_t *rows, int32_t *scratch, Bin *bins,
+size_t bin_ws_bytes(int64_t m) {
+  const int64_t nblk = cdiv(std::max<int64_t>(m, 1), 256), E = 7 * nblk;
+  Arena ar;
+  ar.dry = true;
+  ar.take<int32_t>(16);               // totals per bin
+  ar.take<int32_t>(E);                // block counts
+  ar.take<int64_t>(cdiv(E, kScanTile));  // tile sums
+  ar.take<int64_t>(E + 1);            // their exclusive scan
+  return ar.used;
+}
+
+// Row-length bins, with rows[] listing the rows of bin 0, then bin 1, ...
+// each in ascending order (a permutation of 0..m-1 that depends only on the
+// row lengths).
+void build_bins(int64_t m, const int64_t *rp, int32_t *rows, void *ws, size_t ws_bytes, Bin *bins,
                 int *nbins, hipStream_t s) {
-  // scratch: 16 int32 (counts, offsets, fill)
-  zero_fill(scratch, 16, s);
-  k_bin_count<<<cdiv(m, 256), 256, 0, s>>>(m, rp, scratch);
-  PHS_CHECK_LAUNCH();
-  int32_t cnt[7];
-  PHS_HIP(hipMemcpyAsync(cnt, scratch, 7 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  const int64_t nblk = cdiv(std::max<int64_t>(m, 1), 256), E = 7 * nblk;
+  Arena ar;
+  ar.base = (char *)ws;
+  ar.size = ws_bytes;
+  int32_t *tot = ar.take<int32_t>(16);
+  int32_t *bc = ar.take<int32_t>(E);
+  int64_t *tsum = ar.take<int64_t>(cdiv(E, kScanTile));
+  int64_t *off = ar.take<int64_t>(E + 1);
+  zero_fill(tot, 16, s);
+  if (m > 0) {
+    k_bin_count<<<cdiv(m, 256), 256, 0, s>>>(m, rp, tot);
+    k_bin_blkcount<<<nblk, 256, 0, s>>>(m, rp, nblk, bc);
+    PHS_CHECK_LAUNCH();
+    const int64_t ntiles = cdiv(E, kScanTile);
+    k_tile_sums<<<ntiles, 256, 0, s>>>(E, bc, tsum);
+    k_scan_tiles<<<1, 256, 0, s>>>(ntiles, tsum);
+    k_tile_scan<<<ntiles, 256, 0, s>>>(E, bc, tsum, off);
+    k_bin_place<<<nblk, 256, 0, s>>>(m, rp, nblk, off, rows);
+    PHS_CHECK_LAUNCH();
+  }
+  int32_t cnt[7] = {0, 0, 0, 0, 0, 0, 0};
+  PHS_HIP(hipMemcpyAsync(cnt, tot, 7 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   PHS_HIP(hipStreamSynchronize(s));
-  int32_t offs[8];
-  offs[0] = 0;
-  for (int g = 0; g < 7; ++g) offs[g + 1] = offs[g] + cnt[g];
-  PHS_HIP(hipMemcpyAsync(scratch + 8, offs, 7 * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  zero_fill(scratch, 7, s);
-  k_bin_fill<<<cdiv(m, 256), 256, 0, s>>>(m, rp, scratch + 8, scratch, rows);
-  PHS_CHECK_LAUNCH();
-  int nb = 0;
+  int nb = 0, o = 0;
   for (int g = 0; g < 7; ++g) {
-    if (cnt[g] == 0) continue;
-    bins[nb].offset = offs[g];
-    bins[nb].count = cnt[g];
-    bins[nb].lanes = 1 << g;
-    ++nb;
+    if (cnt[g] > 0) {
+      bins[nb].offset = o;
+      bins[nb].count = cnt[g];
+      bins[nb].lanes = 1 << g;
+      ++nb;
+    }
+    o += cnt[g];
   }
   *nbins = nb;
-  PHS_HIP(hipStreamSynchronize(s));
+}
+
+// inv[rows[q]] = q
+__global__ void k_invert_perm(int64_t m, const int32_t *__restrict__ rows, int32_t *inv) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < m) inv[rows[q]] = (int32_t)q;
+}
+// ci[p] <- inv[ci[p]]
+__global__ void k_remap_idx(int64_t nnz, const int32_t *__restrict__ inv, int32_t *ci) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nnz) ci[p] = inv[ci[p]];
+}
+// dst[rows[q]] = src[q] for each of w columns (ld m)
+__global__ void k_unpermute_cols(int64_t m, int w, const int32_t *__restrict__ rows,
+                                 const double *__restrict__ src, double *dst) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const int64_t r = rows[q];
+  for (int j = 0; j < w; ++j) dst[r + (int64_t)j * m] = src[q + (int64_t)j * m];
+}
+
+void permute_row_space(int64_t m, int64_t nnz, const int32_t *rows, int32_t *inv, int32_t *tci,
+                       hipStream_t s) {
+  if (m <= 0) return;
+  k_invert_perm<<<cdiv(m, 256), 256, 0, s>>>(m, rows, inv);
+  if (nnz > 0) k_remap_idx<<<cdiv(nnz, 256), 256, 0, s>>>(nnz, inv, tci);
+  PHS_CHECK_LAUNCH();
+}
+
+void unpermute_rows(int64_t m, int w, const int32_t *rows, const double *src, double *dst,
+                    hipStream_t s) {
+  if (m <= 0 || w <= 0) return;
+  k_unpermute_cols<<<cdiv(m, 256), 256, 0, s>>>(m, w, rows, src, dst);
+  PHS_CHECK_LAUNCH();
 }
 
 }  // namespace phs
