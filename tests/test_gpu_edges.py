@@ -114,3 +114,33 @@ def test_initial_columns_dependent_on_the_basis_are_replaced():
     assert np.all(np.abs(sig - ex) <= 1e-10 * ex), (sig, ex)
     res = dense.triplet_residuals(A, sig, as_np(U), as_np(V))
     assert np.all(res <= 1e-12 * np.sqrt(8.0)), res
+
+
+@gpu
+@pytest.mark.parametrize("fp32", [False, True])
+def test_power_law_rows_left_vectors_in_the_callers_order(fp32):
+    """Rows of seven length classes (power law, 2000 x 1000): the solver
+    keeps the row space in bin order internally; sigma against LAPACK and
+    the oracle, residuals within tol ||A||, and U against LAPACK's left
+    vectors up to sign, in the caller's row order."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A = wl.powerlaw_sparse(2000, 1000, mean=10, kmax=200, seed=41)
+    assert len(np.unique(np.minimum(np.ceil(np.log2(np.maximum(np.diff(A.indptr), 4) / 4)),
+                                     6))) >= 5
+    Ud, s_all, Vdt = np.linalg.svd(A.toarray(), full_matrices=False)
+    an = float(s_all[0])
+    k = 4
+    ex, Uex = s_all[::-1][:k], Ud[:, ::-1][:, :k]
+    say("power-law rows", A.shape, "fp32", fp32)
+    sig, U, V, info = P.svds_smallest(to_dev(A), k, 1e-12, block=2, anorm=an,
+                                      stage1_fp32=fp32)
+    say({q: info[q] for q in ("status", "mv_total", "stage2_pairs")})
+    assert info["status"] == 0
+    assert np.all(np.abs(sig - ex) <= 1e-10 * ex), (sig, ex)
+    Un = as_np(U)
+    res = dense.triplet_residuals(A, sig, Un, as_np(V))
+    assert np.all(res <= 1e-12 * an), res
+    assert np.all(np.abs(np.abs(np.sum(Un * Uex, axis=0)) - 1.0) <= 1e-9), Un.T @ Uex
+    out = ph.phsvds(A, k, 1e-12, block=2, anorm=an)
+    assert out["converged"] and np.all(np.abs(out["sigma"] - sig) <= 1e-10 * ex)
