@@ -144,3 +144,22 @@ def test_power_law_rows_left_vectors_in_the_callers_order(fp32):
     assert np.all(np.abs(np.abs(np.sum(Un * Uex, axis=0)) - 1.0) <= 1e-9), Un.T @ Uex
     out = ph.phsvds(A, k, 1e-12, block=2, anorm=an)
     assert out["converged"] and np.all(np.abs(out["sigma"] - sig) <= 1e-10 * ex)
+
+
+@gpu
+def test_power_law_rows_solve_is_deterministic():
+    """Two solves of the same power-law matrix (rows of seven length
+    classes, so the row space is in bin order) give bit-identical sigma,
+    U, V and product counts: the bin order depends only on the row lengths
+    and every sum has a fixed order."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A = wl.powerlaw_sparse(2000, 1000, mean=10, kmax=200, seed=41)
+    an = float(np.linalg.norm(A.toarray(), 2))
+    Ad = to_dev(A)
+    say("deterministic power-law solve", A.shape)
+    out = [P.svds_smallest(Ad, 4, 1e-12, block=2, anorm=an) for _ in range(2)]
+    (s1, U1, V1, i1), (s2, U2, V2, i2) = out
+    assert i1["mv_total"] == i2["mv_total"] and i1["status"] == i2["status"] == 0
+    assert np.array_equal(s1, s2)
+    assert np.array_equal(as_np(U1), as_np(U2)) and np.array_equal(as_np(V1), as_np(V2))
