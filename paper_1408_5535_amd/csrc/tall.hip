@@ -252,6 +252,29 @@ struct Mfma16<double> {
 
 constexpr int kTmRows = 64, kTmPitch = 17, kTmMaxWaves = 8;
 
+// A row of a row-major block, NB values at p (16-byte aligned), written by
+// 16-byte stores: one instruction then covers whole rows of the wavefront's
+// lanes instead of one value of each (element-wise stores of the row-major
+// outputs halved the rate of the Ritz block and slowed the X S kernel by a
+// fifth).
+template <typename T, int NB>
+__device__ inline void store_row16(T *p, const T (&v)[NB]) {
+  constexpr int VW = 16 / (int)sizeof(T);
+  static_assert(NB % VW == 0, "row not a multiple of 16 bytes");
+  typedef T vec __attribute__((ext_vector_type(VW)));
+#pragma unroll
+  for (int c = 0; c < NB; c += VW) {
+    vec a;
+#pragma unroll
+    for (int u = 0; u < VW; ++u) a[u] = v[c + u];
+    *reinterpret_cast<vec *>(p + c) = a;
+  }
+}
+template <typename T, int NB>
+constexpr bool row16_ok() {
+  return NB % (16 / (int)sizeof(T)) == 0;
+}
+
 template <typename T>
 __device__ inline T tall_at(const TV<T> &x1, const TV<T> &x2, int64_t r, int i) {
   return i < x1.cols ? x1.p[r * x1.rs + (int64_t)i * x1.cs]
@@ -473,6 +496,9 @@ __global__ __launch_bounds__(NG > 0 ? 1024 : 256) void k_nn(TV<T> x1, TV<T> x2, 
 #pragma unroll
       for (int c = 0; c < NG; ++c) g[a][c] = 0.0;
   }
+  // the output is a whole row-major block of NT columns: 16-byte row stores
+  const bool yrow16 = row16_ok<T, NT>() && o.ycs == 1 && o.yrs == NT && c0 == 0 && nc == NT &&
+                      ((uintptr_t)o.y & 15) == 0;
   for (int64_t r = rb * blockDim.x + threadIdx.x; r < N; r += nrb * blockDim.x) {
     T acc[NT];
 #pragma unroll
@@ -494,10 +520,13 @@ __global__ __launch_bounds__(NG > 0 ? 1024 : 256) void k_nn(TV<T> x1, TV<T> x2, 
         const int64_t col = c0 + c;
         T v = (T)alpha * acc[c];
         if (beta != 0.0) v += (T)beta * o.z[r * o.zrs + col * o.zcs];
-        o.y[r * o.yrs + col * o.ycs] = v;
+        if (!yrow16) o.y[r * o.yrs + col * o.ycs] = v;
         if (o.y2) o.y2[r * o.y2rs + col * o.y2cs] = v;
         acc[c] = v;
       }
+    }
+    if constexpr (row16_ok<T, NT>()) {
+      if (yrow16) store_row16<T, NT>(o.y + r * o.yrs, acc);
     }
     if constexpr (NG > 0) {
 #pragma unroll
@@ -743,13 +772,25 @@ __global__ __launch_bounds__(256) void k_ritz(TV<T> V, TV<T> W, const double *S,
         }
       }
     }
+    T rrv[NB];
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
       T rr = aw[c] - th[c] * ax[c];
-      X[r * ldx + c] = ax[c];
-      R[r * ldx + c] = rr;
+      rrv[c] = rr;
       rs[c] += (double)rr * (double)rr;
       if (r < ntop) xs[c] += (double)ax[c] * (double)ax[c];
+    }
+    if constexpr (row16_ok<T, NB>()) {
+      if (ldx == NB && (((uintptr_t)X | (uintptr_t)R) & 15) == 0) {
+        store_row16<T, NB>(X + r * ldx, ax);
+        store_row16<T, NB>(R + r * ldx, rrv);
+        continue;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      X[r * ldx + c] = ax[c];
+      R[r * ldx + c] = rrv[c];
     }
   }
   // block reduction of the 2 nb sums
