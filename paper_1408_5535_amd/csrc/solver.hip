@@ -316,12 +316,15 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     dg.n0 = sn0;
     dg.n1 = sn1;
     dg.n2 = sn2v;
-    if (!fused) tn(T1, none<T>(n), T1, Gram, ld, c.sc, c.s, &gp);
-    chol_inv(Gram, ld, nb, 0.0, R1, Ri1, ld, sflag, c.s, &dg, &gp);
+    // an X^T X Gram (width 8 and up) is reduced across blocks before the
+    // Cholesky: its partials (one per block of the product, up to 1024) are
+    // too many for the single workgroup of the Cholesky kernel to sum fast
+    if (!fused) tn(T1, none<T>(n), T1, Gram, ld, c.sc, c.s);
+    chol_inv(Gram, ld, nb, 0.0, R1, Ri1, ld, sflag, c.s, &dg, fused ? &gp : nullptr);
     nn<T>(T1, none<T>(n), Ri1, ld, 1.0, T2, 0.0, c.s, nullptr, nullptr, &c.sc,
           fused ? &gp : nullptr);
-    if (!fused) tn(T2, none<T>(n), T2, Gram, ld, c.sc, c.s, &gp);
-    chol_inv(Gram, ld, nb, 0.0, R1, Ri1, ld, sflag + 1, c.s, nullptr, &gp);
+    if (!fused) tn(T2, none<T>(n), T2, Gram, ld, c.sc, c.s);
+    chol_inv(Gram, ld, nb, 0.0, R1, Ri1, ld, sflag + 1, c.s, nullptr, fused ? &gp : nullptr);
     const Tall<T> Vn = cm(V[cur] + (int64_t)p * n, n, nb, n);
     nn<T>(T2, none<T>(n), Ri1, ld, 1.0, T1, 0.0, c.s, nullptr, &Vn);
     Tb = w1;
