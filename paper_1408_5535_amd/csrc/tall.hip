@@ -576,25 +576,57 @@ __global__ __launch_bounds__(NG > 0 ? 1024 : 256) void k_nn(TV<T> x1, TV<T> x2, 
   }
 }
 
+// One element through a raw buffer view (loads past the view's byte extent
+// return zero).
+template <typename T>
+__device__ inline T raw_load(__amdgpu_buffer_rsrc_t rs, int off) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+}
+// One element stored through a raw buffer view at byte offset voff + soff
+// (soff uniform over the wave).
+template <typename T>
+__device__ inline void raw_store(T v, __amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+  if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, voff, soff, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(
+        __builtin_bit_cast(unsigned __attribute__((ext_vector_type(2))), v), rs, voff, soff, 0);
+}
+
 // X S on the matrix cores for long operands, computed as (X S)^T = S^T X^T
 // with 16 x 16 x 4 MFMA tiles: lane l supplies S(k0 + l/16, 16t + l%16)
 // (from LDS) and X(r0 + l%16, k0 + l/16), so each X load instruction reads
 // four runs of 16 consecutive rows, and receives (X S)(r0 + l%16, 16t + r)
 // with r the accumulator's row of D: every store instruction writes runs of
 // 16 consecutive rows of one output column.  A wave owns 16 rows at a time
-// and all NT column tiles of the output (one X operand feeds NT MFMAs);
-// sixteen K-steps of X loads (64 columns: every restart in one pass) are
-// issued before their MFMAs.
-constexpr int kNmKU = 16;
-
-template <typename T, int NT, bool PLAIN>
-__global__ __launch_bounds__(256) void k_nn_mfma(TV<T> x1, TV<T> x2, const double *S, int lds,
+// and all NT column tiles of the output (one X operand feeds NT MFMAs).
+// The K dimension is taken KS steps of 4 columns per pass (S zero padded to
+// whole passes): the KS loads of a pass are issued before its MFMAs, and
+// neither carries a branch, so each MFMA waits for its own load only.
+// Row r of X reaches output row r only, so rows past N may hold anything.
+// BUF: X is one column-major operand (ld >= N) read through a buffer view
+// of its extent, so columns past nx load as zero and each load is one
+// 32-bit offset, and a plain product's column-major output is stored through
+// a buffer view, its per-column offset uniform over the wave; otherwise every
+// load reads an in-bounds element (row and column clamped) and columns past
+// nx are zeroed where they are used.  The row offsets are rebuilt each tile
+// (the empty asm hides them from the loop), so that sixteen load offsets and
+// the stores' column offsets are not held in registers across the loop.
+// (The float64 buffer path asks for at least five waves per SIMD: left to
+// itself the scheduler holds S operands of later steps in registers and the
+// kernel runs four waves, 6% slower.)
+template <typename T, int NT, int KS, bool PLAIN, bool BUF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && BUF ? 5 : 1)))
+void k_nn_mfma(TV<T> x1, TV<T> x2, const double *S, int lds,
                                                   int ny, double alpha, double beta,
                                                   NnOut<T> o) {
   extern __shared__ __align__(16) unsigned char smem[];
   T *ss = reinterpret_cast<T *>(smem);  // S(k, c) at k * 16 NT + c, zero padded
   const int nx = x1.cols + x2.cols, W = 16 * NT;
-  const int nk = (nx + 3) / 4 * 4;
+  const int nk = (nx + 4 * KS - 1) / (4 * KS) * (4 * KS);
   for (int idx = threadIdx.x; idx < nk * W; idx += blockDim.x) {
     const int k = idx / W, c = idx % W;
     ss[idx] = (k < nx && c < ny) ? (T)S[k + (int64_t)c * lds] : T(0);
@@ -604,30 +636,56 @@ __global__ __launch_bounds__(256) void k_nn_mfma(TV<T> x1, TV<T> x2, const doubl
   const int64_t N = x1.cols ? x1.rows : x2.rows;
   const int64_t ntile = (N + 15) / 16;
   const int lr = lane & 15, lk = lane >> 4;
+  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)x1.p, (short)0, BUF ? (int)((N + (int64_t)(nx - 1) * x1.cs) * sizeof(T)) : 0,
+      0x00020000);
+  const int ldb = BUF ? (int)(x1.cs * sizeof(T)) : 0;
+  const __amdgpu_buffer_rsrc_t yr = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)o.y, (short)0, BUF ? (int)((N + (int64_t)(ny - 1) * o.ycs) * sizeof(T)) : 0,
+      0x00020000);
+  const int ldy = BUF ? (int)(o.ycs * sizeof(T)) : 0;
+  // the lane's part of the output column (the rest is uniform over the wave)
+  const int lcol = Mfma16<T>::row(lane, 0);
   for (int64_t tile = (int64_t)blockIdx.x * 4 + w; tile < ntile; tile += (int64_t)gridDim.x * 4) {
     const int64_t r = tile * 16 + lr;
     const bool rin = r < N;
     typename Mfma16<T>::v4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = typename Mfma16<T>::v4{T(0), T(0), T(0), T(0)};
-    for (int k0 = 0; k0 < nx; k0 += 4 * kNmKU) {
-      T xb[kNmKU];
+    for (int k0 = 0; k0 < nk; k0 += 4 * KS) {
+      T xb[KS];
+      if constexpr (BUF) {
+        int off = (int)r * (int)sizeof(T) + (k0 + lk) * ldb;
+        asm("" : "+v"(off));
 #pragma unroll
-      for (int u = 0; u < kNmKU; ++u) {
-        const int k = k0 + 4 * u + lk;
-        xb[u] = (rin && k < nx) ? tall_at(x1, x2, r, k) : T(0);
+        for (int u = 0; u < KS; ++u) xb[u] = raw_load<T>(xr, off + 4 * u * ldb);
+      } else {
+        const int64_t rr = rin ? r : N - 1;
+#pragma unroll
+        for (int u = 0; u < KS; ++u) xb[u] = tall_at(x1, x2, rr, min(k0 + 4 * u + lk, nx - 1));
       }
 #pragma unroll
-      for (int u = 0; u < kNmKU; ++u) {
+      for (int u = 0; u < KS; ++u) {
         const int k = k0 + 4 * u + lk;
-        if (k0 + 4 * u < nk) {
+        const T xv = (BUF || k < nx) ? xb[u] : T(0);
 #pragma unroll
-          for (int t = 0; t < NT; ++t)
-            acc[t] = Mfma16<T>::op(ss[k * W + 16 * t + lr], xb[u], acc[t]);
-        }
+        for (int t = 0; t < NT; ++t) acc[t] = Mfma16<T>::op(ss[k * W + 16 * t + lr], xv, acc[t]);
       }
     }
-    if (rin) {
+    if constexpr (BUF && PLAIN) {
+      int yoff = (int)r * (int)sizeof(T) + lcol * ldy;
+      asm("" : "+v"(yoff));
+      if (rin) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int cu = 16 * t + Mfma16<T>::row(0, v);  // uniform part of the column
+            if (cu + lcol < ny) raw_store<T>((T)alpha * acc[t][v], yr, yoff, cu * ldy);
+          }
+        }
+      }
+    } else if (rin) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
 #pragma unroll
@@ -647,6 +705,18 @@ __global__ __launch_bounds__(256) void k_nn_mfma(TV<T> x1, TV<T> x2, const doubl
   }
 }
 
+// K-steps of 4 columns per pass of k_nn_mfma for nx columns of X: the
+// fewest wasted steps among passes of 8, 12 or 16.
+inline int nnm_ksteps(int nx) {
+  const int steps = (nx + 3) / 4;
+  int best = 16, waste = 1 << 30;
+  for (int ks : {16, 12, 8}) {
+    const int w = (steps + ks - 1) / ks * ks - steps;
+    if (w < waste) best = ks, waste = w;
+  }
+  return best;
+}
+
 // Row count from which X S (without the Gram output) takes the MFMA kernel.
 constexpr int64_t kNnMfmaRows = 65536;
 
@@ -663,7 +733,16 @@ void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double a
               "nn: the Gram output needs 1, 2 or 4 columns");
   if (nx == 0 && beta == 1.0 && !Z && !Y2 && !gram) return;
   const int nt_m = (ny + 15) / 16;
-  const size_t shm_m = (size_t)((nx + 3) / 4 * 4) * 16 * nt_m * sizeof(T);
+  // one column-major operand whose padded extent fits a 31-bit byte offset
+  // goes through a buffer view, with the fewest wasted K-steps
+  const int ks_b = nnm_ksteps(nx), nk_b = (nx + 4 * ks_b - 1) / (4 * ks_b) * (4 * ks_b);
+  const bool buf = X2.cols == 0 && X1.rs == 1 && X1.cs >= X1.rows &&
+                   (double)(nk_b + 1) * (double)X1.cs * sizeof(T) < 2147483648.0 &&
+                   Y.rs == 1 && Y.cs >= Y.rows &&
+                   (double)(16 * nt_m + 1) * (double)Y.cs * sizeof(T) < 2147483648.0;
+  const int ks_m = buf ? ks_b : 16;
+  const size_t shm_m =
+      (size_t)((nx + 4 * ks_m - 1) / (4 * ks_m) * (4 * ks_m)) * 16 * nt_m * sizeof(T);
   // (up to 16 output columns the vector kernel streams X faster: its loads
   // are runs of 64 rows, the MFMA operand's runs of 16)
   if (!gram && nx > 0 && ny > 16 && ny <= 64 && Y.rows >= kNnMfmaRows &&
@@ -678,13 +757,21 @@ void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double a
     // plain products (Y = alpha X S, the restarts) store one output only,
     // which keeps the hoisted store offsets out of the registers
     const bool plain = beta == 0.0 && !Z && !Y2;
-#define PHS_NNM(NT_)                                                                            \
-  do {                                                                                          \
-    if (plain)                                                                                  \
-      k_nn_mfma<T, NT_, true><<<grid, 256, shm, s>>>(tv(X1), tv(X2), S, lds, ny, alpha, beta, o); \
-    else                                                                                        \
-      k_nn_mfma<T, NT_, false><<<grid, 256, shm, s>>>(tv(X1), tv(X2), S, lds, ny, alpha, beta,   \
-                                                      o);                                       \
+#define PHS_NNK(NT_, KS_, BUF_)                                                                  \
+  do {                                                                                           \
+    if (plain)                                                                                   \
+      k_nn_mfma<T, NT_, KS_, true, BUF_>                                                         \
+          <<<grid, 256, shm, s>>>(tv(X1), tv(X2), S, lds, ny, alpha, beta, o);                   \
+    else                                                                                         \
+      k_nn_mfma<T, NT_, KS_, false, BUF_>                                                        \
+          <<<grid, 256, shm, s>>>(tv(X1), tv(X2), S, lds, ny, alpha, beta, o);                   \
+  } while (0)
+#define PHS_NNM(NT_)                                     \
+  do {                                                   \
+    if (!buf) PHS_NNK(NT_, 16, false);                   \
+    else if (ks_m == 16) PHS_NNK(NT_, 16, true);         \
+    else if (ks_m == 12) PHS_NNK(NT_, 12, true);         \
+    else PHS_NNK(NT_, 8, true);                          \
   } while (0)
     switch (nt) {
       case 1: PHS_NNM(1); break;
@@ -693,6 +780,7 @@ void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double a
       default: PHS_NNM(4); break;
     }
 #undef PHS_NNM
+#undef PHS_NNK
     PHS_CHECK_LAUNCH();
     prof_end(kProfNn, s, (double)Y.rows * (nx + ny * (beta != 0.0 ? 2 : 1)) * sizeof(T));
     return;

@@ -65,9 +65,18 @@ def test_tsgemm_tn_signed_data_and_ragged_tail(dtype):
 
 @gpu
 @pytest.mark.parametrize("dtype", ["float32", "float64"])
-@pytest.mark.parametrize("rows,nx,ny", [(70000, 8, 8), (300001, 56, 42), (300001, 76, 8),
-                                         (65536 + 37, 64, 64), (100003, 80, 20), (99999, 5, 17)])
-def test_tsgemm_nn_vs_numpy(rows, nx, ny, dtype):
+@pytest.mark.parametrize("beta", [-0.5, 0.0])
+@pytest.mark.parametrize("rows,nx,ny,pad", [(70000, 8, 8, 0), (300001, 56, 42, 0),
+                                             (300001, 50, 42, 7), (300001, 76, 8, 0),
+                                             (65536 + 37, 64, 64, 0), (100003, 80, 20, 0),
+                                             (99999, 5, 17, 0), (262144, 33, 25, 0),
+                                             (100003, 33, 25, 3)])
+def test_tsgemm_nn_vs_numpy(rows, nx, ny, pad, beta, dtype):
+    """Y = alpha X S + beta Y against float64 numpy.  With pad > 0 the
+    columns of X and Y sit in longer columns (leading dimension rows + pad):
+    X's padding holds NaN, which no stored output may see, and Y's padding
+    must come back untouched; beta = 0 is the plain product of the
+    restarts."""
     need_gpu()
     import paper_1408_5535_amd as P
     rng = np.random.default_rng(rows + nx)
@@ -75,12 +84,17 @@ def test_tsgemm_nn_vs_numpy(rows, nx, ny, dtype):
     S = rng.uniform(0.5, 1.5, (nx, ny))
     Y0 = rng.uniform(0.5, 1.5, (ny, rows))
     dt = torch.float32 if dtype == "float32" else torch.float64
-    Xd = torch.tensor(X, dtype=dt, device="cuda")
-    Yd = torch.tensor(Y0, dtype=dt, device="cuda")
+    Xf = torch.full((nx, rows + pad), float("nan"), dtype=dt, device="cuda")
+    Yf = torch.full((ny, rows + pad), 7.0, dtype=dt, device="cuda")
+    Xd, Yd = Xf[:, :rows], Yf[:, :rows]
+    Xd.copy_(torch.tensor(X, dtype=dt))
+    Yd.copy_(torch.tensor(Y0, dtype=dt))
     Sd = torch.tensor(S, dtype=torch.float64, device="cuda")
     Y0r = Yd.double().cpu().numpy()
-    P.tsgemm_nn(Xd, Sd, Yd, alpha=0.75, beta=-0.5)
-    ref = 0.75 * (S.T @ Xd.double().cpu().numpy()) - 0.5 * Y0r
+    P.tsgemm_nn(Xd, Sd, Yd, alpha=0.75, beta=beta)
+    ref = 0.75 * (S.T @ Xd.double().cpu().numpy()) + beta * Y0r
     got = Yd.double().cpu().numpy()
-    scale = 0.75 * (S.T @ np.abs(Xd.double().cpu().numpy())) + 0.5 * np.abs(Y0r)
+    scale = 0.75 * (S.T @ np.abs(Xd.double().cpu().numpy())) + abs(beta) * np.abs(Y0r)
     assert np.max(np.abs(got - ref) / scale) < (2e-6 * nx if dtype == "float32" else 1e-14 * nx)
+    if pad:
+        assert torch.all(Yf[:, rows:] == 7.0)
