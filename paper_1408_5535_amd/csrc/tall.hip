@@ -706,11 +706,13 @@ void k_nn_mfma(TV<T> x1, TV<T> x2, const double *S, int lds,
 }
 
 // K-steps of 4 columns per pass of k_nn_mfma for nx columns of X: the
-// fewest wasted steps among passes of 8, 12 or 16.
+// fewest wasted steps among passes of 8, 9, 12, 13 or 16 (restarts from 33
+// and from 50 columns take 9 and 13 steps exactly; a zero-padded step costs
+// its MFMAs, 3-9% of the kernel's time at those widths).
 inline int nnm_ksteps(int nx) {
   const int steps = (nx + 3) / 4;
   int best = 16, waste = 1 << 30;
-  for (int ks : {16, 12, 8}) {
+  for (int ks : {16, 13, 12, 9, 8}) {
     const int w = (steps + ks - 1) / ks * ks - steps;
     if (w < waste) best = ks, waste = w;
   }
@@ -770,7 +772,9 @@ void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double a
   do {                                                   \
     if (!buf) PHS_NNK(NT_, 16, false);                   \
     else if (ks_m == 16) PHS_NNK(NT_, 16, true);         \
+    else if (ks_m == 13) PHS_NNK(NT_, 13, true);         \
     else if (ks_m == 12) PHS_NNK(NT_, 12, true);         \
+    else if (ks_m == 9) PHS_NNK(NT_, 9, true);           \
     else PHS_NNK(NT_, 8, true);                          \
   } while (0)
     switch (nt) {

@@ -98,3 +98,33 @@ def test_tsgemm_nn_vs_numpy(rows, nx, ny, pad, beta, dtype):
     assert np.max(np.abs(got - ref) / scale) < (2e-6 * nx if dtype == "float32" else 1e-14 * nx)
     if pad:
         assert torch.all(Yf[:, rows:] == 7.0)
+
+
+@gpu
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+@pytest.mark.parametrize("rows,nx,ny", [(300001, 50, 42), (262144 + 5, 33, 25), (70001, 5, 17)])
+def test_tsgemm_nn_reads_and_writes_only_its_columns(rows, nx, ny, dtype):
+    """X and Y are the leading columns of wider tensors whose further
+    columns hold NaN (X) or a sentinel (Y): the product's loads past
+    column nx must read zero, not the neighbours, and its stores must stay
+    within Y's ny columns (plain product and with beta)."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    rng = np.random.default_rng(rows + 3 * nx)
+    dt = torch.float32 if dtype == "float32" else torch.float64
+    X = rng.uniform(0.5, 1.5, (nx, rows))
+    S = rng.uniform(0.5, 1.5, (nx, ny))
+    Xf = torch.full((nx + 3, rows), float("nan"), dtype=dt, device="cuda")
+    Xf[:nx].copy_(torch.tensor(X, dtype=dt))
+    Sd = torch.tensor(S, dtype=torch.float64, device="cuda")
+    Xr = Xf[:nx].double().cpu().numpy()
+    for beta in (0.0, 0.5):
+        Yf = torch.full((ny + 2, rows), 7.0, dtype=dt, device="cuda")
+        Yf[:ny].fill_(1.0)
+        P.tsgemm_nn(Xf[:nx], Sd, Yf[:ny], alpha=1.0, beta=beta)
+        got = Yf[:ny].double().cpu().numpy()
+        ref = S.T @ Xr + beta
+        scale = S.T @ np.abs(Xr) + beta
+        assert np.all(np.isfinite(got))
+        assert np.max(np.abs(got - ref) / scale) < (2e-6 * nx if dtype == "float32" else 1e-14 * nx)
+        assert torch.all(Yf[ny:] == 7.0)
