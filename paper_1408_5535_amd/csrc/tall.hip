@@ -705,6 +705,92 @@ void k_nn_mfma(TV<T> x1, TV<T> x2, const double *S, int lds,
   }
 }
 
+// The float32 plain product of k_nn_mfma with each lane on a pair of
+// consecutive rows: an 8-byte load gives the X operands of two MFMA tiles
+// (rows r0 + 2j and r0 + 2j + 1 for the operand column j) that share every
+// S operand, and an 8-byte store writes both outputs, so one load or store
+// instruction covers four whole 128-byte runs of a column where the 16-row
+// tile covers four halves.  Needs even leading dimensions and 8-byte aligned
+// X and Y: the byte extents are then rounded up to 8 without reaching the
+// next column, so a pair is wholly inside or wholly past the view.
+template <int NT, int KS>
+__global__ __launch_bounds__(256) void k_nn_mfma_pair(TV<float> x1, const double *S, int lds,
+                                                       int ny, double alpha, NnOut<float> o) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  float *ss = reinterpret_cast<float *>(smem);  // S(k, c) at k * 16 NT + c, zero padded
+  const int nx = x1.cols, W = 16 * NT;
+  const int nk = (nx + 4 * KS - 1) / (4 * KS) * (4 * KS);
+  for (int idx = threadIdx.x; idx < nk * W; idx += blockDim.x) {
+    const int k = idx / W, c = idx % W;
+    ss[idx] = (k < nx && c < ny) ? (float)S[k + (int64_t)c * lds] : 0.0f;
+  }
+  __syncthreads();
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t N = x1.rows;
+  const int64_t ntile = (N + 31) / 32;
+  const int lr = lane & 15, lk = lane >> 4;
+  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)x1.p, (short)0, (int)(((N + (int64_t)(nx - 1) * x1.cs) * 4 + 7) & ~(int64_t)7),
+      0x00020000);
+  const __amdgpu_buffer_rsrc_t yr = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)o.y, (short)0, (int)(((N + (int64_t)(ny - 1) * o.ycs) * 4 + 7) & ~(int64_t)7),
+      0x00020000);
+  const unsigned ldb = (unsigned)(x1.cs * 4);
+  const int ldy = (int)(o.ycs * 4);
+  const int lcol = Mfma16<float>::row(lane, 0);
+  const float al = (float)alpha;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + w; tile < ntile; tile += (int64_t)gridDim.x * 4) {
+    const int64_t r = tile * 32 + 2 * lr;  // rows r and r + 1
+    Mfma16<float>::v4 a0[NT], a1[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      a0[t] = Mfma16<float>::v4{0.0f, 0.0f, 0.0f, 0.0f};
+      a1[t] = a0[t];
+    }
+    for (int k0 = 0; k0 < nk; k0 += 4 * KS) {
+      f2 xb[KS];
+      unsigned off = (unsigned)r * 4u + (unsigned)(k0 + lk) * ldb;
+      asm("" : "+v"(off));
+#pragma unroll
+      for (int u = 0; u < KS; ++u)
+        xb[u] = __builtin_bit_cast(
+            f2, __builtin_amdgcn_raw_buffer_load_b64(xr, (int)(off + 4u * (unsigned)u * ldb), 0, 0));
+#pragma unroll
+      for (int u = 0; u < KS; ++u) {
+        const int k = k0 + 4 * u + lk;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const float sv = ss[k * W + 16 * t + lr];
+          a0[t] = Mfma16<float>::op(sv, xb[u].x, a0[t]);
+          a1[t] = Mfma16<float>::op(sv, xb[u].y, a1[t]);
+        }
+      }
+    }
+    if (r < N) {
+      const bool two = r + 1 < N;
+      int yoff = (int)r * 4 + lcol * ldy;
+      asm("" : "+v"(yoff));
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int cu = 16 * t + Mfma16<float>::row(0, v);  // uniform part of the column
+          if (cu + lcol < ny) {
+            const f2 y2 = {al * a0[t][v], al * a1[t][v]};
+            if (two)
+              __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, y2), yr, yoff, cu * ldy, 0);
+            else
+              __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, y2.x), yr, yoff,
+                                                    cu * ldy, 0);
+          }
+        }
+      }
+    }
+  }
+}
+
 // K-steps of 4 columns per pass of k_nn_mfma for nx columns of X: the
 // fewest wasted steps among passes of 8, 9, 12, 13 or 16 (restarts from 33
 // and from 50 columns take 9 and 13 steps exactly; a zero-padded step costs
@@ -759,8 +845,19 @@ void nn(const Tall<T> &X1, const Tall<T> &X2, const double *S, int lds, double a
     // plain products (Y = alpha X S, the restarts) store one output only,
     // which keeps the hoisted store offsets out of the registers
     const bool plain = beta == 0.0 && !Z && !Y2;
+    // float32 plain products in row pairs: even leading dimensions, 8-byte
+    // aligned operands
+    const bool pair = sizeof(T) == 4 && plain && buf && X1.cs % 2 == 0 && Y.cs % 2 == 0 &&
+                      ((uintptr_t)X1.p & 7) == 0 && ((uintptr_t)Y.p & 7) == 0;
+    const unsigned grid2 = (unsigned)std::min<int64_t>(((Y.rows + 31) / 32 + 3) / 4, 2048);
 #define PHS_NNK(NT_, KS_, BUF_)                                                                  \
   do {                                                                                           \
+    if constexpr (sizeof(T) == 4 && BUF_) {                                                      \
+      if (pair) {                                                                                \
+        k_nn_mfma_pair<NT_, KS_><<<grid2, 256, shm, s>>>(tv(X1), S, lds, ny, alpha, o);          \
+        break;                                                                                   \
+      }                                                                                          \
+    }                                                                                            \
     if (plain)                                                                                   \
       k_nn_mfma<T, NT_, KS_, true, BUF_>                                                         \
           <<<grid, 256, shm, s>>>(tv(X1), tv(X2), S, lds, ny, alpha, beta, o);                   \

@@ -102,7 +102,8 @@ def test_tsgemm_nn_vs_numpy(rows, nx, ny, pad, beta, dtype):
 
 @gpu
 @pytest.mark.parametrize("dtype", ["float32", "float64"])
-@pytest.mark.parametrize("rows,nx,ny", [(300001, 50, 42), (262144 + 5, 33, 25), (70001, 5, 17)])
+@pytest.mark.parametrize("rows,nx,ny", [(300001, 50, 42), (300002, 50, 42), (262144 + 5, 33, 25),
+                                         (262144, 33, 25), (70001, 5, 17)])
 def test_tsgemm_nn_reads_and_writes_only_its_columns(rows, nx, ny, dtype):
     """X and Y are the leading columns of wider tensors whose further
     columns hold NaN (X) or a sentinel (Y): the product's loads past
