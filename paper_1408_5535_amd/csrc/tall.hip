@@ -613,16 +613,15 @@ __device__ inline void raw_store(T v, __amdgpu_buffer_rsrc_t rs, int voff, int s
 // a buffer view, its per-column offset uniform over the wave; otherwise every
 // load reads an in-bounds element (row and column clamped) and columns past
 // nx are zeroed where they are used.  The row offsets are rebuilt each tile
-// (the empty asm hides them from the loop), so that sixteen load offsets and
+// (the empty asm hides them from the loop), so that the KS load offsets and
 // the stores' column offsets are not held in registers across the loop.
 // (The float64 buffer path asks for at least five waves per SIMD: left to
 // itself the scheduler holds S operands of later steps in registers and the
 // kernel runs four waves, 6% slower.)
 template <typename T, int NT, int KS, bool PLAIN, bool BUF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && BUF ? 5 : 1)))
-void k_nn_mfma(TV<T> x1, TV<T> x2, const double *S, int lds,
-                                                  int ny, double alpha, double beta,
-                                                  NnOut<T> o) {
+void k_nn_mfma(TV<T> x1, TV<T> x2, const double *S, int lds, int ny, double alpha, double beta,
+               NnOut<T> o) {
   extern __shared__ __align__(16) unsigned char smem[];
   T *ss = reinterpret_cast<T *>(smem);  // S(k, c) at k * 16 NT + c, zero padded
   const int nx = x1.cols + x2.cols, W = 16 * NT;
