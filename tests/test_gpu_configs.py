@@ -66,3 +66,43 @@ def test_reduced_weighted_grid_vs_oracle():
             ratio = info["mv_total"] / out["stats"].mv_total
             say("MV gpu/oracle", ratio)
             assert 0.5 <= ratio <= 2.0
+
+
+@gpu
+def test_random_300k_full_size_invariants():
+    """The random family at its stated size (300000 x 200000, 12 per row,
+    N(0,1), diagonal shift; k = 10, block 4, float64).  No oracle solve fits
+    a test at this size, so the triplets are held to what fixes them without
+    one: the explicit float64 residuals recomputed on the host against ||A||
+    from ARPACK, orthonormal singular vectors, and the same singular values
+    from independent solves (another start block, no preconditioner, a
+    float32 first stage), which agree only if none of them skipped one of
+    the k smallest."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A = wl.random_sparse(300_000, 200_000, 12, seed=2000)
+    an = float(sla.svds(A, k=1, return_singular_vectors=False)[0])
+    Ad = to_dev(A)
+
+    def run(seed, **kw):
+        X0 = torch.tensor(wl.initial_block(A.shape[1], 4, seed))
+        return P.svds_smallest(Ad, 10, 1e-12, block=4, init_block=X0, anorm=an, **kw)
+
+    sig, U, V, info = run(2, precond="jacobi")
+    say("random 300k x 200k k=10 b=4 Jacobi:", info["status"], info["mv_total"], sig)
+    assert info["status"] == 0
+    assert np.all(np.diff(sig) >= 0) and sig[0] > 0
+    U, V = as_np(U), as_np(V)
+    res = dense.triplet_residuals(A, sig, U, V)
+    assert np.all(res <= 1e-12 * an), res
+    assert np.allclose(res, info["res"], rtol=1e-6, atol=1e-15 * an)
+    assert np.linalg.norm(V.T @ V - np.eye(10)) < 1e-10
+    assert np.linalg.norm(U.T @ U - np.eye(10)) < 1e-10
+    for label, kw in (("other start", dict(seed=3, precond="jacobi")),
+                      ("no preconditioner", dict(seed=2)),
+                      ("float32 first stage", dict(seed=2, precond="jacobi", stage1_fp32=True))):
+        s2, _, _, i2 = run(**kw)
+        say(label, i2["status"], i2["mv_total"])
+        assert i2["status"] == 0
+        # each set is within its residual of the exact values
+        assert np.all(np.abs(s2 - sig) <= 2e-12 * an), (label, s2 - sig)
