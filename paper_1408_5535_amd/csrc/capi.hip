@@ -129,8 +129,8 @@ bool make_dims(int64_t m, int64_t n, int64_t nnz, int k, const phsvds_opts &o, D
 template <typename T>
 void take_stage1(Arena &ar, const Dims &d, Stage1Bufs<T> &b) {
   for (int i = 0; i < 2; ++i) {
-    b.V[i] = ar.take<T>(d.n * d.pmax);
-    b.W[i] = ar.take<T>(d.n * d.pmax);
+    b.V[i] = ar.take<T>(basis_ld(d.n) * d.pmax);
+    b.W[i] = ar.take<T>(basis_ld(d.n) * d.pmax);
   }
   b.Xl = ar.take<T>(d.n * d.k);
   b.Xb = ar.take<T>(d.n * d.bw);

@@ -112,6 +112,10 @@ struct Scratch {
   int *flag = nullptr;     // status flags (64 ints)
 };
 constexpr int64_t kPartCap = 1 << 21;
+// Leading dimension of the first stage's bases (V, W): n rounded up to 64
+// elements, so that every column starts on a 256-byte boundary and the
+// tall-skinny kernels move whole cache lines whatever n is.
+inline int64_t basis_ld(int64_t n) { return (n + 63) / 64 * 64; }
 constexpr int64_t kAuxCap = 1 << 16;
 
 // Block partials of a product X^T Y left for a consumer kernel to reduce:

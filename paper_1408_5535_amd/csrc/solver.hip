@@ -214,6 +214,7 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
   const double eps = fp32 ? kEps32 : kEps64;
   const double dep_drop = fp32 ? 1e-4 : kDepDropF64;
   const int ld = kSP;
+  const int64_t ldv = basis_ld(n);  // leading dimension of V and W
   T *V[2] = {bf.V[0], bf.V[1]}, *W[2] = {bf.W[0], bf.W[1]};
   int cur = 0, p = 0, nl = 0, nprev = 0;
   T *Tb = bf.Tb, *T2b = bf.T2b, *Rb = bf.Rb;
@@ -258,31 +259,31 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
   auto append = [&](int nb, bool v_written) {
     if (P.opC) {
       P.opC(Tb, bf.WTb, bw);
-      copy(rmv(bf.WTb, n, nb, bw), cm(W[cur] + (int64_t)p * n, n, nb, n), c.s);
+      copy(rmv(bf.WTb, n, nb, bw), cm(W[cur] + (int64_t)p * ldv, n, nb, ldv), c.s);
     } else {
       prof_group_begin(pkind, c.s, 2);
       spmm(A, bw, Tb, bf.Yb, false, c.s);
       if (At.op) {  // an operator writes row-major blocks only
         spmm(At, bw, bf.Yb, bf.WTb, false, c.s);
-        copy(rmv(bf.WTb, n, nb, bw), cm(W[cur] + (int64_t)p * n, n, nb, n), c.s);
+        copy(rmv(bf.WTb, n, nb, bw), cm(W[cur] + (int64_t)p * ldv, n, nb, ldv), c.s);
       } else {
-        spmm(At, bw, bf.Yb, W[cur] + (int64_t)p * n, false, c.s, n, nb);
+        spmm(At, bw, bf.Yb, W[cur] + (int64_t)p * ldv, false, c.s, ldv, nb);
       }
       prof_group_end(pkind, c.s, cbytes);
     }
     c.st->mv_stage1 += nb;
-    if (!v_written) copy(rmv(Tb, n, nb, bw), cm(V[cur] + (int64_t)p * n, n, nb, n), c.s);
+    if (!v_written) copy(rmv(Tb, n, nb, bw), cm(V[cur] + (int64_t)p * ldv, n, nb, ldv), c.s);
     // border of H; the previous block's coefficients have no component on
     // the new columns
     TnParts gp;
-    tn(cm(V[cur], n, p + nb, n), none<T>(n), cm(W[cur] + (int64_t)p * n, n, nb, n), Gb, ld,
+    tn(cm(V[cur], n, p + nb, ldv), none<T>(n), cm(W[cur] + (int64_t)p * ldv, n, nb, ldv), Gb, ld,
        c.sc, c.s, &gp);
     reduce_border(gp, H, ld, nprev ? prev : nullptr, ld, nprev, c.s);
     p += nb;
   };
   // checked expansion (host decisions on dependence and breakdown)
   auto expand = [&](int nb) {
-    orth_block(c, Tb, T2b, n, nb, bw, cm(bf.Xl, n, nl, n), cm(V[cur], n, p, n), dep_drop, sp);
+    orth_block(c, Tb, T2b, n, nb, bw, cm(bf.Xl, n, nl, n), cm(V[cur], n, p, ldv), dep_drop, sp);
     append(nb, false);
   };
   // unchecked expansion: CGS2 + CholQR2, diagnostics left in the status
@@ -291,7 +292,7 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
   // the last one also writes the new columns of V.
   auto expand_fast = [&](int nb) {
     T *orig = Tb, *w1 = T2b, *w2 = bf.Fb;
-    const Tall<T> B1 = cm(bf.Xl, n, nl, n), B2 = cm(V[cur], n, p, n);
+    const Tall<T> B1 = cm(bf.Xl, n, nl, n), B2 = cm(V[cur], n, p, ldv);
     const Tall<T> T0 = rmv(orig, n, nb, bw), T1 = rmv(w1, n, nb, bw), T2 = rmv(w2, n, nb, bw);
     // classical Gram-Schmidt, always twice: a single pass that cancels
     // little (unpreconditioned corrections are nearly orthogonal to V
@@ -325,7 +326,7 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
           fused ? &gp : nullptr);
     if (!fused) tn(T2, none<T>(n), T2, Gram, ld, c.sc, c.s);
     chol_inv(Gram, ld, nb, 0.0, R1, Ri1, ld, sflag + 1, c.s, nullptr, fused ? &gp : nullptr);
-    const Tall<T> Vn = cm(V[cur] + (int64_t)p * n, n, nb, n);
+    const Tall<T> Vn = cm(V[cur] + (int64_t)p * ldv, n, nb, ldv);
     nn<T>(T2, none<T>(n), Ri1, ld, 1.0, T1, 0.0, c.s, nullptr, &Vn);
     Tb = w1;
     T2b = w2;
@@ -377,12 +378,12 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
     if (restart_due) {
       restart_basis(S, ld, p, pmin, prev, ld, nprev, Y, ld, cnt, c.s);
       hc = std::min(pmin + nprev, p);  // restart_basis fills every column
-      nn(cm(V[cur], n, p, n), none<T>(n), Y, ld, 1.0, cm(V[1 - cur], n, hc, n), 0.0, c.s);
-      nn(cm(W[cur], n, p, n), none<T>(n), Y, ld, 1.0, cm(W[1 - cur], n, hc, n), 0.0, c.s);
-      ritz(cm(V[1 - cur], n, nb, n), cm(W[1 - cur], n, nb, n), sp.eye(), ld, theta, bf.Xb, Rb,
+      nn(cm(V[cur], n, p, ldv), none<T>(n), Y, ld, 1.0, cm(V[1 - cur], n, hc, ldv), 0.0, c.s);
+      nn(cm(W[cur], n, p, ldv), none<T>(n), Y, ld, 1.0, cm(W[1 - cur], n, hc, ldv), 0.0, c.s);
+      ritz(cm(V[1 - cur], n, nb, ldv), cm(W[1 - cur], n, nb, ldv), sp.eye(), ld, theta, bf.Xb, Rb,
            nb, bw, rn2, nullptr, 0, c.sc, c.s);
     } else {
-      ritz(cm(V[cur], n, p, n), cm(W[cur], n, p, n), S, ld, theta, bf.Xb, Rb, nb, bw, rn2,
+      ritz(cm(V[cur], n, p, ldv), cm(W[cur], n, p, ldv), S, ld, theta, bf.Xb, Rb, nb, bw, rn2,
            nullptr, 0, c.sc, c.s);
     }
     const bool want_rho = fp32 && rho_age >= 10;
@@ -510,13 +511,13 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
         last_rebuild = it;
         for (int c0 = 0; c0 < p; c0 += bw) {
           int w = std::min(bw, p - c0);
-          copy(cm(V[cur] + (int64_t)c0 * n, n, w, n), rmv(Tb, n, w, bw), c.s);
+          copy(cm(V[cur] + (int64_t)c0 * ldv, n, w, ldv), rmv(Tb, n, w, bw), c.s);
           applyC(Tb, w);
-          copy(rmv(bf.WTb, n, w, bw), cm(W[cur] + (int64_t)c0 * n, n, w, n), c.s);
+          copy(rmv(bf.WTb, n, w, bw), cm(W[cur] + (int64_t)c0 * ldv, n, w, ldv), c.s);
         }
         for (int c0 = 0; c0 < p; c0 += 32) {
           int w = std::min(32, p - c0);
-          tn(cm(V[cur], n, p, n), none<T>(n), cm(W[cur] + (int64_t)c0 * n, n, w, n),
+          tn(cm(V[cur], n, p, ldv), none<T>(n), cm(W[cur] + (int64_t)c0 * ldv, n, w, ldv),
              H + (int64_t)c0 * ld, ld, c.sc, c.s);
         }
         nprev = 0;
@@ -551,8 +552,8 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
         gather_cols(S, ld, p, c.didx, nv, Hs, ld, c.s);
         restart_basis(Hs, ld, p, nv, sp.eye(), ld, p - nv, Y, ld, cnt, c.s);
         const double *Yk = Y + (int64_t)conv.size() * ld;
-        nn(cm(V[cur], n, p, n), none<T>(n), Yk, ld, 1.0, cm(V[1 - cur], n, nk, n), 0.0, c.s);
-        nn(cm(W[cur], n, p, n), none<T>(n), Yk, ld, 1.0, cm(W[1 - cur], n, nk, n), 0.0, c.s);
+        nn(cm(V[cur], n, p, ldv), none<T>(n), Yk, ld, 1.0, cm(V[1 - cur], n, nk, ldv), 0.0, c.s);
+        nn(cm(W[cur], n, p, ldv), none<T>(n), Yk, ld, 1.0, cm(W[1 - cur], n, nk, ldv), 0.0, c.s);
         restart_project(H, ld, p, Yk, ld, nk, nullptr, ld, 0, nullptr, ld, c.s);
         cur = 1 - cur;
       }
@@ -578,7 +579,7 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
       const int nbest = std::min(need, p);
       if (nbest > 0) {
         syev_rr(H, ld, p, nbest, largest, theta, S, ld, c.s);
-        nn(cm(V[cur], n, p, n), none<T>(n), S, ld, 1.0, cm(bf.Xl + (int64_t)nl * n, n, nbest, n),
+        nn(cm(V[cur], n, p, ldv), none<T>(n), S, ld, 1.0, cm(bf.Xl + (int64_t)nl * n, n, nbest, n),
            0.0, c.s);
         res.best_theta.resize(nbest);
         c.d2h(res.best_theta.data(), theta, nbest * sizeof(double));
@@ -629,7 +630,10 @@ Stage1Result run_stage1(Ctx &c, const SpMat<T> &A, const SpMat<T> &At, const Sta
   res.iters = it;
   res.nl = nl;
   res.p = p;
-  res.Vrest = V[cur];
+  // the basis leaves with leading dimension n (compacted into the other
+  // buffer, which is free now, when the padded one differs)
+  if (ldv != n && p > 0) copy(cm(V[cur], n, p, ldv), cm(V[1 - cur], n, p, n), c.s);
+  res.Vrest = ldv != n ? V[1 - cur] : V[cur];
   bf.Tb = Tb;
   bf.T2b = T2b;
   bf.Rb = Rb;
