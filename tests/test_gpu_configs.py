@@ -186,3 +186,30 @@ def test_orthogonality_bound_holds_for_perturbed_triplets():
         np.fill_diagonal(off, 0.0)
         assert np.all(off <= b + 1e-15)
         assert (off / np.where(b > 0, b, 1.0)).max() > 1e-3
+
+
+@gpu
+def test_unaligned_rows_solve_float64_and_float32_first_stage():
+    """A random member whose column count (70001) is off every alignment,
+    above the row count where the tall products take the matrix cores: the
+    first stage keeps its bases at a padded leading dimension (70016) and
+    hands them on compacted.  Both precisions must converge to the same
+    singular values, with host-recomputed residuals at the tolerance."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    A = wl.random_sparse(100_000, 70_001, 12, seed=77)
+    an = float(sla.svds(A, k=1, return_singular_vectors=False)[0])
+    Ad = to_dev(A)
+    out = []
+    for fp32 in (False, True):
+        X0 = torch.tensor(wl.initial_block(A.shape[1], 4, 2))
+        sig, U, V, info = P.svds_smallest(Ad, 6, 1e-12, block=4, init_block=X0, anorm=an,
+                                          precond="jacobi", stage1_fp32=fp32)
+        say("random 100000 x 70001 k=6 b=4 Jacobi fp32 first stage" if fp32 else
+            "random 100000 x 70001 k=6 b=4 Jacobi float64", info["status"], info["mv_total"])
+        assert info["status"] == 0
+        res = dense.triplet_residuals(A, sig, as_np(U), as_np(V))
+        assert np.all(res <= 1e-12 * an), res
+        _check_orthogonality(as_np(U), as_np(V), sig, res)
+        out.append(sig)
+    assert np.all(np.abs(out[1] - out[0]) <= 2e-12 * an), out[1] - out[0]
