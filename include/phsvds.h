@@ -303,9 +303,12 @@ int phsvds_small_svd(const double *M, int ldm, int rows, int cols, double *sv, d
  * Rayleigh-Ritz border V^T W, the Gram-Schmidt coefficients [X_lock V]^T T
  * and the CholQR Gram matrices are X^T Y; the basis updates and restarts are
  * X S).  Long operands (rows >= 65536, ny <= 16) run on the matrix cores.
- *   tsgemm_tn: G = X^T Y, X device rows x nx column-major (ld ldx >= rows),
- *     Y device rows x ny, column-major with ld ldy >= rows if ycm, else
- *     row-major with row stride ldy >= ny; G device nx x ny float64
+ *   tsgemm_tn: G = X^T Y, X device rows x nx, Y device rows x ny; layout
+ *     bit 0 set: Y column-major with ld ldy >= rows, else row-major with row
+ *     stride ldy >= ny; bit 1 set: X row-major with row stride ldx >= nx,
+ *     else column-major with ld ldx >= rows; other bits are PHSVDS_EINVAL.
+ *     (The Gram matrix X^T X of one row-major block of 8 columns, X == Y,
+ *     rows >= 65536, takes a kernel of its own.)  G device nx x ny float64
  *     column-major (ld ldg >= nx).  1 <= nx <= 128, 1 <= ny <= 32.  fp32:
  *     X, Y float32, products accumulated in float32 within a block of rows
  *     and the blocks added in float64, in a fixed order (deterministic).
@@ -316,7 +319,7 @@ int phsvds_small_svd(const double *M, int ldm, int rows, int cols, double *sv, d
  *     1 <= ny <= 64. */
 size_t phsvds_tsgemm_ws_bytes(void);
 int phsvds_tsgemm_tn(int fp32, int64_t rows, int nx, int ny, const void *X, int64_t ldx,
-                     const void *Y, int64_t ldy, int ycm, double *G, int ldg, void *ws,
+                     const void *Y, int64_t ldy, int layout, double *G, int ldg, void *ws,
                      size_t ws_bytes, void *stream);
 int phsvds_tsgemm_nn(int fp32, int64_t rows, int nx, int ny, double alpha, const void *X,
                      int64_t ldx, const double *S, int lds, double beta, void *Y, int64_t ldy,

@@ -294,20 +294,27 @@ _lib.phsvds_tsgemm_nn.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, ct
                                   ctypes.c_double, _P, ctypes.c_int64, _P]
 
 
-def tsgemm_tn(X: torch.Tensor, Y: torch.Tensor, y_row_major: bool = False) -> torch.Tensor:
+def tsgemm_tn(X: torch.Tensor, Y: torch.Tensor, y_row_major: bool = False,
+              x_row_major: bool = False) -> torch.Tensor:
     """G = X^T Y (float64, nx x ny) for X (nx x rows storage: X[i] is column
-    i, i.e. a column-major rows x nx matrix) and Y given the same way (or,
-    with y_row_major, as a rows x ny row-major tensor)."""
+    i, i.e. a column-major rows x nx matrix, or with x_row_major a rows x nx
+    row-major tensor) and Y given the same way (or, with y_row_major, as a
+    rows x ny row-major tensor)."""
     fp32 = X.dtype == torch.float32
-    nx, rows = X.shape
-    if y_row_major:
-        ny, ldy, ycm = Y.shape[1], Y.stride(0), 0
+    if x_row_major:
+        rows, nx = X.shape
     else:
-        ny, ldy, ycm = Y.shape[0], Y.stride(0), 1
+        nx, rows = X.shape
+    if y_row_major:
+        ny, ldy, layout = Y.shape[1], Y.stride(0), 0
+    else:
+        ny, ldy, layout = Y.shape[0], Y.stride(0), 1
+    if x_row_major:
+        layout |= 2
     G = torch.empty((ny, nx), dtype=torch.float64, device=X.device)  # column-major nx x ny
     ws = torch.empty(int(_lib.phsvds_tsgemm_ws_bytes()), dtype=torch.uint8, device=X.device)
     _check(_lib.phsvds_tsgemm_tn(int(fp32), rows, nx, ny, X.data_ptr(), X.stride(0),
-                                 Y.data_ptr(), ldy, ycm, G.data_ptr(), nx, ws.data_ptr(),
+                                 Y.data_ptr(), ldy, layout, G.data_ptr(), nx, ws.data_ptr(),
                                  ws.numel(), _stream()), "tsgemm_tn")
     return G.t()
 

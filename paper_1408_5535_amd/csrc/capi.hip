@@ -1280,28 +1280,30 @@ int phsvds_spmm_noalloc(const phsvds_csr *A, const float *val32, int trans, int 
 size_t phsvds_tsgemm_ws_bytes(void) { return (size_t)kPartCap * sizeof(double); }
 
 int phsvds_tsgemm_tn(int fp32, int64_t rows, int nx, int ny, const void *X, int64_t ldx,
-                     const void *Y, int64_t ldy, int ycm, double *G, int ldg, void *ws,
+                     const void *Y, int64_t ldy, int layout, double *G, int ldg, void *ws,
                      size_t ws_bytes, void *stream) {
   return guarded([&]() {
     PHS_REQUIRE(X && Y && G && ws, kEinval, "null argument");
+    PHS_REQUIRE((layout & ~3) == 0, kEinval, "tsgemm_tn: unknown layout bits");
+    const bool ycol = (layout & 1) != 0, xrow = (layout & 2) != 0;
     PHS_REQUIRE(rows >= 1 && nx >= 1 && nx <= 128 && ny >= 1 && ny <= 32, kEinval,
                 "tsgemm_tn: need rows >= 1, 1 <= nx <= 128, 1 <= ny <= 32");
-    PHS_REQUIRE(ldx >= rows && ldg >= nx && (ycm ? ldy >= rows : ldy >= ny), kEinval,
-                "tsgemm_tn: leading dimension too small");
+    PHS_REQUIRE((xrow ? ldx >= nx : ldx >= rows) && ldg >= nx && (ycol ? ldy >= rows : ldy >= ny),
+                kEinval, "tsgemm_tn: leading dimension too small");
     PHS_REQUIRE(ws_bytes >= (size_t)kPartCap * sizeof(double), kEnomem,
                 "tsgemm_tn: workspace too small");
     Scratch sc;
     sc.part = (double *)ws;
     const hipStream_t s = (hipStream_t)stream;
     if (fp32) {
-      Tall<float> x = cm((float *)const_cast<void *>(X), rows, nx, ldx);
-      Tall<float> y = ycm ? cm((float *)const_cast<void *>(Y), rows, ny, ldy)
-                          : Tall<float>{(float *)const_cast<void *>(Y), rows, ny, ldy, 1};
+      float *xp = (float *)const_cast<void *>(X), *yp = (float *)const_cast<void *>(Y);
+      Tall<float> x = xrow ? Tall<float>{xp, rows, nx, ldx, 1} : cm(xp, rows, nx, ldx);
+      Tall<float> y = ycol ? cm(yp, rows, ny, ldy) : Tall<float>{yp, rows, ny, ldy, 1};
       tn(x, cm<float>(nullptr, rows, 0, rows), y, G, ldg, sc, s);
     } else {
-      Tall<double> x = cm((double *)const_cast<void *>(X), rows, nx, ldx);
-      Tall<double> y = ycm ? cm((double *)const_cast<void *>(Y), rows, ny, ldy)
-                           : Tall<double>{(double *)const_cast<void *>(Y), rows, ny, ldy, 1};
+      double *xp = (double *)const_cast<void *>(X), *yp = (double *)const_cast<void *>(Y);
+      Tall<double> x = xrow ? Tall<double>{xp, rows, nx, ldx, 1} : cm(xp, rows, nx, ldx);
+      Tall<double> y = ycol ? cm(yp, rows, ny, ldy) : Tall<double>{yp, rows, ny, ldy, 1};
       tn(x, cm<double>(nullptr, rows, 0, rows), y, G, ldg, sc, s);
     }
     return PHSVDS_OK;

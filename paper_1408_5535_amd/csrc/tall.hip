@@ -363,6 +363,67 @@ __global__ __launch_bounds__(64 * kTmMaxWaves) void k_tn_mfma(TV<T> x1, TV<T> x2
   }
 }
 
+// G = X^T X for a row-major block of NB columns (row stride NB, rows
+// 16-byte aligned) on long operands.  Each thread takes whole rows with
+// 16-byte loads, two rows ahead of their products, so a wave reads 64
+// consecutive rows as one contiguous run (the column-at-a-time loads of the
+// MFMA kernel touch every line of the block once per column); the upper
+// triangle of the products is accumulated in float64 (exact products of
+// float32 values).  The block's sums (wave reductions, then the waves in a
+// fixed order) go out as a full NB x NB partial, entry (i, j) at i NB + j.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_gram_rows(const T *__restrict__ X, int64_t N, int64_t rpb,
+                                                   double *part) {
+  constexpr int NE = NB * (NB + 1) / 2;
+  constexpr int RU = 2;
+  double acc[NE];
+#pragma unroll
+  for (int e = 0; e < NE; ++e) acc[e] = 0.0;
+  const int64_t r0 = (int64_t)blockIdx.x * rpb;
+  const int64_t r1 = r0 + rpb < N ? r0 + rpb : N;
+  const int64_t step = blockDim.x;
+  for (int64_t rb = r0 + threadIdx.x; rb < r1; rb += RU * step) {
+    T x[RU][NB];
+#pragma unroll
+    for (int q = 0; q < RU; ++q) {
+      const int64_t r = rb + q * step;
+      if (r < r1) {
+        load_row16<T, NB>(X + r * NB, x[q]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) x[q][i] = T(0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RU; ++q) {
+      int e = 0;
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = i; j < NB; ++j, ++e)
+          acc[e] = fma((double)x[q][i], (double)x[q][j], acc[e]);
+    }
+  }
+  __shared__ double red[4][NE];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const double v = wave_total(acc[e]);
+    if (lane == 0) red[w][e] = v;
+  }
+  __syncthreads();
+  const int nw = blockDim.x >> 6;
+  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+    double v = red[0][e];
+    for (int q = 1; q < nw; ++q) v += red[q][e];
+    int i = 0, rem = e;
+    while (rem >= NB - i) rem -= NB - i, ++i;
+    const int j = i + rem;
+    part[(int64_t)blockIdx.x * NB * NB + i * NB + j] = v;
+    part[(int64_t)blockIdx.x * NB * NB + j * NB + i] = v;
+  }
+}
+
 // LDS bytes a workgroup may use on the current device (read once).
 int device_lds_max() {
   static int lds_max = -1;
@@ -391,6 +452,25 @@ void tn(const Tall<T> &X1, const Tall<T> &X2, const Tall<T> &Y, double *G, int l
   const int lds_max = device_lds_max();
   const int waves_m = std::max(4, (nx + 15) / 16);
   const size_t shm_m = (size_t)(1 + waves_m) * kTmRows * kTmPitch * sizeof(T);
+  // the Gram matrix of a whole row-major block of 8 columns
+  if (X2.cols == 0 && X1.p == Y.p && nx == 8 && ny == 8 && X1.cs == 1 && Y.cs == 1 &&
+      X1.rs == 8 && Y.rs == 8 && X1.rows == Y.rows && Y.rows >= kTnMfmaRows &&
+      ((uintptr_t)X1.p & 15) == 0) {
+    const int64_t N = Y.rows, E = 64;
+    const int64_t nblk = std::min<int64_t>(1024, kPartCap / E);
+    const int64_t rpb = (N + nblk - 1) / nblk;
+    const int nb_used = (int)((N + rpb - 1) / rpb);
+    prof_begin(kProfTn, s);
+    k_gram_rows<T, 8><<<nb_used, 256, 0, s>>>(X1.p, N, rpb, sc.part);
+    if (keep) {
+      *keep = TnParts{sc.part, nb_used, nx, ny};
+    } else {
+      k_reduce_parts<<<(int)E, 64, 0, s>>>(sc.part, nb_used, nx, ny, G, ldg);
+    }
+    PHS_CHECK_LAUNCH();
+    prof_end(kProfTn, s, (double)Y.rows * nx * sizeof(T));
+    return;
+  }
   if (ny <= 16 && Y.rows >= kTnMfmaRows && shm_m <= (size_t)lds_max) {
     const int64_t N = Y.rows, E = (int64_t)nx * ny;
     const int waves = waves_m;

@@ -129,3 +129,25 @@ def test_tsgemm_nn_reads_and_writes_only_its_columns(rows, nx, ny, dtype):
         assert np.all(np.isfinite(got))
         assert np.max(np.abs(got - ref) / scale) < (2e-6 * nx if dtype == "float32" else 1e-14 * nx)
         assert torch.all(Yf[ny:] == 7.0)
+
+
+@gpu
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+@pytest.mark.parametrize("rows,nb", [(300001, 8), (65536, 8), (100003, 6), (70001, 16), (5000, 8)])
+def test_tsgemm_tn_row_major_gram(rows, nb, dtype):
+    """G = X^T X of a row-major block (the CholQR Gram matrices of the
+    solver): width 8 from 65536 rows takes the Gram kernel, the others the
+    general products with a row-major X; against float64 numpy within the
+    forward-error bound of the sums."""
+    need_gpu()
+    import paper_1408_5535_amd as P
+    rng = np.random.default_rng(rows + nb)
+    dt = torch.float32 if dtype == "float32" else torch.float64
+    Xd = torch.tensor(rng.standard_normal((rows, nb)), dtype=dt, device="cuda")
+    G = as_np(P.tsgemm_tn(Xd, Xd, y_row_major=True, x_row_major=True))
+    Xr = Xd.double().cpu().numpy()
+    eps = 2.0 ** -24 if dtype == "float32" else 2.0 ** -53
+    bound = np.abs(Xr).T @ np.abs(Xr) * rows * eps
+    assert np.all(np.abs(G - Xr.T @ Xr) <= bound)
+    if nb == 8 and rows >= 65536:
+        assert np.array_equal(G, G.T)  # one sum per pair, written to both
